@@ -1,0 +1,407 @@
+/*
+ * numarck_oracle.c -- plain, slow CPU reference of the NUMARCK compression path
+ * ("Parallel Implementation of Lossy Data Compression for Temporal Data Sets",
+ * Yuan et al., arXiv 1703.02438).
+ *
+ * TEST INFRASTRUCTURE ONLY: used by the tests, the smoke check and the
+ * CPU-baseline leg of the benchmark.  The product library never calls it and
+ * shares no code with it.
+ *
+ * The method is a heuristic (top-k coverage is not optimal, Sec. V-D), so this
+ * file spells its steps out in the paper's order:
+ *   1. change ratio of every point, eq. (1)                    (Sec. III-A, IV-A)
+ *   2. range [lo, hi] of the ratios                              (Sec. IV-A)
+ *   3. fine bins of width 2E anchored at lo, histogram           (Sec. IV-B-1)
+ *   4. top-k bins, k = 2^B - 1, by count                         (Sec. IV-B-1)
+ *   5. index each point by its bin, escape code 2^B - 1 otherwise (Sec. III-C)
+ *   6. incompressible values kept as they are, in element order  (Sec. III-C)
+ *   7. B-bit packing of the index table                          (Sec. IV-C)
+ *   8. per-block count of earlier incompressible points          (Sec. IV-C)
+ *   9. decompression by eq. (4), full and partial                (Sec. III-E, V-C)
+ *
+ * Readings taken where the paper is silent or garbled:
+ *   - a point is valid when its previous value is nonzero and finite, the new
+ *     value is finite, the ratio is finite and |ratio| <= E * 2^50; invalid
+ *     points are always stored as incompressible values;
+ *   - bin m holds ratios with floor((d - lo) / (2E)) == m, evaluated in binary64;
+ *   - ties in the top-k order go to the lower bin id; empty bins are never
+ *     selected; the selected bins get indices in ascending bin-id order;
+ *   - bin centre c_m = lo + (2m + 1) E in binary64, stored in the snapshot type;
+ *   - reconstruction R = T(p * (1 + c)) (the only reading of eq. (4) consistent
+ *     with eq. (1)); a point is kept only if |R - q| <= E |p| after rounding;
+ *   - index bits are written least-significant first into a contiguous stream
+ *     of little-endian 32-bit words; elements per block = floor(8 * bytes / B).
+ *
+ * All arithmetic is binary64, round-to-nearest-even, evaluated exactly as
+ * written; build with -ffp-contract=off and without fast-math.
+ */
+#include "numarck_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ---------------------------------------------------------------- helpers */
+
+static double load_as_double(const void* base, int dtype, uint64_t j) {
+  if (dtype == ORC_F32) {
+    float v;
+    memcpy(&v, (const char*)base + 4 * j, 4);
+    return (double)v;
+  }
+  double v;
+  memcpy(&v, (const char*)base + 8 * j, 8);
+  return v;
+}
+
+/* Round a binary64 value to the snapshot type (nearest-even) and store it. */
+static void store_rounded(void* base, int dtype, uint64_t j, double v) {
+  if (dtype == ORC_F32) {
+    float f = (float)v;
+    memcpy((char*)base + 4 * j, &f, 4);
+  } else {
+    memcpy((char*)base + 8 * j, &v, 8);
+  }
+}
+
+/* The value as stored in the snapshot type, read back as binary64. */
+static double rounded_to_type(int dtype, double v) {
+  if (dtype == ORC_F32) return (double)(float)v;
+  return v;
+}
+
+/* Copy one element bit for bit (keeps NaN payloads and signed zeros). */
+static void copy_elem(void* dst, uint64_t dj, const void* src, uint64_t sj, int dtype) {
+  size_t L = dtype == ORC_F32 ? 4 : 8;
+  memcpy((char*)dst + L * dj, (const char*)src + L * sj, L);
+}
+
+static void zero_elem(void* dst, uint64_t dj, int dtype) {
+  size_t L = dtype == ORC_F32 ? 4 : 8;
+  memset((char*)dst + L * dj, 0, L);
+}
+
+static size_t elem_size(int dtype) { return dtype == ORC_F32 ? 4 : 8; }
+
+static int check_args(int dtype, double E, uint32_t B) {
+  if (dtype != ORC_F32 && dtype != ORC_F64) return ORC_EDTYPE;
+  if (B < 1 || B > 16) return ORC_EBITS;
+  if (!(E > 0.0 && E <= 1.0)) return ORC_EBOUND;
+  return ORC_OK;
+}
+
+/* ------------------------------------------------ step 1: change ratio, eq. (1) */
+
+int orc_ratio(const void* prev, const void* curr, uint64_t n, int dtype, double E,
+              double* d, uint8_t* valid) {
+  double cap = ldexp(E, 50);
+  for (uint64_t j = 0; j < n; j++) {
+    double p = load_as_double(prev, dtype, j);
+    double q = load_as_double(curr, dtype, j);
+    double r = (q - p) / p;
+    d[j] = r;
+    valid[j] = (p != 0.0) && isfinite(p) && isfinite(q) && isfinite(r) && fabs(r) <= cap;
+  }
+  return ORC_OK;
+}
+
+/* ------------------------------------------------ step 2: range of the ratios */
+
+/* a precedes b in the order used for lo/hi: numeric order, -0 before +0. */
+static int precedes(double a, double b) {
+  if (a < b) return 1;
+  return a == b && signbit(a) && !signbit(b);
+}
+
+uint64_t orc_range(const double* d, const uint8_t* valid, uint64_t n, double* lo, double* hi) {
+  uint64_t nv = 0;
+  double mn = 0.0, mx = 0.0;
+  for (uint64_t j = 0; j < n; j++) {
+    if (!valid[j]) continue;
+    if (nv == 0) {
+      mn = d[j];
+      mx = d[j];
+    } else {
+      if (precedes(d[j], mn)) mn = d[j];
+      if (precedes(mx, d[j])) mx = d[j];
+    }
+    nv++;
+  }
+  *lo = mn;
+  *hi = mx;
+  return nv;
+}
+
+/* ------------------------------------------------ step 3: fine bins of width 2E */
+
+void orc_bin_ids(const double* d, const uint8_t* valid, uint64_t n, double lo, double E,
+                 int64_t* m) {
+  double width = 2.0 * E;
+  for (uint64_t j = 0; j < n; j++) {
+    if (valid[j])
+      m[j] = (int64_t)floor((d[j] - lo) / width);
+    else
+      m[j] = -1;
+  }
+}
+
+/* ------------------------------------------------ step 4: histogram */
+
+static int cmp_i64(const void* a, const void* b) {
+  int64_t x = *(const int64_t*)a, y = *(const int64_t*)b;
+  return (x > y) - (x < y);
+}
+
+int64_t orc_histogram(const int64_t* m, const uint8_t* valid, uint64_t n, int64_t* ids,
+                      uint32_t* counts) {
+  int64_t* s = (int64_t*)malloc((n ? n : 1) * sizeof(int64_t));
+  if (!s) return -1;
+  uint64_t nv = 0;
+  for (uint64_t j = 0; j < n; j++)
+    if (valid[j]) s[nv++] = m[j];
+  qsort(s, nv, sizeof(int64_t), cmp_i64);
+  int64_t nb = 0;
+  for (uint64_t i = 0; i < nv; i++) {
+    if (nb > 0 && ids[nb - 1] == s[i]) {
+      counts[nb - 1] += 1;
+    } else {
+      ids[nb] = s[i];
+      counts[nb] = 1;
+      nb++;
+    }
+  }
+  free(s);
+  return nb;
+}
+
+/* ------------------------------------------------ step 5: top-k selection */
+
+typedef struct {
+  int64_t id;
+  uint32_t count;
+} bin_t;
+
+/* Larger count first; equal counts: lower bin id first. */
+static int cmp_rank(const void* a, const void* b) {
+  const bin_t* x = (const bin_t*)a;
+  const bin_t* y = (const bin_t*)b;
+  if (x->count != y->count) return x->count > y->count ? -1 : 1;
+  return (x->id > y->id) - (x->id < y->id);
+}
+
+int64_t orc_topk(const int64_t* ids, const uint32_t* counts, int64_t nbins, uint32_t k,
+                 int64_t* sel, uint32_t* tau) {
+  bin_t* b = (bin_t*)malloc((nbins ? nbins : 1) * sizeof(bin_t));
+  if (!b) return -1;
+  for (int64_t i = 0; i < nbins; i++) {
+    b[i].id = ids[i];
+    b[i].count = counts[i];
+  }
+  qsort(b, (size_t)nbins, sizeof(bin_t), cmp_rank);
+  int64_t take = nbins < (int64_t)k ? nbins : (int64_t)k;
+  for (int64_t i = 0; i < take; i++) sel[i] = b[i].id;
+  *tau = nbins > (int64_t)k ? b[take - 1].count : 0;
+  free(b);
+  qsort(sel, (size_t)take, sizeof(int64_t), cmp_i64);
+  return take;
+}
+
+/* ------------------------------------------------ bit packing (Sec. IV-C) */
+
+static void put_index(uint32_t* packed, uint64_t j, uint32_t B, uint32_t idx) {
+  for (uint32_t b = 0; b < B; b++) {
+    uint64_t bit = j * B + b;
+    if ((idx >> b) & 1u) packed[bit >> 5] |= 1u << (bit & 31);
+  }
+}
+
+static uint32_t get_index(const uint32_t* packed, uint64_t j, uint32_t B) {
+  uint32_t idx = 0;
+  for (uint32_t b = 0; b < B; b++) {
+    uint64_t bit = j * B + b;
+    idx |= ((packed[bit >> 5] >> (bit & 31)) & 1u) << b;
+  }
+  return idx;
+}
+
+static int64_t find_sorted(const int64_t* a, int64_t len, int64_t key) {
+  const int64_t* hit = (const int64_t*)bsearch(&key, a, (size_t)len, sizeof(int64_t), cmp_i64);
+  return hit ? (int64_t)(hit - a) : -1;
+}
+
+/* ------------------------------------------------ the whole compression */
+
+int orc_compress(const void* prev, const void* curr, uint64_t n, int dtype, double E,
+                 uint32_t B, uint64_t block_bytes, uint32_t* packed, void* centers,
+                 void* incomp, int64_t* block_inc_off, void* recon, uint16_t* index,
+                 int64_t* sel_ids, orc_info* info) {
+  int st = check_args(dtype, E, B);
+  if (st != ORC_OK) return st;
+  if (n >= ((uint64_t)1 << 32)) return ORC_EINVAL;
+  if (!info || (n && (!prev || !curr || !incomp || !packed)) || !centers) return ORC_EINVAL;
+  if (block_bytes == 0) block_bytes = (uint64_t)1 << 20;
+
+  const uint32_t k = (1u << B) - 1u;
+  const uint32_t esc = k;
+  const size_t L = elem_size(dtype);
+  const uint64_t nn = n ? n : 1;
+
+  double* d = (double*)malloc(nn * sizeof(double));
+  uint8_t* valid = (uint8_t*)malloc(nn);
+  int64_t* m = (int64_t*)malloc(nn * sizeof(int64_t));
+  int64_t* hid = (int64_t*)malloc(nn * sizeof(int64_t));
+  uint32_t* hcnt = (uint32_t*)malloc(nn * sizeof(uint32_t));
+  int64_t* sel = (int64_t*)malloc((size_t)k * sizeof(int64_t));
+  uint32_t* idx = (uint32_t*)malloc(nn * sizeof(uint32_t));
+  if (!d || !valid || !m || !hid || !hcnt || !sel || !idx) {
+    free(d); free(valid); free(m); free(hid); free(hcnt); free(sel); free(idx);
+    return ORC_ENOMEM;
+  }
+
+  /* steps 1-2 */
+  orc_ratio(prev, curr, n, dtype, E, d, valid);
+  double lo = 0.0, hi = 0.0;
+  uint64_t n_valid = orc_range(d, valid, n, &lo, &hi);
+
+  /* steps 3-5 */
+  int64_t M = 0, nbins = 0, k_used = 0;
+  uint32_t tau = 0;
+  if (n_valid > 0) {
+    orc_bin_ids(d, valid, n, lo, E, m);
+    M = (int64_t)floor((hi - lo) / (2.0 * E)) + 1;
+    nbins = orc_histogram(m, valid, n, hid, hcnt);
+    k_used = orc_topk(hid, hcnt, nbins, k, sel, &tau);
+  } else {
+    lo = 0.0;
+    hi = 0.0;
+  }
+
+  /* bin centres: c = lo + (2m + 1) E, stored in the snapshot type; unused slots 0 */
+  memset(centers, 0, ((size_t)1 << B) * L);
+  for (int64_t i = 0; i < k_used; i++)
+    store_rounded(centers, dtype, (uint64_t)i, lo + (double)(2 * sel[i] + 1) * E);
+
+  /* step 5-6: index every point, verify the bound after rounding */
+  uint64_t n_inc = 0;
+  for (uint64_t j = 0; j < n; j++) {
+    uint32_t code = esc;
+    if (valid[j]) {
+      int64_t i = find_sorted(sel, k_used, m[j]);
+      if (i >= 0) {
+        double p = load_as_double(prev, dtype, j);
+        double q = load_as_double(curr, dtype, j);
+        double c = load_as_double(centers, dtype, (uint64_t)i);
+        double r = rounded_to_type(dtype, p * (1.0 + c));
+        if (fabs(r - q) <= E * fabs(p)) {
+          code = (uint32_t)i;
+          if (recon) store_rounded(recon, dtype, j, r);
+        }
+      }
+    }
+    if (code == esc) {
+      copy_elem(incomp, n_inc, curr, j, dtype);
+      n_inc++;
+      if (recon) copy_elem(recon, j, curr, j, dtype);
+    }
+    idx[j] = code;
+    if (index) index[j] = (uint16_t)code;
+  }
+
+  /* step 7: packing */
+  uint64_t words = (n * B + 31) / 32;
+  memset(packed, 0, words * 4);
+  for (uint64_t j = 0; j < n; j++) put_index(packed, j, B, idx[j]);
+
+  /* step 8: per-block offsets into the incompressible array */
+  uint64_t epb = (8 * block_bytes) / B;
+  uint64_t n_blocks = (n + epb - 1) / epb;
+  {
+    uint64_t seen = 0;
+    for (uint64_t j = 0; j < n; j++) {
+      if (j % epb == 0 && block_inc_off) block_inc_off[j / epb] = (int64_t)seen;
+      if (idx[j] == esc) seen++;
+    }
+  }
+
+  if (sel_ids)
+    for (int64_t i = 0; i < k_used; i++) sel_ids[i] = sel[i];
+
+  info->n = n;
+  info->n_valid = n_valid;
+  info->n_invalid = n - n_valid;
+  info->n_inc = n_inc;
+  info->n_blocks = n_blocks;
+  info->elems_per_block = epb;
+  info->block_bytes = block_bytes;
+  info->M = M;
+  info->n_nonzero = (uint64_t)nbins;
+  info->B = B;
+  info->k = k;
+  info->k_used = (uint32_t)k_used;
+  info->dtype = (uint32_t)dtype;
+  info->tau = tau;
+  info->E = E;
+  info->lo = lo;
+  info->hi = hi;
+  info->packed_words = words;
+  info->packed_bytes = words * 4;
+  /* eq. (6) with the actual packed size: 2^B L + packed + n_inc L */
+  info->compressed_bytes = ((uint64_t)1 << B) * L + words * 4 + n_inc * L;
+
+  free(d); free(valid); free(m); free(hid); free(hcnt); free(sel); free(idx);
+  return ORC_OK;
+}
+
+/* ------------------------------------------------ decompression, eq. (4) */
+
+static void decode_one(const orc_info* info, const void* prev, const uint32_t* packed,
+                       const void* centers, const void* incomp, uint64_t j, uint64_t* rank,
+                       void* out, uint64_t oj, uint32_t* flags) {
+  int dtype = (int)info->dtype;
+  uint32_t esc = (1u << info->B) - 1u;
+  uint32_t code = get_index(packed, j, info->B);
+  if (code == esc) {
+    if (*rank < info->n_inc) {
+      copy_elem(out, oj, incomp, *rank, dtype);
+    } else {
+      *flags |= ORC_FLAG_INC_OVERRUN;
+      zero_elem(out, oj, dtype);
+    }
+    *rank += 1;
+    return;
+  }
+  if (code >= info->k_used) *flags |= ORC_FLAG_BAD_INDEX;
+  double p = load_as_double(prev, dtype, j);
+  double c = load_as_double(centers, dtype, code);
+  store_rounded(out, dtype, oj, p * (1.0 + c));
+}
+
+int orc_decompress(const orc_info* info, const void* prev, const uint32_t* packed,
+                   const void* centers, const void* incomp, void* out, uint32_t* flags) {
+  if (!info || !flags) return ORC_EINVAL;
+  *flags = 0;
+  uint64_t rank = 0;
+  for (uint64_t j = 0; j < info->n; j++)
+    decode_one(info, prev, packed, centers, incomp, j, &rank, out, j, flags);
+  return ORC_OK;
+}
+
+int orc_decompress_range(const orc_info* info, const void* prev, const uint32_t* packed,
+                         const void* centers, const void* incomp,
+                         const int64_t* block_inc_off, uint64_t start, uint64_t len,
+                         void* out, uint32_t* flags) {
+  if (!info || !flags) return ORC_EINVAL;
+  if (start > info->n || len > info->n - start) return ORC_ERANGE;
+  *flags = 0;
+  if (len == 0) return ORC_OK;
+  uint32_t esc = (1u << info->B) - 1u;
+  uint64_t epb = info->elems_per_block;
+  uint64_t blk = start / epb;
+  /* escapes before the block come from the offset table, the rest by counting */
+  uint64_t rank = (uint64_t)block_inc_off[blk];
+  for (uint64_t j = blk * epb; j < start; j++)
+    if (get_index(packed, j, info->B) == esc) rank++;
+  for (uint64_t t = 0; t < len; t++)
+    decode_one(info, prev, packed, centers, incomp, start + t, &rank, out, t, flags);
+  return ORC_OK;
+}

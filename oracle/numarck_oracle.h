@@ -1,0 +1,101 @@
+/*
+ * numarck_oracle.h -- plain CPU reference of the NUMARCK compression path.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library includes, links
+ * or calls this code; only the tests, the smoke check and the CPU-baseline leg
+ * of the benchmark use it.  It shares no header, helper or table with the
+ * HIP implementation.
+ *
+ * Every routine works in IEEE-754 binary64 with round-to-nearest-even,
+ * evaluates expressions in the order written and must be compiled without
+ * floating-point contraction (-ffp-contract=off) and without fast-math.
+ *
+ * Notation (Sec. III): n points, error bound E, B index bits,
+ * k = 2^B - 1 selectable bins, escape code ESC = 2^B - 1, L = sizeof(T).
+ */
+#ifndef NUMARCK_ORACLE_H
+#define NUMARCK_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { ORC_F32 = 0, ORC_F64 = 1 };
+
+enum {
+  ORC_OK = 0,
+  ORC_EINVAL = 1,  /* null pointer or n too large */
+  ORC_EDTYPE = 2,  /* dtype not f32/f64 */
+  ORC_EBITS = 3,   /* B outside [1, 16] */
+  ORC_EBOUND = 4,  /* E not in (0, 1] */
+  ORC_ENOMEM = 5,  /* host allocation failed */
+  ORC_ERANGE = 6   /* start + len > n */
+};
+
+/* Decompression flags (ORed). */
+#define ORC_FLAG_BAD_INDEX 1u    /* an index in [k_used, ESC) was found */
+#define ORC_FLAG_INC_OVERRUN 2u  /* more escape codes than stored values */
+
+typedef struct {
+  uint64_t n, n_valid, n_invalid, n_inc;
+  uint64_t n_blocks, elems_per_block, block_bytes;
+  int64_t M;            /* number of fine bins, 0 when no point is valid */
+  uint64_t n_nonzero;   /* bins with a nonzero count */
+  uint32_t B, k, k_used, dtype;
+  uint32_t tau;         /* smallest selected count; 0 when every nonzero bin is selected */
+  double E, lo, hi;
+  uint64_t packed_words, packed_bytes, compressed_bytes;
+} orc_info;
+
+/* Step 1, eq. (1): change ratio and validity of every point. */
+int orc_ratio(const void* prev, const void* curr, uint64_t n, int dtype, double E,
+              double* d, uint8_t* valid);
+
+/* Step 2 (Sec. IV-A): range of the valid ratios. Returns the number of valid points. */
+uint64_t orc_range(const double* d, const uint8_t* valid, uint64_t n, double* lo, double* hi);
+
+/* Step 3 (Sec. IV-B-1): fine bin id of each valid point (bins of width 2E anchored at lo). */
+void orc_bin_ids(const double* d, const uint8_t* valid, uint64_t n, double lo, double E,
+                 int64_t* m);
+
+/* Step 4 (Sec. IV-B-1): histogram as ascending (id, count) pairs over nonzero bins.
+ * ids/counts need room for n entries.  Returns the number of nonzero bins. */
+int64_t orc_histogram(const int64_t* m, const uint8_t* valid, uint64_t n, int64_t* ids,
+                      uint32_t* counts);
+
+/* Step 5 (Sec. IV-B-1/2): top-k selection.  sel receives min(k, nbins) ids in
+ * ascending order.  Returns that number; *tau gets the smallest selected count
+ * (0 when every nonzero bin was selected). */
+int64_t orc_topk(const int64_t* ids, const uint32_t* counts, int64_t nbins, uint32_t k,
+                 int64_t* sel, uint32_t* tau);
+
+/* The whole compression of one snapshot pair.
+ *   packed         : ceil(n*B/32) u32 words
+ *   centers        : 2^B values of the snapshot type
+ *   incomp         : room for n values of the snapshot type
+ *   block_inc_off  : ceil(n / elems_per_block) int64
+ *   recon, index   : optional (NULL) n values / n u16 indices
+ *   sel_ids        : optional (NULL) 2^B - 1 int64, selected bin ids in index order
+ * block_bytes = 0 means 2^20. */
+int orc_compress(const void* prev, const void* curr, uint64_t n, int dtype, double E,
+                 uint32_t B, uint64_t block_bytes, uint32_t* packed, void* centers,
+                 void* incomp, int64_t* block_inc_off, void* recon, uint16_t* index,
+                 int64_t* sel_ids, orc_info* info);
+
+/* Full decompression, eq. (4). *flags receives ORC_FLAG_* bits. */
+int orc_decompress(const orc_info* info, const void* prev, const uint32_t* packed,
+                   const void* centers, const void* incomp, void* out, uint32_t* flags);
+
+/* Partial decompression of [start, start+len) through the per-block
+ * incompressible offsets (Sec. IV-C).  prev is the whole previous snapshot. */
+int orc_decompress_range(const orc_info* info, const void* prev, const uint32_t* packed,
+                         const void* centers, const void* incomp,
+                         const int64_t* block_inc_off, uint64_t start, uint64_t len,
+                         void* out, uint32_t* flags);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

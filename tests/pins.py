@@ -1,0 +1,484 @@
+"""Pins: checks that tie the CPU oracle to what the paper and plain mathematics
+fix, without re-deriving the oracle's own arithmetic.
+
+Every check takes an ``oracle.Oracle`` (the real one, or a copy compiled with a
+planted mistake) and raises AssertionError on failure.  The kinds of pins:
+
+* exact rationals (``fractions.Fraction``): the change ratio of eq. (1), bin
+  membership of Sec. IV-B-1, bin centres, and the element-wise error bound
+  (Sec. III, VI), each within the rounding the binary64 evaluation allows;
+* closed forms on constructed inputs whose ratios sit exactly on bin centres,
+  so the selected bins, the indices and the escapes are known by construction;
+* brute force on tiny inputs: top-k by rank counting, the index-table bit
+  string built character by character, block offsets by direct counting;
+* library/textbook special cases: min/max of the valid ratios;
+* the paper's printed numbers: Fig. 2's block layout and the CMIP
+  compression-ratio example of Sec. V-B (fixtures under ``tests/golden``);
+* the dynamic-programming optimum of Sec. V-D as an upper bound on coverage.
+"""
+from __future__ import annotations
+
+import bisect
+import math
+import os
+from fractions import Fraction
+
+import numpy as np
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def read_golden(name: str) -> dict:
+    out = {}
+    with open(os.path.join(GOLDEN, name)) as f:
+        for line in f:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            k, v = (s.strip() for s in line.split("=", 1))
+            out[k] = float(v) if any(c in v for c in ".e") else int(v)
+    return out
+
+
+# ----------------------------------------------------------------- inputs
+
+def mixture_case(n: int, seed: int, dtype=np.float64, E=1e-3):
+    """Lognormal previous values with 0.1 % zeros; ratio mixture
+    70 % N(0, 2E), 25 % N(10E, 5E), 5 % U[-0.5, 0.5]."""
+    rng = np.random.default_rng(seed)
+    prev = rng.lognormal(0.0, 1.0, n)
+    prev[rng.choice(n, max(1, n // 1000), replace=False)] = 0.0
+    u = rng.random(n)
+    r = np.where(u < 0.7, rng.normal(0, 2 * E, n),
+                 np.where(u < 0.95, rng.normal(10 * E, 5 * E, n), rng.uniform(-0.5, 0.5, n)))
+    if dtype == np.float32:
+        p32 = prev.astype(np.float32)
+        return p32, (p32.astype(np.float64) * (1 + r)).astype(np.float32)
+    return prev, prev * (1 + r)
+
+
+def adversarial_case(dtype=np.float64):
+    """Signed zeros, infinities, NaNs with payloads, subnormals, huge values,
+    equal values, negative values, and ratios just inside/outside the cap."""
+    tiny = np.finfo(dtype).smallest_subnormal
+    big = np.finfo(dtype).max
+    nan_payload = (np.array([0x7FF8DEADBEEF0001], np.uint64).view(np.float64)[0]
+                   if dtype == np.float64 else
+                   np.array([0x7FC0BEEF], np.uint32).view(np.float32)[0])
+    prev = np.array([0.0, -0.0, 1.0, np.inf, 1.0, -np.inf, 1.0, tiny, 2.0, big, -3.0,
+                     1.0, 1.0, 5.0, -5.0, 7.0, 1.0, 1.0, np.nan, 1.0], dtype)
+    curr = np.array([1.0, 2.0, np.inf, 1.0, -np.inf, 2.0, nan_payload, 1.0, 2.0, big, -3.0,
+                     -0.0, 0.0, 5.0 * 1.0005, -5.0 * 1.0005, 7.0, tiny, -tiny, 1.0,
+                     nan_payload], dtype)
+    return prev, curr
+
+
+def cap_case(E: float):
+    """Ratios just above and just below the validity cap |d| <= E * 2^50."""
+    cap = math.ldexp(E, 50)
+    prev = np.array([1.0, 1.0, 1.0, 1.0, 1.0, 1.0])
+    curr = np.array([1.0 + 4 * cap, 1.0 + cap / 4, 1.0 - cap / 4, 1.0 - 4 * cap, 1.0, 1.0])
+    return prev, curr, np.array([False, True, True, False, True, True])
+
+
+def centred_case(counts: dict, dtype=np.float64, E_exp: int = -10, seed: int = 0):
+    """Points whose ratios are exactly (2m+1)E for bin m (E a power of two, the
+    grid anchored at 0 by a ratio-0 point that belongs to bin 0).  Every
+    product and quotient involved is exact, so a point is compressible exactly
+    when its bin is selected."""
+    E = 2.0 ** E_exp
+    rng = np.random.default_rng(seed)
+    bins = []
+    for m, c in sorted(counts.items()):
+        bins += [m] * c
+    bins = np.array(bins, np.int64)
+    d = (2 * bins + 1).astype(np.float64) * E
+    # the anchor: one point of bin 0 has ratio exactly 0
+    first0 = int(np.flatnonzero(bins == 0)[0])
+    d[first0] = 0.0
+    order = rng.permutation(bins.size)
+    bins, d = bins[order], d[order]
+    p = (2.0 ** rng.integers(-3, 4, bins.size)) * np.where(rng.random(bins.size) < 0.3, -1, 1)
+    q = p * (1.0 + d)
+    return p.astype(dtype), q.astype(dtype), bins, E
+
+
+# ------------------------------------------------------------- small helpers
+
+def bits(a: np.ndarray) -> np.ndarray:
+    a = np.ascontiguousarray(a)
+    return a.view(np.uint32 if a.dtype == np.float32 else np.uint64)
+
+
+def F(x) -> Fraction:
+    return Fraction(float(x))
+
+
+def type_ulp(x: float, dtype) -> float:
+    if dtype == np.float32:
+        return float(np.spacing(np.float32(abs(x))))
+    return math.ulp(abs(x))
+
+
+# ------------------------------------------------------------------- pins
+
+def pin_ratio_exact(o):
+    """eq. (1): the ratio equals (q - p)/p to within two binary64 roundings."""
+    for dt in (np.float64, np.float32):
+        p, q = mixture_case(3000, 5, dt)
+        d, v = o.ratio(p, q, 1e-3)
+        for j in np.flatnonzero(v)[:800]:
+            ex = (F(q[j]) - F(p[j])) / F(p[j])
+            err = abs(F(d[j]) - ex)
+            assert err <= 2 * Fraction(math.ulp(float(ex))) + Fraction(1, 2 ** 1074), \
+                f"ratio mismatch at {j}: {d[j]} vs {float(ex)}"
+
+
+def pin_validity(o):
+    """Invalid points: zero or non-finite previous value, non-finite new value
+    or ratio, |ratio| beyond E*2^50."""
+    for dt in (np.float64, np.float32):
+        p, q = adversarial_case(dt)
+        _, v = o.ratio(p, q, 1e-3)
+        with np.errstate(all="ignore"):
+            pp, qq = p.astype(np.float64), q.astype(np.float64)
+            r = (qq - pp) / pp
+            exp = (pp != 0) & np.isfinite(pp) & np.isfinite(qq) & np.isfinite(r) & \
+                (np.abs(r) <= math.ldexp(1e-3, 50))
+        assert np.array_equal(v, exp), (v, exp)
+    p, q, exp = cap_case(1e-3)
+    _, v = o.ratio(p, q, 1e-3)
+    assert np.array_equal(v, exp), (v, exp)
+
+
+def pin_range_minmax(o):
+    """Sec. IV-A: lo/hi are the minimum and maximum of the valid ratios."""
+    for seed in range(3):
+        p, q = mixture_case(2000, 100 + seed)
+        d, v = o.ratio(p, q, 1e-3)
+        nv, lo, hi = o.range(d, v)
+        assert nv == int(v.sum())
+        assert lo == d[v].min() and hi == d[v].max()
+    d = np.array([3.0, -0.0, 0.0, 5.0, -1.0])
+    nv, lo, hi = o.range(d, np.array([0, 1, 1, 0, 0], bool))
+    assert nv == 2 and lo == 0.0 and math.copysign(1, lo) < 0 and math.copysign(1, hi) > 0
+
+
+def pin_bins_exact(o):
+    """Sec. IV-B-1: bins of width 2E anchored at lo; the binary64 bin id is the
+    exact floor((d - lo)/(2E)) except within rounding of a bin edge."""
+    for E in (1e-3, 1e-4, 0.05):
+        p, q = mixture_case(3000, 7, E=E)
+        d, v = o.ratio(p, q, E)
+        _, lo, hi = o.range(d, v)
+        m = o.bin_ids(d, v, lo, E)
+        for j in np.flatnonzero(v)[:1500]:
+            t = (F(d[j]) - F(lo)) / (2 * F(E))
+            fl = math.floor(t)
+            near = min(t - fl, fl + 1 - t) < Fraction(1, 10 ** 9) * (1 + t)
+            assert m[j] == fl or (near and abs(m[j] - fl) <= 1), (j, m[j], float(t))
+        assert np.all(m[~v] == -1)
+
+
+def pin_histogram(o):
+    """Counts sum to the number of valid points and equal a direct count of
+    the exact bins (points near a bin edge excluded from the comparison)."""
+    E = 1e-3
+    p, q = mixture_case(4000, 9)
+    d, v = o.ratio(p, q, E)
+    _, lo, _ = o.range(d, v)
+    m = o.bin_ids(d, v, lo, E)
+    ids, cnt = o.histogram(m, v)
+    assert int(cnt.sum()) == int(v.sum())
+    assert np.all(np.diff(ids) > 0) and np.all(cnt > 0)
+    exact = {}
+    for j in np.flatnonzero(v):
+        t = (F(d[j]) - F(lo)) / (2 * F(E))
+        b = math.floor(t)
+        exact[b] = exact.get(b, 0) + 1
+    got = dict(zip(ids.tolist(), cnt.tolist()))
+    diff = sum(abs(exact.get(b, 0) - got.get(b, 0)) for b in set(exact) | set(got))
+    assert diff <= 2, diff  # at most an edge point moving between neighbours
+
+
+def _brute_topk(ids, counts, k):
+    """b is selected iff fewer than k nonzero bins precede it, where a bin
+    precedes another when its count is larger, or equal with a lower id."""
+    sel = []
+    for i in range(len(ids)):
+        ahead = 0
+        for j in range(len(ids)):
+            if counts[j] > counts[i] or (counts[j] == counts[i] and ids[j] < ids[i]):
+                ahead += 1
+        if ahead < k:
+            sel.append(ids[i])
+    return sorted(sel)
+
+
+def pin_topk_brute(o):
+    """Sec. IV-B-1: the k bins with most points, ties to the lower id."""
+    rng = np.random.default_rng(3)
+    for trial in range(40):
+        nb = int(rng.integers(1, 60))
+        ids = np.sort(rng.choice(10 ** 6, nb, replace=False)).astype(np.int64)
+        counts = rng.integers(1, 6, nb).astype(np.uint32)  # many ties
+        k = int(rng.integers(1, 40))
+        sel, tau = o.topk(ids, counts, k)
+        exp = _brute_topk(ids.tolist(), counts.tolist(), k)
+        assert sel.tolist() == exp, (trial, sel, exp)
+        if nb > k:
+            assert tau == min(int(counts[ids.tolist().index(s)]) for s in exp)
+        else:
+            assert tau == 0
+
+
+def pin_centred_literal(o):
+    """Constructed bin-centred data: counts {0:4, 1:7, 2:5, 3:5, 4:5, 6:1},
+    B = 2 (k = 3).  Top-3 = bin 1 (7 points) and, of the three bins tied at 5,
+    the two lowest: bins 2 and 3.  Indices follow bin order: 1->0, 2->1, 3->2.
+    M = floor(13E/2E) + 1 = 7.  Every point of a selected bin is reconstructed
+    exactly; every other point escapes."""
+    for dt in (np.float64, np.float32):
+        p, q, b, E = centred_case({0: 4, 1: 7, 2: 5, 3: 5, 4: 5, 6: 1}, dt)
+        res = o.compress(p, q, E, 2)
+        h = res.info
+        assert h["M"] == 7 and h["lo"] == 0.0 and h["k_used"] == 3 and h["n_nonzero"] == 6
+        assert res.sel_ids.tolist() == [1, 2, 3]
+        assert h["tau"] == 5
+        want = np.where(b == 1, 0, np.where(b == 2, 1, np.where(b == 3, 2, 3)))
+        assert np.array_equal(res.index, want), (res.index, want)
+        ok = want != 3
+        assert np.array_equal(bits(res.recon[ok]), bits(q[ok]))  # exact reconstruction
+        assert np.array_equal(bits(res.incomp), bits(q[~ok]))
+        cen = res.centers.astype(np.float64)
+        assert cen.tolist() == [3 * E, 5 * E, 7 * E, 0.0]
+
+
+def pin_centred_small_k(o):
+    """B = 1 picks the single fullest bin (tie -> lower id); with fewer
+    nonzero bins than k every nonzero bin is selected."""
+    p, q, b, E = centred_case({0: 3, 2: 3, 4: 2})
+    res = o.compress(p, q, E, 1)
+    assert res.sel_ids.tolist() == [0] and res.info["k_used"] == 1
+    assert np.array_equal(res.index, np.where(b == 0, 0, 1))
+    p, q, b, E = centred_case({0: 1, 3: 2, 9: 1})
+    res = o.compress(p, q, E, 4)
+    assert res.sel_ids.tolist() == [0, 3, 9] and res.info["k_used"] == 3 and res.info["tau"] == 0
+    assert np.array_equal(res.index, np.where(b == 0, 0, np.where(b == 3, 1, 2)))
+    assert res.info["n_inc"] == 0
+
+
+def pin_all_equal(o):
+    """All ratios equal: one bin, M = 1, lo = hi = that ratio."""
+    p = np.array([1.0, 2.0, 4.0, -8.0, 0.5] * 20)
+    q = p * 1.25
+    res = o.compress(p, q, 1e-3, 8)
+    h = res.info
+    assert h["M"] == 1 and h["n_nonzero"] == 1 and h["k_used"] == 1
+    assert h["lo"] == 0.25 and h["hi"] == 0.25 and res.sel_ids.tolist() == [0]
+
+
+def pin_error_bound_exact(o):
+    """Sec. III/VI: every indexed point is reconstructed within E|prev|
+    (exact rationals; slack for the binary64 comparison) and its ratio lies
+    within E of its bin centre (plus the centre's rounding); centres equal
+    lo + (2m+1)E rounded to the snapshot type."""
+    cases = [(np.float64, 1e-3, 8), (np.float32, 1e-3, 8), (np.float32, 2.0 ** -23, 8),
+             (np.float64, 1e-12, 6)]
+    for dt, E, B in cases:
+        p, q = mixture_case(3000, 21, dt, E=max(E, 1e-6) if dt == np.float32 else E)
+        if dt == np.float32 and E < 1e-6:  # ratios comparable to float32 rounding
+            rng = np.random.default_rng(22)
+            p = rng.lognormal(0, 1, 3000).astype(np.float32)
+            q = (p.astype(np.float64) * (1 + rng.normal(0, 3e-6, 3000))).astype(np.float32)
+        res = o.compress(p, q, E, B)
+        d, v = o.ratio(p, q, E)
+        lo = res.info["lo"]
+        for i, m in enumerate(res.sel_ids.tolist()):
+            c = F(res.centers[i])
+            ex = F(lo) + (2 * m + 1) * F(E)
+            # two binary64 roundings (product, sum) plus the rounding to the type
+            tol = Fraction(math.ulp(max(abs(lo), (2 * m + 1) * E))) + \
+                Fraction(type_ulp(float(ex), dt))
+            assert abs(c - ex) <= tol, (i, m)
+        idx = res.index.astype(np.int64)
+        comp = np.flatnonzero(idx != (1 << B) - 1)
+        assert comp.size > 0
+        slack = 1 + Fraction(1, 2 ** 50)
+        for j in comp:
+            r, pj, qj = F(res.recon[j]), F(p[j]), F(q[j])
+            assert abs(r - qj) <= F(E) * abs(pj) * slack, (dt, E, j)
+            c = F(res.centers[idx[j]])
+            tol = F(E) * (1 + Fraction(1, 2 ** 40)) + 4 * Fraction(type_ulp(float(c), dt))
+            assert abs(F(d[j]) - c) <= tol, (dt, E, j)
+
+
+def pin_escapes_bitexact(o):
+    """Sec. III-C: incompressible values are stored as they are, in element
+    order (signed zeros and NaN payloads preserved); invalid points escape."""
+    for dt in (np.float64, np.float32):
+        p, q = adversarial_case(dt)
+        res = o.compress(p, q, 1e-3, 4)
+        esc = res.index == (1 << 4) - 1
+        _, v = o.ratio(p, q, 1e-3)
+        assert np.all(esc[~v])
+        assert np.array_equal(bits(res.incomp), bits(q[esc]))
+        assert np.array_equal(bits(res.recon[esc]), bits(q[esc]))
+
+
+def pin_packing_bitstring(o):
+    """Sec. IV-C: the index table is the concatenation of the B low bits of each
+    index, least significant bit first, cut into 32-bit little-endian words."""
+    for B in (1, 3, 8, 10, 13, 16):
+        p, q = mixture_case(777, 40 + B)
+        res = o.compress(p, q, 1e-3, B)
+        s = "".join(format(int(i), f"0{B}b")[::-1] for i in res.index)
+        s += "0" * (-len(s) % 32)
+        words = [int(s[w:w + 32][::-1], 2) for w in range(0, len(s), 32)]
+        assert res.packed.tolist() == words, B
+
+
+def pin_block_offsets(o):
+    """Sec. IV-C: block p starts at element p * floor(8 * bytes / B) and stores
+    the number of incompressible points before it."""
+    p, q = mixture_case(5000, 55)
+    for B, bb in ((8, 64), (5, 100), (13, 333)):
+        res = o.compress(p, q, 1e-3, B, block_bytes=bb)
+        epb = (8 * bb) // B
+        assert res.info["elems_per_block"] == epb
+        assert res.info["n_blocks"] == -(-5000 // epb) == res.block_inc_off.size
+        esc = res.index == (1 << B) - 1
+        for blk in range(res.block_inc_off.size):
+            assert res.block_inc_off[blk] == int(esc[: blk * epb].sum())
+
+
+def pin_fig2_layout(o):
+    """Fig. 2: UU of ASR, n = 3,758,400 points, B = 13, 1 MB blocks ->
+    8192 centres, 645,277 indices per block, 6 blocks."""
+    g = read_golden("fig2_asr_uu_header.txt")
+    n = g["total_data_num"]
+    p = np.ones(n, np.float32)
+    res = o.compress(p, p, 1e-3, g["index_bits"], block_bytes=g["block_bytes"], recon=False)
+    assert res.centers.size == g["bin_centers_number"]
+    assert res.info["elems_per_block"] == g["elements_per_block"]
+    assert res.info["n_blocks"] == g["block_table_dim"]
+
+
+def pin_cmip_cr(o):
+    """Sec. V-B: with 12-bit indices, 2 % incompressible float32 points and a
+    2.2x lossless index-table stage the compression ratio is about 5.2; the
+    size accounting (2^B centres + n B bits + alpha n L, eq. (6)) must match the
+    returned arrays and reproduce the example."""
+    g = read_golden("cmip_cr_example.txt")
+    n = 500_000
+    B = g["index_bits"]
+    rng = np.random.default_rng(0)
+    E = 2.0 ** -10
+    # every valid ratio is exactly +E/2 except one anchor at -E/2, so the single
+    # bin's centre is +E/2 and every valid point is reconstructed within E
+    p = (2.0 ** rng.integers(-3, 4, n)).astype(np.float32)
+    q = p * np.float32(1 + 2.0 ** -11)
+    q[0] = p[0] * np.float32(1 - 2.0 ** -11)
+    nz = int(round(g["incompressible_fraction"] * n))
+    p[1 + rng.choice(n - 1, nz, replace=False)] = 0.0  # invalid -> incompressible
+    res = o.compress(p, q, E, B, recon=False)
+    h = res.info
+    assert h["n_inc"] == nz
+    L = g["value_bits"] // 8
+    assert h["compressed_bytes"] == res.centers.size * L + res.packed.size * 4 + res.incomp.size * L
+    assert res.packed.size == -(-n * B // 32)
+    cr_idx = (n * L) / (res.packed.size * 4 / g["index_table_lossless_ratio"] + res.incomp.size * L)
+    assert round(cr_idx, int(g["reported_digits"])) in (5.2, 5.3), cr_idx
+    assert abs(cr_idx - g["reported_cr"]) < 0.1
+
+
+def pin_roundtrip(o):
+    """Sec. III-E and V-C: decompression reproduces the compressor's
+    reconstruction bit for bit, and a partial decompression of [s, s+len)
+    equals that slice, for ranges inside one block, across blocks, and empty."""
+    rng = np.random.default_rng(77)
+    for dt, B, bb in ((np.float64, 8, 256), (np.float32, 10, 1000), (np.float64, 3, 0)):
+        p, q = mixture_case(6000, 78, dt)
+        res = o.compress(p, q, 1e-3, B, block_bytes=bb)
+        out, fl = o.decompress(res, p)
+        assert fl == 0
+        assert np.array_equal(bits(out), bits(res.recon))
+        for _ in range(12):
+            s = int(rng.integers(0, 6000))
+            ln = int(rng.integers(0, 6000 - s + 1))
+            part, fl = o.decompress_range(res, p, s, ln)
+            assert fl == 0 and np.array_equal(bits(part), bits(out[s:s + ln]))
+        part, fl = o.decompress_range(res, p, 6000, 0)
+        assert part.size == 0
+
+
+def pin_decode_flags(o):
+    """A corrupt index table is reported, not silently decoded: an index in
+    [k_used, ESC) sets the bad-index flag; too many escapes set the overrun
+    flag."""
+    p, q, b, E = centred_case({0: 1, 3: 2, 9: 1})
+    res = o.compress(p, q, E, 4)
+    res.packed[0] = (res.packed[0] & ~np.uint32(0xF)) | np.uint32(7)  # index 7 >= k_used = 3
+    _, fl = o.decompress(res, p)
+    assert fl & 1
+    p2, q2 = adversarial_case()
+    res2 = o.compress(p2, q2, 1e-3, 4)
+    res2.packed[:] = np.uint32(0xFFFFFFFF)  # every index = ESC
+    res2.info["n_inc"] = 1
+    res2._info.n_inc = 1
+    _, fl = o.decompress(res2, p2)
+    assert fl & 2
+
+
+def pin_empty_and_tiny(o):
+    """n = 0 and n = 1, and an input with no valid point."""
+    e = np.zeros(0)
+    res = o.compress(e, e, 1e-3, 8)
+    assert res.info["n"] == 0 and res.info["n_blocks"] == 0 and res.packed.size == 0
+    res = o.compress(np.array([2.0]), np.array([2.0]), 1e-3, 8)
+    assert res.info["k_used"] == 1 and res.sel_ids.tolist() == [0] and res.info["n_blocks"] == 1
+    p = np.zeros(10)
+    res = o.compress(p, p + 1, 1e-3, 8)
+    assert res.info["n_inc"] == 10 and res.info["M"] == 0 and res.info["k_used"] == 0
+    assert res.centers.tolist() == [0.0] * 256
+
+
+def _dp_opt(vals, W, k):
+    """Sec. V-D (text form): OPT(i, j) = max(OPT(i+1, j), OPT(i+c(i), j-1) + c(i)),
+    c(i) = number of sorted values in [v_i, v_i + W]; OPT(N+1, .) = OPT(., 0) = 0."""
+    v = sorted(vals)
+    N = len(v)
+    c = [bisect.bisect_right(v, v[i] + W) - i for i in range(N)]
+    opt = [[0] * (k + 1) for _ in range(N + 2)]
+    for i in range(N - 1, -1, -1):
+        for j in range(1, k + 1):
+            opt[i][j] = max(opt[i + 1][j], opt[i + c[i]][j - 1] + c[i])
+    return opt[0][k]
+
+
+def pin_dp_bound(o):
+    """Sec. V-D: no choice of k bins of width 2E covers more ratios than the
+    dynamic-programming optimum; on bin-aligned clusters top-k attains it."""
+    for seed, B in ((1, 3), (2, 4), (3, 2)):
+        p, q = mixture_case(1200, 300 + seed)
+        res = o.compress(p, q, 1e-3, B)
+        d, v = o.ratio(p, q, 1e-3)
+        lo = res.info["lo"]
+        m = o.bin_ids(d, v, lo, 1e-3)
+        covered = int(np.isin(m[v], res.sel_ids).sum())
+        opt = _dp_opt(d[v].tolist(), 2e-3 * (1 + 1e-9), (1 << B) - 1)
+        assert covered <= opt, (covered, opt)
+    p, q, b, E = centred_case({0: 6, 2: 9, 5: 4, 8: 7, 9: 2})
+    res = o.compress(p, q, E, 2)
+    d, v = o.ratio(p, q, E)
+    opt = _dp_opt(d.tolist(), 2 * E * (1 - 1e-9), 3)
+    assert opt == 22 and int((res.index != 3).sum()) == 22
+
+
+ALL_PINS = [
+    pin_ratio_exact, pin_validity, pin_range_minmax, pin_bins_exact, pin_histogram,
+    pin_topk_brute, pin_centred_literal, pin_centred_small_k, pin_all_equal,
+    pin_error_bound_exact, pin_escapes_bitexact, pin_packing_bitstring, pin_block_offsets,
+    pin_fig2_layout, pin_cmip_cr, pin_roundtrip, pin_decode_flags, pin_empty_and_tiny,
+    pin_dp_bound,
+]

@@ -1,0 +1,74 @@
+"""Each plausible mistake planted in a copy of the oracle source must make at
+least one pin fail (CPU only; the real oracle is never modified)."""
+import os
+
+import pytest
+
+import oracle
+from pins import ALL_PINS
+
+SRC = os.path.join(os.path.dirname(oracle.__file__), "numarck_oracle.c")
+
+# (name, original text, planted mistake) -- each original occurs exactly once
+MUTANTS = [
+    ("ratio_sign", "double r = (q - p) / p;", "double r = (p - q) / p;"),
+    ("ratio_denominator", "double r = (q - p) / p;", "double r = (q - p) / q;"),
+    ("cap_dropped", "isfinite(r) && fabs(r) <= cap;", "isfinite(r);"),
+    ("lo_is_max", "if (precedes(d[j], mn)) mn = d[j];", "if (precedes(mn, d[j])) mn = d[j];"),
+    ("zero_order", "return a == b && signbit(a) && !signbit(b);", "return 0;"),
+    ("bin_width_E", "double width = 2.0 * E;", "double width = E;"),
+    ("bin_round", "(int64_t)floor((d[j] - lo) / width)", "(int64_t)round((d[j] - lo) / width)"),
+    ("bin_anchor", "(int64_t)floor((d[j] - lo) / width)", "(int64_t)floor(d[j] / width)"),
+    ("count_init", "counts[nb] = 1;", "counts[nb] = 0;"),
+    ("M_off_by_one", "M = (int64_t)floor((hi - lo) / (2.0 * E)) + 1;",
+     "M = (int64_t)floor((hi - lo) / (2.0 * E));"),
+    ("topk_ascending", "return x->count > y->count ? -1 : 1;", "return x->count < y->count ? -1 : 1;"),
+    ("tie_higher_id", "return (x->id > y->id) - (x->id < y->id);",
+     "return (x->id < y->id) - (x->id > y->id);"),
+    ("centre_lower_edge", "(double)(2 * sel[i] + 1) * E", "(double)(2 * sel[i]) * E"),
+    ("centre_upper_edge", "(double)(2 * sel[i] + 1) * E", "(double)(2 * sel[i] + 2) * E"),
+    ("recon_sign", "rounded_to_type(dtype, p * (1.0 + c));", "rounded_to_type(dtype, p * (1.0 - c));"),
+    ("recon_unrounded", "double r = rounded_to_type(dtype, p * (1.0 + c));", "double r = p * (1.0 + c);"),
+    ("verify_dropped", "if (fabs(r - q) <= E * fabs(p)) {", "if (1) {"),
+    ("verify_wrong_base", "if (fabs(r - q) <= E * fabs(p)) {", "if (fabs(r - q) <= E * fabs(q)) {"),
+    ("escape_stores_prev", "copy_elem(incomp, n_inc, curr, j, dtype);",
+     "copy_elem(incomp, n_inc, prev, j, dtype);"),
+    ("pack_msb_first", "if ((idx >> b) & 1u) packed[bit >> 5]",
+     "if ((idx >> (B - 1 - b)) & 1u) packed[bit >> 5]"),
+    ("block_size_bytes", "uint64_t epb = (8 * block_bytes) / B;", "uint64_t epb = block_bytes / B;"),
+    ("block_offset_inclusive",
+     "if (j % epb == 0 && block_inc_off) block_inc_off[j / epb] = (int64_t)seen;\n"
+     "      if (idx[j] == esc) seen++;",
+     "if (idx[j] == esc) seen++;\n"
+     "      if (j % epb == 0 && block_inc_off) block_inc_off[j / epb] = (int64_t)seen;"),
+    ("size_words_as_bytes", "+ words * 4 + n_inc * L;", "+ words + n_inc * L;"),
+    ("decode_sign", "store_rounded(out, dtype, oj, p * (1.0 + c));",
+     "store_rounded(out, dtype, oj, p * (1.0 - c));"),
+    ("range_rank_from_zero", "uint64_t rank = (uint64_t)block_inc_off[blk];", "uint64_t rank = 0;"),
+    ("bad_index_unflagged", "if (code >= info->k_used) *flags |= ORC_FLAG_BAD_INDEX;", "if (0) {}"),
+]
+
+
+def test_mutants_are_listed_uniquely():
+    src = open(SRC).read()
+    for name, old, _ in MUTANTS:
+        assert src.count(old) == 1, name
+
+
+@pytest.mark.parametrize("name,old,new", MUTANTS, ids=[m[0] for m in MUTANTS])
+def test_mutant_is_caught(tmp_path, name, old, new):
+    src = open(SRC).read().replace(old, new)
+    path = tmp_path / "mutant.c"
+    path.write_text(src)
+    import shutil
+    shutil.copy(os.path.join(os.path.dirname(SRC), "numarck_oracle.h"), tmp_path / "numarck_oracle.h")
+    lib = oracle.build(str(path), str(tmp_path / "libmutant.so"))
+    o = oracle.Oracle(lib)
+    failed = []
+    for pin in ALL_PINS:
+        try:
+            pin(o)
+        except (AssertionError, ValueError) as e:  # ValueError: status from the library
+            failed.append(pin.__name__)
+            break
+    assert failed, f"mutant {name} survived every pin"
