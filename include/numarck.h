@@ -1,0 +1,195 @@
+/*
+ * numarck.h -- C ABI of the MI355X (gfx950) NUMARCK compression library.
+ *
+ * NUMARCK ("Parallel Implementation of Lossy Data Compression for Temporal
+ * Data Sets", Yuan et al., arXiv 1703.02438) compresses a snapshot D_i of a
+ * simulation variable against the previous snapshot D_{i-1}:
+ *   - change ratio of every point, d_j = (D_i,j - D_i-1,j) / D_i-1,j   (eq. 1)
+ *   - a fine histogram of the ratios in bins of width 2E over their range,
+ *     and the k = 2^B - 1 bins holding the most points     (Sec. IV-A, IV-B-1)
+ *   - every point whose ratio falls in a selected bin is replaced by its
+ *     B-bit bin index; the others get the escape index 2^B - 1 and their
+ *     value is kept as is, in order, in the incompressible array (Sec. III-C)
+ *   - the indices are bit-packed into the index table, which is cut into
+ *     blocks; for each block the number of earlier incompressible points is
+ *     recorded so that any range can be decompressed on its own (Sec. IV-C)
+ *   - decompression multiplies the previous value by one plus the bin centre
+ *     of its index (eq. 4, Sec. III-E), fully or for a range (Sec. V-C).
+ *
+ * Conventions shared by every entry point:
+ *   - All data buffers are device memory owned by the caller.  The library
+ *     never allocates device memory and keeps no state between calls except
+ *     a per-device count of compute units and the optional timing records.
+ *   - Calls are asynchronous on `stream` (a hipStream_t; NULL = the null
+ *     stream).  The returned status reports argument validation and launch
+ *     errors only; data-dependent results (counts, flags) are written to
+ *     device memory and are valid once the stream reaches that point.
+ *   - Concurrent calls must use distinct workspaces and outputs.
+ *   - Arithmetic: binary64 for both snapshot types, round-to-nearest-even,
+ *     no contraction, subnormals kept.
+ *   - Readings of the paper used here: a point is valid when its previous
+ *     value is nonzero and finite, its new value is finite, and its ratio is
+ *     finite with |d| <= E * 2^50; invalid points are always incompressible.
+ *     Bin m holds the ratios with floor((d - lo) / (2E)) == m, lo being the
+ *     smallest valid ratio.  Ties between bins of equal count go to the
+ *     lower bin id; empty bins are never selected; selected bins are indexed
+ *     in ascending bin-id order.  Bin centre c_m = lo + (2m + 1) E rounded to
+ *     the snapshot type.  A point is indexed only if its reconstruction
+ *     T(p * (1 + c)) is within E * |p| of its value.
+ */
+#ifndef NUMARCK_H
+#define NUMARCK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Snapshot element type. */
+typedef enum { NUMARCK_F32 = 0, NUMARCK_F64 = 1 } numarck_dtype;
+
+/* Status returned by every entry point. */
+typedef enum {
+  NUMARCK_OK = 0,
+  NUMARCK_EINVAL = 1,    /* a required pointer is NULL, n >= 2^32, or a header is inconsistent */
+  NUMARCK_EDTYPE = 2,    /* dtype is not NUMARCK_F32 / NUMARCK_F64 */
+  NUMARCK_EBITS = 3,     /* B outside [1, 16] */
+  NUMARCK_EBOUND = 4,    /* E is not a number in (0, 1] */
+  NUMARCK_EALIGN = 5,    /* a snapshot pointer is not 16-byte aligned */
+  NUMARCK_ECAPACITY = 6, /* the workspace is smaller than the minimum for this call */
+  NUMARCK_EHIP = 7,      /* a HIP runtime call or kernel launch failed (see numarck_last_error) */
+  NUMARCK_ERANGE = 8     /* start + len > n */
+} numarck_status;
+
+/* Bits of numarck_header.flags (compression) and of the decompression flag word. */
+#define NUMARCK_FLAG_BAD_INDEX 1u     /* decompression met an index in [k_used, 2^B - 1) */
+#define NUMARCK_FLAG_INC_OVERRUN 2u   /* decompression met more escapes than n_inc */
+#define NUMARCK_FLAG_TAIL_OVERFLOW 4u /* compression: more points outside the on-chip bin
+                                         window than the workspace's tail capacity; the
+                                         outputs of that call are not valid */
+
+/* Result summary of one compression, written by the device (Fig. 2 holds the
+ * paper's version of these fields). */
+typedef struct numarck_header {
+  uint64_t n;                /* points */
+  uint64_t n_valid;          /* points with a valid change ratio */
+  uint64_t n_invalid;        /* n - n_valid */
+  uint64_t n_inc;            /* incompressible points (entries of incomp) */
+  uint64_t n_blocks;         /* index-table blocks = ceil(n / elems_per_block) */
+  uint64_t elems_per_block;  /* floor(8 * block_bytes / B) */
+  uint64_t block_bytes;      /* index-table block size used */
+  int64_t M;                 /* fine bins floor((hi - lo) / 2E) + 1; 0 if no valid point */
+  uint64_t n_nonzero;        /* fine bins holding at least one point */
+  uint32_t B;                /* index bits */
+  uint32_t k_used;           /* selected bins = min(2^B - 1, n_nonzero) */
+  uint32_t dtype;            /* numarck_dtype */
+  uint32_t flags;            /* NUMARCK_FLAG_* */
+  uint32_t tau;              /* smallest selected count; 0 when all nonzero bins are selected */
+  uint32_t reserved0;
+  double E;                  /* error bound */
+  double lo, hi;             /* range of the valid ratios; 0, 0 when none is valid */
+  uint64_t packed_bytes;     /* 4 * ceil(n * B / 32) */
+  uint64_t compressed_bytes; /* 2^B * L + packed_bytes + n_inc * L, eq. (6) with actual sizes */
+  uint64_t tail_count;       /* valid points whose bin lay outside the on-chip window */
+  int64_t window_base;       /* first bin id of the on-chip window */
+} numarck_header;
+
+/* Output buffers of numarck_compress (all device memory, caller-owned). */
+typedef struct numarck_out {
+  uint32_t* packed;        /* numarck_packed_bytes(n, B) bytes: index table */
+  void* centers;           /* numarck_centers_bytes(B, dtype) bytes: 2^B bin centres */
+  void* incomp;            /* n * L bytes (worst case): incompressible values in element order */
+  int64_t* block_inc_off;  /* numarck_block_count(n, B, block_bytes) entries */
+  void* recon;             /* optional (NULL): n * L bytes, the value decompression will return */
+  int64_t* bin_ids;        /* optional (NULL): 2^B - 1 entries, the fine bin of each index
+                              (-1 past k_used) */
+  numarck_header* hdr;     /* one header */
+} numarck_out;
+
+/* ---- sizes (host only, no device access) ---- */
+
+/* Bytes of the packed index table: 4 * ceil(n * B / 32) (Sec. IV-C). */
+size_t numarck_packed_bytes(uint64_t n, uint32_t B);
+/* Bytes of the bin-centre table: 2^B * L (Sec. IV-B-2). 0 on a bad argument. */
+size_t numarck_centers_bytes(uint32_t B, numarck_dtype dtype);
+/* Indices per index-table block: floor(8 * block_bytes / B); block_bytes 0 means 2^20. */
+uint64_t numarck_elems_per_block(uint32_t B, uint64_t block_bytes);
+/* Number of index-table blocks: ceil(n / numarck_elems_per_block(B, block_bytes)). */
+uint64_t numarck_block_count(uint64_t n, uint32_t B, uint64_t block_bytes);
+/* Workspace bytes for numarck_compress that never overflow (tail capacity n). */
+size_t numarck_workspace_bytes(uint64_t n, numarck_dtype dtype, uint32_t B);
+/* Workspace bytes for a tail capacity of tail_cap points (clamped to n).  With a
+ * smaller workspace numarck_compress uses the largest tail capacity that fits and
+ * reports NUMARCK_FLAG_TAIL_OVERFLOW in the header if the data needs more. */
+size_t numarck_workspace_bytes_tail(uint64_t n, uint64_t tail_cap);
+/* Workspace bytes for decompressing len points (full or range). */
+size_t numarck_decompress_workspace_bytes(uint64_t len);
+
+/* ---- compression (Sec. III-A..C, IV-A..C) ----
+ * prev, curr : n values of `dtype`, 16-byte aligned (D_{i-1} and D_i)
+ * E          : error bound in (0, 1]
+ * B          : index bits in [1, 16]
+ * block_bytes: index-table block size in bytes (0 = 2^20, the paper's 1 MB)
+ * out        : host pointer to the output descriptor (device buffers)
+ * ws         : device workspace of ws_bytes (>= numarck_workspace_bytes_tail(n, 0))
+ * Inputs are only read; outputs are fully written (packed padding bits are 0,
+ * centre slots past k_used are 0). */
+numarck_status numarck_compress(const void* prev, const void* curr, uint64_t n,
+                                numarck_dtype dtype, double E, uint32_t B,
+                                uint64_t block_bytes, const numarck_out* out, void* ws,
+                                size_t ws_bytes, void* stream);
+
+/* ---- full decompression (eq. 4, Sec. III-E) ----
+ * hdr   : host copy of the header numarck_compress wrote
+ * prev  : n values, the snapshot the data was compressed against
+ * out   : n values
+ * flags : device uint32; set to 0, then ORed with NUMARCK_FLAG_BAD_INDEX /
+ *         NUMARCK_FLAG_INC_OVERRUN.  An escape past n_inc decodes to 0; an index
+ *         in [k_used, ESC) decodes with its (zero) centre.
+ * ws    : device workspace of >= numarck_decompress_workspace_bytes(n) bytes */
+numarck_status numarck_decompress(const numarck_header* hdr, const void* prev,
+                                  const uint32_t* packed, const void* centers,
+                                  const void* incomp, const int64_t* block_inc_off, void* out,
+                                  uint32_t* flags, void* ws, size_t ws_bytes, void* stream);
+
+/* ---- partial decompression of [start, start + len) (Sec. IV-C, V-C) ----
+ * Uses the block table to find the escapes before the range; reads the packed
+ * table only from the start of the block holding `start`.
+ * prev : the whole previous snapshot (n values); out : len values.
+ * ws   : >= numarck_decompress_workspace_bytes(len) bytes.
+ * Same flag behaviour as numarck_decompress.  start + len > n -> NUMARCK_ERANGE. */
+numarck_status numarck_decompress_range(const numarck_header* hdr, const void* prev,
+                                        const uint32_t* packed, const void* centers,
+                                        const void* incomp, const int64_t* block_inc_off,
+                                        uint64_t start, uint64_t len, void* out,
+                                        uint32_t* flags, void* ws, size_t ws_bytes,
+                                        void* stream);
+
+/* ---- inspection of the last compression's histogram (Sec. IV-B-1) ----
+ * After numarck_compress on the same workspace and stream, writes the nonzero
+ * fine bins (id, count), in no particular order, to ids/counts (device, room
+ * for `capacity` entries) and their number to *count_dev (device uint64).
+ * Entries beyond `capacity` are dropped (the count is still exact). */
+numarck_status numarck_histogram_export(const void* ws, size_t ws_bytes, uint64_t n,
+                                        int64_t* ids, uint32_t* counts, uint64_t capacity,
+                                        uint64_t* count_dev, void* stream);
+
+/* ---- diagnostics ---- */
+const char* numarck_status_str(numarck_status s);
+/* Text of the last HIP error seen by this thread ("" if none). */
+const char* numarck_last_error(void);
+
+/* Per-kernel timing with HIP events on the calls' streams (for benchmarks).
+ * numarck_timing_enable(1) starts recording every kernel launch of later calls;
+ * numarck_timing_read synchronises the recorded events and returns, for up to
+ * `cap` kernel kinds, the name, launch count and summed milliseconds, then
+ * clears the records.  Not thread-safe; disabled by default. */
+void numarck_timing_enable(int on);
+int numarck_timing_read(const char** names, uint32_t* launches, double* ms, int cap);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,256 @@
+"""ctypes binding of libnumarck.so (the C ABI declared in include/numarck.h).
+
+The functions named ``numarck_*`` take exactly the arguments of the C entry
+points of the same name (integers for device pointers and streams) and return
+the status code.  The helpers below them (:func:`compress`,
+:func:`decompress`, :func:`decompress_range`, :func:`histogram`) only
+allocate device tensors with torch, pass their pointers and the current HIP
+stream, and wrap the results; every step of the method runs in the library's
+kernels.  There is no CPU fallback: if the library is missing this module
+fails to import.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import torch  # loads torch's HIP runtime before the library binds to it
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libnumarck.so")
+
+F32, F64 = 0, 1
+OK, EINVAL, EDTYPE, EBITS, EBOUND, EALIGN, ECAPACITY, EHIP, ERANGE = range(9)
+FLAG_BAD_INDEX, FLAG_INC_OVERRUN, FLAG_TAIL_OVERFLOW = 1, 2, 4
+
+
+class NumarckHeader(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_uint64), ("n_valid", ctypes.c_uint64), ("n_invalid", ctypes.c_uint64),
+        ("n_inc", ctypes.c_uint64), ("n_blocks", ctypes.c_uint64),
+        ("elems_per_block", ctypes.c_uint64), ("block_bytes", ctypes.c_uint64),
+        ("M", ctypes.c_int64), ("n_nonzero", ctypes.c_uint64),
+        ("B", ctypes.c_uint32), ("k_used", ctypes.c_uint32), ("dtype", ctypes.c_uint32),
+        ("flags", ctypes.c_uint32), ("tau", ctypes.c_uint32), ("reserved0", ctypes.c_uint32),
+        ("E", ctypes.c_double), ("lo", ctypes.c_double), ("hi", ctypes.c_double),
+        ("packed_bytes", ctypes.c_uint64), ("compressed_bytes", ctypes.c_uint64),
+        ("tail_count", ctypes.c_uint64), ("window_base", ctypes.c_int64),
+    ]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class NumarckOut(ctypes.Structure):
+    _fields_ = [
+        ("packed", ctypes.c_void_p), ("centers", ctypes.c_void_p), ("incomp", ctypes.c_void_p),
+        ("block_inc_off", ctypes.c_void_p), ("recon", ctypes.c_void_p),
+        ("bin_ids", ctypes.c_void_p), ("hdr", ctypes.c_void_p),
+    ]
+
+
+HEADER_BYTES = ctypes.sizeof(NumarckHeader)
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
+                      "(the NUMARCK path has no CPU fallback)")
+_lib = ctypes.CDLL(LIB_PATH)
+
+_u64, _u32, _sz, _vp, _d = ctypes.c_uint64, ctypes.c_uint32, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_double
+_i = ctypes.c_int
+
+
+def _bind(name, res, args):
+    f = getattr(_lib, name)
+    f.restype = res
+    f.argtypes = args
+    return f
+
+
+numarck_packed_bytes = _bind("numarck_packed_bytes", _sz, [_u64, _u32])
+numarck_centers_bytes = _bind("numarck_centers_bytes", _sz, [_u32, _i])
+numarck_elems_per_block = _bind("numarck_elems_per_block", _u64, [_u32, _u64])
+numarck_block_count = _bind("numarck_block_count", _u64, [_u64, _u32, _u64])
+numarck_workspace_bytes = _bind("numarck_workspace_bytes", _sz, [_u64, _i, _u32])
+numarck_workspace_bytes_tail = _bind("numarck_workspace_bytes_tail", _sz, [_u64, _u64])
+numarck_decompress_workspace_bytes = _bind("numarck_decompress_workspace_bytes", _sz, [_u64])
+numarck_compress = _bind("numarck_compress", _i,
+                         [_vp, _vp, _u64, _i, _d, _u32, _u64, ctypes.POINTER(NumarckOut), _vp,
+                          _sz, _vp])
+numarck_decompress = _bind("numarck_decompress", _i,
+                           [ctypes.POINTER(NumarckHeader), _vp, _vp, _vp, _vp, _vp, _vp, _vp,
+                            _vp, _sz, _vp])
+numarck_decompress_range = _bind("numarck_decompress_range", _i,
+                                 [ctypes.POINTER(NumarckHeader), _vp, _vp, _vp, _vp, _vp, _u64,
+                                  _u64, _vp, _vp, _vp, _sz, _vp])
+numarck_histogram_export = _bind("numarck_histogram_export", _i,
+                                 [_vp, _sz, _u64, _vp, _vp, _u64, _vp, _vp])
+numarck_status_str = _bind("numarck_status_str", ctypes.c_char_p, [_i])
+numarck_last_error = _bind("numarck_last_error", ctypes.c_char_p, [])
+numarck_timing_enable = _bind("numarck_timing_enable", None, [_i])
+numarck_timing_read = _bind("numarck_timing_read", _i,
+                            [ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(_u32),
+                             ctypes.POINTER(_d), _i])
+
+
+class NumarckError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        msg = numarck_status_str(status).decode()
+        if status == EHIP:
+            msg += ": " + numarck_last_error().decode()
+        super().__init__(f"{where}: {msg} (status {status})")
+        self.status = status
+
+
+def _check(st: int, where: str):
+    if st != OK:
+        raise NumarckError(st, where)
+
+
+def _ptr(t):
+    return None if t is None else t.data_ptr()
+
+
+def _stream(stream=None) -> int:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+def dtype_code(t: torch.dtype) -> int:
+    if t == torch.float32:
+        return F32
+    if t == torch.float64:
+        return F64
+    raise ValueError(f"unsupported dtype {t}")
+
+
+def header_from_device(hdr: torch.Tensor) -> NumarckHeader:
+    """Copy a device header (uint8 tensor) to the host; synchronises its stream."""
+    raw = hdr.cpu().numpy().tobytes()
+    return NumarckHeader.from_buffer_copy(raw)
+
+
+@dataclass
+class Compressed:
+    """Device buffers of one compression.  ``incomp`` has room for n values;
+    its first ``header().n_inc`` entries are meaningful."""
+    packed: torch.Tensor
+    centers: torch.Tensor
+    incomp: torch.Tensor
+    block_inc_off: torch.Tensor
+    recon: torch.Tensor | None
+    bin_ids: torch.Tensor | None
+    hdr: torch.Tensor
+    ws: torch.Tensor
+    n: int
+    dtype: torch.dtype
+    _host: NumarckHeader | None = None
+
+    def header(self) -> NumarckHeader:
+        if self._host is None:
+            self._host = header_from_device(self.hdr)
+        return self._host
+
+
+def alloc_outputs(n: int, dtype: torch.dtype, B: int, block_bytes: int = 0, recon=False,
+                  bin_ids=False, device="cuda"):
+    L = 4 if dtype == torch.float32 else 8
+    pw = numarck_packed_bytes(n, B) // 4
+    nb = numarck_block_count(n, B, block_bytes)
+    return dict(
+        packed=torch.empty(max(pw, 1), dtype=torch.int32, device=device),
+        centers=torch.empty(1 << B, dtype=dtype, device=device),
+        incomp=torch.empty(max(n, 1), dtype=dtype, device=device),
+        block_inc_off=torch.empty(max(nb, 1), dtype=torch.int64, device=device),
+        recon=torch.empty(max(n, 1), dtype=dtype, device=device) if recon else None,
+        bin_ids=torch.empty(max((1 << B) - 1, 1), dtype=torch.int64, device=device) if bin_ids else None,
+        hdr=torch.empty(HEADER_BYTES, dtype=torch.uint8, device=device),
+    )
+
+
+def out_struct(o: dict) -> NumarckOut:
+    return NumarckOut(_ptr(o["packed"]), _ptr(o["centers"]), _ptr(o["incomp"]),
+                      _ptr(o["block_inc_off"]), _ptr(o["recon"]), _ptr(o["bin_ids"]),
+                      _ptr(o["hdr"]))
+
+
+def compress(prev: torch.Tensor, curr: torch.Tensor, E: float, B: int, block_bytes: int = 0,
+             recon: bool = False, bin_ids: bool = False, ws: torch.Tensor | None = None,
+             outputs: dict | None = None, stream=None) -> Compressed:
+    """Compress `curr` against `prev` (1-D contiguous float32/float64 device tensors)."""
+    if prev.dtype != curr.dtype or prev.numel() != curr.numel():
+        raise ValueError("prev and curr must have the same dtype and size")
+    if not (prev.is_cuda and curr.is_cuda):
+        raise ValueError("prev and curr must be device tensors")
+    prev = prev.reshape(-1)
+    curr = curr.reshape(-1)
+    n = prev.numel()
+    dt = dtype_code(prev.dtype)
+    o = outputs if outputs is not None else alloc_outputs(n, prev.dtype, B, block_bytes, recon,
+                                                          bin_ids, prev.device)
+    if ws is None:
+        ws = torch.empty(numarck_workspace_bytes(n, dt, B), dtype=torch.uint8, device=prev.device)
+    out = out_struct(o)
+    st = numarck_compress(_ptr(prev), _ptr(curr), n, dt, float(E), int(B), int(block_bytes),
+                          ctypes.byref(out), _ptr(ws), ws.numel(), _stream(stream))
+    _check(st, "numarck_compress")
+    return Compressed(o["packed"], o["centers"], o["incomp"], o["block_inc_off"], o["recon"],
+                      o["bin_ids"], o["hdr"], ws, n, prev.dtype)
+
+
+def decompress(c: Compressed, prev: torch.Tensor, out: torch.Tensor | None = None,
+               stream=None):
+    """Full decompression; returns (values, flags tensor)."""
+    h = c.header()
+    if out is None:
+        out = torch.empty(max(h.n, 1), dtype=c.dtype, device=prev.device)
+    flags = torch.zeros(1, dtype=torch.int32, device=prev.device)
+    ws = torch.empty(numarck_decompress_workspace_bytes(h.n), dtype=torch.uint8, device=prev.device)
+    st = numarck_decompress(ctypes.byref(h), _ptr(prev), _ptr(c.packed), _ptr(c.centers),
+                            _ptr(c.incomp), _ptr(c.block_inc_off), _ptr(out), _ptr(flags),
+                            _ptr(ws), ws.numel(), _stream(stream))
+    _check(st, "numarck_decompress")
+    return out[: h.n], flags
+
+
+def decompress_range(c: Compressed, prev: torch.Tensor, start: int, length: int,
+                     out: torch.Tensor | None = None, stream=None):
+    """Partial decompression of [start, start + length); returns (values, flags)."""
+    h = c.header()
+    if out is None:
+        out = torch.empty(max(length, 1), dtype=c.dtype, device=prev.device)
+    flags = torch.zeros(1, dtype=torch.int32, device=prev.device)
+    ws = torch.empty(numarck_decompress_workspace_bytes(length), dtype=torch.uint8,
+                     device=prev.device)
+    st = numarck_decompress_range(ctypes.byref(h), _ptr(prev), _ptr(c.packed), _ptr(c.centers),
+                                  _ptr(c.incomp), _ptr(c.block_inc_off), int(start), int(length),
+                                  _ptr(out), _ptr(flags), _ptr(ws), ws.numel(), _stream(stream))
+    _check(st, "numarck_decompress_range")
+    return out[:length], flags
+
+
+def histogram(c: Compressed, capacity: int | None = None, stream=None):
+    """Nonzero fine bins of the compression `c` (unordered ids, counts)."""
+    if capacity is None:
+        capacity = max(c.n, 1)
+    ids = torch.empty(max(capacity, 1), dtype=torch.int64, device=c.hdr.device)
+    counts = torch.empty(max(capacity, 1), dtype=torch.int32, device=c.hdr.device)
+    cnt = torch.zeros(1, dtype=torch.int64, device=c.hdr.device)
+    st = numarck_histogram_export(_ptr(c.ws), c.ws.numel(), c.n, _ptr(ids), _ptr(counts),
+                                  capacity, _ptr(cnt), _stream(stream))
+    _check(st, "numarck_histogram_export")
+    k = int(cnt.item())
+    return ids[:min(k, capacity)], counts[:min(k, capacity)], k
+
+
+def timing_enable(on: bool = True):
+    numarck_timing_enable(1 if on else 0)
+
+
+def timing_read(cap: int = 32) -> dict:
+    names = (ctypes.c_char_p * cap)()
+    launches = (_u32 * cap)()
+    ms = (_d * cap)()
+    k = numarck_timing_read(names, launches, ms, cap)
+    return {names[i].decode(): (int(launches[i]), float(ms[i])) for i in range(k)}

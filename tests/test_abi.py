@@ -1,0 +1,130 @@
+"""The C-ABI library: it loads, exports every entry point include/numarck.h
+declares, and its host-only functions (sizes, validation) behave as
+documented.  No kernel is launched here (no GPU)."""
+import ctypes
+import math
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "numarck.h")
+
+
+@pytest.fixture(scope="module")
+def nk():
+    from paper_1703_02438_amd import build
+
+    if not os.path.exists(build.LIB):
+        build.build()
+    import paper_1703_02438_amd.numarck as nk
+    return nk
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(numarck_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_header_declares_entry_points():
+    names = declared_functions()
+    for must in ("numarck_compress", "numarck_decompress", "numarck_decompress_range"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol(nk):
+    out = subprocess.run(["nm", "-D", "--defined-only", nk.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(re.findall(r"\bT (numarck_\w+)", out))
+    missing = [f for f in declared_functions() if f not in exported]
+    assert not missing, missing
+    lib = ctypes.CDLL(nk.LIB_PATH)
+    for f in declared_functions():
+        assert hasattr(lib, f)
+
+
+def test_sizes(nk):
+    assert nk.numarck_packed_bytes(0, 8) == 0
+    assert nk.numarck_packed_bytes(3, 8) == 4
+    assert nk.numarck_packed_bytes(33, 1) == 8
+    assert nk.numarck_packed_bytes(1000, 13) == 4 * math.ceil(13000 / 32)
+    assert nk.numarck_centers_bytes(13, nk.F32) == 8192 * 4
+    assert nk.numarck_centers_bytes(8, nk.F64) == 256 * 8
+    assert nk.numarck_centers_bytes(0, nk.F64) == 0
+    # Fig. 2: 13-bit indices, 1 MB blocks -> 645,277 per block, 6 blocks for 3,758,400
+    assert nk.numarck_elems_per_block(13, 1 << 20) == 645277
+    assert nk.numarck_block_count(3758400, 13, 0) == 6
+    assert nk.numarck_block_count(0, 13, 0) == 0
+    w_full = nk.numarck_workspace_bytes(1 << 20, nk.F64, 8)
+    w_none = nk.numarck_workspace_bytes_tail(1 << 20, 0)
+    assert w_full > w_none > 0
+    assert nk.numarck_workspace_bytes_tail(1 << 20, 1 << 20) == w_full
+    assert nk.numarck_decompress_workspace_bytes(0) > 0
+
+
+class _FakeOut(ctypes.Structure):
+    pass
+
+
+def _out(nk, base=0x100000):
+    return nk.NumarckOut(base, base + 0x1000, base + 0x2000, base + 0x3000, None, None,
+                         base + 0x4000)
+
+
+def test_compress_validation_without_gpu(nk):
+    o = _out(nk)
+    ws = 0x200000
+    p, q = 0x300000, 0x400000
+    big = 1 << 40
+    call = lambda *a: nk.numarck_compress(*a)
+    assert call(p, q, 10, 7, 1e-3, 8, 0, ctypes.byref(o), ws, big, None) == nk.EDTYPE
+    assert call(p, q, 10, nk.F64, 1e-3, 0, 0, ctypes.byref(o), ws, big, None) == nk.EBITS
+    assert call(p, q, 10, nk.F64, 1e-3, 17, 0, ctypes.byref(o), ws, big, None) == nk.EBITS
+    for bad_e in (0.0, -1e-3, 1.5, float("nan"), float("inf")):
+        assert call(p, q, 10, nk.F64, bad_e, 8, 0, ctypes.byref(o), ws, big, None) == nk.EBOUND
+    assert call(p, q, 1 << 32, nk.F64, 1e-3, 8, 0, ctypes.byref(o), ws, big, None) == nk.EINVAL
+    assert call(p, q, 10, nk.F64, 1e-3, 8, 0, None, ws, big, None) == nk.EINVAL
+    assert call(None, q, 10, nk.F64, 1e-3, 8, 0, ctypes.byref(o), ws, big, None) == nk.EINVAL
+    assert call(p + 8, q, 10, nk.F64, 1e-3, 8, 0, ctypes.byref(o), ws, big, None) == nk.EALIGN
+    assert call(p, q, 10, nk.F64, 1e-3, 8, 0, ctypes.byref(o), ws + 64, big, None) == nk.EALIGN
+    assert call(p, q, 10, nk.F64, 1e-3, 8, 0, ctypes.byref(o), ws, 1024, None) == nk.ECAPACITY
+    assert call(p, q, 10, nk.F64, 1e-3, 16, 1, ctypes.byref(o), ws, big, None) == nk.EINVAL
+
+
+def _header(nk, n=1000, B=8, bb=1 << 20):
+    h = nk.NumarckHeader()
+    h.n, h.B, h.dtype, h.block_bytes = n, B, nk.F64, bb
+    h.elems_per_block = 8 * bb // B
+    h.n_blocks = -(-n // h.elems_per_block)
+    h.k_used, h.n_inc = 10, 5
+    return h
+
+
+def test_decompress_validation_without_gpu(nk):
+    h = _header(nk)
+    ws, big = 0x200000, 1 << 30
+    args = lambda hh, s, ln: (ctypes.byref(hh), 0x300000, 0x400000, 0x500000, 0x600000,
+                              0x700000, s, ln, 0x800000, 0x900000, ws, big, None)
+    assert nk.numarck_decompress_range(*args(h, 900, 101)) == nk.ERANGE
+    assert nk.numarck_decompress_range(*args(h, 1001, 0)) == nk.ERANGE
+    bad = _header(nk)
+    bad.elems_per_block += 1
+    assert nk.numarck_decompress_range(*args(bad, 0, 10)) == nk.EINVAL
+    bad = _header(nk)
+    bad.B = 0
+    assert nk.numarck_decompress_range(*args(bad, 0, 10)) == nk.EBITS
+    bad = _header(nk)
+    bad.k_used = 300
+    assert nk.numarck_decompress_range(*args(bad, 0, 10)) == nk.EINVAL
+    small = list(args(h, 0, 1000))
+    small[11] = 16
+    assert nk.numarck_decompress_range(*small) == nk.ECAPACITY
+
+
+def test_status_strings(nk):
+    for s in range(9):
+        assert nk.numarck_status_str(s)
+    assert nk.numarck_status_str(99) == b"unknown status"

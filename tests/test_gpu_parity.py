@@ -1,0 +1,198 @@
+"""HIP library vs the CPU oracle, element by element (bit-exact), through the
+C ABI.  Sizes span several tiles and ragged tails; edge cases cover empty and
+one-element inputs, every index width, invalid points, the tail (out-of-
+window) path of the histogram and the capacity flag."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from gpu_util import bits, compare_compress, compare_decompress, gpu_compress, to_np
+from paper_1703_02438_amd import inputs
+from pins import adversarial_case, centred_case, mixture_case
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def nk():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_1703_02438_amd.numarck as nk
+    return nk
+
+
+def _ranges(n, rng, k=6, epb=None):
+    out = [(0, n), (0, 0), (n, 0)]
+    for _ in range(k):
+        s = int(rng.integers(0, n + 1))
+        out.append((s, int(rng.integers(0, n - s + 1))))
+    if epb and n > epb + 10:
+        out.append((epb - 5, 10))  # crosses a block boundary
+    return out
+
+
+def test_cfg1_fp64(nk):
+    """64^3 float64, lognormal prev with 0.1 % zeros, 3-component ratio
+    mixture, E = 1e-3, B = 8."""
+    prev, curr = inputs.mixture_pair(64 ** 3, seed=1704)
+    prev, curr = prev.numpy(), curr.numpy()
+    c, o, p = compare_compress(nk, prev, curr, 1e-3, 8, label="cfg1")
+    compare_decompress(nk, c, o, p, prev, _ranges(prev.size, np.random.default_rng(1)))
+
+
+def test_cfg1_fp32(nk):
+    prev, curr = inputs.mixture_pair(64 ** 3, seed=1704, dtype=torch.float32)
+    prev, curr = prev.numpy(), curr.numpy()
+    c, o, p = compare_compress(nk, prev, curr, 1e-3, 8, label="cfg1-f32")
+    compare_decompress(nk, c, o, p, prev, _ranges(prev.size, np.random.default_rng(2)))
+
+
+@pytest.mark.parametrize("n", [0, 1, 2, 3, 5, 31, 33, 4095, 4096, 4097, 12289, 100003])
+@pytest.mark.parametrize("dt", [np.float64, np.float32])
+def test_ragged_sizes(nk, n, dt):
+    prev, curr = mixture_case(max(n, 1), 1000 + n, dt)
+    prev, curr = prev[:n], curr[:n]
+    B = 3 if n < 100 else 10
+    c, o, p = compare_compress(nk, prev, curr, 1e-3, B, label="ragged")
+    compare_decompress(nk, c, o, p, prev, _ranges(n, np.random.default_rng(n)))
+
+
+@pytest.mark.parametrize("B", [1, 2, 3, 5, 8, 10, 12, 13, 15, 16])
+def test_index_widths(nk, B):
+    prev, curr = mixture_case(50021, 77 + B, np.float64, E=1e-4)
+    c, o, p = compare_compress(nk, prev, curr, 1e-4, B, label="bits")
+    compare_decompress(nk, c, o, p, prev, _ranges(prev.size, np.random.default_rng(B)))
+
+
+@pytest.mark.parametrize("dt", [np.float64, np.float32])
+def test_adversarial_values(nk, dt):
+    """Signed zeros, infinities, NaN payloads, subnormals, huge values, tiled
+    and shuffled among ordinary points."""
+    ap, aq = adversarial_case(dt)
+    mp, mq = mixture_case(30000, 5, dt)
+    rng = np.random.default_rng(9)
+    prev = np.concatenate([mp, np.tile(ap, 200)])
+    curr = np.concatenate([mq, np.tile(aq, 200)])
+    perm = rng.permutation(prev.size)
+    prev, curr = prev[perm], curr[perm]
+    c, o, p = compare_compress(nk, prev, curr, 1e-3, 6, label="adversarial")
+    compare_decompress(nk, c, o, p, prev, _ranges(prev.size, rng))
+
+
+@pytest.mark.parametrize("dt", [np.float64, np.float32])
+def test_centred_ties(nk, dt):
+    """Bin-centred data with ties across the top-k cut (known answer)."""
+    counts = {0: 4, 1: 7, 2: 5, 3: 5, 4: 5, 6: 1}
+    counts = {m: c * 1000 for m, c in counts.items()}
+    prev, curr, b, E = centred_case(counts, dt)
+    c, o, p = compare_compress(nk, prev, curr, E, 2, label="centred")
+    assert to_np(c.bin_ids)[:3].tolist() == [1, 2, 3]
+    compare_decompress(nk, c, o, p, prev)
+
+
+def test_all_invalid(nk):
+    prev = np.zeros(9000)
+    curr = np.linspace(-1, 1, 9000)
+    c, o, p = compare_compress(nk, prev, curr, 1e-3, 8, label="invalid")
+    assert c.header().n_inc == 9000 and c.header().k_used == 0
+    compare_decompress(nk, c, o, p, prev)
+
+
+def test_all_equal(nk):
+    prev = np.tile(np.array([1.0, 2.0, 4.0, -8.0, 0.5]), 3000)
+    c, o, p = compare_compress(nk, prev, prev * 1.25, 1e-3, 8, label="equal")
+    assert c.header().M == 1
+
+
+@pytest.mark.parametrize("bb", [1, 2, 64, 1000, 65536])
+def test_small_blocks(nk, bb):
+    prev, curr = mixture_case(20011, 31, np.float32)
+    B = 8
+    c, o, p = compare_compress(nk, prev, curr, 1e-3, B, block_bytes=bb, label="blocks")
+    epb = 8 * bb // B
+    compare_decompress(nk, c, o, p, prev, _ranges(prev.size, np.random.default_rng(bb), 8, epb))
+
+
+def tail_case(n=200_000, seed=3, dt=np.float64):
+    """Ratios spread over [-0.5, 0.5] with E = 1e-5 (M = 50,000 bins > window):
+    clusters at +0.4 and -0.45 lie outside the on-chip window around 0, so
+    selected bins come from the tail below and above the window."""
+    rng = np.random.default_rng(seed)
+    prev = rng.lognormal(0, 1, n)
+    u = rng.random(n)
+    r = np.where(u < 0.3, rng.normal(0, 1e-5, n),
+                 np.where(u < 0.5, rng.normal(0.4, 3e-5, n),
+                          np.where(u < 0.7, rng.normal(-0.45, 3e-5, n), rng.uniform(-0.5, 0.5, n))))
+    curr = prev * (1 + r)
+    return prev.astype(dt), curr.astype(dt)
+
+
+@pytest.mark.parametrize("B", [8, 12, 16])
+def test_tail_bins_selected(nk, B):
+    prev, curr = tail_case()
+    c, o, p = compare_compress(nk, prev, curr, 1e-5, B, label="tail")
+    h = c.header()
+    assert h.M > 16384 and h.tail_count > 0
+    ids = to_np(c.bin_ids)[: h.k_used]
+    wb = h.window_base
+    assert (ids < wb).any() and (ids >= wb + 16384).any()  # selected on both sides
+    compare_decompress(nk, c, o, p, prev, _ranges(prev.size, np.random.default_rng(B)))
+
+
+def test_tail_capacity(nk):
+    """A workspace with a small tail capacity: exact while the tail fits, the
+    overflow flag when it does not."""
+    prev, curr = tail_case(60_000, 4)
+    big = gpu_compress(nk, prev, curr, 1e-5, 8)[0]
+    T = big.header().tail_count
+    assert T > 1000
+    ws = torch.empty(nk.numarck_workspace_bytes_tail(prev.size, T), dtype=torch.uint8,
+                     device="cuda")
+    c, _, _ = gpu_compress(nk, prev, curr, 1e-5, 8, ws=ws)
+    assert c.header().flags == 0
+    assert np.array_equal(to_np(c.packed), to_np(big.packed))
+    ws = torch.empty(nk.numarck_workspace_bytes_tail(prev.size, T // 2), dtype=torch.uint8,
+                     device="cuda")
+    c, _, _ = gpu_compress(nk, prev, curr, 1e-5, 8, ws=ws)
+    assert c.header().flags & nk.FLAG_TAIL_OVERFLOW
+
+
+def test_flash_like_small(nk):
+    """32^3 FLASH-like pair: smooth ratios plus Cauchy shocks -> a huge bin
+    range with a sparse tail."""
+    s = inputs.FlashSeries(edge=32, seed=11)
+    prev = s.x.clone().numpy()
+    curr = s.step().numpy()
+    c, o, p = compare_compress(nk, prev, curr, 1e-3, 8, label="flash")
+    assert c.header().M > 16384
+    compare_decompress(nk, c, o, p, prev, _ranges(prev.size, np.random.default_rng(5)))
+
+
+@pytest.mark.parametrize("spill", [False, True])
+def test_climate_like_small(nk, spill):
+    kw = dict(outlier_lo=-0.9, outlier_hi=1.5) if spill else {}
+    s = inputs.ClimateSeries(nlat=180, nlon=360, seed=12, **kw)
+    prev = s.x.clone().numpy()
+    curr = s.step().numpy()
+    c, o, p = compare_compress(nk, prev, curr, 1e-4, 10, label="climate")
+    compare_decompress(nk, c, o, p, prev, _ranges(prev.size, np.random.default_rng(6)))
+
+
+def test_deterministic(nk):
+    prev, curr = tail_case(120_000, 8)
+    a = gpu_compress(nk, prev, curr, 1e-5, 12)[0]
+    b = gpu_compress(nk, prev, curr, 1e-5, 12)[0]
+    for f in ("packed", "centers", "incomp", "block_inc_off", "recon", "bin_ids", "hdr"):
+        assert torch.equal(getattr(a, f).view(torch.uint8), getattr(b, f).view(torch.uint8)), f
+
+
+def test_decode_flags(nk):
+    prev, curr, b, E = centred_case({0: 1, 3: 2, 9: 1})
+    c, p, q = gpu_compress(nk, prev, curr, E, 4)
+    c.packed[0] = (c.packed[0] & ~0xF) | 7  # index 7 >= k_used = 3
+    _, fl = nk.decompress(c, p)
+    assert int(fl.item()) & nk.FLAG_BAD_INDEX
+    c2, p2, _ = gpu_compress(nk, prev, curr, E, 4)
+    c2.packed.fill_(-1)  # every index is the escape code
+    _, fl = nk.decompress(c2, p2)
+    assert int(fl.item()) & nk.FLAG_INC_OVERRUN
