@@ -123,7 +123,7 @@ size_t numarck_workspace_bytes(uint64_t n, numarck_dtype dtype, uint32_t B);
 /* Workspace bytes for a tail capacity of tail_cap points (clamped to n).  With a
  * smaller workspace numarck_compress uses the largest tail capacity that fits and
  * reports NUMARCK_FLAG_TAIL_OVERFLOW in the header if the data needs more. */
-size_t numarck_workspace_bytes_tail(uint64_t n, uint64_t tail_cap);
+size_t numarck_workspace_bytes_tail(uint64_t n, numarck_dtype dtype, uint64_t tail_cap);
 /* Workspace bytes for decompressing len points (full or range). */
 size_t numarck_decompress_workspace_bytes(uint64_t len);
 
@@ -168,13 +168,14 @@ numarck_status numarck_decompress_range(const numarck_header* hdr, const void* p
                                         void* stream);
 
 /* ---- inspection of the last compression's histogram (Sec. IV-B-1) ----
- * After numarck_compress on the same workspace and stream, writes the nonzero
- * fine bins (id, count), in no particular order, to ids/counts (device, room
- * for `capacity` entries) and their number to *count_dev (device uint64).
- * Entries beyond `capacity` are dropped (the count is still exact). */
+ * After numarck_compress on the same workspace, size and dtype and on the same
+ * stream, writes the nonzero fine bins (id, count), in no particular order, to
+ * ids/counts (device, room for `capacity` entries) and their number to
+ * *count_dev (device uint64).  Entries beyond `capacity` are dropped (the count
+ * is still exact). */
 numarck_status numarck_histogram_export(const void* ws, size_t ws_bytes, uint64_t n,
-                                        int64_t* ids, uint32_t* counts, uint64_t capacity,
-                                        uint64_t* count_dev, void* stream);
+                                        numarck_dtype dtype, int64_t* ids, uint32_t* counts,
+                                        uint64_t capacity, uint64_t* count_dev, void* stream);
 
 /* ---- diagnostics ---- */
 const char* numarck_status_str(numarck_status s);

@@ -26,12 +26,11 @@ static uint64_t next_pow2_u64(uint64_t x) {
   return p;
 }
 
-Layout compress_layout(uint64_t n, uint64_t tail_cap) {
+Layout compress_layout(uint64_t n, uint64_t elem_bytes, uint64_t tail_cap) {
   Layout L{};
   if (tail_cap > n) tail_cap = n;
   L.tail_cap = tail_cap;
   L.hcap = next_pow2_u64(2 * tail_cap > 1024 ? 2 * tail_cap : 1024);
-  L.n_tiles = (n + ENC_TILE - 1) / ENC_TILE;
   size_t off = 0;
   auto take = [&](size_t bytes) {
     const size_t o = off;
@@ -40,10 +39,12 @@ Layout compress_layout(uint64_t n, uint64_t tail_cap) {
   };
   L.ctl = take(sizeof(Ctl));
   L.gwin = take((size_t)WIN * 4);
-  L.lut = take((size_t)WIN * 2);
+  L.lutbits = take((size_t)LUT_GROUPS * 8);
+  L.lutbase = take((size_t)LUT_GROUPS * 4);
   L.sel_tail = take((size_t)(MAX_SEL + 1) * 8);
   L.sorted_tail = take((size_t)(MAX_SEL + 1) * 8);
-  L.status = take((size_t)L.n_tiles * 8);
+  L.unit_cnt = take((size_t)MAX_UNITS * 4);
+  L.scratch = take((size_t)n * elem_bytes);
   L.tail = take((size_t)tail_cap * 8);
   L.hslot = take((size_t)L.hcap * 4);
   L.hcnt = take((size_t)L.hcap * 4);
@@ -52,28 +53,28 @@ Layout compress_layout(uint64_t n, uint64_t tail_cap) {
 }
 
 // Largest tail capacity whose layout fits ws_bytes; false if none does.
-static bool fit_layout(uint64_t n, size_t ws_bytes, Layout* out) {
-  Layout full = compress_layout(n, n);
+static bool fit_layout(uint64_t n, uint64_t elem_bytes, size_t ws_bytes, Layout* out) {
+  Layout full = compress_layout(n, elem_bytes, n);
   if (full.total <= ws_bytes) {
     *out = full;
     return true;
   }
-  Layout none = compress_layout(n, 0);
+  Layout none = compress_layout(n, elem_bytes, 0);
   if (none.total > ws_bytes) return false;
-  uint64_t a = 0, b = n;  // compress_layout(n, a) fits, (n, b) does not
+  uint64_t a = 0, b = n;  // capacity a fits, b does not
   while (b - a > 1) {
     const uint64_t m = a + (b - a) / 2;
-    if (compress_layout(n, m).total <= ws_bytes) a = m; else b = m;
+    if (compress_layout(n, elem_bytes, m).total <= ws_bytes) a = m; else b = m;
   }
-  *out = compress_layout(n, a);
+  *out = compress_layout(n, elem_bytes, a);
   return true;
 }
 
-static size_t decompress_layout_bytes(uint64_t len, size_t* status_off) {
-  const uint64_t tiles = (len + DEC_TILE - 1) / DEC_TILE;
+static size_t decompress_layout_bytes(uint64_t len, size_t* cnt_off) {
+  (void)len;
   const size_t s = align256(sizeof(DCtl));
-  if (status_off) *status_off = s;
-  return s + align256((size_t)tiles * 8);
+  if (cnt_off) *cnt_off = s;
+  return s + align256((size_t)MAX_UNITS * 4);
 }
 
 static int g_cus[128];
@@ -94,8 +95,9 @@ Geometry geometry() {
 
 // ------------------------------------------------------------- event timing
 static const char* kKindNames[KK_COUNT] = {
-    "init", "range", "derive", "hist", "hash_clear", "hash_insert", "select",
-    "tail_rank", "encode", "final", "dec_init", "dec_prefix", "decode", "export"};
+    "init", "range", "derive", "hist", "hash_clear", "hash_insert", "select", "tail_rank",
+    "encode", "unit_scan", "gather", "final", "dec_init", "dec_prefix", "dec_count",
+    "dec_scan", "decode", "export"};
 static bool g_timing = false;
 struct EvPair {
   hipEvent_t a, b;
@@ -158,14 +160,15 @@ uint64_t numarck_block_count(uint64_t n, uint32_t B, uint64_t block_bytes) {
   return (n + epb - 1) / epb;
 }
 
+static uint64_t elem_bytes_of(numarck_dtype dtype) { return dtype == NUMARCK_F32 ? 4 : 8; }
+
 size_t numarck_workspace_bytes(uint64_t n, numarck_dtype dtype, uint32_t B) {
-  (void)dtype;
   (void)B;
-  return compress_layout(n, n).total;
+  return compress_layout(n, elem_bytes_of(dtype), n).total;
 }
 
-size_t numarck_workspace_bytes_tail(uint64_t n, uint64_t tail_cap) {
-  return compress_layout(n, tail_cap).total;
+size_t numarck_workspace_bytes_tail(uint64_t n, numarck_dtype dtype, uint64_t tail_cap) {
+  return compress_layout(n, elem_bytes_of(dtype), tail_cap).total;
 }
 
 size_t numarck_decompress_workspace_bytes(uint64_t len) {
@@ -190,7 +193,8 @@ numarck_status numarck_compress(const void* prev, const void* curr, uint64_t n,
   if (!aligned16(prev) || !aligned16(curr) || !aligned16(out->recon)) return NUMARCK_EALIGN;
   if (((uintptr_t)ws & 255u) != 0) return NUMARCK_EALIGN;
   Layout L;
-  if (!fit_layout(n, ws_bytes, &L)) return NUMARCK_ECAPACITY;
+  const uint64_t eb = elem_bytes_of(dtype);
+  if (!fit_layout(n, eb, ws_bytes, &L)) return NUMARCK_ECAPACITY;
 
   char* base = static_cast<char*>(ws);
   CParams P{};
@@ -200,16 +204,22 @@ numarck_status numarck_compress(const void* prev, const void* curr, uint64_t n,
   P.E = E;
   P.twoE = 2.0 * E;
   P.cap = ldexp(E, 50);
+  P.inv2E = 1.0 / P.twoE;
+  P.fastbin = (isfinite(P.inv2E) && P.inv2E >= 2.2250738585072014e-308) ? 1 : 0;
   P.B = B;
   P.k = (1u << B) - 1u;
   P.block_bytes = block_bytes;
   P.epb = 8 * block_bytes / B;
   P.n_blocks = (n + P.epb - 1) / P.epb;
-  P.n_tiles = L.n_tiles;
+  const uint64_t tile = wave_tile(eb);
+  P.n_tiles = (n + tile - 1) / tile;
   P.packed_words = (n * B + 31) / 32;
   P.ctl = reinterpret_cast<Ctl*>(base + L.ctl);
   P.gwin = reinterpret_cast<uint32_t*>(base + L.gwin);
-  P.lut = reinterpret_cast<uint16_t*>(base + L.lut);
+  P.lutbits = reinterpret_cast<unsigned long long*>(base + L.lutbits);
+  P.lutbase = reinterpret_cast<uint32_t*>(base + L.lutbase);
+  P.unit_cnt = reinterpret_cast<uint32_t*>(base + L.unit_cnt);
+  P.scratch = base + L.scratch;
   P.tail = reinterpret_cast<int64_t*>(base + L.tail);
   P.tail_cap = L.tail_cap;
   P.hslot = reinterpret_cast<uint32_t*>(base + L.hslot);
@@ -217,7 +227,6 @@ numarck_status numarck_compress(const void* prev, const void* curr, uint64_t n,
   P.hcap = L.hcap;
   P.sel_tail = reinterpret_cast<int64_t*>(base + L.sel_tail);
   P.sorted_tail = reinterpret_cast<int64_t*>(base + L.sorted_tail);
-  P.status = reinterpret_cast<unsigned long long*>(base + L.status);
   P.packed = out->packed;
   P.centers = out->centers;
   P.incomp = out->incomp;
@@ -256,8 +265,8 @@ static numarck_status decompress_impl(const numarck_header* hdr, const void* pre
   if (len > 0 && (!prev || !packed || !centers || !out || !block_inc_off)) return NUMARCK_EINVAL;
   if (len > 0 && hdr->n_inc > 0 && !incomp) return NUMARCK_EINVAL;
   if (((uintptr_t)ws & 255u) != 0) return NUMARCK_EALIGN;
-  size_t status_off = 0;
-  if (ws_bytes < decompress_layout_bytes(len, &status_off)) return NUMARCK_ECAPACITY;
+  size_t cnt_off = 0;
+  if (ws_bytes < decompress_layout_bytes(len, &cnt_off)) return NUMARCK_ECAPACITY;
   char* base = static_cast<char*>(ws);
   DParams P{};
   P.prev = prev;
@@ -277,8 +286,9 @@ static numarck_status decompress_impl(const numarck_header* hdr, const void* pre
   P.k_used = hdr->k_used;
   P.dtype = (int)hdr->dtype;
   P.dctl = reinterpret_cast<DCtl*>(base);
-  P.status = reinterpret_cast<unsigned long long*>(base + status_off);
-  P.n_tiles = (len + DEC_TILE - 1) / DEC_TILE;
+  P.unit_cnt = reinterpret_cast<uint32_t*>(base + cnt_off);
+  P.tile_elems = wave_tile(hdr->dtype == NUMARCK_F32 ? 4 : 8);
+  P.n_tiles = (len + P.tile_elems - 1) / P.tile_elems;
   const hipError_t e = launch_decompress(P, static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(e);
   return NUMARCK_OK;
@@ -304,12 +314,13 @@ numarck_status numarck_decompress_range(const numarck_header* hdr, const void* p
 }
 
 numarck_status numarck_histogram_export(const void* ws, size_t ws_bytes, uint64_t n,
-                                        int64_t* ids, uint32_t* counts, uint64_t capacity,
-                                        uint64_t* count_dev, void* stream) {
+                                        numarck_dtype dtype, int64_t* ids, uint32_t* counts,
+                                        uint64_t capacity, uint64_t* count_dev, void* stream) {
   if (!ws || !count_dev || (capacity > 0 && (!ids || !counts))) return NUMARCK_EINVAL;
   if (n >= ((uint64_t)1 << 32)) return NUMARCK_EINVAL;
+  if (dtype != NUMARCK_F32 && dtype != NUMARCK_F64) return NUMARCK_EDTYPE;
   Layout L;
-  if (!fit_layout(n, ws_bytes, &L)) return NUMARCK_ECAPACITY;
+  if (!fit_layout(n, elem_bytes_of(dtype), ws_bytes, &L)) return NUMARCK_ECAPACITY;
   const char* base = static_cast<const char*>(ws);
   const hipError_t e = launch_histogram_export(
       reinterpret_cast<Ctl*>(const_cast<char*>(base) + L.ctl),

@@ -7,20 +7,23 @@
 //   k_init      reset the control block
 //   k_range     pass 1: ratio + validity of every point, min/max of the valid
 //               ratios, number of invalid points (Sec. IV-A); also clears the
-//               window counts and the look-back status words
+//               window counts
 //   k_derive    lo, hi, M = floor((hi-lo)/2E)+1 and the on-chip bin window
 //   k_hist      pass 2: fine histogram (Sec. IV-B-1).  Bins inside a
-//               16384-bin window are counted in LDS with wave-aggregated
-//               atomics; the ids of points outside it go to a tail list
+//               16384-bin window are counted with LDS atomics; the ids of
+//               points outside it go to a tail list
 //   k_hclear / k_hinsert   exact counts of the tail bins in a hash table
 //   k_select    top-k over window + tail counts: the k-th largest count tau by
 //               radix select, the lowest-id ties, indices in bin order, the
-//               window LUT and the centres (Sec. IV-B-1, III-B)
+//               window LUT and the centres (Sec. IV-B-1, III-B); the tail is
+//               skipped when no tail bin can reach the window's k-th count
 //   k_tailrank  rank of the selected tail bins (rare; O(t^2) over t <= 65535)
 //   k_encode    pass 3: index + verify every point, pack the B-bit indices,
-//               write incompressible values in element order through a
-//               decoupled look-back over tiles, and the per-block offsets
-//               (Sec. III-C, IV-C)
+//               stage incompressible values per wave range with
+//               range-relative block offsets (Sec. III-C, IV-C)
+//   k_uscan     offsets of the wave ranges
+//   k_gather    move the staged values to their final, element-order offsets
+//               and complete the block offsets
 //   k_final     write the header
 #include "nk_device.h"
 
@@ -37,7 +40,8 @@ __global__ void k_init(Ctl* ctl) {
     ctl->tail_count = 0ull;
     ctl->tile_ticket = 0u;
     ctl->flags = 0u;
-    ctl->sel_tail_count = 0u;
+    ctl->tail_bins = 0u;
+    ctl->tail_max = 0u;
   }
 }
 
@@ -55,12 +59,11 @@ __global__ void __launch_bounds__(RNG_TPB) k_range(CParams P) {
   const uint64_t nvec = P.n / V;
   const int tid = threadIdx.x;
 
-  // side job: clear the global window counts and the look-back words
+  // side job: clear the global window counts
   {
     const uint64_t gt = (uint64_t)blockIdx.x * RNG_TPB + tid;
     const uint64_t gs = (uint64_t)gridDim.x * RNG_TPB;
     for (uint64_t i = gt; i < (uint64_t)WIN; i += gs) P.gwin[i] = 0u;
-    for (uint64_t i = gt; i < P.n_tiles; i += gs) P.status[i] = 0ull;
   }
 
   unsigned long long kmin = ~0ull, kmax = 0ull, ninv = 0ull;
@@ -180,32 +183,25 @@ __global__ void k_derive(CParams P) {
 constexpr int HIST_TPB = 512;
 constexpr int HIST_UNROLL = 2;
 
-// Count one element per lane: window bins in LDS (one atomic per distinct bin
-// per wave), other valid points appended to the tail list (one global atomic
-// per wave).
-__device__ __forceinline__ void hist_count(uint32_t* lds, bool valid, long long m, long long wbase,
-                                           unsigned win_len, const CParams& P) {
-  const long long w = m - wbase;
-  const bool inwin = valid && w >= 0 && w < (long long)win_len;
+// Count one element per lane: window bins with LDS atomics, other valid
+// points appended to the tail list (one global atomic per wave).
+__device__ __forceinline__ void hist_count(uint32_t* lds, bool valid, double m, double wbase_d,
+                                           double wlen_d, const CParams& P) {
+  const double w = m - wbase_d;  // exact: both are integers below 2^51
+  const bool inwin = valid && w >= 0.0 && w < wlen_d;
+  if (inwin) atomicAdd(&lds[(int)w], 1u);
   const bool tail = valid && !inwin;
-  const unsigned key = inwin ? (unsigned)w : 0xFFFFFFFFu;
-  unsigned long long act = __ballot(inwin);
-  while (act) {
-    const int leader = __ffsll((long long)act) - 1;
-    const unsigned lk = (unsigned)__builtin_amdgcn_readlane((int)key, leader);
-    const unsigned long long same = __ballot(key == lk);
-    if (lane_id() == leader) atomicAdd(&lds[lk], (unsigned)__popcll(same));
-    act &= ~same;
-  }
   const unsigned long long tm = __ballot(tail);
   if (tm) {
     const int leader = __ffsll((long long)tm) - 1;
     unsigned long long base = 0;
     if (lane_id() == leader) base = atomicAdd(&P.ctl->tail_count, (unsigned long long)__popcll(tm));
-    base = __shfl(base, leader, 64);
+    const unsigned lo32 = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)base, leader);
+    const unsigned hi32 = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(base >> 32), leader);
+    base = ((unsigned long long)hi32 << 32) | lo32;
     if (tail) {
       const unsigned long long pos = base + (unsigned long long)__popcll(tm & lanemask_lt());
-      if (pos < P.tail_cap) P.tail[pos] = m;
+      if (pos < P.tail_cap) P.tail[pos] = (long long)m;
     }
   }
 }
@@ -217,8 +213,10 @@ __global__ void __launch_bounds__(HIST_TPB) k_hist(CParams P) {
   const Ctl* c = P.ctl;
   if (c->empty) return;
   const double lo = c->lo;
-  const long long wbase = c->wbase;
+  const double wbase_d = (double)c->wbase;
+  const double wlen_d = (double)c->win_len;
   const unsigned win_len = c->win_len;
+  const bool fast = P.fastbin != 0;
   const int tid = threadIdx.x;
   for (int i = tid; i < WIN; i += HIST_TPB) lds[i] = 0u;
   __syncthreads();
@@ -246,8 +244,8 @@ __global__ void __launch_bounds__(HIST_TPB) k_hist(CParams P) {
         double d = 0.0;
         const bool valid =
             inr && ratio_of((double)pv[u][v], (double)qv[u][v], P.cap, d);
-        const long long m = valid ? bin_of(d, lo, P.twoE) : 0;
-        hist_count(lds, valid, m, wbase, win_len, P);
+        const double m = valid ? bin_floor(d - lo, P.twoE, P.inv2E, fast) : 0.0;
+        hist_count(lds, valid, m, wbase_d, wlen_d, P);
       }
     }
   }
@@ -256,8 +254,8 @@ __global__ void __launch_bounds__(HIST_TPB) k_hist(CParams P) {
     double d = 0.0;
     bool valid = false;
     if (j < P.n) valid = ratio_of((double)prev[j], (double)curr[j], P.cap, d);
-    const long long m = valid ? bin_of(d, lo, P.twoE) : 0;
-    hist_count(lds, valid, m, wbase, win_len, P);
+    const double m = valid ? bin_floor(d - lo, P.twoE, P.inv2E, fast) : 0.0;
+    hist_count(lds, valid, m, wbase_d, wlen_d, P);
   }
   __syncthreads();
   for (unsigned i = tid; i < win_len; i += HIST_TPB) {
@@ -306,131 +304,225 @@ __global__ void k_hinsert(CParams P) {
   const unsigned long long mask = c->H - 1;
   const uint64_t gt = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const uint64_t gs = (uint64_t)gridDim.x * blockDim.x;
+  unsigned long long fresh = 0, top = 0;
   for (uint64_t i = gt; i < used; i += gs) {
     const long long id = P.tail[i];
     unsigned long long h = hash_id(id) & mask;
     while (true) {  // load factor <= 1/2: a free or matching slot exists
       const uint32_t old = atomicCAS(&P.hslot[h], HEMPTY, (uint32_t)i);
       if (old == HEMPTY || P.tail[old] == id) {
-        atomicAdd(&P.hcnt[h], 1u);
+        const uint32_t before = atomicAdd(&P.hcnt[h], 1u);
+        top = before + 1 > top ? before + 1 : top;
+        fresh += old == HEMPTY ? 1 : 0;
         break;
       }
       h = (h + 1) & mask;
     }
+  }
+  // distinct tail bins and the largest final count (the last increment of a
+  // bin returns its final count minus one)
+  fresh = wave_sum_u64(fresh);
+  top = wave_max_u64(top);
+  if (lane_id() == 0) {
+    if (fresh) atomicAdd(&P.ctl->tail_bins, (unsigned)fresh);
+    if (top) atomicMax(&P.ctl->tail_max, (unsigned)top);
   }
 }
 
 // =====================================================================
 // k_select: top-k over the window and the tail bins (one workgroup)
 // =====================================================================
+// The window counts are staged in LDS.  tau (the k-th largest count) and the
+// tie cut are found by MSD radix select with 2048-bucket LDS histograms.  If
+// the window alone holds k nonzero bins, its k-th count tau_w bounds tau from
+// below; when every tail bin count is smaller than tau_w (k_hinsert records
+// the largest), no tail bin can be selected or tie, and the tail is never
+// read.  Otherwise the hash table's slots are visited too.
 constexpr int SEL_TPB = 1024;
 constexpr int SEL_DIGIT = 11;
 constexpr int SEL_BUCKETS = 1 << SEL_DIGIT;
 
-struct Cand {
-  long long id;
-  uint32_t cnt;
+struct SelShared {
+  uint32_t win[WIN];
+  uint32_t hist[SEL_BUCKETS];
+  unsigned long long red[SEL_TPB / 64];
+  unsigned scan[SEL_TPB];
+  unsigned bucket;
+  unsigned long long before;
+  unsigned tail_pos;
 };
 
-// Candidate i: i < win_len is window bin wbase + i, otherwise hash slot
-// i - win_len (count 0 when the slot is empty).
-__device__ __forceinline__ Cand cand_at(const CParams& P, uint64_t i, long long wbase,
-                                        unsigned win_len) {
-  Cand c;
-  if (i < win_len) {
-    c.id = wbase + (long long)i;
-    c.cnt = P.gwin[i];
-  } else {
-    const uint64_t s = i - win_len;
-    const uint32_t slot = P.hslot[s];
-    if (slot == HEMPTY) {
-      c.id = -1;
-      c.cnt = 0;
-    } else {
-      c.id = P.tail[slot];
-      c.cnt = P.hcnt[s];
-    }
-  }
-  return c;
-}
-
-// Block-wide sum of one value per thread (SEL_TPB threads).
-__device__ unsigned long long sel_block_sum(unsigned long long v, unsigned long long* red) {
+// Block-wide reductions (every thread calls them).
+__device__ unsigned long long sel_sum(unsigned long long v, SelShared& S) {
   v = wave_sum_u64(v);
-  const int w = threadIdx.x / 64;
   __syncthreads();
-  if (lane_id() == 0) red[w] = v;
+  if (lane_id() == 0) S.red[threadIdx.x / 64] = v;
   __syncthreads();
   unsigned long long t = 0;
-  for (int i = 0; i < SEL_TPB / 64; ++i) t += red[i];
+  for (int i = 0; i < SEL_TPB / 64; ++i) t += S.red[i];
+  __syncthreads();
+  return t;
+}
+__device__ unsigned long long sel_max(unsigned long long v, SelShared& S) {
+  v = wave_max_u64(v);
+  __syncthreads();
+  if (lane_id() == 0) S.red[threadIdx.x / 64] = v;
+  __syncthreads();
+  unsigned long long t = 0;
+  for (int i = 0; i < SEL_TPB / 64; ++i) t = S.red[i] > t ? S.red[i] : t;
+  __syncthreads();
+  return t;
+}
+__device__ unsigned long long sel_min(unsigned long long v, SelShared& S) {
+  v = wave_min_u64(v);
+  __syncthreads();
+  if (lane_id() == 0) S.red[threadIdx.x / 64] = v;
+  __syncthreads();
+  unsigned long long t = ~0ull;
+  for (int i = 0; i < SEL_TPB / 64; ++i) t = S.red[i] < t ? S.red[i] : t;
   __syncthreads();
   return t;
 }
 
-// Add one to bucket `b` for every lane with `on`, one LDS atomic per distinct bucket.
-__device__ __forceinline__ void bucket_add(uint32_t* hist, bool on, unsigned b) {
-  const unsigned key = on ? b : 0xFFFFFFFFu;
-  unsigned long long act = __ballot(on);
-  while (act) {
-    const int leader = __ffsll((long long)act) - 1;
-    const unsigned lk = (unsigned)__builtin_amdgcn_readlane((int)key, leader);
-    const unsigned long long same = __ballot(key == lk);
-    if (lane_id() == leader) atomicAdd(&hist[lk], (unsigned)__popcll(same));
-    act &= ~same;
-  }
-}
-
-// Find, scanning buckets from the top (descending=true) or bottom, the bucket
-// where the running count reaches `target` (1-based).  Returns the bucket and
-// the count strictly before it in scan order.
-__device__ void scan_buckets(const uint32_t* hist, unsigned long long target, bool descending,
-                             unsigned* out_bucket, unsigned long long* out_before,
-                             unsigned long long* red) {
-  // one wave: each lane owns 32 consecutive buckets in scan order
-  __shared__ unsigned s_bucket;
-  __shared__ unsigned long long s_before;
+// Bucket where the running count, scanned from the top (descending) or the
+// bottom, reaches `target` (1-based); S.before = count strictly before it.
+__device__ void sel_scan(SelShared& S, unsigned long long target, bool descending) {
   if (threadIdx.x < 64) {
     const int lane = threadIdx.x;
+    constexpr int PER = SEL_BUCKETS / 64;
     unsigned long long mine = 0;
-    for (int i = 0; i < SEL_BUCKETS / 64; ++i) {
-      const int pos = lane * (SEL_BUCKETS / 64) + i;
-      const int b = descending ? SEL_BUCKETS - 1 - pos : pos;
-      mine += hist[b];
+    for (int i = 0; i < PER; ++i) {
+      const int pos = lane * PER + i;
+      mine += S.hist[descending ? SEL_BUCKETS - 1 - pos : pos];
     }
-    // inclusive scan over lanes
     unsigned long long inc = mine;
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
-      unsigned long long t = __shfl_up(inc, o, 64);
+      const unsigned long long t = __shfl_up(inc, o, 64);
       if (lane >= o) inc += t;
     }
     const unsigned long long exc = inc - mine;
-    const bool here = exc < target && inc >= target;
-    if (here) {
+    if (exc < target && inc >= target) {
       unsigned long long run = exc;
-      for (int i = 0; i < SEL_BUCKETS / 64; ++i) {
-        const int pos = lane * (SEL_BUCKETS / 64) + i;
+      for (int i = 0; i < PER; ++i) {
+        const int pos = lane * PER + i;
         const int b = descending ? SEL_BUCKETS - 1 - pos : pos;
-        if (run + hist[b] >= target) {
-          s_bucket = (unsigned)b;
-          s_before = run;
+        if (run + S.hist[b] >= target) {
+          S.bucket = (unsigned)b;
+          S.before = run;
           break;
         }
-        run += hist[b];
+        run += S.hist[b];
       }
     }
   }
   __syncthreads();
-  *out_bucket = s_bucket;
-  *out_before = s_before;
-  (void)red;
+}
+
+// Visit every nonzero candidate (id, count): the window from LDS, then, if
+// `tail`, the occupied hash slots.
+template <typename F>
+__device__ __forceinline__ void sel_visit(const CParams& P, const SelShared& S, long long wbase,
+                                          unsigned win_len, bool tail, unsigned long long H, F f) {
+  for (unsigned w = threadIdx.x; w < win_len; w += SEL_TPB) {
+    const uint32_t cn = S.win[w];
+    if (cn) f(wbase + (long long)w, cn);
+  }
+  if (tail) {
+    for (unsigned long long s0 = 0; s0 < H; s0 += (unsigned long long)SEL_TPB * 4) {
+      uint32_t slot[4], cn[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const unsigned long long si = s0 + (unsigned long long)u * SEL_TPB + threadIdx.x;
+        slot[u] = si < H ? P.hslot[si] : HEMPTY;
+        cn[u] = si < H ? P.hcnt[si] : 0u;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (slot[u] != HEMPTY && cn[u]) f((long long)P.tail[slot[u]], cn[u]);
+    }
+  }
+}
+
+// k-th largest count (k-th from the top, 1-based) among the visited candidates.
+template <typename Visit>
+__device__ unsigned sel_kth_count(SelShared& S, unsigned long long mx, unsigned long long k,
+                                  Visit visit) {
+  unsigned long long target = k;
+  unsigned prefix = 0;
+  int top = 0;
+  while (top < 32 && (mx >> top) != 0) top += SEL_DIGIT;
+  for (int shift = top - SEL_DIGIT; shift >= 0; shift -= SEL_DIGIT) {
+    for (int i = threadIdx.x; i < SEL_BUCKETS; i += SEL_TPB) S.hist[i] = 0u;
+    __syncthreads();
+    const unsigned hmask =
+        (shift + SEL_DIGIT >= 32) ? 0u : (unsigned)(0xFFFFFFFFull << (shift + SEL_DIGIT));
+    visit([&](long long, uint32_t cn) {
+      if ((cn & hmask) == (prefix & hmask)) atomicAdd(&S.hist[(cn >> shift) & (SEL_BUCKETS - 1)], 1u);
+    });
+    __syncthreads();
+    sel_scan(S, target, true);
+    target -= S.before;
+    prefix |= S.bucket << shift;
+    __syncthreads();
+  }
+  return prefix;
+}
+
+// The r-th smallest id (1-based) among candidates with count == tau, given
+// the smallest and largest such id.
+template <typename Visit>
+__device__ long long sel_rth_tie(SelShared& S, unsigned tau, unsigned long long r,
+                                 unsigned long long tmin, unsigned long long tmax, Visit visit) {
+  const unsigned long long span = tmax - tmin;
+  int topb = 0;
+  while (topb < 64 && (span >> topb) != 0) topb += SEL_DIGIT;
+  unsigned long long pre = 0, tgt = r;
+  for (int shift = topb - SEL_DIGIT; shift >= 0; shift -= SEL_DIGIT) {
+    for (int i = threadIdx.x; i < SEL_BUCKETS; i += SEL_TPB) S.hist[i] = 0u;
+    __syncthreads();
+    const unsigned long long hmask =
+        (shift + SEL_DIGIT >= 64) ? 0ull : (~0ull << (shift + SEL_DIGIT));
+    visit([&](long long id, uint32_t cn) {
+      const unsigned long long rel = (unsigned long long)id - tmin;
+      if (cn == tau && (rel & hmask) == (pre & hmask))
+        atomicAdd(&S.hist[(rel >> shift) & (SEL_BUCKETS - 1)], 1u);
+    });
+    __syncthreads();
+    sel_scan(S, tgt, false);
+    tgt -= S.before;
+    pre |= (unsigned long long)S.bucket << shift;
+    __syncthreads();
+  }
+  return (long long)(tmin + pre);
+}
+
+// tau and the tie cut over the visited candidates (nz nonzero of them, nz > k).
+template <typename Visit>
+__device__ void sel_threshold(SelShared& S, unsigned long long mx, unsigned long long k,
+                              Visit visit, unsigned* tau_out, long long* cut_out) {
+  const unsigned tau = sel_kth_count(S, mx, k, visit);
+  unsigned long long gt = 0, ties = 0, tmin = ~0ull, tmax = 0;
+  visit([&](long long id, uint32_t cn) {
+    if (cn > tau) gt += 1;
+    if (cn == tau) {
+      ties += 1;
+      tmin = (unsigned long long)id < tmin ? (unsigned long long)id : tmin;
+      tmax = (unsigned long long)id > tmax ? (unsigned long long)id : tmax;
+    }
+  });
+  gt = sel_sum(gt, S);
+  ties = sel_sum(ties, S);
+  tmin = sel_min(tmin, S);
+  tmax = sel_max(tmax, S);
+  const unsigned long long r = k - gt;  // ties to take, >= 1
+  *tau_out = tau;
+  *cut_out = r >= ties ? (long long)tmax : sel_rth_tie(S, tau, r, tmin, tmax, visit);
 }
 
 template <typename T>
 __global__ void __launch_bounds__(SEL_TPB) k_select(CParams P) {
-  __shared__ uint32_t hist[SEL_BUCKETS];
-  __shared__ unsigned long long red[SEL_TPB / 64];
-  __shared__ unsigned long long s_scan[SEL_TPB];
+  __shared__ SelShared S;
   Ctl* c = P.ctl;
   const int tid = threadIdx.x;
   const uint32_t k = P.k;
@@ -445,180 +537,128 @@ __global__ void __launch_bounds__(SEL_TPB) k_select(CParams P) {
   const bool empty = c->empty != 0;
   const long long wbase = empty ? 0 : c->wbase;
   const unsigned win_len = empty ? 0u : c->win_len;
-  const unsigned long long H = (empty || c->tail_used == 0) ? 0ull : c->H;
-  const uint64_t ncand = (uint64_t)win_len + H;
+  const bool has_tail = !empty && c->tail_used > 0;
+  const unsigned long long H = has_tail ? c->H : 0ull;
+  const unsigned long long tail_bins = has_tail ? c->tail_bins : 0ull;
+  const unsigned long long tail_max = has_tail ? c->tail_max : 0ull;
   const double lo = empty ? 0.0 : c->lo;
+  if (tid == 0) S.tail_pos = 0;
+  for (int i = tid; i < WIN; i += SEL_TPB) S.win[i] = (unsigned)i < win_len ? P.gwin[i] : 0u;
+  __syncthreads();
 
-  // ---- pass 0: number of nonzero bins and the largest count
-  unsigned long long nz = 0, mx = 0;
-  for (uint64_t i = tid; i < ncand; i += SEL_TPB) {
-    const Cand cd = cand_at(P, i, wbase, win_len);
-    if (cd.cnt) {
-      nz += 1;
-      mx = cd.cnt > mx ? cd.cnt : mx;
-    }
+  // window statistics
+  unsigned long long nzw = 0, mxw = 0;
+  for (unsigned w = tid; w < win_len; w += SEL_TPB) {
+    const uint32_t cn = S.win[w];
+    nzw += cn ? 1 : 0;
+    mxw = cn > mxw ? cn : mxw;
   }
-  nz = sel_block_sum(nz, red);
-  {
-    mx = wave_max_u64(mx);
-    if (lane_id() == 0) red[tid / 64] = mx;
-    __syncthreads();
-    unsigned long long t = 0;
-    for (int i = 0; i < SEL_TPB / 64; ++i) t = red[i] > t ? red[i] : t;
-    mx = t;
-    __syncthreads();
-  }
+  nzw = sel_sum(nzw, S);
+  mxw = sel_max(mxw, S);
+  const unsigned long long nz = nzw + tail_bins;
+
+  auto visit_win = [&](auto f) { sel_visit(P, S, wbase, win_len, false, 0ull, f); };
+  auto visit_all = [&](auto f) { sel_visit(P, S, wbase, win_len, has_tail, H, f); };
 
   unsigned tau = 0;
   long long cut = -1;
+  bool tail_matters = has_tail;
   if (nz > k) {
-    // ---- tau = k-th largest count, radix select from the top digit
-    unsigned long long target = k;  // rank from the top, 1-based
-    unsigned prefix = 0;
-    int top = 0;
-    while (top < 32 && (mx >> top) != 0) top += SEL_DIGIT;
-    for (int shift = top - SEL_DIGIT; shift >= 0; shift -= SEL_DIGIT) {
-      for (int i = tid; i < SEL_BUCKETS; i += SEL_TPB) hist[i] = 0u;
-      __syncthreads();
-      const unsigned long long hmask = (shift + SEL_DIGIT >= 32) ? 0ull
-                                       : (~0ull << (shift + SEL_DIGIT)) & 0xFFFFFFFFull;
-      for (uint64_t i0 = 0; i0 < ncand; i0 += SEL_TPB) {
-        const uint64_t i = i0 + tid;
-        Cand cd;
-        cd.cnt = 0;
-        if (i < ncand) cd = cand_at(P, i, wbase, win_len);
-        const bool on = cd.cnt != 0 && ((cd.cnt & hmask) == (prefix & hmask));
-        bucket_add(hist, on, (cd.cnt >> shift) & (SEL_BUCKETS - 1));
-      }
-      __syncthreads();
-      unsigned b;
-      unsigned long long before;
-      scan_buckets(hist, target, true, &b, &before, red);
-      target -= before;
-      prefix |= b << shift;
-      __syncthreads();
-    }
-    tau = prefix;
-    // ---- ties: the r lowest ids among count == tau
-    unsigned long long gt = 0, ties = 0, tmin = ~0ull, tmax = 0;
-    for (uint64_t i = tid; i < ncand; i += SEL_TPB) {
-      const Cand cd = cand_at(P, i, wbase, win_len);
-      if (cd.cnt > tau) gt += 1;
-      if (cd.cnt == tau && cd.cnt) {
-        ties += 1;
-        tmin = (unsigned long long)cd.id < tmin ? (unsigned long long)cd.id : tmin;
-        tmax = (unsigned long long)cd.id > tmax ? (unsigned long long)cd.id : tmax;
+    bool done = false;
+    if (nzw >= k) {
+      unsigned tw;
+      long long cw;
+      sel_threshold(S, mxw, k, visit_win, &tw, &cw);
+      if (tail_max < tw) {  // no tail bin reaches the window's k-th count
+        tau = tw;
+        cut = cw;
+        done = true;
+        tail_matters = false;
       }
     }
-    gt = sel_block_sum(gt, red);
-    ties = sel_block_sum(ties, red);
-    tmin = wave_min_u64(tmin);
-    tmax = wave_max_u64(tmax);
-    if (lane_id() == 0) red[tid / 64] = tmin;
-    __syncthreads();
-    unsigned long long t0 = ~0ull;
-    for (int i = 0; i < SEL_TPB / 64; ++i) t0 = red[i] < t0 ? red[i] : t0;
-    __syncthreads();
-    if (lane_id() == 0) red[tid / 64] = tmax;
-    __syncthreads();
-    unsigned long long t1 = 0;
-    for (int i = 0; i < SEL_TPB / 64; ++i) t1 = red[i] > t1 ? red[i] : t1;
-    __syncthreads();
-    tmin = t0;
-    tmax = t1;
-    const unsigned long long r = (unsigned long long)k - gt;  // ties to take, >= 1
-    if (r >= ties) {
-      cut = (long long)tmax;
-    } else {
-      // radix select the r-th smallest (id - tmin) among the ties
-      const unsigned long long span = tmax - tmin;
-      int topb = 0;
-      while (topb < 64 && (span >> topb) != 0) topb += SEL_DIGIT;
-      unsigned long long pre = 0;
-      unsigned long long tgt = r;
-      for (int shift = topb - SEL_DIGIT; shift >= 0; shift -= SEL_DIGIT) {
-        for (int i = tid; i < SEL_BUCKETS; i += SEL_TPB) hist[i] = 0u;
-        __syncthreads();
-        const unsigned long long hmask =
-            (shift + SEL_DIGIT >= 64) ? 0ull : (~0ull << (shift + SEL_DIGIT));
-        for (uint64_t i0 = 0; i0 < ncand; i0 += SEL_TPB) {
-          const uint64_t i = i0 + tid;
-          Cand cd;
-          cd.cnt = 0;
-          cd.id = 0;
-          if (i < ncand) cd = cand_at(P, i, wbase, win_len);
-          const unsigned long long rel = (unsigned long long)cd.id - tmin;
-          const bool on = cd.cnt == tau && cd.cnt != 0 && ((rel & hmask) == (pre & hmask));
-          bucket_add(hist, on, (unsigned)((rel >> shift) & (SEL_BUCKETS - 1)));
-        }
-        __syncthreads();
-        unsigned b;
-        unsigned long long before;
-        scan_buckets(hist, tgt, false, &b, &before, red);
-        tgt -= before;
-        pre |= (unsigned long long)b << shift;
-        __syncthreads();
-      }
-      cut = (long long)(tmin + pre);
+    if (!done) {
+      const unsigned long long mx = mxw > tail_max ? mxw : tail_max;
+      sel_threshold(S, mx, k, visit_all, &tau, &cut);
     }
   }
-  // selected <=> cnt > tau, or cnt == tau (nonzero) and id <= cut
-  // ---- selected tail bins: counts and the ones below the window
+  // selected <=> cnt > tau, or cnt == tau and id <= cut (cnt nonzero)
   unsigned long long sel_tail = 0, sel_below = 0;
-  __shared__ unsigned s_tail_pos;
-  if (tid == 0) s_tail_pos = 0;
-  __syncthreads();
-  for (uint64_t i = (uint64_t)win_len + tid; i < ncand; i += SEL_TPB) {
-    const Cand cd = cand_at(P, i, wbase, win_len);
-    const bool s = cd.cnt != 0 && (cd.cnt > tau || (cd.cnt == tau && cd.id <= cut));
-    if (s) {
-      sel_tail += 1;
-      if (cd.id < wbase) sel_below += 1;
-      const unsigned pos = atomicAdd(&s_tail_pos, 1u);
-      P.sel_tail[pos] = cd.id;
+  if (tail_matters) {
+    for (unsigned long long si = tid; si < H; si += SEL_TPB) {
+      const uint32_t slot = P.hslot[si];
+      if (slot == HEMPTY) continue;
+      const uint32_t cn = P.hcnt[si];
+      const long long id = P.tail[slot];
+      if (cn != 0 && (cn > tau || (cn == tau && id <= cut))) {
+        sel_tail += 1;
+        if (id < wbase) sel_below += 1;
+        const unsigned pos = atomicAdd(&S.tail_pos, 1u);
+        P.sel_tail[pos] = id;
+      }
     }
   }
-  sel_tail = sel_block_sum(sel_tail, red);
-  sel_below = sel_block_sum(sel_below, red);
+  sel_tail = sel_sum(sel_tail, S);
+  sel_below = sel_sum(sel_below, S);
 
-  // ---- window: LUT and ranks.  Thread t owns bins [t*per, (t+1)*per).
+  // window: LUT, centres and bin ids in ascending bin order.
+  // Thread t owns window bins [t*PER, (t+1)*PER).
   constexpr int PER = WIN / SEL_TPB;
   unsigned mine = 0;
+#pragma unroll
   for (int q = 0; q < PER; ++q) {
     const unsigned w = tid * PER + q;
-    if (w < win_len) {
-      const uint32_t cn = P.gwin[w];
-      const long long id = wbase + (long long)w;
-      mine += (cn != 0 && (cn > tau || (cn == tau && id <= cut))) ? 1u : 0u;
-    }
+    const uint32_t cn = S.win[w];
+    const long long id = wbase + (long long)w;
+    mine += (cn != 0 && (cn > tau || (cn == tau && id <= cut))) ? 1u : 0u;
   }
-  s_scan[tid] = mine;
+  S.scan[tid] = mine;
   __syncthreads();
-  if (tid == 0) {  // exclusive scan over 1024 partial counts
-    unsigned long long run = 0;
-    for (int i = 0; i < SEL_TPB; ++i) {
-      const unsigned long long t = s_scan[i];
-      s_scan[i] = run;
-      run += t;
+  if (tid < 64) {  // exclusive scan of 1024 partial counts by one wave
+    unsigned run = 0;
+    unsigned v[SEL_TPB / 64];
+#pragma unroll
+    for (int i = 0; i < SEL_TPB / 64; ++i) {
+      v[i] = S.scan[tid * (SEL_TPB / 64) + i];
+      run += v[i];
     }
-    c->nsel_window = (unsigned)run;
+    unsigned inc = run;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const unsigned t = __shfl_up(inc, o, 64);
+      if (tid >= o) inc += t;
+    }
+    unsigned ex = inc - run;
+#pragma unroll
+    for (int i = 0; i < SEL_TPB / 64; ++i) {
+      S.scan[tid * (SEL_TPB / 64) + i] = ex;
+      ex += v[i];
+    }
+    if (tid == 63) c->nsel_window = inc;
   }
   __syncthreads();
-  unsigned rank = (unsigned)(sel_below + s_scan[tid]);
+  unsigned rank = (unsigned)sel_below + S.scan[tid];
+  unsigned mask16 = 0;
+#pragma unroll
   for (int q = 0; q < PER; ++q) {
     const unsigned w = tid * PER + q;
-    uint16_t l = NOSEL;
-    if (w < win_len) {
-      const uint32_t cn = P.gwin[w];
-      const long long id = wbase + (long long)w;
-      if (cn != 0 && (cn > tau || (cn == tau && id <= cut))) {
-        l = (uint16_t)rank;
-        centers[rank] = (T)centre_of<T>(id, lo, P.E);
-        if (P.bin_ids) P.bin_ids[rank] = id;
-        rank += 1;
-      }
+    const uint32_t cn = S.win[w];
+    const long long id = wbase + (long long)w;
+    if (cn != 0 && (cn > tau || (cn == tau && id <= cut))) {
+      mask16 |= 1u << q;
+      centers[rank] = (T)centre_of<T>(id, lo, P.E);
+      if (P.bin_ids) P.bin_ids[rank] = id;
+      rank += 1;
     }
-    P.lut[w] = l;
+  }
+  // selection bitmap of the window, 64 bins per word, and the index of the
+  // first selected bin of each word (4 threads own one word's 64 bins)
+  static_assert(PER == 16, "four threads per 64-bin group");
+  const unsigned long long m0 = (unsigned long long)mask16 << (16 * (tid & 3));
+  const unsigned long long m1 = m0 | __shfl_xor(m0, 1, 64);
+  const unsigned long long m2 = m1 | __shfl_xor(m1, 2, 64);
+  if ((tid & 3) == 0) {
+    P.lutbits[tid >> 2] = m2;
+    P.lutbase[tid >> 2] = (unsigned)sel_below + S.scan[tid];
   }
   if (tid == 0) {
     c->n_nonzero = nz;
@@ -667,19 +707,23 @@ __global__ void __launch_bounds__(TR_TPB) k_tailrank(CParams P) {
 }
 
 // =====================================================================
-// k_encode: pass 3, index + verify + pack + compaction + block offsets
+// k_encode: pass 3, index + verify + pack + staged compaction
 // =====================================================================
+// Wave u owns wave tiles [u*tpu, (u+1)*tpu).  It keeps a running count of
+// the incompressible points of its range: their values go to scratch at
+// (first element of the range + running rank), each block boundary in the
+// range gets its range-relative count, and the count of the range goes to
+// unit_cnt[u].  k_uscan and k_gather then place every range.  No wave waits
+// for another and the loop has no workgroup barrier.
 template <typename T>
-__global__ void __launch_bounds__(ENC_TPB) k_encode(CParams P) {
+__global__ void __launch_bounds__(UNIT_TPB) k_encode(CParams P) {
   constexpr int V = Traits<T>::V;
-  constexpr int R = ENC_TILE / (ENC_TPB * V);  // vector rounds per tile
-  constexpr int NW = ENC_TPB / 64;
-  using U = typename Traits<T>::U;
-  __shared__ uint16_t s_lut[WIN];
-  __shared__ uint16_t s_idx[ENC_TILE];
-  __shared__ unsigned s_wcnt[R][NW];
-  __shared__ unsigned long long s_prefix;
-  __shared__ uint64_t s_tile;
+  constexpr int R = UNIT_ROUNDS;
+  constexpr int WT = R * 64 * V;  // elements of a wave tile
+  constexpr int NWAVE = UNIT_TPB / 64;
+  __shared__ unsigned long long s_bits[LUT_GROUPS];
+  __shared__ uint32_t s_base[LUT_GROUPS];
+  __shared__ uint16_t s_idx[NWAVE][WT];
 
   const Ctl* c = P.ctl;
   const int tid = threadIdx.x;
@@ -688,31 +732,41 @@ __global__ void __launch_bounds__(ENC_TPB) k_encode(CParams P) {
   const bool empty = c->empty != 0;
   const double lo = empty ? 0.0 : c->lo;
   const long long wbase = empty ? 0 : c->wbase;
+  const double wbase_d = (double)wbase;
   const unsigned win_len = empty ? 0u : c->win_len;
+  const double wlen_d = (double)win_len;
   const unsigned nsel_tail = empty ? 0u : c->nsel_tail;
   const unsigned nsel_win = empty ? 0u : c->nsel_window;
   const uint32_t esc = P.k;
-  for (unsigned i = tid; i < win_len; i += ENC_TPB) s_lut[i] = P.lut[i];
+  const bool fast = P.fastbin != 0;
+  for (int i = tid; i < LUT_GROUPS; i += UNIT_TPB) {
+    s_bits[i] = P.lutbits[i];
+    s_base[i] = P.lutbase[i];
+  }
+  __syncthreads();
 
   const T* __restrict__ prev = static_cast<const T*>(P.prev);
   const T* __restrict__ curr = static_cast<const T*>(P.curr);
-  T* __restrict__ incomp = static_cast<T*>(P.incomp);
+  T* __restrict__ scratch = static_cast<T*>(P.scratch);
   T* __restrict__ recon = static_cast<T*>(P.recon);
+  uint16_t* idx = s_idx[wave];
   const uint64_t nvec = P.n / V;
-  const uint64_t tile_words = (uint64_t)ENC_TILE * P.B / 32;
+  const uint32_t tile_words = (uint32_t)(WT * P.B / 32);
+  const uint32_t unit = blockIdx.x * NWAVE + wave;
+  const uint64_t tb = (uint64_t)unit * P.tiles_per_unit;
+  uint64_t te = tb + P.tiles_per_unit;
+  te = te < P.n_tiles ? te : P.n_tiles;
+  const uint64_t e_base = tb * WT;
+  const bool single_boundary = P.epb >= (uint64_t)WT;
+  const unsigned long long lt = lanemask_lt();
+  unsigned run = 0;  // incompressible points so far in this range
 
-  while (true) {
-    __syncthreads();
-    if (tid == 0) s_tile = atomicAdd(&P.ctl->tile_ticket, 1u);
-    __syncthreads();
-    const uint64_t tile = s_tile;
-    if (tile >= P.n_tiles) break;
-    const uint64_t t0 = tile * ENC_TILE;
-
+  for (uint64_t tile = tb; tile < te; ++tile) {
+    const uint64_t t0 = tile * WT;
     T pv[R][V], qv[R][V];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      const uint64_t vi = t0 / V + (uint64_t)r * ENC_TPB + tid;
+      const uint64_t vi = t0 / V + (uint64_t)r * 64 + lane;
       if (vi < nvec) {
         load_vec(prev, vi, pv[r]);
         load_vec(curr, vi, qv[r]);
@@ -727,11 +781,9 @@ __global__ void __launch_bounds__(ENC_TPB) k_encode(CParams P) {
     }
 
     unsigned long long emask[R][V];
-    unsigned my_esc_bits[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      my_esc_bits[r] = 0;
-      const uint64_t e0 = ((uint64_t)r * ENC_TPB + tid) * V;  // tile-local element
+      const uint32_t e0 = ((uint32_t)r * 64 + lane) * V;  // tile-local element
 #pragma unroll
       for (int v = 0; v < V; ++v) {
         const uint64_t j = t0 + e0 + v;
@@ -743,23 +795,28 @@ __global__ void __launch_bounds__(ENC_TPB) k_encode(CParams P) {
         uint32_t code = esc;
         T rv = qv[r][v];
         if (valid) {
-          const long long m = bin_of(d, lo, P.twoE);
-          const long long w = m - wbase;
+          const double m = bin_floor(d - lo, P.twoE, P.inv2E, fast);
+          const double w = m - wbase_d;  // exact
           int sel = -1;
-          if (w >= 0 && w < (long long)win_len) {
-            const uint16_t l = s_lut[w];
-            if (l != NOSEL) sel = l;
+          if (w >= 0.0 && w < wlen_d) {
+            const int wi = (int)w;
+            const unsigned long long bw = s_bits[wi >> 6];
+            const unsigned bit = (unsigned)(wi & 63);
+            if ((bw >> bit) & 1ull)
+              sel = (int)(s_base[wi >> 6] + (unsigned)__popcll(bw & ((1ull << bit) - 1ull)));
           } else if (nsel_tail) {
             // binary search among the selected tail bins
+            const long long mi = (long long)m;
             unsigned a = 0, b = nsel_tail;
             while (a < b) {
               const unsigned mid = (a + b) >> 1;
-              if (P.sorted_tail[mid] < m) a = mid + 1; else b = mid;
+              if (P.sorted_tail[mid] < mi) a = mid + 1; else b = mid;
             }
-            if (a < nsel_tail && P.sorted_tail[a] == m) sel = (int)(a + (m > wbase ? nsel_win : 0u));
+            if (a < nsel_tail && P.sorted_tail[a] == mi)
+              sel = (int)(a + (mi > wbase ? nsel_win : 0u));
           }
           if (sel >= 0) {
-            const double cc = centre_of<T>(m, lo, P.E);
+            const double cc = centre_of_d<T>(m, lo, P.E);
             const T r_t = (T)(p * (1.0 + cc));
             if (fabs((double)r_t - q) <= P.E * fabs(p)) {
               code = (uint32_t)sel;
@@ -767,22 +824,15 @@ __global__ void __launch_bounds__(ENC_TPB) k_encode(CParams P) {
             }
           }
         }
-        const bool is_esc = inr && code == esc;
-        if (!inr) code = 0;
-        s_idx[e0 + v] = (uint16_t)code;
-        emask[r][v] = __ballot(is_esc);
-        my_esc_bits[r] |= (is_esc ? 1u : 0u) << v;
-        if (recon) pv[r][v] = rv;  // reuse the register for the reconstruction
+        idx[e0 + v] = (uint16_t)(inr ? code : 0u);
+        emask[r][v] = __ballot(inr && code == esc);
+        if (recon) pv[r][v] = rv;  // the register now holds the reconstruction
       }
-      unsigned wc = 0;
-#pragma unroll
-      for (int v = 0; v < V; ++v) wc += (unsigned)__popcll(emask[r][v]);
-      if (lane == 0) s_wcnt[r][wave] = wc;
     }
     if (recon) {
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        const uint64_t vi = t0 / V + (uint64_t)r * ENC_TPB + tid;
+        const uint64_t vi = t0 / V + (uint64_t)r * 64 + lane;
         if (vi < nvec) {
           uint4 x;
           __builtin_memcpy(&x, pv[r], 16);
@@ -796,36 +846,20 @@ __global__ void __launch_bounds__(ENC_TPB) k_encode(CParams P) {
         }
       }
     }
-    __syncthreads();
-    // exclusive offsets of (round, wave) groups in element order, tile total
-    if (tid < 64) {
-      unsigned long long tot = 0;
-      if (tid == 0) {
-        for (int r = 0; r < R; ++r)
-          for (int w = 0; w < NW; ++w) {
-            const unsigned t = s_wcnt[r][w];
-            s_wcnt[r][w] = (unsigned)tot;
-            tot += t;
-          }
-      }
-      tot = __shfl(tot, 0, 64);
-      const unsigned long long ex = lookback(P.status, tile, tot);
-      if (tid == 0) s_prefix = ex;
-    }
-    __syncthreads();
-    const unsigned long long tprefix = s_prefix;
-    const unsigned long long lt = lanemask_lt();
 
-    // incompressible values and block offsets
-    const bool single_boundary = P.epb >= (uint64_t)ENC_TILE;
+    // incompressible values and block offsets, in element order (round,
+    // lane, vector slot); ranks are range-relative
     const uint64_t first_b = (t0 + P.epb - 1) / P.epb * P.epb;  // first boundary >= t0
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      unsigned below = 0;
+      unsigned below = 0, all = 0;
 #pragma unroll
-      for (int v = 0; v < V; ++v) below += (unsigned)__popcll(emask[r][v] & lt);
-      unsigned long long rank = tprefix + s_wcnt[r][wave] + below;
-      const uint64_t e0 = ((uint64_t)r * ENC_TPB + tid) * V;
+      for (int v = 0; v < V; ++v) {
+        below += (unsigned)__popcll(emask[r][v] & lt);
+        all += (unsigned)__popcll(emask[r][v]);
+      }
+      unsigned rank = run + below;
+      const uint32_t e0 = ((uint32_t)r * 64 + lane) * V;
 #pragma unroll
       for (int v = 0; v < V; ++v) {
         const uint64_t j = t0 + e0 + v;
@@ -833,29 +867,65 @@ __global__ void __launch_bounds__(ENC_TPB) k_encode(CParams P) {
           const bool at_b = single_boundary ? (j == first_b) : (j % P.epb == 0);
           if (at_b) P.block_inc_off[j / P.epb] = (long long)rank;
         }
-        if ((my_esc_bits[r] >> v) & 1u) {
-          incomp[rank] = qv[r][v];
+        if ((emask[r][v] >> lane) & 1ull) {
+          scratch[e_base + rank] = qv[r][v];
           rank += 1;
         }
       }
+      run += all;
     }
 
-    // bit-pack the tile: word w holds bits [32w, 32w + 32) of the tile's stream
+    // bit-pack the wave tile: word w holds bits [32w, 32w + 32) of its stream
+    wave_lds_sync();
     const uint64_t word0 = t0 * P.B / 32;
-    for (uint64_t w = tid; w < tile_words; w += ENC_TPB) {
+    for (uint32_t w = lane; w < tile_words; w += 64) {
       if (word0 + w >= P.packed_words) break;
-      const uint64_t bit0 = w * 32;
-      const uint32_t e_first = (uint32_t)(bit0 / P.B);
-      const uint32_t e_last = (uint32_t)((bit0 + 31) / P.B);
+      const uint32_t bit0 = w * 32;
+      const uint32_t e_first = bit0 / P.B;
+      const uint32_t e_last = (bit0 + 31) / P.B;
       uint32_t word = 0;
       for (uint32_t e = e_first; e <= e_last; ++e) {
-        const uint32_t v = s_idx[e];
-        const long long sh = (long long)e * P.B - (long long)bit0;
+        const uint32_t v = idx[e];
+        const int sh = (int)(e * P.B) - (int)bit0;
         word |= sh >= 0 ? (v << sh) : (v >> (-sh));
       }
       P.packed[word0 + w] = word;
     }
+    wave_lds_sync();
   }
+  if (lane == 0 && unit < P.n_units) P.unit_cnt[unit] = run;
+}
+
+// =====================================================================
+// k_uscan: unit counts -> exclusive unit offsets (one workgroup)
+// =====================================================================
+__global__ void __launch_bounds__(USCAN_TPB) k_uscan(CParams P) {
+  const unsigned long long total = unit_scan(P.unit_cnt, P.n_units);
+  if (threadIdx.x == 0) P.ctl->n_inc = (unsigned)total;
+}
+
+// =====================================================================
+// k_gather: move each unit's incompressible values to their final offset
+// =====================================================================
+template <typename T>
+__global__ void __launch_bounds__(UNIT_TPB) k_gather(CParams P) {
+  constexpr int V = Traits<T>::V;
+  constexpr int WT = UNIT_ROUNDS * 64 * V;
+  const uint32_t unit = blockIdx.x * (UNIT_TPB / 64) + threadIdx.x / 64;
+  if (unit >= P.n_units) return;
+  const int lane = lane_id();
+  const uint64_t e0 = (uint64_t)unit * P.tiles_per_unit * WT;
+  if (e0 >= P.n) return;
+  uint64_t e1 = e0 + P.tiles_per_unit * WT;
+  e1 = e1 < P.n ? e1 : P.n;
+  const unsigned long long off = P.unit_cnt[unit];
+  const unsigned long long next = unit + 1 < P.n_units ? P.unit_cnt[unit + 1] : P.ctl->n_inc;
+  const unsigned cnt = (unsigned)(next - off);
+  const T* __restrict__ scratch = static_cast<const T*>(P.scratch);
+  T* __restrict__ incomp = static_cast<T*>(P.incomp);
+  for (unsigned i = lane; i < cnt; i += 64) incomp[off + i] = scratch[e0 + i];
+  const uint64_t b0 = (e0 + P.epb - 1) / P.epb;
+  for (uint64_t b = b0 + lane; b * P.epb < e1; b += 64) P.block_inc_off[b] += (long long)off;
 }
 
 // =====================================================================
@@ -866,7 +936,7 @@ __global__ void k_final(CParams P) {
   const Ctl* c = P.ctl;
   numarck_header* h = P.hdr;
   const uint64_t L = P.dtype == NUMARCK_F32 ? 4 : 8;
-  const unsigned long long n_inc = P.n_tiles ? (P.status[P.n_tiles - 1] & LB_VAL) : 0ull;
+  const unsigned long long n_inc = c->n_inc;
   h->n = P.n;
   h->n_valid = c->n_valid;
   h->n_invalid = P.n - c->n_valid;
@@ -904,8 +974,18 @@ __global__ void k_final(CParams P) {
   } while (0)
 
 template <typename T>
-static hipError_t launch_compress_t(const CParams& P, hipStream_t s) {
+static hipError_t launch_compress_t(CParams P, hipStream_t s) {
   const Geometry g = geometry();
+  {  // as many encoder units as can be resident at once (4 per workgroup)
+    static int occ = 0;
+    if (occ == 0 &&
+        (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_encode<T>, UNIT_TPB, 0) !=
+             hipSuccess ||
+         occ < 1))
+      occ = 1;
+    P.n_units = range_units(P.n_tiles, g.cus * occ * 4);
+    P.tiles_per_unit = (P.n_tiles + P.n_units - 1) / P.n_units;
+  }
   constexpr int V = Traits<T>::V;
   const uint64_t nvec = P.n / V;
   uint64_t rng_blocks = (nvec + RNG_TPB * RNG_UNROLL - 1) / (RNG_TPB * RNG_UNROLL);
@@ -916,10 +996,6 @@ static hipError_t launch_compress_t(const CParams& P, hipStream_t s) {
   const uint64_t hist_cap = (uint64_t)g.cus * 2;
   if (hist_blocks > hist_cap) hist_blocks = hist_cap;
   if (hist_blocks < 1) hist_blocks = 1;
-  uint64_t enc_blocks = P.n_tiles;
-  const uint64_t enc_cap = (uint64_t)g.cus * 3;
-  if (enc_blocks > enc_cap) enc_blocks = enc_cap;
-  if (enc_blocks < 1) enc_blocks = 1;
   const uint64_t aux_blocks = (uint64_t)g.cus * 2;
 
   NK_LAUNCH(KK_INIT, k_init, 1, 64, P.ctl);
@@ -930,7 +1006,9 @@ static hipError_t launch_compress_t(const CParams& P, hipStream_t s) {
   NK_LAUNCH(KK_HINSERT, k_hinsert, aux_blocks, 256, P);
   NK_LAUNCH(KK_SELECT, k_select<T>, 1, SEL_TPB, P);
   NK_LAUNCH(KK_TAILRANK, k_tailrank<T>, 256, TR_TPB, P);
-  NK_LAUNCH(KK_ENCODE, k_encode<T>, enc_blocks, ENC_TPB, P);
+  NK_LAUNCH(KK_ENCODE, k_encode<T>, P.n_units / 4, UNIT_TPB, P);
+  NK_LAUNCH(KK_USCAN, k_uscan, 1, USCAN_TPB, P);
+  NK_LAUNCH(KK_GATHER, k_gather<T>, P.n_units / 4, UNIT_TPB, P);
   NK_LAUNCH(KK_FINAL, k_final, 1, 64, P);
   return hipSuccess;
 }

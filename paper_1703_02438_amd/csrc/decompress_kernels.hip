@@ -2,14 +2,17 @@
 // (arXiv 1703.02438, eq. 4 / Sec. III-E, partial decompression Sec. IV-C and
 // V-C).
 //
-// A range [start, start + len) is decoded in tiles taken in ticket order:
-//   k_dinit    reset the control block, the flag word and the look-back words
+// A range [start, start + len) is cut into wave tiles; each wave ("unit")
+// owns a contiguous run of them:
+//   k_dinit    reset the control block and the flag word
 //   k_dprefix  escapes before `start`: the block table gives the count up to
 //              the start of start's block, the rest is counted from the
-//              packed indices (at most one block)
-//   k_decode   unpack each index; an escape takes the next incompressible
-//              value (its rank comes from a decoupled look-back over tiles),
-//              any other index gives T(prev * (1 + centre[index]))
+//              packed indices (less than one block)
+//   k_dcount   escapes in each unit's run (reads the packed indices only)
+//   k_dscan    exclusive offsets of the runs
+//   k_decode   each unit decodes its tiles in order: an escape takes the next
+//              incompressible value, any other index gives
+//              T(prev * (1 + centre[index]))
 #include "nk_device.h"
 
 namespace nk {
@@ -25,14 +28,10 @@ __device__ __forceinline__ uint32_t unpack_index(const uint32_t* __restrict__ pa
 }
 
 __global__ void k_dinit(DParams P) {
-  const uint64_t gt = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const uint64_t gs = (uint64_t)gridDim.x * blockDim.x;
-  if (gt == 0) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
     P.dctl->base = 0ull;
-    P.dctl->ticket = 0u;
     *P.flags = 0u;
   }
-  for (uint64_t i = gt; i < P.n_tiles; i += gs) P.status[i] = 0ull;
 }
 
 __global__ void k_dprefix(DParams P) {
@@ -50,112 +49,185 @@ __global__ void k_dprefix(DParams P) {
   if (lane_id() == 0 && cnt) atomicAdd(&P.dctl->base, cnt);
 }
 
-template <typename T>
-__global__ void __launch_bounds__(DEC_TPB) k_decode(DParams P) {
-  constexpr int R = DEC_TILE / DEC_TPB;
-  constexpr int NW = DEC_TPB / 64;
-  __shared__ unsigned s_wcnt[R][NW];
-  __shared__ unsigned long long s_prefix;
-  __shared__ uint64_t s_tile;
+// Escapes in each unit's range of wave tiles (reads the packed indices only).
+__global__ void __launch_bounds__(UNIT_TPB) k_dcount(DParams P) {
+  const uint32_t unit = blockIdx.x * (UNIT_TPB / 64) + threadIdx.x / 64;
+  const int lane = lane_id();
+  const uint32_t esc = (1u << P.B) - 1u;
+  const uint64_t end = P.start + P.len;
+  uint64_t r0 = P.start + (uint64_t)unit * P.tiles_per_unit * P.tile_elems;
+  uint64_t r1 = r0 + P.tiles_per_unit * P.tile_elems;
+  r0 = r0 < end ? r0 : end;
+  r1 = r1 < end ? r1 : end;
+  unsigned long long cnt = 0;
+  for (uint64_t j = r0 + lane; j < r1; j += 64)
+    cnt += unpack_index(P.packed, j, P.B) == esc ? 1ull : 0ull;
+  cnt = wave_sum_u64(cnt);
+  if (lane == 0) P.unit_cnt[unit] = (uint32_t)cnt;
+}
+
+__global__ void __launch_bounds__(USCAN_TPB) k_dscan(DParams P) {
+  (void)unit_scan(P.unit_cnt, P.n_units);
+}
+
+// LDS budget for the centre table (used when 2^B entries fit).
+constexpr int DEC_CENT_BYTES = 32768;
+
+// Unit u decodes its wave tiles in order.  Each lane handles V consecutive
+// elements per round (V = 16 / sizeof(T)); VEC selects 16-byte vector loads
+// of prev and stores of out (start a multiple of V, pointers 16-byte
+// aligned), otherwise the same elements are moved one by one.
+template <typename T, bool VEC>
+__global__ void __launch_bounds__(UNIT_TPB) k_decode(DParams P) {
+  constexpr int V = Traits<T>::V;
+  constexpr int R = UNIT_ROUNDS;
+  constexpr int WT = R * 64 * V;
+  constexpr int NWAVE = UNIT_TPB / 64;
+  constexpr int TW = WT * 16 / 32 + 2;  // packed words of one wave tile, at most
+  __shared__ uint32_t s_words[NWAVE][TW];
+  extern __shared__ unsigned char s_dyn[];  // centre table when it fits
+  T* s_cent = reinterpret_cast<T*>(s_dyn);
   const int tid = threadIdx.x;
   const int wave = tid / 64;
   const int lane = lane_id();
-  const uint32_t esc = (1u << P.B) - 1u;
+  const uint32_t B = P.B;
+  const uint32_t esc = (1u << B) - 1u;
   const T* __restrict__ prev = static_cast<const T*>(P.prev);
   const T* __restrict__ centers = static_cast<const T*>(P.centers);
   const T* __restrict__ incomp = static_cast<const T*>(P.incomp);
   T* __restrict__ out = static_cast<T*>(P.out);
   const uint64_t end = P.start + P.len;
+  const bool lds_cent = ((uint64_t)1 << B) * sizeof(T) <= (uint64_t)DEC_CENT_BYTES;
+  if (lds_cent)
+    for (int i = tid; i < (1 << B); i += UNIT_TPB) s_cent[i] = centers[i];
+  __syncthreads();
 
-  while (true) {
-    __syncthreads();
-    if (tid == 0) s_tile = atomicAdd(&P.dctl->ticket, 1u);
-    __syncthreads();
-    const uint64_t tile = s_tile;
-    if (tile >= P.n_tiles) break;
-    const uint64_t t0 = P.start + tile * DEC_TILE;
+  const uint32_t unit = blockIdx.x * NWAVE + wave;
+  uint32_t* words = s_words[wave];
+  const uint64_t tb = (uint64_t)unit * P.tiles_per_unit;
+  uint64_t te = tb + P.tiles_per_unit;
+  te = te < P.n_tiles ? te : P.n_tiles;
+  unsigned long long run = P.dctl->base + (tb < te ? P.unit_cnt[unit] : 0u);
+  const unsigned long long lt = lanemask_lt();
+  bool bad = false, over = false;
+  for (uint64_t tile = tb; tile < te; ++tile) {
+    const uint64_t t0 = P.start + tile * WT;
+    const uint64_t rem = end - t0;
+    const uint32_t tn = rem < (uint64_t)WT ? (uint32_t)rem : (uint32_t)WT;
+    const uint64_t wlo = (t0 * B) >> 5;
+    const uint32_t nw = (uint32_t)((((t0 + tn) * B + 31) >> 5) - wlo);
+    for (uint32_t i = lane; i < nw; i += 64) words[i] = P.packed[wlo + i];
 
-    uint32_t code[R];
-    unsigned long long emask[R];
+    T pv[R][V];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      const uint64_t j = t0 + (uint64_t)r * DEC_TPB + tid;
-      const bool inr = j < end;
-      code[r] = inr ? unpack_index(P.packed, j, P.B) : 0u;
-      emask[r] = __ballot(inr && code[r] == esc);
-      if (lane == 0) s_wcnt[r][wave] = (unsigned)__popcll(emask[r]);
-    }
-    __syncthreads();
-    if (tid < 64) {
-      unsigned long long tot = 0;
-      if (tid == 0) {
-        for (int r = 0; r < R; ++r)
-          for (int w = 0; w < NW; ++w) {
-            const unsigned t = s_wcnt[r][w];
-            s_wcnt[r][w] = (unsigned)tot;
-            tot += t;
-          }
+      const uint32_t e = ((uint32_t)r * 64 + lane) * V;
+      if (VEC && e + V <= tn) {
+        load_vec(prev, (t0 + e) / V, pv[r]);
+      } else {
+#pragma unroll
+        for (int v = 0; v < V; ++v) pv[r][v] = e + v < tn ? prev[t0 + e + v] : (T)0;
       }
-      tot = __shfl(tot, 0, 64);
-      const unsigned long long ex = lookback(P.status, tile, tot);
-      if (tid == 0) s_prefix = ex;
     }
-    __syncthreads();
-    const unsigned long long base = P.dctl->base + s_prefix;
-    const unsigned long long lt = lanemask_lt();
-    bool bad = false, over = false;
+    wave_lds_sync();
+
+    const uint32_t bitbase = (uint32_t)(t0 * B - wlo * 32);
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      const uint64_t j = t0 + (uint64_t)r * DEC_TPB + tid;
-      if (j < end) {
-        T v;
-        if (code[r] == esc) {
-          const unsigned long long rank =
-              base + s_wcnt[r][wave] + (unsigned long long)__popcll(emask[r] & lt);
+      const uint32_t e = ((uint32_t)r * 64 + lane) * V;
+      uint32_t code[V];
+      unsigned long long emask[V];
+      unsigned below = 0, all = 0;
+#pragma unroll
+      for (int v = 0; v < V; ++v) {
+        uint32_t cd = 0;
+        if (e + v < tn) {
+          const uint32_t bit = bitbase + (e + v) * B;
+          const uint32_t w = bit >> 5, sh = bit & 31;
+          uint32_t x = words[w] >> sh;
+          if (sh + B > 32) x |= words[w + 1] << (32 - sh);
+          cd = x & esc;
+        }
+        code[v] = cd;
+        emask[v] = __ballot(e + v < tn && cd == esc);
+        below += (unsigned)__popcll(emask[v] & lt);
+        all += (unsigned)__popcll(emask[v]);
+      }
+      unsigned long long rank = run + below;
+      T ov[V];
+#pragma unroll
+      for (int v = 0; v < V; ++v) {
+        const uint32_t cd = code[v];
+        if ((emask[v] >> lane) & 1ull) {
           if (rank < P.n_inc) {
-            v = incomp[rank];
+            ov[v] = incomp[rank];
           } else {
             over = true;
-            v = (T)0;
+            ov[v] = (T)0;
           }
+          rank += 1;
         } else {
-          bad |= code[r] >= P.k_used;
-          const double c = (double)centers[code[r]];
-          v = (T)((double)prev[j] * (1.0 + c));
+          bad |= (e + v < tn) && cd >= P.k_used;
+          const double c = (double)(lds_cent ? s_cent[cd] : centers[cd]);
+          ov[v] = (T)((double)pv[r][v] * (1.0 + c));
         }
-        out[j - P.start] = v;
       }
+      const uint64_t o = t0 + e - P.start;
+      if (VEC && e + V <= tn) {
+        uint4 x;
+        __builtin_memcpy(&x, ov, 16);
+        reinterpret_cast<uint4*>(out)[o / V] = x;
+      } else {
+#pragma unroll
+        for (int v = 0; v < V; ++v)
+          if (e + v < tn) out[o + v] = ov[v];
+      }
+      run += all;
     }
-    if (__ballot(bad) && lane == 0) atomicOr(P.flags, NUMARCK_FLAG_BAD_INDEX);
-    if (__ballot(over) && lane == 0) atomicOr(P.flags, NUMARCK_FLAG_INC_OVERRUN);
+    wave_lds_sync();
   }
+  if (__ballot(bad) && lane == 0) atomicOr(P.flags, NUMARCK_FLAG_BAD_INDEX);
+  if (__ballot(over) && lane == 0) atomicOr(P.flags, NUMARCK_FLAG_INC_OVERRUN);
 }
 
-#define NK_DLAUNCH(kind, kern, grid, block, ...)                                 \
+#define NK_DLAUNCH(kind, kern, grid, block, lds, ...)                            \
   do {                                                                           \
     timing_begin(kind, s);                                                       \
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(block), 0, s, __VA_ARGS__);        \
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(block), lds, s, __VA_ARGS__);      \
     timing_end(kind, s);                                                         \
     hipError_t e_ = hipGetLastError();                                           \
     if (e_ != hipSuccess) return e_;                                             \
   } while (0)
 
-template <typename T>
-static hipError_t launch_decompress_t(const DParams& P, hipStream_t s) {
+template <typename T, bool VEC>
+static hipError_t launch_decode_chain(DParams P, size_t cent_lds, hipStream_t s) {
   const Geometry g = geometry();
-  uint64_t init_blocks = (P.n_tiles + 255) / 256;
-  if (init_blocks < 1) init_blocks = 1;
-  if (init_blocks > (uint64_t)g.cus) init_blocks = g.cus;
+  // as many units as can be resident at once (4 per workgroup)
+  int occ = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_decode<T, VEC>, UNIT_TPB,
+                                                   cent_lds) != hipSuccess || occ < 1)
+    occ = 1;
+  P.n_units = range_units(P.n_tiles, g.cus * occ * 4);
+  P.tiles_per_unit = (P.n_tiles + P.n_units - 1) / P.n_units;
   uint64_t pre_blocks = P.len ? ((P.start % P.epb) + 255) / 256 : 1;
   if (pre_blocks < 1) pre_blocks = 1;
   if (pre_blocks > (uint64_t)g.cus * 2) pre_blocks = (uint64_t)g.cus * 2;
-  uint64_t dec_blocks = P.n_tiles;
-  if (dec_blocks > (uint64_t)g.cus * 4) dec_blocks = (uint64_t)g.cus * 4;
-  if (dec_blocks < 1) dec_blocks = 1;
-  NK_DLAUNCH(KK_DINIT, k_dinit, init_blocks, 256, P);
-  NK_DLAUNCH(KK_DPREFIX, k_dprefix, pre_blocks, 256, P);
-  NK_DLAUNCH(KK_DECODE, k_decode<T>, dec_blocks, DEC_TPB, P);
+  NK_DLAUNCH(KK_DINIT, k_dinit, 1, 64, 0, P);
+  NK_DLAUNCH(KK_DPREFIX, k_dprefix, pre_blocks, 256, 0, P);
+  NK_DLAUNCH(KK_DCOUNT, k_dcount, P.n_units / 4, UNIT_TPB, 0, P);
+  NK_DLAUNCH(KK_DSCAN, k_dscan, 1, USCAN_TPB, 0, P);
+  NK_DLAUNCH(KK_DECODE, (k_decode<T, VEC>), P.n_units / 4, UNIT_TPB, cent_lds, P);
   return hipSuccess;
+}
+
+template <typename T>
+static hipError_t launch_decompress_t(const DParams& P, hipStream_t s) {
+  const size_t cent = ((size_t)1 << P.B) * sizeof(T);
+  const size_t cent_lds = cent <= (size_t)DEC_CENT_BYTES ? cent : 0;
+  const bool vec = (P.start % Traits<T>::V) == 0 && ((uintptr_t)P.prev & 15u) == 0 &&
+                   ((uintptr_t)P.out & 15u) == 0;
+  return vec ? launch_decode_chain<T, true>(P, cent_lds, s)
+             : launch_decode_chain<T, false>(P, cent_lds, s);
 }
 
 hipError_t launch_decompress(const DParams& P, hipStream_t s) {

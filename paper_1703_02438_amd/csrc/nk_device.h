@@ -1,6 +1,6 @@
 // nk_device.h -- device helpers shared by the NUMARCK kernels: element
 // traits, the change ratio and its validity, bin ids and centres, wave
-// reductions and the decoupled look-back used for order-preserving scans.
+// reductions.
 #pragma once
 
 #include "nk_internal.h"
@@ -52,6 +52,31 @@ __device__ __forceinline__ long long bin_of(double d, double lo, double twoE) {
   return (long long)floor((d - lo) / twoE);
 }
 
+// floor(x / twoE) for x >= 0, as a double, bit-identical to flooring the
+// correctly rounded quotient.  The fast path multiplies by inv = fl(1/twoE):
+// t' = fl(x * inv) is within 2^-51 * t' of t = fl(x / twoE) (three roundings
+// of at most 2^-53 each), so floor(t') == floor(t) unless an integer lies
+// within that distance of t'.  Those cases (and non-finite t') take the
+// exact division.
+__device__ __forceinline__ double bin_floor(double x, double twoE, double inv, bool fast) {
+  if (fast) {
+    const double t = x * inv;
+    const double f = floor(t);
+    const double frac = t - f;  // exact (Sterbenz) for t >= 0
+    const double thr = t * 0x1p-49;
+    if ((frac > thr) && ((1.0 - frac) > thr)) return f;
+  }
+  return floor(x / twoE);
+}
+
+// Bin centre lo + (2m + 1) E from a bin id held as a double (an integer below
+// 2^51, so 2m + 1 is exact), rounded to the snapshot type and widened back.
+template <typename T>
+__device__ __forceinline__ double centre_of_d(double m, double lo, double E) {
+  const double c = lo + (2.0 * m + 1.0) * E;
+  return (double)(T)c;
+}
+
 // Bin centre lo + (2m + 1) E, rounded to the snapshot type and widened back.
 template <typename T>
 __device__ __forceinline__ double centre_of(long long m, double lo, double E) {
@@ -60,6 +85,16 @@ __device__ __forceinline__ double centre_of(long long m, double lo, double E) {
 }
 
 __device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
+
+// Order this wave's LDS accesses before and after: LDS instructions of one
+// wave execute in order, so a compiler barrier plus waiting for the wave's
+// own LDS operations is enough for lanes to read what other lanes wrote.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0)
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
 __device__ __forceinline__ unsigned long long lanemask_lt() {
   const int l = lane_id();
@@ -88,51 +123,57 @@ __device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v)
   return v;
 }
 
-__device__ __forceinline__ unsigned long long ld_status(unsigned long long* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ void st_status(unsigned long long* p, unsigned long long v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
+constexpr int USCAN_TPB = 1024;
 
-// Decoupled look-back over tiles taken in ticket order.  Called by all 64
-// lanes of one wave; `agg` is the tile's own total.  Publishes the tile's
-// aggregate, walks back over the predecessors 64 at a time until it meets an
-// inclusive prefix, publishes its own inclusive prefix and returns the
-// exclusive one.  Every predecessor holds an earlier ticket, so its block is
-// resident and publishes its aggregate without waiting: every wait ends.
-__device__ __forceinline__ unsigned long long lookback(unsigned long long* status,
-                                                       uint64_t tile,
-                                                       unsigned long long agg) {
-  const int lane = lane_id();
-  if (tile == 0) {
-    if (lane == 0) st_status(&status[0], LB_INC | agg);
-    return 0;
+// Exclusive scan of cnt[0..n) in place (n <= MAX_UNITS) by one workgroup of
+// USCAN_TPB threads; every thread returns the total.
+__device__ __forceinline__ unsigned long long unit_scan(uint32_t* cnt, uint32_t n) {
+  constexpr int PER = MAX_UNITS / USCAN_TPB;
+  constexpr int Q = USCAN_TPB / 64;
+  __shared__ unsigned long long s_part[USCAN_TPB];
+  __shared__ unsigned long long s_total;
+  const int tid = threadIdx.x;
+  uint32_t v[PER];
+  unsigned long long mine = 0;
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const uint32_t k = (uint32_t)tid * PER + i;
+    v[i] = k < n ? cnt[k] : 0u;
+    mine += v[i];
   }
-  if (lane == 0) st_status(&status[tile], LB_AGG | agg);
-  unsigned long long excl = 0;
-  long long j = (long long)tile - 1 - lane;
-  while (true) {
-    unsigned long long s = LB_INC;  // before tile 0: inclusive prefix 0
-    if (j >= 0) {
-      s = ld_status(&status[j]);
-      while ((s >> 62) == 0) {
-        __builtin_amdgcn_s_sleep(1);
-        s = ld_status(&status[j]);
-      }
+  s_part[tid] = mine;
+  __syncthreads();
+  if (tid < 64) {
+    unsigned long long loc[Q];
+    unsigned long long run = 0;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      loc[i] = s_part[tid * Q + i];
+      run += loc[i];
     }
-    const unsigned long long incl = __ballot((s >> 62) == 2);
-    unsigned long long v = s & LB_VAL;
-    if (incl) {
-      const int first = __ffsll((long long)incl) - 1;  // nearest inclusive predecessor
-      excl += wave_sum_u64(lane <= first ? v : 0ull);
-      break;
+    unsigned long long inc = run;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const unsigned long long t = __shfl_up(inc, o, 64);
+      if (tid >= o) inc += t;
     }
-    excl += wave_sum_u64(v);
-    j -= 64;
+    unsigned long long ex = inc - run;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      s_part[tid * Q + i] = ex;
+      ex += loc[i];
+    }
+    if (tid == 63) s_total = inc;
   }
-  if (lane == 0) st_status(&status[tile], LB_INC | (excl + agg));
-  return excl;
+  __syncthreads();
+  unsigned long long run = s_part[tid];
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const uint32_t k = (uint32_t)tid * PER + i;
+    if (k < n) cnt[k] = (uint32_t)run;
+    run += v[i];
+  }
+  return s_total;
 }
 
 }  // namespace nk

@@ -17,16 +17,14 @@ constexpr uint16_t NOSEL = 0xFFFF;       // window LUT entry: bin not selected
 constexpr uint32_t HEMPTY = 0xFFFFFFFFu;  // empty hash slot
 constexpr int MAX_SEL = 65535;            // k for B = 16
 
-// Tile of the encoder / decoder (elements per tile, threads per block).
-constexpr int ENC_TPB = 256;
-constexpr int ENC_TILE = 4096;
-constexpr int DEC_TPB = 256;
-constexpr int DEC_TILE = 4096;
-
-// Look-back status words: 2 flag bits over a 62-bit value.
-constexpr uint64_t LB_AGG = 1ull << 62;
-constexpr uint64_t LB_INC = 2ull << 62;
-constexpr uint64_t LB_VAL = (1ull << 62) - 1;
+// The encoder and decoder are range-partitioned by wave: each wave ("unit")
+// owns a contiguous run of wave tiles and keeps a running count of
+// incompressible points, so no wave ever waits for another.  A wave tile is
+// 4 rounds of one 16-byte vector per lane: 512 float64 or 1024 float32.
+constexpr int UNIT_TPB = 256;      // 4 units per workgroup
+constexpr int UNIT_ROUNDS = 4;
+constexpr int MAX_UNITS = 8192;
+constexpr int LUT_GROUPS = WIN / 64;
 
 // ------------------------------------------------ device control block
 // Lives at the start of the compression workspace.  Fields above `lo` are
@@ -38,8 +36,8 @@ struct Ctl {
   unsigned long long tail_count;  // points outside the window (may exceed capacity)
   unsigned int tile_ticket;       // encoder tile tickets
   unsigned int flags;             // NUMARCK_FLAG_*
-  unsigned int sel_tail_count;    // selected tail bins appended by k_select
-  unsigned int pad0;
+  unsigned int tail_bins;         // distinct tail bins (k_hinsert)
+  unsigned int tail_max;          // largest tail-bin count (k_hinsert)
   // derived by k_derive
   double lo, hi;
   long long M;
@@ -58,23 +56,21 @@ struct Ctl {
   unsigned int nsel_window;
   unsigned int nsel_tail;
   unsigned int nsel_tail_below;
-  unsigned int pad1;
+  unsigned int n_inc;             // incompressible points (k_gather)
 };
 
 // Control block of a decompression call.
 struct DCtl {
   unsigned long long base;  // escapes before `start`
-  unsigned int ticket;
-  unsigned int pad;
 };
 
 // Workspace layout of one compression (byte offsets from the workspace base).
 struct Layout {
-  size_t ctl, gwin, lut, sel_tail, sorted_tail, status, tail, hslot, hcnt, total;
+  size_t ctl, gwin, lutbits, lutbase, sel_tail, sorted_tail, unit_cnt, scratch, tail, hslot,
+      hcnt, total;
   uint64_t tail_cap, hcap;
-  uint64_t n_tiles;
 };
-Layout compress_layout(uint64_t n, uint64_t tail_cap);
+Layout compress_layout(uint64_t n, uint64_t elem_bytes, uint64_t tail_cap);
 
 // Everything a compression kernel needs (passed by value).
 struct CParams {
@@ -82,6 +78,8 @@ struct CParams {
   const void* curr;
   uint64_t n;
   double E, twoE, cap;
+  double inv2E;      // binary64 1/(2E), used with an exactness check
+  int fastbin;       // inv2E is finite and normal
   uint32_t B;
   uint32_t k;        // 2^B - 1 (also the escape code)
   uint64_t epb;      // elements per index-table block
@@ -90,7 +88,8 @@ struct CParams {
   uint64_t packed_words;
   Ctl* ctl;
   uint32_t* gwin;
-  uint16_t* lut;
+  unsigned long long* lutbits;  // selected window bins, one bit per bin
+  uint32_t* lutbase;            // index of the first selected bin of each 64-bin group
   int64_t* tail;
   uint64_t tail_cap;
   uint32_t* hslot;
@@ -98,7 +97,10 @@ struct CParams {
   uint64_t hcap;
   int64_t* sel_tail;
   int64_t* sorted_tail;
-  unsigned long long* status;
+  uint32_t* unit_cnt;  // incompressible points per encoder unit, then their offsets
+  void* scratch;       // incompressible values staged per unit range
+  uint32_t n_units;
+  uint64_t tiles_per_unit;
   uint32_t* packed;
   void* centers;
   void* incomp;
@@ -122,8 +124,11 @@ struct DParams {
   uint32_t B, k_used;
   int dtype;
   DCtl* dctl;
-  unsigned long long* status;
+  uint32_t* unit_cnt;  // escapes per decoder unit range, then their offsets
+  uint32_t n_units;
+  uint64_t tiles_per_unit;
   uint64_t n_tiles;
+  uint64_t tile_elems;  // elements of a wave tile
 };
 
 // Launch geometry of the streaming kernels for the current device.
@@ -132,10 +137,24 @@ struct Geometry {
 };
 Geometry geometry();
 
+// Elements of one wave tile for an element size (16-byte vectors).
+inline uint64_t wave_tile(uint64_t elem_bytes) { return UNIT_ROUNDS * 64 * (16 / elem_bytes); }
+// Units (waves) of a range-partitioned pass over `tiles` wave tiles, at most
+// `resident` (the waves that fit on the device at once); a multiple of the 4
+// units of a workgroup.
+inline uint32_t range_units(uint64_t tiles, int resident) {
+  uint64_t u = (uint64_t)resident;
+  if (u > (uint64_t)MAX_UNITS) u = MAX_UNITS;
+  if (u > tiles) u = tiles;
+  if (u < 1) u = 1;
+  return (uint32_t)((u + 3) / 4 * 4);
+}
+
 // Kernel kinds for the optional event timing.
 enum KernelKind {
   KK_INIT = 0, KK_RANGE, KK_DERIVE, KK_HIST, KK_HCLEAR, KK_HINSERT, KK_SELECT,
-  KK_TAILRANK, KK_ENCODE, KK_FINAL, KK_DINIT, KK_DPREFIX, KK_DECODE, KK_EXPORT, KK_COUNT
+  KK_TAILRANK, KK_ENCODE, KK_USCAN, KK_GATHER, KK_FINAL, KK_DINIT, KK_DPREFIX, KK_DCOUNT,
+  KK_DSCAN, KK_DECODE, KK_EXPORT, KK_COUNT
 };
 void timing_begin(KernelKind k, hipStream_t s);
 void timing_end(KernelKind k, hipStream_t s);

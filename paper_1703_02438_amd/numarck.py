@@ -73,7 +73,7 @@ numarck_centers_bytes = _bind("numarck_centers_bytes", _sz, [_u32, _i])
 numarck_elems_per_block = _bind("numarck_elems_per_block", _u64, [_u32, _u64])
 numarck_block_count = _bind("numarck_block_count", _u64, [_u64, _u32, _u64])
 numarck_workspace_bytes = _bind("numarck_workspace_bytes", _sz, [_u64, _i, _u32])
-numarck_workspace_bytes_tail = _bind("numarck_workspace_bytes_tail", _sz, [_u64, _u64])
+numarck_workspace_bytes_tail = _bind("numarck_workspace_bytes_tail", _sz, [_u64, _i, _u64])
 numarck_decompress_workspace_bytes = _bind("numarck_decompress_workspace_bytes", _sz, [_u64])
 numarck_compress = _bind("numarck_compress", _i,
                          [_vp, _vp, _u64, _i, _d, _u32, _u64, ctypes.POINTER(NumarckOut), _vp,
@@ -85,7 +85,7 @@ numarck_decompress_range = _bind("numarck_decompress_range", _i,
                                  [ctypes.POINTER(NumarckHeader), _vp, _vp, _vp, _vp, _vp, _u64,
                                   _u64, _vp, _vp, _vp, _sz, _vp])
 numarck_histogram_export = _bind("numarck_histogram_export", _i,
-                                 [_vp, _sz, _u64, _vp, _vp, _u64, _vp, _vp])
+                                 [_vp, _sz, _u64, _i, _vp, _vp, _u64, _vp, _vp])
 numarck_status_str = _bind("numarck_status_str", ctypes.c_char_p, [_i])
 numarck_last_error = _bind("numarck_last_error", ctypes.c_char_p, [])
 numarck_timing_enable = _bind("numarck_timing_enable", None, [_i])
@@ -237,8 +237,8 @@ def histogram(c: Compressed, capacity: int | None = None, stream=None):
     ids = torch.empty(max(capacity, 1), dtype=torch.int64, device=c.hdr.device)
     counts = torch.empty(max(capacity, 1), dtype=torch.int32, device=c.hdr.device)
     cnt = torch.zeros(1, dtype=torch.int64, device=c.hdr.device)
-    st = numarck_histogram_export(_ptr(c.ws), c.ws.numel(), c.n, _ptr(ids), _ptr(counts),
-                                  capacity, _ptr(cnt), _stream(stream))
+    st = numarck_histogram_export(_ptr(c.ws), c.ws.numel(), c.n, dtype_code(c.dtype), _ptr(ids),
+                                  _ptr(counts), capacity, _ptr(cnt), _stream(stream))
     _check(st, "numarck_histogram_export")
     k = int(cnt.item())
     return ids[:min(k, capacity)], counts[:min(k, capacity)], k

@@ -59,9 +59,9 @@ def test_sizes(nk):
     assert nk.numarck_block_count(3758400, 13, 0) == 6
     assert nk.numarck_block_count(0, 13, 0) == 0
     w_full = nk.numarck_workspace_bytes(1 << 20, nk.F64, 8)
-    w_none = nk.numarck_workspace_bytes_tail(1 << 20, 0)
+    w_none = nk.numarck_workspace_bytes_tail(1 << 20, nk.F64, 0)
     assert w_full > w_none > 0
-    assert nk.numarck_workspace_bytes_tail(1 << 20, 1 << 20) == w_full
+    assert nk.numarck_workspace_bytes_tail(1 << 20, nk.F64, 1 << 20) == w_full
     assert nk.numarck_decompress_workspace_bytes(0) > 0
 
 

@@ -26,7 +26,7 @@ def _ranges(n, rng, k=6, epb=None):
     for _ in range(k):
         s = int(rng.integers(0, n + 1))
         out.append((s, int(rng.integers(0, n - s + 1))))
-    if epb and n > epb + 10:
+    if epb and epb >= 5 and n > epb + 10:
         out.append((epb - 5, 10))  # crosses a block boundary
     return out
 
@@ -146,12 +146,12 @@ def test_tail_capacity(nk):
     big = gpu_compress(nk, prev, curr, 1e-5, 8)[0]
     T = big.header().tail_count
     assert T > 1000
-    ws = torch.empty(nk.numarck_workspace_bytes_tail(prev.size, T), dtype=torch.uint8,
+    ws = torch.empty(nk.numarck_workspace_bytes_tail(prev.size, nk.F64, T), dtype=torch.uint8,
                      device="cuda")
     c, _, _ = gpu_compress(nk, prev, curr, 1e-5, 8, ws=ws)
     assert c.header().flags == 0
     assert np.array_equal(to_np(c.packed), to_np(big.packed))
-    ws = torch.empty(nk.numarck_workspace_bytes_tail(prev.size, T // 2), dtype=torch.uint8,
+    ws = torch.empty(nk.numarck_workspace_bytes_tail(prev.size, nk.F64, T // 2), dtype=torch.uint8,
                      device="cuda")
     c, _, _ = gpu_compress(nk, prev, curr, 1e-5, 8, ws=ws)
     assert c.header().flags & nk.FLAG_TAIL_OVERFLOW
@@ -182,7 +182,10 @@ def test_deterministic(nk):
     prev, curr = tail_case(120_000, 8)
     a = gpu_compress(nk, prev, curr, 1e-5, 12)[0]
     b = gpu_compress(nk, prev, curr, 1e-5, 12)[0]
-    for f in ("packed", "centers", "incomp", "block_inc_off", "recon", "bin_ids", "hdr"):
+    ninc = a.header().n_inc
+    assert ninc == b.header().n_inc
+    assert torch.equal(a.incomp[:ninc].view(torch.uint8), b.incomp[:ninc].view(torch.uint8))
+    for f in ("packed", "centers", "block_inc_off", "recon", "bin_ids", "hdr"):
         assert torch.equal(getattr(a, f).view(torch.uint8), getattr(b, f).view(torch.uint8)), f
 
 
