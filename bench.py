@@ -98,7 +98,7 @@ def summarize_pmc(fetch_dir: str, write_dir: str, kernel: str, workload: str, cm
     for d, counter in ((fetch_dir, "FETCH_SIZE"), (write_dir, "WRITE_SIZE")):
         v = per_kernel(d, counter)
         copy = [x for k, xs in v.items() if "copy" in k.lower() or "elementwise" in k.lower()
-                for x in xs if x * 1024 > 0.5 * COPY_CALIB_BYTES]
+                for x in xs if x * 1024 > 0.25 * COPY_CALIB_BYTES]
         mine = [x for k, xs in v.items() if f"k_{kernel}" in k for x in xs]
         if not copy or not mine:
             raise SystemExit(f"no {counter} samples for the copy or k_{kernel}")
