@@ -39,8 +39,7 @@ Layout compress_layout(uint64_t n, uint64_t elem_bytes, uint64_t tail_cap) {
   };
   L.ctl = take(sizeof(Ctl));
   L.gwin = take((size_t)WIN * 4);
-  L.lutbits = take((size_t)LUT_GROUPS * 8);
-  L.lutbase = take((size_t)LUT_GROUPS * 4);
+  L.lut = take((size_t)WIN * 2);
   L.sel_tail = take((size_t)(MAX_SEL + 1) * 8);
   L.sorted_tail = take((size_t)(MAX_SEL + 1) * 8);
   L.unit_cnt = take((size_t)MAX_UNITS * 4);
@@ -96,7 +95,7 @@ Geometry geometry() {
 // ------------------------------------------------------------- event timing
 static const char* kKindNames[KK_COUNT] = {
     "init", "range", "derive", "hist", "hash_clear", "hash_insert", "select", "tail_rank",
-    "encode", "unit_scan", "gather", "final", "dec_init", "dec_prefix", "dec_count",
+    "encode", "unit_scan", "gather", "dec_init", "dec_prefix", "dec_count",
     "dec_scan", "decode", "export"};
 static bool g_timing = false;
 struct EvPair {
@@ -211,13 +210,13 @@ numarck_status numarck_compress(const void* prev, const void* curr, uint64_t n,
   P.block_bytes = block_bytes;
   P.epb = 8 * block_bytes / B;
   P.n_blocks = (n + P.epb - 1) / P.epb;
-  const uint64_t tile = wave_tile(eb);
+  const uint64_t tile = enc_wave_tile(eb);
   P.n_tiles = (n + tile - 1) / tile;
   P.packed_words = (n * B + 31) / 32;
   P.ctl = reinterpret_cast<Ctl*>(base + L.ctl);
   P.gwin = reinterpret_cast<uint32_t*>(base + L.gwin);
-  P.lutbits = reinterpret_cast<unsigned long long*>(base + L.lutbits);
-  P.lutbase = reinterpret_cast<uint32_t*>(base + L.lutbase);
+  P.lut = reinterpret_cast<uint16_t*>(base + L.lut);
+  P.mulB = B > 1 ? (uint32_t)((((uint64_t)1 << 32) + B - 1) / B) : 0u;  // unused for B = 1
   P.unit_cnt = reinterpret_cast<uint32_t*>(base + L.unit_cnt);
   P.scratch = base + L.scratch;
   P.tail = reinterpret_cast<int64_t*>(base + L.tail);
@@ -287,7 +286,7 @@ static numarck_status decompress_impl(const numarck_header* hdr, const void* pre
   P.dtype = (int)hdr->dtype;
   P.dctl = reinterpret_cast<DCtl*>(base);
   P.unit_cnt = reinterpret_cast<uint32_t*>(base + cnt_off);
-  P.tile_elems = wave_tile(hdr->dtype == NUMARCK_F32 ? 4 : 8);
+  P.tile_elems = dec_wave_tile(hdr->dtype == NUMARCK_F32 ? 4 : 8);
   P.n_tiles = (len + P.tile_elems - 1) / P.tile_elems;
   const hipError_t e = launch_decompress(P, static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(e);

@@ -22,9 +22,10 @@
 //               stage incompressible values per wave range with
 //               range-relative block offsets (Sec. III-C, IV-C)
 //   k_uscan     offsets of the wave ranges
-//   k_gather    move the staged values to their final, element-order offsets
-//               and complete the block offsets
-//   k_final     write the header
+//   k_gather    move the staged values to their final, element-order offsets,
+//               complete the block offsets and write the header
+#include <type_traits>
+
 #include "nk_device.h"
 
 namespace nk {
@@ -180,7 +181,7 @@ __global__ void k_derive(CParams P) {
 // =====================================================================
 // k_hist: pass 2, fine histogram
 // =====================================================================
-constexpr int HIST_TPB = 512;
+constexpr int HIST_TPB = NK_HIST_TPB;
 constexpr int HIST_UNROLL = 2;
 
 // Count one element per lane: window bins with LDS atomics, other valid
@@ -189,7 +190,11 @@ __device__ __forceinline__ void hist_count(uint32_t* lds, bool valid, double m, 
                                            double wlen_d, const CParams& P) {
   const double w = m - wbase_d;  // exact: both are integers below 2^51
   const bool inwin = valid && w >= 0.0 && w < wlen_d;
+#if NK_HIST_HYBRID
+  lds_count(lds, inwin, inwin ? (unsigned)(int)w : 0u);
+#else
   if (inwin) atomicAdd(&lds[(int)w], 1u);
+#endif
   const bool tail = valid && !inwin;
   const unsigned long long tm = __ballot(tail);
   if (tm) {
@@ -224,6 +229,9 @@ __global__ void __launch_bounds__(HIST_TPB) k_hist(CParams P) {
   const T* __restrict__ prev = static_cast<const T*>(P.prev);
   const T* __restrict__ curr = static_cast<const T*>(P.curr);
   const uint64_t nvec = P.n / V;
+  // With NK_HIST_REVERSE the sweep runs from the end of the arrays to the
+  // start: the range pass ended on the high addresses, which may still sit in
+  // the memory-side cache.
   for (uint64_t vb = (uint64_t)blockIdx.x * (HIST_TPB * HIST_UNROLL) + tid; vb < nvec;
        vb += (uint64_t)gridDim.x * (HIST_TPB * HIST_UNROLL)) {
     T pv[HIST_UNROLL][V], qv[HIST_UNROLL][V];
@@ -231,8 +239,9 @@ __global__ void __launch_bounds__(HIST_TPB) k_hist(CParams P) {
     for (int u = 0; u < HIST_UNROLL; ++u) {
       const uint64_t vi = vb + (uint64_t)u * HIST_TPB;
       if (vi < nvec) {
-        load_vec(prev, vi, pv[u]);
-        load_vec(curr, vi, qv[u]);
+        const uint64_t vv = NK_HIST_REVERSE ? nvec - 1 - vi : vi;
+        load_vec(prev, vv, pv[u]);
+        load_vec(curr, vv, qv[u]);
       }
     }
 #pragma unroll
@@ -419,15 +428,15 @@ __device__ void sel_scan(SelShared& S, unsigned long long target, bool descendin
   __syncthreads();
 }
 
-// Visit every nonzero candidate (id, count): the window from LDS, then, if
-// `tail`, the occupied hash slots.
+// Visit the candidates (id, count): the window from LDS, then, if `tail`,
+// the hash slots.  Every lane of the workgroup makes the same number of
+// calls (wave-level counting inside f); count 0 means "no candidate".
 template <typename F>
 __device__ __forceinline__ void sel_visit(const CParams& P, const SelShared& S, long long wbase,
                                           unsigned win_len, bool tail, unsigned long long H, F f) {
-  for (unsigned w = threadIdx.x; w < win_len; w += SEL_TPB) {
-    const uint32_t cn = S.win[w];
-    if (cn) f(wbase + (long long)w, cn);
-  }
+  (void)win_len;
+  for (unsigned w = threadIdx.x; w < (unsigned)WIN; w += SEL_TPB)
+    f(wbase + (long long)w, S.win[w]);  // bins past win_len hold 0
   if (tail) {
     for (unsigned long long s0 = 0; s0 < H; s0 += (unsigned long long)SEL_TPB * 4) {
       uint32_t slot[4], cn[4];
@@ -438,8 +447,10 @@ __device__ __forceinline__ void sel_visit(const CParams& P, const SelShared& S, 
         cn[u] = si < H ? P.hcnt[si] : 0u;
       }
 #pragma unroll
-      for (int u = 0; u < 4; ++u)
-        if (slot[u] != HEMPTY && cn[u]) f((long long)P.tail[slot[u]], cn[u]);
+      for (int u = 0; u < 4; ++u) {
+        const bool ok = slot[u] != HEMPTY && cn[u] != 0;
+        f(ok ? (long long)P.tail[slot[u]] : 0ll, ok ? cn[u] : 0u);
+      }
     }
   }
 }
@@ -458,7 +469,8 @@ __device__ unsigned sel_kth_count(SelShared& S, unsigned long long mx, unsigned 
     const unsigned hmask =
         (shift + SEL_DIGIT >= 32) ? 0u : (unsigned)(0xFFFFFFFFull << (shift + SEL_DIGIT));
     visit([&](long long, uint32_t cn) {
-      if ((cn & hmask) == (prefix & hmask)) atomicAdd(&S.hist[(cn >> shift) & (SEL_BUCKETS - 1)], 1u);
+      const bool on = cn != 0 && (cn & hmask) == (prefix & hmask);
+      lds_count(S.hist, on, (cn >> shift) & (SEL_BUCKETS - 1));
     });
     __syncthreads();
     sel_scan(S, target, true);
@@ -485,8 +497,8 @@ __device__ long long sel_rth_tie(SelShared& S, unsigned tau, unsigned long long 
         (shift + SEL_DIGIT >= 64) ? 0ull : (~0ull << (shift + SEL_DIGIT));
     visit([&](long long id, uint32_t cn) {
       const unsigned long long rel = (unsigned long long)id - tmin;
-      if (cn == tau && (rel & hmask) == (pre & hmask))
-        atomicAdd(&S.hist[(rel >> shift) & (SEL_BUCKETS - 1)], 1u);
+      const bool on = cn != 0 && cn == tau && (rel & hmask) == (pre & hmask);
+      lds_count(S.hist, on, (unsigned)((rel >> shift) & (SEL_BUCKETS - 1)));
     });
     __syncthreads();
     sel_scan(S, tgt, false);
@@ -504,6 +516,7 @@ __device__ void sel_threshold(SelShared& S, unsigned long long mx, unsigned long
   const unsigned tau = sel_kth_count(S, mx, k, visit);
   unsigned long long gt = 0, ties = 0, tmin = ~0ull, tmax = 0;
   visit([&](long long id, uint32_t cn) {
+    if (cn == 0) return;
     if (cn > tau) gt += 1;
     if (cn == tau) {
       ties += 1;
@@ -637,28 +650,19 @@ __global__ void __launch_bounds__(SEL_TPB) k_select(CParams P) {
   }
   __syncthreads();
   unsigned rank = (unsigned)sel_below + S.scan[tid];
-  unsigned mask16 = 0;
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
     const unsigned w = tid * PER + q;
     const uint32_t cn = S.win[w];
     const long long id = wbase + (long long)w;
+    uint16_t l = (uint16_t)k;  // escape code: not selected
     if (cn != 0 && (cn > tau || (cn == tau && id <= cut))) {
-      mask16 |= 1u << q;
+      l = (uint16_t)rank;
       centers[rank] = (T)centre_of<T>(id, lo, P.E);
       if (P.bin_ids) P.bin_ids[rank] = id;
       rank += 1;
     }
-  }
-  // selection bitmap of the window, 64 bins per word, and the index of the
-  // first selected bin of each word (4 threads own one word's 64 bins)
-  static_assert(PER == 16, "four threads per 64-bin group");
-  const unsigned long long m0 = (unsigned long long)mask16 << (16 * (tid & 3));
-  const unsigned long long m1 = m0 | __shfl_xor(m0, 1, 64);
-  const unsigned long long m2 = m1 | __shfl_xor(m1, 2, 64);
-  if ((tid & 3) == 0) {
-    P.lutbits[tid >> 2] = m2;
-    P.lutbase[tid >> 2] = (unsigned)sel_below + S.scan[tid];
+    P.lut[w] = l;
   }
   if (tid == 0) {
     c->n_nonzero = nz;
@@ -715,15 +719,24 @@ __global__ void __launch_bounds__(TR_TPB) k_tailrank(CParams P) {
 // range gets its range-relative count, and the count of the range goes to
 // unit_cnt[u].  k_uscan and k_gather then place every range.  No wave waits
 // for another and the loop has no workgroup barrier.
-template <typename T>
+//
+// LT: element type of the window LUT in LDS (uint8_t when B <= 8, else
+// uint16_t); a LUT entry is the bin's index or the escape code.
+// PACK: 8 or 16 when B is 8 or 16 -- the LDS index array is then already the
+// packed stream -- or 0 for any B.
+constexpr int ENC_CTAB = 2048;  // LDS centre table when 2^B <= this
+
+template <typename T, typename LT, int PACK>
 __global__ void __launch_bounds__(UNIT_TPB) k_encode(CParams P) {
   constexpr int V = Traits<T>::V;
-  constexpr int R = UNIT_ROUNDS;
+  constexpr int R = ENC_ROUNDS;
   constexpr int WT = R * 64 * V;  // elements of a wave tile
   constexpr int NWAVE = UNIT_TPB / 64;
-  __shared__ unsigned long long s_bits[LUT_GROUPS];
-  __shared__ uint32_t s_base[LUT_GROUPS];
-  __shared__ uint16_t s_idx[NWAVE][WT];
+  using IT = typename std::conditional<PACK == 8, uint8_t, uint16_t>::type;
+  constexpr int NCTAB = sizeof(LT) == 1 ? 256 : ENC_CTAB;
+  __shared__ LT s_lut[WIN];
+  __shared__ double s_ctab[NCTAB];
+  __shared__ IT s_idx[NWAVE][WT];
 
   const Ctl* c = P.ctl;
   const int tid = threadIdx.x;
@@ -738,10 +751,13 @@ __global__ void __launch_bounds__(UNIT_TPB) k_encode(CParams P) {
   const unsigned nsel_tail = empty ? 0u : c->nsel_tail;
   const unsigned nsel_win = empty ? 0u : c->nsel_window;
   const uint32_t esc = P.k;
+  const uint32_t B = P.B;
   const bool fast = P.fastbin != 0;
-  for (int i = tid; i < LUT_GROUPS; i += UNIT_TPB) {
-    s_bits[i] = P.lutbits[i];
-    s_base[i] = P.lutbase[i];
+  const bool use_ctab = ((uint32_t)1 << B) <= (uint32_t)NCTAB;
+  for (int i = tid; i < WIN; i += UNIT_TPB) s_lut[i] = (LT)P.lut[i];
+  if (use_ctab) {
+    const T* cen = static_cast<const T*>(P.centers);
+    for (int i = tid; i < (1 << B); i += UNIT_TPB) s_ctab[i] = (double)cen[i];
   }
   __syncthreads();
 
@@ -749,63 +765,66 @@ __global__ void __launch_bounds__(UNIT_TPB) k_encode(CParams P) {
   const T* __restrict__ curr = static_cast<const T*>(P.curr);
   T* __restrict__ scratch = static_cast<T*>(P.scratch);
   T* __restrict__ recon = static_cast<T*>(P.recon);
-  uint16_t* idx = s_idx[wave];
+  IT* idx = s_idx[wave];
   const uint64_t nvec = P.n / V;
-  const uint32_t tile_words = (uint32_t)(WT * P.B / 32);
+  const uint32_t tile_words = (uint32_t)(WT * B / 32);
   const uint32_t unit = blockIdx.x * NWAVE + wave;
   const uint64_t tb = (uint64_t)unit * P.tiles_per_unit;
   uint64_t te = tb + P.tiles_per_unit;
   te = te < P.n_tiles ? te : P.n_tiles;
   const uint64_t e_base = tb * WT;
-  const bool single_boundary = P.epb >= (uint64_t)WT;
-  const unsigned long long lt = lanemask_lt();
   unsigned run = 0;  // incompressible points so far in this range
 
-  for (uint64_t tile = tb; tile < te; ++tile) {
-    const uint64_t t0 = tile * WT;
-    T pv[R][V], qv[R][V];
+  auto load_tile = [&](uint64_t t0, T (&pa)[R][V], T (&qa)[R][V]) {
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const uint64_t vi = t0 / V + (uint64_t)r * 64 + lane;
       if (vi < nvec) {
-        load_vec(prev, vi, pv[r]);
-        load_vec(curr, vi, qv[r]);
+        load_vec(prev, vi, pa[r]);
+        load_vec(curr, vi, qa[r]);
       } else {
 #pragma unroll
         for (int v = 0; v < V; ++v) {
           const uint64_t j = vi * V + v;
-          pv[r][v] = j < P.n ? prev[j] : (T)0;
-          qv[r][v] = j < P.n ? curr[j] : (T)0;
+          pa[r][v] = j < P.n ? prev[j] : (T)0;
+          qa[r][v] = j < P.n ? curr[j] : (T)0;
         }
       }
     }
+  };
 
+  // One wave tile: index, verify, stage escapes, pack.  The common path is
+  // branch-free; the exact division and the tail-bin search run only when a
+  // lane of the wave needs them.
+  auto process = [&](uint64_t tile, T (&pv)[R][V], T (&qv)[R][V]) {
+    const uint64_t t0 = tile * WT;
+    const uint64_t left = P.n - t0;
+    const uint32_t lim = left < (uint64_t)WT ? (uint32_t)left : (uint32_t)WT;
     unsigned long long emask[R][V];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const uint32_t e0 = ((uint32_t)r * 64 + lane) * V;  // tile-local element
 #pragma unroll
       for (int v = 0; v < V; ++v) {
-        const uint64_t j = t0 + e0 + v;
-        const bool inr = j < P.n;
+        const bool inr = e0 + v < lim;
         const double p = (double)pv[r][v];
         const double q = (double)qv[r][v];
-        double d = 0.0;
-        const bool valid = inr && ratio_of(p, q, P.cap, d);
-        uint32_t code = esc;
-        T rv = qv[r][v];
-        if (valid) {
-          const double m = bin_floor(d - lo, P.twoE, P.inv2E, fast);
-          const double w = m - wbase_d;  // exact
-          int sel = -1;
-          if (w >= 0.0 && w < wlen_d) {
-            const int wi = (int)w;
-            const unsigned long long bw = s_bits[wi >> 6];
-            const unsigned bit = (unsigned)(wi & 63);
-            if ((bw >> bit) & 1ull)
-              sel = (int)(s_base[wi >> 6] + (unsigned)__popcll(bw & ((1ull << bit) - 1ull)));
-          } else if (nsel_tail) {
-            // binary search among the selected tail bins
+        double d;
+        const bool valid = ratio_of(p, q, P.cap, d) & inr;
+        const double x = d - lo;
+        bool sure = true;
+        double m = fast ? bin_floor_fast(x, P.inv2E, sure) : 0.0;
+        const bool exact = valid & !(fast & sure);
+        if (__ballot(exact)) {
+          if (exact) m = floor(x / P.twoE);
+        }
+        const double w = m - wbase_d;  // exact
+        const bool inwin = valid & (w >= 0.0) & (w < wlen_d);
+        uint32_t code = s_lut[inwin ? (int)w : 0];
+        code = inwin ? code : esc;
+        const bool tail = valid & !inwin & (nsel_tail != 0);
+        if (__ballot(tail)) {
+          if (tail) {  // binary search among the selected tail bins
             const long long mi = (long long)m;
             unsigned a = 0, b = nsel_tail;
             while (a < b) {
@@ -813,20 +832,22 @@ __global__ void __launch_bounds__(UNIT_TPB) k_encode(CParams P) {
               if (P.sorted_tail[mid] < mi) a = mid + 1; else b = mid;
             }
             if (a < nsel_tail && P.sorted_tail[a] == mi)
-              sel = (int)(a + (mi > wbase ? nsel_win : 0u));
-          }
-          if (sel >= 0) {
-            const double cc = centre_of_d<T>(m, lo, P.E);
-            const T r_t = (T)(p * (1.0 + cc));
-            if (fabs((double)r_t - q) <= P.E * fabs(p)) {
-              code = (uint32_t)sel;
-              rv = r_t;
-            }
+              code = a + (mi > wbase ? nsel_win : 0u);
           }
         }
-        idx[e0 + v] = (uint16_t)(inr ? code : 0u);
-        emask[r][v] = __ballot(inr && code == esc);
-        if (recon) pv[r][v] = rv;  // the register now holds the reconstruction
+        const bool sel = code != esc;
+        double cc;
+        if (use_ctab) {
+          cc = s_ctab[sel ? code : 0u];
+        } else {
+          cc = centre_of_d<T>(m, lo, P.E);
+        }
+        const T r_t = (T)(p * (1.0 + cc));
+        const bool ok = sel & (fabs((double)r_t - q) <= P.E * fabs(p));
+        code = ok ? code : esc;
+        idx[e0 + v] = (IT)(inr ? code : 0u);
+        emask[r][v] = __ballot(inr & !ok);
+        if (recon) pv[r][v] = ok ? r_t : qv[r][v];  // the register now holds the reconstruction
       }
     }
     if (recon) {
@@ -834,9 +855,9 @@ __global__ void __launch_bounds__(UNIT_TPB) k_encode(CParams P) {
       for (int r = 0; r < R; ++r) {
         const uint64_t vi = t0 / V + (uint64_t)r * 64 + lane;
         if (vi < nvec) {
-          uint4 x;
-          __builtin_memcpy(&x, pv[r], 16);
-          reinterpret_cast<uint4*>(recon)[vi] = x;
+          uint4 xv;
+          __builtin_memcpy(&xv, pv[r], 16);
+          reinterpret_cast<uint4*>(recon)[vi] = xv;
         } else {
 #pragma unroll
           for (int v = 0; v < V; ++v) {
@@ -850,21 +871,27 @@ __global__ void __launch_bounds__(UNIT_TPB) k_encode(CParams P) {
     // incompressible values and block offsets, in element order (round,
     // lane, vector slot); ranks are range-relative
     const uint64_t first_b = (t0 + P.epb - 1) / P.epb * P.epb;  // first boundary >= t0
+    const bool any_b = first_b < t0 + lim;
+    const bool one_b = P.epb >= (uint64_t)WT;
+    const uint32_t b_local = (uint32_t)(first_b - t0);
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       unsigned below = 0, all = 0;
 #pragma unroll
       for (int v = 0; v < V; ++v) {
-        below += (unsigned)__popcll(emask[r][v] & lt);
-        all += (unsigned)__popcll(emask[r][v]);
+        const unsigned long long mk = emask[r][v];
+        below += __builtin_amdgcn_mbcnt_hi((unsigned)(mk >> 32),
+                                           __builtin_amdgcn_mbcnt_lo((unsigned)mk, 0u));
+        all += (unsigned)__popcll(mk);
       }
       unsigned rank = run + below;
       const uint32_t e0 = ((uint32_t)r * 64 + lane) * V;
 #pragma unroll
       for (int v = 0; v < V; ++v) {
-        const uint64_t j = t0 + e0 + v;
-        if (j < P.n) {
-          const bool at_b = single_boundary ? (j == first_b) : (j % P.epb == 0);
+        if (any_b) {
+          const uint64_t j = t0 + e0 + v;
+          const bool at_b =
+              e0 + v < lim && (one_b ? (e0 + v == b_local) : (j % P.epb == 0));
           if (at_b) P.block_inc_off[j / P.epb] = (long long)rank;
         }
         if ((emask[r][v] >> lane) & 1ull) {
@@ -877,21 +904,41 @@ __global__ void __launch_bounds__(UNIT_TPB) k_encode(CParams P) {
 
     // bit-pack the wave tile: word w holds bits [32w, 32w + 32) of its stream
     wave_lds_sync();
-    const uint64_t word0 = t0 * P.B / 32;
-    for (uint32_t w = lane; w < tile_words; w += 64) {
-      if (word0 + w >= P.packed_words) break;
-      const uint32_t bit0 = w * 32;
-      const uint32_t e_first = bit0 / P.B;
-      const uint32_t e_last = (bit0 + 31) / P.B;
-      uint32_t word = 0;
-      for (uint32_t e = e_first; e <= e_last; ++e) {
-        const uint32_t v = idx[e];
-        const int sh = (int)(e * P.B) - (int)bit0;
-        word |= sh >= 0 ? (v << sh) : (v >> (-sh));
+    const uint64_t word0 = t0 * B / 32;
+    if (PACK != 0) {
+      // 8- or 16-bit indices: the index array is the packed stream
+      const uint32_t* iw = reinterpret_cast<const uint32_t*>(idx);
+      for (uint32_t w = lane; w < tile_words; w += 64)
+        if (word0 + w < P.packed_words) P.packed[word0 + w] = iw[w];
+    } else {
+      for (uint32_t w = lane; w < tile_words; w += 64) {
+        if (word0 + w >= P.packed_words) break;
+        const uint32_t bit0 = w * 32;
+        // floor(bit0 / B) and floor((bit0 + 31) / B); mulB does not exist for B = 1
+        const uint32_t e_first = B == 1 ? bit0 : __umulhi(bit0, P.mulB);
+        const uint32_t e_last = B == 1 ? bit0 + 31 : __umulhi(bit0 + 31, P.mulB);
+        uint32_t word = 0;
+        for (uint32_t e = e_first; e <= e_last; ++e) {
+          const uint32_t v = idx[e];
+          const int sh = (int)(e * B) - (int)bit0;
+          word |= sh >= 0 ? (v << sh) : (v >> (-sh));
+        }
+        P.packed[word0 + w] = word;
       }
-      P.packed[word0 + w] = word;
     }
     wave_lds_sync();
+  };
+
+  // Two register sets: the loads of one tile are in flight while the other
+  // is processed.
+  T pa[R][V], qa[R][V], pb[R][V], qb[R][V];
+  if (tb < te) load_tile(tb * WT, pa, qa);
+  for (uint64_t tile = tb; tile < te; tile += 2) {
+    if (tile + 1 < te) load_tile((tile + 1) * WT, pb, qb);
+    process(tile, pa, qa);
+    if (tile + 1 >= te) break;
+    if (tile + 2 < te) load_tile((tile + 2) * WT, pa, qa);
+    process(tile + 1, pb, qb);
   }
   if (lane == 0 && unit < P.n_units) P.unit_cnt[unit] = run;
 }
@@ -907,10 +954,13 @@ __global__ void __launch_bounds__(USCAN_TPB) k_uscan(CParams P) {
 // =====================================================================
 // k_gather: move each unit's incompressible values to their final offset
 // =====================================================================
+__device__ void write_header(const CParams& P);
+
 template <typename T>
 __global__ void __launch_bounds__(UNIT_TPB) k_gather(CParams P) {
   constexpr int V = Traits<T>::V;
-  constexpr int WT = UNIT_ROUNDS * 64 * V;
+  constexpr int WT = ENC_ROUNDS * 64 * V;
+  if (blockIdx.x == 0 && threadIdx.x == 0) write_header(P);
   const uint32_t unit = blockIdx.x * (UNIT_TPB / 64) + threadIdx.x / 64;
   if (unit >= P.n_units) return;
   const int lane = lane_id();
@@ -928,11 +978,8 @@ __global__ void __launch_bounds__(UNIT_TPB) k_gather(CParams P) {
   for (uint64_t b = b0 + lane; b * P.epb < e1; b += 64) P.block_inc_off[b] += (long long)off;
 }
 
-// =====================================================================
-// k_final: header
-// =====================================================================
-__global__ void k_final(CParams P) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// Header of the call (Fig. 2's attributes plus the counts of this build).
+__device__ void write_header(const CParams& P) {
   const Ctl* c = P.ctl;
   numarck_header* h = P.hdr;
   const uint64_t L = P.dtype == NUMARCK_F32 ? 4 : 8;
@@ -976,12 +1023,15 @@ __global__ void k_final(CParams P) {
 template <typename T>
 static hipError_t launch_compress_t(CParams P, hipStream_t s) {
   const Geometry g = geometry();
+  // encoder specialisation: LUT element type and packing by index width
+  void (*enc)(CParams) = P.B == 8    ? k_encode<T, uint8_t, 8>
+                         : P.B == 16 ? k_encode<T, uint16_t, 16>
+                         : P.B < 8   ? k_encode<T, uint8_t, 0>
+                                     : k_encode<T, uint16_t, 0>;
   {  // as many encoder units as can be resident at once (4 per workgroup)
-    static int occ = 0;
-    if (occ == 0 &&
-        (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_encode<T>, UNIT_TPB, 0) !=
-             hipSuccess ||
-         occ < 1))
+    int occ = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, enc, UNIT_TPB, 0) != hipSuccess ||
+        occ < 1)
       occ = 1;
     P.n_units = range_units(P.n_tiles, g.cus * occ * 4);
     P.tiles_per_unit = (P.n_tiles + P.n_units - 1) / P.n_units;
@@ -1006,10 +1056,9 @@ static hipError_t launch_compress_t(CParams P, hipStream_t s) {
   NK_LAUNCH(KK_HINSERT, k_hinsert, aux_blocks, 256, P);
   NK_LAUNCH(KK_SELECT, k_select<T>, 1, SEL_TPB, P);
   NK_LAUNCH(KK_TAILRANK, k_tailrank<T>, 256, TR_TPB, P);
-  NK_LAUNCH(KK_ENCODE, k_encode<T>, P.n_units / 4, UNIT_TPB, P);
+  NK_LAUNCH(KK_ENCODE, enc, P.n_units / 4, UNIT_TPB, P);
   NK_LAUNCH(KK_USCAN, k_uscan, 1, USCAN_TPB, P);
   NK_LAUNCH(KK_GATHER, k_gather<T>, P.n_units / 4, UNIT_TPB, P);
-  NK_LAUNCH(KK_FINAL, k_final, 1, 64, P);
   return hipSuccess;
 }
 

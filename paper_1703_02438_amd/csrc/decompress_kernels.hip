@@ -49,19 +49,66 @@ __global__ void k_dprefix(DParams P) {
   if (lane_id() == 0 && cnt) atomicAdd(&P.dctl->base, cnt);
 }
 
-// Escapes in each unit's range of wave tiles (reads the packed indices only).
+// Escapes in each unit's range [r0, r1) of indices (reads the packed indices
+// only).  Lane l takes words w = w_lo + l, w_lo + l + 64, ... and counts the
+// indices that start in word w (those straddling into w + 1 read it too).
+// The first index starting in w and its bit offset there are advanced from
+// one word to the next without divisions: 64 words are 2048 bits.
 __global__ void __launch_bounds__(UNIT_TPB) k_dcount(DParams P) {
   const uint32_t unit = blockIdx.x * (UNIT_TPB / 64) + threadIdx.x / 64;
   const int lane = lane_id();
-  const uint32_t esc = (1u << P.B) - 1u;
+  const uint32_t B = P.B;
+  const uint32_t esc = (1u << B) - 1u;
   const uint64_t end = P.start + P.len;
   uint64_t r0 = P.start + (uint64_t)unit * P.tiles_per_unit * P.tile_elems;
   uint64_t r1 = r0 + P.tiles_per_unit * P.tile_elems;
   r0 = r0 < end ? r0 : end;
   r1 = r1 < end ? r1 : end;
   unsigned long long cnt = 0;
-  for (uint64_t j = r0 + lane; j < r1; j += 64)
-    cnt += unpack_index(P.packed, j, P.B) == esc ? 1ull : 0ull;
+  if (r0 < r1 && (32 % B) == 0) {
+    // B divides 32: indices never straddle words.  AND-folding each word by
+    // 1, 2, 4, ... < B bit positions leaves at the first bit of each field
+    // the AND of the field's B bits (1 exactly for the escape code).
+    const uint32_t per = 32 / B;
+    uint32_t start_mask = 0;
+    for (uint32_t b = 0; b < 32; b += B) start_mask |= 1u << b;
+    for (uint64_t w = r0 / per + lane; w * per < r1; w += 64) {
+      uint32_t t = P.packed[w];
+      for (uint32_t sh = 1; sh < B; sh <<= 1) t &= t >> sh;
+      t &= start_mask;
+      const uint64_t e0 = w * per;  // index of the word's first field
+      if (e0 < r0) t &= ~0u << (uint32_t)((r0 - e0) * B);
+      if (e0 + per > r1) {
+        const uint32_t keep = (uint32_t)((r1 - e0) * B);  // < 32 here
+        t &= (1u << keep) - 1u;
+      }
+      cnt += (unsigned long long)__popc(t);
+    }
+  } else if (r0 < r1) {
+    const uint64_t wlo = (r0 * B) >> 5;
+    const uint64_t whi = (r1 * B + 31) >> 5;  // exclusive
+    uint64_t w = wlo + lane;
+    // first index starting at or after bit 32w, and its offset in word w
+    uint64_t e = (32 * w + B - 1) / B;
+    uint32_t off = (uint32_t)(e * B - 32 * w);
+    const uint32_t q = 2048 / B, rem = 2048 % B;
+    for (; w < whi; w += 64) {
+      const uint32_t lo = P.packed[w];
+      const uint32_t hi = w + 1 < P.packed_words ? P.packed[w + 1] : 0u;
+      const unsigned long long x = (unsigned long long)lo | ((unsigned long long)hi << 32);
+      uint64_t ee = e;
+      for (uint32_t o = off; o < 32; o += B, ++ee)
+        cnt += (ee >= r0 && ee < r1 && (uint32_t)((x >> o) & esc) == esc) ? 1ull : 0ull;
+      // advance by 64 words: offset drops by 2048 bits = q indices + rem bits
+      e += q;
+      if (off >= rem) {
+        off -= rem;
+      } else {
+        off = off + B - rem;
+        e += 1;
+      }
+    }
+  }
   cnt = wave_sum_u64(cnt);
   if (lane == 0) P.unit_cnt[unit] = (uint32_t)cnt;
 }
@@ -80,10 +127,10 @@ constexpr int DEC_CENT_BYTES = 32768;
 template <typename T, bool VEC>
 __global__ void __launch_bounds__(UNIT_TPB) k_decode(DParams P) {
   constexpr int V = Traits<T>::V;
-  constexpr int R = UNIT_ROUNDS;
+  constexpr int R = DEC_ROUNDS;
   constexpr int WT = R * 64 * V;
   constexpr int NWAVE = UNIT_TPB / 64;
-  constexpr int TW = WT * 16 / 32 + 2;  // packed words of one wave tile, at most
+  constexpr int TW = NK_DEC_DIRECT ? 1 : WT * 16 / 32 + 2;  // packed words of a tile, at most
   __shared__ uint32_t s_words[NWAVE][TW];
   extern __shared__ unsigned char s_dyn[];  // centre table when it fits
   T* s_cent = reinterpret_cast<T*>(s_dyn);
@@ -116,7 +163,8 @@ __global__ void __launch_bounds__(UNIT_TPB) k_decode(DParams P) {
     const uint32_t tn = rem < (uint64_t)WT ? (uint32_t)rem : (uint32_t)WT;
     const uint64_t wlo = (t0 * B) >> 5;
     const uint32_t nw = (uint32_t)((((t0 + tn) * B + 31) >> 5) - wlo);
-    for (uint32_t i = lane; i < nw; i += 64) words[i] = P.packed[wlo + i];
+    if (!NK_DEC_DIRECT)
+      for (uint32_t i = lane; i < nw; i += 64) words[i] = P.packed[wlo + i];
 
     T pv[R][V];
 #pragma unroll
@@ -129,7 +177,7 @@ __global__ void __launch_bounds__(UNIT_TPB) k_decode(DParams P) {
         for (int v = 0; v < V; ++v) pv[r][v] = e + v < tn ? prev[t0 + e + v] : (T)0;
       }
     }
-    wave_lds_sync();
+    if (!NK_DEC_DIRECT) wave_lds_sync();
 
     const uint32_t bitbase = (uint32_t)(t0 * B - wlo * 32);
 #pragma unroll
@@ -142,11 +190,15 @@ __global__ void __launch_bounds__(UNIT_TPB) k_decode(DParams P) {
       for (int v = 0; v < V; ++v) {
         uint32_t cd = 0;
         if (e + v < tn) {
-          const uint32_t bit = bitbase + (e + v) * B;
-          const uint32_t w = bit >> 5, sh = bit & 31;
-          uint32_t x = words[w] >> sh;
-          if (sh + B > 32) x |= words[w + 1] << (32 - sh);
-          cd = x & esc;
+          if (NK_DEC_DIRECT) {
+            cd = unpack_index(P.packed, t0 + e + v, B);
+          } else {
+            const uint32_t bit = bitbase + (e + v) * B;
+            const uint32_t w = bit >> 5, sh = bit & 31;
+            uint32_t x = words[w] >> sh;
+            if (sh + B > 32) x |= words[w + 1] << (32 - sh);
+            cd = x & esc;
+          }
         }
         code[v] = cd;
         emask[v] = __ballot(e + v < tn && cd == esc);
@@ -184,7 +236,7 @@ __global__ void __launch_bounds__(UNIT_TPB) k_decode(DParams P) {
       }
       run += all;
     }
-    wave_lds_sync();
+    if (!NK_DEC_DIRECT) wave_lds_sync();
   }
   if (__ballot(bad) && lane == 0) atomicOr(P.flags, NUMARCK_FLAG_BAD_INDEX);
   if (__ballot(over) && lane == 0) atomicOr(P.flags, NUMARCK_FLAG_INC_OVERRUN);

@@ -39,12 +39,14 @@ __device__ __forceinline__ double key_value(unsigned long long k) {
   return __longlong_as_double((long long)b);
 }
 
-// eq. (1): change ratio d = (q - p) / p in binary64; returns validity
-// (nonzero finite p, finite q, finite d, |d| <= cap = E * 2^50).
+// eq. (1): change ratio d = (q - p) / p in binary64; returns validity:
+// p nonzero and finite, q finite, d finite and |d| <= cap = E * 2^50.
+// Evaluated as isfinite(p) && |d| <= cap, which is the same predicate: the
+// comparison is false for a NaN or infinite d, and with p finite a zero p
+// (division by zero) or a non-finite q always yields such a d.
 __device__ __forceinline__ bool ratio_of(double p, double q, double cap, double& d) {
   d = (q - p) / p;
-  return (p != 0.0) & __builtin_isfinite(p) & __builtin_isfinite(q) & __builtin_isfinite(d) &
-         (fabs(d) <= cap);
+  return __builtin_isfinite(p) & (fabs(d) <= cap);
 }
 
 // Fine bin of a valid ratio: bins of width 2E anchored at lo.
@@ -69,6 +71,17 @@ __device__ __forceinline__ double bin_floor(double x, double twoE, double inv, b
   return floor(x / twoE);
 }
 
+// The fast part of bin_floor: floor(x * inv) and whether it is certain.
+// When `sure` is false the caller takes floor(x / twoE).
+__device__ __forceinline__ double bin_floor_fast(double x, double inv, bool& sure) {
+  const double t = x * inv;
+  const double f = floor(t);
+  const double frac = t - f;
+  const double thr = t * 0x1p-49;
+  sure = (frac > thr) && ((1.0 - frac) > thr);
+  return f;
+}
+
 // Bin centre lo + (2m + 1) E from a bin id held as a double (an integer below
 // 2^51, so 2m + 1 is exact), rounded to the snapshot type and widened back.
 template <typename T>
@@ -85,6 +98,20 @@ __device__ __forceinline__ double centre_of(long long m, double lo, double E) {
 }
 
 __device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
+
+// Add one to counter `key` of an LDS histogram for every lane with `on`.
+// The wave's most common case -- the key of its first active lane -- takes a
+// single atomic for all lanes that share it; the other lanes add directly.
+__device__ __forceinline__ void lds_count(uint32_t* hist, bool on, unsigned key) {
+  const unsigned long long act = __ballot(on);
+  if (!act) return;
+  const int leader = __ffsll((long long)act) - 1;
+  const unsigned lk = (unsigned)__builtin_amdgcn_readlane((int)key, leader);
+  const bool same = on && key == lk;
+  const unsigned long long sm = __ballot(same);
+  if (lane_id() == leader) atomicAdd(&hist[lk], (unsigned)__popcll(sm));
+  if (on && !same) atomicAdd(&hist[key], 1u);
+}
 
 // Order this wave's LDS accesses before and after: LDS instructions of one
 // wave execute in order, so a compiler barrier plus waiting for the wave's

@@ -13,7 +13,6 @@ namespace nk {
 // On-chip (LDS) window of fine bins used by the histogram and the encoder.
 // Bins outside it are counted exactly through the tail list + hash table.
 constexpr int WIN = 16384;
-constexpr uint16_t NOSEL = 0xFFFF;       // window LUT entry: bin not selected
 constexpr uint32_t HEMPTY = 0xFFFFFFFFu;  // empty hash slot
 constexpr int MAX_SEL = 65535;            // k for B = 16
 
@@ -21,10 +20,32 @@ constexpr int MAX_SEL = 65535;            // k for B = 16
 // owns a contiguous run of wave tiles and keeps a running count of
 // incompressible points, so no wave ever waits for another.  A wave tile is
 // 4 rounds of one 16-byte vector per lane: 512 float64 or 1024 float32.
+// Tuning knobs (compile-time; every setting computes identical outputs).
+#ifndef NK_ENC_ROUNDS
+#define NK_ENC_ROUNDS 2      // vector rounds per encoder wave tile
+#endif
+#ifndef NK_ENC_PREFETCH
+#define NK_ENC_PREFETCH 1    // issue the next tile's loads before computing
+#endif
+#ifndef NK_DEC_ROUNDS
+#define NK_DEC_ROUNDS 4      // vector rounds per decoder wave tile
+#endif
+#ifndef NK_DEC_DIRECT
+#define NK_DEC_DIRECT 0      // decoder reads index bits from global, not via LDS
+#endif
+#ifndef NK_HIST_HYBRID
+#define NK_HIST_HYBRID 0     // aggregate the wave's most common bin
+#endif
+#ifndef NK_HIST_REVERSE
+#define NK_HIST_REVERSE 0    // histogram sweep from the end of the arrays
+#endif
+#ifndef NK_HIST_TPB
+#define NK_HIST_TPB 512
+#endif
 constexpr int UNIT_TPB = 256;      // 4 units per workgroup
-constexpr int UNIT_ROUNDS = 4;
+constexpr int ENC_ROUNDS = NK_ENC_ROUNDS;
+constexpr int DEC_ROUNDS = NK_DEC_ROUNDS;
 constexpr int MAX_UNITS = 8192;
-constexpr int LUT_GROUPS = WIN / 64;
 
 // ------------------------------------------------ device control block
 // Lives at the start of the compression workspace.  Fields above `lo` are
@@ -66,7 +87,7 @@ struct DCtl {
 
 // Workspace layout of one compression (byte offsets from the workspace base).
 struct Layout {
-  size_t ctl, gwin, lutbits, lutbase, sel_tail, sorted_tail, unit_cnt, scratch, tail, hslot,
+  size_t ctl, gwin, lut, sel_tail, sorted_tail, unit_cnt, scratch, tail, hslot,
       hcnt, total;
   uint64_t tail_cap, hcap;
 };
@@ -88,8 +109,8 @@ struct CParams {
   uint64_t packed_words;
   Ctl* ctl;
   uint32_t* gwin;
-  unsigned long long* lutbits;  // selected window bins, one bit per bin
-  uint32_t* lutbase;            // index of the first selected bin of each 64-bin group
+  uint16_t* lut;      // window bin -> index, or the escape code if not selected
+  uint32_t mulB;      // ceil(2^32 / B) for B > 1: floor(x / B) = mulhi(x, mulB) for x < 2^15
   int64_t* tail;
   uint64_t tail_cap;
   uint32_t* hslot;
@@ -137,8 +158,9 @@ struct Geometry {
 };
 Geometry geometry();
 
-// Elements of one wave tile for an element size (16-byte vectors).
-inline uint64_t wave_tile(uint64_t elem_bytes) { return UNIT_ROUNDS * 64 * (16 / elem_bytes); }
+// Elements of one encoder / decoder wave tile for an element size (16-byte vectors).
+inline uint64_t enc_wave_tile(uint64_t elem_bytes) { return ENC_ROUNDS * 64 * (16 / elem_bytes); }
+inline uint64_t dec_wave_tile(uint64_t elem_bytes) { return DEC_ROUNDS * 64 * (16 / elem_bytes); }
 // Units (waves) of a range-partitioned pass over `tiles` wave tiles, at most
 // `resident` (the waves that fit on the device at once); a multiple of the 4
 // units of a workgroup.
@@ -153,7 +175,7 @@ inline uint32_t range_units(uint64_t tiles, int resident) {
 // Kernel kinds for the optional event timing.
 enum KernelKind {
   KK_INIT = 0, KK_RANGE, KK_DERIVE, KK_HIST, KK_HCLEAR, KK_HINSERT, KK_SELECT,
-  KK_TAILRANK, KK_ENCODE, KK_USCAN, KK_GATHER, KK_FINAL, KK_DINIT, KK_DPREFIX, KK_DCOUNT,
+  KK_TAILRANK, KK_ENCODE, KK_USCAN, KK_GATHER, KK_DINIT, KK_DPREFIX, KK_DCOUNT,
   KK_DSCAN, KK_DECODE, KK_EXPORT, KK_COUNT
 };
 void timing_begin(KernelKind k, hipStream_t s);
