@@ -177,6 +177,83 @@ numarck_status numarck_histogram_export(const void* ws, size_t ws_bytes, uint64_
                                         numarck_dtype dtype, int64_t* ids, uint32_t* counts,
                                         uint64_t capacity, uint64_t* count_dev, void* stream);
 
+/* ---- launch tuning ----
+ * Launch parameters of the passes.  No setting changes any output; they only
+ * trade occupancy, atomic traffic and work granularity.  Filled with the
+ * defaults by numarck_tuning_default; numarck_autotune measures candidates. */
+typedef struct numarck_tuning {
+  uint32_t range_blocks_per_cu; /* pass-1 workgroups per compute unit */
+  uint32_t hist_blocks_per_cu;  /* histogram workgroups per compute unit */
+  uint32_t hist_lds;            /* 1: window counts in LDS (64 KB per workgroup); 0: in global memory */
+  uint32_t chunk_vec;           /* 16-byte vectors per streaming chunk of the first two passes */
+  uint32_t unit_pct;            /* encoder waves as a percentage of the resident capacity (1..100) */
+} numarck_tuning;
+
+void numarck_tuning_default(numarck_tuning* t);
+
+/* numarck_compress with explicit launch tuning (NULL = the tuning recorded by
+ * numarck_autotune for this size class and dtype, else the defaults). */
+numarck_status numarck_compress_tuned(const void* prev, const void* curr, uint64_t n,
+                                      numarck_dtype dtype, double E, uint32_t B,
+                                      uint64_t block_bytes, const numarck_out* out, void* ws,
+                                      size_t ws_bytes, const numarck_tuning* tune, void* stream);
+
+/* Measure candidate tunings on one compression (inputs as for numarck_compress,
+ * `reps` timed runs per candidate), write the fastest to *best and record it
+ * for the size class (floor(log2 n)) and dtype.  Synchronises `stream`.  The
+ * outputs buffers are overwritten by the trial runs. */
+numarck_status numarck_autotune(const void* prev, const void* curr, uint64_t n,
+                                numarck_dtype dtype, double E, uint32_t B, uint64_t block_bytes,
+                                const numarck_out* out, void* ws, size_t ws_bytes, uint32_t reps,
+                                void* stream, numarck_tuning* best);
+/* Save / load the recorded tunings as text (one line per size class). */
+numarck_status numarck_tuning_save(const char* path);
+numarck_status numarck_tuning_load(const char* path);
+
+/* ---- batched compression: many variables / time steps in one chain ----
+ * Each job is one numarck_compress (its own inputs, E, B, block size and
+ * outputs).  All jobs go through the same passes with one launch per pass and
+ * element type (the encoder: per index-width class), whatever their number;
+ * results are identical to compressing each job alone. */
+typedef struct numarck_job {
+  const void* prev;
+  const void* curr;
+  uint64_t n;
+  numarck_dtype dtype;
+  double E;
+  uint32_t B;
+  uint64_t block_bytes;  /* 0 = 2^20 */
+  numarck_out out;
+} numarck_job;
+
+/* Most jobs in one batch (one grid row per job in the per-job passes). */
+#define NUMARCK_MAX_JOBS 65535u
+
+/* A plan: the static description of a batch (job table, per-job workspace,
+ * work partition) written once into the workspace; running it only launches
+ * kernels, so it can be captured into a HIP graph and replayed. */
+typedef struct numarck_plan numarck_plan;
+
+/* Workspace bytes for a batch (every job with full tail capacity). */
+size_t numarck_batch_workspace_bytes(const numarck_job* jobs, uint32_t njobs);
+/* Validate the jobs, lay out the workspace and copy the job table to it on
+ * `stream` (asynchronous).  tune = NULL: defaults.  *plan is host memory owned
+ * by the caller until numarck_plan_destroy. */
+numarck_status numarck_plan_create(const numarck_job* jobs, uint32_t njobs,
+                                   const numarck_tuning* tune, void* ws, size_t ws_bytes,
+                                   void* stream, numarck_plan** plan);
+/* Compress every job of the plan on `stream`. */
+numarck_status numarck_plan_run(const numarck_plan* plan, void* stream);
+/* Capture numarck_plan_run on `stream` (not the null stream) into a HIP graph
+ * kept by the plan; numarck_plan_replay launches it.  Inputs and outputs are
+ * the plan's buffers: replays compress whatever they hold at that time. */
+numarck_status numarck_plan_capture(numarck_plan* plan, void* stream);
+numarck_status numarck_plan_replay(const numarck_plan* plan, void* stream);
+void numarck_plan_destroy(numarck_plan* plan);
+/* One-shot batch: plan, run, destroy. */
+numarck_status numarck_compress_batch(const numarck_job* jobs, uint32_t njobs, void* ws,
+                                      size_t ws_bytes, void* stream);
+
 /* ---- diagnostics ---- */
 const char* numarck_status_str(numarck_status s);
 /* Text of the last HIP error seen by this thread ("" if none). */

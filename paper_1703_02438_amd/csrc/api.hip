@@ -4,6 +4,11 @@
 #include <math.h>
 #include <string.h>
 
+#include <stdio.h>
+
+#include <algorithm>
+#include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -176,26 +181,30 @@ size_t numarck_decompress_workspace_bytes(uint64_t len) {
 
 static bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
 
-numarck_status numarck_compress(const void* prev, const void* curr, uint64_t n,
+// Validate one compression's arguments (the checks every entry point makes).
+static numarck_status check_job(const void* prev, const void* curr, uint64_t n,
                                 numarck_dtype dtype, double E, uint32_t B,
-                                uint64_t block_bytes, const numarck_out* out, void* ws,
-                                size_t ws_bytes, void* stream) {
+                                uint64_t block_bytes, const numarck_out* out) {
   if (dtype != NUMARCK_F32 && dtype != NUMARCK_F64) return NUMARCK_EDTYPE;
   if (B < 1 || B > 16) return NUMARCK_EBITS;
   if (!(E > 0.0 && E <= 1.0)) return NUMARCK_EBOUND;
   if (n >= ((uint64_t)1 << 32)) return NUMARCK_EINVAL;
-  if (!out || !out->hdr || !out->centers || !ws) return NUMARCK_EINVAL;
+  if (!out || !out->hdr || !out->centers) return NUMARCK_EINVAL;
   if (n > 0 && (!prev || !curr || !out->packed || !out->incomp || !out->block_inc_off))
     return NUMARCK_EINVAL;
   if (block_bytes == 0) block_bytes = (uint64_t)1 << 20;
   if (8 * block_bytes < B) return NUMARCK_EINVAL;
   if (!aligned16(prev) || !aligned16(curr) || !aligned16(out->recon)) return NUMARCK_EALIGN;
-  if (((uintptr_t)ws & 255u) != 0) return NUMARCK_EALIGN;
-  Layout L;
-  const uint64_t eb = elem_bytes_of(dtype);
-  if (!fit_layout(n, eb, ws_bytes, &L)) return NUMARCK_ECAPACITY;
+  return NUMARCK_OK;
+}
 
-  char* base = static_cast<char*>(ws);
+// Kernel parameters of one checked compression whose workspace slice starts
+// at `base` with layout L (encoder units are set by the launcher).
+static CParams make_params(const void* prev, const void* curr, uint64_t n, numarck_dtype dtype,
+                           double E, uint32_t B, uint64_t block_bytes, const numarck_out* out,
+                           char* base, const Layout& L) {
+  if (block_bytes == 0) block_bytes = (uint64_t)1 << 20;
+  const uint64_t eb = elem_bytes_of(dtype);
   CParams P{};
   P.prev = prev;
   P.curr = curr;
@@ -234,9 +243,428 @@ numarck_status numarck_compress(const void* prev, const void* curr, uint64_t n,
   P.bin_ids = out->bin_ids;
   P.hdr = out->hdr;
   P.dtype = (int)dtype;
-  const hipError_t e = launch_compress(P, static_cast<hipStream_t>(stream));
+  return P;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------- tuning table
+namespace nk {
+
+static std::mutex g_tune_mu;
+// recorded tunings by (dtype, floor(log2 n))
+static std::map<std::pair<int, int>, Tuning> g_tune;
+
+static int size_class(uint64_t n) {
+  int c = 0;
+  while (n > 1) {
+    n >>= 1;
+    ++c;
+  }
+  return c;
+}
+
+static bool tuning_valid(const Tuning& t) {
+  return t.range_blocks_per_cu >= 1 && t.range_blocks_per_cu <= 64 &&
+         t.hist_blocks_per_cu >= 1 && t.hist_blocks_per_cu <= 16 && t.hist_lds <= 1 &&
+         t.chunk_vec >= 64 && t.chunk_vec <= (1u << 20) && t.unit_pct >= 1 &&
+         t.unit_pct <= 100;
+}
+
+static Tuning to_internal(const numarck_tuning& t) {
+  return Tuning{t.range_blocks_per_cu, t.hist_blocks_per_cu, t.hist_lds, t.chunk_vec,
+                t.unit_pct};
+}
+
+static numarck_tuning to_public(const Tuning& t) {
+  numarck_tuning o;
+  o.range_blocks_per_cu = t.range_blocks_per_cu;
+  o.hist_blocks_per_cu = t.hist_blocks_per_cu;
+  o.hist_lds = t.hist_lds;
+  o.chunk_vec = t.chunk_vec;
+  o.unit_pct = t.unit_pct;
+  return o;
+}
+
+static Tuning recorded_tuning(int dtype, uint64_t n) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  auto it = g_tune.find({dtype, size_class(n)});
+  return it == g_tune.end() ? default_tuning() : it->second;
+}
+
+}  // namespace nk
+
+extern "C" {
+
+void numarck_tuning_default(numarck_tuning* t) {
+  if (t) *t = to_public(default_tuning());
+}
+
+numarck_status numarck_compress_tuned(const void* prev, const void* curr, uint64_t n,
+                                      numarck_dtype dtype, double E, uint32_t B,
+                                      uint64_t block_bytes, const numarck_out* out, void* ws,
+                                      size_t ws_bytes, const numarck_tuning* tune, void* stream) {
+  const numarck_status st = check_job(prev, curr, n, dtype, E, B, block_bytes, out);
+  if (st != NUMARCK_OK) return st;
+  if (!ws) return NUMARCK_EINVAL;
+  if (((uintptr_t)ws & 255u) != 0) return NUMARCK_EALIGN;
+  Tuning tn = tune ? to_internal(*tune) : recorded_tuning((int)dtype, n);
+  if (!tuning_valid(tn)) return NUMARCK_EINVAL;
+  Layout L;
+  if (!fit_layout(n, elem_bytes_of(dtype), ws_bytes, &L)) return NUMARCK_ECAPACITY;
+  const CParams P = make_params(prev, curr, n, dtype, E, B, block_bytes, out,
+                                static_cast<char*>(ws), L);
+  const hipError_t e = launch_compress(P, tn, static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(e);
   return NUMARCK_OK;
+}
+
+numarck_status numarck_compress(const void* prev, const void* curr, uint64_t n,
+                                numarck_dtype dtype, double E, uint32_t B,
+                                uint64_t block_bytes, const numarck_out* out, void* ws,
+                                size_t ws_bytes, void* stream) {
+  return numarck_compress_tuned(prev, curr, n, dtype, E, B, block_bytes, out, ws, ws_bytes,
+                                nullptr, stream);
+}
+
+numarck_status numarck_autotune(const void* prev, const void* curr, uint64_t n,
+                                numarck_dtype dtype, double E, uint32_t B, uint64_t block_bytes,
+                                const numarck_out* out, void* ws, size_t ws_bytes, uint32_t reps,
+                                void* stream, numarck_tuning* best) {
+  if (reps < 1) reps = 1;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipEvent_t a = nullptr, b = nullptr;
+  if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess)
+    return hip_fail(hipGetLastError());
+  numarck_status st = NUMARCK_OK;
+  auto measure = [&](const Tuning& t, float* ms) -> numarck_status {
+    const numarck_tuning pt = to_public(t);
+    numarck_status r = numarck_compress_tuned(prev, curr, n, dtype, E, B, block_bytes, out, ws,
+                                              ws_bytes, &pt, stream);  // warm
+    if (r != NUMARCK_OK) return r;
+    hipError_t e = hipEventRecord(a, s);
+    for (uint32_t i = 0; i < reps && r == NUMARCK_OK && e == hipSuccess; ++i)
+      r = numarck_compress_tuned(prev, curr, n, dtype, E, B, block_bytes, out, ws, ws_bytes,
+                                 &pt, stream);
+    if (r != NUMARCK_OK) return r;
+    if (e == hipSuccess) e = hipEventRecord(b, s);
+    if (e == hipSuccess) e = hipEventSynchronize(b);
+    if (e == hipSuccess) e = hipEventElapsedTime(ms, a, b);
+    return e == hipSuccess ? NUMARCK_OK : hip_fail(e);
+  };
+  // coordinate descent from the defaults, one parameter family at a time
+  Tuning cur = default_tuning();
+  float cur_ms = 0.f;
+  st = measure(cur, &cur_ms);
+  const uint32_t rbpc[] = {2, 4, 8, 16};
+  // LDS counting only: global window counts serialise on the hot bins of
+  // concentrated ratio distributions (orders of magnitude slower there)
+  const uint32_t hist[][2] = {{1, 1}, {1, 2}, {1, 4}};
+  const uint32_t cvec[] = {1024, 4096, 16384, 65536};
+  const uint32_t upct[] = {25, 50, 75, 100};
+  auto try_one = [&](const Tuning& t) {
+    if (st != NUMARCK_OK) return;
+    float ms = 0.f;
+    st = measure(t, &ms);
+    if (st == NUMARCK_OK && ms < cur_ms) {
+      cur = t;
+      cur_ms = ms;
+    }
+  };
+  for (uint32_t v : rbpc) { Tuning t = cur; t.range_blocks_per_cu = v; try_one(t); }
+  for (auto& h : hist) { Tuning t = cur; t.hist_lds = h[0]; t.hist_blocks_per_cu = h[1]; try_one(t); }
+  for (uint32_t v : cvec) { Tuning t = cur; t.chunk_vec = v; try_one(t); }
+  for (uint32_t v : upct) { Tuning t = cur; t.unit_pct = v; try_one(t); }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  if (st != NUMARCK_OK) return st;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[{(int)dtype, size_class(n)}] = cur;
+  }
+  if (best) *best = to_public(cur);
+  return NUMARCK_OK;
+}
+
+numarck_status numarck_tuning_save(const char* path) {
+  if (!path) return NUMARCK_EINVAL;
+  FILE* f = fopen(path, "w");
+  if (!f) {
+    g_last_error = std::string("cannot write ") + path;
+    return NUMARCK_EINVAL;
+  }
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  fprintf(f, "# dtype log2n range_blocks_per_cu hist_blocks_per_cu hist_lds chunk_vec unit_pct\n");
+  for (const auto& kv : g_tune) {
+    const Tuning& t = kv.second;
+    fprintf(f, "%s %d %u %u %u %u %u\n", kv.first.first == NUMARCK_F32 ? "f32" : "f64",
+            kv.first.second, t.range_blocks_per_cu, t.hist_blocks_per_cu, t.hist_lds,
+            t.chunk_vec, t.unit_pct);
+  }
+  fclose(f);
+  return NUMARCK_OK;
+}
+
+numarck_status numarck_tuning_load(const char* path) {
+  if (!path) return NUMARCK_EINVAL;
+  FILE* f = fopen(path, "r");
+  if (!f) {
+    g_last_error = std::string("cannot read ") + path;
+    return NUMARCK_EINVAL;
+  }
+  std::map<std::pair<int, int>, Tuning> got;
+  char line[256];
+  numarck_status st = NUMARCK_OK;
+  while (fgets(line, sizeof line, f)) {
+    if (line[0] == '#' || line[0] == '\n') continue;
+    char dt[8];
+    int cls = 0;
+    Tuning t{};
+    if (sscanf(line, "%7s %d %u %u %u %u %u", dt, &cls, &t.range_blocks_per_cu,
+               &t.hist_blocks_per_cu, &t.hist_lds, &t.chunk_vec, &t.unit_pct) != 7 ||
+        (strcmp(dt, "f32") != 0 && strcmp(dt, "f64") != 0) || cls < 0 || cls > 63 ||
+        !tuning_valid(t)) {
+      g_last_error = std::string("malformed tuning line: ") + line;
+      st = NUMARCK_EINVAL;
+      break;
+    }
+    got[{strcmp(dt, "f32") == 0 ? (int)NUMARCK_F32 : (int)NUMARCK_F64, cls}] = t;
+  }
+  fclose(f);
+  if (st != NUMARCK_OK) return st;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  for (const auto& kv : got) g_tune[kv.first] = kv.second;
+  return NUMARCK_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------- batch plans
+struct numarck_plan {
+  uint32_t njobs;
+  std::vector<CParams> table;        // sorted by (dtype, encoder class)
+  std::vector<uint64_t> chunk0;      // njobs + 1
+  std::vector<uint32_t> unit0;       // njobs + 1
+  std::vector<nk::JobGroup> dgroups, egroups;
+  nk::BatchLaunch bl;
+  hipEvent_t uploaded = nullptr;     // the descriptor copy has completed
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+namespace nk {
+
+// Batch workspace: the job table, the two prefix arrays, then one
+// compression layout (full tail capacity) per job.
+static size_t batch_head_bytes(uint32_t njobs) {
+  return align256((size_t)njobs * sizeof(CParams)) + align256((size_t)(njobs + 1) * 8) +
+         align256((size_t)(njobs + 1) * 4);
+}
+
+static size_t job_slice_bytes(const numarck_job& j) {
+  return align256(compress_layout(j.n, j.dtype == NUMARCK_F32 ? 4 : 8, j.n).total);
+}
+
+}  // namespace nk
+
+extern "C" {
+
+size_t numarck_batch_workspace_bytes(const numarck_job* jobs, uint32_t njobs) {
+  if (!jobs || njobs == 0) return 0;
+  size_t total = batch_head_bytes(njobs);
+  for (uint32_t i = 0; i < njobs; ++i) total += job_slice_bytes(jobs[i]);
+  return total;
+}
+
+numarck_status numarck_plan_create(const numarck_job* jobs, uint32_t njobs,
+                                   const numarck_tuning* tune, void* ws, size_t ws_bytes,
+                                   void* stream, numarck_plan** plan_out) {
+  if (!plan_out) return NUMARCK_EINVAL;
+  *plan_out = nullptr;
+  if (!jobs || njobs == 0 || njobs > NUMARCK_MAX_JOBS || !ws) return NUMARCK_EINVAL;
+  if (((uintptr_t)ws & 255u) != 0) return NUMARCK_EALIGN;
+  const Tuning tn = tune ? to_internal(*tune) : default_tuning();
+  if (!tuning_valid(tn)) return NUMARCK_EINVAL;
+  for (uint32_t i = 0; i < njobs; ++i) {
+    const numarck_job& j = jobs[i];
+    const numarck_status st =
+        check_job(j.prev, j.curr, j.n, j.dtype, j.E, j.B, j.block_bytes, &j.out);
+    if (st != NUMARCK_OK) {
+      g_last_error = "job " + std::to_string(i) + ": " + numarck_status_str(st);
+      return st;
+    }
+  }
+  if (numarck_batch_workspace_bytes(jobs, njobs) > ws_bytes) return NUMARCK_ECAPACITY;
+
+  // order: element type, then encoder class (each launch covers a contiguous run)
+  std::vector<uint32_t> order(njobs);
+  for (uint32_t i = 0; i < njobs; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) {
+    const int ka = (int)jobs[a].dtype * 8 + enc_class(jobs[a].B);
+    const int kb = (int)jobs[b].dtype * 8 + enc_class(jobs[b].B);
+    return ka < kb;
+  });
+
+  numarck_plan* pl = new numarck_plan();
+  pl->njobs = njobs;
+  pl->table.resize(njobs);
+  pl->chunk0.assign(njobs + 1, 0);
+  pl->unit0.assign(njobs + 1, 0);
+  char* base = static_cast<char*>(ws);
+  size_t off = batch_head_bytes(njobs);
+  for (uint32_t r = 0; r < njobs; ++r) {
+    const numarck_job& j = jobs[order[r]];
+    const uint64_t eb = j.dtype == NUMARCK_F32 ? 4 : 8;
+    const Layout L = compress_layout(j.n, eb, j.n);
+    pl->table[r] = make_params(j.prev, j.curr, j.n, j.dtype, j.E, j.B, j.block_bytes, &j.out,
+                               base + off, L);
+    off += align256(L.total);
+    pl->chunk0[r + 1] = pl->chunk0[r] + stream_chunks(j.n, (int)j.dtype, tn.chunk_vec);
+  }
+
+  // groups, and encoder units split within each encoder group in proportion
+  // to the jobs' tiles (a multiple of 4 per job, at least 4)
+  const Geometry G = geometry();
+  for (uint32_t r = 0; r < njobs;) {
+    uint32_t e = r + 1;
+    const int dt = pl->table[r].dtype, cls = enc_class(pl->table[r].B);
+    while (e < njobs && pl->table[e].dtype == dt && enc_class(pl->table[e].B) == cls) ++e;
+    uint64_t tiles = 0;
+    for (uint32_t q = r; q < e; ++q) tiles += pl->table[q].n_tiles;
+    const int occ = encoder_occupancy(dt, cls, true);
+    uint64_t resident = (uint64_t)G.cus * occ * 4 * tn.unit_pct / 100;
+    if (resident < 4) resident = 4;
+    for (uint32_t q = r; q < e; ++q) {
+      CParams& P = pl->table[q];
+      const uint64_t share =
+          tiles ? (resident * P.n_tiles + tiles - 1) / tiles : 1;  // ceil
+      P.n_units = range_units(P.n_tiles, (int)(share < 4 ? 4 : share));
+      P.tiles_per_unit = (P.n_tiles + P.n_units - 1) / P.n_units;
+      pl->unit0[q + 1] = pl->unit0[q] + P.n_units;
+    }
+    JobGroup g{};
+    g.dtype = dt;
+    g.cls = cls;
+    g.job_begin = r;
+    g.job_end = e;
+    g.c_begin = pl->chunk0[r];
+    g.c_end = pl->chunk0[e];
+    g.u_begin = pl->unit0[r];
+    g.u_end = pl->unit0[e];
+    pl->egroups.push_back(g);
+    if (!pl->dgroups.empty() && pl->dgroups.back().dtype == dt) {
+      pl->dgroups.back().job_end = e;
+      pl->dgroups.back().c_end = g.c_end;
+      pl->dgroups.back().u_end = g.u_end;
+    } else {
+      pl->dgroups.push_back(g);
+    }
+    r = e;
+  }
+  if ((uint64_t)pl->unit0[njobs] / 4 > 0x7FFFFFFFull) {
+    delete pl;
+    return NUMARCK_EINVAL;
+  }
+
+  // descriptors to the workspace head
+  const size_t t_off = 0;
+  const size_t c_off = align256((size_t)njobs * sizeof(CParams));
+  const size_t u_off = c_off + align256((size_t)(njobs + 1) * 8);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = hipMemcpyAsync(base + t_off, pl->table.data(), njobs * sizeof(CParams),
+                                hipMemcpyHostToDevice, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(base + c_off, pl->chunk0.data(), (njobs + 1) * 8, hipMemcpyHostToDevice,
+                       s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(base + u_off, pl->unit0.data(), (njobs + 1) * 4, hipMemcpyHostToDevice,
+                       s);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&pl->uploaded, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventRecord(pl->uploaded, s);
+  if (e != hipSuccess) {
+    if (pl->uploaded) (void)hipEventDestroy(pl->uploaded);
+    delete pl;
+    return hip_fail(e);
+  }
+  BatchLaunch& bl = pl->bl;
+  bl.jobs_dev = reinterpret_cast<const CParams*>(base + t_off);
+  bl.chunk0_dev = reinterpret_cast<const uint64_t*>(base + c_off);
+  bl.unit0_dev = reinterpret_cast<const uint32_t*>(base + u_off);
+  bl.njobs = njobs;
+  bl.dgroups = pl->dgroups.data();
+  bl.n_dgroups = (uint32_t)pl->dgroups.size();
+  bl.egroups = pl->egroups.data();
+  bl.n_egroups = (uint32_t)pl->egroups.size();
+  bl.tune = tn;
+  *plan_out = pl;
+  return NUMARCK_OK;
+}
+
+numarck_status numarck_plan_run(const numarck_plan* plan, void* stream) {
+  if (!plan) return NUMARCK_EINVAL;
+  const hipError_t e = launch_compress_batch(plan->bl, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? NUMARCK_OK : hip_fail(e);
+}
+
+numarck_status numarck_plan_capture(numarck_plan* plan, void* stream) {
+  if (!plan || !stream) return NUMARCK_EINVAL;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (plan->exec) {
+    (void)hipGraphExecDestroy(plan->exec);
+    plan->exec = nullptr;
+  }
+  if (plan->graph) {
+    (void)hipGraphDestroy(plan->graph);
+    plan->graph = nullptr;
+  }
+  // the descriptors must be in place before the graph's first replay
+  hipError_t e = hipStreamWaitEvent(s, plan->uploaded, 0);
+  if (e != hipSuccess) return hip_fail(e);
+  const bool timing = g_timing;
+  g_timing = false;  // no event records inside the graph
+  e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+  hipError_t le = hipSuccess;
+  if (e == hipSuccess) {
+    le = launch_compress_batch(plan->bl, s);
+    e = hipStreamEndCapture(s, &plan->graph);
+  }
+  g_timing = timing;
+  if (le != hipSuccess) e = le;
+  if (e == hipSuccess) e = hipGraphInstantiate(&plan->exec, plan->graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    if (plan->graph) (void)hipGraphDestroy(plan->graph);
+    plan->graph = nullptr;
+    plan->exec = nullptr;
+    return hip_fail(e);
+  }
+  return NUMARCK_OK;
+}
+
+numarck_status numarck_plan_replay(const numarck_plan* plan, void* stream) {
+  if (!plan || !plan->exec) return NUMARCK_EINVAL;
+  const hipError_t e = hipGraphLaunch(plan->exec, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? NUMARCK_OK : hip_fail(e);
+}
+
+void numarck_plan_destroy(numarck_plan* plan) {
+  if (!plan) return;
+  if (plan->uploaded) {
+    (void)hipEventSynchronize(plan->uploaded);  // the host tables feed the copy
+    (void)hipEventDestroy(plan->uploaded);
+  }
+  if (plan->exec) (void)hipGraphExecDestroy(plan->exec);
+  if (plan->graph) (void)hipGraphDestroy(plan->graph);
+  delete plan;
+}
+
+numarck_status numarck_compress_batch(const numarck_job* jobs, uint32_t njobs, void* ws,
+                                      size_t ws_bytes, void* stream) {
+  numarck_plan* pl = nullptr;
+  numarck_status st = numarck_plan_create(jobs, njobs, nullptr, ws, ws_bytes, stream, &pl);
+  if (st != NUMARCK_OK) return st;
+  st = numarck_plan_run(pl, stream);
+  numarck_plan_destroy(pl);
+  return st;
 }
 
 static numarck_status check_header(const numarck_header* h) {

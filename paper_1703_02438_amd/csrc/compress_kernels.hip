@@ -30,11 +30,58 @@
 
 namespace nk {
 
+// Job sources: the plain path passes its one job by value, a batch reads the
+// job table in device memory.
+struct OneJob {
+  CParams p;
+  __device__ __forceinline__ const CParams& job(uint32_t) const { return p; }
+};
+struct JobTable {
+  const CParams* t;
+  __device__ __forceinline__ const CParams& job(uint32_t j) const { return t[j]; }
+};
+
+// Largest j in [lo, hi) with starts[j] <= x (starts ascending).
+template <typename U>
+__device__ __forceinline__ uint32_t find_job(const U* starts, uint32_t lo, uint32_t hi, U x) {
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (starts[mid] <= x) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+// A streaming workgroup's current job and that job's chunk span, kept in
+// registers: chunks rise monotonically per workgroup, so the prefix array is
+// searched only when a chunk lies past the span.
+struct ChunkCursor {
+  uint32_t j = 0xFFFFFFFFu;
+  uint64_t first = 0, end = 0;  // chunks of job j: [first, end)
+
+  // Moves to the job of chunk c; true if that is another job than before.
+  __device__ __forceinline__ bool seek(const Geo& g, uint64_t c) {
+    if (j != 0xFFFFFFFFu && c < end) return false;
+    if (!g.chunk0) {
+      j = g.job_begin;
+      first = 0;
+      end = ~0ull;
+      return true;
+    }
+    j = find_job(g.chunk0, j == 0xFFFFFFFFu ? g.job_begin : j + 1, g.job_end, c);
+    first = g.chunk0[j];
+    end = g.chunk0[j + 1];
+    return true;
+  }
+};
+
 // =====================================================================
 // k_init
 // =====================================================================
-__global__ void k_init(Ctl* ctl) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
+template <typename S>
+__global__ void k_init(S src, Geo g) {
+  const CParams& P = src.job(g.job_begin + blockIdx.x);
+  Ctl* ctl = P.ctl;
+  if (threadIdx.x == 0) {
     ctl->lo_key = ~0ull;
     ctl->hi_key = 0ull;
     ctl->n_invalid = 0ull;
@@ -44,6 +91,7 @@ __global__ void k_init(Ctl* ctl) {
     ctl->tail_bins = 0u;
     ctl->tail_max = 0u;
   }
+  for (int i = threadIdx.x; i < WIN; i += blockDim.x) P.gwin[i] = 0u;
 }
 
 // =====================================================================
@@ -52,94 +100,117 @@ __global__ void k_init(Ctl* ctl) {
 constexpr int RNG_TPB = 256;
 constexpr int RNG_UNROLL = 4;
 
-template <typename T>
-__global__ void __launch_bounds__(RNG_TPB) k_range(CParams P) {
-  constexpr int V = Traits<T>::V;
-  const T* __restrict__ prev = static_cast<const T*>(P.prev);
-  const T* __restrict__ curr = static_cast<const T*>(P.curr);
-  const uint64_t nvec = P.n / V;
-  const int tid = threadIdx.x;
-
-  // side job: clear the global window counts
-  {
-    const uint64_t gt = (uint64_t)blockIdx.x * RNG_TPB + tid;
-    const uint64_t gs = (uint64_t)gridDim.x * RNG_TPB;
-    for (uint64_t i = gt; i < (uint64_t)WIN; i += gs) P.gwin[i] = 0u;
-  }
-
-  unsigned long long kmin = ~0ull, kmax = 0ull, ninv = 0ull;
-  for (uint64_t vb = (uint64_t)blockIdx.x * (RNG_TPB * RNG_UNROLL) + tid; vb < nvec;
-       vb += (uint64_t)gridDim.x * (RNG_TPB * RNG_UNROLL)) {
-    T pv[RNG_UNROLL][V], qv[RNG_UNROLL][V];
-#pragma unroll
-    for (int u = 0; u < RNG_UNROLL; ++u) {
-      const uint64_t vi = vb + (uint64_t)u * RNG_TPB;
-      if (vi < nvec) {
-        load_vec(prev, vi, pv[u]);
-        load_vec(curr, vi, qv[u]);
-      }
-    }
-#pragma unroll
-    for (int u = 0; u < RNG_UNROLL; ++u) {
-      const uint64_t vi = vb + (uint64_t)u * RNG_TPB;
-      if (vi < nvec) {
-#pragma unroll
-        for (int v = 0; v < V; ++v) {
-          double d;
-          if (ratio_of((double)pv[u][v], (double)qv[u][v], P.cap, d)) {
-            const unsigned long long k = order_key(d);
-            kmin = k < kmin ? k : kmin;
-            kmax = k > kmax ? k : kmax;
-          } else {
-            ninv += 1;
-          }
-        }
-      }
-    }
-  }
-  // scalar remainder (n not a multiple of V)
-  if (blockIdx.x == 0) {
-    const uint64_t j = nvec * V + tid;
-    if (j < P.n) {
-      double d;
-      if (ratio_of((double)prev[j], (double)curr[j], P.cap, d)) {
-        const unsigned long long k = order_key(d);
-        kmin = k < kmin ? k : kmin;
-        kmax = k > kmax ? k : kmax;
-      } else {
-        ninv += 1;
-      }
-    }
-  }
-
+// Block reduction of the running extremes and invalid count, added to the
+// job's control block.  Every thread of the block calls it.
+__device__ void range_flush(Ctl* ctl, unsigned long long& kmin, unsigned long long& kmax,
+                            unsigned long long& ninv) {
+  __shared__ unsigned long long smin[RNG_TPB / 64], smax[RNG_TPB / 64], sinv[RNG_TPB / 64];
   kmin = wave_min_u64(kmin);
   kmax = wave_max_u64(kmax);
   ninv = wave_sum_u64(ninv);
-  __shared__ unsigned long long smin[RNG_TPB / 64], smax[RNG_TPB / 64], sinv[RNG_TPB / 64];
-  const int w = tid / 64;
+  const int w = threadIdx.x / 64;
+  __syncthreads();
   if (lane_id() == 0) {
     smin[w] = kmin;
     smax[w] = kmax;
     sinv[w] = ninv;
   }
   __syncthreads();
-  if (tid == 0) {
+  if (threadIdx.x == 0) {
     for (int i = 1; i < RNG_TPB / 64; ++i) {
       kmin = smin[i] < kmin ? smin[i] : kmin;
       kmax = smax[i] > kmax ? smax[i] : kmax;
       ninv += sinv[i];
     }
-    if (kmin != ~0ull) atomicMin(&P.ctl->lo_key, kmin);
-    if (kmax != 0ull) atomicMax(&P.ctl->hi_key, kmax);
-    if (ninv) atomicAdd(&P.ctl->n_invalid, ninv);
+    if (kmin != ~0ull) atomicMin(&ctl->lo_key, kmin);
+    if (kmax != 0ull) atomicMax(&ctl->hi_key, kmax);
+    if (ninv) atomicAdd(&ctl->n_invalid, ninv);
   }
+  kmin = ~0ull;
+  kmax = 0ull;
+  ninv = 0ull;
+}
+
+// Streaming chunks [c_begin, c_end), block-strided; a chunk is chunk_vec
+// vectors of one job, and a job's last chunk also takes its scalar tail.
+template <typename T, typename S>
+__global__ void __launch_bounds__(RNG_TPB) k_range(S src, Geo g) {
+  constexpr int V = Traits<T>::V;
+  const int tid = threadIdx.x;
+  unsigned long long kmin = ~0ull, kmax = 0ull, ninv = 0ull;
+  ChunkCursor cu;
+  // the current job's parameters, loaded when the workgroup reaches it
+  Ctl* ctl = nullptr;
+  const T* prev = nullptr;
+  const T* curr = nullptr;
+  uint64_t n = 0, nvec = 0;
+  double cap = 0.0;
+  for (uint64_t c = g.c_begin + blockIdx.x; c < g.c_end; c += gridDim.x) {
+    if (cu.seek(g, c)) {
+      if (ctl) range_flush(ctl, kmin, kmax, ninv);
+      const CParams& P = src.job(cu.j);
+      ctl = P.ctl;
+      prev = static_cast<const T*>(P.prev);
+      curr = static_cast<const T*>(P.curr);
+      n = P.n;
+      nvec = n / V;
+      cap = P.cap;
+    }
+    const uint64_t v0 = (c - cu.first) * g.chunk_vec;
+    uint64_t v1 = v0 + g.chunk_vec;
+    v1 = v1 < nvec ? v1 : nvec;
+    for (uint64_t vb = v0 + tid; vb < v1; vb += RNG_TPB * RNG_UNROLL) {
+      T pv[RNG_UNROLL][V], qv[RNG_UNROLL][V];
+#pragma unroll
+      for (int u = 0; u < RNG_UNROLL; ++u) {
+        const uint64_t vi = vb + (uint64_t)u * RNG_TPB;
+        if (vi < v1) {
+          load_vec(prev, vi, pv[u]);
+          load_vec(curr, vi, qv[u]);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < RNG_UNROLL; ++u) {
+        const uint64_t vi = vb + (uint64_t)u * RNG_TPB;
+        if (vi < v1) {
+#pragma unroll
+          for (int v = 0; v < V; ++v) {
+            double d;
+            if (ratio_of((double)pv[u][v], (double)qv[u][v], cap, d)) {
+              const unsigned long long k = order_key(d);
+              kmin = k < kmin ? k : kmin;
+              kmax = k > kmax ? k : kmax;
+            } else {
+              ninv += 1;
+            }
+          }
+        }
+      }
+    }
+    if (v1 == nvec) {  // the job's last chunk: scalar remainder
+      const uint64_t jj = nvec * V + tid;
+      if (jj < n) {
+        double d;
+        if (ratio_of((double)prev[jj], (double)curr[jj], cap, d)) {
+          const unsigned long long k = order_key(d);
+          kmin = k < kmin ? k : kmin;
+          kmax = k > kmax ? k : kmax;
+        } else {
+          ninv += 1;
+        }
+      }
+    }
+  }
+  if (ctl) range_flush(ctl, kmin, kmax, ninv);
 }
 
 // =====================================================================
 // k_derive: lo, hi, M and the bin window
 // =====================================================================
-__global__ void k_derive(CParams P) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+template <typename S>
+__global__ void k_derive(S src, Geo g) {
+  if (threadIdx.x != 0) return;
+  const CParams& P = src.job(g.job_begin + blockIdx.x);
   Ctl* c = P.ctl;
   const unsigned long long n_valid = P.n - c->n_invalid;
   c->n_valid = n_valid;
@@ -184,93 +255,136 @@ __global__ void k_derive(CParams P) {
 constexpr int HIST_TPB = NK_HIST_TPB;
 constexpr int HIST_UNROLL = 2;
 
-// Count one element per lane: window bins with LDS atomics, other valid
-// points appended to the tail list (one global atomic per wave).
-__device__ __forceinline__ void hist_count(uint32_t* lds, bool valid, double m, double wbase_d,
-                                           double wlen_d, const CParams& P) {
+// Where a job's out-of-window points go: the tail list and its fill count.
+struct TailSink {
+  unsigned long long* count;
+  int64_t* list;
+  uint64_t cap;
+};
+
+// Count one element per lane: window bins with atomics on `win` (LDS or the
+// job's global window counts), other valid points appended to the tail list
+// (one global atomic per wave).
+__device__ __forceinline__ void hist_count(uint32_t* win, bool valid, double m, double wbase_d,
+                                           double wlen_d, const TailSink& ts) {
   const double w = m - wbase_d;  // exact: both are integers below 2^51
   const bool inwin = valid && w >= 0.0 && w < wlen_d;
 #if NK_HIST_HYBRID
-  lds_count(lds, inwin, inwin ? (unsigned)(int)w : 0u);
+  lds_count(win, inwin, inwin ? (unsigned)(int)w : 0u);
 #else
-  if (inwin) atomicAdd(&lds[(int)w], 1u);
+  if (inwin) atomicAdd(&win[(int)w], 1u);
 #endif
   const bool tail = valid && !inwin;
   const unsigned long long tm = __ballot(tail);
   if (tm) {
     const int leader = __ffsll((long long)tm) - 1;
     unsigned long long base = 0;
-    if (lane_id() == leader) base = atomicAdd(&P.ctl->tail_count, (unsigned long long)__popcll(tm));
+    if (lane_id() == leader) base = atomicAdd(ts.count, (unsigned long long)__popcll(tm));
     const unsigned lo32 = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)base, leader);
     const unsigned hi32 = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(base >> 32), leader);
     base = ((unsigned long long)hi32 << 32) | lo32;
     if (tail) {
       const unsigned long long pos = base + (unsigned long long)__popcll(tm & lanemask_lt());
-      if (pos < P.tail_cap) P.tail[pos] = (long long)m;
+      if (pos < ts.cap) ts.list[pos] = (long long)m;
     }
   }
 }
 
-template <typename T>
-__global__ void __launch_bounds__(HIST_TPB) k_hist(CParams P) {
+// LDSH: count window bins in an LDS copy flushed to the job's global counts
+// when the block moves to another job (or finishes); otherwise count
+// directly in the global counts (more atomic traffic, no LDS, higher
+// occupancy).  Same counts either way.
+template <typename T, typename S, bool LDSH>
+__global__ void __launch_bounds__(HIST_TPB) k_hist(S src, Geo g) {
   constexpr int V = Traits<T>::V;
-  __shared__ uint32_t lds[WIN];
-  const Ctl* c = P.ctl;
-  if (c->empty) return;
-  const double lo = c->lo;
-  const double wbase_d = (double)c->wbase;
-  const double wlen_d = (double)c->win_len;
-  const unsigned win_len = c->win_len;
-  const bool fast = P.fastbin != 0;
+  __shared__ uint32_t lds[LDSH ? WIN : 1];
   const int tid = threadIdx.x;
-  for (int i = tid; i < WIN; i += HIST_TPB) lds[i] = 0u;
-  __syncthreads();
-
-  const T* __restrict__ prev = static_cast<const T*>(P.prev);
-  const T* __restrict__ curr = static_cast<const T*>(P.curr);
-  const uint64_t nvec = P.n / V;
-  // With NK_HIST_REVERSE the sweep runs from the end of the arrays to the
-  // start: the range pass ended on the high addresses, which may still sit in
-  // the memory-side cache.
-  for (uint64_t vb = (uint64_t)blockIdx.x * (HIST_TPB * HIST_UNROLL) + tid; vb < nvec;
-       vb += (uint64_t)gridDim.x * (HIST_TPB * HIST_UNROLL)) {
-    T pv[HIST_UNROLL][V], qv[HIST_UNROLL][V];
+  if (LDSH) {
+    for (int i = tid; i < WIN; i += HIST_TPB) lds[i] = 0u;
+    __syncthreads();
+  }
+  ChunkCursor cu;
+  // The current job's parameters and window, loaded once when the workgroup
+  // reaches the job: inside a saturated stream a dependent load per chunk
+  // would stall every wave of the workgroup.
+  bool have = false, empty = true, fast = false;
+  double lo = 0.0, wbase_d = 0.0, wlen_d = 0.0, cap = 0.0, twoE = 1.0, inv2E = 1.0;
+  unsigned wl = 0;
+  uint32_t* gwin = nullptr;
+  const T* prev = nullptr;
+  const T* curr = nullptr;
+  uint64_t n = 0, nvec = 0;
+  TailSink ts{nullptr, nullptr, 0};
+  auto flush = [&]() {  // LDS window counts to the job's global counts
+    if (!LDSH) return;
+    __syncthreads();
+    for (unsigned i = tid; i < (unsigned)WIN; i += HIST_TPB) {
+      const uint32_t v = lds[i];
+      if (v && i < wl) atomicAdd(&gwin[i], v);
+      lds[i] = 0u;
+    }
+    __syncthreads();
+  };
+  for (uint64_t c = g.c_begin + blockIdx.x; c < g.c_end; c += gridDim.x) {
+    if (cu.seek(g, c)) {
+      if (have) flush();
+      have = true;
+      const CParams& P = src.job(cu.j);
+      const Ctl* ctl = P.ctl;
+      empty = ctl->empty != 0;
+      wl = empty ? 0u : ctl->win_len;
+      lo = ctl->lo;
+      wbase_d = (double)ctl->wbase;
+      wlen_d = (double)wl;
+      gwin = P.gwin;
+      prev = static_cast<const T*>(P.prev);
+      curr = static_cast<const T*>(P.curr);
+      n = P.n;
+      nvec = n / V;
+      cap = P.cap;
+      twoE = P.twoE;
+      inv2E = P.inv2E;
+      fast = P.fastbin != 0;
+      ts = TailSink{&P.ctl->tail_count, P.tail, P.tail_cap};
+    }
+    if (empty) continue;  // uniform: the whole chunk belongs to this job
+    uint32_t* win = LDSH ? lds : gwin;
+    const uint64_t v0 = (c - cu.first) * g.chunk_vec;
+    uint64_t v1 = v0 + g.chunk_vec;
+    v1 = v1 < nvec ? v1 : nvec;
+    for (uint64_t vb = v0 + tid; vb < v1; vb += HIST_TPB * HIST_UNROLL) {
+      T pv[HIST_UNROLL][V], qv[HIST_UNROLL][V];
 #pragma unroll
-    for (int u = 0; u < HIST_UNROLL; ++u) {
-      const uint64_t vi = vb + (uint64_t)u * HIST_TPB;
-      if (vi < nvec) {
-        const uint64_t vv = NK_HIST_REVERSE ? nvec - 1 - vi : vi;
-        load_vec(prev, vv, pv[u]);
-        load_vec(curr, vv, qv[u]);
+      for (int u = 0; u < HIST_UNROLL; ++u) {
+        const uint64_t vi = vb + (uint64_t)u * HIST_TPB;
+        if (vi < v1) {
+          load_vec(prev, vi, pv[u]);
+          load_vec(curr, vi, qv[u]);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < HIST_UNROLL; ++u) {
+        const uint64_t vi = vb + (uint64_t)u * HIST_TPB;
+        const bool inr = vi < v1;
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+          double d = 0.0;
+          const bool valid = inr && ratio_of((double)pv[u][v], (double)qv[u][v], cap, d);
+          const double m = valid ? bin_floor(d - lo, twoE, inv2E, fast) : 0.0;
+          hist_count(win, valid, m, wbase_d, wlen_d, ts);
+        }
       }
     }
-#pragma unroll
-    for (int u = 0; u < HIST_UNROLL; ++u) {
-      const uint64_t vi = vb + (uint64_t)u * HIST_TPB;
-      const bool inr = vi < nvec;
-#pragma unroll
-      for (int v = 0; v < V; ++v) {
-        double d = 0.0;
-        const bool valid =
-            inr && ratio_of((double)pv[u][v], (double)qv[u][v], P.cap, d);
-        const double m = valid ? bin_floor(d - lo, P.twoE, P.inv2E, fast) : 0.0;
-        hist_count(lds, valid, m, wbase_d, wlen_d, P);
-      }
+    if (v1 == nvec) {  // the job's last chunk: scalar remainder
+      const uint64_t jj = nvec * V + tid;
+      double d = 0.0;
+      bool valid = false;
+      if (jj < n) valid = ratio_of((double)prev[jj], (double)curr[jj], cap, d);
+      const double m = valid ? bin_floor(d - lo, twoE, inv2E, fast) : 0.0;
+      hist_count(win, valid, m, wbase_d, wlen_d, ts);
     }
   }
-  if (blockIdx.x == 0) {
-    const uint64_t j = nvec * V + tid;
-    double d = 0.0;
-    bool valid = false;
-    if (j < P.n) valid = ratio_of((double)prev[j], (double)curr[j], P.cap, d);
-    const double m = valid ? bin_floor(d - lo, P.twoE, P.inv2E, fast) : 0.0;
-    hist_count(lds, valid, m, wbase_d, wlen_d, P);
-  }
-  __syncthreads();
-  for (unsigned i = tid; i < win_len; i += HIST_TPB) {
-    const uint32_t v = lds[i];
-    if (v) atomicAdd(&P.gwin[i], v);
-  }
+  if (have) flush();
 }
 
 // =====================================================================
@@ -287,7 +401,9 @@ __device__ __forceinline__ unsigned long long next_pow2(unsigned long long x) {
   return p;
 }
 
-__global__ void k_hclear(CParams P) {
+template <typename S>
+__global__ void k_hclear(S src, Geo g) {
+  const CParams& P = src.job(g.job_begin + blockIdx.y);
   Ctl* c = P.ctl;
   const unsigned long long T = c->tail_count;
   const unsigned long long used = T < P.tail_cap ? T : P.tail_cap;
@@ -307,7 +423,9 @@ __global__ void k_hclear(CParams P) {
   }
 }
 
-__global__ void k_hinsert(CParams P) {
+template <typename S>
+__global__ void k_hinsert(S src, Geo g) {
+  const CParams& P = src.job(g.job_begin + blockIdx.y);
   const Ctl* c = P.ctl;
   const unsigned long long used = c->tail_used;
   const unsigned long long mask = c->H - 1;
@@ -533,8 +651,9 @@ __device__ void sel_threshold(SelShared& S, unsigned long long mx, unsigned long
   *cut_out = r >= ties ? (long long)tmax : sel_rth_tie(S, tau, r, tmin, tmax, visit);
 }
 
-template <typename T>
-__global__ void __launch_bounds__(SEL_TPB) k_select(CParams P) {
+template <typename T, typename SRC>
+__global__ void __launch_bounds__(SEL_TPB) k_select(SRC src, Geo g) {
+  const CParams& P = src.job(g.job_begin + blockIdx.x);
   __shared__ SelShared S;
   Ctl* c = P.ctl;
   const int tid = threadIdx.x;
@@ -679,8 +798,9 @@ __global__ void __launch_bounds__(SEL_TPB) k_select(CParams P) {
 // =====================================================================
 constexpr int TR_TPB = 256;
 
-template <typename T>
-__global__ void __launch_bounds__(TR_TPB) k_tailrank(CParams P) {
+template <typename T, typename S>
+__global__ void __launch_bounds__(TR_TPB) k_tailrank(S src, Geo g) {
+  const CParams& P = src.job(g.job_begin + blockIdx.y);
   __shared__ long long chunk[TR_TPB];
   const Ctl* c = P.ctl;
   const unsigned t = c->nsel_tail;
@@ -726,8 +846,8 @@ __global__ void __launch_bounds__(TR_TPB) k_tailrank(CParams P) {
 // packed stream -- or 0 for any B.
 constexpr int ENC_CTAB = 2048;  // LDS centre table when 2^B <= this
 
-template <typename T, typename LT, int PACK>
-__global__ void __launch_bounds__(UNIT_TPB) k_encode(CParams P) {
+template <typename T, typename LT, int PACK, typename S>
+__global__ void __launch_bounds__(UNIT_TPB) k_encode(S src, Geo g) {
   constexpr int V = Traits<T>::V;
   constexpr int R = ENC_ROUNDS;
   constexpr int WT = R * 64 * V;  // elements of a wave tile
@@ -738,6 +858,10 @@ __global__ void __launch_bounds__(UNIT_TPB) k_encode(CParams P) {
   __shared__ double s_ctab[NCTAB];
   __shared__ IT s_idx[NWAVE][WT];
 
+  // the 4 units of a workgroup belong to one job (jobs own multiples of 4)
+  const uint32_t ublk = g.u_begin + blockIdx.x * NWAVE;
+  const uint32_t jb = g.unit0 ? find_job(g.unit0, g.job_begin, g.job_end, ublk) : g.job_begin;
+  const CParams P = src.job(jb);  // a copy: stores below cannot alias it
   const Ctl* c = P.ctl;
   const int tid = threadIdx.x;
   const int wave = tid / 64;
@@ -768,7 +892,7 @@ __global__ void __launch_bounds__(UNIT_TPB) k_encode(CParams P) {
   IT* idx = s_idx[wave];
   const uint64_t nvec = P.n / V;
   const uint32_t tile_words = (uint32_t)(WT * B / 32);
-  const uint32_t unit = blockIdx.x * NWAVE + wave;
+  const uint32_t unit = ublk + wave - (g.unit0 ? g.unit0[jb] : 0u);  // unit within the job
   const uint64_t tb = (uint64_t)unit * P.tiles_per_unit;
   uint64_t te = tb + P.tiles_per_unit;
   te = te < P.n_tiles ? te : P.n_tiles;
@@ -946,7 +1070,9 @@ __global__ void __launch_bounds__(UNIT_TPB) k_encode(CParams P) {
 // =====================================================================
 // k_uscan: unit counts -> exclusive unit offsets (one workgroup)
 // =====================================================================
-__global__ void __launch_bounds__(USCAN_TPB) k_uscan(CParams P) {
+template <typename S>
+__global__ void __launch_bounds__(USCAN_TPB) k_uscan(S src, Geo g) {
+  const CParams& P = src.job(g.job_begin + blockIdx.x);
   const unsigned long long total = unit_scan(P.unit_cnt, P.n_units);
   if (threadIdx.x == 0) P.ctl->n_inc = (unsigned)total;
 }
@@ -956,12 +1082,16 @@ __global__ void __launch_bounds__(USCAN_TPB) k_uscan(CParams P) {
 // =====================================================================
 __device__ void write_header(const CParams& P);
 
-template <typename T>
-__global__ void __launch_bounds__(UNIT_TPB) k_gather(CParams P) {
+template <typename T, typename S>
+__global__ void __launch_bounds__(UNIT_TPB) k_gather(S src, Geo g) {
   constexpr int V = Traits<T>::V;
   constexpr int WT = ENC_ROUNDS * 64 * V;
-  if (blockIdx.x == 0 && threadIdx.x == 0) write_header(P);
-  const uint32_t unit = blockIdx.x * (UNIT_TPB / 64) + threadIdx.x / 64;
+  const uint32_t u = g.u_begin + blockIdx.x * (UNIT_TPB / 64) + threadIdx.x / 64;
+  if (u >= g.u_end) return;
+  const uint32_t jb = g.unit0 ? find_job(g.unit0, g.job_begin, g.job_end, u) : g.job_begin;
+  const CParams& P = src.job(jb);
+  const uint32_t unit = u - (g.unit0 ? g.unit0[jb] : 0u);
+  if (unit == 0 && threadIdx.x % 64 == 0) write_header(P);
   if (unit >= P.n_units) return;
   const int lane = lane_id();
   const uint64_t e0 = (uint64_t)unit * P.tiles_per_unit * WT;
@@ -1020,51 +1150,160 @@ __device__ void write_header(const CParams& P) {
     if (e_ != hipSuccess) return e_;                                             \
   } while (0)
 
-template <typename T>
-static hipError_t launch_compress_t(CParams P, hipStream_t s) {
-  const Geometry g = geometry();
-  // encoder specialisation: LUT element type and packing by index width
-  void (*enc)(CParams) = P.B == 8    ? k_encode<T, uint8_t, 8>
-                         : P.B == 16 ? k_encode<T, uint16_t, 16>
-                         : P.B < 8   ? k_encode<T, uint8_t, 0>
-                                     : k_encode<T, uint16_t, 0>;
-  {  // as many encoder units as can be resident at once (4 per workgroup)
-    int occ = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, enc, UNIT_TPB, 0) != hipSuccess ||
-        occ < 1)
-      occ = 1;
-    P.n_units = range_units(P.n_tiles, g.cus * occ * 4);
-    P.tiles_per_unit = (P.n_tiles + P.n_units - 1) / P.n_units;
+// Kernel of an encoder specialisation.
+template <typename T, typename S>
+static void (*encoder_kernel(int cls))(S, Geo) {
+  switch (cls) {
+    case 0: return k_encode<T, uint8_t, 0, S>;
+    case 1: return k_encode<T, uint8_t, 8, S>;
+    case 2: return k_encode<T, uint16_t, 0, S>;
+    default: return k_encode<T, uint16_t, 16, S>;
   }
-  constexpr int V = Traits<T>::V;
-  const uint64_t nvec = P.n / V;
-  uint64_t rng_blocks = (nvec + RNG_TPB * RNG_UNROLL - 1) / (RNG_TPB * RNG_UNROLL);
-  const uint64_t rng_cap = (uint64_t)g.cus * 8;
-  if (rng_blocks > rng_cap) rng_blocks = rng_cap;
-  if (rng_blocks < 8) rng_blocks = 8;  // also clears WIN window counts
-  uint64_t hist_blocks = (nvec + HIST_TPB * HIST_UNROLL - 1) / (HIST_TPB * HIST_UNROLL);
-  const uint64_t hist_cap = (uint64_t)g.cus * 2;
-  if (hist_blocks > hist_cap) hist_blocks = hist_cap;
-  if (hist_blocks < 1) hist_blocks = 1;
-  const uint64_t aux_blocks = (uint64_t)g.cus * 2;
+}
 
-  NK_LAUNCH(KK_INIT, k_init, 1, 64, P.ctl);
-  NK_LAUNCH(KK_RANGE, k_range<T>, rng_blocks, RNG_TPB, P);
-  NK_LAUNCH(KK_DERIVE, k_derive, 1, 64, P);
-  NK_LAUNCH(KK_HIST, k_hist<T>, hist_blocks, HIST_TPB, P);
-  NK_LAUNCH(KK_HCLEAR, k_hclear, aux_blocks, 256, P);
-  NK_LAUNCH(KK_HINSERT, k_hinsert, aux_blocks, 256, P);
-  NK_LAUNCH(KK_SELECT, k_select<T>, 1, SEL_TPB, P);
-  NK_LAUNCH(KK_TAILRANK, k_tailrank<T>, 256, TR_TPB, P);
-  NK_LAUNCH(KK_ENCODE, enc, P.n_units / 4, UNIT_TPB, P);
-  NK_LAUNCH(KK_USCAN, k_uscan, 1, USCAN_TPB, P);
-  NK_LAUNCH(KK_GATHER, k_gather<T>, P.n_units / 4, UNIT_TPB, P);
+template <typename S>
+static int encoder_occupancy_t(int dtype, int cls) {
+  void (*k)(S, Geo) = dtype == NUMARCK_F32 ? encoder_kernel<float, S>(cls)
+                                           : encoder_kernel<double, S>(cls);
+  int occ = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k, UNIT_TPB, 0) != hipSuccess || occ < 1)
+    occ = 1;
+  return occ;
+}
+
+int encoder_occupancy(int dtype, int cls, bool table) {
+  return table ? encoder_occupancy_t<JobTable>(dtype, cls) : encoder_occupancy_t<OneJob>(dtype, cls);
+}
+
+Tuning default_tuning() { return Tuning{8u, 2u, 1u, 4096u, 100u}; }
+
+static Geo group_geo(const Geo& base, const JobGroup& jg) {
+  Geo g = base;
+  g.job_begin = jg.job_begin;
+  g.job_end = jg.job_end;
+  g.c_begin = jg.c_begin;
+  g.c_end = jg.c_end;
+  g.u_begin = jg.u_begin;
+  g.u_end = jg.u_end;
+  return g;
+}
+
+static uint64_t clamp_blocks(uint64_t want, uint64_t cap) {
+  if (want > cap) want = cap;
+  return want < 1 ? 1 : want;
+}
+
+// The compression chain over all jobs of `src`: one launch per pass and per
+// element type (per index-width class for the encoder), whatever the number
+// of jobs.
+template <typename S>
+static hipError_t run_chain(S src, const Geo& base, uint32_t njobs, const JobGroup* dg,
+                            uint32_t ndg, const JobGroup* eg, uint32_t neg, const Tuning& tn,
+                            hipStream_t s) {
+  const Geometry G = geometry();
+  Geo all = base;
+  all.job_begin = 0;
+  all.job_end = njobs;
+  const uint64_t aux = njobs == 1 ? (uint64_t)G.cus * 2
+                                  : clamp_blocks((uint64_t)G.cus * 2 / njobs, 64) < 8
+                                        ? 8
+                                        : clamp_blocks((uint64_t)G.cus * 2 / njobs, 64);
+  NK_LAUNCH(KK_INIT, k_init<S>, njobs, 256, src, all);
+  for (uint32_t i = 0; i < ndg; ++i) {
+    const Geo g = group_geo(base, dg[i]);
+    const uint64_t chunks = g.c_end - g.c_begin;
+    if (!chunks) continue;
+    const uint64_t blocks = clamp_blocks(chunks, (uint64_t)G.cus * tn.range_blocks_per_cu);
+    if (dg[i].dtype == NUMARCK_F32)
+      NK_LAUNCH(KK_RANGE, (k_range<float, S>), blocks, RNG_TPB, src, g);
+    else
+      NK_LAUNCH(KK_RANGE, (k_range<double, S>), blocks, RNG_TPB, src, g);
+  }
+  NK_LAUNCH(KK_DERIVE, k_derive<S>, njobs, 64, src, all);
+  for (uint32_t i = 0; i < ndg; ++i) {
+    const Geo g = group_geo(base, dg[i]);
+    const uint64_t chunks = g.c_end - g.c_begin;
+    if (!chunks) continue;
+    const uint64_t blocks = clamp_blocks(chunks, (uint64_t)G.cus * tn.hist_blocks_per_cu);
+    const bool f32 = dg[i].dtype == NUMARCK_F32;
+    if (tn.hist_lds) {
+      if (f32) NK_LAUNCH(KK_HIST, (k_hist<float, S, true>), blocks, HIST_TPB, src, g);
+      else NK_LAUNCH(KK_HIST, (k_hist<double, S, true>), blocks, HIST_TPB, src, g);
+    } else {
+      if (f32) NK_LAUNCH(KK_HIST, (k_hist<float, S, false>), blocks, HIST_TPB, src, g);
+      else NK_LAUNCH(KK_HIST, (k_hist<double, S, false>), blocks, HIST_TPB, src, g);
+    }
+  }
+  NK_LAUNCH(KK_HCLEAR, k_hclear<S>, dim3((unsigned)aux, njobs), 256, src, all);
+  NK_LAUNCH(KK_HINSERT, k_hinsert<S>, dim3((unsigned)aux, njobs), 256, src, all);
+  for (uint32_t i = 0; i < ndg; ++i) {
+    const Geo g = group_geo(base, dg[i]);
+    const uint32_t nj = g.job_end - g.job_begin;
+    if (dg[i].dtype == NUMARCK_F32) {
+      NK_LAUNCH(KK_SELECT, (k_select<float, S>), nj, SEL_TPB, src, g);
+      NK_LAUNCH(KK_TAILRANK, (k_tailrank<float, S>), dim3(64, nj), TR_TPB, src, g);
+    } else {
+      NK_LAUNCH(KK_SELECT, (k_select<double, S>), nj, SEL_TPB, src, g);
+      NK_LAUNCH(KK_TAILRANK, (k_tailrank<double, S>), dim3(64, nj), TR_TPB, src, g);
+    }
+  }
+  for (uint32_t i = 0; i < neg; ++i) {
+    const Geo g = group_geo(base, eg[i]);
+    const uint32_t blocks = (g.u_end - g.u_begin) / 4;
+    if (!blocks) continue;
+    void (*k)(S, Geo) = eg[i].dtype == NUMARCK_F32 ? encoder_kernel<float, S>(eg[i].cls)
+                                                   : encoder_kernel<double, S>(eg[i].cls);
+    NK_LAUNCH(KK_ENCODE, k, blocks, UNIT_TPB, src, g);
+  }
+  NK_LAUNCH(KK_USCAN, k_uscan<S>, njobs, USCAN_TPB, src, all);
+  for (uint32_t i = 0; i < ndg; ++i) {
+    const Geo g = group_geo(base, dg[i]);
+    const uint32_t blocks = (g.u_end - g.u_begin) / 4;
+    if (!blocks) continue;
+    if (dg[i].dtype == NUMARCK_F32)
+      NK_LAUNCH(KK_GATHER, (k_gather<float, S>), blocks, UNIT_TPB, src, g);
+    else
+      NK_LAUNCH(KK_GATHER, (k_gather<double, S>), blocks, UNIT_TPB, src, g);
+  }
   return hipSuccess;
 }
 
-hipError_t launch_compress(const CParams& P, hipStream_t s) {
-  return P.dtype == NUMARCK_F32 ? launch_compress_t<float>(P, s)
-                                : launch_compress_t<double>(P, s);
+uint64_t stream_chunks(uint64_t n, int dtype, uint32_t chunk_vec) {
+  if (n == 0) return 0;
+  const uint64_t nvec = n / (dtype == NUMARCK_F32 ? 4 : 2);
+  const uint64_t c = (nvec + chunk_vec - 1) / chunk_vec;
+  return c < 1 ? 1 : c;
+}
+
+hipError_t launch_compress(const CParams& P0, const Tuning& tn, hipStream_t s) {
+  const Geometry G = geometry();
+  CParams P = P0;
+  const int cls = enc_class(P.B);
+  const int occ = encoder_occupancy(P.dtype, cls, false);
+  const uint64_t resident = (uint64_t)G.cus * occ * 4 * tn.unit_pct / 100;
+  P.n_units = range_units(P.n_tiles, (int)(resident < 4 ? 4 : resident));
+  P.tiles_per_unit = (P.n_tiles + P.n_units - 1) / P.n_units;
+  Geo base{};
+  base.chunk_vec = tn.chunk_vec;
+  JobGroup grp{};
+  grp.dtype = P.dtype;
+  grp.cls = cls;
+  grp.job_begin = 0;
+  grp.job_end = 1;
+  grp.c_begin = 0;
+  grp.c_end = stream_chunks(P.n, P.dtype, tn.chunk_vec);
+  grp.u_begin = 0;
+  grp.u_end = P.n_units;
+  return run_chain(OneJob{P}, base, 1, &grp, 1, &grp, 1, tn, s);
+}
+
+hipError_t launch_compress_batch(const BatchLaunch& b, hipStream_t s) {
+  Geo base{};
+  base.chunk0 = b.chunk0_dev;
+  base.unit0 = b.unit0_dev;
+  base.chunk_vec = b.tune.chunk_vec;
+  return run_chain(JobTable{b.jobs_dev}, base, b.njobs, b.dgroups, b.n_dgroups, b.egroups,
+                   b.n_egroups, b.tune, s);
 }
 
 // =====================================================================

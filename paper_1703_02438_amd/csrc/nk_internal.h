@@ -158,6 +158,39 @@ struct Geometry {
 };
 Geometry geometry();
 
+// Where a launch's work items come from: for a batch, the device prefix
+// arrays map a streaming chunk or an encoder unit to its job; for one job
+// they are null and everything belongs to job_begin.
+struct Geo {
+  const uint64_t* chunk0;  // first streaming chunk of each job, then the total
+  const uint32_t* unit0;   // first encoder unit of each job, then the total
+  uint32_t job_begin, job_end;
+  uint64_t c_begin, c_end;  // streaming chunks of this launch
+  uint32_t u_begin, u_end;  // encoder units of this launch
+  uint32_t chunk_vec;       // 16-byte vectors per streaming chunk
+};
+
+// Launch parameters a tuner may change (none changes any output).
+struct Tuning {
+  uint32_t range_blocks_per_cu;  // k_range grid = this x CUs (capped by chunks)
+  uint32_t hist_blocks_per_cu;   // k_hist grid
+  uint32_t hist_lds;             // 1: LDS window counts, 0: global window counts
+  uint32_t chunk_vec;            // 16-byte vectors per streaming chunk
+  uint32_t unit_pct;             // encoder units, % of the resident capacity
+};
+Tuning default_tuning();
+
+// A contiguous group of jobs of one element type (and, for the encoder, one
+// index-width class: 0 = B < 8, 1 = B == 8, 2 = 8 < B < 16, 3 = B == 16).
+struct JobGroup {
+  int dtype;
+  int cls;
+  uint32_t job_begin, job_end;
+  uint64_t c_begin, c_end;
+  uint32_t u_begin, u_end;
+};
+inline int enc_class(uint32_t B) { return B < 8 ? 0 : B == 8 ? 1 : B < 16 ? 2 : 3; }
+
 // Elements of one encoder / decoder wave tile for an element size (16-byte vectors).
 inline uint64_t enc_wave_tile(uint64_t elem_bytes) { return ENC_ROUNDS * 64 * (16 / elem_bytes); }
 inline uint64_t dec_wave_tile(uint64_t elem_bytes) { return DEC_ROUNDS * 64 * (16 / elem_bytes); }
@@ -183,7 +216,25 @@ void timing_end(KernelKind k, hipStream_t s);
 
 // Launch wrappers (compress_kernels.hip / decompress_kernels.hip).  Each
 // returns the hipError_t of the launch.
-hipError_t launch_compress(const CParams& p, hipStream_t s);
+hipError_t launch_compress(const CParams& p, const Tuning& tn, hipStream_t s);
+// A batch: the job table and prefix arrays live in device memory; groups are
+// contiguous runs of jobs sorted by (dtype, class).
+struct BatchLaunch {
+  const CParams* jobs_dev;
+  const uint64_t* chunk0_dev;
+  const uint32_t* unit0_dev;
+  uint32_t njobs;
+  const JobGroup* dgroups;  // by dtype
+  uint32_t n_dgroups;
+  const JobGroup* egroups;  // by (dtype, class)
+  uint32_t n_egroups;
+  Tuning tune;
+};
+hipError_t launch_compress_batch(const BatchLaunch& b, hipStream_t s);
+// Resident workgroups per CU of one encoder specialisation (for sizing units).
+int encoder_occupancy(int dtype, int cls, bool table);
+// Streaming chunks of a job (0 for an empty job, at least 1 otherwise).
+uint64_t stream_chunks(uint64_t n, int dtype, uint32_t chunk_vec);
 hipError_t launch_decompress(const DParams& p, hipStream_t s);
 hipError_t launch_histogram_export(Ctl* ctl, const uint32_t* gwin, const uint32_t* hslot,
                                    const uint32_t* hcnt, const int64_t* tail, int64_t* ids,

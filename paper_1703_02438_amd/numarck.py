@@ -50,7 +50,27 @@ class NumarckOut(ctypes.Structure):
     ]
 
 
+class NumarckTuning(ctypes.Structure):
+    _fields_ = [
+        ("range_blocks_per_cu", ctypes.c_uint32), ("hist_blocks_per_cu", ctypes.c_uint32),
+        ("hist_lds", ctypes.c_uint32), ("chunk_vec", ctypes.c_uint32),
+        ("unit_pct", ctypes.c_uint32),
+    ]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class NumarckJob(ctypes.Structure):
+    _fields_ = [
+        ("prev", ctypes.c_void_p), ("curr", ctypes.c_void_p), ("n", ctypes.c_uint64),
+        ("dtype", ctypes.c_int), ("E", ctypes.c_double), ("B", ctypes.c_uint32),
+        ("block_bytes", ctypes.c_uint64), ("out", NumarckOut),
+    ]
+
+
 HEADER_BYTES = ctypes.sizeof(NumarckHeader)
+MAX_JOBS = 65535
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
@@ -86,6 +106,26 @@ numarck_decompress_range = _bind("numarck_decompress_range", _i,
                                   _u64, _vp, _vp, _vp, _sz, _vp])
 numarck_histogram_export = _bind("numarck_histogram_export", _i,
                                  [_vp, _sz, _u64, _i, _vp, _vp, _u64, _vp, _vp])
+numarck_tuning_default = _bind("numarck_tuning_default", None, [ctypes.POINTER(NumarckTuning)])
+numarck_compress_tuned = _bind("numarck_compress_tuned", _i,
+                               [_vp, _vp, _u64, _i, _d, _u32, _u64, ctypes.POINTER(NumarckOut),
+                                _vp, _sz, ctypes.POINTER(NumarckTuning), _vp])
+numarck_autotune = _bind("numarck_autotune", _i,
+                         [_vp, _vp, _u64, _i, _d, _u32, _u64, ctypes.POINTER(NumarckOut), _vp,
+                          _sz, _u32, _vp, ctypes.POINTER(NumarckTuning)])
+numarck_tuning_save = _bind("numarck_tuning_save", _i, [ctypes.c_char_p])
+numarck_tuning_load = _bind("numarck_tuning_load", _i, [ctypes.c_char_p])
+numarck_batch_workspace_bytes = _bind("numarck_batch_workspace_bytes", _sz,
+                                      [ctypes.POINTER(NumarckJob), _u32])
+numarck_plan_create = _bind("numarck_plan_create", _i,
+                            [ctypes.POINTER(NumarckJob), _u32, ctypes.POINTER(NumarckTuning), _vp,
+                             _sz, _vp, ctypes.POINTER(_vp)])
+numarck_plan_run = _bind("numarck_plan_run", _i, [_vp, _vp])
+numarck_plan_capture = _bind("numarck_plan_capture", _i, [_vp, _vp])
+numarck_plan_replay = _bind("numarck_plan_replay", _i, [_vp, _vp])
+numarck_plan_destroy = _bind("numarck_plan_destroy", None, [_vp])
+numarck_compress_batch = _bind("numarck_compress_batch", _i,
+                               [ctypes.POINTER(NumarckJob), _u32, _vp, _sz, _vp])
 numarck_status_str = _bind("numarck_status_str", ctypes.c_char_p, [_i])
 numarck_last_error = _bind("numarck_last_error", ctypes.c_char_p, [])
 numarck_timing_enable = _bind("numarck_timing_enable", None, [_i])
@@ -142,7 +182,7 @@ class Compressed:
     recon: torch.Tensor | None
     bin_ids: torch.Tensor | None
     hdr: torch.Tensor
-    ws: torch.Tensor
+    ws: torch.Tensor | None  # the workspace of a plain compression (histogram export)
     n: int
     dtype: torch.dtype
     _host: NumarckHeader | None = None
@@ -177,7 +217,7 @@ def out_struct(o: dict) -> NumarckOut:
 
 def compress(prev: torch.Tensor, curr: torch.Tensor, E: float, B: int, block_bytes: int = 0,
              recon: bool = False, bin_ids: bool = False, ws: torch.Tensor | None = None,
-             outputs: dict | None = None, stream=None) -> Compressed:
+             outputs: dict | None = None, stream=None, _tune=None) -> Compressed:
     """Compress `curr` against `prev` (1-D contiguous float32/float64 device tensors)."""
     if prev.dtype != curr.dtype or prev.numel() != curr.numel():
         raise ValueError("prev and curr must have the same dtype and size")
@@ -192,11 +232,141 @@ def compress(prev: torch.Tensor, curr: torch.Tensor, E: float, B: int, block_byt
     if ws is None:
         ws = torch.empty(numarck_workspace_bytes(n, dt, B), dtype=torch.uint8, device=prev.device)
     out = out_struct(o)
-    st = numarck_compress(_ptr(prev), _ptr(curr), n, dt, float(E), int(B), int(block_bytes),
-                          ctypes.byref(out), _ptr(ws), ws.numel(), _stream(stream))
+    if _tune is None:
+        st = numarck_compress(_ptr(prev), _ptr(curr), n, dt, float(E), int(B), int(block_bytes),
+                              ctypes.byref(out), _ptr(ws), ws.numel(), _stream(stream))
+    else:
+        st = numarck_compress_tuned(_ptr(prev), _ptr(curr), n, dt, float(E), int(B),
+                                    int(block_bytes), ctypes.byref(out), _ptr(ws), ws.numel(),
+                                    ctypes.byref(_tune) if _tune is not False else None,
+                                    _stream(stream))
     _check(st, "numarck_compress")
     return Compressed(o["packed"], o["centers"], o["incomp"], o["block_inc_off"], o["recon"],
                       o["bin_ids"], o["hdr"], ws, n, prev.dtype)
+
+
+def default_tuning() -> NumarckTuning:
+    t = NumarckTuning()
+    numarck_tuning_default(ctypes.byref(t))
+    return t
+
+
+def compress_tuned(prev: torch.Tensor, curr: torch.Tensor, E: float, B: int,
+                   tune: NumarckTuning | None, block_bytes: int = 0, ws: torch.Tensor | None = None,
+                   outputs: dict | None = None, stream=None) -> Compressed:
+    """:func:`compress` with explicit launch tuning (None: the recorded one)."""
+    return compress(prev, curr, E, B, block_bytes, ws=ws, outputs=outputs, stream=stream,
+                    _tune=tune if tune is not None else False)
+
+
+def autotune(prev: torch.Tensor, curr: torch.Tensor, E: float, B: int, block_bytes: int = 0,
+             reps: int = 3, stream=None) -> NumarckTuning:
+    """Measure launch tunings on one compression; records and returns the fastest."""
+    prev, curr = prev.reshape(-1), curr.reshape(-1)
+    n, dt = prev.numel(), dtype_code(prev.dtype)
+    o = alloc_outputs(n, prev.dtype, B, block_bytes, device=prev.device)
+    ws = torch.empty(numarck_workspace_bytes(n, dt, B), dtype=torch.uint8, device=prev.device)
+    out = out_struct(o)
+    best = NumarckTuning()
+    st = numarck_autotune(_ptr(prev), _ptr(curr), n, dt, float(E), int(B), int(block_bytes),
+                          ctypes.byref(out), _ptr(ws), ws.numel(), int(reps), _stream(stream),
+                          ctypes.byref(best))
+    _check(st, "numarck_autotune")
+    return best
+
+
+@dataclass
+class BatchJob:
+    """One compression of a batch: curr against prev with its own E, B and block size."""
+    prev: torch.Tensor
+    curr: torch.Tensor
+    E: float
+    B: int
+    block_bytes: int = 0
+
+
+class Plan:
+    """A batch plan (numarck_plan_*): the jobs' outputs are allocated here (or
+    passed in), the descriptors are uploaded once; :meth:`run` launches the
+    chain, :meth:`capture` / :meth:`replay` use a HIP graph of it."""
+
+    def __init__(self, jobs: list[BatchJob], recon: bool = False, bin_ids: bool = False,
+                 outputs: list[dict] | None = None, tune: NumarckTuning | None = None,
+                 stream=None):
+        if not jobs:
+            raise ValueError("empty batch")
+        self.jobs = []
+        self.outputs = []
+        arr = (NumarckJob * len(jobs))()
+        for i, j in enumerate(jobs):
+            p, q = j.prev.reshape(-1), j.curr.reshape(-1)
+            if p.dtype != q.dtype or p.numel() != q.numel() or not (p.is_cuda and q.is_cuda):
+                raise ValueError(f"job {i}: prev and curr must be device tensors of one dtype and size")
+            o = outputs[i] if outputs is not None else alloc_outputs(
+                p.numel(), p.dtype, j.B, j.block_bytes, recon, bin_ids, p.device)
+            arr[i] = NumarckJob(_ptr(p), _ptr(q), p.numel(), dtype_code(p.dtype), float(j.E),
+                                int(j.B), int(j.block_bytes), out_struct(o))
+            self.jobs.append((p, q, j))
+            self.outputs.append(o)
+        self._arr = arr
+        dev = jobs[0].prev.device
+        self.ws = torch.empty(max(numarck_batch_workspace_bytes(arr, len(jobs)), 1),
+                              dtype=torch.uint8, device=dev)
+        h = _vp()
+        st = numarck_plan_create(arr, len(jobs), ctypes.byref(tune) if tune is not None else None,
+                                 _ptr(self.ws), self.ws.numel(), _stream(stream), ctypes.byref(h))
+        _check(st, "numarck_plan_create")
+        self._h = h
+
+    def results(self) -> list[Compressed]:
+        return [Compressed(o["packed"], o["centers"], o["incomp"], o["block_inc_off"],
+                           o["recon"], o["bin_ids"], o["hdr"], None, p.numel(), p.dtype)
+                for (p, _, _), o in zip(self.jobs, self.outputs)]
+
+    def run(self, stream=None) -> list[Compressed]:
+        _check(numarck_plan_run(self._h, _stream(stream)), "numarck_plan_run")
+        return self.results()
+
+    def capture(self, stream):
+        _check(numarck_plan_capture(self._h, _stream(stream)), "numarck_plan_capture")
+
+    def replay(self, stream=None) -> list[Compressed]:
+        _check(numarck_plan_replay(self._h, _stream(stream)), "numarck_plan_replay")
+        return self.results()
+
+    def close(self):
+        if self._h:
+            numarck_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def compress_batch(jobs: list[BatchJob], recon: bool = False, bin_ids: bool = False,
+                   stream=None) -> list[Compressed]:
+    """One-shot batch through numarck_compress_batch."""
+    arr = (NumarckJob * len(jobs))()
+    outs = []
+    for i, j in enumerate(jobs):
+        p, q = j.prev.reshape(-1), j.curr.reshape(-1)
+        o = alloc_outputs(p.numel(), p.dtype, j.B, j.block_bytes, recon, bin_ids, p.device)
+        arr[i] = NumarckJob(_ptr(p), _ptr(q), p.numel(), dtype_code(p.dtype), float(j.E),
+                            int(j.B), int(j.block_bytes), out_struct(o))
+        outs.append((p, o))
+    dev = jobs[0].prev.device
+    ws = torch.empty(max(numarck_batch_workspace_bytes(arr, len(jobs)), 1), dtype=torch.uint8,
+                     device=dev)
+    _check(numarck_compress_batch(arr, len(jobs), _ptr(ws), ws.numel(), _stream(stream)),
+           "numarck_compress_batch")
+    res = [Compressed(o["packed"], o["centers"], o["incomp"], o["block_inc_off"], o["recon"],
+                      o["bin_ids"], o["hdr"], None, p.numel(), p.dtype) for p, o in outs]
+    for c in res:
+        c._batch_ws = ws  # keep the workspace alive until the chain has run
+    return res
 
 
 def decompress(c: Compressed, prev: torch.Tensor, out: torch.Tensor | None = None,

@@ -34,11 +34,10 @@ HEADER_FIELDS = ["n", "n_valid", "n_invalid", "n_inc", "n_blocks", "elems_per_bl
                  "compressed_bytes"]
 
 
-def compare_compress(nk, prev, curr, E, B, block_bytes=0, check_hist=True, label=""):
-    """Compress on both sides and assert every output is identical."""
+def assert_matches_oracle(nk, c, o, prev, curr, E, B, block_bytes=0, check_hist=True,
+                          label=""):
+    """Assert that the GPU compression `c` equals the oracle's `o` in every output."""
     orc = oracle.get()
-    o = orc.compress(prev, curr, E, B, block_bytes=block_bytes)
-    c, p, q = gpu_compress(nk, prev, curr, E, B, block_bytes)
     h = c.header().as_dict()
     tag = f"[{label} n={prev.size} {prev.dtype} E={E} B={B} bb={block_bytes}]"
     for f in HEADER_FIELDS:
@@ -55,12 +54,13 @@ def compare_compress(nk, prev, curr, E, B, block_bytes=0, check_hist=True, label
     assert np.array_equal(bits(to_np(c.incomp)[:ninc]), bits(o.incomp)), f"{tag} incomp"
     nb = o.info["n_blocks"]
     assert np.array_equal(to_np(c.block_inc_off)[:nb], o.block_inc_off), f"{tag} blocks"
-    if n:
+    if n and c.recon is not None:
         assert np.array_equal(bits(to_np(c.recon)[:n]), bits(o.recon)), f"{tag} recon"
-    ku = o.info["k_used"]
-    gb = to_np(c.bin_ids)
-    assert np.array_equal(gb[:ku], o.sel_ids), f"{tag} selected bins"
-    assert np.all(gb[ku:] == -1), f"{tag} unused bin ids"
+    if c.bin_ids is not None:
+        ku = o.info["k_used"]
+        gb = to_np(c.bin_ids)
+        assert np.array_equal(gb[:ku], o.sel_ids), f"{tag} selected bins"
+        assert np.all(gb[ku:] == -1), f"{tag} unused bin ids"
     if check_hist:
         ids, cnt, k = nk.histogram(c)
         assert k == o.info["n_nonzero"], f"{tag} nonzero bins"
@@ -74,7 +74,34 @@ def compare_compress(nk, prev, curr, E, B, block_bytes=0, check_hist=True, label
             oi, oc = np.zeros(0, np.int64), np.zeros(0, np.uint32)
         assert np.array_equal(gi[order], oi), f"{tag} histogram ids"
         assert np.array_equal(gc[order], oc), f"{tag} histogram counts"
+
+
+def compare_compress(nk, prev, curr, E, B, block_bytes=0, check_hist=True, label=""):
+    """Compress on both sides and assert every output is identical."""
+    o = oracle.get().compress(prev, curr, E, B, block_bytes=block_bytes)
+    c, p, q = gpu_compress(nk, prev, curr, E, B, block_bytes)
+    assert_matches_oracle(nk, c, o, prev, curr, E, B, block_bytes, check_hist, label)
     return c, o, p
+
+
+def assert_same_compression(a, b, label=""):
+    """Two GPU compressions of the same input are identical in every output."""
+    ha, hb = a.header().as_dict(), b.header().as_dict()
+    for f in HEADER_FIELDS + ["flags", "lo", "hi", "tail_count", "window_base"]:
+        assert bits(np.array([ha[f]])).tolist() == bits(np.array([hb[f]])).tolist(), \
+            f"[{label}] header {f}: {ha[f]} vs {hb[f]}"
+    nw = ha["packed_bytes"] // 4
+    assert torch.equal(a.packed[:nw], b.packed[:nw]), f"[{label}] packed"
+    assert torch.equal(a.centers.view(torch.int32) if a.centers.dtype == torch.float32
+                       else a.centers.view(torch.int64),
+                       b.centers.view(torch.int32) if b.centers.dtype == torch.float32
+                       else b.centers.view(torch.int64)), f"[{label}] centers"
+    ni = ha["n_inc"]
+    ia, ib = a.incomp[:ni], b.incomp[:ni]
+    iv = torch.int32 if ia.dtype == torch.float32 else torch.int64
+    assert torch.equal(ia.view(iv), ib.view(iv)), f"[{label}] incomp"
+    nb = ha["n_blocks"]
+    assert torch.equal(a.block_inc_off[:nb], b.block_inc_off[:nb]), f"[{label}] blocks"
 
 
 def compare_decompress(nk, c, o, p, prev, ranges=(), label=""):

@@ -128,3 +128,63 @@ def test_status_strings(nk):
     for s in range(9):
         assert nk.numarck_status_str(s)
     assert nk.numarck_status_str(99) == b"unknown status"
+
+
+def _job(nk, n=1000, dtype=None, E=1e-3, B=8, base=0x300000):
+    return nk.NumarckJob(base, base + 0x100000, n, nk.F64 if dtype is None else dtype, E, B, 0,
+                         _out(nk))
+
+
+def test_plan_validation_without_gpu(nk):
+    jobs = (nk.NumarckJob * 3)(_job(nk), _job(nk, 5000, nk.F32, 1e-4, 12), _job(nk, 0))
+    need = nk.numarck_batch_workspace_bytes(jobs, 3)
+    single = sum(nk.numarck_workspace_bytes(j.n, j.dtype, j.B) for j in jobs)
+    assert need > single  # job table and prefix arrays come first
+    h = ctypes.c_void_p()
+    ws = 0x10000000
+    create = lambda js, nj, w=ws, wb=need, t=None: nk.numarck_plan_create(
+        js, nj, t, w, wb, None, ctypes.byref(h))
+    assert create(jobs, 0) == nk.EINVAL
+    assert create(jobs, nk.MAX_JOBS + 1) == nk.EINVAL
+    assert create(jobs, 3, w=ws + 16) == nk.EALIGN
+    assert create(jobs, 3, wb=need - 1) == nk.ECAPACITY
+    bad = (nk.NumarckJob * 2)(_job(nk), _job(nk, B=0))
+    assert create(bad, 2) == nk.EBITS
+    assert b"job 1" in nk.numarck_last_error()
+    bad = (nk.NumarckJob * 2)(_job(nk, E=2.0), _job(nk))
+    assert create(bad, 2) == nk.EBOUND
+    bad = (nk.NumarckJob * 1)(_job(nk, base=0x300008))
+    assert create(bad, 1) == nk.EALIGN
+    t = nk.NumarckTuning(8, 2, 1, 4096, 0)  # unit_pct 0
+    assert create(jobs, 3, t=ctypes.byref(t)) == nk.EINVAL
+    assert not h.value
+    assert nk.numarck_plan_run(None, None) == nk.EINVAL
+    assert nk.numarck_plan_replay(None, None) == nk.EINVAL
+    nk.numarck_plan_destroy(None)
+
+
+def test_tuning_defaults_and_files(nk, tmp_path):
+    t = nk.default_tuning()
+    assert t.as_dict() == {"range_blocks_per_cu": 8, "hist_blocks_per_cu": 2, "hist_lds": 1,
+                           "chunk_vec": 4096, "unit_pct": 100}
+    good = tmp_path / "good.txt"
+    good.write_text("# comment\nf64 27 4 2 1 8192 75\nf32 20 8 4 0 2048 100\n")
+    assert nk.numarck_tuning_load(str(good).encode()) == nk.OK
+    out = tmp_path / "out.txt"
+    assert nk.numarck_tuning_save(str(out).encode()) == nk.OK
+    lines = [ln for ln in out.read_text().splitlines() if not ln.startswith("#")]
+    assert "f64 27 4 2 1 8192 75" in lines and "f32 20 8 4 0 2048 100" in lines
+    for bad in ("f16 3 1 1 1 64 1\n", "f64 3 0 1 1 64 1\n", "f64 3 1 1 2 64 1\n",
+                "f64 3 1 1 1 63 1\n", "f64 3 1 1 1 64 101\n", "f64 3 1 1\n"):
+        p = tmp_path / "bad.txt"
+        p.write_text(bad)
+        assert nk.numarck_tuning_load(str(p).encode()) == nk.EINVAL, bad
+    assert nk.numarck_tuning_load(str(tmp_path / "missing.txt").encode()) == nk.EINVAL
+
+
+def test_compress_tuned_validation_without_gpu(nk):
+    o = _out(nk)
+    bad = nk.NumarckTuning(8, 2, 1, 32, 100)  # chunk_vec below 64
+    st = nk.numarck_compress_tuned(0x300000, 0x400000, 10, nk.F64, 1e-3, 8, 0, ctypes.byref(o),
+                                   0x200000, 1 << 40, ctypes.byref(bad), None)
+    assert st == nk.EINVAL

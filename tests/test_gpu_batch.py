@@ -1,0 +1,189 @@
+"""Batched compression (one chain of launches for many jobs) through the C ABI:
+every job's outputs equal the CPU oracle's bit for bit, and equal those of a
+plain per-job compression; plans replay through a HIP graph; the autotuner's
+choice changes no output."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from gpu_util import assert_matches_oracle, assert_same_compression, to_np
+from paper_1703_02438_amd import inputs
+from pins import adversarial_case, mixture_case
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def nk():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_1703_02438_amd.numarck as nk
+    return nk
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+
+
+def _mixed_jobs():
+    """Jobs of both element types, every encoder class (B < 8, 8, 8 < B < 16,
+    16), empty and one-element inputs, ragged sizes, block sizes, an all-invalid
+    input and one whose histogram spills out of the window."""
+    spec = [
+        (0, np.float64, 1e-3, 8, 0), (1, np.float32, 1e-3, 3, 0),
+        (100003, np.float64, 1e-3, 10, 0), (4097, np.float32, 1e-2, 1, 0),
+        (33, np.float64, 1e-3, 16, 0), (250000, np.float32, 1e-4, 12, 0),
+        (65536, np.float64, 1e-3, 8, 4096), (12289, np.float32, 1e-3, 8, 1 << 20),
+        (77777, np.float64, 1e-4, 13, 0), (5, np.float64, 1e-3, 5, 0),
+        (131071, np.float64, 1e-5, 16, 0), (3, np.float32, 1e-3, 16, 0),
+    ]
+    jobs = []
+    for i, (n, dt, E, B, bb) in enumerate(spec):
+        p, q = mixture_case(max(n, 1), 3000 + i, dt)
+        jobs.append((p[:n], q[:n], E, B, bb))
+    pa, qa = adversarial_case(np.float64)
+    pm, qm = mixture_case(20000, 3100, np.float64)
+    jobs.append((np.concatenate([pa, pm, pa]), np.concatenate([qa, qm, qa]), 1e-3, 8, 0))
+    z = np.zeros(999, np.float64)
+    jobs.append((z, z + 1.0, 1e-3, 8, 0))  # no valid point
+    return jobs
+
+
+def _run_plan(nk, jobs, graph=False, tune=None):
+    bj = [nk.BatchJob(_dev(p), _dev(q), E, B, bb) for p, q, E, B, bb in jobs]
+    plan = nk.Plan(bj, recon=True, bin_ids=True, tune=tune)
+    if graph:
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            plan.capture(s)
+            res = plan.replay(s)
+        torch.cuda.current_stream().wait_stream(s)
+    else:
+        res = plan.run()
+    return plan, bj, res
+
+
+def test_mixed_batch_vs_oracle(nk):
+    jobs = _mixed_jobs()
+    plan, bj, res = _run_plan(nk, jobs)
+    torch.cuda.synchronize()
+    orc = oracle.get()
+    for i, ((p, q, E, B, bb), c) in enumerate(zip(jobs, res)):
+        o = orc.compress(p, q, E, B, block_bytes=bb)
+        assert_matches_oracle(nk, c, o, p, q, E, B, bb, check_hist=False, label=f"job{i}")
+        out, fl = nk.decompress(c, bj[i].prev)
+        ref, rfl = orc.decompress(o, p)
+        assert int(fl.item()) == rfl == 0
+        assert np.array_equal(to_np(out).view(np.uint8), ref.view(np.uint8)), f"job{i} decode"
+    plan.close()
+
+
+def test_batch_equals_plain_and_one_shot(nk):
+    jobs = _mixed_jobs()
+    plan, bj, res = _run_plan(nk, jobs)
+    one = nk.compress_batch(bj, recon=True, bin_ids=True)
+    for i, (j, c, c1) in enumerate(zip(bj, res, one)):
+        plain = nk.compress(j.prev, j.curr, j.E, j.B, j.block_bytes, recon=True, bin_ids=True)
+        assert_same_compression(c, plain, f"plan vs plain job{i}")
+        assert_same_compression(c1, plain, f"one-shot vs plain job{i}")
+    plan.close()
+
+
+def test_graph_replays(nk):
+    """A captured plan replays several times, with eager work and new input
+    values between replays; every replay matches the oracle on what the
+    inputs held at that time."""
+    jobs = _mixed_jobs()[:6]
+    plan, bj, res = _run_plan(nk, jobs, graph=True)
+    torch.cuda.synchronize()
+    orc = oracle.get()
+    s = torch.cuda.Stream()
+    for rep in range(3):
+        if rep:
+            for i, j in enumerate(bj):  # new current snapshots, written in place
+                n = j.curr.numel()
+                if n == 0:
+                    continue
+                _, q = mixture_case(n, 5000 + 31 * rep + i,
+                                    np.float32 if j.curr.dtype == torch.float32 else np.float64)
+                j.curr.copy_(_dev(q))
+            junk = torch.randn(1 << 20, device="cuda").sum()  # eager work between replays
+            torch.cuda.synchronize()
+            s.wait_stream(torch.cuda.current_stream())
+            with torch.cuda.stream(s):
+                res = plan.replay(s)
+            s.synchronize()
+            del junk
+        for i, (j, c) in enumerate(zip(bj, res)):
+            p, q = to_np(j.prev), to_np(j.curr)
+            o = orc.compress(p, q, j.E, j.B, block_bytes=j.block_bytes)
+            assert_matches_oracle(nk, c, o, p, q, j.E, j.B, j.block_bytes, check_hist=False,
+                                  label=f"replay{rep} job{i}")
+    plan.close()
+
+
+def test_uneven_variables_batch(nk):
+    """The uneven multi-variable workload (log-uniform cube edges, mixed
+    float32/float64, E in {1e-4, 1e-3, 1e-2}, B in {8, 10, 12}), 64 variables
+    at reduced edges, against the oracle."""
+    specs = inputs.batched_specs(64, lo_edge=8, hi_edge=64)
+    jobs = []
+    for sp in specs:
+        p, q = inputs.mixture_pair(sp.n, seed=sp.seed, dtype=sp.dtype)
+        jobs.append((p.numpy(), q.numpy(), sp.E, sp.B, 0))
+    plan, bj, res = _run_plan(nk, jobs)
+    torch.cuda.synchronize()
+    orc = oracle.get()
+    for i, ((p, q, E, B, bb), c) in enumerate(zip(jobs, res)):
+        o = orc.compress(p, q, E, B)
+        assert_matches_oracle(nk, c, o, p, q, E, B, check_hist=False, label=f"var{i}")
+    plan.close()
+
+
+def test_time_series_pairs(nk):
+    """Sixteen consecutive snapshot pairs of one climate-like series in one
+    batch (pairs share snapshots), against the oracle."""
+    s = inputs.ClimateSeries(nlat=90, nlon=180, seed=1708, device="cuda")
+    snaps = [s.x.clone()]
+    for _ in range(16):
+        snaps.append(s.step().clone())
+    bj = [nk.BatchJob(snaps[t], snaps[t + 1], 1e-4, 10) for t in range(16)]
+    plan = nk.Plan(bj, recon=True, bin_ids=True)
+    res = plan.run()
+    torch.cuda.synchronize()
+    orc = oracle.get()
+    for t, c in enumerate(res):
+        p, q = to_np(snaps[t]), to_np(snaps[t + 1])
+        o = orc.compress(p, q, 1e-4, 10)
+        assert_matches_oracle(nk, c, o, p, q, 1e-4, 10, check_hist=False, label=f"pair{t}")
+    plan.close()
+
+
+def test_tunings_change_no_output(nk):
+    p, q = mixture_case(300001, 4242, np.float64)
+    P, Q = _dev(p), _dev(q)
+    ref = nk.compress(P, Q, 1e-3, 8, recon=True, bin_ids=True)
+    for rb, hb, hl, cv, up in [(1, 1, 1, 64, 1), (16, 4, 0, 16384, 50), (64, 16, 0, 1 << 20, 100),
+                               (3, 2, 1, 777, 33)]:
+        t = nk.NumarckTuning(rb, hb, hl, cv, up)
+        c = nk.compress_tuned(P, Q, 1e-3, 8, t)
+        assert_same_compression(c, ref, f"tuning {t.as_dict()}")
+        plan, _, res = _run_plan(nk, [(p, q, 1e-3, 8, 0)], tune=t)
+        assert_same_compression(res[0], ref, f"plan tuning {t.as_dict()}")
+        plan.close()
+
+
+def test_autotune(nk, tmp_path):
+    p, q = mixture_case(1 << 20, 4343, np.float32)
+    P, Q = _dev(p), _dev(q)
+    best = nk.autotune(P, Q, 1e-3, 8, reps=2)
+    d = best.as_dict()
+    assert 1 <= d["unit_pct"] <= 100 and d["hist_lds"] in (0, 1)
+    c = nk.compress(P, Q, 1e-3, 8, recon=True, bin_ids=True)  # uses the recorded tuning
+    o = oracle.get().compress(p, q, 1e-3, 8)
+    assert_matches_oracle(nk, c, o, p, q, 1e-3, 8, check_hist=False, label="autotuned")
+    path = str(tmp_path / "tune.txt")
+    assert nk.numarck_tuning_save(path.encode()) == nk.OK
+    assert "f32 20 " in open(path).read()
+    assert nk.numarck_tuning_load(path.encode()) == nk.OK

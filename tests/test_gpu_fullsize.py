@@ -1,0 +1,71 @@
+"""Parity at the benchmark's full sizes, in the launch configuration bench.py
+times: the 512^3 float64 FLASH-like pair and the 1800 x 3600 float32
+climate-like pair, every output compared with the CPU oracle run on the whole
+input (the oracle finishes these in tens of seconds)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from gpu_util import HEADER_FIELDS, bits, to_np
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def nk():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_1703_02438_amd.numarck as nk
+    return nk
+
+
+def _full_check(nk, prev_t, curr_t, E, B, label):
+    n = prev_t.numel()
+    dt = prev_t.dtype
+    ws = torch.empty(nk.numarck_workspace_bytes(n, nk.dtype_code(dt), B), dtype=torch.uint8,
+                     device="cuda")
+    c = nk.compress(prev_t, curr_t, E, B, recon=True, bin_ids=True, ws=ws)
+    h = c.header().as_dict()
+    out, fl = nk.decompress(c, prev_t)
+    s, ln = n // 3 + 12345, n // 5
+    part, pfl = nk.decompress_range(c, prev_t, s, ln)
+    torch.cuda.synchronize()
+    prev, curr = prev_t.cpu().numpy(), curr_t.cpu().numpy()
+    o = oracle.get().compress(prev, curr, E, B)
+    for f in HEADER_FIELDS:
+        assert h[f] == o.info[f], f"[{label}] header {f}: gpu {h[f]} oracle {o.info[f]}"
+    assert h["flags"] == 0
+    assert bits(np.array([h["lo"], h["hi"]])).tolist() == \
+        bits(np.array([o.info["lo"], o.info["hi"]])).tolist()
+    assert np.array_equal(to_np(c.packed)[: o.info["packed_words"]].view(np.uint32), o.packed)
+    assert np.array_equal(bits(to_np(c.centers)), bits(o.centers))
+    assert np.array_equal(bits(to_np(c.incomp)[: o.info["n_inc"]]), bits(o.incomp))
+    assert np.array_equal(to_np(c.block_inc_off)[: o.info["n_blocks"]], o.block_inc_off)
+    assert np.array_equal(bits(to_np(c.recon)[:n]), bits(o.recon))
+    assert np.array_equal(to_np(c.bin_ids)[: o.info["k_used"]], o.sel_ids)
+    ref, rfl = oracle.get().decompress(o, prev)
+    assert int(fl.item()) == rfl == 0
+    assert np.array_equal(bits(to_np(out)), bits(ref))
+    assert int(pfl.item()) == 0
+    assert np.array_equal(bits(to_np(part)), bits(ref[s:s + ln]))
+    return h
+
+
+@pytest.mark.timeout(600)
+def test_flash_512cubed_f64_full(nk):
+    from paper_1703_02438_amd import inputs
+    s = inputs.FlashSeries(edge=512, seed=1705, device="cuda")
+    prev = s.x.clone()
+    curr = s.step().clone()
+    del s
+    h = _full_check(nk, prev, curr, 1e-3, 8, "flash 512^3")
+    assert h["M"] > 16384 and h["tail_count"] > 0
+
+
+@pytest.mark.timeout(300)
+def test_climate_1800x3600_f32_full(nk):
+    from paper_1703_02438_amd import inputs
+    s = inputs.ClimateSeries(nlat=1800, nlon=3600, seed=1707, device="cuda")
+    prev = s.x.clone()
+    curr = s.step().clone()
+    _full_check(nk, prev, curr, 1e-4, 10, "climate 1800x3600")
