@@ -136,6 +136,168 @@ def cpu_baseline(prev, curr, sample_elems: int):
     }
 
 
+def time_ms(torch, fn, reps: int, stream) -> float:
+    """Average ms of fn() over reps runs, HIP events on `stream` (after one warm run)."""
+    fn()
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    for _ in range(reps):
+        fn()
+    b.record(stream)
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / reps
+
+
+def batched_vs_plain(torch, nk, jobs, reps: int) -> dict:
+    """One workload of many jobs: plain per-job launches, one batched plan, and
+    the plan replayed as a HIP graph (input GB/s of each)."""
+    stream = torch.cuda.current_stream()
+    in_bytes = sum(j.curr.numel() * j.curr.element_size() for j in jobs)
+    wss = [torch.empty(nk.numarck_workspace_bytes(j.curr.numel(), nk.dtype_code(j.curr.dtype), j.B),
+                       dtype=torch.uint8, device="cuda") for j in jobs]
+    outs = [nk.alloc_outputs(j.curr.numel(), j.curr.dtype, j.B, j.block_bytes) for j in jobs]
+
+    def plain():
+        for j, w, o in zip(jobs, wss, outs):
+            nk.compress(j.prev, j.curr, j.E, j.B, j.block_bytes, ws=w, outputs=o, stream=stream)
+
+    t_plain = time_ms(torch, plain, reps, stream)
+    del wss
+    plan = nk.Plan(jobs, outputs=outs, stream=stream)
+    t_plan = time_ms(torch, lambda: plan.run(stream), reps, stream)
+    gs = torch.cuda.Stream()
+    gs.wait_stream(stream)
+    with torch.cuda.stream(gs):
+        plan.capture(gs)
+        t_graph = time_ms(torch, lambda: plan.replay(gs), reps, gs)
+    stream.wait_stream(gs)
+    flags = [plan.results()[i].header().flags for i in range(len(jobs))]
+    assert not any(flags), flags
+    plan.close()
+    return {
+        "jobs": len(jobs),
+        "input_bytes": in_bytes,
+        "plain_gbs": round(in_bytes / t_plain / 1e6, 1),
+        "batched_gbs": round(in_bytes / t_plan / 1e6, 1),
+        "graph_gbs": round(in_bytes / t_graph / 1e6, 1),
+        "plain_ms": round(t_plain, 3),
+        "batched_ms": round(t_plan, 3),
+        "graph_ms": round(t_graph, 3),
+        "speedup": round(t_plain / t_plan, 2),
+    }
+
+
+def batched_section(torch, nk, inputs, reps: int) -> dict:
+    """The uneven 64-variable workload (cube edges log-uniform in [32, 384],
+    60 % float64, E in {1e-4, 1e-3, 1e-2}, B in {8, 10, 12}) and 16 consecutive
+    pairs of a 3600 x 1800 float32 climate-like series (E = 1e-4, B = 10)."""
+    out = {}
+    jobs = []
+    for sp in inputs.batched_specs(64):
+        p, q = inputs.mixture_pair(sp.n, seed=sp.seed, dtype=sp.dtype, device="cuda")
+        jobs.append(nk.BatchJob(p, q, sp.E, sp.B))
+    out["uneven_64vars"] = batched_vs_plain(torch, nk, jobs, reps)
+    del jobs
+    s = inputs.ClimateSeries(nlat=1800, nlon=3600, seed=1707, device="cuda")
+    snaps = [s.x.clone()] + [s.step().clone() for _ in range(16)]
+    del s
+    out["climate_16pairs"] = batched_vs_plain(
+        torch, nk, [nk.BatchJob(snaps[t], snaps[t + 1], 1e-4, 10) for t in range(16)], reps)
+    return out
+
+
+SERVE_BUDGET = 200 << 30
+
+
+def serving_section(torch, nk, inputs, seconds: float, rate: float = 200.0) -> dict:
+    """The serving loop: 32 live variables (sizes log-uniform 16 MB .. 4 GB,
+    float32/float64, E in {1e-4, 1e-3}, B = 8) with their previous snapshots
+    resident, Poisson arrivals at `rate` requests/s for `seconds`, 5 % of them
+    range decompressions, admission under a 200 GB budget.  Then the same
+    server saturated: every variable's next compression submitted at once."""
+    import numpy as np
+
+    specs = inputs.serving_specs()
+    snaps = []
+    for sp in specs:  # two snapshots per variable; compressions alternate between them
+        p, q = inputs.mixture_pair(sp.n, seed=sp.seed, dtype=sp.dtype, device="cuda")
+        snaps.append((p, q))
+    torch.cuda.synchronize()
+    resident = sum(sp.n * sp.dtype.itemsize for sp in specs)
+    free, _ = torch.cuda.mem_get_info()
+    arena = min(SERVE_BUDGET - resident, free - (8 << 30))
+    srv = nk.Server(budget_bytes=SERVE_BUDGET, arena_bytes=arena, slots=2, max_batch=32)
+    for sp, (p, q) in zip(specs, snaps):
+        srv.add_variable(p, sp.E, sp.B)
+    state = [0] * len(specs)  # index of the resident snapshot
+    # live variables already hold a record: one compression each first
+    for v in range(len(specs)):
+        state[v] ^= 1
+        srv.compress(v, snaps[v][state[v]])
+    srv.drain()
+    assert all(c["status"] == 0 for c in srv.poll())
+    reqs = inputs.serving_requests(specs, rate, seconds)
+    outs = {}
+    done = []
+    t0 = time.perf_counter()
+    for (t, v, kind, st, ln) in reqs:
+        while time.perf_counter() - t0 < t:
+            time.sleep(5e-5)
+        if kind == 0:
+            state[v] ^= 1
+            srv.compress(v, snaps[v][state[v]])
+        else:
+            tk, o = srv.range(v, st, ln)
+            outs[tk] = o
+        if len(done) % 16 == 0:
+            done += srv.poll()
+    srv.drain()
+    done += srv.poll()
+    comp = [c for c in done if c["kind"] == 0]
+    rng = [c for c in done if c["kind"] == 1]
+    assert all(c["status"] == 0 and c["flags"] == 0 for c in done), \
+        [c for c in done if c["status"] or c["flags"]][:3]
+    lat = np.array([c["done_us"] - c["submit_us"] for c in comp]) / 1e3
+    rlat = np.array([c["done_us"] - c["submit_us"] for c in rng]) / 1e3 if rng else np.zeros(1)
+    span_s = (max(c["done_us"] for c in done) - min(c["submit_us"] for c in done)) / 1e6
+    in_bytes = sum(c["bytes"] for c in comp)
+    # saturated: one compression of every variable submitted at once
+    srv.drain()
+    srv.poll()
+    sat_t0 = time.perf_counter()
+    for v in range(len(specs)):
+        state[v] ^= 1
+        srv.compress(v, snaps[v][state[v]])
+    srv.drain()
+    sat_s = time.perf_counter() - sat_t0
+    sat = srv.poll()
+    assert all(c["status"] == 0 and c["flags"] == 0 for c in sat)
+    sat_bytes = sum(c["bytes"] for c in sat)
+    stats = srv.stats()
+    srv.close()
+    del snaps, outs
+    torch.cuda.empty_cache()
+    return {
+        "workload": "32 live variables, 16 MB..4 GB log-uniform, f32/f64, E in {1e-4,1e-3}, B=8; "
+                    f"Poisson {rate:g} req/s for {seconds:g} s, 5% range decompressions",
+        "requests": len(done), "compress": len(comp), "range": len(rng),
+        "offered_gbs": round(in_bytes / seconds / 1e9, 1),
+        "sustained_gbs": round(in_bytes / span_s / 1e9, 1),
+        "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 3),
+                       "p99": round(float(np.percentile(lat, 99)), 3),
+                       "max": round(float(lat.max()), 3)},
+        "range_latency_ms": {"p50": round(float(np.percentile(rlat, 50)), 3),
+                             "p99": round(float(np.percentile(rlat, 99)), 3)},
+        "saturated_gbs": round(sat_bytes / sat_s / 1e9, 1),
+        "budget_gb": SERVE_BUDGET / 2**30, "resident_gb": round(resident / 2**30, 2),
+        "arena_gb": round(arena / 2**30, 2), "arena_peak_gb": round(stats["arena_peak"] / 2**30, 2),
+        "batches": stats["batches"], "max_batch": stats["max_batch_seen"],
+        "waits_for_memory": stats["waits_for_memory"],
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -144,6 +306,10 @@ def main():
     ap.add_argument("--edge", type=int, default=EDGE)
     ap.add_argument("--cpu-sample", type=int, default=1 << 26,
                     help="elements of the oracle's CPU-baseline sample (0 = skip)")
+    ap.add_argument("--batched-reps", type=int, default=10,
+                    help="timed runs of each batched-vs-plain comparison (0 = skip)")
+    ap.add_argument("--serve-seconds", type=float, default=3.0,
+                    help="seconds of Poisson arrivals of the serving measurement (0 = skip)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run a 1 GiB device copy first (counter calibration)")
     ap.add_argument("--summarize-pmc", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "KERNEL", "CMD"),
@@ -172,6 +338,9 @@ def main():
         snaps.append(series.step().clone())
     del series
     torch.cuda.synchronize()
+    # the CPU baseline's sample (host copies taken before the GPU buffers go)
+    cs = min(args.cpu_sample, snaps[0].numel()) if args.cpu_sample > 0 else 0
+    cpu_prev, cpu_curr = snaps[0][:cs].cpu(), snaps[1][:cs].cpu()
     print(f"# generated {SNAPSHOTS} snapshots of {args.edge}^3 float64 in "
           f"{time.time() - t_gen:.1f}s", file=sys.stderr, flush=True)
     n = snaps[0].numel()
@@ -229,9 +398,19 @@ def main():
 
     in_bytes = n * 8
     value = in_bytes * args.steps / wall / 1e9
+    del snaps, ws, outs, c
+    torch.cuda.empty_cache()
+    batched = None
+    if args.batched_reps > 0:
+        batched = batched_section(torch, nk, inputs, args.batched_reps)
+        print(f"# batched: {json.dumps(batched)}", file=sys.stderr, flush=True)
+    serving = None
+    if args.serve_seconds > 0:
+        serving = serving_section(torch, nk, inputs, args.serve_seconds)
+        print(f"# serving: {json.dumps(serving)}", file=sys.stderr, flush=True)
     cpu = None
     if args.cpu_sample > 0:
-        cpu = cpu_baseline(snaps[0], snaps[1], min(args.cpu_sample, n))
+        cpu = cpu_baseline(cpu_prev, cpu_curr, min(args.cpu_sample, n))
 
     p50 = lat[len(lat) // 2]
     p99 = lat[min(len(lat) - 1, int(round(0.99 * (len(lat) - 1))))]
@@ -255,6 +434,8 @@ def main():
             "alpha": round(alpha, 5),
         },
         "latency_ms": {"p50": round(p50, 4), "p99": round(p99, 4)},
+        "batched": batched,
+        "serving": serving,
         "kernels_us": {k: round(v[1] / v[0] * 1e3, 1) for k, v in per_kernel.items()},
         "roofline": {
             "bound": "hbm",

@@ -254,6 +254,98 @@ void numarck_plan_destroy(numarck_plan* plan);
 numarck_status numarck_compress_batch(const numarck_job* jobs, uint32_t njobs, void* ws,
                                       size_t ws_bytes, void* stream);
 
+/* ---- serving loop: continuous batching under a device memory budget ----
+ * A server owns a device arena (one allocation at creation) for compressed
+ * records and workspaces, a scheduler thread and `slots` HIP streams.
+ * Variables are registered with their first snapshot; each compression
+ * request brings the variable's next snapshot and is compressed against the
+ * previous one, which stays resident on the device (zero copy: the snapshot
+ * buffers are the caller's).  Requests of one variable run in submission
+ * order; requests of different variables are batched together (one plan per
+ * batch, numarck_plan_*) and batches on different slots overlap.  A request
+ * is admitted when its record and workspace fit in the arena; otherwise it
+ * waits for memory to be released.  Range requests decompress part of the
+ * variable's latest record (the record of its last compression submitted
+ * before the range request).  Results are identical to numarck_compress /
+ * numarck_decompress_range called on each request alone. */
+typedef struct numarck_server numarck_server;
+
+typedef struct numarck_server_config {
+  uint64_t budget_bytes; /* device bytes the server may account for: the arena plus the
+                            registered variables' resident snapshots */
+  uint64_t arena_bytes;  /* device arena for records and workspaces (<= budget_bytes) */
+  uint32_t slots;        /* batches in flight at once, one HIP stream each (1..8) */
+  uint32_t max_batch;    /* compression requests per batch (1..NUMARCK_MAX_JOBS) */
+  int32_t device;        /* HIP device of the server */
+  uint32_t reserved;
+} numarck_server_config;
+
+typedef enum numarck_req_kind {
+  NUMARCK_REQ_COMPRESS = 0,
+  NUMARCK_REQ_RANGE = 1
+} numarck_req_kind;
+
+typedef struct numarck_request {
+  uint32_t kind;   /* numarck_req_kind */
+  uint32_t var;    /* variable id from numarck_server_add_variable */
+  const void* curr; /* COMPRESS: the next snapshot (device, n elements, 16-byte aligned).  It
+                       becomes the variable's resident previous snapshot, and it is the
+                       reference of the new record: keep it unchanged until the variable's
+                       second-next compression has completed. */
+  uint64_t start;  /* RANGE: first element */
+  uint64_t len;    /* RANGE: element count */
+  void* out;       /* RANGE: destination (device, len elements, 16-byte aligned) */
+  void* ready;     /* optional hipEvent_t: the request's stream waits for it before reading
+                      curr / writing out (the event must outlive the request); NULL: the
+                      caller has made the data ready before submitting */
+} numarck_request;
+
+typedef struct numarck_completion {
+  uint64_t ticket;
+  uint32_t var;
+  uint32_t kind;
+  int32_t status;    /* numarck_status of the request */
+  uint32_t flags;    /* record flags (COMPRESS) or decode flags (RANGE) */
+  uint64_t bytes;    /* input bytes (COMPRESS) or output bytes (RANGE) */
+  uint64_t batch;    /* serial number of the batch that ran it */
+  double submit_us;  /* host clock, microseconds since the server's creation */
+  double start_us;   /* launch of its batch */
+  double done_us;    /* completion observed by the scheduler */
+} numarck_completion;
+
+typedef struct numarck_server_stats {
+  uint64_t submitted, completed, batches, max_batch_seen;
+  uint64_t arena_capacity, arena_peak, resident_bytes;
+  uint64_t waits_for_memory; /* scheduler passes that left an eligible request queued for lack of memory */
+} numarck_server_stats;
+
+/* Create a server (allocates the arena with hipMalloc, creates the streams
+ * and starts the scheduler thread).  ECAPACITY if arena_bytes > budget_bytes. */
+numarck_status numarck_server_create(const numarck_server_config* cfg, numarck_server** out);
+/* Register a variable of n elements with its first snapshot `initial` (device,
+ * caller-owned, kept unchanged until the variable's second compression has
+ * completed).  ECAPACITY if the resident snapshots would exceed the budget or
+ * one compression of it could never fit in the arena. */
+numarck_status numarck_server_add_variable(numarck_server* s, uint64_t n, numarck_dtype dtype,
+                                           double E, uint32_t B, uint64_t block_bytes,
+                                           const void* initial, uint32_t* var_id);
+/* Queue a request (thread-safe, non-blocking); *ticket identifies its completion. */
+numarck_status numarck_server_submit(numarck_server* s, const numarck_request* r,
+                                     uint64_t* ticket);
+/* Completed requests since the last poll, oldest first (at most cap); returns the count. */
+uint32_t numarck_server_poll(numarck_server* s, numarck_completion* out, uint32_t cap);
+/* Block until every submitted request has completed. */
+numarck_status numarck_server_drain(numarck_server* s);
+/* Copy the variable's latest record to caller buffers (sized as for
+ * numarck_compress of the variable; recon and bin_ids are not copied) on
+ * `stream`, synchronously.  EINVAL if it has none yet.  Call it when no
+ * request of the variable is queued (e.g. after numarck_server_drain). */
+numarck_status numarck_server_fetch(numarck_server* s, uint32_t var, const numarck_out* dst,
+                                    void* stream);
+numarck_status numarck_server_get_stats(numarck_server* s, numarck_server_stats* st);
+/* Drain, stop the scheduler, release the arena and streams. */
+void numarck_server_destroy(numarck_server* s);
+
 /* ---- diagnostics ---- */
 const char* numarck_status_str(numarck_status s);
 /* Text of the last HIP error seen by this thread ("" if none). */

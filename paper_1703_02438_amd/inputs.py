@@ -182,3 +182,52 @@ def batched_specs(count: int = 64, seed: int = 1706, lo_edge: int = 32, hi_edge:
         B = (8, 10, 12)[min(int(u[3] * 3), 2)]
         specs.append(VarSpec(edge, dt, E, B, seed * 1000 + i))
     return specs
+
+
+@dataclass
+class ServeVar:
+    n: int
+    dtype: torch.dtype
+    E: float
+    B: int
+    seed: int
+
+
+def serving_specs(count: int = 32, seed: int = 1709, lo_bytes: int = 16 << 20,
+                  hi_bytes: int = 4 << 30):
+    """Live variables of the serving workload: sizes log-uniform in
+    [lo_bytes, hi_bytes], float32 / float64 equally likely, E in {1e-4, 1e-3},
+    B = 8."""
+    g = _gen(seed, "cpu")
+    out = []
+    for i in range(count):
+        u = torch.rand(3, generator=g, dtype=torch.float64).tolist()
+        nbytes = math.exp(math.log(lo_bytes) + u[0] * (math.log(hi_bytes) - math.log(lo_bytes)))
+        dt = torch.float32 if u[1] < 0.5 else torch.float64
+        L = 4 if dt == torch.float32 else 8
+        n = max(int(nbytes // L) // 4 * 4, 4)
+        out.append(ServeVar(n, dt, (1e-4, 1e-3)[min(int(u[2] * 2), 1)], 8, seed * 1000 + i))
+    return out
+
+
+def serving_requests(specs, rate: float, seconds: float, range_frac: float = 0.05,
+                     seed: int = 1710):
+    """Poisson arrivals at `rate` per second for `seconds`: (time, var, kind,
+    start, length); kind 0 = compress, 1 = range decompression of a random
+    contiguous range (length log-uniform from 1024 elements to n / 10)."""
+    g = _gen(seed, "cpu")
+    t, reqs = 0.0, []
+    while True:
+        u = torch.rand(5, generator=g, dtype=torch.float64).tolist()
+        t += -math.log(1.0 - u[0]) / rate
+        if t >= seconds:
+            return reqs
+        v = min(int(u[1] * len(specs)), len(specs) - 1)
+        n = specs[v].n
+        if u[2] < range_frac:
+            hi = max(n // 10, 1024)
+            ln = min(int(math.exp(math.log(1024) + u[3] * (math.log(hi) - math.log(1024)))), n)
+            st = min(int(u[4] * (n - ln + 1)), n - ln)
+            reqs.append((t, v, 1, st, ln))
+        else:
+            reqs.append((t, v, 0, 0, 0))

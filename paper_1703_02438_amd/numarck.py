@@ -69,8 +69,46 @@ class NumarckJob(ctypes.Structure):
     ]
 
 
+class NumarckServerConfig(ctypes.Structure):
+    _fields_ = [
+        ("budget_bytes", ctypes.c_uint64), ("arena_bytes", ctypes.c_uint64),
+        ("slots", ctypes.c_uint32), ("max_batch", ctypes.c_uint32), ("device", ctypes.c_int32),
+        ("reserved", ctypes.c_uint32),
+    ]
+
+
+class NumarckRequest(ctypes.Structure):
+    _fields_ = [
+        ("kind", ctypes.c_uint32), ("var", ctypes.c_uint32), ("curr", ctypes.c_void_p),
+        ("start", ctypes.c_uint64), ("len", ctypes.c_uint64), ("out", ctypes.c_void_p),
+        ("ready", ctypes.c_void_p),
+    ]
+
+
+class NumarckCompletion(ctypes.Structure):
+    _fields_ = [
+        ("ticket", ctypes.c_uint64), ("var", ctypes.c_uint32), ("kind", ctypes.c_uint32),
+        ("status", ctypes.c_int32), ("flags", ctypes.c_uint32), ("bytes", ctypes.c_uint64),
+        ("batch", ctypes.c_uint64), ("submit_us", ctypes.c_double),
+        ("start_us", ctypes.c_double), ("done_us", ctypes.c_double),
+    ]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class NumarckServerStats(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_uint64) for f in (
+        "submitted", "completed", "batches", "max_batch_seen", "arena_capacity", "arena_peak",
+        "resident_bytes", "waits_for_memory")]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
 HEADER_BYTES = ctypes.sizeof(NumarckHeader)
 MAX_JOBS = 65535
+REQ_COMPRESS, REQ_RANGE = 0, 1
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
@@ -126,6 +164,19 @@ numarck_plan_replay = _bind("numarck_plan_replay", _i, [_vp, _vp])
 numarck_plan_destroy = _bind("numarck_plan_destroy", None, [_vp])
 numarck_compress_batch = _bind("numarck_compress_batch", _i,
                                [ctypes.POINTER(NumarckJob), _u32, _vp, _sz, _vp])
+numarck_server_create = _bind("numarck_server_create", _i,
+                              [ctypes.POINTER(NumarckServerConfig), ctypes.POINTER(_vp)])
+numarck_server_add_variable = _bind("numarck_server_add_variable", _i,
+                                    [_vp, _u64, _i, _d, _u32, _u64, _vp, ctypes.POINTER(_u32)])
+numarck_server_submit = _bind("numarck_server_submit", _i,
+                              [_vp, ctypes.POINTER(NumarckRequest), ctypes.POINTER(_u64)])
+numarck_server_poll = _bind("numarck_server_poll", _u32,
+                            [_vp, ctypes.POINTER(NumarckCompletion), _u32])
+numarck_server_drain = _bind("numarck_server_drain", _i, [_vp])
+numarck_server_fetch = _bind("numarck_server_fetch", _i, [_vp, _u32, ctypes.POINTER(NumarckOut), _vp])
+numarck_server_get_stats = _bind("numarck_server_get_stats", _i,
+                                 [_vp, ctypes.POINTER(NumarckServerStats)])
+numarck_server_destroy = _bind("numarck_server_destroy", None, [_vp])
 numarck_status_str = _bind("numarck_status_str", ctypes.c_char_p, [_i])
 numarck_last_error = _bind("numarck_last_error", ctypes.c_char_p, [])
 numarck_timing_enable = _bind("numarck_timing_enable", None, [_i])
@@ -367,6 +418,110 @@ def compress_batch(jobs: list[BatchJob], recon: bool = False, bin_ids: bool = Fa
     for c in res:
         c._batch_ws = ws  # keep the workspace alive until the chain has run
     return res
+
+
+class Server:
+    """The serving loop (numarck_server_*): variables keep their previous
+    snapshot resident; compression and range requests of different variables
+    are batched by the library's scheduler thread under a device memory
+    budget.  This wrapper only keeps the tensors it hands to the library
+    alive while the library may still read or write them."""
+
+    def __init__(self, budget_bytes: int, arena_bytes: int, slots: int = 2, max_batch: int = 64,
+                 device: int = 0):
+        cfg = NumarckServerConfig(int(budget_bytes), int(arena_bytes), int(slots), int(max_batch),
+                                  int(device), 0)
+        h = _vp()
+        _check(numarck_server_create(ctypes.byref(cfg), ctypes.byref(h)), "numarck_server_create")
+        self._h = h
+        self.vars = []        # (n, torch dtype, E, B, block_bytes)
+        # snapshot k of a variable is the reference of its record k + 1, so it
+        # stays referenced until compression k + 2 has completed
+        self._keep = {}       # var -> [(sequence number, snapshot)]
+        self._seq = {}        # var -> snapshots handed over so far
+        self._done = {}       # var -> compressions completed
+        self._inflight = {}   # ticket -> tensors / events the request uses
+        self._kind = {}       # ticket -> (var, kind)
+
+    def add_variable(self, initial: torch.Tensor, E: float, B: int, block_bytes: int = 0) -> int:
+        x = initial.reshape(-1)
+        v = _u32()
+        st = numarck_server_add_variable(self._h, x.numel(), dtype_code(x.dtype), float(E), int(B),
+                                         int(block_bytes), _ptr(x), ctypes.byref(v))
+        _check(st, "numarck_server_add_variable")
+        self.vars.append((x.numel(), x.dtype, float(E), int(B), int(block_bytes)))
+        self._keep[v.value] = [(0, x)]  # (sequence number, snapshot)
+        self._seq[v.value] = 0
+        self._done[v.value] = 0
+        return v.value
+
+    def _submit(self, req: NumarckRequest, keep) -> int:
+        t = _u64()
+        _check(numarck_server_submit(self._h, ctypes.byref(req), ctypes.byref(t)),
+               "numarck_server_submit")
+        self._inflight[t.value] = keep
+        return t.value
+
+    def compress(self, var: int, curr: torch.Tensor, ready: "torch.cuda.Event | None" = None) -> int:
+        x = curr.reshape(-1)
+        req = NumarckRequest(REQ_COMPRESS, var, _ptr(x), 0, 0, None,
+                             ready.cuda_event if ready is not None else None)
+        t = self._submit(req, (x, ready))
+        self._seq[var] += 1
+        self._keep[var].append((self._seq[var], x))
+        self._kind[t] = (var, REQ_COMPRESS)
+        return t
+
+    def range(self, var: int, start: int, length: int, out: torch.Tensor | None = None,
+              ready: "torch.cuda.Event | None" = None):
+        n, dt = self.vars[var][0], self.vars[var][1]
+        if out is None:
+            out = torch.empty(max(length, 1), dtype=dt, device="cuda")
+        req = NumarckRequest(REQ_RANGE, var, None, int(start), int(length), _ptr(out),
+                             ready.cuda_event if ready is not None else None)
+        return self._submit(req, (out, ready)), out
+
+    def poll(self, cap: int = 4096) -> list[dict]:
+        buf = (NumarckCompletion * cap)()
+        k = numarck_server_poll(self._h, buf, cap)
+        res = [buf[i].as_dict() for i in range(k)]
+        for c in res:
+            self._inflight.pop(c["ticket"], None)
+            var, kind = self._kind.pop(c["ticket"], (c["var"], c["kind"]))
+            if kind == REQ_COMPRESS and c["status"] == OK:
+                self._done[var] += 1
+                lim = self._done[var] - 1
+                self._keep[var] = [(q, x) for q, x in self._keep[var] if q >= lim]
+        return res
+
+    def drain(self):
+        _check(numarck_server_drain(self._h), "numarck_server_drain")
+
+    def fetch(self, var: int, stream=None) -> Compressed:
+        n, dt, E, B, bb = self.vars[var]
+        o = alloc_outputs(n, dt, B, bb)
+        out = out_struct(o)
+        _check(numarck_server_fetch(self._h, var, ctypes.byref(out), _stream(stream)),
+               "numarck_server_fetch")
+        return Compressed(o["packed"], o["centers"], o["incomp"], o["block_inc_off"], None, None,
+                          o["hdr"], None, n, dt)
+
+    def stats(self) -> dict:
+        st = NumarckServerStats()
+        _check(numarck_server_get_stats(self._h, ctypes.byref(st)), "numarck_server_get_stats")
+        return st.as_dict()
+
+    def close(self):
+        if self._h:
+            numarck_server_destroy(self._h)
+            self._h = None
+            self._inflight.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def decompress(c: Compressed, prev: torch.Tensor, out: torch.Tensor | None = None,

@@ -1,0 +1,181 @@
+"""The serving loop (numarck_server_*) through the C ABI: requests of several
+variables, interleaved and batched by the scheduler, give exactly the results
+of the same requests run alone (numarck_compress / numarck_decompress_range);
+a memory budget that admits one request at a time changes only the timing;
+inputs made ready by an event are waited for."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from gpu_util import assert_matches_oracle, assert_same_compression, bits, to_np
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def nk():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_1703_02438_amd.numarck as nk
+    return nk
+
+
+def _series(n, dt, seed, steps, E=1e-3):
+    """steps + 1 snapshots: lognormal start with 0.1 % zeros, each step
+    multiplied by 1 + r, r from the ratio mixture of the plain workload."""
+    rng = np.random.default_rng(seed)
+    x = rng.lognormal(0.0, 1.0, n)
+    x[rng.choice(n, max(1, n // 1000), replace=False)] = 0.0
+    out = [x.astype(dt)]
+    for _ in range(steps):
+        u = rng.random(n)
+        r = np.where(u < 0.7, rng.normal(0, 2 * E, n),
+                     np.where(u < 0.95, rng.normal(10 * E, 5 * E, n), rng.uniform(-0.5, 0.5, n)))
+        out.append((out[-1].astype(np.float64) * (1 + r)).astype(dt))
+    return [torch.from_numpy(a).to("cuda") for a in out]
+
+
+VARS = [(100003, np.float64, 1e-3, 8), (65536, np.float32, 1e-4, 10), (4097, np.float64, 1e-3, 3),
+        (1, np.float32, 1e-3, 8), (250000, np.float64, 1e-4, 12), (33, np.float32, 1e-2, 16),
+        (131072, np.float64, 1e-3, 8)]
+STEPS = 3
+
+
+def _workload(seed):
+    """Per variable its snapshots; a request list interleaving every
+    variable's compressions (in order) with range requests, some of them
+    before the variable's first compression."""
+    rng = np.random.default_rng(seed)
+    snaps = [_series(n, dt, 700 + i, STEPS, E) for i, (n, dt, E, B) in enumerate(VARS)]
+    reqs = []
+    nxt = [1] * len(VARS)
+    while any(k <= STEPS for k in nxt):
+        v = int(rng.integers(len(VARS)))
+        if rng.random() < 0.3:
+            n = VARS[v][0]
+            s = int(rng.integers(0, n + 1))
+            reqs.append(("range", v, s, int(rng.integers(0, n - s + 1))))
+        elif nxt[v] <= STEPS:
+            reqs.append(("compress", v, nxt[v]))
+            nxt[v] += 1
+    return snaps, reqs
+
+
+def _run_server(nk, snaps, reqs, arena_bytes, slots=2, max_batch=4):
+    srv = nk.Server(budget_bytes=64 << 30, arena_bytes=arena_bytes, slots=slots,
+                    max_batch=max_batch)
+    for i, (n, dt, E, B) in enumerate(VARS):
+        assert srv.add_variable(snaps[i][0], E, B) == i
+    torch.cuda.synchronize()
+    tickets, outs = [], []
+    for r in reqs:
+        if r[0] == "compress":
+            tickets.append(srv.compress(r[1], snaps[r[1]][r[2]]))
+            outs.append(None)
+        else:
+            t, o = srv.range(r[1], r[2], r[3])
+            tickets.append(t)
+            outs.append(o)
+    srv.drain()
+    done = {c["ticket"]: c for c in srv.poll()}
+    assert sorted(done) == sorted(tickets)
+    return srv, tickets, outs, done
+
+
+def _check_against_alone(nk, snaps, reqs, tickets, outs, done, srv):
+    step = [0] * len(VARS)
+    alone = {}  # (var, step) -> Compressed of the plain path
+    for r, t, o in zip(reqs, tickets, outs):
+        c = done[t]
+        v = r[1]
+        n, dt, E, B = VARS[v]
+        if r[0] == "compress":
+            assert c["status"] == nk.OK and c["flags"] == 0, c
+            step[v] = r[2]
+            assert c["bytes"] == n * np.dtype(dt).itemsize
+            continue
+        if step[v] == 0:
+            assert c["status"] == nk.EINVAL, c  # nothing compressed yet
+            continue
+        assert c["status"] == nk.OK and c["flags"] == 0, c
+        k = step[v]
+        if (v, k) not in alone:
+            alone[(v, k)] = nk.compress(snaps[v][k - 1], snaps[v][k], E, B)
+        ref, fl = nk.decompress_range(alone[(v, k)], snaps[v][k - 1], r[2], r[3])
+        assert int(fl.item()) == 0
+        assert torch.equal(o[:r[3]].view(torch.uint8), ref[:r[3]].view(torch.uint8)), \
+            f"range {r} differs from the same request alone"
+    for v, (n, dt, E, B) in enumerate(VARS):
+        rec = srv.fetch(v)
+        plain = nk.compress(snaps[v][STEPS - 1], snaps[v][STEPS], E, B)
+        assert_same_compression(rec, plain, f"var {v} last record")
+
+
+def test_mix_equals_alone(nk):
+    snaps, reqs = _workload(11)
+    srv, tickets, outs, done = _run_server(nk, snaps, reqs, arena_bytes=1 << 30)
+    _check_against_alone(nk, snaps, reqs, tickets, outs, done, srv)
+    st = srv.stats()
+    assert st["completed"] == len(reqs) and st["batches"] >= 1
+    assert st["max_batch_seen"] > 1  # requests of different variables shared batches
+    # the last record of one variable against the oracle as well
+    n, dt, E, B = VARS[4]
+    p, q = to_np(snaps[4][STEPS - 1]), to_np(snaps[4][STEPS])
+    o = oracle.get().compress(p, q, E, B)
+    assert_matches_oracle(nk, srv.fetch(4), o, p, q, E, B, check_hist=False, label="served")
+    srv.close()
+
+
+def _record_bytes(nk, n, dt, B):
+    L = np.dtype(dt).itemsize
+    a = lambda x: (x + 255) // 256 * 256
+    nb = nk.numarck_block_count(n, B, 0)
+    return (a(nk.numarck_packed_bytes(n, B) + 4) + a(nk.numarck_centers_bytes(B, nk.dtype_code(
+        torch.float32 if dt == np.float32 else torch.float64))) + a(max(n, 1) * L)
+        + a(max(nb, 1) * 8) + a(nk.HEADER_BYTES))
+
+
+def test_tight_budget_serialises(nk):
+    """An arena that holds the record blocks and one request's workspace:
+    requests run one at a time, waiting for memory, with the same results."""
+    snaps, reqs = _workload(12)
+    recs = sum(2 * _record_bytes(nk, n, dt, B) for n, dt, E, B in VARS)
+    one = []
+    for n, dt, E, B in VARS:
+        j = (nk.NumarckJob * 1)()
+        j[0].n, j[0].dtype, j[0].B = n, nk.dtype_code(torch.float32 if dt == np.float32
+                                                      else torch.float64), B
+        one.append(nk.numarck_batch_workspace_bytes(j, 1))
+    arena = recs + max(one) + max(one) // 2
+    srv, tickets, outs, done = _run_server(nk, snaps, reqs, arena_bytes=arena)
+    _check_against_alone(nk, snaps, reqs, tickets, outs, done, srv)
+    st = srv.stats()
+    assert st["waits_for_memory"] > 0
+    assert st["arena_peak"] <= arena
+    srv.close()
+
+
+def test_capacity_and_ready_event(nk):
+    srv = nk.Server(budget_bytes=1 << 30, arena_bytes=1 << 24, slots=1, max_batch=2)
+    big = torch.zeros(1 << 22, dtype=torch.float64, device="cuda")
+    with pytest.raises(nk.NumarckError) as e:
+        srv.add_variable(big, 1e-3, 8)  # its records alone exceed the arena
+    assert e.value.status == nk.ECAPACITY
+    snaps = _series(50000, np.float64, 99, 1)
+    v = srv.add_variable(snaps[0], 1e-3, 8)
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):  # the next snapshot is produced on another stream
+        torch.cuda._sleep(20_000_000)
+        curr = snaps[1] * 1.0
+        ev = torch.cuda.Event()
+        ev.record(side)
+    srv.compress(v, curr, ready=ev)
+    srv.drain()
+    (c,) = srv.poll()
+    assert c["status"] == nk.OK
+    plain = nk.compress(snaps[0], snaps[1], 1e-3, 8)
+    assert_same_compression(srv.fetch(v), plain, "ready event")
+    with pytest.raises(nk.NumarckError):
+        srv.range(v, 49990, 11)
+    srv.close()
