@@ -15,6 +15,7 @@ sample of the same workload.
 from __future__ import annotations
 
 import argparse
+import ctypes
 import hashlib
 import json
 import os
@@ -99,9 +100,12 @@ def summarize_pmc(fetch_dir: str, write_dir: str, kernel: str, workload: str, cm
         v = per_kernel(d, counter)
         copy = [x for k, xs in v.items() if "copy" in k.lower() or "elementwise" in k.lower()
                 for x in xs if x * 1024 > 0.25 * COPY_CALIB_BYTES]
-        mine = [x for k, xs in v.items() if f"k_{kernel}" in k for x in xs]
+        mine = [x for k, xs in v.items() if f"k_{kernel}<" in k or f"k_{kernel}(" in k
+                for x in xs]
         if not copy or not mine:
             raise SystemExit(f"no {counter} samples for the copy or k_{kernel}")
+        # full-size launches only (range decompressions launch the same kernel on 1 %)
+        mine = [x for x in mine if x >= 0.5 * max(mine)]
         copy_kib = sorted(copy)[len(copy) // 2]
         scale = (COPY_CALIB_BYTES / 1024) / copy_kib
         kib = sum(mine) / len(mine)
@@ -133,6 +137,66 @@ def cpu_baseline(prev, curr, sample_elems: int):
         "kind": "oracle",
         "sample": f"first {p.size} elements of pair 0 ({p.size * 8 / 2**20:.0f} MiB), "
                   f"single-threaded C oracle, {dt:.2f} s",
+    }
+
+
+def decompress_section(torch, nk, c, prev, reps: int, stream, workload: str) -> dict:
+    """Full decompression of one 512^3 float64 record and range decompressions
+    of 1 % of it at seeded offsets: output GB/s, and the decode kernel against
+    its algorithmic bytes (read prev 8 + index B/8 + incompressible 8 alpha,
+    write 8 per element)."""
+    import random
+
+    h = c.header()
+    n = h.n
+    out = torch.empty(n, dtype=torch.float64, device="cuda")
+    flags = torch.zeros(1, dtype=torch.int32, device="cuda")
+    dws = torch.empty(nk.numarck_decompress_workspace_bytes(n), dtype=torch.uint8, device="cuda")
+    st = stream.cuda_stream
+
+    def full():
+        nk._check(nk.numarck_decompress(ctypes.byref(h), prev.data_ptr(), c.packed.data_ptr(),
+                                        c.centers.data_ptr(), c.incomp.data_ptr(),
+                                        c.block_inc_off.data_ptr(), out.data_ptr(),
+                                        flags.data_ptr(), dws.data_ptr(), dws.numel(), st),
+                  "numarck_decompress")
+
+    t_full = time_ms(torch, full, reps, stream)
+    nk.timing_enable(True)
+    for _ in range(reps):
+        full()
+    torch.cuda.synchronize()
+    tk = nk.timing_read()
+    nk.timing_enable(False)
+    dl, dms = tk["decode"]
+    ln = n // 100
+    rnd = random.Random(1711)
+    starts = [rnd.randrange(0, n - ln) for _ in range(reps)]
+    it = iter(starts * 2)
+
+    def part():
+        s0 = next(it)
+        nk._check(nk.numarck_decompress_range(ctypes.byref(h), prev.data_ptr(), c.packed.data_ptr(),
+                                              c.centers.data_ptr(), c.incomp.data_ptr(),
+                                              c.block_inc_off.data_ptr(), s0, ln, out.data_ptr(),
+                                              flags.data_ptr(), dws.data_ptr(), dws.numel(), st),
+                  "numarck_decompress_range")
+
+    t_part = time_ms(torch, part, reps - 1, stream)
+    assert int(flags.item()) == 0
+    alpha = h.n_inc / n
+    algo = (8 + 8 + h.B / 8 + 8 * alpha) * n
+    dec_s = dms / dl / 1e3
+    return {
+        "full_gbs": round(n * 8 / t_full / 1e6, 1),
+        "full_ms": round(t_full, 4),
+        "range_1pct_ms": round(t_part, 4),
+        "range_1pct_gbs": round(ln * 8 / t_part / 1e6, 1),
+        "decode_kernel": {"achieved": round(algo / dec_s / 1e9, 1), "peak": HBM_PEAK_GBS,
+                          "unit": "GB/s", "frac": round(algo / dec_s / 1e9 / HBM_PEAK_GBS, 4),
+                          "traffic": load_traffic("decode", workload),
+                          "algorithmic_bytes_per_launch": int(algo),
+                          "avg_launch_us": round(dec_s * 1e6, 2)},
     }
 
 
@@ -398,6 +462,7 @@ def main():
 
     in_bytes = n * 8
     value = in_bytes * args.steps / wall / 1e9
+    dec = decompress_section(torch, nk, step(0), snaps[0], args.steps, stream, workload)
     del snaps, ws, outs, c
     torch.cuda.empty_cache()
     batched = None
@@ -434,6 +499,7 @@ def main():
             "alpha": round(alpha, 5),
         },
         "latency_ms": {"p50": round(p50, 4), "p99": round(p99, 4)},
+        "decompress": dec,
         "batched": batched,
         "serving": serving,
         "kernels_us": {k: round(v[1] / v[0] * 1e3, 1) for k, v in per_kernel.items()},
