@@ -473,75 +473,84 @@ struct SelShared {
   uint32_t win[WIN];
   uint32_t hist[SEL_BUCKETS];
   unsigned long long red[SEL_TPB / 64];
-  unsigned scan[SEL_TPB];
+  unsigned long long red4[SEL_TPB / 64][4];
   unsigned bucket;
   unsigned long long before;
   unsigned tail_pos;
 };
 
-// Block-wide reductions (every thread calls them).
-__device__ unsigned long long sel_sum(unsigned long long v, SelShared& S) {
-  v = wave_sum_u64(v);
+// Four block-wide reductions at once: sums of a and b, min of c, max of d.
+__device__ void sel_reduce4(unsigned long long& a, unsigned long long& b, unsigned long long& c,
+                            unsigned long long& d, SelShared& S) {
+  a = wave_sum_u64(a);
+  b = wave_sum_u64(b);
+  c = wave_min_u64(c);
+  d = wave_max_u64(d);
   __syncthreads();
-  if (lane_id() == 0) S.red[threadIdx.x / 64] = v;
+  if (lane_id() == 0) {
+    const int w = threadIdx.x / 64;
+    S.red4[w][0] = a;
+    S.red4[w][1] = b;
+    S.red4[w][2] = c;
+    S.red4[w][3] = d;
+  }
   __syncthreads();
-  unsigned long long t = 0;
-  for (int i = 0; i < SEL_TPB / 64; ++i) t += S.red[i];
+  a = 0;
+  b = 0;
+  c = ~0ull;
+  d = 0;
+  for (int i = 0; i < SEL_TPB / 64; ++i) {
+    a += S.red4[i][0];
+    b += S.red4[i][1];
+    c = S.red4[i][2] < c ? S.red4[i][2] : c;
+    d = S.red4[i][3] > d ? S.red4[i][3] : d;
+  }
   __syncthreads();
-  return t;
 }
-__device__ unsigned long long sel_max(unsigned long long v, SelShared& S) {
-  v = wave_max_u64(v);
+
+// Block-wide exclusive prefix sum of one value per thread (thread order);
+// *total gets the sum over the block.
+__device__ unsigned long long sel_excl_scan(unsigned long long v, SelShared& S,
+                                            unsigned long long* total) {
+  const int lane = lane_id();
+  const int w = threadIdx.x / 64;
+  unsigned long long inc = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const unsigned long long t = __shfl_up(inc, o, 64);
+    if (lane >= o) inc += t;
+  }
   __syncthreads();
-  if (lane_id() == 0) S.red[threadIdx.x / 64] = v;
+  if (lane == 63) S.red[w] = inc;
   __syncthreads();
-  unsigned long long t = 0;
-  for (int i = 0; i < SEL_TPB / 64; ++i) t = S.red[i] > t ? S.red[i] : t;
+  unsigned long long base = 0, tot = 0;
+  for (int i = 0; i < SEL_TPB / 64; ++i) {
+    const unsigned long long r = S.red[i];
+    base += i < w ? r : 0ull;
+    tot += r;
+  }
   __syncthreads();
-  return t;
-}
-__device__ unsigned long long sel_min(unsigned long long v, SelShared& S) {
-  v = wave_min_u64(v);
-  __syncthreads();
-  if (lane_id() == 0) S.red[threadIdx.x / 64] = v;
-  __syncthreads();
-  unsigned long long t = ~0ull;
-  for (int i = 0; i < SEL_TPB / 64; ++i) t = S.red[i] < t ? S.red[i] : t;
-  __syncthreads();
-  return t;
+  *total = tot;
+  return base + inc - v;
 }
 
 // Bucket where the running count, scanned from the top (descending) or the
 // bottom, reaches `target` (1-based); S.before = count strictly before it.
+// Thread t takes scan positions 2t and 2t + 1.
 __device__ void sel_scan(SelShared& S, unsigned long long target, bool descending) {
-  if (threadIdx.x < 64) {
-    const int lane = threadIdx.x;
-    constexpr int PER = SEL_BUCKETS / 64;
-    unsigned long long mine = 0;
-    for (int i = 0; i < PER; ++i) {
-      const int pos = lane * PER + i;
-      mine += S.hist[descending ? SEL_BUCKETS - 1 - pos : pos];
-    }
-    unsigned long long inc = mine;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-      const unsigned long long t = __shfl_up(inc, o, 64);
-      if (lane >= o) inc += t;
-    }
-    const unsigned long long exc = inc - mine;
-    if (exc < target && inc >= target) {
-      unsigned long long run = exc;
-      for (int i = 0; i < PER; ++i) {
-        const int pos = lane * PER + i;
-        const int b = descending ? SEL_BUCKETS - 1 - pos : pos;
-        if (run + S.hist[b] >= target) {
-          S.bucket = (unsigned)b;
-          S.before = run;
-          break;
-        }
-        run += S.hist[b];
-      }
-    }
+  static_assert(SEL_BUCKETS == 2 * SEL_TPB, "two buckets per thread");
+  const int p0 = 2 * (int)threadIdx.x;
+  const int b0 = descending ? SEL_BUCKETS - 1 - p0 : p0;
+  const int b1 = descending ? b0 - 1 : b0 + 1;
+  const unsigned long long c0 = S.hist[b0], c1 = S.hist[b1];
+  unsigned long long tot;
+  const unsigned long long ex = sel_excl_scan(c0 + c1, S, &tot);
+  if (ex < target && ex + c0 >= target) {
+    S.bucket = (unsigned)b0;
+    S.before = ex;
+  } else if (ex + c0 < target && ex + c0 + c1 >= target) {
+    S.bucket = (unsigned)b1;
+    S.before = ex + c0;
   }
   __syncthreads();
 }
@@ -553,6 +562,7 @@ template <typename F>
 __device__ __forceinline__ void sel_visit(const CParams& P, const SelShared& S, long long wbase,
                                           unsigned win_len, bool tail, unsigned long long H, F f) {
   (void)win_len;
+#pragma unroll 4
   for (unsigned w = threadIdx.x; w < (unsigned)WIN; w += SEL_TPB)
     f(wbase + (long long)w, S.win[w]);  // bins past win_len hold 0
   if (tail) {
@@ -642,10 +652,7 @@ __device__ void sel_threshold(SelShared& S, unsigned long long mx, unsigned long
       tmax = (unsigned long long)id > tmax ? (unsigned long long)id : tmax;
     }
   });
-  gt = sel_sum(gt, S);
-  ties = sel_sum(ties, S);
-  tmin = sel_min(tmin, S);
-  tmax = sel_max(tmax, S);
+  sel_reduce4(gt, ties, tmin, tmax, S);
   const unsigned long long r = k - gt;  // ties to take, >= 1
   *tau_out = tau;
   *cut_out = r >= ties ? (long long)tmax : sel_rth_tie(S, tau, r, tmin, tmax, visit);
@@ -675,18 +682,15 @@ __global__ void __launch_bounds__(SEL_TPB) k_select(SRC src, Geo g) {
   const unsigned long long tail_max = has_tail ? c->tail_max : 0ull;
   const double lo = empty ? 0.0 : c->lo;
   if (tid == 0) S.tail_pos = 0;
-  for (int i = tid; i < WIN; i += SEL_TPB) S.win[i] = (unsigned)i < win_len ? P.gwin[i] : 0u;
-  __syncthreads();
-
-  // window statistics
-  unsigned long long nzw = 0, mxw = 0;
-  for (unsigned w = tid; w < win_len; w += SEL_TPB) {
-    const uint32_t cn = S.win[w];
+  // window counts to LDS, with their statistics
+  unsigned long long nzw = 0, mxw = 0, unused0 = ~0ull, unused1 = 0;
+  for (int i = tid; i < WIN; i += SEL_TPB) {
+    const uint32_t cn = (unsigned)i < win_len ? P.gwin[i] : 0u;
+    S.win[i] = cn;
     nzw += cn ? 1 : 0;
     mxw = cn > mxw ? cn : mxw;
   }
-  nzw = sel_sum(nzw, S);
-  mxw = sel_max(mxw, S);
+  sel_reduce4(nzw, unused1, unused0, mxw, S);  // also orders the LDS writes
   const unsigned long long nz = nzw + tail_bins;
 
   auto visit_win = [&](auto f) { sel_visit(P, S, wbase, win_len, false, 0ull, f); };
@@ -729,8 +733,10 @@ __global__ void __launch_bounds__(SEL_TPB) k_select(SRC src, Geo g) {
       }
     }
   }
-  sel_tail = sel_sum(sel_tail, S);
-  sel_below = sel_sum(sel_below, S);
+  {
+    unsigned long long u0 = ~0ull, u1 = 0;
+    sel_reduce4(sel_tail, sel_below, u0, u1, S);
+  }
 
   // window: LUT, centres and bin ids in ascending bin order.
   // Thread t owns window bins [t*PER, (t+1)*PER).
@@ -743,46 +749,28 @@ __global__ void __launch_bounds__(SEL_TPB) k_select(SRC src, Geo g) {
     const long long id = wbase + (long long)w;
     mine += (cn != 0 && (cn > tau || (cn == tau && id <= cut))) ? 1u : 0u;
   }
-  S.scan[tid] = mine;
-  __syncthreads();
-  if (tid < 64) {  // exclusive scan of 1024 partial counts by one wave
-    unsigned run = 0;
-    unsigned v[SEL_TPB / 64];
-#pragma unroll
-    for (int i = 0; i < SEL_TPB / 64; ++i) {
-      v[i] = S.scan[tid * (SEL_TPB / 64) + i];
-      run += v[i];
-    }
-    unsigned inc = run;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-      const unsigned t = __shfl_up(inc, o, 64);
-      if (tid >= o) inc += t;
-    }
-    unsigned ex = inc - run;
-#pragma unroll
-    for (int i = 0; i < SEL_TPB / 64; ++i) {
-      S.scan[tid * (SEL_TPB / 64) + i] = ex;
-      ex += v[i];
-    }
-    if (tid == 63) c->nsel_window = inc;
-  }
-  __syncthreads();
-  unsigned rank = (unsigned)sel_below + S.scan[tid];
-#pragma unroll
+  unsigned long long nwin_sel;
+  unsigned rank = (unsigned)sel_below + (unsigned)sel_excl_scan(mine, S, &nwin_sel);
+  if (tid == 0) c->nsel_window = (unsigned)nwin_sel;
+  // codes into LDS (each thread rewrites only its own bins), then out coalesced
+#pragma unroll 4
   for (int q = 0; q < PER; ++q) {
     const unsigned w = tid * PER + q;
     const uint32_t cn = S.win[w];
     const long long id = wbase + (long long)w;
-    uint16_t l = (uint16_t)k;  // escape code: not selected
+    uint32_t l = k;  // escape code: not selected
     if (cn != 0 && (cn > tau || (cn == tau && id <= cut))) {
-      l = (uint16_t)rank;
+      l = rank;
       centers[rank] = (T)centre_of<T>(id, lo, P.E);
       if (P.bin_ids) P.bin_ids[rank] = id;
       rank += 1;
     }
-    P.lut[w] = l;
+    S.win[w] = l;
   }
+  __syncthreads();
+  uint32_t* lut2 = reinterpret_cast<uint32_t*>(P.lut);  // two 16-bit codes per word
+  for (int i = tid; i < WIN / 2; i += SEL_TPB)
+    lut2[i] = (S.win[2 * i] & 0xFFFFu) | (S.win[2 * i + 1] << 16);
   if (tid == 0) {
     c->n_nonzero = nz;
     c->tau = tau;
@@ -917,13 +905,25 @@ __global__ void __launch_bounds__(UNIT_TPB) k_encode(S src, Geo g) {
     }
   };
 
+  // Lanes with nothing to store in a full tile write here (one 256-byte slot
+  // per wave, never read).
+  T* const sinkp = reinterpret_cast<T*>(static_cast<char*>(P.sink) +
+                                        (size_t)(unit % SINK_SLOTS) * 256);
+
   // One wave tile: index, verify, stage escapes, pack.  The common path is
   // branch-free; the exact division and the tail-bin search run only when a
-  // lane of the wave needs them.
-  auto process = [&](uint64_t tile, T (&pv)[R][V], T (&qv)[R][V]) {
+  // lane of the wave needs them.  FULL: the tile lies wholly in the vector
+  // part of the arrays.  A full tile then issues a fixed set of stores (the
+  // packed words, one store per element slot for the escapes, lanes without
+  // an escape writing the sink): the loop's wait for the next tile's loads
+  // can leave exactly those stores outstanding, instead of waiting for all
+  // of them as it must when their number depends on the data.
+  auto process = [&](auto full, uint64_t tile, T (&pv)[R][V], T (&qv)[R][V]) {
+    constexpr bool FULL = decltype(full)::value;
     const uint64_t t0 = tile * WT;
     const uint64_t left = P.n - t0;
-    const uint32_t lim = left < (uint64_t)WT ? (uint32_t)left : (uint32_t)WT;
+    const uint32_t lim = FULL ? (uint32_t)WT
+                              : (left < (uint64_t)WT ? (uint32_t)left : (uint32_t)WT);
     unsigned long long emask[R][V];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -978,7 +978,7 @@ __global__ void __launch_bounds__(UNIT_TPB) k_encode(S src, Geo g) {
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         const uint64_t vi = t0 / V + (uint64_t)r * 64 + lane;
-        if (vi < nvec) {
+        if (FULL || vi < nvec) {
           uint4 xv;
           __builtin_memcpy(&xv, pv[r], 16);
           reinterpret_cast<uint4*>(recon)[vi] = xv;
@@ -1018,10 +1018,13 @@ __global__ void __launch_bounds__(UNIT_TPB) k_encode(S src, Geo g) {
               e0 + v < lim && (one_b ? (e0 + v == b_local) : (j % P.epb == 0));
           if (at_b) P.block_inc_off[j / P.epb] = (long long)rank;
         }
-        if ((emask[r][v] >> lane) & 1ull) {
+        const bool escp = (emask[r][v] >> lane) & 1ull;
+        if (FULL) {  // every lane stores: the escape, or into the sink
+          *(escp ? scratch + e_base + rank : sinkp) = qv[r][v];
+        } else if (escp) {
           scratch[e_base + rank] = qv[r][v];
-          rank += 1;
         }
+        rank += escp ? 1u : 0u;
       }
       run += all;
     }
@@ -1032,8 +1035,36 @@ __global__ void __launch_bounds__(UNIT_TPB) k_encode(S src, Geo g) {
     if (PACK != 0) {
       // 8- or 16-bit indices: the index array is the packed stream
       const uint32_t* iw = reinterpret_cast<const uint32_t*>(idx);
-      for (uint32_t w = lane; w < tile_words; w += 64)
-        if (word0 + w < P.packed_words) P.packed[word0 + w] = iw[w];
+      if (FULL) {
+        constexpr uint32_t TW = (uint32_t)(WT * (PACK != 0 ? PACK : 8) / 32);  // a multiple of 64
+#pragma unroll
+        for (uint32_t w = lane; w < TW; w += 64) P.packed[word0 + w] = iw[w];
+      } else {
+        for (uint32_t w = lane; w < tile_words; w += 64)
+          if (word0 + w < P.packed_words) P.packed[word0 + w] = iw[w];
+      }
+    } else if (FULL) {
+      // at most B = 7 (u8 indices) or 15 (u16) bits: a fixed number of store
+      // rounds, lanes past the tile's words writing the sink
+      constexpr uint32_t BMAX = sizeof(LT) == 1 ? 7u : 15u;
+      constexpr uint32_t KW = (uint32_t)((WT * BMAX / 32 + 63) / 64);
+#pragma unroll
+      for (uint32_t k = 0; k < KW; ++k) {
+        const uint32_t w = lane + 64 * k;
+        const bool in = w < tile_words;
+        uint32_t word = 0;
+        if (in) {
+          const uint32_t bit0 = w * 32;
+          const uint32_t e_first = B == 1 ? bit0 : __umulhi(bit0, P.mulB);
+          const uint32_t e_last = B == 1 ? bit0 + 31 : __umulhi(bit0 + 31, P.mulB);
+          for (uint32_t e = e_first; e <= e_last; ++e) {
+            const uint32_t v = idx[e];
+            const int sh = (int)(e * B) - (int)bit0;
+            word |= sh >= 0 ? (v << sh) : (v >> (-sh));
+          }
+        }
+        *(in ? P.packed + word0 + w : reinterpret_cast<uint32_t*>(sinkp)) = word;
+      }
     } else {
       for (uint32_t w = lane; w < tile_words; w += 64) {
         if (word0 + w >= P.packed_words) break;
@@ -1054,15 +1085,50 @@ __global__ void __launch_bounds__(UNIT_TPB) k_encode(S src, Geo g) {
   };
 
   // Two register sets: the loads of one tile are in flight while the other
-  // is processed.
+  // is processed.  Tiles wholly inside the vector part of the arrays load
+  // without bounds checks and the next tile's loads are issued on every
+  // iteration (the last one re-reads its own tile), so the loop has a fixed
+  // number of loads in flight and the wait before processing a tile leaves
+  // the following tile's loads outstanding.  A ragged last tile takes the
+  // checked loads.
+  auto load_full = [&](uint64_t t0, T (&pa)[R][V], T (&qa)[R][V]) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const uint64_t vi = t0 / V + (uint64_t)r * 64 + lane;
+      load_vec(prev, vi, pa[r]);
+      load_vec(curr, vi, qa[r]);
+    }
+  };
+  const uint64_t full_tiles = nvec / (WT / V);  // tiles with every vector in range
+  const uint64_t tf = te < full_tiles ? te : (tb > full_tiles ? tb : full_tiles);
   T pa[R][V], qa[R][V], pb[R][V], qb[R][V];
-  if (tb < te) load_tile(tb * WT, pa, qa);
-  for (uint64_t tile = tb; tile < te; tile += 2) {
-    if (tile + 1 < te) load_tile((tile + 1) * WT, pb, qb);
-    process(tile, pa, qa);
-    if (tile + 1 >= te) break;
-    if (tile + 2 < te) load_tile((tile + 2) * WT, pa, qa);
-    process(tile + 1, pb, qb);
+  if (tb < tf) {
+    load_full(tb * WT, pa, qa);
+    {
+      // A tile's wait counts the stores issued after its loads and takes the
+      // smallest count over the paths reaching it.  Entering the loop, as
+      // many stores follow the first tile's loads as follow any later
+      // tile's (a full tile issues at most R*V escape stores and 4 rounds
+      // of packed words), so the entry path does not lower that count.
+      __builtin_amdgcn_sched_barrier(0);  // keep them after the loads
+#pragma unroll
+      for (int i = 0; i < R * V + 4; ++i) sinkp[2 * i] = (T)i;  // distinct, never merged
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    for (uint64_t tile = tb;; tile += 2) {
+      const uint64_t n1 = tile + 1 < tf ? tile + 1 : tile;
+      load_full(n1 * WT, pb, qb);
+      process(std::true_type{}, tile, pa, qa);
+      if (tile + 1 >= tf) break;
+      const uint64_t n2 = tile + 2 < tf ? tile + 2 : tile + 1;
+      load_full(n2 * WT, pa, qa);
+      process(std::true_type{}, tile + 1, pb, qb);
+      if (tile + 2 >= tf) break;
+    }
+  }
+  for (uint64_t tile = tf; tile < te; ++tile) {  // at most the array's last tile
+    load_tile(tile * WT, pa, qa);
+    process(std::false_type{}, tile, pa, qa);
   }
   if (lane == 0 && unit < P.n_units) P.unit_cnt[unit] = run;
 }

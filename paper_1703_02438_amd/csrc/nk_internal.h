@@ -42,6 +42,9 @@ constexpr int MAX_SEL = 65535;            // k for B = 16
 #ifndef NK_HIST_TPB
 #define NK_HIST_TPB 512
 #endif
+// Encoder lanes with nothing to store write to a per-wave slot here instead,
+// so every full tile issues the same number of stores (see k_encode).
+constexpr int SINK_SLOTS = 256;
 constexpr int UNIT_TPB = 256;      // 4 units per workgroup
 constexpr int ENC_ROUNDS = NK_ENC_ROUNDS;
 constexpr int DEC_ROUNDS = NK_DEC_ROUNDS;
@@ -87,7 +90,7 @@ struct DCtl {
 
 // Workspace layout of one compression (byte offsets from the workspace base).
 struct Layout {
-  size_t ctl, gwin, lut, sel_tail, sorted_tail, unit_cnt, scratch, tail, hslot,
+  size_t ctl, gwin, lut, sel_tail, sorted_tail, unit_cnt, sink, scratch, tail, hslot,
       hcnt, total;
   uint64_t tail_cap, hcap;
 };
@@ -120,6 +123,7 @@ struct CParams {
   int64_t* sorted_tail;
   uint32_t* unit_cnt;  // incompressible points per encoder unit, then their offsets
   void* scratch;       // incompressible values staged per unit range
+  void* sink;          // SINK_SLOTS x 256 bytes written by masked-off lanes (never read)
   uint32_t n_units;
   uint64_t tiles_per_unit;
   uint32_t* packed;
