@@ -17,9 +17,12 @@
  *     of its index (eq. 4, Sec. III-E), fully or for a range (Sec. V-C).
  *
  * Conventions shared by every entry point:
- *   - All data buffers are device memory owned by the caller.  The library
- *     never allocates device memory and keeps no state between calls except
- *     a per-device count of compute units and the optional timing records.
+ *   - All data buffers are device memory owned by the caller.  The
+ *     compression and decompression entry points never allocate device
+ *     memory; a serving loop (numarck_server_*) allocates its arena once,
+ *     at creation.  State kept between calls: a per-device count of compute
+ *     units, the tunings recorded by numarck_autotune, and the optional
+ *     timing records.
  *   - Calls are asynchronous on `stream` (a hipStream_t; NULL = the null
  *     stream).  The returned status reports argument validation and launch
  *     errors only; data-dependent results (counts, flags) are written to
@@ -187,6 +190,9 @@ typedef struct numarck_tuning {
   uint32_t hist_lds;            /* 1: window counts in LDS (64 KB per workgroup); 0: in global memory */
   uint32_t chunk_vec;           /* 16-byte vectors per streaming chunk of the first two passes */
   uint32_t unit_pct;            /* encoder waves as a percentage of the resident capacity (1..100) */
+  uint32_t stream_loads;        /* input loads of the three passes: 0 automatic (non-temporal when
+                                   a pass streams at least 512 MB and no input is shared between
+                                   jobs), 1 non-temporal, 2 cached */
 } numarck_tuning;
 
 void numarck_tuning_default(numarck_tuning* t);

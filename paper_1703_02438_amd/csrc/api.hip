@@ -270,12 +270,12 @@ static bool tuning_valid(const Tuning& t) {
   return t.range_blocks_per_cu >= 1 && t.range_blocks_per_cu <= 64 &&
          t.hist_blocks_per_cu >= 1 && t.hist_blocks_per_cu <= 16 && t.hist_lds <= 1 &&
          t.chunk_vec >= 64 && t.chunk_vec <= (1u << 20) && t.unit_pct >= 1 &&
-         t.unit_pct <= 100;
+         t.unit_pct <= 100 && t.stream_loads <= 2;
 }
 
 static Tuning to_internal(const numarck_tuning& t) {
   return Tuning{t.range_blocks_per_cu, t.hist_blocks_per_cu, t.hist_lds, t.chunk_vec,
-                t.unit_pct};
+                t.unit_pct, t.stream_loads};
 }
 
 static numarck_tuning to_public(const Tuning& t) {
@@ -285,6 +285,7 @@ static numarck_tuning to_public(const Tuning& t) {
   o.hist_lds = t.hist_lds;
   o.chunk_vec = t.chunk_vec;
   o.unit_pct = t.unit_pct;
+  o.stream_loads = t.stream_loads;
   return o;
 }
 
@@ -364,6 +365,7 @@ numarck_status numarck_autotune(const void* prev, const void* curr, uint64_t n,
   const uint32_t hist[][2] = {{1, 1}, {1, 2}, {1, 4}};
   const uint32_t cvec[] = {1024, 4096, 16384, 65536};
   const uint32_t upct[] = {25, 50, 75, 100};
+  const uint32_t sload[] = {1, 2};
   auto try_one = [&](const Tuning& t) {
     if (st != NUMARCK_OK) return;
     float ms = 0.f;
@@ -377,6 +379,7 @@ numarck_status numarck_autotune(const void* prev, const void* curr, uint64_t n,
   for (auto& h : hist) { Tuning t = cur; t.hist_lds = h[0]; t.hist_blocks_per_cu = h[1]; try_one(t); }
   for (uint32_t v : cvec) { Tuning t = cur; t.chunk_vec = v; try_one(t); }
   for (uint32_t v : upct) { Tuning t = cur; t.unit_pct = v; try_one(t); }
+  for (uint32_t v : sload) { Tuning t = cur; t.stream_loads = v; try_one(t); }
   (void)hipEventDestroy(a);
   (void)hipEventDestroy(b);
   if (st != NUMARCK_OK) return st;
@@ -396,12 +399,13 @@ numarck_status numarck_tuning_save(const char* path) {
     return NUMARCK_EINVAL;
   }
   std::lock_guard<std::mutex> lk(g_tune_mu);
-  fprintf(f, "# dtype log2n range_blocks_per_cu hist_blocks_per_cu hist_lds chunk_vec unit_pct\n");
+  fprintf(f, "# dtype log2n range_blocks_per_cu hist_blocks_per_cu hist_lds chunk_vec unit_pct "
+             "stream_loads\n");
   for (const auto& kv : g_tune) {
     const Tuning& t = kv.second;
-    fprintf(f, "%s %d %u %u %u %u %u\n", kv.first.first == NUMARCK_F32 ? "f32" : "f64",
+    fprintf(f, "%s %d %u %u %u %u %u %u\n", kv.first.first == NUMARCK_F32 ? "f32" : "f64",
             kv.first.second, t.range_blocks_per_cu, t.hist_blocks_per_cu, t.hist_lds,
-            t.chunk_vec, t.unit_pct);
+            t.chunk_vec, t.unit_pct, t.stream_loads);
   }
   fclose(f);
   return NUMARCK_OK;
@@ -422,8 +426,11 @@ numarck_status numarck_tuning_load(const char* path) {
     char dt[8];
     int cls = 0;
     Tuning t{};
-    if (sscanf(line, "%7s %d %u %u %u %u %u", dt, &cls, &t.range_blocks_per_cu,
-               &t.hist_blocks_per_cu, &t.hist_lds, &t.chunk_vec, &t.unit_pct) != 7 ||
+    const int got_n = sscanf(line, "%7s %d %u %u %u %u %u %u", dt, &cls, &t.range_blocks_per_cu,
+                             &t.hist_blocks_per_cu, &t.hist_lds, &t.chunk_vec, &t.unit_pct,
+                             &t.stream_loads);
+    if (got_n == 7) t.stream_loads = 0;  // lines without the last column: automatic
+    if ((got_n != 7 && got_n != 8) ||
         (strcmp(dt, "f32") != 0 && strcmp(dt, "f64") != 0) || cls < 0 || cls > 63 ||
         !tuning_valid(t)) {
       g_last_error = std::string("malformed tuning line: ") + line;
@@ -524,6 +531,20 @@ numarck_status numarck_plan_create(const numarck_job* jobs, uint32_t njobs,
     pl->chunk0[r + 1] = pl->chunk0[r] + stream_chunks(j.n, (int)j.dtype, tn.chunk_vec);
   }
 
+  // a snapshot read by two jobs (consecutive time pairs) is better kept in
+  // the caches between its two reads than streamed past them
+  bool shared_inputs = false;
+  {
+    std::vector<const void*> in;
+    for (uint32_t i = 0; i < njobs; ++i)
+      if (jobs[i].n) {
+        in.push_back(jobs[i].prev);
+        in.push_back(jobs[i].curr);
+      }
+    std::sort(in.begin(), in.end());
+    for (size_t i = 1; i < in.size() && !shared_inputs; ++i) shared_inputs = in[i] == in[i - 1];
+  }
+
   // groups, and encoder units split within each encoder group in proportion
   // to the jobs' tiles (a multiple of 4 per job, at least 4)
   const Geometry G = geometry();
@@ -544,9 +565,13 @@ numarck_status numarck_plan_create(const numarck_job* jobs, uint32_t njobs,
       P.tiles_per_unit = (P.n_tiles + P.n_units - 1) / P.n_units;
       pl->unit0[q + 1] = pl->unit0[q] + P.n_units;
     }
+    uint64_t gbytes = 0;
+    for (uint32_t q = r; q < e; ++q)
+      gbytes += 2 * pl->table[q].n * (dt == NUMARCK_F32 ? 4 : 8);
     JobGroup g{};
     g.dtype = dt;
     g.cls = cls;
+    g.nt = stream_nt_for(tn.stream_loads, gbytes, shared_inputs);
     g.job_begin = r;
     g.job_end = e;
     g.c_begin = pl->chunk0[r];
@@ -562,6 +587,12 @@ numarck_status numarck_plan_create(const numarck_job* jobs, uint32_t njobs,
       pl->dgroups.push_back(g);
     }
     r = e;
+  }
+  for (JobGroup& dg : pl->dgroups) {  // the streaming passes decide per element type
+    uint64_t bytes = 0;
+    for (uint32_t q = dg.job_begin; q < dg.job_end; ++q)
+      bytes += 2 * pl->table[q].n * (dg.dtype == NUMARCK_F32 ? 4 : 8);
+    dg.nt = stream_nt_for(tn.stream_loads, bytes, shared_inputs);
   }
   if ((uint64_t)pl->unit0[njobs] / 4 > 0x7FFFFFFFull) {
     delete pl;

@@ -133,7 +133,7 @@ __device__ void range_flush(Ctl* ctl, unsigned long long& kmin, unsigned long lo
 
 // Streaming chunks [c_begin, c_end), block-strided; a chunk is chunk_vec
 // vectors of one job, and a job's last chunk also takes its scalar tail.
-template <typename T, typename S>
+template <typename T, typename S, bool NT>
 __global__ void __launch_bounds__(RNG_TPB) k_range(S src, Geo g) {
   constexpr int V = Traits<T>::V;
   const int tid = threadIdx.x;
@@ -165,8 +165,8 @@ __global__ void __launch_bounds__(RNG_TPB) k_range(S src, Geo g) {
       for (int u = 0; u < RNG_UNROLL; ++u) {
         const uint64_t vi = vb + (uint64_t)u * RNG_TPB;
         if (vi < v1) {
-          load_vec(prev, vi, pv[u]);
-          load_vec(curr, vi, qv[u]);
+          load_vec_t<NT>(prev, vi, pv[u]);
+          load_vec_t<NT>(curr, vi, qv[u]);
         }
       }
 #pragma unroll
@@ -294,7 +294,7 @@ __device__ __forceinline__ void hist_count(uint32_t* win, bool valid, double m, 
 // when the block moves to another job (or finishes); otherwise count
 // directly in the global counts (more atomic traffic, no LDS, higher
 // occupancy).  Same counts either way.
-template <typename T, typename S, bool LDSH>
+template <typename T, typename S, bool LDSH, bool NT>
 __global__ void __launch_bounds__(HIST_TPB) k_hist(S src, Geo g) {
   constexpr int V = Traits<T>::V;
   __shared__ uint32_t lds[LDSH ? WIN : 1];
@@ -358,8 +358,8 @@ __global__ void __launch_bounds__(HIST_TPB) k_hist(S src, Geo g) {
       for (int u = 0; u < HIST_UNROLL; ++u) {
         const uint64_t vi = vb + (uint64_t)u * HIST_TPB;
         if (vi < v1) {
-          load_vec(prev, vi, pv[u]);
-          load_vec(curr, vi, qv[u]);
+          load_vec_t<NT>(prev, vi, pv[u]);
+          load_vec_t<NT>(curr, vi, qv[u]);
         }
       }
 #pragma unroll
@@ -834,7 +834,7 @@ __global__ void __launch_bounds__(TR_TPB) k_tailrank(S src, Geo g) {
 // packed stream -- or 0 for any B.
 constexpr int ENC_CTAB = 2048;  // LDS centre table when 2^B <= this
 
-template <typename T, typename LT, int PACK, typename S>
+template <typename T, typename LT, int PACK, typename S, bool NT>
 __global__ void __launch_bounds__(UNIT_TPB) k_encode(S src, Geo g) {
   constexpr int V = Traits<T>::V;
   constexpr int R = ENC_ROUNDS;
@@ -892,8 +892,8 @@ __global__ void __launch_bounds__(UNIT_TPB) k_encode(S src, Geo g) {
     for (int r = 0; r < R; ++r) {
       const uint64_t vi = t0 / V + (uint64_t)r * 64 + lane;
       if (vi < nvec) {
-        load_vec(prev, vi, pa[r]);
-        load_vec(curr, vi, qa[r]);
+        load_vec_t<NT>(prev, vi, pa[r]);
+        load_vec_t<NT>(curr, vi, qa[r]);
       } else {
 #pragma unroll
         for (int v = 0; v < V; ++v) {
@@ -1095,8 +1095,8 @@ __global__ void __launch_bounds__(UNIT_TPB) k_encode(S src, Geo g) {
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const uint64_t vi = t0 / V + (uint64_t)r * 64 + lane;
-      load_vec(prev, vi, pa[r]);
-      load_vec(curr, vi, qa[r]);
+      load_vec_t<NT>(prev, vi, pa[r]);
+      load_vec_t<NT>(curr, vi, qa[r]);
     }
   };
   const uint64_t full_tiles = nvec / (WT / V);  // tiles with every vector in range
@@ -1217,20 +1217,24 @@ __device__ void write_header(const CParams& P) {
   } while (0)
 
 // Kernel of an encoder specialisation.
-template <typename T, typename S>
-static void (*encoder_kernel(int cls))(S, Geo) {
+template <typename T, typename S, bool NT>
+static void (*encoder_kernel_nt(int cls))(S, Geo) {
   switch (cls) {
-    case 0: return k_encode<T, uint8_t, 0, S>;
-    case 1: return k_encode<T, uint8_t, 8, S>;
-    case 2: return k_encode<T, uint16_t, 0, S>;
-    default: return k_encode<T, uint16_t, 16, S>;
+    case 0: return k_encode<T, uint8_t, 0, S, NT>;
+    case 1: return k_encode<T, uint8_t, 8, S, NT>;
+    case 2: return k_encode<T, uint16_t, 0, S, NT>;
+    default: return k_encode<T, uint16_t, 16, S, NT>;
   }
+}
+template <typename T, typename S>
+static void (*encoder_kernel(int cls, bool nt))(S, Geo) {
+  return nt ? encoder_kernel_nt<T, S, true>(cls) : encoder_kernel_nt<T, S, false>(cls);
 }
 
 template <typename S>
 static int encoder_occupancy_t(int dtype, int cls) {
-  void (*k)(S, Geo) = dtype == NUMARCK_F32 ? encoder_kernel<float, S>(cls)
-                                           : encoder_kernel<double, S>(cls);
+  void (*k)(S, Geo) = dtype == NUMARCK_F32 ? encoder_kernel<float, S>(cls, false)
+                                           : encoder_kernel<double, S>(cls, false);
   int occ = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k, UNIT_TPB, 0) != hipSuccess || occ < 1)
     occ = 1;
@@ -1241,10 +1245,11 @@ int encoder_occupancy(int dtype, int cls, bool table) {
   return table ? encoder_occupancy_t<JobTable>(dtype, cls) : encoder_occupancy_t<OneJob>(dtype, cls);
 }
 
-Tuning default_tuning() { return Tuning{8u, 2u, 1u, 4096u, 100u}; }
+Tuning default_tuning() { return Tuning{8u, 2u, 1u, 4096u, 100u, 0u}; }
 
 static Geo group_geo(const Geo& base, const JobGroup& jg) {
   Geo g = base;
+  g.stream_nt = jg.nt;
   g.job_begin = jg.job_begin;
   g.job_end = jg.job_end;
   g.c_begin = jg.c_begin;
@@ -1280,10 +1285,14 @@ static hipError_t run_chain(S src, const Geo& base, uint32_t njobs, const JobGro
     const uint64_t chunks = g.c_end - g.c_begin;
     if (!chunks) continue;
     const uint64_t blocks = clamp_blocks(chunks, (uint64_t)G.cus * tn.range_blocks_per_cu);
-    if (dg[i].dtype == NUMARCK_F32)
-      NK_LAUNCH(KK_RANGE, (k_range<float, S>), blocks, RNG_TPB, src, g);
-    else
-      NK_LAUNCH(KK_RANGE, (k_range<double, S>), blocks, RNG_TPB, src, g);
+    const bool f32 = dg[i].dtype == NUMARCK_F32;
+    if (g.stream_nt) {
+      if (f32) NK_LAUNCH(KK_RANGE, (k_range<float, S, true>), blocks, RNG_TPB, src, g);
+      else NK_LAUNCH(KK_RANGE, (k_range<double, S, true>), blocks, RNG_TPB, src, g);
+    } else {
+      if (f32) NK_LAUNCH(KK_RANGE, (k_range<float, S, false>), blocks, RNG_TPB, src, g);
+      else NK_LAUNCH(KK_RANGE, (k_range<double, S, false>), blocks, RNG_TPB, src, g);
+    }
   }
   NK_LAUNCH(KK_DERIVE, k_derive<S>, njobs, 64, src, all);
   for (uint32_t i = 0; i < ndg; ++i) {
@@ -1292,12 +1301,18 @@ static hipError_t run_chain(S src, const Geo& base, uint32_t njobs, const JobGro
     if (!chunks) continue;
     const uint64_t blocks = clamp_blocks(chunks, (uint64_t)G.cus * tn.hist_blocks_per_cu);
     const bool f32 = dg[i].dtype == NUMARCK_F32;
+    const bool nt = g.stream_nt != 0;
     if (tn.hist_lds) {
-      if (f32) NK_LAUNCH(KK_HIST, (k_hist<float, S, true>), blocks, HIST_TPB, src, g);
-      else NK_LAUNCH(KK_HIST, (k_hist<double, S, true>), blocks, HIST_TPB, src, g);
-    } else {
-      if (f32) NK_LAUNCH(KK_HIST, (k_hist<float, S, false>), blocks, HIST_TPB, src, g);
-      else NK_LAUNCH(KK_HIST, (k_hist<double, S, false>), blocks, HIST_TPB, src, g);
+      if (f32) {
+        if (nt) NK_LAUNCH(KK_HIST, (k_hist<float, S, true, true>), blocks, HIST_TPB, src, g);
+        else NK_LAUNCH(KK_HIST, (k_hist<float, S, true, false>), blocks, HIST_TPB, src, g);
+      } else {
+        if (nt) NK_LAUNCH(KK_HIST, (k_hist<double, S, true, true>), blocks, HIST_TPB, src, g);
+        else NK_LAUNCH(KK_HIST, (k_hist<double, S, true, false>), blocks, HIST_TPB, src, g);
+      }
+    } else {  // global counts: the chosen few; streamed inputs are cached
+      if (f32) NK_LAUNCH(KK_HIST, (k_hist<float, S, false, false>), blocks, HIST_TPB, src, g);
+      else NK_LAUNCH(KK_HIST, (k_hist<double, S, false, false>), blocks, HIST_TPB, src, g);
     }
   }
   NK_LAUNCH(KK_HCLEAR, k_hclear<S>, dim3((unsigned)aux, njobs), 256, src, all);
@@ -1317,8 +1332,9 @@ static hipError_t run_chain(S src, const Geo& base, uint32_t njobs, const JobGro
     const Geo g = group_geo(base, eg[i]);
     const uint32_t blocks = (g.u_end - g.u_begin) / 4;
     if (!blocks) continue;
-    void (*k)(S, Geo) = eg[i].dtype == NUMARCK_F32 ? encoder_kernel<float, S>(eg[i].cls)
-                                                   : encoder_kernel<double, S>(eg[i].cls);
+    void (*k)(S, Geo) = eg[i].dtype == NUMARCK_F32
+                            ? encoder_kernel<float, S>(eg[i].cls, g.stream_nt != 0)
+                            : encoder_kernel<double, S>(eg[i].cls, g.stream_nt != 0);
     NK_LAUNCH(KK_ENCODE, k, blocks, UNIT_TPB, src, g);
   }
   NK_LAUNCH(KK_USCAN, k_uscan<S>, njobs, USCAN_TPB, src, all);
@@ -1360,6 +1376,8 @@ hipError_t launch_compress(const CParams& P0, const Tuning& tn, hipStream_t s) {
   grp.c_end = stream_chunks(P.n, P.dtype, tn.chunk_vec);
   grp.u_begin = 0;
   grp.u_end = P.n_units;
+  grp.nt = stream_nt_for(tn.stream_loads, 2 * P.n * (P.dtype == NUMARCK_F32 ? 4 : 8),
+                         P.prev == P.curr);
   return run_chain(OneJob{P}, base, 1, &grp, 1, &grp, 1, tn, s);
 }
 

@@ -29,6 +29,21 @@ __device__ __forceinline__ void load_vec(const T* __restrict__ base, uint64_t vi
   __builtin_memcpy(out, &x, 16);
 }
 
+// The same load, marked non-temporal when NT: streamed data that will not
+// be read again then does not displace what will (the written outputs,
+// inputs shared with another job of a batch).  A compile-time choice: the
+// compiler merges a run-time choice between the two into one cached load.
+template <bool NT, typename T>
+__device__ __forceinline__ void load_vec_t(const T* __restrict__ base, uint64_t vi, T* out) {
+  if constexpr (NT) {
+    typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+    const u32x4 x = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(base) + vi);
+    __builtin_memcpy(out, &x, 16);
+  } else {
+    load_vec(base, vi, out);
+  }
+}
+
 // Order-preserving map of binary64 to uint64: numeric order, -0 below +0.
 __device__ __forceinline__ unsigned long long order_key(double x) {
   unsigned long long b = (unsigned long long)__double_as_longlong(x);

@@ -172,6 +172,7 @@ struct Geo {
   uint64_t c_begin, c_end;  // streaming chunks of this launch
   uint32_t u_begin, u_end;  // encoder units of this launch
   uint32_t chunk_vec;       // 16-byte vectors per streaming chunk
+  uint32_t stream_nt;       // input loads of the streaming passes are non-temporal
 };
 
 // Launch parameters a tuner may change (none changes any output).
@@ -181,6 +182,7 @@ struct Tuning {
   uint32_t hist_lds;             // 1: LDS window counts, 0: global window counts
   uint32_t chunk_vec;            // 16-byte vectors per streaming chunk
   uint32_t unit_pct;             // encoder units, % of the resident capacity
+  uint32_t stream_loads;         // 0: automatic, 1: non-temporal, 2: cached
 };
 Tuning default_tuning();
 
@@ -189,11 +191,22 @@ Tuning default_tuning();
 struct JobGroup {
   int dtype;
   int cls;
+  uint32_t nt;  // streaming loads non-temporal for this group
   uint32_t job_begin, job_end;
   uint64_t c_begin, c_end;
   uint32_t u_begin, u_end;
 };
 inline int enc_class(uint32_t B) { return B < 8 ? 0 : B == 8 ? 1 : B < 16 ? 2 : 3; }
+
+// Input bytes per pass above which a streaming pass gains nothing from
+// caching its inputs (well past the 256 MB Infinity Cache).
+constexpr uint64_t NT_STREAM_BYTES = 512ull << 20;
+// Non-temporal input loads for a group streaming `bytes` per pass?
+inline uint32_t stream_nt_for(uint32_t mode, uint64_t bytes, bool shared_inputs) {
+  if (mode == 1) return 1u;
+  if (mode == 2) return 0u;
+  return (bytes >= NT_STREAM_BYTES && !shared_inputs) ? 1u : 0u;
+}
 
 // Elements of one encoder / decoder wave tile for an element size (16-byte vectors).
 inline uint64_t enc_wave_tile(uint64_t elem_bytes) { return ENC_ROUNDS * 64 * (16 / elem_bytes); }

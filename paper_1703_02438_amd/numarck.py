@@ -54,7 +54,7 @@ class NumarckTuning(ctypes.Structure):
     _fields_ = [
         ("range_blocks_per_cu", ctypes.c_uint32), ("hist_blocks_per_cu", ctypes.c_uint32),
         ("hist_lds", ctypes.c_uint32), ("chunk_vec", ctypes.c_uint32),
-        ("unit_pct", ctypes.c_uint32),
+        ("unit_pct", ctypes.c_uint32), ("stream_loads", ctypes.c_uint32),
     ]
 
     def as_dict(self) -> dict:

@@ -155,7 +155,7 @@ def test_plan_validation_without_gpu(nk):
     assert create(bad, 2) == nk.EBOUND
     bad = (nk.NumarckJob * 1)(_job(nk, base=0x300008))
     assert create(bad, 1) == nk.EALIGN
-    t = nk.NumarckTuning(8, 2, 1, 4096, 0)  # unit_pct 0
+    t = nk.NumarckTuning(8, 2, 1, 4096, 0, 0)  # unit_pct 0
     assert create(jobs, 3, t=ctypes.byref(t)) == nk.EINVAL
     assert not h.value
     assert nk.numarck_plan_run(None, None) == nk.EINVAL
@@ -166,16 +166,17 @@ def test_plan_validation_without_gpu(nk):
 def test_tuning_defaults_and_files(nk, tmp_path):
     t = nk.default_tuning()
     assert t.as_dict() == {"range_blocks_per_cu": 8, "hist_blocks_per_cu": 2, "hist_lds": 1,
-                           "chunk_vec": 4096, "unit_pct": 100}
+                           "chunk_vec": 4096, "unit_pct": 100, "stream_loads": 0}
     good = tmp_path / "good.txt"
-    good.write_text("# comment\nf64 27 4 2 1 8192 75\nf32 20 8 4 0 2048 100\n")
+    good.write_text("# comment\nf64 27 4 2 1 8192 75 1\nf32 20 8 4 0 2048 100\n")
     assert nk.numarck_tuning_load(str(good).encode()) == nk.OK
     out = tmp_path / "out.txt"
     assert nk.numarck_tuning_save(str(out).encode()) == nk.OK
     lines = [ln for ln in out.read_text().splitlines() if not ln.startswith("#")]
-    assert "f64 27 4 2 1 8192 75" in lines and "f32 20 8 4 0 2048 100" in lines
+    assert "f64 27 4 2 1 8192 75 1" in lines and "f32 20 8 4 0 2048 100 0" in lines
     for bad in ("f16 3 1 1 1 64 1\n", "f64 3 0 1 1 64 1\n", "f64 3 1 1 2 64 1\n",
-                "f64 3 1 1 1 63 1\n", "f64 3 1 1 1 64 101\n", "f64 3 1 1\n"):
+                "f64 3 1 1 1 63 1\n", "f64 3 1 1 1 64 101\n", "f64 3 1 1\n",
+                "f64 3 1 1 1 64 1 3\n"):
         p = tmp_path / "bad.txt"
         p.write_text(bad)
         assert nk.numarck_tuning_load(str(p).encode()) == nk.EINVAL, bad
@@ -184,7 +185,7 @@ def test_tuning_defaults_and_files(nk, tmp_path):
 
 def test_compress_tuned_validation_without_gpu(nk):
     o = _out(nk)
-    bad = nk.NumarckTuning(8, 2, 1, 32, 100)  # chunk_vec below 64
+    bad = nk.NumarckTuning(8, 2, 1, 32, 100, 0)  # chunk_vec below 64
     st = nk.numarck_compress_tuned(0x300000, 0x400000, 10, nk.F64, 1e-3, 8, 0, ctypes.byref(o),
                                    0x200000, 1 << 40, ctypes.byref(bad), None)
     assert st == nk.EINVAL

@@ -164,9 +164,9 @@ def test_tunings_change_no_output(nk):
     p, q = mixture_case(300001, 4242, np.float64)
     P, Q = _dev(p), _dev(q)
     ref = nk.compress(P, Q, 1e-3, 8, recon=True, bin_ids=True)
-    for rb, hb, hl, cv, up in [(1, 1, 1, 64, 1), (16, 4, 0, 16384, 50), (64, 16, 0, 1 << 20, 100),
-                               (3, 2, 1, 777, 33)]:
-        t = nk.NumarckTuning(rb, hb, hl, cv, up)
+    for rb, hb, hl, cv, up, sl in [(1, 1, 1, 64, 1, 1), (16, 4, 0, 16384, 50, 2),
+                                   (64, 16, 0, 1 << 20, 100, 0), (3, 2, 1, 777, 33, 1)]:
+        t = nk.NumarckTuning(rb, hb, hl, cv, up, sl)
         c = nk.compress_tuned(P, Q, 1e-3, 8, t)
         assert_same_compression(c, ref, f"tuning {t.as_dict()}")
         plan, _, res = _run_plan(nk, [(p, q, 1e-3, 8, 0)], tune=t)
