@@ -230,6 +230,9 @@ typedef struct numarck_job {
   uint32_t B;
   uint64_t block_bytes;  /* 0 = 2^20 */
   numarck_out out;
+  uint64_t tail_cap;     /* points outside the on-chip bin window the job's workspace can hold
+                            (0 or >= n: n, which never overflows); a smaller capacity shrinks the
+                            workspace, and data needing more sets NUMARCK_FLAG_TAIL_OVERFLOW */
 } numarck_job;
 
 /* Most jobs in one batch (one grid row per job in the per-job passes). */
@@ -240,7 +243,7 @@ typedef struct numarck_job {
  * kernels, so it can be captured into a HIP graph and replayed. */
 typedef struct numarck_plan numarck_plan;
 
-/* Workspace bytes for a batch (every job with full tail capacity). */
+/* Workspace bytes for a batch (each job with its tail_cap). */
 size_t numarck_batch_workspace_bytes(const numarck_job* jobs, uint32_t njobs);
 /* Validate the jobs, lay out the workspace and copy the job table to it on
  * `stream` (asynchronous).  tune = NULL: defaults.  *plan is host memory owned
@@ -272,8 +275,12 @@ numarck_status numarck_compress_batch(const numarck_job* jobs, uint32_t njobs, v
  * is admitted when its record and workspace fit in the arena; otherwise it
  * waits for memory to be released.  Range requests decompress part of the
  * variable's latest record (the record of its last compression submitted
- * before the range request).  Results are identical to numarck_compress /
- * numarck_decompress_range called on each request alone. */
+ * before the range request).  A compression first runs with a bounded tail
+ * capacity (n / 16 points outside the on-chip bin window, at least 2^20),
+ * which keeps its workspace near n * L bytes; if the data needs more, it is
+ * run again with full capacity before anything else of its variable.
+ * Results are identical to numarck_compress / numarck_decompress_range
+ * called on each request alone. */
 typedef struct numarck_server numarck_server;
 
 typedef struct numarck_server_config {
@@ -323,6 +330,7 @@ typedef struct numarck_server_stats {
   uint64_t submitted, completed, batches, max_batch_seen;
   uint64_t arena_capacity, arena_peak, resident_bytes;
   uint64_t waits_for_memory; /* scheduler passes that left an eligible request queued for lack of memory */
+  uint64_t tail_retries;     /* compressions run again with full tail capacity (see below) */
 } numarck_server_stats;
 
 /* Create a server (allocates the arena with hipMalloc, creates the streams

@@ -470,8 +470,12 @@ static size_t batch_head_bytes(uint32_t njobs) {
          align256((size_t)(njobs + 1) * 4);
 }
 
+static uint64_t job_tail_cap(const numarck_job& j) {
+  return (j.tail_cap == 0 || j.tail_cap > j.n) ? j.n : j.tail_cap;
+}
+
 static size_t job_slice_bytes(const numarck_job& j) {
-  return align256(compress_layout(j.n, j.dtype == NUMARCK_F32 ? 4 : 8, j.n).total);
+  return align256(compress_layout(j.n, j.dtype == NUMARCK_F32 ? 4 : 8, job_tail_cap(j)).total);
 }
 
 }  // namespace nk
@@ -524,7 +528,7 @@ numarck_status numarck_plan_create(const numarck_job* jobs, uint32_t njobs,
   for (uint32_t r = 0; r < njobs; ++r) {
     const numarck_job& j = jobs[order[r]];
     const uint64_t eb = j.dtype == NUMARCK_F32 ? 4 : 8;
-    const Layout L = compress_layout(j.n, eb, j.n);
+    const Layout L = compress_layout(j.n, eb, job_tail_cap(j));
     pl->table[r] = make_params(j.prev, j.curr, j.n, j.dtype, j.E, j.B, j.block_bytes, &j.out,
                                base + off, L);
     off += align256(L.total);

@@ -93,18 +93,21 @@ struct Variable {
   bool busy = false;
   uint64_t queued = 0;  // requests waiting
   RecordLayout rl;
-  uint64_t need;  // largest transient block one request of it takes
+  uint64_t tail_small;  // tail capacity of a first attempt (a bounded workspace)
+  uint64_t need;        // largest transient block one request of it can take
 };
 
 struct Pending {
   numarck_request r;
   double submit_us;
+  bool full_tail;  // a retry with the tail capacity that cannot overflow
 };
 
 struct Item {
   uint64_t ticket;
   uint32_t var, kind;
   const void* curr = nullptr;     // COMPRESS: the new snapshot
+  bool full_tail = false;         // COMPRESS: workspace with full tail capacity
   Record rec;                     // COMPRESS: the new record
   uint64_t ws_off = Arena::kFail;  // RANGE: workspace + flags block
   uint64_t bytes;
@@ -140,7 +143,7 @@ struct numarck_server {
   std::thread thr;
   bool stop = false;
   uint64_t next_ticket = 1, submitted = 0, completed = 0, batches = 0, max_batch_seen = 0;
-  uint64_t resident = 0, waits = 0;
+  uint64_t resident = 0, waits = 0, tail_retries = 0;
   uint64_t permanent = 0;  // arena bytes held by record blocks
   std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
 
@@ -186,6 +189,19 @@ bool numarck_server::retire() {
     for (size_t i = 0; i < s.comp.size(); ++i) {
       Item& it = s.comp[i];
       Variable& v = vars[it.var];
+      if (st == NUMARCK_OK && (s.pin_hdr[i].flags & NUMARCK_FLAG_TAIL_OVERFLOW) && !it.full_tail) {
+        // the bounded tail did not hold this snapshot's out-of-window points:
+        // run it again, first in its variable's queue, with full capacity
+        numarck_request r{};
+        r.kind = NUMARCK_REQ_COMPRESS;
+        r.var = it.var;
+        r.curr = it.curr;
+        pending[it.ticket] = Pending{r, it.submit_us, true};
+        ++v.queued;
+        v.busy = false;
+        ++tail_retries;
+        continue;
+      }
       if (st == NUMARCK_OK) {  // the new record becomes the latest
         it.rec.hdr = s.pin_hdr[i];
         v.rec = it.rec;
@@ -242,6 +258,7 @@ bool numarck_server::launch() {
     item.var = r.var;
     item.kind = r.kind;
     item.submit_us = it->second.submit_us;
+    item.full_tail = it->second.full_tail;
     if (r.kind == NUMARCK_REQ_COMPRESS) {
       if (comp.size() >= cfg.max_batch) {
         taken.push_back(r.var);  // keep its later requests behind it
@@ -300,6 +317,7 @@ bool numarck_server::launch() {
       j.B = v.B;
       j.block_bytes = v.bb;
       j.out = c.rec.out;
+      j.tail_cap = c.full_tail ? 0 : v.tail_small;
       jobs.push_back(j);
     }
     ws_off = arena.alloc(numarck_batch_workspace_bytes(jobs.data(), (uint32_t)jobs.size()));
@@ -489,11 +507,14 @@ numarck_status numarck_server_add_variable(numarck_server* s, uint64_t n, numarc
   v.bb = block_bytes;
   v.ref = initial;
   v.rl = record_layout(n, dtype, B, block_bytes);
+  // first attempts use a bounded tail; a retry needs the full capacity
+  const uint64_t small = n / 16 > ((uint64_t)1 << 20) ? n / 16 : ((uint64_t)1 << 20);
+  v.tail_small = small < n ? small : n;
   numarck_job j{};
   j.n = n;
   j.dtype = dtype;
   j.B = B;
-  const uint64_t slice = numarck_batch_workspace_bytes(&j, 1);
+  const uint64_t slice = numarck_batch_workspace_bytes(&j, 1);  // tail_cap 0: full
   const uint64_t rws = range_ws_bytes(n);
   v.need = slice > rws ? slice : rws;
   std::lock_guard<std::mutex> lk(s->mu);
@@ -537,7 +558,7 @@ numarck_status numarck_server_submit(numarck_server* s, const numarck_request* r
     return NUMARCK_EINVAL;
   }
   const uint64_t t = s->next_ticket++;
-  s->pending[t] = Pending{*r, s->now_us()};
+  s->pending[t] = Pending{*r, s->now_us(), false};
   ++s->vars[r->var].queued;
   ++s->submitted;
   if (ticket) *ticket = t;
@@ -604,6 +625,7 @@ numarck_status numarck_server_get_stats(numarck_server* s, numarck_server_stats*
   st->arena_peak = s->arena.peak();
   st->resident_bytes = s->resident;
   st->waits_for_memory = s->waits;
+  st->tail_retries = s->tail_retries;
   return NUMARCK_OK;
 }
 

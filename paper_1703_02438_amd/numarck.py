@@ -65,7 +65,7 @@ class NumarckJob(ctypes.Structure):
     _fields_ = [
         ("prev", ctypes.c_void_p), ("curr", ctypes.c_void_p), ("n", ctypes.c_uint64),
         ("dtype", ctypes.c_int), ("E", ctypes.c_double), ("B", ctypes.c_uint32),
-        ("block_bytes", ctypes.c_uint64), ("out", NumarckOut),
+        ("block_bytes", ctypes.c_uint64), ("out", NumarckOut), ("tail_cap", ctypes.c_uint64),
     ]
 
 
@@ -100,7 +100,7 @@ class NumarckCompletion(ctypes.Structure):
 class NumarckServerStats(ctypes.Structure):
     _fields_ = [(f, ctypes.c_uint64) for f in (
         "submitted", "completed", "batches", "max_batch_seen", "arena_capacity", "arena_peak",
-        "resident_bytes", "waits_for_memory")]
+        "resident_bytes", "waits_for_memory", "tail_retries")]
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -334,6 +334,7 @@ class BatchJob:
     E: float
     B: int
     block_bytes: int = 0
+    tail_cap: int = 0  # 0: n (never overflows)
 
 
 class Plan:
@@ -356,7 +357,7 @@ class Plan:
             o = outputs[i] if outputs is not None else alloc_outputs(
                 p.numel(), p.dtype, j.B, j.block_bytes, recon, bin_ids, p.device)
             arr[i] = NumarckJob(_ptr(p), _ptr(q), p.numel(), dtype_code(p.dtype), float(j.E),
-                                int(j.B), int(j.block_bytes), out_struct(o))
+                                int(j.B), int(j.block_bytes), out_struct(o), int(j.tail_cap))
             self.jobs.append((p, q, j))
             self.outputs.append(o)
         self._arr = arr
@@ -406,7 +407,7 @@ def compress_batch(jobs: list[BatchJob], recon: bool = False, bin_ids: bool = Fa
         p, q = j.prev.reshape(-1), j.curr.reshape(-1)
         o = alloc_outputs(p.numel(), p.dtype, j.B, j.block_bytes, recon, bin_ids, p.device)
         arr[i] = NumarckJob(_ptr(p), _ptr(q), p.numel(), dtype_code(p.dtype), float(j.E),
-                            int(j.B), int(j.block_bytes), out_struct(o))
+                            int(j.B), int(j.block_bytes), out_struct(o), int(j.tail_cap))
         outs.append((p, o))
     dev = jobs[0].prev.device
     ws = torch.empty(max(numarck_batch_workspace_bytes(arr, len(jobs)), 1), dtype=torch.uint8,

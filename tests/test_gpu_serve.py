@@ -179,3 +179,30 @@ def test_capacity_and_ready_event(nk):
     with pytest.raises(nk.NumarckError):
         srv.range(v, 49990, 11)
     srv.close()
+
+
+def test_bounded_tail_retry(nk):
+    """A first attempt runs with a bounded tail capacity (here 2^20 of 4M
+    points); data with more points outside the on-chip bin window overflows
+    it and is run again with full capacity: the record and a range of it
+    equal the plain call's, and the retry is counted."""
+    n = 4 << 20
+    rng = np.random.default_rng(1713)
+    p = rng.lognormal(0.0, 1.0, n)
+    r = np.where(rng.random(n) < 0.6, rng.normal(0, 1e-4, n), rng.uniform(0.3, 3.0, n))
+    snaps = [torch.from_numpy(p).to("cuda"), torch.from_numpy(p * (1 + r)).to("cuda")]
+    srv = nk.Server(budget_bytes=8 << 30, arena_bytes=2 << 30, slots=2, max_batch=4)
+    v = srv.add_variable(snaps[0], 1e-5, 12)
+    torch.cuda.synchronize()
+    srv.compress(v, snaps[1])
+    t, part = srv.range(v, n - 5000, 4000)
+    srv.drain()
+    done = {c["ticket"]: c for c in srv.poll()}
+    assert all(c["status"] == nk.OK and c["flags"] == 0 for c in done.values()), done
+    assert srv.stats()["tail_retries"] == 1
+    plain = nk.compress(snaps[0], snaps[1], 1e-5, 12)
+    assert plain.header().tail_count > (1 << 20)
+    assert_same_compression(srv.fetch(v), plain, "after the retry")
+    ref, fl = nk.decompress_range(plain, snaps[0], n - 5000, 4000)
+    assert torch.equal(part[:4000].view(torch.int64), ref[:4000].view(torch.int64))
+    srv.close()
