@@ -285,7 +285,7 @@ __device__ __forceinline__ void hist_count(uint32_t* win, bool valid, double m, 
     base = ((unsigned long long)hi32 << 32) | lo32;
     if (tail) {
       const unsigned long long pos = base + (unsigned long long)__popcll(tm & lanemask_lt());
-      if (pos < ts.cap) ts.list[pos] = (long long)m;
+      if (pos < ts.cap) gstore(ts.list + pos, (int64_t)m);
     }
   }
 }
@@ -562,7 +562,6 @@ template <typename F>
 __device__ __forceinline__ void sel_visit(const CParams& P, const SelShared& S, long long wbase,
                                           unsigned win_len, bool tail, unsigned long long H, F f) {
   (void)win_len;
-#pragma unroll 4
   for (unsigned w = threadIdx.x; w < (unsigned)WIN; w += SEL_TPB)
     f(wbase + (long long)w, S.win[w]);  // bins past win_len hold 0
   if (tail) {
@@ -845,6 +844,12 @@ __global__ void __launch_bounds__(UNIT_TPB) k_encode(S src, Geo g) {
   __shared__ LT s_lut[WIN];
   __shared__ double s_ctab[NCTAB];
   __shared__ IT s_idx[NWAVE][WT];
+  // float64 full tiles stage up to 64 escapes in LDS and write them with one
+  // store; float32 tiles (8 element slots per lane, a compute-bound loop)
+  // store each slot directly, lanes without an escape writing the sink
+  constexpr bool STAGE = V == 2;
+  constexpr int ESC_STAGE = 64;
+  __shared__ T s_esc[NWAVE][STAGE ? ESC_STAGE : 1];
 
   // the 4 units of a workgroup belong to one job (jobs own multiples of 4)
   const uint32_t ublk = g.u_begin + blockIdx.x * NWAVE;
@@ -866,10 +871,10 @@ __global__ void __launch_bounds__(UNIT_TPB) k_encode(S src, Geo g) {
   const uint32_t B = P.B;
   const bool fast = P.fastbin != 0;
   const bool use_ctab = ((uint32_t)1 << B) <= (uint32_t)NCTAB;
-  for (int i = tid; i < WIN; i += UNIT_TPB) s_lut[i] = (LT)P.lut[i];
+  for (int i = tid; i < WIN; i += UNIT_TPB) s_lut[i] = (LT)gload(P.lut + i);
   if (use_ctab) {
     const T* cen = static_cast<const T*>(P.centers);
-    for (int i = tid; i < (1 << B); i += UNIT_TPB) s_ctab[i] = (double)cen[i];
+    for (int i = tid; i < (1 << B); i += UNIT_TPB) s_ctab[i] = (double)gload(cen + i);
   }
   __syncthreads();
 
@@ -898,8 +903,8 @@ __global__ void __launch_bounds__(UNIT_TPB) k_encode(S src, Geo g) {
 #pragma unroll
         for (int v = 0; v < V; ++v) {
           const uint64_t j = vi * V + v;
-          pa[r][v] = j < P.n ? prev[j] : (T)0;
-          qa[r][v] = j < P.n ? curr[j] : (T)0;
+          pa[r][v] = j < P.n ? gload(prev + j) : (T)0;
+          qa[r][v] = j < P.n ? gload(curr + j) : (T)0;
         }
       }
     }
@@ -953,9 +958,9 @@ __global__ void __launch_bounds__(UNIT_TPB) k_encode(S src, Geo g) {
             unsigned a = 0, b = nsel_tail;
             while (a < b) {
               const unsigned mid = (a + b) >> 1;
-              if (P.sorted_tail[mid] < mi) a = mid + 1; else b = mid;
+              if (gload(P.sorted_tail + mid) < mi) a = mid + 1; else b = mid;
             }
-            if (a < nsel_tail && P.sorted_tail[a] == mi)
+            if (a < nsel_tail && gload(P.sorted_tail + a) == mi)
               code = a + (mi > wbase ? nsel_win : 0u);
           }
         }
@@ -981,12 +986,14 @@ __global__ void __launch_bounds__(UNIT_TPB) k_encode(S src, Geo g) {
         if (FULL || vi < nvec) {
           uint4 xv;
           __builtin_memcpy(&xv, pv[r], 16);
-          reinterpret_cast<uint4*>(recon)[vi] = xv;
+          nk_u32x4 yv;
+          __builtin_memcpy(&yv, &xv, 16);
+          gstore(reinterpret_cast<nk_u32x4*>(recon) + vi, yv);
         } else {
 #pragma unroll
           for (int v = 0; v < V; ++v) {
             const uint64_t j = vi * V + v;
-            if (j < P.n) recon[j] = pv[r][v];
+            if (j < P.n) gstore(recon + j, pv[r][v]);
           }
         }
       }
@@ -998,6 +1005,7 @@ __global__ void __launch_bounds__(UNIT_TPB) k_encode(S src, Geo g) {
     const bool any_b = first_b < t0 + lim;
     const bool one_b = P.epb >= (uint64_t)WT;
     const uint32_t b_local = (uint32_t)(first_b - t0);
+    const unsigned run0 = run;  // escapes of the range before this tile
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       unsigned below = 0, all = 0;
@@ -1016,13 +1024,17 @@ __global__ void __launch_bounds__(UNIT_TPB) k_encode(S src, Geo g) {
           const uint64_t j = t0 + e0 + v;
           const bool at_b =
               e0 + v < lim && (one_b ? (e0 + v == b_local) : (j % P.epb == 0));
-          if (at_b) P.block_inc_off[j / P.epb] = (long long)rank;
+          if (at_b) gstore(P.block_inc_off + j / P.epb, (int64_t)rank);
         }
         const bool escp = (emask[r][v] >> lane) & 1ull;
-        if (FULL) {  // every lane stores: the escape, or into the sink
-          *(escp ? scratch + e_base + rank : sinkp) = qv[r][v];
+        if (FULL && !STAGE) {  // every lane stores: the escape, or into the sink
+          gstore(escp ? scratch + e_base + rank : sinkp, qv[r][v]);
         } else if (escp) {
-          scratch[e_base + rank] = qv[r][v];
+          const unsigned tl = rank - run0;  // rank within the tile
+          if (FULL && tl < (unsigned)ESC_STAGE)
+            s_esc[wave][tl] = qv[r][v];  // written below, one store for the tile
+          else
+            gstore(scratch + e_base + rank, qv[r][v]);
         }
         rank += escp ? 1u : 0u;
       }
@@ -1031,6 +1043,11 @@ __global__ void __launch_bounds__(UNIT_TPB) k_encode(S src, Geo g) {
 
     // bit-pack the wave tile: word w holds bits [32w, 32w + 32) of its stream
     wave_lds_sync();
+    if (FULL && STAGE) {  // the staged escapes: lane i writes the tile's i-th, the others the sink
+      const bool has = (unsigned)lane < run - run0;
+      const T val = s_esc[wave][lane];
+      gstore(has ? scratch + e_base + run0 + lane : sinkp, val);
+    }
     const uint64_t word0 = t0 * B / 32;
     if (PACK != 0) {
       // 8- or 16-bit indices: the index array is the packed stream
@@ -1038,10 +1055,10 @@ __global__ void __launch_bounds__(UNIT_TPB) k_encode(S src, Geo g) {
       if (FULL) {
         constexpr uint32_t TW = (uint32_t)(WT * (PACK != 0 ? PACK : 8) / 32);  // a multiple of 64
 #pragma unroll
-        for (uint32_t w = lane; w < TW; w += 64) P.packed[word0 + w] = iw[w];
+        for (uint32_t w = lane; w < TW; w += 64) gstore(P.packed + word0 + w, iw[w]);
       } else {
         for (uint32_t w = lane; w < tile_words; w += 64)
-          if (word0 + w < P.packed_words) P.packed[word0 + w] = iw[w];
+          if (word0 + w < P.packed_words) gstore(P.packed + word0 + w, iw[w]);
       }
     } else if (FULL) {
       // at most B = 7 (u8 indices) or 15 (u16) bits: a fixed number of store
@@ -1063,7 +1080,7 @@ __global__ void __launch_bounds__(UNIT_TPB) k_encode(S src, Geo g) {
             word |= sh >= 0 ? (v << sh) : (v >> (-sh));
           }
         }
-        *(in ? P.packed + word0 + w : reinterpret_cast<uint32_t*>(sinkp)) = word;
+        gstore(in ? P.packed + word0 + w : reinterpret_cast<uint32_t*>(sinkp), word);
       }
     } else {
       for (uint32_t w = lane; w < tile_words; w += 64) {
@@ -1078,7 +1095,7 @@ __global__ void __launch_bounds__(UNIT_TPB) k_encode(S src, Geo g) {
           const int sh = (int)(e * B) - (int)bit0;
           word |= sh >= 0 ? (v << sh) : (v >> (-sh));
         }
-        P.packed[word0 + w] = word;
+        gstore(P.packed + word0 + w, word);
       }
     }
     wave_lds_sync();
@@ -1108,11 +1125,12 @@ __global__ void __launch_bounds__(UNIT_TPB) k_encode(S src, Geo g) {
       // A tile's wait counts the stores issued after its loads and takes the
       // smallest count over the paths reaching it.  Entering the loop, as
       // many stores follow the first tile's loads as follow any later
-      // tile's (a full tile issues at most R*V escape stores and 4 rounds
-      // of packed words), so the entry path does not lower that count.
+      // tile's (a full tile issues at most R*V escape stores and 4 rounds of
+      // packed words, plus rare extra ones), so the entry path does not
+      // lower that count.
       __builtin_amdgcn_sched_barrier(0);  // keep them after the loads
 #pragma unroll
-      for (int i = 0; i < R * V + 4; ++i) sinkp[2 * i] = (T)i;  // distinct, never merged
+      for (int i = 0; i < R * V + 4; ++i) gstore(sinkp + 2 * i, (T)i);  // distinct, never merged
       __builtin_amdgcn_sched_barrier(0);
     }
     for (uint64_t tile = tb;; tile += 2) {
@@ -1130,7 +1148,7 @@ __global__ void __launch_bounds__(UNIT_TPB) k_encode(S src, Geo g) {
     load_tile(tile * WT, pa, qa);
     process(std::false_type{}, tile, pa, qa);
   }
-  if (lane == 0 && unit < P.n_units) P.unit_cnt[unit] = run;
+  if (lane == 0 && unit < P.n_units) gstore(P.unit_cnt + unit, run);
 }
 
 // =====================================================================
@@ -1164,14 +1182,16 @@ __global__ void __launch_bounds__(UNIT_TPB) k_gather(S src, Geo g) {
   if (e0 >= P.n) return;
   uint64_t e1 = e0 + P.tiles_per_unit * WT;
   e1 = e1 < P.n ? e1 : P.n;
-  const unsigned long long off = P.unit_cnt[unit];
-  const unsigned long long next = unit + 1 < P.n_units ? P.unit_cnt[unit + 1] : P.ctl->n_inc;
+  const unsigned long long off = gload(P.unit_cnt + unit);
+  const unsigned long long next =
+      unit + 1 < P.n_units ? gload(P.unit_cnt + unit + 1) : gload(&P.ctl->n_inc);
   const unsigned cnt = (unsigned)(next - off);
   const T* __restrict__ scratch = static_cast<const T*>(P.scratch);
   T* __restrict__ incomp = static_cast<T*>(P.incomp);
-  for (unsigned i = lane; i < cnt; i += 64) incomp[off + i] = scratch[e0 + i];
+  for (unsigned i = lane; i < cnt; i += 64) gstore(incomp + off + i, gload(scratch + e0 + i));
   const uint64_t b0 = (e0 + P.epb - 1) / P.epb;
-  for (uint64_t b = b0 + lane; b * P.epb < e1; b += 64) P.block_inc_off[b] += (long long)off;
+  for (uint64_t b = b0 + lane; b * P.epb < e1; b += 64)
+    gstore(P.block_inc_off + b, gload(P.block_inc_off + b) + (int64_t)off);
 }
 
 // Header of the call (Fig. 2's attributes plus the counts of this build).

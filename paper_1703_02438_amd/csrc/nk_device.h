@@ -23,9 +23,26 @@ struct Traits<float> {
 };
 
 // 16-byte vector load of V elements (the snapshot pointers are 16-byte aligned).
+// Global-memory access through a generic pointer.  Pointers that kernels
+// read from memory (a batch's job table) carry no address space, and the
+// compiler would otherwise access through them with flat instructions, which
+// also count against the LDS counter: every LDS wait then waits for the
+// streamed loads as well.
+#define NK_GLOBAL __attribute__((address_space(1)))
+template <typename T>
+__device__ __forceinline__ void gstore(T* p, T v) {
+  *((NK_GLOBAL T*)p) = v;  // a C-style cast: it may change the address space
+}
+template <typename T>
+__device__ __forceinline__ T gload(const T* p) {
+  return *((const NK_GLOBAL T*)p);
+}
+
+typedef unsigned int nk_u32x4 __attribute__((ext_vector_type(4)));
+
 template <typename T>
 __device__ __forceinline__ void load_vec(const T* __restrict__ base, uint64_t vi, T* out) {
-  const uint4 x = reinterpret_cast<const uint4*>(base)[vi];
+  const nk_u32x4 x = ((const NK_GLOBAL nk_u32x4*)base)[vi];
   __builtin_memcpy(out, &x, 16);
 }
 
@@ -36,8 +53,7 @@ __device__ __forceinline__ void load_vec(const T* __restrict__ base, uint64_t vi
 template <bool NT, typename T>
 __device__ __forceinline__ void load_vec_t(const T* __restrict__ base, uint64_t vi, T* out) {
   if constexpr (NT) {
-    typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
-    const u32x4 x = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(base) + vi);
+    const nk_u32x4 x = __builtin_nontemporal_load(((const NK_GLOBAL nk_u32x4*)base) + vi);
     __builtin_memcpy(out, &x, 16);
   } else {
     load_vec(base, vi, out);
