@@ -91,7 +91,7 @@ __global__ void k_init(S src, Geo g) {
     ctl->tail_bins = 0u;
     ctl->tail_max = 0u;
   }
-  for (int i = threadIdx.x; i < WIN; i += blockDim.x) P.gwin[i] = 0u;
+  for (int i = threadIdx.x; i < WIN; i += blockDim.x) gstore(P.gwin + i, 0u);
 }
 
 // =====================================================================
@@ -570,13 +570,13 @@ __device__ __forceinline__ void sel_visit(const CParams& P, const SelShared& S, 
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         const unsigned long long si = s0 + (unsigned long long)u * SEL_TPB + threadIdx.x;
-        slot[u] = si < H ? P.hslot[si] : HEMPTY;
-        cn[u] = si < H ? P.hcnt[si] : 0u;
+        slot[u] = si < H ? gload(P.hslot + si) : HEMPTY;
+        cn[u] = si < H ? gload(P.hcnt + si) : 0u;
       }
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         const bool ok = slot[u] != HEMPTY && cn[u] != 0;
-        f(ok ? (long long)P.tail[slot[u]] : 0ll, ok ? cn[u] : 0u);
+        f(ok ? (long long)gload(P.tail + slot[u]) : 0ll, ok ? cn[u] : 0u);
       }
     }
   }
@@ -668,9 +668,9 @@ __global__ void __launch_bounds__(SEL_TPB) k_select(SRC src, Geo g) {
 
   // centres and bin ids start cleared
   T* centers = static_cast<T*>(P.centers);
-  for (uint64_t i = tid; i < ncent; i += SEL_TPB) centers[i] = (T)0;
+  for (uint64_t i = tid; i < ncent; i += SEL_TPB) gstore(centers + i, (T)0);
   if (P.bin_ids)
-    for (uint64_t i = tid; i < k; i += SEL_TPB) P.bin_ids[i] = -1;
+    for (uint64_t i = tid; i < k; i += SEL_TPB) gstore(P.bin_ids + i, (int64_t)-1);
 
   const bool empty = c->empty != 0;
   const long long wbase = empty ? 0 : c->wbase;
@@ -684,7 +684,7 @@ __global__ void __launch_bounds__(SEL_TPB) k_select(SRC src, Geo g) {
   // window counts to LDS, with their statistics
   unsigned long long nzw = 0, mxw = 0, unused0 = ~0ull, unused1 = 0;
   for (int i = tid; i < WIN; i += SEL_TPB) {
-    const uint32_t cn = (unsigned)i < win_len ? P.gwin[i] : 0u;
+    const uint32_t cn = (unsigned)i < win_len ? gload(P.gwin + i) : 0u;
     S.win[i] = cn;
     nzw += cn ? 1 : 0;
     mxw = cn > mxw ? cn : mxw;
@@ -720,15 +720,15 @@ __global__ void __launch_bounds__(SEL_TPB) k_select(SRC src, Geo g) {
   unsigned long long sel_tail = 0, sel_below = 0;
   if (tail_matters) {
     for (unsigned long long si = tid; si < H; si += SEL_TPB) {
-      const uint32_t slot = P.hslot[si];
+      const uint32_t slot = gload(P.hslot + si);
       if (slot == HEMPTY) continue;
-      const uint32_t cn = P.hcnt[si];
-      const long long id = P.tail[slot];
+      const uint32_t cn = gload(P.hcnt + si);
+      const long long id = gload(P.tail + slot);
       if (cn != 0 && (cn > tau || (cn == tau && id <= cut))) {
         sel_tail += 1;
         if (id < wbase) sel_below += 1;
         const unsigned pos = atomicAdd(&S.tail_pos, 1u);
-        P.sel_tail[pos] = id;
+        gstore(P.sel_tail + pos, (int64_t)id);
       }
     }
   }
@@ -760,8 +760,8 @@ __global__ void __launch_bounds__(SEL_TPB) k_select(SRC src, Geo g) {
     uint32_t l = k;  // escape code: not selected
     if (cn != 0 && (cn > tau || (cn == tau && id <= cut))) {
       l = rank;
-      centers[rank] = (T)centre_of<T>(id, lo, P.E);
-      if (P.bin_ids) P.bin_ids[rank] = id;
+      gstore(centers + rank, (T)centre_of<T>(id, lo, P.E));
+      if (P.bin_ids) gstore(P.bin_ids + rank, (int64_t)id);
       rank += 1;
     }
     S.win[w] = l;
@@ -769,7 +769,7 @@ __global__ void __launch_bounds__(SEL_TPB) k_select(SRC src, Geo g) {
   __syncthreads();
   uint32_t* lut2 = reinterpret_cast<uint32_t*>(P.lut);  // two 16-bit codes per word
   for (int i = tid; i < WIN / 2; i += SEL_TPB)
-    lut2[i] = (S.win[2 * i] & 0xFFFFu) | (S.win[2 * i + 1] << 16);
+    gstore(lut2 + i, (S.win[2 * i] & 0xFFFFu) | (S.win[2 * i + 1] << 16));
   if (tid == 0) {
     c->n_nonzero = nz;
     c->tau = tau;

@@ -188,50 +188,42 @@ constexpr int USCAN_TPB = 1024;
 __device__ __forceinline__ unsigned long long unit_scan(uint32_t* cnt, uint32_t n) {
   constexpr int PER = MAX_UNITS / USCAN_TPB;
   constexpr int Q = USCAN_TPB / 64;
-  __shared__ unsigned long long s_part[USCAN_TPB];
-  __shared__ unsigned long long s_total;
+  __shared__ unsigned long long s_part[Q];
   const int tid = threadIdx.x;
   uint32_t v[PER];
   unsigned long long mine = 0;
 #pragma unroll
   for (int i = 0; i < PER; ++i) {
     const uint32_t k = (uint32_t)tid * PER + i;
-    v[i] = k < n ? cnt[k] : 0u;
+    v[i] = k < n ? gload(cnt + k) : 0u;
     mine += v[i];
   }
-  s_part[tid] = mine;
-  __syncthreads();
-  if (tid < 64) {
-    unsigned long long loc[Q];
-    unsigned long long run = 0;
+  // exclusive prefix of `mine` over the workgroup: wave scans, then the
+  // wave totals (every thread reads all Q of them: broadcast, no conflicts)
+  const int lane = tid & 63, w = tid >> 6;
+  unsigned long long inc = mine;
 #pragma unroll
-    for (int i = 0; i < Q; ++i) {
-      loc[i] = s_part[tid * Q + i];
-      run += loc[i];
-    }
-    unsigned long long inc = run;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-      const unsigned long long t = __shfl_up(inc, o, 64);
-      if (tid >= o) inc += t;
-    }
-    unsigned long long ex = inc - run;
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-      s_part[tid * Q + i] = ex;
-      ex += loc[i];
-    }
-    if (tid == 63) s_total = inc;
+  for (int o = 1; o < 64; o <<= 1) {
+    const unsigned long long t = __shfl_up(inc, o, 64);
+    if (lane >= o) inc += t;
   }
+  if (lane == 63) s_part[w] = inc;
   __syncthreads();
-  unsigned long long run = s_part[tid];
+  unsigned long long base = 0, tot = 0;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const unsigned long long r = s_part[i];
+    base += i < w ? r : 0ull;
+    tot += r;
+  }
+  unsigned long long run = base + inc - mine;
 #pragma unroll
   for (int i = 0; i < PER; ++i) {
     const uint32_t k = (uint32_t)tid * PER + i;
-    if (k < n) cnt[k] = (uint32_t)run;
+    if (k < n) gstore(cnt + k, (uint32_t)run);
     run += v[i];
   }
-  return s_total;
+  return tot;
 }
 
 }  // namespace nk
