@@ -188,7 +188,9 @@ typedef struct numarck_tuning {
   uint32_t range_blocks_per_cu; /* pass-1 workgroups per compute unit */
   uint32_t hist_blocks_per_cu;  /* histogram workgroups per compute unit */
   uint32_t hist_lds;            /* 1: window counts in LDS (64 KB per workgroup); 0: in global memory */
-  uint32_t chunk_vec;           /* 16-byte vectors per streaming chunk of the first two passes */
+  uint32_t chunk_vec;           /* 16-byte vectors per streaming chunk of the first two passes;
+                                   0: automatic, about four chunks per compute unit for each
+                                   element type's group (a power of two in [4096, 65536]) */
   uint32_t unit_pct;            /* encoder waves as a percentage of the resident capacity (1..100) */
   uint32_t stream_loads;        /* input loads of the three passes: 0 automatic (non-temporal when
                                    a pass streams at least 512 MB and no input is shared between

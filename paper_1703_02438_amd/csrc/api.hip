@@ -269,7 +269,8 @@ static int size_class(uint64_t n) {
 static bool tuning_valid(const Tuning& t) {
   return t.range_blocks_per_cu >= 1 && t.range_blocks_per_cu <= 64 &&
          t.hist_blocks_per_cu >= 1 && t.hist_blocks_per_cu <= 16 && t.hist_lds <= 1 &&
-         t.chunk_vec >= 64 && t.chunk_vec <= (1u << 20) && t.unit_pct >= 1 &&
+         (t.chunk_vec == 0 || (t.chunk_vec >= 64 && t.chunk_vec <= (1u << 20))) &&
+         t.unit_pct >= 1 &&
          t.unit_pct <= 100 && t.stream_loads <= 2;
 }
 
@@ -363,7 +364,7 @@ numarck_status numarck_autotune(const void* prev, const void* curr, uint64_t n,
   // LDS counting only: global window counts serialise on the hot bins of
   // concentrated ratio distributions (orders of magnitude slower there)
   const uint32_t hist[][2] = {{1, 1}, {1, 2}, {1, 4}};
-  const uint32_t cvec[] = {1024, 4096, 16384, 65536};
+  const uint32_t cvec[] = {4096, 16384, 65536, 131072};
   const uint32_t upct[] = {25, 50, 75, 100};
   const uint32_t sload[] = {1, 2};
   auto try_one = [&](const Tuning& t) {
@@ -532,8 +533,23 @@ numarck_status numarck_plan_create(const numarck_job* jobs, uint32_t njobs,
     pl->table[r] = make_params(j.prev, j.curr, j.n, j.dtype, j.E, j.B, j.block_bytes, &j.out,
                                base + off, L);
     off += align256(L.total);
-    pl->chunk0[r + 1] = pl->chunk0[r] + stream_chunks(j.n, (int)j.dtype, tn.chunk_vec);
   }
+  // streaming chunks: each element type's group gets its own chunk size
+  const Geometry G0 = geometry();
+  std::vector<uint32_t> cvec_of(njobs);
+  for (uint32_t r = 0; r < njobs;) {
+    uint32_t e = r + 1;
+    while (e < njobs && pl->table[e].dtype == pl->table[r].dtype) ++e;
+    uint64_t vecs = 0;
+    for (uint32_t q = r; q < e; ++q)
+      vecs += pl->table[q].n / (pl->table[q].dtype == NUMARCK_F32 ? 4 : 2);
+    const uint32_t cv = chunk_vec_for(tn.chunk_vec, vecs, G0.cus);
+    for (uint32_t q = r; q < e; ++q) cvec_of[q] = cv;
+    r = e;
+  }
+  for (uint32_t r = 0; r < njobs; ++r)
+    pl->chunk0[r + 1] =
+        pl->chunk0[r] + stream_chunks(pl->table[r].n, pl->table[r].dtype, cvec_of[r]);
 
   // a snapshot read by two jobs (consecutive time pairs) is better kept in
   // the caches between its two reads than streamed past them
@@ -576,6 +592,7 @@ numarck_status numarck_plan_create(const numarck_job* jobs, uint32_t njobs,
     g.dtype = dt;
     g.cls = cls;
     g.nt = stream_nt_for(tn.stream_loads, gbytes, shared_inputs);
+    g.chunk_vec = cvec_of[r];
     g.job_begin = r;
     g.job_end = e;
     g.c_begin = pl->chunk0[r];

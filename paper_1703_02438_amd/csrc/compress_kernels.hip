@@ -1265,11 +1265,12 @@ int encoder_occupancy(int dtype, int cls, bool table) {
   return table ? encoder_occupancy_t<JobTable>(dtype, cls) : encoder_occupancy_t<OneJob>(dtype, cls);
 }
 
-Tuning default_tuning() { return Tuning{8u, 2u, 1u, 4096u, 100u, 0u}; }
+Tuning default_tuning() { return Tuning{8u, 2u, 1u, 0u, 100u, 0u}; }
 
 static Geo group_geo(const Geo& base, const JobGroup& jg) {
   Geo g = base;
   g.stream_nt = jg.nt;
+  if (jg.chunk_vec) g.chunk_vec = jg.chunk_vec;
   g.job_begin = jg.job_begin;
   g.job_end = jg.job_end;
   g.c_begin = jg.c_begin;
@@ -1386,14 +1387,15 @@ hipError_t launch_compress(const CParams& P0, const Tuning& tn, hipStream_t s) {
   P.n_units = range_units(P.n_tiles, (int)(resident < 4 ? 4 : resident));
   P.tiles_per_unit = (P.n_tiles + P.n_units - 1) / P.n_units;
   Geo base{};
-  base.chunk_vec = tn.chunk_vec;
+  base.chunk_vec = chunk_vec_for(tn.chunk_vec, P.n / (P.dtype == NUMARCK_F32 ? 4 : 2), G.cus);
   JobGroup grp{};
   grp.dtype = P.dtype;
   grp.cls = cls;
   grp.job_begin = 0;
   grp.job_end = 1;
   grp.c_begin = 0;
-  grp.c_end = stream_chunks(P.n, P.dtype, tn.chunk_vec);
+  grp.chunk_vec = base.chunk_vec;
+  grp.c_end = stream_chunks(P.n, P.dtype, base.chunk_vec);
   grp.u_begin = 0;
   grp.u_end = P.n_units;
   grp.nt = stream_nt_for(tn.stream_loads, 2 * P.n * (P.dtype == NUMARCK_F32 ? 4 : 8),
@@ -1405,7 +1407,7 @@ hipError_t launch_compress_batch(const BatchLaunch& b, hipStream_t s) {
   Geo base{};
   base.chunk0 = b.chunk0_dev;
   base.unit0 = b.unit0_dev;
-  base.chunk_vec = b.tune.chunk_vec;
+  base.chunk_vec = b.tune.chunk_vec ? b.tune.chunk_vec : 4096;  // groups carry their own
   return run_chain(JobTable{b.jobs_dev}, base, b.njobs, b.dgroups, b.n_dgroups, b.egroups,
                    b.n_egroups, b.tune, s);
 }

@@ -180,7 +180,7 @@ struct Tuning {
   uint32_t range_blocks_per_cu;  // k_range grid = this x CUs (capped by chunks)
   uint32_t hist_blocks_per_cu;   // k_hist grid
   uint32_t hist_lds;             // 1: LDS window counts, 0: global window counts
-  uint32_t chunk_vec;            // 16-byte vectors per streaming chunk
+  uint32_t chunk_vec;            // 16-byte vectors per streaming chunk (0: automatic)
   uint32_t unit_pct;             // encoder units, % of the resident capacity
   uint32_t stream_loads;         // 0: automatic, 1: non-temporal, 2: cached
 };
@@ -191,7 +191,8 @@ Tuning default_tuning();
 struct JobGroup {
   int dtype;
   int cls;
-  uint32_t nt;  // streaming loads non-temporal for this group
+  uint32_t nt;         // streaming loads non-temporal for this group
+  uint32_t chunk_vec;  // 16-byte vectors per streaming chunk of this group
   uint32_t job_begin, job_end;
   uint64_t c_begin, c_end;
   uint32_t u_begin, u_end;
@@ -206,6 +207,18 @@ inline uint32_t stream_nt_for(uint32_t mode, uint64_t bytes, bool shared_inputs)
   if (mode == 1) return 1u;
   if (mode == 2) return 0u;
   return (bytes >= NT_STREAM_BYTES && !shared_inputs) ? 1u : 0u;
+}
+
+// Streaming chunk of a launch group moving `vecs` 16-byte vectors per pass:
+// `fixed` when the tuning sets one, else about four chunks per compute unit
+// (a power of two in [4096, 65536]): long chunks keep a workgroup on one
+// contiguous stretch of each array, enough of them keep every workgroup busy.
+inline uint32_t chunk_vec_for(uint32_t fixed, uint64_t vecs, int cus) {
+  if (fixed) return fixed;
+  const uint64_t want = vecs / ((uint64_t)cus * 4);
+  uint32_t c = 4096;
+  while (c < 65536 && (uint64_t)c * 2 <= want) c *= 2;
+  return c;
 }
 
 // Elements of one encoder / decoder wave tile for an element size (16-byte vectors).

@@ -166,7 +166,7 @@ def test_plan_validation_without_gpu(nk):
 def test_tuning_defaults_and_files(nk, tmp_path):
     t = nk.default_tuning()
     assert t.as_dict() == {"range_blocks_per_cu": 8, "hist_blocks_per_cu": 2, "hist_lds": 1,
-                           "chunk_vec": 4096, "unit_pct": 100, "stream_loads": 0}
+                           "chunk_vec": 0, "unit_pct": 100, "stream_loads": 0}
     good = tmp_path / "good.txt"
     good.write_text("# comment\nf64 27 4 2 1 8192 75 1\nf32 20 8 4 0 2048 100\n")
     assert nk.numarck_tuning_load(str(good).encode()) == nk.OK
