@@ -75,11 +75,13 @@ static bool fit_layout(uint64_t n, uint64_t elem_bytes, size_t ws_bytes, Layout*
   return true;
 }
 
-static size_t decompress_layout_bytes(uint64_t len, size_t* cnt_off) {
+static size_t decompress_layout_bytes(uint64_t len, size_t* cnt_off, size_t* pre_off = nullptr) {
   (void)len;
   const size_t s = align256(sizeof(DCtl));
+  const size_t p = s + align256((size_t)MAX_UNITS * 4);
   if (cnt_off) *cnt_off = s;
-  return s + align256((size_t)MAX_UNITS * 4);
+  if (pre_off) *pre_off = p;
+  return p + align256((size_t)MAX_PRE_UNITS * 4);
 }
 
 static int g_cus[128];
@@ -746,8 +748,8 @@ static numarck_status decompress_impl(const numarck_header* hdr, const void* pre
   if (len > 0 && (!prev || !packed || !centers || !out || !block_inc_off)) return NUMARCK_EINVAL;
   if (len > 0 && hdr->n_inc > 0 && !incomp) return NUMARCK_EINVAL;
   if (((uintptr_t)ws & 255u) != 0) return NUMARCK_EALIGN;
-  size_t cnt_off = 0;
-  if (ws_bytes < decompress_layout_bytes(len, &cnt_off)) return NUMARCK_ECAPACITY;
+  size_t cnt_off = 0, pre_off = 0;
+  if (ws_bytes < decompress_layout_bytes(len, &cnt_off, &pre_off)) return NUMARCK_ECAPACITY;
   char* base = static_cast<char*>(ws);
   DParams P{};
   P.prev = prev;
@@ -768,6 +770,7 @@ static numarck_status decompress_impl(const numarck_header* hdr, const void* pre
   P.dtype = (int)hdr->dtype;
   P.dctl = reinterpret_cast<DCtl*>(base);
   P.unit_cnt = reinterpret_cast<uint32_t*>(base + cnt_off);
+  P.pre_cnt = reinterpret_cast<uint32_t*>(base + pre_off);
   P.tile_elems = dec_wave_tile(hdr->dtype == NUMARCK_F32 ? 4 : 8);
   P.n_tiles = (len + P.tile_elems - 1) / P.tile_elems;
   const hipError_t e = launch_decompress(P, static_cast<hipStream_t>(stream));

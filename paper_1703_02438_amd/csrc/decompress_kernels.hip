@@ -4,12 +4,11 @@
 //
 // A range [start, start + len) is cut into wave tiles; each wave ("unit")
 // owns a contiguous run of them:
-//   k_dinit    reset the control block and the flag word
-//   k_dprefix  escapes before `start`: the block table gives the count up to
-//              the start of start's block, the rest is counted from the
-//              packed indices (less than one block)
-//   k_dcount   escapes in each unit's run (reads the packed indices only)
-//   k_dscan    exclusive offsets of the runs
+//   k_dcount   escapes in each unit's run, and in pieces of the part of
+//              start's block before the range (reads the packed indices only)
+//   k_dscan    escapes before `start` (the block table gives the count up to
+//              the start of start's block, plus the counted pieces), exclusive
+//              offsets of the runs, and the flag word cleared
 //   k_decode   each unit decodes its tiles in order: an escape takes the next
 //              incompressible value, any other index gives
 //              T(prev * (1 + centre[index]))
@@ -27,64 +26,60 @@ __device__ __forceinline__ uint32_t unpack_index(const uint32_t* __restrict__ pa
   return v & ((1u << B) - 1u);
 }
 
-__global__ void k_dinit(DParams P) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    P.dctl->base = 0ull;
-    *P.flags = 0u;
-  }
-}
-
-__global__ void k_dprefix(DParams P) {
-  if (P.len == 0) return;
-  const uint64_t blk = P.start / P.epb;
-  const uint64_t b0 = blk * P.epb;
-  const uint32_t esc = (1u << P.B) - 1u;
-  const uint64_t gt = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const uint64_t gs = (uint64_t)gridDim.x * blockDim.x;
-  unsigned long long cnt = 0;
-  if (gt == 0) cnt += (unsigned long long)P.block_inc_off[blk];
-  for (uint64_t j = b0 + gt; j < P.start; j += gs)
-    cnt += unpack_index(P.packed, j, P.B) == esc ? 1ull : 0ull;
-  cnt = wave_sum_u64(cnt);
-  if (lane_id() == 0 && cnt) atomicAdd(&P.dctl->base, cnt);
-}
-
-// Escapes in each unit's range [r0, r1) of indices (reads the packed indices
-// only).  Lane l takes words w = w_lo + l, w_lo + l + 64, ... and counts the
-// indices that start in word w (those straddling into w + 1 read it too).
-// The first index starting in w and its bit offset there are advanced from
-// one word to the next without divisions: 64 words are 2048 bits.
-__global__ void __launch_bounds__(UNIT_TPB) k_dcount(DParams P) {
-  const uint32_t unit = blockIdx.x * (UNIT_TPB / 64) + threadIdx.x / 64;
+// Escapes among the indices of [r0, r1), summed over the calling wave (every
+// lane returns the total).  Reads the packed indices only.
+__device__ unsigned long long wave_count_escapes(const uint32_t* __restrict__ packed,
+                                                 uint64_t packed_words, uint32_t B, uint64_t r0,
+                                                 uint64_t r1) {
   const int lane = lane_id();
-  const uint32_t B = P.B;
   const uint32_t esc = (1u << B) - 1u;
-  const uint64_t end = P.start + P.len;
-  uint64_t r0 = P.start + (uint64_t)unit * P.tiles_per_unit * P.tile_elems;
-  uint64_t r1 = r0 + P.tiles_per_unit * P.tile_elems;
-  r0 = r0 < end ? r0 : end;
-  r1 = r1 < end ? r1 : end;
   unsigned long long cnt = 0;
   if (r0 < r1 && (32 % B) == 0) {
-    // B divides 32: indices never straddle words.  AND-folding each word by
-    // 1, 2, 4, ... < B bit positions leaves at the first bit of each field
-    // the AND of the field's B bits (1 exactly for the escape code).
+    // B divides 32: indices never straddle words.  AND-folding a word by 1,
+    // 2, 4, ... < B bit positions leaves at the first bit of each field the
+    // AND of the field's B bits (1 exactly for the escape code).  Lanes take
+    // 16-byte groups of four words when the stream is 16-byte aligned.
     const uint32_t per = 32 / B;
     uint32_t start_mask = 0;
     for (uint32_t b = 0; b < 32; b += B) start_mask |= 1u << b;
-    for (uint64_t w = r0 / per + lane; w * per < r1; w += 64) {
-      uint32_t t = P.packed[w];
-      for (uint32_t sh = 1; sh < B; sh <<= 1) t &= t >> sh;
-      t &= start_mask;
-      const uint64_t e0 = w * per;  // index of the word's first field
-      if (e0 < r0) t &= ~0u << (uint32_t)((r0 - e0) * B);
-      if (e0 + per > r1) {
-        const uint32_t keep = (uint32_t)((r1 - e0) * B);  // < 32 here
-        t &= (1u << keep) - 1u;
+    const uint64_t wlo = r0 / per, whi = (r1 + per - 1) / per;  // words [wlo, whi)
+    // escapes among the fields of word w that lie in [r0, r1)
+    auto word_escapes = [&](uint64_t w, uint32_t x) -> uint32_t {
+      for (uint32_t sh = 1; sh < B; sh <<= 1) x &= x >> sh;
+      x &= start_mask;
+      const uint64_t e0 = w * per;
+      if (e0 < r0) x &= ~0u << (uint32_t)((r0 - e0) * B);  // r0 - e0 < per here
+      if (e0 + per > r1) x &= (1u << (uint32_t)((r1 - e0) * B)) - 1u;  // < 32 bits kept
+      return (uint32_t)__popc(x);
+    };
+    if (((uintptr_t)packed & 15u) == 0) {
+      for (uint64_t g = wlo / 4 + lane; 4 * g < whi; g += 64) {
+        uint32_t x[4];
+        if (4 * g + 4 <= packed_words) {
+          const nk_u32x4 v = gload(reinterpret_cast<const nk_u32x4*>(packed) + g);
+          x[0] = v.x;
+          x[1] = v.y;
+          x[2] = v.z;
+          x[3] = v.w;
+        } else {
+#pragma unroll
+          for (int k = 0; k < 4; ++k) x[k] = 4 * g + k < packed_words ? packed[4 * g + k] : 0u;
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const uint64_t w = 4 * g + k;
+          if (w >= wlo && w < whi) cnt += word_escapes(w, x[k]);
+        }
       }
-      cnt += (unsigned long long)__popc(t);
+    } else {
+      for (uint64_t w = wlo + lane; w < whi; w += 64) cnt += word_escapes(w, packed[w]);
     }
   } else if (r0 < r1) {
+    // Lane l takes words w = w_lo + l, w_lo + l + 64, ... and counts the
+    // indices that start in word w (those straddling into w + 1 read it
+    // too).  The first index starting in w and its bit offset there are
+    // advanced from one word to the next without divisions: 64 words are
+    // 2048 bits.
     const uint64_t wlo = (r0 * B) >> 5;
     const uint64_t whi = (r1 * B + 31) >> 5;  // exclusive
     uint64_t w = wlo + lane;
@@ -93,8 +88,8 @@ __global__ void __launch_bounds__(UNIT_TPB) k_dcount(DParams P) {
     uint32_t off = (uint32_t)(e * B - 32 * w);
     const uint32_t q = 2048 / B, rem = 2048 % B;
     for (; w < whi; w += 64) {
-      const uint32_t lo = P.packed[w];
-      const uint32_t hi = w + 1 < P.packed_words ? P.packed[w + 1] : 0u;
+      const uint32_t lo = packed[w];
+      const uint32_t hi = w + 1 < packed_words ? packed[w + 1] : 0u;
       const unsigned long long x = (unsigned long long)lo | ((unsigned long long)hi << 32);
       uint64_t ee = e;
       for (uint32_t o = off; o < 32; o += B, ++ee)
@@ -109,12 +104,57 @@ __global__ void __launch_bounds__(UNIT_TPB) k_dcount(DParams P) {
       }
     }
   }
-  cnt = wave_sum_u64(cnt);
-  if (lane == 0) P.unit_cnt[unit] = (uint32_t)cnt;
+  return wave_sum_u64(cnt);
 }
 
+// One launch counts escapes for the whole decode.  The first n_units waves
+// are the decoder units: wave u counts its tile run of the range.  The
+// pre_units waves after them split [start of start's block, start), the part
+// of the block before the range, into pieces of pre_elems indices.
+__global__ void __launch_bounds__(UNIT_TPB) k_dcount(DParams P) {
+  const uint32_t wave = blockIdx.x * (UNIT_TPB / 64) + threadIdx.x / 64;
+  uint64_t r0, r1;
+  if (wave < P.n_units) {
+    const uint64_t end = P.start + P.len;
+    r0 = P.start + (uint64_t)wave * P.tiles_per_unit * P.tile_elems;
+    r1 = r0 + P.tiles_per_unit * P.tile_elems;
+    r0 = r0 < end ? r0 : end;
+    r1 = r1 < end ? r1 : end;
+  } else {
+    const uint32_t i = wave - P.n_units;
+    if (i >= P.pre_units) return;
+    const uint64_t b0 = P.start / P.epb * P.epb;
+    r0 = b0 + (uint64_t)i * P.pre_elems;
+    r1 = r0 + P.pre_elems;
+    r0 = r0 < P.start ? r0 : P.start;
+    r1 = r1 < P.start ? r1 : P.start;
+  }
+  const unsigned long long cnt = wave_count_escapes(P.packed, P.packed_words, P.B, r0, r1);
+  if (lane_id() == 0) {
+    if (wave < P.n_units)
+      P.unit_cnt[wave] = (uint32_t)cnt;
+    else
+      P.pre_cnt[wave - P.n_units] = (uint32_t)cnt;
+  }
+}
+
+// Escapes before the range (the block table's count at start's block plus
+// the counted pieces), the unit offsets by an exclusive scan, and the flag
+// word cleared for the decoder.
 __global__ void __launch_bounds__(USCAN_TPB) k_dscan(DParams P) {
-  (void)unit_scan(P.unit_cnt, P.n_units);
+  __shared__ unsigned long long s_pre[USCAN_TPB / 64];
+  const int tid = threadIdx.x;
+  unsigned long long pre = 0;
+  for (uint32_t i = tid; i < P.pre_units; i += USCAN_TPB) pre += gload(P.pre_cnt + i);
+  pre = wave_sum_u64(pre);
+  if (lane_id() == 0) s_pre[tid / 64] = pre;
+  (void)unit_scan(P.unit_cnt, P.n_units);  // synchronises the workgroup
+  if (tid == 0) {
+    unsigned long long base = P.len ? (unsigned long long)P.block_inc_off[P.start / P.epb] : 0ull;
+    for (int w = 0; w < USCAN_TPB / 64; ++w) base += s_pre[w];
+    P.dctl->base = base;
+    gstore(P.flags, 0u);
+  }
 }
 
 // LDS budget for the centre table (used when 2^B entries fit).
@@ -261,12 +301,15 @@ static hipError_t launch_decode_chain(DParams P, size_t cent_lds, hipStream_t s)
     occ = 1;
   P.n_units = range_units(P.n_tiles, g.cus * occ * 4);
   P.tiles_per_unit = (P.n_tiles + P.n_units - 1) / P.n_units;
-  uint64_t pre_blocks = P.len ? ((P.start % P.epb) + 255) / 256 : 1;
-  if (pre_blocks < 1) pre_blocks = 1;
-  if (pre_blocks > (uint64_t)g.cus * 2) pre_blocks = (uint64_t)g.cus * 2;
-  NK_DLAUNCH(KK_DINIT, k_dinit, 1, 64, 0, P);
-  NK_DLAUNCH(KK_DPREFIX, k_dprefix, pre_blocks, 256, 0, P);
-  NK_DLAUNCH(KK_DCOUNT, k_dcount, P.n_units / 4, UNIT_TPB, 0, P);
+  // the part of start's block before the range, in pieces of at least 8192
+  // indices, at most MAX_PRE_UNITS of them
+  const uint64_t pre = P.len ? P.start % P.epb : 0;
+  uint64_t piece = (pre + MAX_PRE_UNITS - 1) / MAX_PRE_UNITS;
+  piece = piece < 8192 ? 8192 : piece;
+  P.pre_units = (uint32_t)((pre + piece - 1) / piece);
+  P.pre_elems = piece;
+  const uint32_t waves = P.n_units + P.pre_units;
+  NK_DLAUNCH(KK_DCOUNT, k_dcount, (waves + 3) / 4, UNIT_TPB, 0, P);
   NK_DLAUNCH(KK_DSCAN, k_dscan, 1, USCAN_TPB, 0, P);
   NK_DLAUNCH(KK_DECODE, (k_decode<T, VEC>), P.n_units / 4, UNIT_TPB, cent_lds, P);
   return hipSuccess;

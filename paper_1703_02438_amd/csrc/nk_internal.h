@@ -49,6 +49,9 @@ constexpr int UNIT_TPB = 256;      // 4 units per workgroup
 constexpr int ENC_ROUNDS = NK_ENC_ROUNDS;
 constexpr int DEC_ROUNDS = NK_DEC_ROUNDS;
 constexpr int MAX_UNITS = 8192;
+// Pieces of the part of a block before a decompression range, counted in
+// parallel, at most.
+constexpr int MAX_PRE_UNITS = 1024;
 
 // ------------------------------------------------ device control block
 // Lives at the start of the compression workspace.  Fields above `lo` are
@@ -150,7 +153,10 @@ struct DParams {
   int dtype;
   DCtl* dctl;
   uint32_t* unit_cnt;  // escapes per decoder unit range, then their offsets
+  uint32_t* pre_cnt;   // escapes per piece of start's block before start
   uint32_t n_units;
+  uint32_t pre_units;  // pieces of [start of start's block, start)
+  uint64_t pre_elems;  // indices per piece
   uint64_t tiles_per_unit;
   uint64_t n_tiles;
   uint64_t tile_elems;  // elements of a wave tile

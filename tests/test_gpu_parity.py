@@ -199,3 +199,53 @@ def test_decode_flags(nk):
     c2.packed.fill_(-1)  # every index is the escape code
     _, fl = nk.decompress(c2, p2)
     assert int(fl.item()) & nk.FLAG_INC_OVERRUN
+
+
+def _range_at(nk, c, p, s, ln, packed=None):
+    """numarck_decompress_range through the C ABI, optionally with the index
+    stream read from another buffer."""
+    import ctypes
+    h = c.header()
+    out = torch.empty(max(ln, 1), dtype=c.dtype, device="cuda")
+    fl = torch.zeros(1, dtype=torch.int32, device="cuda")
+    ws = torch.empty(nk.numarck_decompress_workspace_bytes(ln), dtype=torch.uint8, device="cuda")
+    pk = c.packed.data_ptr() if packed is None else packed
+    nk._check(nk.numarck_decompress_range(
+        ctypes.byref(h), p.data_ptr(), pk, c.centers.data_ptr(), c.incomp.data_ptr(),
+        c.block_inc_off.data_ptr(), s, ln, out.data_ptr(), fl.data_ptr(), ws.data_ptr(),
+        ws.numel(), torch.cuda.current_stream().cuda_stream), "numarck_decompress_range")
+    return out[:ln], fl
+
+
+@pytest.mark.parametrize("B", [4, 5, 8, 16])
+def test_range_deep_in_block(nk, B):
+    """Ranges that start far into a large compression block (the escapes
+    before them are counted from the index stream in many pieces), ranges
+    across block boundaries, and the same ranges with the index stream at a
+    4-, 8- and 12-byte offset from a 16-byte boundary."""
+    n = 3_000_017
+    prev, curr = mixture_case(n, 500 + B, np.float32)
+    c, o, p = compare_compress(nk, prev, curr, 1e-3, B, check_hist=False, label="deep")
+    epb = c.header().elems_per_block
+    assert epb >= 1 << 19
+    rng = np.random.default_rng(B)
+    want = [(epb - 1, 2), (epb + epb // 2 + 3, 70_001), (n - 1, 1), (n - 9000, 9000),
+            (2 * epb - 8191, 8193), (n // 2 + 77, 100_000)]
+    want += [(int(s), int(rng.integers(0, 200_001))) for s in rng.integers(0, n, 6)]
+    ranges = [(min(s, n - 1), min(ln, n - min(s, n - 1))) for s, ln in want]
+    orc = oracle.get()
+    nw = c.header().packed_bytes // 4
+    shifted = {}
+    for off in (1, 2, 3):
+        buf = torch.zeros(nw + 4, dtype=torch.int32, device="cuda")
+        buf[off:off + nw] = c.packed[:nw]
+        shifted[off] = buf
+    for s, ln in ranges:
+        r, rfl = orc.decompress_range(o, prev, s, ln)
+        g, gfl = _range_at(nk, c, p, s, ln)
+        assert int(gfl.item()) == rfl == 0
+        assert np.array_equal(bits(to_np(g)), bits(r)), f"range {s},{ln}"
+        for off, buf in shifted.items():
+            g, gfl = _range_at(nk, c, p, s, ln, packed=buf.data_ptr() + 4 * off)
+            assert int(gfl.item()) == 0
+            assert np.array_equal(bits(to_np(g)), bits(r)), f"range {s},{ln} offset {4 * off}"
