@@ -457,7 +457,7 @@ struct numarck_plan {
   std::vector<CParams> table;        // sorted by (dtype, encoder class)
   std::vector<uint64_t> chunk0;      // njobs + 1
   std::vector<uint32_t> unit0;       // njobs + 1
-  std::vector<nk::JobGroup> dgroups, egroups;
+  std::vector<nk::JobGroup> dgroups, egroups, rgroups;
   nk::BatchLaunch bl;
   hipEvent_t uploaded = nullptr;     // the descriptor copy has completed
   hipGraph_t graph = nullptr;
@@ -617,6 +617,45 @@ numarck_status numarck_plan_create(const numarck_job* jobs, uint32_t njobs,
       bytes += 2 * pl->table[q].n * (dg.dtype == NUMARCK_F32 ? 4 : 8);
     dg.nt = stream_nt_for(tn.stream_loads, bytes, shared_inputs);
   }
+  // range pass: a time chain (consecutive jobs of one n, each job's prev the
+  // previous job's curr) is swept once, every snapshot read once; the other
+  // jobs stream per run as in the other passes
+  for (const JobGroup& dg : pl->dgroups) {
+    uint32_t run = dg.job_begin, q = dg.job_begin;
+    auto plain_run = [&](uint32_t a, uint32_t b) {
+      if (a == b) return;
+      JobGroup r = dg;
+      r.job_begin = a;
+      r.job_end = b;
+      r.c_begin = pl->chunk0[a];
+      r.c_end = pl->chunk0[b];
+      r.chunk_vec = cvec_of[a];
+      r.chain = 0;
+      pl->rgroups.push_back(r);
+    };
+    while (q < dg.job_end) {
+      uint32_t e = q + 1;
+      while (e < dg.job_end && e - q < CHAIN_MAX && pl->table[q].n > 0 &&
+             pl->table[e].n == pl->table[q].n && pl->table[e].prev == pl->table[e - 1].curr)
+        ++e;
+      if (e - q < 2) {
+        ++q;
+        continue;
+      }
+      plain_run(run, q);
+      JobGroup r = dg;
+      r.job_begin = q;
+      r.job_end = e;
+      const uint64_t nvec = pl->table[q].n / (dg.dtype == NUMARCK_F32 ? 4 : 2);
+      r.chunk_vec = chain_chunk_vec(nvec, G.cus);
+      r.c_begin = 0;
+      r.c_end = stream_chunks(pl->table[q].n, dg.dtype, r.chunk_vec);
+      r.chain = 1;
+      pl->rgroups.push_back(r);
+      run = q = e;
+    }
+    plain_run(run, dg.job_end);
+  }
   if ((uint64_t)pl->unit0[njobs] / 4 > 0x7FFFFFFFull) {
     delete pl;
     return NUMARCK_EINVAL;
@@ -651,6 +690,8 @@ numarck_status numarck_plan_create(const numarck_job* jobs, uint32_t njobs,
   bl.n_dgroups = (uint32_t)pl->dgroups.size();
   bl.egroups = pl->egroups.data();
   bl.n_egroups = (uint32_t)pl->egroups.size();
+  bl.rgroups = pl->rgroups.data();
+  bl.n_rgroups = (uint32_t)pl->rgroups.size();
   bl.tune = tn;
   *plan_out = pl;
   return NUMARCK_OK;

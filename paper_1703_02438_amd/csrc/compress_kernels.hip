@@ -204,6 +204,143 @@ __global__ void __launch_bounds__(RNG_TPB) k_range(S src, Geo g) {
   if (ctl) range_flush(ctl, kmin, kmax, ninv);
 }
 
+// Pass 1 over a time chain: jobs j0 .. j0 + T - 1 (T <= CHAIN_MAX) with
+// one n, job t comparing snapshot t with snapshot t + 1.  Each thread holds
+// CHAIN_K vectors of snapshots t and t + 1 in registers, takes the ratios of
+// pair t while the same positions of snapshot t + 2 load, and moves on to
+// pair t + 1: every snapshot is read once per sweep instead of twice.  A
+// wave folds its extremes and invalid count of pair t into its own LDS slot
+// after each step; the workgroup adds the slots to the jobs' control blocks
+// once, at the end.
+static_assert(RNG_TPB == 256, "chain chunks are sized for 256-thread workgroups");
+
+template <typename T, bool NT>
+__global__ void __launch_bounds__(RNG_TPB) k_range_chain(JobTable src, Geo g) {
+  constexpr int V = Traits<T>::V;
+  constexpr int NW = RNG_TPB / 64;
+  constexpr int K = (int)CHAIN_K;
+  __shared__ const T* s_in[CHAIN_MAX + 1];
+  __shared__ double s_cap[CHAIN_MAX];
+  __shared__ unsigned long long s_min[CHAIN_MAX][NW], s_max[CHAIN_MAX][NW], s_inv[CHAIN_MAX][NW];
+  const int tid = threadIdx.x;
+  const int wave = tid / 64;
+  const int lane = lane_id();
+  const uint32_t j0 = g.job_begin;
+  const uint32_t npair = g.job_end - g.job_begin;
+  for (uint32_t t = tid; t < npair; t += RNG_TPB) {
+    const CParams& P = src.job(j0 + t);
+    if (t == 0) s_in[0] = static_cast<const T*>(P.prev);
+    s_in[t + 1] = static_cast<const T*>(P.curr);
+    s_cap[t] = P.cap;
+  }
+  for (uint32_t i = tid; i < npair * NW; i += RNG_TPB) {
+    s_min[i / NW][i % NW] = ~0ull;
+    s_max[i / NW][i % NW] = 0ull;
+    s_inv[i / NW][i % NW] = 0ull;
+  }
+  __syncthreads();
+  const uint64_t n = src.job(j0).n;
+  const uint64_t nvec = n / V;
+
+  // pair t's extremes and invalid count of one step into the wave's slot
+  // (the whole wave calls it)
+  auto fold = [&](uint32_t t, unsigned long long kmin, unsigned long long kmax,
+                  unsigned long long ninv) {
+    kmin = wave_min_u64(kmin);
+    kmax = wave_max_u64(kmax);
+    ninv = wave_sum_u64(ninv);
+    if (lane == 0) {
+      s_min[t][wave] = kmin < s_min[t][wave] ? kmin : s_min[t][wave];
+      s_max[t][wave] = kmax > s_max[t][wave] ? kmax : s_max[t][wave];
+      s_inv[t][wave] += ninv;
+    }
+  };
+
+  for (uint64_t c = g.c_begin + blockIdx.x; c < g.c_end; c += gridDim.x) {
+    const uint64_t v0 = (c - g.c_begin) * g.chunk_vec;
+    uint64_t v1 = v0 + g.chunk_vec;
+    v1 = v1 < nvec ? v1 : nvec;
+    for (uint64_t vb = v0; vb < v1; vb += (uint64_t)RNG_TPB * K) {
+      // positions past the chunk load its last vector (every load is issued,
+      // so the waits below count a fixed number of loads) and are skipped
+      uint64_t vl[K];
+      bool on[K];
+#pragma unroll
+      for (int u = 0; u < K; ++u) {
+        const uint64_t vi = vb + (uint64_t)u * RNG_TPB + tid;
+        on[u] = vi < v1;
+        vl[u] = on[u] ? vi : v1 - 1;
+      }
+      // snapshot t in cur, t + 1 in nxt; t + 2 is loaded while pair t is
+      // computed
+      T cur[K][V], nxt[K][V];
+#pragma unroll
+      for (int u = 0; u < K; ++u) load_vec_t<NT>(s_in[0], vl[u], cur[u]);
+#pragma unroll
+      for (int u = 0; u < K; ++u) load_vec_t<NT>(s_in[1], vl[u], nxt[u]);
+      const T* ahead = s_in[2 <= npair ? 2 : npair];
+      for (uint32_t t = 0; t < npair; ++t) {
+        T nn[K][V];
+#pragma unroll
+        for (int u = 0; u < K; ++u) load_vec_t<NT>(ahead, vl[u], nn[u]);
+        // the loads go out before the arithmetic of this step
+        __builtin_amdgcn_sched_barrier(0);
+        ahead = s_in[t + 3 <= npair ? t + 3 : npair];
+        const double cap = s_cap[t];
+        unsigned long long kmin = ~0ull, kmax = 0ull, ninv = 0ull;
+#pragma unroll
+        for (int u = 0; u < K; ++u) {
+#pragma unroll
+          for (int v = 0; v < V; ++v) {
+            double d;
+            const bool ok = ratio_of((double)cur[u][v], (double)nxt[u][v], cap, d);
+            const unsigned long long k = ok ? order_key(d) : 0ull;
+            kmin = on[u] && ok && k < kmin ? k : kmin;
+            kmax = on[u] && ok && k > kmax ? k : kmax;
+            ninv += on[u] && !ok ? 1ull : 0ull;
+          }
+        }
+        fold(t, kmin, kmax, ninv);
+#pragma unroll
+        for (int u = 0; u < K; ++u)
+#pragma unroll
+          for (int v = 0; v < V; ++v) {
+            cur[u][v] = nxt[u][v];
+            nxt[u][v] = nn[u][v];
+          }
+      }
+    }
+    if (v1 == nvec && wave == 0) {  // the last chunk: scalar remainder (< V points)
+      const uint64_t jj = nvec * V + lane;
+      for (uint32_t t = 0; t < npair; ++t) {
+        unsigned long long kmin = ~0ull, kmax = 0ull, ninv = 0ull;
+        if (jj < n) {
+          double d;
+          if (ratio_of((double)s_in[t][jj], (double)s_in[t + 1][jj], s_cap[t], d)) {
+            kmin = kmax = order_key(d);
+          } else {
+            ninv = 1;
+          }
+        }
+        fold(t, kmin, kmax, ninv);
+      }
+    }
+  }
+  __syncthreads();
+  for (uint32_t t = tid; t < npair; t += RNG_TPB) {
+    unsigned long long kmin = ~0ull, kmax = 0ull, ninv = 0ull;
+    for (int w = 0; w < NW; ++w) {
+      kmin = s_min[t][w] < kmin ? s_min[t][w] : kmin;
+      kmax = s_max[t][w] > kmax ? s_max[t][w] : kmax;
+      ninv += s_inv[t][w];
+    }
+    Ctl* ctl = src.job(j0 + t).ctl;
+    if (kmin != ~0ull) atomicMin(&ctl->lo_key, kmin);
+    if (kmax != 0ull) atomicMax(&ctl->hi_key, kmax);
+    if (ninv) atomicAdd(&ctl->n_invalid, ninv);
+  }
+}
+
 // =====================================================================
 // k_derive: lo, hi, M and the bin window
 // =====================================================================
@@ -1289,9 +1426,9 @@ static uint64_t clamp_blocks(uint64_t want, uint64_t cap) {
 // element type (per index-width class for the encoder), whatever the number
 // of jobs.
 template <typename S>
-static hipError_t run_chain(S src, const Geo& base, uint32_t njobs, const JobGroup* dg,
-                            uint32_t ndg, const JobGroup* eg, uint32_t neg, const Tuning& tn,
-                            hipStream_t s) {
+static hipError_t run_chain(S src, const Geo& base, uint32_t njobs, const JobGroup* rg,
+                            uint32_t nrg, const JobGroup* dg, uint32_t ndg, const JobGroup* eg,
+                            uint32_t neg, const Tuning& tn, hipStream_t s) {
   const Geometry G = geometry();
   Geo all = base;
   all.job_begin = 0;
@@ -1301,13 +1438,25 @@ static hipError_t run_chain(S src, const Geo& base, uint32_t njobs, const JobGro
                                         ? 8
                                         : clamp_blocks((uint64_t)G.cus * 2 / njobs, 64);
   NK_LAUNCH(KK_INIT, k_init<S>, njobs, 256, src, all);
-  for (uint32_t i = 0; i < ndg; ++i) {
-    const Geo g = group_geo(base, dg[i]);
+  for (uint32_t i = 0; i < nrg; ++i) {
+    const Geo g = group_geo(base, rg[i]);
     const uint64_t chunks = g.c_end - g.c_begin;
     if (!chunks) continue;
     const uint64_t blocks = clamp_blocks(chunks, (uint64_t)G.cus * tn.range_blocks_per_cu);
-    const bool f32 = dg[i].dtype == NUMARCK_F32;
-    if (g.stream_nt) {
+    const bool f32 = rg[i].dtype == NUMARCK_F32;
+    if (rg[i].chain) {
+      if constexpr (std::is_same<S, JobTable>::value) {
+        if (g.stream_nt) {
+          if (f32) NK_LAUNCH(KK_RANGE, (k_range_chain<float, true>), blocks, RNG_TPB, src, g);
+          else NK_LAUNCH(KK_RANGE, (k_range_chain<double, true>), blocks, RNG_TPB, src, g);
+        } else {
+          if (f32) NK_LAUNCH(KK_RANGE, (k_range_chain<float, false>), blocks, RNG_TPB, src, g);
+          else NK_LAUNCH(KK_RANGE, (k_range_chain<double, false>), blocks, RNG_TPB, src, g);
+        }
+      } else {
+        return hipErrorInvalidValue;  // chains exist in batches only
+      }
+    } else if (g.stream_nt) {
       if (f32) NK_LAUNCH(KK_RANGE, (k_range<float, S, true>), blocks, RNG_TPB, src, g);
       else NK_LAUNCH(KK_RANGE, (k_range<double, S, true>), blocks, RNG_TPB, src, g);
     } else {
@@ -1400,7 +1549,7 @@ hipError_t launch_compress(const CParams& P0, const Tuning& tn, hipStream_t s) {
   grp.u_end = P.n_units;
   grp.nt = stream_nt_for(tn.stream_loads, 2 * P.n * (P.dtype == NUMARCK_F32 ? 4 : 8),
                          P.prev == P.curr);
-  return run_chain(OneJob{P}, base, 1, &grp, 1, &grp, 1, tn, s);
+  return run_chain(OneJob{P}, base, 1, &grp, 1, &grp, 1, &grp, 1, tn, s);
 }
 
 hipError_t launch_compress_batch(const BatchLaunch& b, hipStream_t s) {
@@ -1408,8 +1557,8 @@ hipError_t launch_compress_batch(const BatchLaunch& b, hipStream_t s) {
   base.chunk0 = b.chunk0_dev;
   base.unit0 = b.unit0_dev;
   base.chunk_vec = b.tune.chunk_vec ? b.tune.chunk_vec : 4096;  // groups carry their own
-  return run_chain(JobTable{b.jobs_dev}, base, b.njobs, b.dgroups, b.n_dgroups, b.egroups,
-                   b.n_egroups, b.tune, s);
+  return run_chain(JobTable{b.jobs_dev}, base, b.njobs, b.rgroups, b.n_rgroups, b.dgroups,
+                   b.n_dgroups, b.egroups, b.n_egroups, b.tune, s);
 }
 
 // =====================================================================

@@ -26,6 +26,8 @@ __device__ __forceinline__ uint32_t unpack_index(const uint32_t* __restrict__ pa
   return v & ((1u << B) - 1u);
 }
 
+constexpr int DCOUNT_GROUPS = 4;
+
 // Escapes among the indices of [r0, r1), summed over the calling wave (every
 // lane returns the total).  Reads the packed indices only.
 __device__ unsigned long long wave_count_escapes(const uint32_t* __restrict__ packed,
@@ -53,22 +55,33 @@ __device__ unsigned long long wave_count_escapes(const uint32_t* __restrict__ pa
       return (uint32_t)__popc(x);
     };
     if (((uintptr_t)packed & 15u) == 0) {
-      for (uint64_t g = wlo / 4 + lane; 4 * g < whi; g += 64) {
-        uint32_t x[4];
-        if (4 * g + 4 <= packed_words) {
-          const nk_u32x4 v = gload(reinterpret_cast<const nk_u32x4*>(packed) + g);
-          x[0] = v.x;
-          x[1] = v.y;
-          x[2] = v.z;
-          x[3] = v.w;
-        } else {
+      // DCOUNT_GROUPS groups per lane are loaded before any is counted, so
+      // that many 16-byte loads per lane are in flight at once
+      const uint64_t gend = (whi + 3) / 4;  // groups [wlo / 4, gend)
+      const uint64_t gfull = packed_words / 4;  // groups wholly inside the stream
+      for (uint64_t g0 = wlo / 4 + lane; g0 < gend; g0 += 64 * DCOUNT_GROUPS) {
+        nk_u32x4 v[DCOUNT_GROUPS];
 #pragma unroll
-          for (int k = 0; k < 4; ++k) x[k] = 4 * g + k < packed_words ? packed[4 * g + k] : 0u;
+        for (int u = 0; u < DCOUNT_GROUPS; ++u) {
+          const uint64_t g = g0 + 64 * (uint64_t)u;
+          if (g < gend && g < gfull) {
+            v[u] = gload(reinterpret_cast<const nk_u32x4*>(packed) + g);
+          } else {
+            v[u] = nk_u32x4{0u, 0u, 0u, 0u};
+            if (g < gend)
+#pragma unroll
+              for (int k = 0; k < 4; ++k)
+                if (4 * g + k < packed_words) v[u][k] = packed[4 * g + k];
+          }
         }
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          const uint64_t w = 4 * g + k;
-          if (w >= wlo && w < whi) cnt += word_escapes(w, x[k]);
+        for (int u = 0; u < DCOUNT_GROUPS; ++u) {
+          const uint64_t g = g0 + 64 * (uint64_t)u;
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            const uint64_t w = 4 * g + k;
+            if (w >= wlo && w < whi) cnt += word_escapes(w, v[u][k]);
+          }
         }
       }
     } else {

@@ -202,6 +202,10 @@ struct JobGroup {
   uint32_t job_begin, job_end;
   uint64_t c_begin, c_end;
   uint32_t u_begin, u_end;
+  // Range pass only: the jobs are a time chain (job i's curr is job i+1's
+  // prev, one n), read as one sweep over the snapshots; c_begin/c_end then
+  // count the chain's own chunks from 0.
+  uint32_t chain;
 };
 inline int enc_class(uint32_t B) { return B < 8 ? 0 : B == 8 ? 1 : B < 16 ? 2 : 3; }
 
@@ -213,6 +217,20 @@ inline uint32_t stream_nt_for(uint32_t mode, uint64_t bytes, bool shared_inputs)
   if (mode == 1) return 1u;
   if (mode == 2) return 0u;
   return (bytes >= NT_STREAM_BYTES && !shared_inputs) ? 1u : 0u;
+}
+
+// Pairs of one time chain in the range pass, at most (longer chains are cut).
+constexpr uint32_t CHAIN_MAX = 64;
+// 16-byte vectors per thread per step of a time chain's sweep.
+constexpr uint32_t CHAIN_K = 4;
+// Streaming chunk of a time chain of `pairs` pairs over `vecs` vectors per
+// snapshot: about four chunks per compute unit, a power of two from one
+// sweep step of a workgroup (CHAIN_K * 256 vectors) to 65536.
+inline uint32_t chain_chunk_vec(uint64_t vecs, int cus) {
+  const uint64_t want = vecs / (4 * (uint64_t)(cus > 0 ? cus : 1));
+  uint32_t c = CHAIN_K * 256;
+  while (c < 65536 && (uint64_t)c * 2 <= want) c *= 2;
+  return c;
 }
 
 // Streaming chunk of a launch group moving `vecs` 16-byte vectors per pass:
@@ -264,6 +282,8 @@ struct BatchLaunch {
   uint32_t n_dgroups;
   const JobGroup* egroups;  // by (dtype, class)
   uint32_t n_egroups;
+  const JobGroup* rgroups;  // range pass: runs of unchained jobs and time chains
+  uint32_t n_rgroups;
   Tuning tune;
 };
 hipError_t launch_compress_batch(const BatchLaunch& b, hipStream_t s);

@@ -187,3 +187,52 @@ def test_autotune(nk, tmp_path):
     assert nk.numarck_tuning_save(path.encode()) == nk.OK
     assert "f32 20 " in open(path).read()
     assert nk.numarck_tuning_load(path.encode()) == nk.OK
+
+
+def _series(n, dt, seed, steps, E=1e-3):
+    rng = np.random.default_rng(seed)
+    x = rng.lognormal(0.0, 1.0, n)
+    x[rng.choice(n, max(1, n // 500), replace=False)] = 0.0  # invalid points
+    out = [x.astype(dt)]
+    for _ in range(steps):
+        u = rng.random(n)
+        r = np.where(u < 0.8, rng.normal(0, 2 * E, n), rng.uniform(-0.3, 0.3, n))
+        out.append((out[-1].astype(np.float64) * (1 + r)).astype(dt))
+    return [_dev(a) for a in out]
+
+
+def test_time_chains(nk):
+    """Batches whose range pass sweeps time chains (each job's prev is the
+    previous job's curr): ragged lengths with a scalar remainder, both element
+    types, a chain longer than one sweep takes (cut in two), a chain broken by
+    another snapshot, per-pair error bounds, and unchained jobs between
+    chains.  Every job equals its plain compression; some equal the oracle."""
+    fa = _series(100_003, np.float64, 51, 6)
+    fb = _series(262_147, np.float32, 52, 5)
+    fc = _series(4_099, np.float32, 53, 70)  # 70 pairs: more than one chain
+    other = _series(100_003, np.float64, 54, 1)
+    jobs = []
+    for t in range(3):
+        jobs.append((fa[t], fa[t + 1], 1e-3 * (t + 1), 8))
+    jobs.append((other[0], other[1], 1e-3, 8))  # breaks the chain of fa
+    for t in range(3, 6):
+        jobs.append((fa[t], fa[t + 1], 1e-4, 12))
+    for t in range(5):
+        jobs.append((fb[t], fb[t + 1], 1e-3, 10))
+    for t in range(70):
+        jobs.append((fc[t], fc[t + 1], 1e-2, 5))
+    bj = [nk.BatchJob(p, q, E, B) for p, q, E, B in jobs]
+    plan = nk.Plan(bj, recon=True, bin_ids=True)
+    for rep in range(2):
+        res = plan.run()
+        torch.cuda.synchronize()
+        for i, ((p, q, E, B), c) in enumerate(zip(jobs, res)):
+            ref = nk.compress(p, q, E, B, recon=True, bin_ids=True)
+            assert_same_compression(c, ref, f"job {i} rep {rep}")
+    orc = oracle.get()
+    for i in (0, 5, 8, 80):
+        p, q, E, B = jobs[i]
+        pn, qn = to_np(p), to_np(q)
+        assert_matches_oracle(nk, res[i], orc.compress(pn, qn, E, B), pn, qn, E, B,
+                              check_hist=False, label=f"chain job {i}")
+    plan.close()
