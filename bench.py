@@ -255,8 +255,9 @@ def batched_vs_plain(torch, nk, jobs, reps: int) -> dict:
 
 def batched_section(torch, nk, inputs, reps: int) -> dict:
     """The uneven 64-variable workload (cube edges log-uniform in [32, 384],
-    60 % float64, E in {1e-4, 1e-3, 1e-2}, B in {8, 10, 12}) and 16 consecutive
-    pairs of a 3600 x 1800 float32 climate-like series (E = 1e-4, B = 10)."""
+    60 % float64, E in {1e-4, 1e-3, 1e-2}, B in {8, 10, 12}), 16 consecutive
+    pairs of a 3600 x 1800 float32 climate-like series (E = 1e-4, B = 10), and
+    the 9 consecutive pairs of the 512^3 float64 FLASH-like series."""
     out = {}
     jobs = []
     for sp in inputs.batched_specs(64):
@@ -269,6 +270,18 @@ def batched_section(torch, nk, inputs, reps: int) -> dict:
     del s
     out["climate_16pairs"] = batched_vs_plain(
         torch, nk, [nk.BatchJob(snaps[t], snaps[t + 1], 1e-4, 10) for t in range(16)], reps)
+    del snaps
+    torch.cuda.empty_cache()
+    # the 9 consecutive pairs of the 512^3 float64 FLASH-like series as one
+    # batch (a time chain: its range pass reads each snapshot once)
+    s = inputs.FlashSeries(edge=512, seed=1705, device="cuda")
+    snaps = [s.x.clone()] + [s.step().clone() for _ in range(SNAPSHOTS - 1)]
+    del s
+    out["flash3d_512cubed_9pairs"] = batched_vs_plain(
+        torch, nk, [nk.BatchJob(snaps[t], snaps[t + 1], E, B) for t in range(SNAPSHOTS - 1)],
+        max(2, reps // 4))
+    del snaps
+    torch.cuda.empty_cache()
     return out
 
 
