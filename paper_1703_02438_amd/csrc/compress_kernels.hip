@@ -818,13 +818,27 @@ __global__ void __launch_bounds__(SEL_TPB) k_select(SRC src, Geo g) {
   const unsigned long long tail_max = has_tail ? c->tail_max : 0ull;
   const double lo = empty ? 0.0 : c->lo;
   if (tid == 0) S.tail_pos = 0;
-  // window counts to LDS, with their statistics
+  // window counts to LDS (16-byte loads, all in flight at once), with their
+  // statistics; the buffer holds WIN counts, zero past win_len
   unsigned long long nzw = 0, mxw = 0, unused0 = ~0ull, unused1 = 0;
-  for (int i = tid; i < WIN; i += SEL_TPB) {
-    const uint32_t cn = (unsigned)i < win_len ? gload(P.gwin + i) : 0u;
-    S.win[i] = cn;
-    nzw += cn ? 1 : 0;
-    mxw = cn > mxw ? cn : mxw;
+  {
+    constexpr int G4 = WIN / 4 / SEL_TPB;
+    nk_u32x4 x[G4];
+#pragma unroll
+    for (int i = 0; i < G4; ++i)
+      x[i] = gload(reinterpret_cast<const nk_u32x4*>(P.gwin) + (tid + i * SEL_TPB));
+#pragma unroll
+    for (int i = 0; i < G4; ++i) {
+      const unsigned w0 = 4u * (unsigned)(tid + i * SEL_TPB);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const uint32_t cn = w0 + e < win_len ? x[i][e] : 0u;
+        x[i][e] = cn;
+        nzw += cn ? 1 : 0;
+        mxw = cn > mxw ? cn : mxw;
+      }
+      reinterpret_cast<nk_u32x4*>(S.win)[tid + i * SEL_TPB] = x[i];
+    }
   }
   sel_reduce4(nzw, unused1, unused0, mxw, S);  // also orders the LDS writes
   const unsigned long long nz = nzw + tail_bins;
@@ -874,39 +888,55 @@ __global__ void __launch_bounds__(SEL_TPB) k_select(SRC src, Geo g) {
     sel_reduce4(sel_tail, sel_below, u0, u1, S);
   }
 
-  // window: LUT, centres and bin ids in ascending bin order.
-  // Thread t owns window bins [t*PER, (t+1)*PER).
-  constexpr int PER = WIN / SEL_TPB;
+  // window: LUT, centres and bin ids in ascending bin order.  Wave v owns
+  // the window bins [v * SEL_WBINS, (v + 1) * SEL_WBINS), read as 64-bin
+  // segments (lane l takes bin l of a segment: no LDS bank conflicts); a
+  // segment's selected bins are ranked by ballot, the waves by one scan.
+  constexpr int SEL_WBINS = WIN / (SEL_TPB / 64);
+  constexpr int SEGS = SEL_WBINS / 64;
+  const int wv = tid / 64, ln = tid & 63;
+  auto chosen = [&](unsigned w) {
+    const uint32_t cn = S.win[w];
+    const long long id = wbase + (long long)w;
+    return cn != 0 && (cn > tau || (cn == tau && id <= cut));
+  };
   unsigned mine = 0;
 #pragma unroll
-  for (int q = 0; q < PER; ++q) {
-    const unsigned w = tid * PER + q;
-    const uint32_t cn = S.win[w];
-    const long long id = wbase + (long long)w;
-    mine += (cn != 0 && (cn > tau || (cn == tau && id <= cut))) ? 1u : 0u;
+  for (int q = 0; q < SEGS; ++q)
+    mine += (unsigned)__popcll(__ballot(chosen((unsigned)(wv * SEL_WBINS + q * 64 + ln))));
+  // exclusive prefix of the wave totals (every lane holds its wave's total)
+  __syncthreads();
+  if (ln == 0) S.red[wv] = mine;
+  __syncthreads();
+  unsigned long long wbefore = 0, nwin_sel = 0;
+  for (int i = 0; i < SEL_TPB / 64; ++i) {
+    const unsigned long long r = S.red[i];
+    wbefore += i < wv ? r : 0ull;
+    nwin_sel += r;
   }
-  unsigned long long nwin_sel;
-  unsigned rank = (unsigned)sel_below + (unsigned)sel_excl_scan(mine, S, &nwin_sel);
   if (tid == 0) c->nsel_window = (unsigned)nwin_sel;
-  // codes into LDS (each thread rewrites only its own bins), then out coalesced
+  unsigned rank = (unsigned)sel_below + (unsigned)wbefore;
 #pragma unroll 4
-  for (int q = 0; q < PER; ++q) {
-    const unsigned w = tid * PER + q;
-    const uint32_t cn = S.win[w];
-    const long long id = wbase + (long long)w;
+  for (int q = 0; q < SEGS; ++q) {
+    const unsigned w = (unsigned)(wv * SEL_WBINS + q * 64 + ln);
+    const unsigned long long mk = __ballot(chosen(w));
+    const unsigned r = rank + __builtin_amdgcn_mbcnt_hi((unsigned)(mk >> 32),
+                                                        __builtin_amdgcn_mbcnt_lo((unsigned)mk, 0u));
     uint32_t l = k;  // escape code: not selected
-    if (cn != 0 && (cn > tau || (cn == tau && id <= cut))) {
-      l = rank;
-      gstore(centers + rank, (T)centre_of<T>(id, lo, P.E));
-      if (P.bin_ids) gstore(P.bin_ids + rank, (int64_t)id);
-      rank += 1;
+    if ((mk >> ln) & 1ull) {
+      l = r;
+      gstore(centers + r, (T)centre_of<T>(wbase + (long long)w, lo, P.E));
+      if (P.bin_ids) gstore(P.bin_ids + r, (int64_t)(wbase + (long long)w));
     }
-    S.win[w] = l;
+    S.win[w] = l;  // each lane rewrites only the bin it read
+    rank += (unsigned)__popcll(mk);
   }
   __syncthreads();
   uint32_t* lut2 = reinterpret_cast<uint32_t*>(P.lut);  // two 16-bit codes per word
-  for (int i = tid; i < WIN / 2; i += SEL_TPB)
-    gstore(lut2 + i, (S.win[2 * i] & 0xFFFFu) | (S.win[2 * i + 1] << 16));
+  for (int i = tid; i < WIN / 2; i += SEL_TPB) {
+    const uint2 pr = reinterpret_cast<const uint2*>(S.win)[i];
+    gstore(lut2 + i, (pr.x & 0xFFFFu) | (pr.y << 16));
+  }
   if (tid == 0) {
     c->n_nonzero = nz;
     c->tau = tau;
