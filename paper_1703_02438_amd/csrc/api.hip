@@ -216,7 +216,6 @@ static CParams make_params(const void* prev, const void* curr, uint64_t n, numar
   P.twoE = 2.0 * E;
   P.cap = ldexp(E, 50);
   P.inv2E = 1.0 / P.twoE;
-  P.fastbin = (isfinite(P.inv2E) && P.inv2E >= 2.2250738585072014e-308) ? 1 : 0;
   P.B = B;
   P.k = (1u << B) - 1u;
   P.block_bytes = block_bytes;

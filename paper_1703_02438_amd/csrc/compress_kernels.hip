@@ -444,7 +444,7 @@ __global__ void __launch_bounds__(HIST_TPB) k_hist(S src, Geo g) {
   // The current job's parameters and window, loaded once when the workgroup
   // reaches the job: inside a saturated stream a dependent load per chunk
   // would stall every wave of the workgroup.
-  bool have = false, empty = true, fast = false;
+  bool have = false, empty = true;
   double lo = 0.0, wbase_d = 0.0, wlen_d = 0.0, cap = 0.0, twoE = 1.0, inv2E = 1.0;
   unsigned wl = 0;
   uint32_t* gwin = nullptr;
@@ -481,7 +481,6 @@ __global__ void __launch_bounds__(HIST_TPB) k_hist(S src, Geo g) {
       cap = P.cap;
       twoE = P.twoE;
       inv2E = P.inv2E;
-      fast = P.fastbin != 0;
       ts = TailSink{&P.ctl->tail_count, P.tail, P.tail_cap};
     }
     if (empty) continue;  // uniform: the whole chunk belongs to this job
@@ -507,7 +506,7 @@ __global__ void __launch_bounds__(HIST_TPB) k_hist(S src, Geo g) {
         for (int v = 0; v < V; ++v) {
           double d = 0.0;
           const bool valid = inr && ratio_of((double)pv[u][v], (double)qv[u][v], cap, d);
-          const double m = valid ? bin_floor(d - lo, twoE, inv2E, fast) : 0.0;
+          const double m = valid ? bin_floor(d - lo, twoE, inv2E) : 0.0;
           hist_count(win, valid, m, wbase_d, wlen_d, ts);
         }
       }
@@ -517,7 +516,7 @@ __global__ void __launch_bounds__(HIST_TPB) k_hist(S src, Geo g) {
       double d = 0.0;
       bool valid = false;
       if (jj < n) valid = ratio_of((double)prev[jj], (double)curr[jj], cap, d);
-      const double m = valid ? bin_floor(d - lo, twoE, inv2E, fast) : 0.0;
+      const double m = valid ? bin_floor(d - lo, twoE, inv2E) : 0.0;
       hist_count(win, valid, m, wbase_d, wlen_d, ts);
     }
   }
@@ -1000,8 +999,13 @@ __global__ void __launch_bounds__(TR_TPB) k_tailrank(S src, Geo g) {
 // packed stream -- or 0 for any B.
 constexpr int ENC_CTAB = 2048;  // LDS centre table when 2^B <= this
 
+// Waves per SIMD the float64 B = 8 encoders are compiled for (their
+// registers fit five without spilling); others take what they need.
+template <typename T, int PACK>
+constexpr int enc_min_waves = (sizeof(T) == 8 && PACK == 8) ? 5 : 1;
+
 template <typename T, typename LT, int PACK, typename S, bool NT>
-__global__ void __launch_bounds__(UNIT_TPB) k_encode(S src, Geo g) {
+__global__ void __launch_bounds__(UNIT_TPB, (enc_min_waves<T, PACK>)) k_encode(S src, Geo g) {
   constexpr int V = Traits<T>::V;
   constexpr int R = ENC_ROUNDS;
   constexpr int WT = R * 64 * V;  // elements of a wave tile
@@ -1036,8 +1040,8 @@ __global__ void __launch_bounds__(UNIT_TPB) k_encode(S src, Geo g) {
   const unsigned nsel_win = empty ? 0u : c->nsel_window;
   const uint32_t esc = P.k;
   const uint32_t B = P.B;
-  const bool fast = P.fastbin != 0;
-  const bool use_ctab = ((uint32_t)1 << B) <= (uint32_t)NCTAB;
+  // with one-byte codes (B <= 8) every centre fits the table
+  const bool use_ctab = sizeof(LT) == 1 || ((uint32_t)1 << B) <= (uint32_t)NCTAB;
   for (int i = tid; i < WIN; i += UNIT_TPB) s_lut[i] = (LT)gload(P.lut + i);
   if (use_ctab) {
     const T* cen = static_cast<const T*>(P.centers);
@@ -1108,9 +1112,9 @@ __global__ void __launch_bounds__(UNIT_TPB) k_encode(S src, Geo g) {
         double d;
         const bool valid = ratio_of(p, q, P.cap, d) & inr;
         const double x = d - lo;
-        bool sure = true;
-        double m = fast ? bin_floor_fast(x, P.inv2E, sure) : 0.0;
-        const bool exact = valid & !(fast & sure);
+        bool sure;
+        double m = bin_floor_fast(x, P.inv2E, sure);
+        const bool exact = valid & !sure;
         if (__ballot(exact)) {
           if (exact) m = floor(x / P.twoE);
         }

@@ -89,16 +89,17 @@ __device__ __forceinline__ long long bin_of(double d, double lo, double twoE) {
 // correctly rounded quotient.  The fast path multiplies by inv = fl(1/twoE):
 // t' = fl(x * inv) is within 2^-51 * t' of t = fl(x / twoE) (three roundings
 // of at most 2^-53 each), so floor(t') == floor(t) unless an integer lies
-// within that distance of t'.  Those cases (and non-finite t') take the
-// exact division.
-__device__ __forceinline__ double bin_floor(double x, double twoE, double inv, bool fast) {
-  if (fast) {
-    const double t = x * inv;
-    const double f = floor(t);
-    const double frac = t - f;  // exact (Sterbenz) for t >= 0
-    const double thr = t * 0x1p-49;
-    if ((frac > thr) && ((1.0 - frac) > thr)) return f;
-  }
+// within that distance of t'.  Those cases take the exact division, and so
+// does every x when 2E is subnormal: inv is then infinite, t' infinite or
+// NaN, and the check fails.  (For x below 2^50 * twoE, as every valid ratio
+// gives, t' cannot overflow; a subnormal t' is below 1, where both floors
+// are 0.)
+__device__ __forceinline__ double bin_floor(double x, double twoE, double inv) {
+  const double t = x * inv;
+  const double f = floor(t);
+  const double frac = t - f;  // exact (Sterbenz) for t >= 0
+  const double thr = t * 0x1p-49;
+  if ((frac > thr) && ((1.0 - frac) > thr)) return f;
   return floor(x / twoE);
 }
 

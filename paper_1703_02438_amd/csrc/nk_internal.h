@@ -106,7 +106,6 @@ struct CParams {
   uint64_t n;
   double E, twoE, cap;
   double inv2E;      // binary64 1/(2E), used with an exactness check
-  int fastbin;       // inv2E is finite and normal
   uint32_t B;
   uint32_t k;        // 2^B - 1 (also the escape code)
   uint64_t epb;      // elements per index-table block

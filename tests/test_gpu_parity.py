@@ -249,3 +249,17 @@ def test_range_deep_in_block(nk, B):
             g, gfl = _range_at(nk, c, p, s, ln, packed=buf.data_ptr() + 4 * off)
             assert int(gfl.item()) == 0
             assert np.array_equal(bits(to_np(g)), bits(r)), f"range {s},{ln} offset {4 * off}"
+
+
+@pytest.mark.parametrize("E", [1e-310, 5e-324, 2.0 ** -1022])
+def test_subnormal_error_bound(nk, E):
+    """An error bound whose bin width 2E is subnormal (1/(2E) overflows):
+    only ratios of exactly 0 are valid, and their bins come from the exact
+    division; every other point escapes."""
+    rng = np.random.default_rng(77)
+    n = 70_001
+    prev = rng.lognormal(0.0, 1.0, n)
+    curr = np.where(rng.random(n) < 0.6, prev, prev * (1 + rng.normal(0, 1e-3, n)))
+    c, o, p = compare_compress(nk, prev, curr, E, 8, label="subnormal E")
+    assert c.header().M == 1
+    compare_decompress(nk, c, o, p, prev, _ranges(n, rng))
