@@ -399,19 +399,9 @@ struct TailSink {
   uint64_t cap;
 };
 
-// Count one element per lane: window bins with atomics on `win` (LDS or the
-// job's global window counts), other valid points appended to the tail list
-// (one global atomic per wave).
-__device__ __forceinline__ void hist_count(uint32_t* win, bool valid, double m, double wbase_d,
-                                           double wlen_d, const TailSink& ts) {
-  const double w = m - wbase_d;  // exact: both are integers below 2^51
-  const bool inwin = valid && w >= 0.0 && w < wlen_d;
-#if NK_HIST_HYBRID
-  lds_count(win, inwin, inwin ? (unsigned)(int)w : 0u);
-#else
-  if (inwin) atomicAdd(&win[(int)w], 1u);
-#endif
-  const bool tail = valid && !inwin;
+// Append the bin id m of every lane with `tail` to the tail list (one global
+// atomic per wave).  The whole wave calls it.
+__device__ __forceinline__ void tail_append(bool tail, double m, const TailSink& ts) {
   const unsigned long long tm = __ballot(tail);
   if (tm) {
     const int leader = __ffsll((long long)tm) - 1;
@@ -427,6 +417,20 @@ __device__ __forceinline__ void hist_count(uint32_t* win, bool valid, double m, 
   }
 }
 
+// Count one element per lane: window bins with atomics on `win` (LDS or the
+// job's global window counts), other valid points appended to the tail list.
+__device__ __forceinline__ void hist_count(uint32_t* win, bool valid, double m, double wbase_d,
+                                           double wlen_d, const TailSink& ts) {
+  const double w = m - wbase_d;  // exact: both are integers below 2^51
+  const bool inwin = valid && w >= 0.0 && w < wlen_d;
+#if NK_HIST_HYBRID
+  lds_count(win, inwin, inwin ? (unsigned)(int)w : 0u);
+#else
+  if (inwin) atomicAdd(&win[(int)w], 1u);
+#endif
+  tail_append(valid && !inwin, m, ts);
+}
+
 // LDSH: count window bins in an LDS copy flushed to the job's global counts
 // when the block moves to another job (or finishes); otherwise count
 // directly in the global counts (more atomic traffic, no LDS, higher
@@ -434,7 +438,9 @@ __device__ __forceinline__ void hist_count(uint32_t* win, bool valid, double m, 
 template <typename T, typename S, bool LDSH, bool NT>
 __global__ void __launch_bounds__(HIST_TPB) k_hist(S src, Geo g) {
   constexpr int V = Traits<T>::V;
-  __shared__ uint32_t lds[LDSH ? WIN : 1];
+  // the window, then one slot per lane for points outside it (never read):
+  // every lane adds to some slot, so the count needs no branch
+  __shared__ uint32_t lds[LDSH ? WIN + 64 : 1];
   const int tid = threadIdx.x;
   if (LDSH) {
     for (int i = tid; i < WIN; i += HIST_TPB) lds[i] = 0u;
@@ -452,8 +458,37 @@ __global__ void __launch_bounds__(HIST_TPB) k_hist(S src, Geo g) {
   const T* curr = nullptr;
   uint64_t n = 0, nvec = 0;
   TailSink ts{nullptr, nullptr, 0};
+  // Points outside the window: each wave gathers their bin ids in its own
+  // LDS buffer and appends a full buffer to the job's tail list with one
+  // global atomic (a returning atomic per point on the one tail counter
+  // stalls the stream wherever the tail is dense).
+  __shared__ long long s_tbuf[LDSH ? HIST_TPB / 64 : 1][64];
+  const int wave = tid / 64;
+  const int lane = tid & 63;
+  unsigned tbn = 0;  // entries in this wave's buffer (wave-uniform)
+  auto tail_flush = [&]() {  // the whole wave calls it
+    if (tbn == 0) return;
+    unsigned long long base = 0;
+    if (lane == 0) base = atomicAdd(ts.count, (unsigned long long)tbn);
+    const unsigned lo32 = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)base, 0);
+    const unsigned hi32 = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(base >> 32), 0);
+    base = ((unsigned long long)hi32 << 32) | lo32;
+    wave_lds_sync();
+    if ((unsigned)lane < tbn && base + lane < ts.cap) gstore(ts.list + base + lane, (int64_t)s_tbuf[wave][lane]);
+    wave_lds_sync();
+    tbn = 0;
+  };
+  auto tail_push = [&](bool tail, double m) {  // the whole wave calls it
+    const unsigned long long tm = __ballot(tail);
+    if (!tm) return;
+    const unsigned cnt = (unsigned)__popcll(tm);
+    if (tbn + cnt > 64u) tail_flush();
+    if (tail) s_tbuf[wave][tbn + (unsigned)__popcll(tm & lanemask_lt())] = (long long)m;
+    tbn += cnt;
+  };
   auto flush = [&]() {  // LDS window counts to the job's global counts
     if (!LDSH) return;
+    tail_flush();
     __syncthreads();
     for (unsigned i = tid; i < (unsigned)WIN; i += HIST_TPB) {
       const uint32_t v = lds[i];
@@ -488,7 +523,10 @@ __global__ void __launch_bounds__(HIST_TPB) k_hist(S src, Geo g) {
     const uint64_t v0 = (c - cu.first) * g.chunk_vec;
     uint64_t v1 = v0 + g.chunk_vec;
     v1 = v1 < nvec ? v1 : nvec;
-    for (uint64_t vb = v0 + tid; vb < v1; vb += HIST_TPB * HIST_UNROLL) {
+    // every lane runs every step (the bound is the workgroup's, not the
+    // lane's): the tail buffer's flush needs the whole wave
+    for (uint64_t vs = v0; vs < v1; vs += HIST_TPB * HIST_UNROLL) {
+      const uint64_t vb = vs + tid;
       T pv[HIST_UNROLL][V], qv[HIST_UNROLL][V];
 #pragma unroll
       for (int u = 0; u < HIST_UNROLL; ++u) {
@@ -498,16 +536,47 @@ __global__ void __launch_bounds__(HIST_TPB) k_hist(S src, Geo g) {
           load_vec_t<NT>(curr, vi, qv[u]);
         }
       }
+      if constexpr (LDSH) {
+        // window points counted without branches; the (rare) points outside
+        // the window go to the tail list after one test for the whole step
+        double mt[HIST_UNROLL][V];
+        bool tl[HIST_UNROLL][V];
+        bool anyt = false;
 #pragma unroll
-      for (int u = 0; u < HIST_UNROLL; ++u) {
-        const uint64_t vi = vb + (uint64_t)u * HIST_TPB;
-        const bool inr = vi < v1;
+        for (int u = 0; u < HIST_UNROLL; ++u) {
+          const uint64_t vi = vb + (uint64_t)u * HIST_TPB;
+          const bool inr = vi < v1;
 #pragma unroll
-        for (int v = 0; v < V; ++v) {
-          double d = 0.0;
-          const bool valid = inr && ratio_of((double)pv[u][v], (double)qv[u][v], cap, d);
-          const double m = valid ? bin_floor(d - lo, twoE, inv2E) : 0.0;
-          hist_count(win, valid, m, wbase_d, wlen_d, ts);
+          for (int v = 0; v < V; ++v) {
+            double d = 0.0;
+            const bool valid = inr && ratio_of((double)pv[u][v], (double)qv[u][v], cap, d);
+            const double m = valid ? bin_floor(d - lo, twoE, inv2E) : 0.0;
+            const double w = m - wbase_d;  // exact: both are integers below 2^51
+            const bool inwin = valid && w >= 0.0 && w < wlen_d;
+            atomicAdd(&lds[inwin ? (int)w : WIN + (tid & 63)], 1u);
+            mt[u][v] = m;
+            tl[u][v] = valid && !inwin;
+            anyt |= tl[u][v];
+          }
+        }
+        if (__ballot(anyt)) {
+#pragma unroll
+          for (int u = 0; u < HIST_UNROLL; ++u)
+#pragma unroll
+            for (int v = 0; v < V; ++v) tail_push(tl[u][v], mt[u][v]);
+        }
+      } else {
+#pragma unroll
+        for (int u = 0; u < HIST_UNROLL; ++u) {
+          const uint64_t vi = vb + (uint64_t)u * HIST_TPB;
+          const bool inr = vi < v1;
+#pragma unroll
+          for (int v = 0; v < V; ++v) {
+            double d = 0.0;
+            const bool valid = inr && ratio_of((double)pv[u][v], (double)qv[u][v], cap, d);
+            const double m = valid ? bin_floor(d - lo, twoE, inv2E) : 0.0;
+            hist_count(win, valid, m, wbase_d, wlen_d, ts);
+          }
         }
       }
     }
