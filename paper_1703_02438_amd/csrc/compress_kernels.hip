@@ -1083,7 +1083,9 @@ __global__ void __launch_bounds__(UNIT_TPB, (enc_min_waves<T, PACK>)) k_encode(S
   constexpr int NCTAB = sizeof(LT) == 1 ? 256 : ENC_CTAB;
   __shared__ LT s_lut[WIN];
   __shared__ double s_ctab[NCTAB];
-  __shared__ IT s_idx[NWAVE][WT];
+  // the tile's indices, for widths that are packed from LDS (8- and 16-bit
+  // codes go from registers straight to the packed stream)
+  __shared__ IT s_idx[NWAVE][PACK == 0 ? WT : 1];
   // float64 full tiles stage up to 64 escapes in LDS and write them with one
   // store; float32 tiles (8 element slots per lane, a compute-bound loop)
   // store each slot directly, lanes without an escape writing the sink
@@ -1170,9 +1172,14 @@ __global__ void __launch_bounds__(UNIT_TPB, (enc_min_waves<T, PACK>)) k_encode(S
     const uint32_t lim = FULL ? (uint32_t)WT
                               : (left < (uint64_t)WT ? (uint32_t)left : (uint32_t)WT);
     unsigned long long emask[R][V];
+    // 8- or 16-bit codes: a lane's V codes of round r, in stream order
+    using CW = typename std::conditional<V * (PACK ? PACK : 8) <= 32, uint32_t,
+                                         unsigned long long>::type;
+    CW cw[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const uint32_t e0 = ((uint32_t)r * 64 + lane) * V;  // tile-local element
+      cw[r] = 0;
 #pragma unroll
       for (int v = 0; v < V; ++v) {
         const bool inr = e0 + v < lim;
@@ -1214,9 +1221,37 @@ __global__ void __launch_bounds__(UNIT_TPB, (enc_min_waves<T, PACK>)) k_encode(S
         const T r_t = (T)(p * (1.0 + cc));
         const bool ok = sel & (fabs((double)r_t - q) <= P.E * fabs(p));
         code = ok ? code : esc;
-        idx[e0 + v] = (IT)(inr ? code : 0u);
+        if constexpr (PACK == 0)
+          idx[e0 + v] = (IT)(inr ? code : 0u);
+        else
+          cw[r] |= (CW)(inr ? code : 0u) << (v * PACK);
         emask[r][v] = __ballot(inr & !ok);
         if (recon) pv[r][v] = ok ? r_t : qv[r][v];  // the register now holds the reconstruction
+      }
+    }
+    if constexpr (PACK != 0) {
+      // element j's code is at bit j * PACK: a lane's V codes of a round are
+      // V * PACK / 8 contiguous bytes (2, 4 or 8), stored as 16- or 32-bit
+      // words; a partial tile stores code by code up to the stream's end
+      // (its padding codes are zero)
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const uint64_t j0 = t0 + ((uint64_t)r * 64 + lane) * V;  // first element
+        if (FULL) {
+          if constexpr (V * PACK == 16) {
+            gstore(reinterpret_cast<uint16_t*>(P.packed) + j0 / 2, (uint16_t)cw[r]);
+          } else {
+#pragma unroll
+            for (int h = 0; h < V * PACK / 32; ++h)
+              gstore(P.packed + j0 * PACK / 32 + h, (uint32_t)(cw[r] >> (32 * h)));
+          }
+        } else {
+          const uint64_t pe = (uint64_t)P.packed_words * (32 / PACK);  // codes in the stream
+#pragma unroll
+          for (int v = 0; v < V; ++v)
+            if (j0 + v < pe)
+              gstore(reinterpret_cast<IT*>(P.packed) + j0 + v, (IT)(cw[r] >> (v * PACK)));
+        }
       }
     }
     if (recon) {
@@ -1282,7 +1317,8 @@ __global__ void __launch_bounds__(UNIT_TPB, (enc_min_waves<T, PACK>)) k_encode(S
     }
 
     // bit-pack the wave tile: word w holds bits [32w, 32w + 32) of its stream
-    wave_lds_sync();
+    constexpr bool USE_LDS = PACK == 0 || STAGE;  // LDS written above, read below
+    if (USE_LDS) wave_lds_sync();
     if (FULL && STAGE) {  // the staged escapes: lane i writes the tile's i-th, the others the sink
       const bool has = (unsigned)lane < run - run0;
       const T val = s_esc[wave][lane];
@@ -1290,16 +1326,7 @@ __global__ void __launch_bounds__(UNIT_TPB, (enc_min_waves<T, PACK>)) k_encode(S
     }
     const uint64_t word0 = t0 * B / 32;
     if (PACK != 0) {
-      // 8- or 16-bit indices: the index array is the packed stream
-      const uint32_t* iw = reinterpret_cast<const uint32_t*>(idx);
-      if (FULL) {
-        constexpr uint32_t TW = (uint32_t)(WT * (PACK != 0 ? PACK : 8) / 32);  // a multiple of 64
-#pragma unroll
-        for (uint32_t w = lane; w < TW; w += 64) gstore(P.packed + word0 + w, iw[w]);
-      } else {
-        for (uint32_t w = lane; w < tile_words; w += 64)
-          if (word0 + w < P.packed_words) gstore(P.packed + word0 + w, iw[w]);
-      }
+      // stored from registers above
     } else if (FULL) {
       // at most B = 7 (u8 indices) or 15 (u16) bits: a fixed number of store
       // rounds, lanes past the tile's words writing the sink
@@ -1338,7 +1365,7 @@ __global__ void __launch_bounds__(UNIT_TPB, (enc_min_waves<T, PACK>)) k_encode(S
         gstore(P.packed + word0 + w, word);
       }
     }
-    wave_lds_sync();
+    if (USE_LDS) wave_lds_sync();
   };
 
   // Two register sets: the loads of one tile are in flight while the other
