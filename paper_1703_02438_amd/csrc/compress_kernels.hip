@@ -1176,6 +1176,42 @@ __global__ void __launch_bounds__(UNIT_TPB, (enc_min_waves<T, PACK>)) k_encode(S
     using CW = typename std::conditional<V * (PACK ? PACK : 8) <= 32, uint32_t,
                                          unsigned long long>::type;
     CW cw[R];
+    // float64 tiles (four points per lane) take the bins of all their points
+    // first -- the multiply by 1/(2E), then, if any lane needs it, the exact
+    // division where it is unsure -- so that one wave-wide test covers the
+    // tile; float32 tiles (eight points per lane) test point by point, which
+    // keeps their registers within four waves per SIMD
+    constexpr bool SPLIT = V == 2;
+    constexpr int RS = SPLIT ? R : 1, VS = SPLIT ? V : 1;
+    double mb[RS][VS];
+    bool vb[RS][VS], ex[RS][VS];
+    if constexpr (SPLIT) {
+      bool need = false;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const uint32_t e0 = ((uint32_t)r * 64 + lane) * V;
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+          double d;
+          vb[r][v] = ratio_of((double)pv[r][v], (double)qv[r][v], P.cap, d) & (e0 + v < lim);
+          bool sure;
+          mb[r][v] = bin_floor_fast(d - lo, P.inv2E, sure);
+          ex[r][v] = vb[r][v] & !sure;
+          need |= ex[r][v];
+        }
+      }
+      if (__ballot(need)) {
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+          for (int v = 0; v < V; ++v)
+            if (ex[r][v]) {
+              double d;
+              (void)ratio_of((double)pv[r][v], (double)qv[r][v], P.cap, d);
+              mb[r][v] = floor((d - lo) / P.twoE);
+            }
+      }
+    }
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const uint32_t e0 = ((uint32_t)r * 64 + lane) * V;  // tile-local element
@@ -1185,30 +1221,39 @@ __global__ void __launch_bounds__(UNIT_TPB, (enc_min_waves<T, PACK>)) k_encode(S
         const bool inr = e0 + v < lim;
         const double p = (double)pv[r][v];
         const double q = (double)qv[r][v];
-        double d;
-        const bool valid = ratio_of(p, q, P.cap, d) & inr;
-        const double x = d - lo;
-        bool sure;
-        double m = bin_floor_fast(x, P.inv2E, sure);
-        const bool exact = valid & !sure;
-        if (__ballot(exact)) {
-          if (exact) m = floor(x / P.twoE);
+        bool valid;
+        double m;
+        if constexpr (SPLIT) {
+          valid = vb[r][v];
+          m = mb[r][v];
+        } else {
+          double d;
+          valid = ratio_of(p, q, P.cap, d) & inr;
+          const double x = d - lo;
+          bool sure;
+          m = bin_floor_fast(x, P.inv2E, sure);
+          const bool exact = valid & !sure;
+          if (__ballot(exact)) {
+            if (exact) m = floor(x / P.twoE);
+          }
         }
         const double w = m - wbase_d;  // exact
         const bool inwin = valid & (w >= 0.0) & (w < wlen_d);
         uint32_t code = s_lut[inwin ? (int)w : 0];
         code = inwin ? code : esc;
-        const bool tail = valid & !inwin & (nsel_tail != 0);
-        if (__ballot(tail)) {
-          if (tail) {  // binary search among the selected tail bins
-            const long long mi = (long long)m;
-            unsigned a = 0, b = nsel_tail;
-            while (a < b) {
-              const unsigned mid = (a + b) >> 1;
-              if (gload(P.sorted_tail + mid) < mi) a = mid + 1; else b = mid;
+        if (nsel_tail != 0) {  // uniform: selected bins outside the window exist
+          const bool tail = valid & !inwin;
+          if (__ballot(tail)) {
+            if (tail) {  // binary search among the selected tail bins
+              const long long mi = (long long)m;
+              unsigned a = 0, b = nsel_tail;
+              while (a < b) {
+                const unsigned mid = (a + b) >> 1;
+                if (gload(P.sorted_tail + mid) < mi) a = mid + 1; else b = mid;
+              }
+              if (a < nsel_tail && gload(P.sorted_tail + a) == mi)
+                code = a + (mi > wbase ? nsel_win : 0u);
             }
-            if (a < nsel_tail && gload(P.sorted_tail + a) == mi)
-              code = a + (mi > wbase ? nsel_win : 0u);
           }
         }
         const bool sel = code != esc;
