@@ -55,34 +55,35 @@ __device__ unsigned long long wave_count_escapes(const uint32_t* __restrict__ pa
       return (uint32_t)__popc(x);
     };
     if (((uintptr_t)packed & 15u) == 0) {
-      // DCOUNT_GROUPS groups per lane are loaded before any is counted, so
-      // that many 16-byte loads per lane are in flight at once
-      const uint64_t gend = (whi + 3) / 4;  // groups [wlo / 4, gend)
-      const uint64_t gfull = packed_words / 4;  // groups wholly inside the stream
-      for (uint64_t g0 = wlo / 4 + lane; g0 < gend; g0 += 64 * DCOUNT_GROUPS) {
+      // Groups of four words wholly inside [r0, r1) count without masks,
+      // DCOUNT_GROUPS of them per lane loaded before any is counted; the few
+      // words at either end (up to seven a side) take word_escapes.
+      const uint64_t cw0 = (r0 + per - 1) / per, cw1 = r1 / per;  // whole words [cw0, cw1)
+      const uint64_t gc0 = (cw0 + 3) / 4;
+      const uint64_t gc1 = cw1 / 4 > gc0 ? cw1 / 4 : gc0;  // clean groups [gc0, gc1)
+      auto clean = [&](uint32_t x) -> uint32_t {
+        for (uint32_t sh = 1; sh < B; sh <<= 1) x &= x >> sh;
+        return (uint32_t)__popc(x & start_mask);
+      };
+      for (uint64_t g0 = gc0 + lane; g0 < gc1; g0 += 64 * DCOUNT_GROUPS) {
         nk_u32x4 v[DCOUNT_GROUPS];
 #pragma unroll
         for (int u = 0; u < DCOUNT_GROUPS; ++u) {
           const uint64_t g = g0 + 64 * (uint64_t)u;
-          if (g < gend && g < gfull) {
-            v[u] = gload(reinterpret_cast<const nk_u32x4*>(packed) + g);
-          } else {
-            v[u] = nk_u32x4{0u, 0u, 0u, 0u};
-            if (g < gend)
-#pragma unroll
-              for (int k = 0; k < 4; ++k)
-                if (4 * g + k < packed_words) v[u][k] = packed[4 * g + k];
-          }
+          v[u] = g < gc1 ? gload(reinterpret_cast<const nk_u32x4*>(packed) + g)
+                         : nk_u32x4{0u, 0u, 0u, 0u};
         }
 #pragma unroll
-        for (int u = 0; u < DCOUNT_GROUPS; ++u) {
-          const uint64_t g = g0 + 64 * (uint64_t)u;
-#pragma unroll
-          for (int k = 0; k < 4; ++k) {
-            const uint64_t w = 4 * g + k;
-            if (w >= wlo && w < whi) cnt += word_escapes(w, v[u][k]);
-          }
-        }
+        for (int u = 0; u < DCOUNT_GROUPS; ++u)
+          cnt += clean(v[u].x) + clean(v[u].y) + clean(v[u].z) + clean(v[u].w);
+      }
+      // the words outside the clean groups: [wlo, 4 gc0) and [4 gc1, whi)
+      const uint64_t a1 = 4 * gc0 < whi ? 4 * gc0 : whi;
+      const uint64_t b0 = 4 * gc1 > a1 ? 4 * gc1 : a1;
+      const uint64_t na = a1 > wlo ? a1 - wlo : 0, nb = whi > b0 ? whi - b0 : 0;
+      for (uint64_t i = lane; i < na + nb; i += 64) {
+        const uint64_t w = i < na ? wlo + i : b0 + (i - na);
+        cnt += word_escapes(w, packed[w]);
       }
     } else {
       for (uint64_t w = wlo + lane; w < whi; w += 64) cnt += word_escapes(w, packed[w]);
