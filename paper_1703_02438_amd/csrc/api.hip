@@ -456,7 +456,7 @@ struct numarck_plan {
   std::vector<CParams> table;        // sorted by (dtype, encoder class)
   std::vector<uint64_t> chunk0;      // njobs + 1
   std::vector<uint32_t> unit0;       // njobs + 1
-  std::vector<nk::JobGroup> dgroups, egroups, rgroups;
+  std::vector<nk::JobGroup> dgroups, egroups, rgroups, hgroups;
   nk::BatchLaunch bl;
   hipEvent_t uploaded = nullptr;     // the descriptor copy has completed
   hipGraph_t graph = nullptr;
@@ -621,6 +621,18 @@ numarck_status numarck_plan_create(const numarck_job* jobs, uint32_t njobs,
   // jobs stream per run as in the other passes
   for (const JobGroup& dg : pl->dgroups) {
     uint32_t run = dg.job_begin, q = dg.job_begin;
+    // the histogram pass takes the same runs and chains, in the batch's
+    // chunk numbering
+    auto hist_group = [&](uint32_t a, uint32_t b, uint32_t chain) {
+      JobGroup h = dg;
+      h.job_begin = a;
+      h.job_end = b;
+      h.c_begin = pl->chunk0[a];
+      h.c_end = pl->chunk0[b];
+      h.chunk_vec = cvec_of[a];
+      h.chain = chain;
+      pl->hgroups.push_back(h);
+    };
     auto plain_run = [&](uint32_t a, uint32_t b) {
       if (a == b) return;
       JobGroup r = dg;
@@ -631,6 +643,7 @@ numarck_status numarck_plan_create(const numarck_job* jobs, uint32_t njobs,
       r.chunk_vec = cvec_of[a];
       r.chain = 0;
       pl->rgroups.push_back(r);
+      hist_group(a, b, 0);
     };
     while (q < dg.job_end) {
       uint32_t e = q + 1;
@@ -651,6 +664,7 @@ numarck_status numarck_plan_create(const numarck_job* jobs, uint32_t njobs,
       r.c_end = stream_chunks(pl->table[q].n, dg.dtype, r.chunk_vec);
       r.chain = 1;
       pl->rgroups.push_back(r);
+      hist_group(q, e, 1);
       run = q = e;
     }
     plain_run(run, dg.job_end);
@@ -691,6 +705,8 @@ numarck_status numarck_plan_create(const numarck_job* jobs, uint32_t njobs,
   bl.n_egroups = (uint32_t)pl->egroups.size();
   bl.rgroups = pl->rgroups.data();
   bl.n_rgroups = (uint32_t)pl->rgroups.size();
+  bl.hgroups = pl->hgroups.data();
+  bl.n_hgroups = (uint32_t)pl->hgroups.size();
   bl.tune = tn;
   *plan_out = pl;
   return NUMARCK_OK;

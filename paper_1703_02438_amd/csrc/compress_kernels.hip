@@ -497,7 +497,21 @@ __global__ void __launch_bounds__(HIST_TPB) k_hist(S src, Geo g) {
     }
     __syncthreads();
   };
-  for (uint64_t c = g.c_begin + blockIdx.x; c < g.c_end; c += gridDim.x) {
+  // Chunks block-strided over the group.  In a time chain, workgroup b works
+  // on job (b mod T) only, taking its chunks b / T, b / T + G / T, ... (G / T
+  // workgroups per job): consecutive jobs read the snapshot they share at the
+  // same positions at about the same time, and its second read can hit the
+  // Infinity Cache.  Workgroups past (G / T) T have nothing to do.
+  uint64_t c0 = g.c_begin + blockIdx.x, cend = g.c_end, cstep = gridDim.x;
+  if (g.chain) {
+    const uint32_t nj = g.job_end - g.job_begin;
+    const uint32_t per = gridDim.x / nj;
+    const uint32_t j = g.job_begin + blockIdx.x % nj;
+    cend = g.chunk0[j + 1];
+    c0 = blockIdx.x < per * nj ? g.chunk0[j] + blockIdx.x / nj : cend;
+    cstep = per;
+  }
+  for (uint64_t c = c0; c < cend; c += cstep) {
     if (cu.seek(g, c)) {
       if (have) flush();
       have = true;
@@ -1582,6 +1596,7 @@ Tuning default_tuning() { return Tuning{8u, 2u, 1u, 0u, 100u, 0u}; }
 static Geo group_geo(const Geo& base, const JobGroup& jg) {
   Geo g = base;
   g.stream_nt = jg.nt;
+  g.chain = jg.chain;
   if (jg.chunk_vec) g.chunk_vec = jg.chunk_vec;
   g.job_begin = jg.job_begin;
   g.job_end = jg.job_end;
@@ -1602,8 +1617,9 @@ static uint64_t clamp_blocks(uint64_t want, uint64_t cap) {
 // of jobs.
 template <typename S>
 static hipError_t run_chain(S src, const Geo& base, uint32_t njobs, const JobGroup* rg,
-                            uint32_t nrg, const JobGroup* dg, uint32_t ndg, const JobGroup* eg,
-                            uint32_t neg, const Tuning& tn, hipStream_t s) {
+                            uint32_t nrg, const JobGroup* hg, uint32_t nhg, const JobGroup* dg,
+                            uint32_t ndg, const JobGroup* eg, uint32_t neg, const Tuning& tn,
+                            hipStream_t s) {
   const Geometry G = geometry();
   Geo all = base;
   all.job_begin = 0;
@@ -1640,12 +1656,13 @@ static hipError_t run_chain(S src, const Geo& base, uint32_t njobs, const JobGro
     }
   }
   NK_LAUNCH(KK_DERIVE, k_derive<S>, njobs, 64, src, all);
-  for (uint32_t i = 0; i < ndg; ++i) {
-    const Geo g = group_geo(base, dg[i]);
+  for (uint32_t i = 0; i < nhg; ++i) {
+    const Geo g = group_geo(base, hg[i]);
     const uint64_t chunks = g.c_end - g.c_begin;
     if (!chunks) continue;
-    const uint64_t blocks = clamp_blocks(chunks, (uint64_t)G.cus * tn.hist_blocks_per_cu);
-    const bool f32 = dg[i].dtype == NUMARCK_F32;
+    uint64_t blocks = clamp_blocks(chunks, (uint64_t)G.cus * tn.hist_blocks_per_cu);
+    if (g.chain && blocks < g.job_end - g.job_begin) blocks = g.job_end - g.job_begin;
+    const bool f32 = hg[i].dtype == NUMARCK_F32;
     const bool nt = g.stream_nt != 0;
     if (tn.hist_lds) {
       if (f32) {
@@ -1724,7 +1741,7 @@ hipError_t launch_compress(const CParams& P0, const Tuning& tn, hipStream_t s) {
   grp.u_end = P.n_units;
   grp.nt = stream_nt_for(tn.stream_loads, 2 * P.n * (P.dtype == NUMARCK_F32 ? 4 : 8),
                          P.prev == P.curr);
-  return run_chain(OneJob{P}, base, 1, &grp, 1, &grp, 1, &grp, 1, tn, s);
+  return run_chain(OneJob{P}, base, 1, &grp, 1, &grp, 1, &grp, 1, &grp, 1, tn, s);
 }
 
 hipError_t launch_compress_batch(const BatchLaunch& b, hipStream_t s) {
@@ -1732,8 +1749,8 @@ hipError_t launch_compress_batch(const BatchLaunch& b, hipStream_t s) {
   base.chunk0 = b.chunk0_dev;
   base.unit0 = b.unit0_dev;
   base.chunk_vec = b.tune.chunk_vec ? b.tune.chunk_vec : 4096;  // groups carry their own
-  return run_chain(JobTable{b.jobs_dev}, base, b.njobs, b.rgroups, b.n_rgroups, b.dgroups,
-                   b.n_dgroups, b.egroups, b.n_egroups, b.tune, s);
+  return run_chain(JobTable{b.jobs_dev}, base, b.njobs, b.rgroups, b.n_rgroups, b.hgroups,
+                   b.n_hgroups, b.dgroups, b.n_dgroups, b.egroups, b.n_egroups, b.tune, s);
 }
 
 // =====================================================================

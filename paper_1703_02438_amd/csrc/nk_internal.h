@@ -178,6 +178,7 @@ struct Geo {
   uint32_t u_begin, u_end;  // encoder units of this launch
   uint32_t chunk_vec;       // 16-byte vectors per streaming chunk
   uint32_t stream_nt;       // input loads of the streaming passes are non-temporal
+  uint32_t chain;           // the jobs are a time chain (see JobGroup::chain)
 };
 
 // Launch parameters a tuner may change (none changes any output).
@@ -201,9 +202,11 @@ struct JobGroup {
   uint32_t job_begin, job_end;
   uint64_t c_begin, c_end;
   uint32_t u_begin, u_end;
-  // Range pass only: the jobs are a time chain (job i's curr is job i+1's
-  // prev, one n), read as one sweep over the snapshots; c_begin/c_end then
-  // count the chain's own chunks from 0.
+  // The jobs are a time chain (job i's curr is job i+1's prev, one n).  In
+  // a range-pass group it is read as one sweep over the snapshots and
+  // c_begin/c_end count the chain's own chunks from 0; in a histogram group
+  // the chunks keep the batch numbering and each workgroup stays on one job,
+  // consecutive jobs in step.
   uint32_t chain;
 };
 inline int enc_class(uint32_t B) { return B < 8 ? 0 : B == 8 ? 1 : B < 16 ? 2 : 3; }
@@ -283,6 +286,8 @@ struct BatchLaunch {
   uint32_t n_egroups;
   const JobGroup* rgroups;  // range pass: runs of unchained jobs and time chains
   uint32_t n_rgroups;
+  const JobGroup* hgroups;  // histogram pass: the same runs and chains
+  uint32_t n_hgroups;
   Tuning tune;
 };
 hipError_t launch_compress_batch(const BatchLaunch& b, hipStream_t s);
