@@ -663,6 +663,10 @@ numarck_status numarck_plan_create(const numarck_job* jobs, uint32_t njobs,
       r.c_begin = 0;
       r.c_end = stream_chunks(pl->table[q].n, dg.dtype, r.chunk_vec);
       r.chain = 1;
+      // the sweep reads each snapshot once: nothing to keep in the caches
+      r.nt = stream_nt_for(tn.stream_loads,
+                           (uint64_t)(e - q + 1) * pl->table[q].n * (dg.dtype == NUMARCK_F32 ? 4 : 8),
+                           false);
       pl->rgroups.push_back(r);
       hist_group(q, e, 1);
       run = q = e;

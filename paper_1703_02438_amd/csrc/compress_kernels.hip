@@ -435,7 +435,7 @@ __device__ __forceinline__ void hist_count(uint32_t* win, bool valid, double m, 
 // when the block moves to another job (or finishes); otherwise count
 // directly in the global counts (more atomic traffic, no LDS, higher
 // occupancy).  Same counts either way.
-template <typename T, typename S, bool LDSH, bool NT>
+template <typename T, typename S, bool LDSH, int NT>
 __global__ void __launch_bounds__(HIST_TPB) k_hist(S src, Geo g) {
   constexpr int V = Traits<T>::V;
   // the window, then one slot per lane for points outside it (never read):
@@ -546,8 +546,8 @@ __global__ void __launch_bounds__(HIST_TPB) k_hist(S src, Geo g) {
       for (int u = 0; u < HIST_UNROLL; ++u) {
         const uint64_t vi = vb + (uint64_t)u * HIST_TPB;
         if (vi < v1) {
-          load_vec_t<NT>(prev, vi, pv[u]);
-          load_vec_t<NT>(curr, vi, qv[u]);
+          load_vec_t<NT != 0>(prev, vi, pv[u]);
+          load_vec_t<NT == 1>(curr, vi, qv[u]);
         }
       }
       if constexpr (LDSH) {
@@ -1087,7 +1087,7 @@ constexpr int ENC_CTAB = 2048;  // LDS centre table when 2^B <= this
 template <typename T, int PACK>
 constexpr int enc_min_waves = (sizeof(T) == 8 && PACK == 8) ? 5 : 1;
 
-template <typename T, typename LT, int PACK, typename S, bool NT>
+template <typename T, typename LT, int PACK, typename S, int NT>
 __global__ void __launch_bounds__(UNIT_TPB, (enc_min_waves<T, PACK>)) k_encode(S src, Geo g) {
   constexpr int V = Traits<T>::V;
   constexpr int R = ENC_ROUNDS;
@@ -1153,8 +1153,8 @@ __global__ void __launch_bounds__(UNIT_TPB, (enc_min_waves<T, PACK>)) k_encode(S
     for (int r = 0; r < R; ++r) {
       const uint64_t vi = t0 / V + (uint64_t)r * 64 + lane;
       if (vi < nvec) {
-        load_vec_t<NT>(prev, vi, pa[r]);
-        load_vec_t<NT>(curr, vi, qa[r]);
+        load_vec_t<NT != 0>(prev, vi, pa[r]);
+        load_vec_t<NT == 1>(curr, vi, qa[r]);
       } else {
 #pragma unroll
         for (int v = 0; v < V; ++v) {
@@ -1438,8 +1438,8 @@ __global__ void __launch_bounds__(UNIT_TPB, (enc_min_waves<T, PACK>)) k_encode(S
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const uint64_t vi = t0 / V + (uint64_t)r * 64 + lane;
-      load_vec_t<NT>(prev, vi, pa[r]);
-      load_vec_t<NT>(curr, vi, qa[r]);
+      load_vec_t<NT != 0>(prev, vi, pa[r]);
+      load_vec_t<NT == 1>(curr, vi, qa[r]);
     }
   };
   const uint64_t full_tiles = nvec / (WT / V);  // tiles with every vector in range
@@ -1563,7 +1563,7 @@ __device__ void write_header(const CParams& P) {
   } while (0)
 
 // Kernel of an encoder specialisation.
-template <typename T, typename S, bool NT>
+template <typename T, typename S, int NT>
 static void (*encoder_kernel_nt(int cls))(S, Geo) {
   switch (cls) {
     case 0: return k_encode<T, uint8_t, 0, S, NT>;
@@ -1573,14 +1573,16 @@ static void (*encoder_kernel_nt(int cls))(S, Geo) {
   }
 }
 template <typename T, typename S>
-static void (*encoder_kernel(int cls, bool nt))(S, Geo) {
-  return nt ? encoder_kernel_nt<T, S, true>(cls) : encoder_kernel_nt<T, S, false>(cls);
+static void (*encoder_kernel(int cls, uint32_t nt))(S, Geo) {
+  if constexpr (std::is_same<S, JobTable>::value)
+    if (nt == 2) return encoder_kernel_nt<T, S, 2>(cls);
+  return nt == 1 ? encoder_kernel_nt<T, S, 1>(cls) : encoder_kernel_nt<T, S, 0>(cls);
 }
 
 template <typename S>
 static int encoder_occupancy_t(int dtype, int cls) {
-  void (*k)(S, Geo) = dtype == NUMARCK_F32 ? encoder_kernel<float, S>(cls, false)
-                                           : encoder_kernel<double, S>(cls, false);
+  void (*k)(S, Geo) = dtype == NUMARCK_F32 ? encoder_kernel<float, S>(cls, 0)
+                                           : encoder_kernel<double, S>(cls, 0);
   int occ = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k, UNIT_TPB, 0) != hipSuccess || occ < 1)
     occ = 1;
@@ -1637,7 +1639,7 @@ static hipError_t run_chain(S src, const Geo& base, uint32_t njobs, const JobGro
     const bool f32 = rg[i].dtype == NUMARCK_F32;
     if (rg[i].chain) {
       if constexpr (std::is_same<S, JobTable>::value) {
-        if (g.stream_nt) {
+        if (g.stream_nt == 1) {
           if (f32) NK_LAUNCH(KK_RANGE, (k_range_chain<float, true>), blocks, RNG_TPB, src, g);
           else NK_LAUNCH(KK_RANGE, (k_range_chain<double, true>), blocks, RNG_TPB, src, g);
         } else {
@@ -1647,7 +1649,7 @@ static hipError_t run_chain(S src, const Geo& base, uint32_t njobs, const JobGro
       } else {
         return hipErrorInvalidValue;  // chains exist in batches only
       }
-    } else if (g.stream_nt) {
+    } else if (g.stream_nt == 1) {
       if (f32) NK_LAUNCH(KK_RANGE, (k_range<float, S, true>), blocks, RNG_TPB, src, g);
       else NK_LAUNCH(KK_RANGE, (k_range<double, S, true>), blocks, RNG_TPB, src, g);
     } else {
@@ -1663,18 +1665,20 @@ static hipError_t run_chain(S src, const Geo& base, uint32_t njobs, const JobGro
     uint64_t blocks = clamp_blocks(chunks, (uint64_t)G.cus * tn.hist_blocks_per_cu);
     if (g.chain && blocks < g.job_end - g.job_begin) blocks = g.job_end - g.job_begin;
     const bool f32 = hg[i].dtype == NUMARCK_F32;
-    const bool nt = g.stream_nt != 0;
+    const uint32_t nt = g.stream_nt;
     if (tn.hist_lds) {
+      // shared snapshots (mode 2) are read cached here: the histogram's
+      // workgroups walk consecutive pairs in step and hit both reads
       if (f32) {
-        if (nt) NK_LAUNCH(KK_HIST, (k_hist<float, S, true, true>), blocks, HIST_TPB, src, g);
-        else NK_LAUNCH(KK_HIST, (k_hist<float, S, true, false>), blocks, HIST_TPB, src, g);
+        if (nt == 1) NK_LAUNCH(KK_HIST, (k_hist<float, S, true, 1>), blocks, HIST_TPB, src, g);
+        else NK_LAUNCH(KK_HIST, (k_hist<float, S, true, 0>), blocks, HIST_TPB, src, g);
       } else {
-        if (nt) NK_LAUNCH(KK_HIST, (k_hist<double, S, true, true>), blocks, HIST_TPB, src, g);
-        else NK_LAUNCH(KK_HIST, (k_hist<double, S, true, false>), blocks, HIST_TPB, src, g);
+        if (nt == 1) NK_LAUNCH(KK_HIST, (k_hist<double, S, true, 1>), blocks, HIST_TPB, src, g);
+        else NK_LAUNCH(KK_HIST, (k_hist<double, S, true, 0>), blocks, HIST_TPB, src, g);
       }
     } else {  // global counts: the chosen few; streamed inputs are cached
-      if (f32) NK_LAUNCH(KK_HIST, (k_hist<float, S, false, false>), blocks, HIST_TPB, src, g);
-      else NK_LAUNCH(KK_HIST, (k_hist<double, S, false, false>), blocks, HIST_TPB, src, g);
+      if (f32) NK_LAUNCH(KK_HIST, (k_hist<float, S, false, 0>), blocks, HIST_TPB, src, g);
+      else NK_LAUNCH(KK_HIST, (k_hist<double, S, false, 0>), blocks, HIST_TPB, src, g);
     }
   }
   NK_LAUNCH(KK_HCLEAR, k_hclear<S>, dim3((unsigned)aux, njobs), 256, src, all);
@@ -1695,8 +1699,8 @@ static hipError_t run_chain(S src, const Geo& base, uint32_t njobs, const JobGro
     const uint32_t blocks = (g.u_end - g.u_begin) / 4;
     if (!blocks) continue;
     void (*k)(S, Geo) = eg[i].dtype == NUMARCK_F32
-                            ? encoder_kernel<float, S>(eg[i].cls, g.stream_nt != 0)
-                            : encoder_kernel<double, S>(eg[i].cls, g.stream_nt != 0);
+                            ? encoder_kernel<float, S>(eg[i].cls, g.stream_nt)
+                            : encoder_kernel<double, S>(eg[i].cls, g.stream_nt);
     NK_LAUNCH(KK_ENCODE, k, blocks, UNIT_TPB, src, g);
   }
   NK_LAUNCH(KK_USCAN, k_uscan<S>, njobs, USCAN_TPB, src, all);
@@ -1741,6 +1745,7 @@ hipError_t launch_compress(const CParams& P0, const Tuning& tn, hipStream_t s) {
   grp.u_end = P.n_units;
   grp.nt = stream_nt_for(tn.stream_loads, 2 * P.n * (P.dtype == NUMARCK_F32 ? 4 : 8),
                          P.prev == P.curr);
+  if (grp.nt == 2) grp.nt = 0;  // one job: its two inputs are one snapshot
   return run_chain(OneJob{P}, base, 1, &grp, 1, &grp, 1, &grp, 1, &grp, 1, tn, s);
 }
 

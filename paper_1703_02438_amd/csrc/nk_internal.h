@@ -177,7 +177,7 @@ struct Geo {
   uint64_t c_begin, c_end;  // streaming chunks of this launch
   uint32_t u_begin, u_end;  // encoder units of this launch
   uint32_t chunk_vec;       // 16-byte vectors per streaming chunk
-  uint32_t stream_nt;       // input loads of the streaming passes are non-temporal
+  uint32_t stream_nt;       // load hints of the streaming passes (stream_nt_for)
   uint32_t chain;           // the jobs are a time chain (see JobGroup::chain)
 };
 
@@ -197,7 +197,7 @@ Tuning default_tuning();
 struct JobGroup {
   int dtype;
   int cls;
-  uint32_t nt;         // streaming loads non-temporal for this group
+  uint32_t nt;         // load hints of the streaming passes (stream_nt_for)
   uint32_t chunk_vec;  // 16-byte vectors per streaming chunk of this group
   uint32_t job_begin, job_end;
   uint64_t c_begin, c_end;
@@ -214,11 +214,16 @@ inline int enc_class(uint32_t B) { return B < 8 ? 0 : B == 8 ? 1 : B < 16 ? 2 : 
 // Input bytes per pass above which a streaming pass gains nothing from
 // caching its inputs (well past the 256 MB Infinity Cache).
 constexpr uint64_t NT_STREAM_BYTES = 512ull << 20;
-// Non-temporal input loads for a group streaming `bytes` per pass?
+// Load hints of a group streaming `bytes` per pass: 0 both inputs cached,
+// 1 both non-temporal, 2 prev non-temporal and curr cached.  The last is for
+// batches whose jobs share snapshots (time-ordered pairs): a pair's prev was
+// the previous pair's curr and is read for the last time, while its curr is
+// read again by the next pair.
 inline uint32_t stream_nt_for(uint32_t mode, uint64_t bytes, bool shared_inputs) {
   if (mode == 1) return 1u;
   if (mode == 2) return 0u;
-  return (bytes >= NT_STREAM_BYTES && !shared_inputs) ? 1u : 0u;
+  if (bytes < NT_STREAM_BYTES) return 0u;
+  return shared_inputs ? 2u : 1u;
 }
 
 // Pairs of one time chain in the range pass, at most (longer chains are cut).
