@@ -103,8 +103,7 @@ Geometry geometry() {
 // ------------------------------------------------------------- event timing
 static const char* kKindNames[KK_COUNT] = {
     "init", "range", "derive", "hist", "hash_clear", "hash_insert", "select", "tail_rank",
-    "encode", "unit_scan", "gather", "dec_init", "dec_prefix", "dec_count",
-    "dec_scan", "decode", "export"};
+    "encode", "unit_scan", "gather", "dec_count", "dec_scan", "decode", "export"};
 static bool g_timing = false;
 struct EvPair {
   hipEvent_t a, b;

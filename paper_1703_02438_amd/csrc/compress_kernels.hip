@@ -423,11 +423,7 @@ __device__ __forceinline__ void hist_count(uint32_t* win, bool valid, double m, 
                                            double wlen_d, const TailSink& ts) {
   const double w = m - wbase_d;  // exact: both are integers below 2^51
   const bool inwin = valid && w >= 0.0 && w < wlen_d;
-#if NK_HIST_HYBRID
-  lds_count(win, inwin, inwin ? (unsigned)(int)w : 0u);
-#else
   if (inwin) atomicAdd(&win[(int)w], 1u);
-#endif
   tail_append(valid && !inwin, m, ts);
 }
 

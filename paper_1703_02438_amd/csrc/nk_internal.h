@@ -33,9 +33,6 @@ constexpr int MAX_SEL = 65535;            // k for B = 16
 #ifndef NK_DEC_DIRECT
 #define NK_DEC_DIRECT 0      // decoder reads index bits from global, not via LDS
 #endif
-#ifndef NK_HIST_HYBRID
-#define NK_HIST_HYBRID 0     // aggregate the wave's most common bin
-#endif
 #ifndef NK_HIST_REVERSE
 #define NK_HIST_REVERSE 0    // histogram sweep from the end of the arrays
 #endif
@@ -269,8 +266,8 @@ inline uint32_t range_units(uint64_t tiles, int resident) {
 // Kernel kinds for the optional event timing.
 enum KernelKind {
   KK_INIT = 0, KK_RANGE, KK_DERIVE, KK_HIST, KK_HCLEAR, KK_HINSERT, KK_SELECT,
-  KK_TAILRANK, KK_ENCODE, KK_USCAN, KK_GATHER, KK_DINIT, KK_DPREFIX, KK_DCOUNT,
-  KK_DSCAN, KK_DECODE, KK_EXPORT, KK_COUNT
+  KK_TAILRANK, KK_ENCODE, KK_USCAN, KK_GATHER, KK_DCOUNT, KK_DSCAN, KK_DECODE, KK_EXPORT,
+  KK_COUNT
 };
 void timing_begin(KernelKind k, hipStream_t s);
 void timing_end(KernelKind k, hipStream_t s);
