@@ -82,6 +82,10 @@ class Oracle:
                                      ctypes.c_uint32, ctypes.c_uint64, _VP, _VP, _VP, _VP, _VP,
                                      _VP, _VP, ctypes.POINTER(_Info)]
         lib.orc_compress.restype = ctypes.c_int
+        lib.orc_choose_B.argtypes = [_VP, _VP, ctypes.c_uint64, ctypes.c_int, ctypes.c_double,
+                                     ctypes.c_uint32, ctypes.c_uint32, _VP,
+                                     ctypes.POINTER(ctypes.c_uint32)]
+        lib.orc_choose_B.restype = ctypes.c_int
         lib.orc_decompress.argtypes = [ctypes.POINTER(_Info), _VP, _VP, _VP, _VP, _VP,
                                        ctypes.POINTER(ctypes.c_uint32)]
         lib.orc_decompress.restype = ctypes.c_int
@@ -164,6 +168,19 @@ class Oracle:
             recon=None if rec is None else rec[:n].copy(), index=index[:n].copy(),
             sel_ids=sel[: h["k_used"]].copy(),
         )
+
+    def choose_B(self, prev: np.ndarray, curr: np.ndarray, E: float, b_lo: int = 1,
+                 b_hi: int = 16):
+        """(B, bits): the B of eqs. (5)-(6) and the estimated size in bits of
+        every B (index B; 0 outside [b_lo, b_hi])."""
+        prev, curr, dt = _pair(prev, curr)
+        bits = np.zeros(17, np.uint64)
+        B = ctypes.c_uint32(0)
+        st = self.lib.orc_choose_B(_p(prev), _p(curr), prev.size, dt, E, b_lo, b_hi, _p(bits),
+                                   ctypes.byref(B))
+        if st != 0:
+            raise ValueError(f"oracle choose_B failed with status {st}")
+        return int(B.value), [int(x) for x in bits]
 
     def decompress(self, res: "OracleResult", prev: np.ndarray):
         prev = np.ascontiguousarray(prev)

@@ -206,6 +206,66 @@ int64_t orc_topk(const int64_t* ids, const uint32_t* counts, int64_t nbins, uint
   return take;
 }
 
+/* ------------------------------------------------ choice of B, eqs. (5)-(6) */
+
+/* Larger count first. */
+static int cmp_count_desc(const void* a, const void* b) {
+  uint32_t x = *(const uint32_t*)a, y = *(const uint32_t*)b;
+  return (x < y) - (x > y);
+}
+
+/* The histogram does not depend on B, so one histogram serves every B: with
+ * the counts sorted in decreasing order, the points the 2^B - 1 selected bins
+ * hold are the sum of the first 2^B - 1 counts (all of them when there are
+ * fewer bins), and every other point -- the invalid ones included -- is
+ * counted as incompressible, eq. (5).  Eq. (6) in bits: 8 * 2^B L for the
+ * centre table, n B for the index table, 8 L per incompressible point. */
+int orc_choose_B(const void* prev, const void* curr, uint64_t n, int dtype, double E,
+                 uint32_t b_lo, uint32_t b_hi, uint64_t* bits, uint32_t* B_out) {
+  if (b_lo < 1 || b_hi > 16 || b_lo > b_hi) return ORC_EBITS;
+  int st = check_args(dtype, E, b_lo);
+  if (st != ORC_OK) return st;
+  if (n >= ((uint64_t)1 << 32)) return ORC_EINVAL;
+  if (!bits || !B_out || (n && (!prev || !curr))) return ORC_EINVAL;
+  const uint64_t L = elem_size(dtype);
+  const uint64_t nn = n ? n : 1;
+  double* d = (double*)malloc(nn * sizeof(double));
+  uint8_t* valid = (uint8_t*)malloc(nn);
+  int64_t* m = (int64_t*)malloc(nn * sizeof(int64_t));
+  int64_t* hid = (int64_t*)malloc(nn * sizeof(int64_t));
+  uint32_t* hcnt = (uint32_t*)malloc(nn * sizeof(uint32_t));
+  if (!d || !valid || !m || !hid || !hcnt) {
+    free(d); free(valid); free(m); free(hid); free(hcnt);
+    return ORC_ENOMEM;
+  }
+  orc_ratio(prev, curr, n, dtype, E, d, valid);
+  double lo = 0.0, hi = 0.0;
+  const uint64_t n_valid = orc_range(d, valid, n, &lo, &hi);
+  int64_t nbins = 0;
+  if (n_valid > 0) {
+    orc_bin_ids(d, valid, n, lo, E, m);
+    nbins = orc_histogram(m, valid, n, hid, hcnt);
+  }
+  qsort(hcnt, (size_t)nbins, sizeof(uint32_t), cmp_count_desc);
+  for (uint32_t B = 0; B <= 16; B++) bits[B] = 0;
+  uint64_t best = 0;
+  uint32_t bestB = 0;
+  for (uint32_t B = b_lo; B <= b_hi; B++) {
+    const int64_t k = ((int64_t)1 << B) - 1;
+    uint64_t covered = 0;
+    for (int64_t i = 0; i < nbins && i < k; i++) covered += hcnt[i];
+    const uint64_t incompressible = n - covered;
+    bits[B] = 8 * ((uint64_t)1 << B) * L + n * (uint64_t)B + 8 * L * incompressible;
+    if (bestB == 0 || bits[B] < best) {
+      best = bits[B];
+      bestB = B;
+    }
+  }
+  *B_out = bestB;
+  free(d); free(valid); free(m); free(hid); free(hcnt);
+  return ORC_OK;
+}
+
 /* ------------------------------------------------ bit packing (Sec. IV-C) */
 
 static void put_index(uint32_t* packed, uint64_t j, uint32_t B, uint32_t idx) {

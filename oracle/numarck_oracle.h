@@ -71,6 +71,15 @@ int64_t orc_histogram(const int64_t* m, const uint8_t* valid, uint64_t n, int64_
 int64_t orc_topk(const int64_t* ids, const uint32_t* counts, int64_t nbins, uint32_t k,
                  int64_t* sel, uint32_t* tau);
 
+/* Selection of B (Sec. IV-B-2, eqs. 5-6): for every B in [b_lo, b_hi] the
+ * estimated compressed size file_size(B) = 2^B L + n B / 8 + n alpha(B) L,
+ * where alpha(B) n = n - (sum of the 2^B - 1 largest bin counts), in bits
+ * (8 file_size, an exact integer): bits[B] for b_lo <= B <= b_hi (bits has 17
+ * entries, index B).  *B_out gets the B of the smallest size, the smallest
+ * such B on equal sizes.  1 <= b_lo <= b_hi <= 16. */
+int orc_choose_B(const void* prev, const void* curr, uint64_t n, int dtype, double E,
+                 uint32_t b_lo, uint32_t b_hi, uint64_t* bits, uint32_t* B_out);
+
 /* The whole compression of one snapshot pair.
  *   packed         : ceil(n*B/32) u32 words
  *   centers        : 2^B values of the snapshot type

@@ -475,10 +475,55 @@ def pin_dp_bound(o):
     assert opt == 22 and int((res.index != 3).sum()) == 22
 
 
+def pin_choose_B_centred(o):
+    """Sec. IV-B-2, eqs. (5)-(6), on bin-centred data with counts
+    {0:4000, 1:7000, 2:5000, 3:5000, 4:5000, 6:1000} (n = 27,000, float64):
+    the 2^B - 1 fullest bins hold 7000 (B = 1), 17,000 (B = 2) and all points
+    (B >= 3), so in bits 8 file_size(B) = 64 * 2^B + 27,000 B + 64 (27,000 - held):
+    1,307,128, 694,256, 81,512, 109,024, ... and B = 3 is chosen.  Every point
+    of a selected bin is compressible here, so the estimated incompressible
+    count of every B equals the n_inc of the compression with that B."""
+    counts = {0: 4000, 1: 7000, 2: 5000, 3: 5000, 4: 5000, 6: 1000}
+    p, q, _, E = centred_case(counts)
+    n = p.size
+    B, bits = o.choose_B(p, q, E, 1, 16)
+    assert B == 3
+    assert bits[1:5] == [1307128, 694256, 81512, 109024]
+    for b in range(1, 17):
+        held = min(sum(sorted(counts.values(), reverse=True)[: (1 << b) - 1]), n)
+        assert bits[b] == 64 * (1 << b) + n * b + 64 * (n - held), b
+    for b in (1, 2, 3, 5):
+        est_inc = (bits[b] - 64 * (1 << b) - n * b) // 64
+        assert est_inc == o.compress(p, q, E, b).info["n_inc"], b
+    # a narrower range: the smallest estimate within it
+    B2, bits2 = o.choose_B(p, q, E, 4, 6)
+    assert B2 == 4 and bits2[4] == 109024 and bits2[3] == 0 and bits2[7] == 0
+
+
+def pin_choose_B_invalid(o):
+    """No valid point: alpha = 1 for every B, so the size 2^B L + n B / 8 + n L
+    grows with B and the lower end of the range is chosen; float32 L = 4."""
+    p = np.zeros(1000, np.float32)
+    q = np.linspace(-1, 1, 1000).astype(np.float32)
+    B, bits = o.choose_B(p, q, 1e-3, 5, 9)
+    assert B == 5
+    assert bits[5:10] == [8 * (1 << b) * 4 + 1000 * b + 32 * 1000 for b in range(5, 10)]
+
+
+def pin_choose_B_ties_lowest(o):
+    """Equal estimates choose the smaller B.  Float64 counts {0:124, 1:2, 2:2}
+    (n = 128): B = 1 holds 124 points, 64 * 2 + 128 + 64 * 4 = 512 bits; B = 2
+    holds all, 64 * 4 + 256 = 512 bits; B = 3 needs 64 * 8 + 384 = 896.  B = 1
+    is chosen."""
+    p, q, _, E = centred_case({0: 124, 1: 2, 2: 2})
+    B, bits = o.choose_B(p, q, E, 1, 3)
+    assert (B, bits[1], bits[2], bits[3]) == (1, 512, 512, 896)
+
+
 ALL_PINS = [
     pin_ratio_exact, pin_validity, pin_range_minmax, pin_bins_exact, pin_histogram,
     pin_topk_brute, pin_centred_literal, pin_centred_small_k, pin_all_equal,
     pin_error_bound_exact, pin_escapes_bitexact, pin_packing_bitstring, pin_block_offsets,
     pin_fig2_layout, pin_cmip_cr, pin_roundtrip, pin_decode_flags, pin_empty_and_tiny,
-    pin_dp_bound,
+    pin_dp_bound, pin_choose_B_centred, pin_choose_B_invalid, pin_choose_B_ties_lowest,
 ]

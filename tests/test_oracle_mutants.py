@@ -46,6 +46,12 @@ MUTANTS = [
      "store_rounded(out, dtype, oj, p * (1.0 - c));"),
     ("range_rank_from_zero", "uint64_t rank = (uint64_t)block_inc_off[blk];", "uint64_t rank = 0;"),
     ("bad_index_unflagged", "if (code >= info->k_used) *flags |= ORC_FLAG_BAD_INDEX;", "if (0) {}"),
+    ("chooseB_k_is_2B", "const int64_t k = ((int64_t)1 << B) - 1;", "const int64_t k = (int64_t)1 << B;"),
+    ("chooseB_invalid_ignored", "const uint64_t incompressible = n - covered;",
+     "const uint64_t incompressible = n_valid - covered;"),
+    ("chooseB_index_bytes", "+ n * (uint64_t)B +", "+ n * (uint64_t)B / 8 +"),
+    ("chooseB_ties_to_larger", "if (bestB == 0 || bits[B] < best) {", "if (bestB == 0 || bits[B] <= best) {"),
+    ("chooseB_counts_ascending", "return (x < y) - (x > y);", "return (x > y) - (x < y);"),
 ]
 
 
