@@ -144,6 +144,28 @@ numarck_status numarck_compress(const void* prev, const void* curr, uint64_t n,
                                 uint64_t block_bytes, const numarck_out* out, void* ws,
                                 size_t ws_bytes, void* stream);
 
+/* ---- compression with B chosen from the histogram (Sec. IV-B-2, eqs. 5-6) ----
+ * As numarck_compress, with the index width chosen in [B_min, B_max]
+ * (1 <= B_min <= B_max <= 16): for each B the estimated size
+ *   file_size(B) = 2^B L + n B / 8 + n alpha(B) L,
+ * alpha(B) n being the points outside the 2^B - 1 fullest bins (invalid points
+ * included), is computed from the histogram, which does not depend on B; the
+ * smallest size wins (the smaller B on equal sizes) and the compression runs
+ * with that B.  The estimate ignores the error-bound check, so the actual
+ * n_inc can be larger.  Exact while the out-of-window bins fit the workspace's
+ * tail capacity (otherwise the header reports NUMARCK_FLAG_TAIL_OVERFLOW).
+ * out.packed, out.centers and out.block_inc_off must be sized for B_max.
+ * The call waits once on the stream (the chosen B sizes the passes after
+ * top-k): it returns with the histogram done and the rest queued.
+ * B_out    : host; the chosen B.
+ * est_bits : NULL, or 17 host uint64: 8 * file_size(B) at index B for
+ *            B_min <= B <= B_max, 0 elsewhere. */
+numarck_status numarck_compress_auto(const void* prev, const void* curr, uint64_t n,
+                                     numarck_dtype dtype, double E, uint32_t B_min,
+                                     uint32_t B_max, uint64_t block_bytes,
+                                     const numarck_out* out, void* ws, size_t ws_bytes,
+                                     void* stream, uint32_t* B_out, uint64_t* est_bits);
+
 /* ---- full decompression (eq. 4, Sec. III-E) ----
  * hdr   : host copy of the header numarck_compress wrote
  * prev  : n values, the snapshot the data was compressed against

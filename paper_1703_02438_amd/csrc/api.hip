@@ -331,6 +331,46 @@ numarck_status numarck_compress(const void* prev, const void* curr, uint64_t n,
                                 nullptr, stream);
 }
 
+numarck_status numarck_compress_auto(const void* prev, const void* curr, uint64_t n,
+                                     numarck_dtype dtype, double E, uint32_t B_min,
+                                     uint32_t B_max, uint64_t block_bytes,
+                                     const numarck_out* out, void* ws, size_t ws_bytes,
+                                     void* stream, uint32_t* B_out, uint64_t* est_bits) {
+  if (!B_out) return NUMARCK_EINVAL;
+  if (B_min < 1 || B_max > 16 || B_min > B_max) return NUMARCK_EBITS;
+  numarck_status st = check_job(prev, curr, n, dtype, E, B_max, block_bytes, out);
+  if (st != NUMARCK_OK) return st;
+  if (!ws) return NUMARCK_EINVAL;
+  if (((uintptr_t)ws & 255u) != 0) return NUMARCK_EALIGN;
+  const Tuning tn = recorded_tuning((int)dtype, n);
+  Layout L;
+  if (!fit_layout(n, elem_bytes_of(dtype), ws_bytes, &L)) return NUMARCK_ECAPACITY;
+  char* base = static_cast<char*>(ws);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  // the passes before top-k do not depend on B
+  const CParams P1 = make_params(prev, curr, n, dtype, E, B_max, block_bytes, out, base, L);
+  hipError_t e = launch_compress_phase(P1, tn, s, 1);
+  if (e == hipSuccess) e = launch_autob(P1, B_min, B_max, s);
+  struct {
+    unsigned long long bits[17];
+    unsigned int B;
+  } got{};
+  Ctl* c = P1.ctl;
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(got.bits, c->est_bits, sizeof(got.bits), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(&got.B, &c->auto_B, sizeof(got.B), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e);
+  if (got.B < B_min || got.B > B_max) return hip_fail(hipErrorUnknown);
+  *B_out = got.B;
+  if (est_bits)
+    for (int b = 0; b <= 16; ++b) est_bits[b] = got.bits[b];
+  const CParams P2 = make_params(prev, curr, n, dtype, E, got.B, block_bytes, out, base, L);
+  e = launch_compress_phase(P2, tn, s, 2);
+  return e == hipSuccess ? NUMARCK_OK : hip_fail(e);
+}
+
 numarck_status numarck_autotune(const void* prev, const void* curr, uint64_t n,
                                 numarck_dtype dtype, double E, uint32_t B, uint64_t block_bytes,
                                 const numarck_out* out, void* ws, size_t ws_bytes, uint32_t reps,

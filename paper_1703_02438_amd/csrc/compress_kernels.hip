@@ -872,6 +872,35 @@ __device__ void sel_threshold(SelShared& S, unsigned long long mx, unsigned long
   *cut_out = r >= ties ? (long long)tmax : sel_rth_tie(S, tau, r, tmin, tmax, visit);
 }
 
+// The window counts to LDS (16-byte loads, all in flight at once), with the
+// number of nonzero bins and the largest count; the buffer holds WIN counts,
+// zero past win_len.  The whole workgroup calls it.
+__device__ void sel_load_window(const CParams& P, SelShared& S, unsigned win_len,
+                                unsigned long long& nzw, unsigned long long& mxw) {
+  constexpr int G4 = WIN / 4 / SEL_TPB;
+  const int tid = threadIdx.x;
+  unsigned long long unused0 = ~0ull, unused1 = 0;
+  nzw = 0;
+  mxw = 0;
+  nk_u32x4 x[G4];
+#pragma unroll
+  for (int i = 0; i < G4; ++i)
+    x[i] = gload(reinterpret_cast<const nk_u32x4*>(P.gwin) + (tid + i * SEL_TPB));
+#pragma unroll
+  for (int i = 0; i < G4; ++i) {
+    const unsigned w0 = 4u * (unsigned)(tid + i * SEL_TPB);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const uint32_t cn = w0 + e < win_len ? x[i][e] : 0u;
+      x[i][e] = cn;
+      nzw += cn ? 1 : 0;
+      mxw = cn > mxw ? cn : mxw;
+    }
+    reinterpret_cast<nk_u32x4*>(S.win)[tid + i * SEL_TPB] = x[i];
+  }
+  sel_reduce4(nzw, unused1, unused0, mxw, S);  // also orders the LDS writes
+}
+
 template <typename T, typename SRC>
 __global__ void __launch_bounds__(SEL_TPB) k_select(SRC src, Geo g) {
   const CParams& P = src.job(g.job_begin + blockIdx.x);
@@ -896,29 +925,8 @@ __global__ void __launch_bounds__(SEL_TPB) k_select(SRC src, Geo g) {
   const unsigned long long tail_max = has_tail ? c->tail_max : 0ull;
   const double lo = empty ? 0.0 : c->lo;
   if (tid == 0) S.tail_pos = 0;
-  // window counts to LDS (16-byte loads, all in flight at once), with their
-  // statistics; the buffer holds WIN counts, zero past win_len
-  unsigned long long nzw = 0, mxw = 0, unused0 = ~0ull, unused1 = 0;
-  {
-    constexpr int G4 = WIN / 4 / SEL_TPB;
-    nk_u32x4 x[G4];
-#pragma unroll
-    for (int i = 0; i < G4; ++i)
-      x[i] = gload(reinterpret_cast<const nk_u32x4*>(P.gwin) + (tid + i * SEL_TPB));
-#pragma unroll
-    for (int i = 0; i < G4; ++i) {
-      const unsigned w0 = 4u * (unsigned)(tid + i * SEL_TPB);
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const uint32_t cn = w0 + e < win_len ? x[i][e] : 0u;
-        x[i][e] = cn;
-        nzw += cn ? 1 : 0;
-        mxw = cn > mxw ? cn : mxw;
-      }
-      reinterpret_cast<nk_u32x4*>(S.win)[tid + i * SEL_TPB] = x[i];
-    }
-  }
-  sel_reduce4(nzw, unused1, unused0, mxw, S);  // also orders the LDS writes
+  unsigned long long nzw = 0, mxw = 0;
+  sel_load_window(P, S, win_len, nzw, mxw);
   const unsigned long long nz = nzw + tail_bins;
 
   auto visit_win = [&](auto f) { sel_visit(P, S, wbase, win_len, false, 0ull, f); };
@@ -1022,6 +1030,77 @@ __global__ void __launch_bounds__(SEL_TPB) k_select(SRC src, Geo g) {
     c->k_used = (unsigned)(nz < k ? nz : k);
     c->nsel_tail = (unsigned)sel_tail;
     c->nsel_tail_below = (unsigned)sel_below;
+  }
+}
+
+// =====================================================================
+// k_autob: choice of B from the histogram (Sec. IV-B-2, eqs. 5-6)
+// =====================================================================
+// For every B in [b_lo, b_hi]: the points held by the 2^B - 1 fullest bins
+// (all valid points when there are no more nonzero bins than that; otherwise
+// the counts above the (2^B - 1)-th largest count tau, plus tau for each of
+// the remaining places), and the estimated size 2^B L + n B / 8 + n alpha L
+// in bits, alpha n being the points not held.  The smallest size wins, the
+// smaller B on equal sizes.  Exact while the tail fits its capacity.
+template <typename SRC>
+__global__ void __launch_bounds__(SEL_TPB) k_autob(SRC src, Geo g, uint32_t b_lo, uint32_t b_hi) {
+  const CParams& P = src.job(g.job_begin + blockIdx.x);
+  __shared__ SelShared S;
+  Ctl* c = P.ctl;
+  const int tid = threadIdx.x;
+  const bool empty = c->empty != 0;
+  const long long wbase = empty ? 0 : c->wbase;
+  const unsigned win_len = empty ? 0u : c->win_len;
+  const bool has_tail = !empty && c->tail_used > 0;
+  const unsigned long long H = has_tail ? c->H : 0ull;
+  const unsigned long long tail_bins = has_tail ? c->tail_bins : 0ull;
+  const unsigned long long tail_max = has_tail ? c->tail_max : 0ull;
+  const unsigned long long n = P.n;
+  const unsigned long long n_valid = empty ? 0ull : c->n_valid;
+  const unsigned long long L = P.dtype == NUMARCK_F32 ? 4ull : 8ull;
+  unsigned long long nzw, mxw;
+  sel_load_window(P, S, win_len, nzw, mxw);
+  const unsigned long long nz = nzw + tail_bins;
+  auto visit_win = [&](auto f) { sel_visit(P, S, wbase, win_len, false, 0ull, f); };
+  auto visit_all = [&](auto f) { sel_visit(P, S, wbase, win_len, has_tail, H, f); };
+
+  unsigned long long best = 0;
+  uint32_t best_B = 0;
+  for (uint32_t B = b_lo; B <= b_hi; ++B) {
+    const unsigned long long k = (1ull << B) - 1ull;
+    unsigned long long held = n_valid;
+    if (nz > k) {
+      // tau from the window alone when no tail bin reaches its k-th count
+      bool win_only = false;
+      unsigned tau = 0;
+      if (nzw >= k) {
+        tau = sel_kth_count(S, mxw, k, visit_win);
+        win_only = tail_max < tau;
+      }
+      if (!win_only) tau = sel_kth_count(S, mxw > tail_max ? mxw : tail_max, k, visit_all);
+      unsigned long long sum_gt = 0, n_gt = 0, u0 = ~0ull, u1 = 0;
+      auto above = [&](long long, uint32_t cn) {
+        if (cn > tau) {
+          sum_gt += cn;
+          n_gt += 1;
+        }
+      };
+      if (win_only) visit_win(above); else visit_all(above);
+      sel_reduce4(sum_gt, n_gt, u0, u1, S);
+      held = sum_gt + (k - n_gt) * (unsigned long long)tau;
+    }
+    const unsigned long long bits =
+        8ull * (1ull << B) * L + n * (unsigned long long)B + 8ull * L * (n - held);
+    if (tid == 0) c->est_bits[B] = bits;
+    if (best_B == 0 || bits < best) {
+      best = bits;
+      best_B = B;
+    }
+  }
+  if (tid == 0) {
+    for (uint32_t B = 0; B <= 16; ++B)
+      if (B < b_lo || B > b_hi) c->est_bits[B] = 0ull;
+    c->auto_B = best_B;
   }
 }
 
@@ -1613,11 +1692,13 @@ static uint64_t clamp_blocks(uint64_t want, uint64_t cap) {
 // The compression chain over all jobs of `src`: one launch per pass and per
 // element type (per index-width class for the encoder), whatever the number
 // of jobs.
+// phases: 1 = the passes before top-k (they do not depend on B), 2 = top-k
+// and after.
 template <typename S>
 static hipError_t run_chain(S src, const Geo& base, uint32_t njobs, const JobGroup* rg,
                             uint32_t nrg, const JobGroup* hg, uint32_t nhg, const JobGroup* dg,
                             uint32_t ndg, const JobGroup* eg, uint32_t neg, const Tuning& tn,
-                            hipStream_t s) {
+                            hipStream_t s, unsigned phases = 3) {
   const Geometry G = geometry();
   Geo all = base;
   all.job_begin = 0;
@@ -1626,6 +1707,7 @@ static hipError_t run_chain(S src, const Geo& base, uint32_t njobs, const JobGro
                                   : clamp_blocks((uint64_t)G.cus * 2 / njobs, 64) < 8
                                         ? 8
                                         : clamp_blocks((uint64_t)G.cus * 2 / njobs, 64);
+  if (phases & 1) {
   NK_LAUNCH(KK_INIT, k_init<S>, njobs, 256, src, all);
   for (uint32_t i = 0; i < nrg; ++i) {
     const Geo g = group_geo(base, rg[i]);
@@ -1679,6 +1761,8 @@ static hipError_t run_chain(S src, const Geo& base, uint32_t njobs, const JobGro
   }
   NK_LAUNCH(KK_HCLEAR, k_hclear<S>, dim3((unsigned)aux, njobs), 256, src, all);
   NK_LAUNCH(KK_HINSERT, k_hinsert<S>, dim3((unsigned)aux, njobs), 256, src, all);
+  }
+  if (!(phases & 2)) return hipSuccess;
   for (uint32_t i = 0; i < ndg; ++i) {
     const Geo g = group_geo(base, dg[i]);
     const uint32_t nj = g.job_end - g.job_begin;
@@ -1720,6 +1804,19 @@ uint64_t stream_chunks(uint64_t n, int dtype, uint32_t chunk_vec) {
 }
 
 hipError_t launch_compress(const CParams& P0, const Tuning& tn, hipStream_t s) {
+  return launch_compress_phase(P0, tn, s, 3);
+}
+
+hipError_t launch_autob(const CParams& P, uint32_t b_lo, uint32_t b_hi, hipStream_t s) {
+  Geo g{};
+  g.job_begin = 0;
+  g.job_end = 1;
+  NK_LAUNCH(KK_SELECT, k_autob<OneJob>, 1, SEL_TPB, OneJob{P}, g, b_lo, b_hi);
+  return hipSuccess;
+}
+
+hipError_t launch_compress_phase(const CParams& P0, const Tuning& tn, hipStream_t s,
+                                 unsigned phases) {
   const Geometry G = geometry();
   CParams P = P0;
   const int cls = enc_class(P.B);
@@ -1742,7 +1839,7 @@ hipError_t launch_compress(const CParams& P0, const Tuning& tn, hipStream_t s) {
   grp.nt = stream_nt_for(tn.stream_loads, 2 * P.n * (P.dtype == NUMARCK_F32 ? 4 : 8),
                          P.prev == P.curr);
   if (grp.nt == 2) grp.nt = 0;  // one job: its two inputs are one snapshot
-  return run_chain(OneJob{P}, base, 1, &grp, 1, &grp, 1, &grp, 1, &grp, 1, tn, s);
+  return run_chain(OneJob{P}, base, 1, &grp, 1, &grp, 1, &grp, 1, &grp, 1, tn, s, phases);
 }
 
 hipError_t launch_compress_batch(const BatchLaunch& b, hipStream_t s) {

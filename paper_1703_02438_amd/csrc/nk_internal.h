@@ -81,6 +81,9 @@ struct Ctl {
   unsigned int nsel_tail;
   unsigned int nsel_tail_below;
   unsigned int n_inc;             // incompressible points (k_gather)
+  // choice of B (k_autob): estimated size in bits per B, and the chosen B
+  unsigned long long est_bits[17];
+  unsigned int auto_B;
 };
 
 // Control block of a decompression call.
@@ -293,6 +296,13 @@ struct BatchLaunch {
   Tuning tune;
 };
 hipError_t launch_compress_batch(const BatchLaunch& b, hipStream_t s);
+// One compression in two halves around the choice of B: phase 1 runs the
+// passes that do not depend on B (ratios, range, histogram, tail hash),
+// phase 2 the rest; launch_autob estimates the size of every B in
+// [b_lo, b_hi] from phase 1's histogram (eqs. 5-6) into the control block.
+hipError_t launch_compress_phase(const CParams& P, const Tuning& tn, hipStream_t s,
+                                 unsigned phases);
+hipError_t launch_autob(const CParams& P, uint32_t b_lo, uint32_t b_hi, hipStream_t s);
 // Resident workgroups per CU of one encoder specialisation (for sizing units).
 int encoder_occupancy(int dtype, int cls, bool table);
 // Streaming chunks of a job (0 for an empty job, at least 1 otherwise).

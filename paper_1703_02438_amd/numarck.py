@@ -136,6 +136,10 @@ numarck_decompress_workspace_bytes = _bind("numarck_decompress_workspace_bytes",
 numarck_compress = _bind("numarck_compress", _i,
                          [_vp, _vp, _u64, _i, _d, _u32, _u64, ctypes.POINTER(NumarckOut), _vp,
                           _sz, _vp])
+numarck_compress_auto = _bind("numarck_compress_auto", _i,
+                              [_vp, _vp, _u64, _i, _d, _u32, _u32, _u64,
+                               ctypes.POINTER(NumarckOut), _vp, _sz, _vp,
+                               ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_uint64)])
 numarck_decompress = _bind("numarck_decompress", _i,
                            [ctypes.POINTER(NumarckHeader), _vp, _vp, _vp, _vp, _vp, _vp, _vp,
                             _vp, _sz, _vp])
@@ -294,6 +298,36 @@ def compress(prev: torch.Tensor, curr: torch.Tensor, E: float, B: int, block_byt
     _check(st, "numarck_compress")
     return Compressed(o["packed"], o["centers"], o["incomp"], o["block_inc_off"], o["recon"],
                       o["bin_ids"], o["hdr"], ws, n, prev.dtype)
+
+
+def compress_auto(prev: torch.Tensor, curr: torch.Tensor, E: float, B_min: int = 1,
+                  B_max: int = 16, block_bytes: int = 0, recon: bool = False,
+                  bin_ids: bool = False, ws: torch.Tensor | None = None,
+                  outputs: dict | None = None, stream=None):
+    """:func:`compress` with B chosen in [B_min, B_max] from the histogram
+    (numarck_compress_auto).  Returns (Compressed, B, est_bits): est_bits[B]
+    is the estimated compressed size in bits of each B of the range."""
+    if prev.dtype != curr.dtype or prev.numel() != curr.numel():
+        raise ValueError("prev and curr must have the same dtype and size")
+    prev = prev.reshape(-1)
+    curr = curr.reshape(-1)
+    n = prev.numel()
+    dt = dtype_code(prev.dtype)
+    o = outputs if outputs is not None else alloc_outputs(n, prev.dtype, B_max, block_bytes,
+                                                          recon, bin_ids, prev.device)
+    if ws is None:
+        ws = torch.empty(numarck_workspace_bytes(n, dt, B_max), dtype=torch.uint8,
+                         device=prev.device)
+    out = out_struct(o)
+    B = ctypes.c_uint32(0)
+    bits = (ctypes.c_uint64 * 17)()
+    st = numarck_compress_auto(_ptr(prev), _ptr(curr), n, dt, float(E), int(B_min), int(B_max),
+                               int(block_bytes), ctypes.byref(out), _ptr(ws), ws.numel(),
+                               _stream(stream), ctypes.byref(B), bits)
+    _check(st, "numarck_compress_auto")
+    c = Compressed(o["packed"], o["centers"], o["incomp"], o["block_inc_off"], o["recon"],
+                   o["bin_ids"], o["hdr"], ws, n, prev.dtype)
+    return c, int(B.value), [int(x) for x in bits]
 
 
 def default_tuning() -> NumarckTuning:

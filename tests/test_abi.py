@@ -103,6 +103,23 @@ def _header(nk, n=1000, B=8, bb=1 << 20):
     return h
 
 
+def test_compress_auto_validation_without_gpu(nk):
+    o = _out(nk)
+    ws, big = 0x200000, 1 << 40
+    p, q = 0x300000, 0x400000
+    B = ctypes.c_uint32(0)
+    bits = (ctypes.c_uint64 * 17)()
+    call = lambda lo, hi, **kw: nk.numarck_compress_auto(
+        kw.get("p", p), q, 10, nk.F64, kw.get("E", 1e-3), lo, hi, 0, ctypes.byref(o), ws, big,
+        None, kw.get("B", ctypes.byref(B)), bits)
+    assert call(0, 8) == nk.EBITS
+    assert call(1, 17) == nk.EBITS
+    assert call(9, 8) == nk.EBITS
+    assert call(1, 16, B=None) == nk.EINVAL
+    assert call(1, 16, E=0.0) == nk.EBOUND
+    assert call(1, 16, p=p + 8) == nk.EALIGN
+
+
 def test_decompress_validation_without_gpu(nk):
     h = _header(nk)
     ws, big = 0x200000, 1 << 30

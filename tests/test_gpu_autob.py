@@ -1,0 +1,90 @@
+"""Compression with B chosen from the histogram (numarck_compress_auto, Sec.
+IV-B-2, eqs. 5-6) through the C ABI: the estimated size of every B in the
+range and the chosen B equal the CPU oracle's, and the compression equals the
+oracle's compression with that B in every output."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from gpu_util import assert_matches_oracle, compare_decompress, to_np
+from paper_1703_02438_amd import inputs
+from pins import centred_case, mixture_case
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def nk():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_1703_02438_amd.numarck as nk
+    return nk
+
+
+def _tail_case(n=200_000, seed=3):
+    rng = np.random.default_rng(seed)
+    prev = rng.lognormal(0, 1, n)
+    u = rng.random(n)
+    r = np.where(u < 0.3, rng.normal(0, 1e-5, n),
+                 np.where(u < 0.5, rng.normal(0.4, 3e-5, n),
+                          np.where(u < 0.7, rng.normal(-0.45, 3e-5, n), rng.uniform(-0.5, 0.5, n))))
+    return prev, prev * (1 + r)
+
+
+def _flash32():
+    s = inputs.FlashSeries(edge=32, seed=11)
+    return s.x.clone().numpy(), s.step().numpy()
+
+
+def _climate_spill():
+    s = inputs.ClimateSeries(nlat=180, nlon=360, seed=12, outlier_lo=-0.9, outlier_hi=1.5)
+    return s.x.clone().numpy(), s.step().numpy()
+
+
+CASES = {
+    "mixture_f64": (lambda: mixture_case(262_144, 1704), 1e-3, 1, 16),
+    "mixture_f32": (lambda: mixture_case(100_003, 1705, np.float32, E=1e-4), 1e-4, 1, 16),
+    "centred": (lambda: centred_case({0: 4000, 1: 7000, 2: 5000, 3: 5000, 4: 5000, 6: 1000})[:2],
+                2.0 ** -10, 1, 16),
+    "tail_bins": (_tail_case, 1e-5, 8, 16),
+    "flash": (_flash32, 1e-3, 1, 16),
+    "climate_spill": (_climate_spill, 1e-4, 6, 14),
+    "all_invalid": (lambda: (np.zeros(9000), np.linspace(-1, 1, 9000)), 1e-3, 5, 9),
+    "one_point": (lambda: mixture_case(1, 7), 1e-3, 1, 16),
+}
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_auto_B_matches_oracle(nk, case):
+    make, E, lo, hi = CASES[case]
+    prev, curr = make()
+    orc = oracle.get()
+    B_ref, bits_ref = orc.choose_B(prev, curr, E, lo, hi)
+    dev = torch.device("cuda:0")
+    p = torch.from_numpy(np.ascontiguousarray(prev)).to(dev)
+    q = torch.from_numpy(np.ascontiguousarray(curr)).to(dev)
+    c, B, bits = nk.compress_auto(p, q, E, lo, hi, recon=True, bin_ids=True)
+    assert bits == bits_ref, f"[{case}] estimated sizes"
+    assert B == B_ref, f"[{case}] chosen B"
+    assert c.header().B == B
+    o = orc.compress(prev, curr, E, B)
+    assert_matches_oracle(nk, c, o, prev, curr, E, B, check_hist=False, label=f"auto {case}")
+    if case in ("mixture_f64", "tail_bins"):
+        compare_decompress(nk, c, o, p, prev, [(0, prev.size), (prev.size // 3, 1000)],
+                           label=f"auto {case}")
+
+
+def test_auto_B_equals_fixed_B(nk):
+    """The automatic path with a one-value range is the plain compression."""
+    prev, curr = mixture_case(70_001, 42)
+    p = torch.from_numpy(prev).cuda()
+    q = torch.from_numpy(curr).cuda()
+    for b in (3, 8, 11):
+        c, B, bits = nk.compress_auto(p, q, 1e-3, b, b)
+        ref = nk.compress(p, q, 1e-3, b)
+        assert B == b and bits[b] > 0 and sum(x > 0 for x in bits) == 1
+        nw = ref.header().packed_bytes // 4
+        assert torch.equal(c.packed[:nw], ref.packed[:nw])
+        ni = ref.header().n_inc
+        assert c.header().n_inc == ni
+        assert torch.equal(c.incomp[:ni].view(torch.int64), ref.incomp[:ni].view(torch.int64))
