@@ -200,6 +200,32 @@ def decompress_section(torch, nk, c, prev, reps: int, stream, workload: str) -> 
     }
 
 
+def auto_b_section(torch, nk, prev, curr, outs_max, ws, reps: int, stream) -> dict:
+    """Compression with B chosen in [1, 16] from the histogram (eqs. 5-6) on
+    the benchmark pair: the choice, every B's estimated size against the
+    compression's actual size, and the time of the automatic call (which
+    waits once on the stream for the choice) against a plain call with the
+    chosen B."""
+    n = prev.numel()
+    c, B, est = nk.compress_auto(prev, curr, E, 1, 16, ws=ws, outputs=outs_max, stream=stream)
+    h = c.header()
+    t_auto = time_ms(torch, lambda: nk.compress_auto(prev, curr, E, 1, 16, ws=ws,
+                                                      outputs=outs_max, stream=stream), reps, stream)
+    outs = nk.alloc_outputs(n, torch.float64, B)
+    t_plain = time_ms(torch, lambda: nk.compress(prev, curr, E, B, ws=ws, outputs=outs,
+                                                 stream=stream), reps, stream)
+    return {
+        "B": B,
+        "est_bytes": {b: est[b] // 8 for b in range(1, 17)},
+        "actual_compressed_bytes": int(h.compressed_bytes),
+        "est_n_inc": (est[B] - 8 * (1 << B) * 8 - n * B) // 64,
+        "actual_n_inc": int(h.n_inc),
+        "auto_ms": round(t_auto, 4),
+        "plain_ms_same_B": round(t_plain, 4),
+        "auto_gbs": round(n * 8 / t_auto / 1e6, 1),
+    }
+
+
 def time_ms(torch, fn, reps: int, stream) -> float:
     """Average ms of fn() over reps runs, HIP events on `stream` (after one warm run)."""
     fn()
@@ -476,6 +502,9 @@ def main():
     in_bytes = n * 8
     value = in_bytes * args.steps / wall / 1e9
     dec = decompress_section(torch, nk, step(0), snaps[0], args.steps, stream, workload)
+    auto_b = auto_b_section(torch, nk, snaps[0], snaps[1],
+                            nk.alloc_outputs(n, torch.float64, 16, device=dev), ws,
+                            max(3, args.steps // 3), stream)
     del snaps, ws, outs, c
     torch.cuda.empty_cache()
     batched = None
@@ -513,6 +542,7 @@ def main():
         },
         "latency_ms": {"p50": round(p50, 4), "p99": round(p99, 4)},
         "decompress": dec,
+        "auto_b": auto_b,
         "batched": batched,
         "serving": serving,
         "kernels_us": {k: round(v[1] / v[0] * 1e3, 1) for k, v in per_kernel.items()},

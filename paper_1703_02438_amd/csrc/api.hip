@@ -351,22 +351,19 @@ numarck_status numarck_compress_auto(const void* prev, const void* curr, uint64_
   const CParams P1 = make_params(prev, curr, n, dtype, E, B_max, block_bytes, out, base, L);
   hipError_t e = launch_compress_phase(P1, tn, s, 1);
   if (e == hipSuccess) e = launch_autob(P1, B_min, B_max, s);
-  struct {
-    unsigned long long bits[17];
-    unsigned int B;
-  } got{};
-  Ctl* c = P1.ctl;
+  unsigned long long bits[17] = {};
   if (e == hipSuccess)
-    e = hipMemcpyAsync(got.bits, c->est_bits, sizeof(got.bits), hipMemcpyDeviceToHost, s);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(&got.B, &c->auto_B, sizeof(got.B), hipMemcpyDeviceToHost, s);
+    e = hipMemcpyAsync(bits, P1.ctl->est_bits, sizeof(bits), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return hip_fail(e);
-  if (got.B < B_min || got.B > B_max) return hip_fail(hipErrorUnknown);
-  *B_out = got.B;
+  // the smallest estimate, the smaller B on equal estimates
+  uint32_t B = B_min;
+  for (uint32_t b = B_min + 1; b <= B_max; ++b)
+    if (bits[b] < bits[B]) B = b;
+  *B_out = B;
   if (est_bits)
-    for (int b = 0; b <= 16; ++b) est_bits[b] = got.bits[b];
-  const CParams P2 = make_params(prev, curr, n, dtype, E, got.B, block_bytes, out, base, L);
+    for (int b = 0; b <= 16; ++b) est_bits[b] = bits[b];
+  const CParams P2 = make_params(prev, curr, n, dtype, E, B, block_bytes, out, base, L);
   e = launch_compress_phase(P2, tn, s, 2);
   return e == hipSuccess ? NUMARCK_OK : hip_fail(e);
 }

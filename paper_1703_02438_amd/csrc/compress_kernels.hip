@@ -1036,16 +1036,22 @@ __global__ void __launch_bounds__(SEL_TPB) k_select(SRC src, Geo g) {
 // =====================================================================
 // k_autob: choice of B from the histogram (Sec. IV-B-2, eqs. 5-6)
 // =====================================================================
-// For every B in [b_lo, b_hi]: the points held by the 2^B - 1 fullest bins
-// (all valid points when there are no more nonzero bins than that; otherwise
-// the counts above the (2^B - 1)-th largest count tau, plus tau for each of
-// the remaining places), and the estimated size 2^B L + n B / 8 + n alpha L
-// in bits, alpha n being the points not held.  The smallest size wins, the
-// smaller B on equal sizes.  Exact while the tail fits its capacity.
+// Workgroup b estimates B = b_lo + b: the points held by the 2^B - 1
+// fullest bins (all valid points when there are no more nonzero bins than
+// that; otherwise the counts above the (2^B - 1)-th largest count tau, plus
+// tau for each of the remaining places), and the estimated size
+// 2^B L + n B / 8 + n alpha L in bits, alpha n being the points not held.
+// Exact while the tail fits its capacity.  The caller picks the smallest.
+// Tail-bin counts held in LDS for the repeated visits (80 KB beside the
+// window); a larger tail is visited in the hash table instead.
+constexpr int AUTOB_TAIL_LDS = 20480;
+
 template <typename SRC>
 __global__ void __launch_bounds__(SEL_TPB) k_autob(SRC src, Geo g, uint32_t b_lo, uint32_t b_hi) {
-  const CParams& P = src.job(g.job_begin + blockIdx.x);
+  const CParams& P = src.job(g.job_begin);
   __shared__ SelShared S;
+  __shared__ uint32_t s_tc[AUTOB_TAIL_LDS];
+  __shared__ unsigned s_ntc;
   Ctl* c = P.ctl;
   const int tid = threadIdx.x;
   const bool empty = c->empty != 0;
@@ -1059,14 +1065,42 @@ __global__ void __launch_bounds__(SEL_TPB) k_autob(SRC src, Geo g, uint32_t b_lo
   const unsigned long long n_valid = empty ? 0ull : c->n_valid;
   const unsigned long long L = P.dtype == NUMARCK_F32 ? 4ull : 8ull;
   unsigned long long nzw, mxw;
-  sel_load_window(P, S, win_len, nzw, mxw);
+  if (tid == 0) s_ntc = 0;
+  sel_load_window(P, S, win_len, nzw, mxw);  // its barriers also publish s_ntc
   const unsigned long long nz = nzw + tail_bins;
+  // the nonzero tail-bin counts (their ids are not needed here) into LDS,
+  // when the window alone cannot decide
+  unsigned ntc = 0;
+  bool tail_lds = false;
+  auto gather_tail = [&]() {
+    for (unsigned long long si = tid; si < H; si += SEL_TPB) {
+      const uint32_t slot = gload(P.hslot + si);
+      const uint32_t cn = slot == HEMPTY ? 0u : gload(P.hcnt + si);
+      if (cn != 0) {
+        const unsigned pos = atomicAdd(&s_ntc, 1u);
+        if (pos < (unsigned)AUTOB_TAIL_LDS) s_tc[pos] = cn;
+      }
+    }
+    __syncthreads();
+    ntc = s_ntc;
+    tail_lds = ntc <= (unsigned)AUTOB_TAIL_LDS;
+  };
   auto visit_win = [&](auto f) { sel_visit(P, S, wbase, win_len, false, 0ull, f); };
-  auto visit_all = [&](auto f) { sel_visit(P, S, wbase, win_len, has_tail, H, f); };
+  auto visit_all = [&](auto f) {
+    if (tail_lds) {  // every lane makes the same number of calls (count 0: none)
+      sel_visit(P, S, wbase, win_len, false, 0ull, f);
+      const unsigned rounds = (ntc + SEL_TPB - 1) / SEL_TPB;
+      for (unsigned r = 0; r < rounds; ++r) {
+        const unsigned i = r * SEL_TPB + tid;
+        f(0ll, i < ntc ? s_tc[i] : 0u);
+      }
+    } else {
+      sel_visit(P, S, wbase, win_len, has_tail, H, f);
+    }
+  };
 
-  unsigned long long best = 0;
-  uint32_t best_B = 0;
-  for (uint32_t B = b_lo; B <= b_hi; ++B) {
+  {
+    const uint32_t B = b_lo + blockIdx.x;
     const unsigned long long k = (1ull << B) - 1ull;
     unsigned long long held = n_valid;
     if (nz > k) {
@@ -1077,7 +1111,10 @@ __global__ void __launch_bounds__(SEL_TPB) k_autob(SRC src, Geo g, uint32_t b_lo
         tau = sel_kth_count(S, mxw, k, visit_win);
         win_only = tail_max < tau;
       }
-      if (!win_only) tau = sel_kth_count(S, mxw > tail_max ? mxw : tail_max, k, visit_all);
+      if (!win_only) {
+        gather_tail();
+        tau = sel_kth_count(S, mxw > tail_max ? mxw : tail_max, k, visit_all);
+      }
       unsigned long long sum_gt = 0, n_gt = 0, u0 = ~0ull, u1 = 0;
       auto above = [&](long long, uint32_t cn) {
         if (cn > tau) {
@@ -1092,16 +1129,9 @@ __global__ void __launch_bounds__(SEL_TPB) k_autob(SRC src, Geo g, uint32_t b_lo
     const unsigned long long bits =
         8ull * (1ull << B) * L + n * (unsigned long long)B + 8ull * L * (n - held);
     if (tid == 0) c->est_bits[B] = bits;
-    if (best_B == 0 || bits < best) {
-      best = bits;
-      best_B = B;
-    }
   }
-  if (tid == 0) {
-    for (uint32_t B = 0; B <= 16; ++B)
-      if (B < b_lo || B > b_hi) c->est_bits[B] = 0ull;
-    c->auto_B = best_B;
-  }
+  if (blockIdx.x == 0 && tid < 17 && (tid < (int)b_lo || tid > (int)b_hi))
+    c->est_bits[tid] = 0ull;
 }
 
 // =====================================================================
@@ -1811,7 +1841,7 @@ hipError_t launch_autob(const CParams& P, uint32_t b_lo, uint32_t b_hi, hipStrea
   Geo g{};
   g.job_begin = 0;
   g.job_end = 1;
-  NK_LAUNCH(KK_SELECT, k_autob<OneJob>, 1, SEL_TPB, OneJob{P}, g, b_lo, b_hi);
+  NK_LAUNCH(KK_SELECT, k_autob<OneJob>, b_hi - b_lo + 1, SEL_TPB, OneJob{P}, g, b_lo, b_hi);
   return hipSuccess;
 }
 

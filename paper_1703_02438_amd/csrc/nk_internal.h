@@ -81,9 +81,8 @@ struct Ctl {
   unsigned int nsel_tail;
   unsigned int nsel_tail_below;
   unsigned int n_inc;             // incompressible points (k_gather)
-  // choice of B (k_autob): estimated size in bits per B, and the chosen B
+  // choice of B (k_autob): estimated size in bits per B
   unsigned long long est_bits[17];
-  unsigned int auto_B;
 };
 
 // Control block of a decompression call.
