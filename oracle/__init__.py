@@ -82,6 +82,10 @@ class Oracle:
                                      ctypes.c_uint32, ctypes.c_uint64, _VP, _VP, _VP, _VP, _VP,
                                      _VP, _VP, ctypes.POINTER(_Info)]
         lib.orc_compress.restype = ctypes.c_int
+        lib.orc_compress_ew.argtypes = [_VP, _VP, ctypes.c_uint64, ctypes.c_int, ctypes.c_double,
+                                        ctypes.c_uint32, ctypes.c_uint64, _VP, _VP, _VP, _VP, _VP,
+                                        _VP, ctypes.POINTER(_Info)]
+        lib.orc_compress_ew.restype = ctypes.c_int
         lib.orc_choose_B.argtypes = [_VP, _VP, ctypes.c_uint64, ctypes.c_int, ctypes.c_double,
                                      ctypes.c_uint32, ctypes.c_uint32, _VP,
                                      ctypes.POINTER(ctypes.c_uint32)]
@@ -137,7 +141,10 @@ class Oracle:
 
     # -- whole path ----------------------------------------------------------
     def compress(self, prev: np.ndarray, curr: np.ndarray, E: float, B: int,
-                 block_bytes: int = 0, recon: bool = True) -> "OracleResult":
+                 block_bytes: int = 0, recon: bool = True,
+                 binning: str = "topk") -> "OracleResult":
+        """The whole compression; binning "topk" (Sec. IV-B-1) or "equal_width"
+        (Sec. IV-B-3)."""
         prev, curr, dt = _pair(prev, curr)
         n = prev.size
         T = prev.dtype
@@ -154,10 +161,18 @@ class Oracle:
         index = np.empty(max(n, 1), np.uint16)
         sel = np.zeros(max((1 << B) - 1, 1), np.int64)
         info = _Info()
-        st = self.lib.orc_compress(_p(prev), _p(curr), n, dt, E, B, block_bytes, _p(packed),
-                                   _p(centers), _p(incomp), _p(blk),
-                                   _p(rec) if rec is not None else None, _p(index), _p(sel),
-                                   ctypes.byref(info))
+        if binning == "topk":
+            st = self.lib.orc_compress(_p(prev), _p(curr), n, dt, E, B, block_bytes, _p(packed),
+                                       _p(centers), _p(incomp), _p(blk),
+                                       _p(rec) if rec is not None else None, _p(index), _p(sel),
+                                       ctypes.byref(info))
+        elif binning == "equal_width":
+            st = self.lib.orc_compress_ew(_p(prev), _p(curr), n, dt, E, B, block_bytes,
+                                          _p(packed), _p(centers), _p(incomp), _p(blk),
+                                          _p(rec) if rec is not None else None, _p(index),
+                                          ctypes.byref(info))
+        else:
+            raise ValueError(f"unknown binning {binning}")
         if st != 0:
             raise ValueError(f"oracle compress failed with status {st}")
         h = info.as_dict()
@@ -166,7 +181,7 @@ class Oracle:
             packed=packed[: h["packed_words"]].copy(), centers=centers,
             incomp=incomp[: h["n_inc"]].copy(), block_inc_off=blk[: h["n_blocks"]].copy(),
             recon=None if rec is None else rec[:n].copy(), index=index[:n].copy(),
-            sel_ids=sel[: h["k_used"]].copy(),
+            sel_ids=sel[: h["k_used"]].copy() if binning == "topk" else np.zeros(0, np.int64),
         )
 
     def choose_B(self, prev: np.ndarray, curr: np.ndarray, E: float, b_lo: int = 1,

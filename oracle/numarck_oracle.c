@@ -18,6 +18,8 @@
  *   7. B-bit packing of the index table                          (Sec. IV-C)
  *   8. per-block count of earlier incompressible points          (Sec. IV-C)
  *   9. decompression by eq. (4), full and partial                (Sec. III-E, V-C)
+ * plus the choice of B by eqs. (5)-(6) (Sec. IV-B-2) and, as an alternative to
+ * steps 3-4, equal-width binning (Sec. III-B, IV-B-3).
  *
  * Readings taken where the paper is silent or garbled:
  *   - a point is valid when its previous value is nonzero and finite, the new
@@ -29,6 +31,8 @@
  *   - bin centre c_m = lo + (2m + 1) E in binary64, stored in the snapshot type;
  *   - reconstruction R = T(p * (1 + c)) (the only reading of eq. (4) consistent
  *     with eq. (1)); a point is kept only if |R - q| <= E |p| after rounding;
+ *   - equal-width binning: w = (hi - lo) / k, chunk i = min(floor((d - lo) / w),
+ *     k - 1) (0 when w is 0), centre lo + (i + 1/2) w; the rest as above;
  *   - index bits are written least-significant first into a contiguous stream
  *     of little-endian 32-bit words; elements per block = floor(8 * bytes / B).
  *
@@ -289,6 +293,80 @@ static int64_t find_sorted(const int64_t* a, int64_t len, int64_t key) {
   return hit ? (int64_t)(hit - a) : -1;
 }
 
+/* ------------------------------------------------ steps 5-8 for any binning */
+
+/* cand[j]: the index of point j's bin among the bin centres, or -1 (invalid
+ * point, or a bin without a centre).  Each candidate is kept only if its
+ * reconstruction T(p (1 + c)) is within E |p| of the new value (Sec. III-C);
+ * every other point gets the escape code and its value is stored as it is.
+ * Then the B-bit packing and the block offsets (Sec. IV-C), and the header:
+ * `part` brings the binning's fields (n_valid, M, n_nonzero, k_used, tau,
+ * lo, hi).  idx: n scratch words. */
+static int index_and_pack(const void* prev, const void* curr, uint64_t n, int dtype, double E,
+                          uint32_t B, uint64_t block_bytes, const int64_t* cand,
+                          const void* centers, uint32_t* packed, void* incomp,
+                          int64_t* block_inc_off, void* recon, uint16_t* index, uint32_t* idx,
+                          const orc_info* part, orc_info* info) {
+  const uint32_t k = (1u << B) - 1u;
+  const uint32_t esc = k;
+  const size_t L = elem_size(dtype);
+  uint64_t n_inc = 0;
+  for (uint64_t j = 0; j < n; j++) {
+    uint32_t code = esc;
+    const int64_t i = cand[j];
+    if (i >= 0) {
+      double p = load_as_double(prev, dtype, j);
+      double q = load_as_double(curr, dtype, j);
+      double c = load_as_double(centers, dtype, (uint64_t)i);
+      double r = rounded_to_type(dtype, p * (1.0 + c));
+      if (fabs(r - q) <= E * fabs(p)) {
+        code = (uint32_t)i;
+        if (recon) store_rounded(recon, dtype, j, r);
+      }
+    }
+    if (code == esc) {
+      copy_elem(incomp, n_inc, curr, j, dtype);
+      n_inc++;
+      if (recon) copy_elem(recon, j, curr, j, dtype);
+    }
+    idx[j] = code;
+    if (index) index[j] = (uint16_t)code;
+  }
+
+  /* step 7: packing */
+  uint64_t words = (n * B + 31) / 32;
+  memset(packed, 0, words * 4);
+  for (uint64_t j = 0; j < n; j++) put_index(packed, j, B, idx[j]);
+
+  /* step 8: per-block offsets into the incompressible array */
+  uint64_t epb = (8 * block_bytes) / B;
+  uint64_t n_blocks = (n + epb - 1) / epb;
+  {
+    uint64_t seen = 0;
+    for (uint64_t j = 0; j < n; j++) {
+      if (j % epb == 0 && block_inc_off) block_inc_off[j / epb] = (int64_t)seen;
+      if (idx[j] == esc) seen++;
+    }
+  }
+
+  *info = *part;
+  info->n = n;
+  info->n_invalid = n - part->n_valid;
+  info->n_inc = n_inc;
+  info->n_blocks = n_blocks;
+  info->elems_per_block = epb;
+  info->block_bytes = block_bytes;
+  info->B = B;
+  info->k = k;
+  info->dtype = (uint32_t)dtype;
+  info->E = E;
+  info->packed_words = words;
+  info->packed_bytes = words * 4;
+  /* eq. (6) with the actual packed size: 2^B L + packed + n_inc L */
+  info->compressed_bytes = ((uint64_t)1 << B) * L + words * 4 + n_inc * L;
+  return ORC_OK;
+}
+
 /* ------------------------------------------------ the whole compression */
 
 int orc_compress(const void* prev, const void* curr, uint64_t n, int dtype, double E,
@@ -302,7 +380,6 @@ int orc_compress(const void* prev, const void* curr, uint64_t n, int dtype, doub
   if (block_bytes == 0) block_bytes = (uint64_t)1 << 20;
 
   const uint32_t k = (1u << B) - 1u;
-  const uint32_t esc = k;
   const size_t L = elem_size(dtype);
   const uint64_t nn = n ? n : 1;
 
@@ -341,75 +418,89 @@ int orc_compress(const void* prev, const void* curr, uint64_t n, int dtype, doub
   for (int64_t i = 0; i < k_used; i++)
     store_rounded(centers, dtype, (uint64_t)i, lo + (double)(2 * sel[i] + 1) * E);
 
-  /* step 5-6: index every point, verify the bound after rounding */
-  uint64_t n_inc = 0;
-  for (uint64_t j = 0; j < n; j++) {
-    uint32_t code = esc;
-    if (valid[j]) {
-      int64_t i = find_sorted(sel, k_used, m[j]);
-      if (i >= 0) {
-        double p = load_as_double(prev, dtype, j);
-        double q = load_as_double(curr, dtype, j);
-        double c = load_as_double(centers, dtype, (uint64_t)i);
-        double r = rounded_to_type(dtype, p * (1.0 + c));
-        if (fabs(r - q) <= E * fabs(p)) {
-          code = (uint32_t)i;
-          if (recon) store_rounded(recon, dtype, j, r);
-        }
-      }
-    }
-    if (code == esc) {
-      copy_elem(incomp, n_inc, curr, j, dtype);
-      n_inc++;
-      if (recon) copy_elem(recon, j, curr, j, dtype);
-    }
-    idx[j] = code;
-    if (index) index[j] = (uint16_t)code;
-  }
+  /* each valid point's candidate index: the rank of its bin among the
+     selected ones, or none */
+  for (uint64_t j = 0; j < n; j++) m[j] = valid[j] ? find_sorted(sel, k_used, m[j]) : -1;
 
-  /* step 7: packing */
-  uint64_t words = (n * B + 31) / 32;
-  memset(packed, 0, words * 4);
-  for (uint64_t j = 0; j < n; j++) put_index(packed, j, B, idx[j]);
-
-  /* step 8: per-block offsets into the incompressible array */
-  uint64_t epb = (8 * block_bytes) / B;
-  uint64_t n_blocks = (n + epb - 1) / epb;
-  {
-    uint64_t seen = 0;
-    for (uint64_t j = 0; j < n; j++) {
-      if (j % epb == 0 && block_inc_off) block_inc_off[j / epb] = (int64_t)seen;
-      if (idx[j] == esc) seen++;
-    }
-  }
-
-  if (sel_ids)
+  orc_info part = {0};
+  part.n_valid = n_valid;
+  part.M = M;
+  part.n_nonzero = (uint64_t)nbins;
+  part.k_used = (uint32_t)k_used;
+  part.tau = tau;
+  part.lo = lo;
+  part.hi = hi;
+  st = index_and_pack(prev, curr, n, dtype, E, B, block_bytes, m, centers, packed, incomp,
+                      block_inc_off, recon, index, idx, &part, info);
+  if (st == ORC_OK && sel_ids)
     for (int64_t i = 0; i < k_used; i++) sel_ids[i] = sel[i];
 
-  info->n = n;
-  info->n_valid = n_valid;
-  info->n_invalid = n - n_valid;
-  info->n_inc = n_inc;
-  info->n_blocks = n_blocks;
-  info->elems_per_block = epb;
-  info->block_bytes = block_bytes;
-  info->M = M;
-  info->n_nonzero = (uint64_t)nbins;
-  info->B = B;
-  info->k = k;
-  info->k_used = (uint32_t)k_used;
-  info->dtype = (uint32_t)dtype;
-  info->tau = tau;
-  info->E = E;
-  info->lo = lo;
-  info->hi = hi;
-  info->packed_words = words;
-  info->packed_bytes = words * 4;
-  /* eq. (6) with the actual packed size: 2^B L + packed + n_inc L */
-  info->compressed_bytes = ((uint64_t)1 << B) * L + words * 4 + n_inc * L;
-
   free(d); free(valid); free(m); free(hid); free(hcnt); free(sel); free(idx);
-  return ORC_OK;
+  return st;
+}
+
+/* ------------------------------------------------ equal-width binning */
+
+/* The range [lo, hi] of the valid ratios cut into k = 2^B - 1 chunks of width
+ * w = (hi - lo) / k (Sec. III-B, Sec. IV-B-3); chunk i holds the ratios with
+ * floor((d - lo) / w) == i, the largest ratio (and any rounding past the last
+ * chunk) in chunk k - 1, every valid ratio in chunk 0 when w = 0.  The centre
+ * of chunk i is its midpoint lo + (i + 1/2) w, stored in the snapshot type.
+ * Indexing, verification, packing and blocks as for top-k binning; the
+ * header's M and k_used are k (0 without a valid point), n_nonzero and tau
+ * are 0. */
+int orc_compress_ew(const void* prev, const void* curr, uint64_t n, int dtype, double E,
+                    uint32_t B, uint64_t block_bytes, uint32_t* packed, void* centers,
+                    void* incomp, int64_t* block_inc_off, void* recon, uint16_t* index,
+                    orc_info* info) {
+  int st = check_args(dtype, E, B);
+  if (st != ORC_OK) return st;
+  if (n >= ((uint64_t)1 << 32)) return ORC_EINVAL;
+  if (!info || (n && (!prev || !curr || !incomp || !packed)) || !centers) return ORC_EINVAL;
+  if (block_bytes == 0) block_bytes = (uint64_t)1 << 20;
+  const uint32_t k = (1u << B) - 1u;
+  const size_t L = elem_size(dtype);
+  const uint64_t nn = n ? n : 1;
+  double* d = (double*)malloc(nn * sizeof(double));
+  uint8_t* valid = (uint8_t*)malloc(nn);
+  int64_t* cand = (int64_t*)malloc(nn * sizeof(int64_t));
+  uint32_t* idx = (uint32_t*)malloc(nn * sizeof(uint32_t));
+  if (!d || !valid || !cand || !idx) {
+    free(d); free(valid); free(cand); free(idx);
+    return ORC_ENOMEM;
+  }
+  orc_ratio(prev, curr, n, dtype, E, d, valid);
+  double lo = 0.0, hi = 0.0;
+  const uint64_t n_valid = orc_range(d, valid, n, &lo, &hi);
+  if (n_valid == 0) {
+    lo = 0.0;
+    hi = 0.0;
+  }
+  const double w = (hi - lo) / (double)k;
+  memset(centers, 0, ((size_t)1 << B) * L);
+  if (n_valid > 0)
+    for (uint32_t i = 0; i < k; i++)
+      store_rounded(centers, dtype, (uint64_t)i, lo + ((double)i + 0.5) * w);
+  for (uint64_t j = 0; j < n; j++) {
+    cand[j] = -1;
+    if (!valid[j]) continue;
+    int64_t i = 0;
+    if (w > 0.0) {
+      const double t = floor((d[j] - lo) / w);
+      i = t < (double)(k - 1) ? (int64_t)t : (int64_t)(k - 1);
+    }
+    cand[j] = i;
+  }
+  orc_info part = {0};
+  part.n_valid = n_valid;
+  part.M = n_valid ? (int64_t)k : 0;
+  part.k_used = n_valid ? k : 0;
+  part.lo = lo;
+  part.hi = hi;
+  st = index_and_pack(prev, curr, n, dtype, E, B, block_bytes, cand, centers, packed, incomp,
+                      block_inc_off, recon, index, idx, &part, info);
+  free(d); free(valid); free(cand); free(idx);
+  return st;
 }
 
 /* ------------------------------------------------ decompression, eq. (4) */

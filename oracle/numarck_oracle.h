@@ -71,6 +71,14 @@ int64_t orc_histogram(const int64_t* m, const uint8_t* valid, uint64_t n, int64_
 int64_t orc_topk(const int64_t* ids, const uint32_t* counts, int64_t nbins, uint32_t k,
                  int64_t* sel, uint32_t* tau);
 
+/* Equal-width binning (Sec. III-B, IV-B-3): the compression of orc_compress
+ * with the 2^B - 1 bins cut evenly from [lo, hi] instead of the top-k fine
+ * bins; same outputs (sel_ids does not apply). */
+int orc_compress_ew(const void* prev, const void* curr, uint64_t n, int dtype, double E,
+                    uint32_t B, uint64_t block_bytes, uint32_t* packed, void* centers,
+                    void* incomp, int64_t* block_inc_off, void* recon, uint16_t* index,
+                    orc_info* info);
+
 /* Selection of B (Sec. IV-B-2, eqs. 5-6): for every B in [b_lo, b_hi] the
  * estimated compressed size file_size(B) = 2^B L + n B / 8 + n alpha(B) L,
  * where alpha(B) n = n - (sum of the 2^B - 1 largest bin counts), in bits

@@ -520,10 +520,85 @@ def pin_choose_B_ties_lowest(o):
     assert (B, bits[1], bits[2], bits[3]) == (1, 512, 512, 896)
 
 
+def _ew_grid(shift: int, E: float, seed: int):
+    """Ratios (j - shift) / 8 for j = 0..7, each four times, on previous
+    values +-2^s: every ratio, product and centre below is exact."""
+    rng = np.random.default_rng(seed)
+    j = np.repeat(np.arange(8), 4)
+    rng.shuffle(j)
+    p = (2.0 ** rng.integers(-3, 4, j.size)) * np.where(rng.random(j.size) < 0.3, -1, 1)
+    q = p * (1.0 + (j - shift) / 8.0)
+    return p, q, j
+
+
+def pin_ew_grid(o):
+    """Sec. III-B / IV-B-3, equal-width binning: ratios (j - s)/8, j = 0..7,
+    B = 3.  The k = 7 chunks of [lo, hi] = [-s/8, (7-s)/8] are 1/8 wide, ratio
+    j falls in chunk j (the largest, on hi, in the last chunk 6), and each
+    centre is the chunk midpoint lo + (i + 1/2)/8.  Every point is then 1/16
+    of |p| from its centre: all compress at E = 1/16 and none at a hair less."""
+    for shift in (0, 3):
+        p, q, j = _ew_grid(shift, 1.0 / 16, 11 + shift)
+        res = o.compress(p, q, 1.0 / 16, 3, binning="equal_width")
+        h = res.info
+        assert h["lo"] == -shift / 8 and h["hi"] == (7 - shift) / 8
+        assert h["k_used"] == 7 and h["M"] == 7 and h["n_inc"] == 0
+        assert res.index.tolist() == np.minimum(j, 6).tolist()
+        want = [(-shift + i + 0.5) / 8 for i in range(7)] + [0.0]
+        assert res.centers.tolist() == want
+        res = o.compress(p, q, 1.0 / 16 - 2.0 ** -30, 3, binning="equal_width")
+        assert res.info["n_inc"] == p.size and res.index.tolist() == [7] * p.size
+
+
+def pin_ew_degenerate(o):
+    """Equal-width binning with every valid ratio equal: the range has width
+    0, every valid point takes chunk 0 and every centre is that ratio; points
+    with a zero previous value escape.  With no valid point nothing is
+    selected."""
+    p = np.array([1.0, 2.0, 0.0, -8.0, 0.5] * 10)
+    q = p * 1.25 + np.where(p == 0, 3.0, 0.0)
+    res = o.compress(p, q, 1e-3, 4, binning="equal_width")
+    zero = p == 0
+    assert res.index.tolist() == np.where(zero, 15, 0).tolist()
+    assert res.centers.tolist() == [0.25] * 15 + [0.0]
+    assert res.info["n_inc"] == zero.sum() and res.info["lo"] == res.info["hi"] == 0.25
+    res = o.compress(np.zeros(6), np.ones(6), 1e-3, 4, binning="equal_width")
+    assert res.info["k_used"] == 0 and res.info["n_inc"] == 6 and res.centers.tolist() == [0.0] * 16
+
+
+def pin_ew_membership(o):
+    """Equal-width binning on a mixture, checked point by point with exact
+    rationals: a valid point's chunk i holds its ratio, lo + i w <= d <=
+    lo + (i+1) w with w = (hi - lo)/k (to the rounding of one division), a
+    compressed point is within E |p| of its reconstruction, and decompression
+    returns the reconstruction."""
+    E = 1e-3
+    for dt, B in ((np.float64, 4), (np.float32, 6)):
+        p, q = mixture_case(700, 31, dt)
+        res = o.compress(p, q, E, B, binning="equal_width")
+        h = res.info
+        k = (1 << B) - 1
+        lo, hi = F(h["lo"]), F(h["hi"])
+        w = (hi - lo) / k
+        slack = (hi - lo) * Fraction(1, 2 ** 50)
+        esc = k
+        for jj in range(p.size):
+            pj, qj = float(p[jj]), float(q[jj])
+            code = int(res.index[jj])
+            if code == esc:
+                continue
+            d = F(np.float64((qj - pj) / pj))
+            assert lo + code * w - slack <= d <= lo + (code + 1) * w + slack
+            assert abs(F(res.recon[jj]) - F(qj)) <= F(E) * abs(F(pj)) * (1 + Fraction(1, 2 ** 40))
+        out, fl = o.decompress(res, p)
+        assert fl == 0 and np.array_equal(bits(out), bits(res.recon))
+
+
 ALL_PINS = [
     pin_ratio_exact, pin_validity, pin_range_minmax, pin_bins_exact, pin_histogram,
     pin_topk_brute, pin_centred_literal, pin_centred_small_k, pin_all_equal,
     pin_error_bound_exact, pin_escapes_bitexact, pin_packing_bitstring, pin_block_offsets,
     pin_fig2_layout, pin_cmip_cr, pin_roundtrip, pin_decode_flags, pin_empty_and_tiny,
     pin_dp_bound, pin_choose_B_centred, pin_choose_B_invalid, pin_choose_B_ties_lowest,
+    pin_ew_grid, pin_ew_degenerate, pin_ew_membership,
 ]

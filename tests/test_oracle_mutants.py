@@ -52,6 +52,12 @@ MUTANTS = [
     ("chooseB_index_bytes", "+ n * (uint64_t)B +", "+ n * (uint64_t)B / 8 +"),
     ("chooseB_ties_to_larger", "if (bestB == 0 || bits[B] < best) {", "if (bestB == 0 || bits[B] <= best) {"),
     ("chooseB_counts_ascending", "return (x < y) - (x > y);", "return (x > y) - (x < y);"),
+    ("ew_k_plus_one_chunks", "const double w = (hi - lo) / (double)k;",
+     "const double w = (hi - lo) / (double)(k + 1);"),
+    ("ew_centre_lower_edge", "lo + ((double)i + 0.5) * w", "lo + (double)i * w"),
+    ("ew_no_clamp", "i = t < (double)(k - 1) ? (int64_t)t : (int64_t)(k - 1);", "i = (int64_t)t;"),
+    ("ew_anchor_zero", "floor((d[j] - lo) / w)", "floor(d[j] / w)"),
+    ("ew_zero_width_divides", "if (w > 0.0) {", "if (1) {"),
 ]
 
 
