@@ -226,6 +226,36 @@ def auto_b_section(torch, nk, prev, curr, outs_max, ws, reps: int, stream) -> di
     }
 
 
+def equal_width_section(torch, nk, prev, curr, topk_hdr, ws, reps: int, stream) -> dict:
+    """Equal-width binning (Sec. III-B, IV-B-3) on the benchmark pair with the
+    same E and B: the time and input rate of the call, its kernels, and its
+    incompressible count and size against top-k's (the comparison of the
+    binning strategies)."""
+    n = prev.numel()
+    outs = nk.alloc_outputs(n, torch.float64, B)
+    run = lambda: nk.compress_equal_width(prev, curr, E, B, ws=ws, outputs=outs, stream=stream)
+    c = run()
+    torch.cuda.synchronize()
+    h = c.header()
+    t = time_ms(torch, run, reps, stream)
+    nk.timing_enable(True)
+    for _ in range(reps):
+        run()
+    torch.cuda.synchronize()
+    tk = nk.timing_read()
+    nk.timing_enable(False)
+    return {
+        "ms": round(t, 4),
+        "gbs": round(n * 8 / t / 1e6, 1),
+        "kernels_us": {k: round(v[1] / v[0] * 1e3, 1) for k, v in tk.items()},
+        "n_inc": int(h.n_inc),
+        "compressed_bytes": int(h.compressed_bytes),
+        "topk_n_inc": int(topk_hdr.n_inc),
+        "topk_compressed_bytes": int(topk_hdr.compressed_bytes),
+        "size_vs_topk": round(h.compressed_bytes / topk_hdr.compressed_bytes, 3),
+    }
+
+
 def time_ms(torch, fn, reps: int, stream) -> float:
     """Average ms of fn() over reps runs, HIP events on `stream` (after one warm run)."""
     fn()
@@ -505,6 +535,8 @@ def main():
     auto_b = auto_b_section(torch, nk, snaps[0], snaps[1],
                             nk.alloc_outputs(n, torch.float64, 16, device=dev), ws,
                             max(3, args.steps // 3), stream)
+    ew = equal_width_section(torch, nk, snaps[0], snaps[1], step(0).header(), ws,
+                             max(3, args.steps // 3), stream)
     del snaps, ws, outs, c
     torch.cuda.empty_cache()
     batched = None
@@ -543,6 +575,7 @@ def main():
         "latency_ms": {"p50": round(p50, 4), "p99": round(p99, 4)},
         "decompress": dec,
         "auto_b": auto_b,
+        "equal_width": ew,
         "batched": batched,
         "serving": serving,
         "kernels_us": {k: round(v[1] / v[0] * 1e3, 1) for k, v in per_kernel.items()},

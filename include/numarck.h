@@ -144,6 +144,21 @@ numarck_status numarck_compress(const void* prev, const void* curr, uint64_t n,
                                 uint64_t block_bytes, const numarck_out* out, void* ws,
                                 size_t ws_bytes, void* stream);
 
+/* ---- compression with equal-width binning (Sec. III-B, IV-B-3) ----
+ * As numarck_compress, with the k = 2^B - 1 bins cut evenly from the range of
+ * the valid ratios instead of chosen by count: w = (hi - lo) / k, a valid
+ * point's index is min(floor((d - lo) / w), k - 1) (0 when w is 0), the centre
+ * of index i is lo + (i + 1/2) w, and the same verification against E keeps
+ * or escapes every point.  The output format is unchanged, so numarck_decompress
+ * and numarck_decompress_range read it.  Header: M = k_used = k (0 with no
+ * valid point), n_nonzero = tau = tail_count = window_base = 0; bin_ids, if
+ * given, is filled with -1.  Same arguments, errors and workspace as
+ * numarck_compress. */
+numarck_status numarck_compress_equal_width(const void* prev, const void* curr, uint64_t n,
+                                            numarck_dtype dtype, double E, uint32_t B,
+                                            uint64_t block_bytes, const numarck_out* out,
+                                            void* ws, size_t ws_bytes, void* stream);
+
 /* ---- compression with B chosen from the histogram (Sec. IV-B-2, eqs. 5-6) ----
  * As numarck_compress, with the index width chosen in [B_min, B_max]
  * (1 <= B_min <= B_max <= 16): for each B the estimated size

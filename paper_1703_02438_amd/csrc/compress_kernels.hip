@@ -387,6 +387,46 @@ __global__ void k_derive(S src, Geo g) {
 }
 
 // =====================================================================
+// k_ewprep: equal-width binning (Sec. III-B, IV-B-3) -- the range [lo, hi]
+// cut into k = 2^B - 1 chunks of width w = (hi - lo) / k, chunk i's centre
+// lo + (i + 1/2) w; it takes the place of the histogram and the top-k
+// selection, and leaves the control block as the encoder and the header
+// expect it (no fine-bin window, k bins in use when a point is valid)
+// =====================================================================
+template <typename T, typename S>
+__global__ void __launch_bounds__(256) k_ewprep(S src, Geo g) {
+  const CParams& P = src.job(g.job_begin + blockIdx.x);
+  Ctl* c = P.ctl;
+  const unsigned long long n_valid = P.n - c->n_invalid;
+  const bool any = n_valid != 0;
+  const double lo = any ? key_value(c->lo_key) : 0.0;
+  const double hi = any ? key_value(c->hi_key) : 0.0;
+  const double w = (hi - lo) / (double)P.k;
+  T* cen = static_cast<T*>(P.centers);
+  for (uint32_t i = threadIdx.x; i <= P.k; i += blockDim.x)
+    gstore(cen + i, (any && i < P.k) ? (T)(lo + ((double)i + 0.5) * w) : (T)0);
+  if (P.bin_ids)
+    for (uint32_t i = threadIdx.x; i < P.k; i += blockDim.x) gstore(P.bin_ids + i, (int64_t)-1);
+  if (threadIdx.x == 0) {
+    c->n_valid = n_valid;
+    c->lo = lo;
+    c->hi = hi;
+    c->M = any ? (long long)P.k : 0;
+    c->empty = any ? 0u : 1u;
+    c->wbase = 0;
+    c->win_len = 0;
+    c->n_nonzero = 0;
+    c->tau = 0;
+    c->k_used = any ? P.k : 0u;
+    c->nsel_window = 0;
+    c->nsel_tail = 0;
+    c->nsel_tail_below = 0;
+    c->ew_w = w;
+    c->ew_inv = 1.0 / w;
+  }
+}
+
+// =====================================================================
 // k_hist: pass 2, fine histogram
 // =====================================================================
 constexpr int HIST_TPB = NK_HIST_TPB;
@@ -1187,13 +1227,15 @@ __global__ void __launch_bounds__(TR_TPB) k_tailrank(S src, Geo g) {
 // packed stream -- or 0 for any B.
 constexpr int ENC_CTAB = 2048;  // LDS centre table when 2^B <= this
 
-// Waves per SIMD the float64 B = 8 encoders are compiled for (their
+// Waves per SIMD the float64 B = 8 top-k encoders are compiled for (their
 // registers fit five without spilling); others take what they need.
-template <typename T, int PACK>
-constexpr int enc_min_waves = (sizeof(T) == 8 && PACK == 8) ? 5 : 1;
+template <typename T, int PACK, bool EW>
+constexpr int enc_min_waves = (sizeof(T) == 8 && PACK == 8 && !EW) ? 5 : 1;
 
-template <typename T, typename LT, int PACK, typename S, int NT>
-__global__ void __launch_bounds__(UNIT_TPB, (enc_min_waves<T, PACK>)) k_encode(S src, Geo g) {
+// EW: equal-width chunks (k_ewprep) instead of the selected fine bins: a
+// valid point's code is min(floor((d - lo) / w), k - 1), 0 when w is 0.
+template <typename T, typename LT, int PACK, typename S, int NT, bool EW = false>
+__global__ void __launch_bounds__(UNIT_TPB, (enc_min_waves<T, PACK, EW>)) k_encode(S src, Geo g) {
   constexpr int V = Traits<T>::V;
   constexpr int R = ENC_ROUNDS;
   constexpr int WT = R * 64 * V;  // elements of a wave tile
@@ -1230,9 +1272,15 @@ __global__ void __launch_bounds__(UNIT_TPB, (enc_min_waves<T, PACK>)) k_encode(S
   const unsigned nsel_win = empty ? 0u : c->nsel_window;
   const uint32_t esc = P.k;
   const uint32_t B = P.B;
+  // bin width and its reciprocal: 2E, or the equal-width chunk
+  const double bw = EW ? (empty ? 0.0 : c->ew_w) : P.twoE;
+  const double binv = EW ? (empty ? 0.0 : c->ew_inv) : P.inv2E;
+  const bool wzero = !(bw > 0.0);
+  const double kmax_d = (double)(P.k - 1u);
   // with one-byte codes (B <= 8) every centre fits the table
   const bool use_ctab = sizeof(LT) == 1 || ((uint32_t)1 << B) <= (uint32_t)NCTAB;
-  for (int i = tid; i < WIN; i += UNIT_TPB) s_lut[i] = (LT)gload(P.lut + i);
+  if constexpr (!EW)
+    for (int i = tid; i < WIN; i += UNIT_TPB) s_lut[i] = (LT)gload(P.lut + i);
   if (use_ctab) {
     const T* cen = static_cast<const T*>(P.centers);
     for (int i = tid; i < (1 << B); i += UNIT_TPB) s_ctab[i] = (double)gload(cen + i);
@@ -1314,7 +1362,7 @@ __global__ void __launch_bounds__(UNIT_TPB, (enc_min_waves<T, PACK>)) k_encode(S
           double d;
           vb[r][v] = ratio_of((double)pv[r][v], (double)qv[r][v], P.cap, d) & (e0 + v < lim);
           bool sure;
-          mb[r][v] = bin_floor_fast(d - lo, P.inv2E, sure);
+          mb[r][v] = bin_floor_fast(d - lo, binv, sure);
           ex[r][v] = vb[r][v] & !sure;
           need |= ex[r][v];
         }
@@ -1327,7 +1375,7 @@ __global__ void __launch_bounds__(UNIT_TPB, (enc_min_waves<T, PACK>)) k_encode(S
             if (ex[r][v]) {
               double d;
               (void)ratio_of((double)pv[r][v], (double)qv[r][v], P.cap, d);
-              mb[r][v] = floor((d - lo) / P.twoE);
+              mb[r][v] = floor((d - lo) / bw);
             }
       }
     }
@@ -1350,15 +1398,20 @@ __global__ void __launch_bounds__(UNIT_TPB, (enc_min_waves<T, PACK>)) k_encode(S
           valid = ratio_of(p, q, P.cap, d) & inr;
           const double x = d - lo;
           bool sure;
-          m = bin_floor_fast(x, P.inv2E, sure);
+          m = bin_floor_fast(x, binv, sure);
           const bool exact = valid & !sure;
           if (__ballot(exact)) {
-            if (exact) m = floor(x / P.twoE);
+            if (exact) m = floor(x / bw);
           }
         }
+        uint32_t code;
+        if constexpr (EW) {
+          const double mc = (wzero | !valid) ? 0.0 : (m < kmax_d ? m : kmax_d);
+          code = valid ? (uint32_t)mc : esc;
+        } else {
         const double w = m - wbase_d;  // exact
         const bool inwin = valid & (w >= 0.0) & (w < wlen_d);
-        uint32_t code = s_lut[inwin ? (int)w : 0];
+        code = s_lut[inwin ? (int)w : 0];
         code = inwin ? code : esc;
         if (nsel_tail != 0) {  // uniform: selected bins outside the window exist
           const bool tail = valid & !inwin;
@@ -1375,10 +1428,13 @@ __global__ void __launch_bounds__(UNIT_TPB, (enc_min_waves<T, PACK>)) k_encode(S
             }
           }
         }
+        }
         const bool sel = code != esc;
         double cc;
         if (use_ctab) {
           cc = s_ctab[sel ? code : 0u];
+        } else if constexpr (EW) {
+          cc = (double)gload(static_cast<const T*>(P.centers) + (sel ? code : 0u));
         } else {
           cc = centre_of_d<T>(m, lo, P.E);
         }
@@ -1677,6 +1733,15 @@ static void (*encoder_kernel_nt(int cls))(S, Geo) {
     default: return k_encode<T, uint16_t, 16, S, NT>;
   }
 }
+template <typename T, int NT>
+static void (*encoder_kernel_ew_nt(int cls))(OneJob, Geo) {
+  switch (cls) {
+    case 0: return k_encode<T, uint8_t, 0, OneJob, NT, true>;
+    case 1: return k_encode<T, uint8_t, 8, OneJob, NT, true>;
+    case 2: return k_encode<T, uint16_t, 0, OneJob, NT, true>;
+    default: return k_encode<T, uint16_t, 16, OneJob, NT, true>;
+  }
+}
 template <typename T, typename S>
 static void (*encoder_kernel(int cls, uint32_t nt))(S, Geo) {
   if constexpr (std::is_same<S, JobTable>::value)
@@ -1870,6 +1935,56 @@ hipError_t launch_compress_phase(const CParams& P0, const Tuning& tn, hipStream_
                          P.prev == P.curr);
   if (grp.nt == 2) grp.nt = 0;  // one job: its two inputs are one snapshot
   return run_chain(OneJob{P}, base, 1, &grp, 1, &grp, 1, &grp, 1, &grp, 1, tn, s, phases);
+}
+
+hipError_t launch_compress_ew(const CParams& P0, const Tuning& tn, hipStream_t s) {
+  const Geometry G = geometry();
+  CParams P = P0;
+  const int cls = enc_class(P.B);
+  const int occ = encoder_occupancy(P.dtype, cls, false);
+  const uint64_t resident = (uint64_t)G.cus * occ * 4 * tn.unit_pct / 100;
+  P.n_units = range_units(P.n_tiles, (int)(resident < 4 ? 4 : resident));
+  P.tiles_per_unit = (P.n_tiles + P.n_units - 1) / P.n_units;
+  const bool f32 = P.dtype == NUMARCK_F32;
+  Geo g{};
+  g.chunk_vec = chunk_vec_for(tn.chunk_vec, P.n / (f32 ? 4 : 2), G.cus);
+  g.job_begin = 0;
+  g.job_end = 1;
+  g.c_begin = 0;
+  g.c_end = stream_chunks(P.n, P.dtype, g.chunk_vec);
+  g.u_begin = 0;
+  g.u_end = P.n_units;
+  uint32_t nt = stream_nt_for(tn.stream_loads, 2 * P.n * (f32 ? 4 : 8), P.prev == P.curr);
+  g.stream_nt = nt == 1 ? 1u : 0u;
+  const OneJob src{P};
+  NK_LAUNCH(KK_INIT, k_init<OneJob>, 1, 256, src, g);
+  if (g.c_end) {
+    const uint64_t blocks = clamp_blocks(g.c_end, (uint64_t)G.cus * tn.range_blocks_per_cu);
+    if (g.stream_nt == 1) {
+      if (f32) NK_LAUNCH(KK_RANGE, (k_range<float, OneJob, true>), blocks, RNG_TPB, src, g);
+      else NK_LAUNCH(KK_RANGE, (k_range<double, OneJob, true>), blocks, RNG_TPB, src, g);
+    } else {
+      if (f32) NK_LAUNCH(KK_RANGE, (k_range<float, OneJob, false>), blocks, RNG_TPB, src, g);
+      else NK_LAUNCH(KK_RANGE, (k_range<double, OneJob, false>), blocks, RNG_TPB, src, g);
+    }
+  }
+  if (f32) NK_LAUNCH(KK_DERIVE, (k_ewprep<float, OneJob>), 1, 256, src, g);
+  else NK_LAUNCH(KK_DERIVE, (k_ewprep<double, OneJob>), 1, 256, src, g);
+  const uint32_t eblocks = (g.u_end - g.u_begin) / 4;
+  if (eblocks) {
+    void (*k)(OneJob, Geo) =
+        f32 ? (g.stream_nt == 1 ? encoder_kernel_ew_nt<float, 1>(cls)
+                                : encoder_kernel_ew_nt<float, 0>(cls))
+            : (g.stream_nt == 1 ? encoder_kernel_ew_nt<double, 1>(cls)
+                                : encoder_kernel_ew_nt<double, 0>(cls));
+    NK_LAUNCH(KK_ENCODE, k, eblocks, UNIT_TPB, src, g);
+  }
+  NK_LAUNCH(KK_USCAN, k_uscan<OneJob>, 1, USCAN_TPB, src, g);
+  if (eblocks) {
+    if (f32) NK_LAUNCH(KK_GATHER, (k_gather<float, OneJob>), eblocks, UNIT_TPB, src, g);
+    else NK_LAUNCH(KK_GATHER, (k_gather<double, OneJob>), eblocks, UNIT_TPB, src, g);
+  }
+  return hipSuccess;
 }
 
 hipError_t launch_compress_batch(const BatchLaunch& b, hipStream_t s) {

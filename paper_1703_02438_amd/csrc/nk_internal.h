@@ -83,6 +83,8 @@ struct Ctl {
   unsigned int n_inc;             // incompressible points (k_gather)
   // choice of B (k_autob): estimated size in bits per B
   unsigned long long est_bits[17];
+  // equal-width binning (k_ewprep): chunk width and its reciprocal
+  double ew_w, ew_inv;
 };
 
 // Control block of a decompression call.
@@ -302,6 +304,9 @@ hipError_t launch_compress_batch(const BatchLaunch& b, hipStream_t s);
 hipError_t launch_compress_phase(const CParams& P, const Tuning& tn, hipStream_t s,
                                  unsigned phases);
 hipError_t launch_autob(const CParams& P, uint32_t b_lo, uint32_t b_hi, hipStream_t s);
+// One compression with equal-width binning (Sec. III-B, IV-B-3): the range
+// pass, the chunk width and centres, then the same index/pack/gather passes.
+hipError_t launch_compress_ew(const CParams& P, const Tuning& tn, hipStream_t s);
 // Resident workgroups per CU of one encoder specialisation (for sizing units).
 int encoder_occupancy(int dtype, int cls, bool table);
 // Streaming chunks of a job (0 for an empty job, at least 1 otherwise).

@@ -136,6 +136,9 @@ numarck_decompress_workspace_bytes = _bind("numarck_decompress_workspace_bytes",
 numarck_compress = _bind("numarck_compress", _i,
                          [_vp, _vp, _u64, _i, _d, _u32, _u64, ctypes.POINTER(NumarckOut), _vp,
                           _sz, _vp])
+numarck_compress_equal_width = _bind("numarck_compress_equal_width", _i,
+                                     [_vp, _vp, _u64, _i, _d, _u32, _u64,
+                                      ctypes.POINTER(NumarckOut), _vp, _sz, _vp])
 numarck_compress_auto = _bind("numarck_compress_auto", _i,
                               [_vp, _vp, _u64, _i, _d, _u32, _u32, _u64,
                                ctypes.POINTER(NumarckOut), _vp, _sz, _vp,
@@ -296,6 +299,33 @@ def compress(prev: torch.Tensor, curr: torch.Tensor, E: float, B: int, block_byt
                                     ctypes.byref(_tune) if _tune is not False else None,
                                     _stream(stream))
     _check(st, "numarck_compress")
+    return Compressed(o["packed"], o["centers"], o["incomp"], o["block_inc_off"], o["recon"],
+                      o["bin_ids"], o["hdr"], ws, n, prev.dtype)
+
+
+def compress_equal_width(prev: torch.Tensor, curr: torch.Tensor, E: float, B: int,
+                         block_bytes: int = 0, recon: bool = False, bin_ids: bool = False,
+                         ws: torch.Tensor | None = None, outputs: dict | None = None,
+                         stream=None) -> Compressed:
+    """:func:`compress` with equal-width binning (numarck_compress_equal_width):
+    the 2^B - 1 bins cut evenly from the range of the ratios."""
+    if prev.dtype != curr.dtype or prev.numel() != curr.numel():
+        raise ValueError("prev and curr must have the same dtype and size")
+    if not (prev.is_cuda and curr.is_cuda):
+        raise ValueError("prev and curr must be device tensors")
+    prev = prev.reshape(-1)
+    curr = curr.reshape(-1)
+    n = prev.numel()
+    dt = dtype_code(prev.dtype)
+    o = outputs if outputs is not None else alloc_outputs(n, prev.dtype, B, block_bytes, recon,
+                                                          bin_ids, prev.device)
+    if ws is None:
+        ws = torch.empty(numarck_workspace_bytes(n, dt, B), dtype=torch.uint8, device=prev.device)
+    out = out_struct(o)
+    st = numarck_compress_equal_width(_ptr(prev), _ptr(curr), n, dt, float(E), int(B),
+                                      int(block_bytes), ctypes.byref(out), _ptr(ws), ws.numel(),
+                                      _stream(stream))
+    _check(st, "numarck_compress_equal_width")
     return Compressed(o["packed"], o["centers"], o["incomp"], o["block_inc_off"], o["recon"],
                       o["bin_ids"], o["hdr"], ws, n, prev.dtype)
 

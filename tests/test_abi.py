@@ -120,6 +120,21 @@ def test_compress_auto_validation_without_gpu(nk):
     assert call(1, 16, p=p + 8) == nk.EALIGN
 
 
+def test_compress_equal_width_validation_without_gpu(nk):
+    o = _out(nk)
+    ws, big = 0x200000, 1 << 40
+    p, q = 0x300000, 0x400000
+    call = lambda **kw: nk.numarck_compress_equal_width(
+        kw.get("p", p), q, 10, nk.F64, kw.get("E", 1e-3), kw.get("B", 8), 0, ctypes.byref(o),
+        kw.get("ws", ws), big, None)
+    assert call(B=0) == nk.EBITS
+    assert call(B=17) == nk.EBITS
+    assert call(E=0.0) == nk.EBOUND
+    assert call(p=p + 8) == nk.EALIGN
+    assert call(ws=ws + 16) == nk.EALIGN
+    assert call(ws=None) == nk.EINVAL
+
+
 def test_decompress_validation_without_gpu(nk):
     h = _header(nk)
     ws, big = 0x200000, 1 << 30
