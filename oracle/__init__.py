@@ -82,6 +82,8 @@ class Oracle:
                                      ctypes.c_uint32, ctypes.c_uint64, _VP, _VP, _VP, _VP, _VP,
                                      _VP, _VP, ctypes.POINTER(_Info)]
         lib.orc_compress.restype = ctypes.c_int
+        lib.orc_compress_za.argtypes = lib.orc_compress.argtypes
+        lib.orc_compress_za.restype = ctypes.c_int
         lib.orc_compress_ew.argtypes = [_VP, _VP, ctypes.c_uint64, ctypes.c_int, ctypes.c_double,
                                         ctypes.c_uint32, ctypes.c_uint64, _VP, _VP, _VP, _VP, _VP,
                                         _VP, ctypes.POINTER(_Info)]
@@ -143,8 +145,9 @@ class Oracle:
     def compress(self, prev: np.ndarray, curr: np.ndarray, E: float, B: int,
                  block_bytes: int = 0, recon: bool = True,
                  binning: str = "topk") -> "OracleResult":
-        """The whole compression; binning "topk" (Sec. IV-B-1) or "equal_width"
-        (Sec. IV-B-3)."""
+        """The whole compression; binning "topk" (Sec. IV-B-1), "zero_anchored"
+        (top-k over bins centred on multiples of 2E) or "equal_width" (Sec.
+        IV-B-3)."""
         prev, curr, dt = _pair(prev, curr)
         n = prev.size
         T = prev.dtype
@@ -166,6 +169,11 @@ class Oracle:
                                        _p(centers), _p(incomp), _p(blk),
                                        _p(rec) if rec is not None else None, _p(index), _p(sel),
                                        ctypes.byref(info))
+        elif binning == "zero_anchored":
+            st = self.lib.orc_compress_za(_p(prev), _p(curr), n, dt, E, B, block_bytes,
+                                          _p(packed), _p(centers), _p(incomp), _p(blk),
+                                          _p(rec) if rec is not None else None, _p(index),
+                                          _p(sel), ctypes.byref(info))
         elif binning == "equal_width":
             st = self.lib.orc_compress_ew(_p(prev), _p(curr), n, dt, E, B, block_bytes,
                                           _p(packed), _p(centers), _p(incomp), _p(blk),
@@ -181,7 +189,8 @@ class Oracle:
             packed=packed[: h["packed_words"]].copy(), centers=centers,
             incomp=incomp[: h["n_inc"]].copy(), block_inc_off=blk[: h["n_blocks"]].copy(),
             recon=None if rec is None else rec[:n].copy(), index=index[:n].copy(),
-            sel_ids=sel[: h["k_used"]].copy() if binning == "topk" else np.zeros(0, np.int64),
+            sel_ids=(sel[: h["k_used"]].copy() if binning != "equal_width"
+                     else np.zeros(0, np.int64)),
         )
 
     def choose_B(self, prev: np.ndarray, curr: np.ndarray, E: float, b_lo: int = 1,

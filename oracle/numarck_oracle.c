@@ -19,7 +19,9 @@
  *   8. per-block count of earlier incompressible points          (Sec. IV-C)
  *   9. decompression by eq. (4), full and partial                (Sec. III-E, V-C)
  * plus the choice of B by eqs. (5)-(6) (Sec. IV-B-2) and, as an alternative to
- * steps 3-4, equal-width binning (Sec. III-B, IV-B-3).
+ * steps 3-4, equal-width binning (Sec. III-B, IV-B-3); and bins anchored at -E
+ * (centred on multiples of 2E) in place of the smallest ratio, which needs no
+ * range before the histogram.
  *
  * Readings taken where the paper is silent or garbled:
  *   - a point is valid when its previous value is nonzero and finite, the new
@@ -31,6 +33,9 @@
  *   - bin centre c_m = lo + (2m + 1) E in binary64, stored in the snapshot type;
  *   - reconstruction R = T(p * (1 + c)) (the only reading of eq. (4) consistent
  *     with eq. (1)); a point is kept only if |R - q| <= E |p| after rounding;
+ *   - zero-anchored bins: lo is taken as -E, so bin m is floor((d + E) / 2E),
+ *     computed as floor((d - lo) / 2E), with centre lo + (2m + 1) E; the
+ *     header then reports lo = -E, hi = 0 and M = 0 (no range is formed);
  *   - equal-width binning: w = (hi - lo) / k, chunk i = min(floor((d - lo) / w),
  *     k - 1) (0 when w is 0), centre lo + (i + 1/2) w; the rest as above;
  *   - index bits are written least-significant first into a contiguous stream
@@ -369,10 +374,13 @@ static int index_and_pack(const void* prev, const void* curr, uint64_t n, int dt
 
 /* ------------------------------------------------ the whole compression */
 
-int orc_compress(const void* prev, const void* curr, uint64_t n, int dtype, double E,
-                 uint32_t B, uint64_t block_bytes, uint32_t* packed, void* centers,
-                 void* incomp, int64_t* block_inc_off, void* recon, uint16_t* index,
-                 int64_t* sel_ids, orc_info* info) {
+/* Top-k compression with bins anchored at the smallest valid ratio (the
+ * paper's), or, with zero_anchor, at -E: bin m then holds the ratios with
+ * floor((d + E) / 2E) == m and is centred on 2mE. */
+static int compress_topk(const void* prev, const void* curr, uint64_t n, int dtype, double E,
+                         uint32_t B, uint64_t block_bytes, uint32_t* packed, void* centers,
+                         void* incomp, int64_t* block_inc_off, void* recon, uint16_t* index,
+                         int64_t* sel_ids, orc_info* info, int zero_anchor) {
   int st = check_args(dtype, E, B);
   if (st != ORC_OK) return st;
   if (n >= ((uint64_t)1 << 32)) return ORC_EINVAL;
@@ -399,16 +407,20 @@ int orc_compress(const void* prev, const void* curr, uint64_t n, int dtype, doub
   orc_ratio(prev, curr, n, dtype, E, d, valid);
   double lo = 0.0, hi = 0.0;
   uint64_t n_valid = orc_range(d, valid, n, &lo, &hi);
+  if (zero_anchor) {  /* no range: the anchor is fixed, M is not known */
+    lo = -E;
+    hi = 0.0;
+  }
 
   /* steps 3-5 */
   int64_t M = 0, nbins = 0, k_used = 0;
   uint32_t tau = 0;
   if (n_valid > 0) {
     orc_bin_ids(d, valid, n, lo, E, m);
-    M = (int64_t)floor((hi - lo) / (2.0 * E)) + 1;
+    if (!zero_anchor) M = (int64_t)floor((hi - lo) / (2.0 * E)) + 1;
     nbins = orc_histogram(m, valid, n, hid, hcnt);
     k_used = orc_topk(hid, hcnt, nbins, k, sel, &tau);
-  } else {
+  } else if (!zero_anchor) {
     lo = 0.0;
     hi = 0.0;
   }
@@ -437,6 +449,22 @@ int orc_compress(const void* prev, const void* curr, uint64_t n, int dtype, doub
 
   free(d); free(valid); free(m); free(hid); free(hcnt); free(sel); free(idx);
   return st;
+}
+
+int orc_compress(const void* prev, const void* curr, uint64_t n, int dtype, double E,
+                 uint32_t B, uint64_t block_bytes, uint32_t* packed, void* centers,
+                 void* incomp, int64_t* block_inc_off, void* recon, uint16_t* index,
+                 int64_t* sel_ids, orc_info* info) {
+  return compress_topk(prev, curr, n, dtype, E, B, block_bytes, packed, centers, incomp,
+                       block_inc_off, recon, index, sel_ids, info, 0);
+}
+
+int orc_compress_za(const void* prev, const void* curr, uint64_t n, int dtype, double E,
+                    uint32_t B, uint64_t block_bytes, uint32_t* packed, void* centers,
+                    void* incomp, int64_t* block_inc_off, void* recon, uint16_t* index,
+                    int64_t* sel_ids, orc_info* info) {
+  return compress_topk(prev, curr, n, dtype, E, B, block_bytes, packed, centers, incomp,
+                       block_inc_off, recon, index, sel_ids, info, 1);
 }
 
 /* ------------------------------------------------ equal-width binning */

@@ -71,6 +71,15 @@ int64_t orc_histogram(const int64_t* m, const uint8_t* valid, uint64_t n, int64_
 int64_t orc_topk(const int64_t* ids, const uint32_t* counts, int64_t nbins, uint32_t k,
                  int64_t* sel, uint32_t* tau);
 
+/* orc_compress with the fine bins anchored at -E instead of the smallest
+ * valid ratio: bins of width 2E centred on multiples of 2E (bin m holds
+ * floor((d + E) / 2E) == m), so no range is needed before the histogram.
+ * info->lo = -E, info->hi = 0, info->M = 0. */
+int orc_compress_za(const void* prev, const void* curr, uint64_t n, int dtype, double E,
+                    uint32_t B, uint64_t block_bytes, uint32_t* packed, void* centers,
+                    void* incomp, int64_t* block_inc_off, void* recon, uint16_t* index,
+                    int64_t* sel_ids, orc_info* info);
+
 /* Equal-width binning (Sec. III-B, IV-B-3): the compression of orc_compress
  * with the 2^B - 1 bins cut evenly from [lo, hi] instead of the top-k fine
  * bins; same outputs (sel_ids does not apply). */

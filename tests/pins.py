@@ -594,6 +594,79 @@ def pin_ew_membership(o):
         assert fl == 0 and np.array_equal(bits(out), bits(res.recon))
 
 
+def _za_case(counts: dict, E_exp: int = -10, seed: int = 0):
+    """Ratios exactly 2mE for bin m (E a power of two) on previous values
+    +-2^s: with the anchor at -E, bin m = floor((2mE + E) / 2E) = m and its
+    centre -E + (2m + 1)E = 2mE, all exact."""
+    E = 2.0 ** E_exp
+    rng = np.random.default_rng(seed)
+    bins = np.array([m for m, c in sorted(counts.items()) for _ in range(c)], np.int64)
+    rng.shuffle(bins)
+    p = (2.0 ** rng.integers(-3, 4, bins.size)) * np.where(rng.random(bins.size) < 0.3, -1, 1)
+    q = p * (1.0 + 2.0 * bins * E)
+    return p, q, bins, E
+
+
+def pin_za_centred(o):
+    """Zero-anchored bins: ratios 2mE fall in bin m, negative bins included;
+    the 2^B - 1 fullest win, their centres are 2mE, their points reconstruct
+    exactly, the others escape.  Header: lo = -E, hi = 0, M = 0."""
+    p, q, bins, E = _za_case({-3: 5, -1: 30, 0: 50, 1: 30, 4: 2})
+    res = o.compress(p, q, E, 2, binning="zero_anchored")
+    h = res.info
+    assert res.sel_ids.tolist() == [-1, 0, 1]
+    assert h["lo"] == -E and h["hi"] == 0.0 and h["M"] == 0
+    assert h["n_nonzero"] == 5 and h["tau"] == 30 and h["k_used"] == 3 and h["n_inc"] == 7
+    assert res.centers.tolist() == [-2 * E, 0.0, 2 * E, 0.0]
+    want = np.select([bins == -1, bins == 0, bins == 1], [0, 1, 2], 3)
+    assert res.index.tolist() == want.tolist()
+    kept = want != 3
+    assert np.array_equal(bits(res.recon[kept]), bits(q[kept]))
+
+
+def pin_za_signed_ties(o):
+    """Equal counts in bins -2 and 2: the single bin of B = 1 is the lower
+    id, -2 (a tie order on unsigned ids would take 2)."""
+    p, q, _, E = _za_case({-2: 10, 2: 10, 5: 3}, seed=3)
+    res = o.compress(p, q, E, 1, binning="zero_anchored")
+    assert res.sel_ids.tolist() == [-2] and res.info["tau"] == 10
+
+
+def pin_za_edges(o):
+    """Bin edges at odd multiples of E: ratio -E opens bin 0, E - 2^-52
+    stays in bin 0, E opens bin 1, -E - 2^-52 lies in bin -1."""
+    E = 2.0 ** -10
+    p = np.ones(4)
+    q = 1.0 + np.array([-E, E - 2.0 ** -52, E, -E - 2.0 ** -52])
+    res = o.compress(p, q, E, 8, binning="zero_anchored")
+    assert res.sel_ids.tolist() == [-1, 0, 1]
+    assert res.index.tolist() == [1, 1, 2, 0]
+
+
+def pin_za_reduces_to_topk(o):
+    """When the smallest valid ratio is exactly -E, the paper's anchor (the
+    minimum) is -E too: every output equals the top-k compression's except
+    the header's hi and M."""
+    E = 2.0 ** -10
+    rng = np.random.default_rng(8)
+    n = 5000
+    r = np.round(rng.normal(0, 4 * E, n) * 2 ** 20) / 2 ** 20
+    r = np.maximum(r, -E)
+    r[17] = -E
+    p = (2.0 ** rng.integers(-3, 4, n)) * np.where(rng.random(n) < 0.3, -1, 1)
+    q = p * (1.0 + r)
+    a = o.compress(p, q, E, 4, binning="zero_anchored")
+    b = o.compress(p, q, E, 4)
+    assert b.info["lo"] == -E
+    for f in ("n_inc", "n_nonzero", "k_used", "tau", "lo"):
+        assert a.info[f] == b.info[f], f
+    assert np.array_equal(a.packed, b.packed) and np.array_equal(a.sel_ids, b.sel_ids)
+    assert np.array_equal(bits(a.centers), bits(b.centers))
+    assert np.array_equal(bits(a.recon), bits(b.recon))
+    out, fl = o.decompress(a, p)
+    assert fl == 0 and np.array_equal(bits(out), bits(a.recon))
+
+
 ALL_PINS = [
     pin_ratio_exact, pin_validity, pin_range_minmax, pin_bins_exact, pin_histogram,
     pin_topk_brute, pin_centred_literal, pin_centred_small_k, pin_all_equal,
@@ -601,4 +674,5 @@ ALL_PINS = [
     pin_fig2_layout, pin_cmip_cr, pin_roundtrip, pin_decode_flags, pin_empty_and_tiny,
     pin_dp_bound, pin_choose_B_centred, pin_choose_B_invalid, pin_choose_B_ties_lowest,
     pin_ew_grid, pin_ew_degenerate, pin_ew_membership,
+    pin_za_centred, pin_za_signed_ties, pin_za_edges, pin_za_reduces_to_topk,
 ]

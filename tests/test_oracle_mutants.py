@@ -58,6 +58,9 @@ MUTANTS = [
     ("ew_no_clamp", "i = t < (double)(k - 1) ? (int64_t)t : (int64_t)(k - 1);", "i = (int64_t)t;"),
     ("ew_anchor_zero", "floor((d[j] - lo) / w)", "floor(d[j] / w)"),
     ("ew_zero_width_divides", "if (w > 0.0) {", "if (1) {"),
+    ("za_anchor_plus_E", "lo = -E;\n    hi = 0.0;\n  }", "lo = E;\n    hi = 0.0;\n  }"),
+    ("za_anchor_zero", "lo = -E;\n    hi = 0.0;\n  }", "lo = 0.0;\n    hi = 0.0;\n  }"),
+    ("za_keeps_range", "if (zero_anchor) {  /* no range", "if (0) {  /* no range"),
 ]
 
 
