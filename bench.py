@@ -226,14 +226,14 @@ def auto_b_section(torch, nk, prev, curr, outs_max, ws, reps: int, stream) -> di
     }
 
 
-def equal_width_section(torch, nk, prev, curr, topk_hdr, ws, reps: int, stream) -> dict:
-    """Equal-width binning (Sec. III-B, IV-B-3) on the benchmark pair with the
-    same E and B: the time and input rate of the call, its kernels, and its
-    incompressible count and size against top-k's (the comparison of the
-    binning strategies)."""
+def variant_section(torch, nk, fn, prev, curr, topk_hdr, ws, reps: int, stream) -> dict:
+    """Another binning on the benchmark pair with the same E and B (equal-width
+    binning, Sec. III-B, IV-B-3, or the zero-anchored top-k bins): the time
+    and input rate of the call, its kernels, and its incompressible count and
+    size against the paper's top-k."""
     n = prev.numel()
     outs = nk.alloc_outputs(n, torch.float64, B)
-    run = lambda: nk.compress_equal_width(prev, curr, E, B, ws=ws, outputs=outs, stream=stream)
+    run = lambda: fn(prev, curr, E, B, ws=ws, outputs=outs, stream=stream)
     c = run()
     torch.cuda.synchronize()
     h = c.header()
@@ -535,8 +535,11 @@ def main():
     auto_b = auto_b_section(torch, nk, snaps[0], snaps[1],
                             nk.alloc_outputs(n, torch.float64, 16, device=dev), ws,
                             max(3, args.steps // 3), stream)
-    ew = equal_width_section(torch, nk, snaps[0], snaps[1], step(0).header(), ws,
-                             max(3, args.steps // 3), stream)
+    topk_hdr = step(0).header()
+    ew = variant_section(torch, nk, nk.compress_equal_width, snaps[0], snaps[1], topk_hdr, ws,
+                         max(3, args.steps // 3), stream)
+    za = variant_section(torch, nk, nk.compress_zero_anchored, snaps[0], snaps[1], topk_hdr, ws,
+                         max(3, args.steps // 3), stream)
     del snaps, ws, outs, c
     torch.cuda.empty_cache()
     batched = None
@@ -576,6 +579,7 @@ def main():
         "decompress": dec,
         "auto_b": auto_b,
         "equal_width": ew,
+        "zero_anchored": za,
         "batched": batched,
         "serving": serving,
         "kernels_us": {k: round(v[1] / v[0] * 1e3, 1) for k, v in per_kernel.items()},

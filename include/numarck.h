@@ -144,6 +144,23 @@ numarck_status numarck_compress(const void* prev, const void* curr, uint64_t n,
                                 uint64_t block_bytes, const numarck_out* out, void* ws,
                                 size_t ws_bytes, void* stream);
 
+/* ---- compression with zero-anchored bins (two passes instead of three) ----
+ * As numarck_compress, with the fine bins of width 2E (Sec. IV-B-1) anchored
+ * at -E instead of at the smallest valid ratio: bin m holds the ratios with
+ * floor((d + E) / 2E) == m (m may be negative) and is centred on 2mE
+ * (lo + (2m + 1) E with lo = -E).  Without a range to find first, the call
+ * reads the snapshots twice (histogram, then index and pack) rather than
+ * three times.  Top-k, verification, escapes, packing and blocks are
+ * unchanged, and so is the output format: numarck_decompress and
+ * numarck_decompress_range read it.  Header: lo = -E, hi = 0, M = 0;
+ * window_base is the first bin of the on-chip window, -8192.  bin_ids, if
+ * given, holds the selected (signed) bin ids.  Same arguments, errors and
+ * workspace as numarck_compress. */
+numarck_status numarck_compress_zero_anchored(const void* prev, const void* curr, uint64_t n,
+                                              numarck_dtype dtype, double E, uint32_t B,
+                                              uint64_t block_bytes, const numarck_out* out,
+                                              void* ws, size_t ws_bytes, void* stream);
+
 /* ---- compression with equal-width binning (Sec. III-B, IV-B-3) ----
  * As numarck_compress, with the k = 2^B - 1 bins cut evenly from the range of
  * the valid ratios instead of chosen by count: w = (hi - lo) / k, a valid

@@ -331,6 +331,23 @@ numarck_status numarck_compress(const void* prev, const void* curr, uint64_t n,
                                 nullptr, stream);
 }
 
+numarck_status numarck_compress_zero_anchored(const void* prev, const void* curr, uint64_t n,
+                                              numarck_dtype dtype, double E, uint32_t B,
+                                              uint64_t block_bytes, const numarck_out* out,
+                                              void* ws, size_t ws_bytes, void* stream) {
+  const numarck_status st = check_job(prev, curr, n, dtype, E, B, block_bytes, out);
+  if (st != NUMARCK_OK) return st;
+  if (!ws) return NUMARCK_EINVAL;
+  if (((uintptr_t)ws & 255u) != 0) return NUMARCK_EALIGN;
+  const Tuning tn = recorded_tuning((int)dtype, n);
+  Layout L;
+  if (!fit_layout(n, elem_bytes_of(dtype), ws_bytes, &L)) return NUMARCK_ECAPACITY;
+  const CParams P = make_params(prev, curr, n, dtype, E, B, block_bytes, out,
+                                static_cast<char*>(ws), L);
+  const hipError_t e = launch_compress_za(P, tn, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? NUMARCK_OK : hip_fail(e);
+}
+
 numarck_status numarck_compress_equal_width(const void* prev, const void* curr, uint64_t n,
                                             numarck_dtype dtype, double E, uint32_t B,
                                             uint64_t block_bytes, const numarck_out* out,

@@ -387,6 +387,47 @@ __global__ void k_derive(S src, Geo g) {
 }
 
 // =====================================================================
+// zero-anchored bins: the anchor is -E, so no range pass precedes the
+// histogram.  k_zaprep sets the window to the 2^14 bins around ratio 0;
+// k_zafin, after the histogram, counts the valid points (window counts plus
+// the points outside the window).  The header reports lo = -E, hi = 0, M = 0.
+// =====================================================================
+template <typename S>
+__global__ void k_zaprep(S src, Geo g) {
+  if (threadIdx.x != 0) return;
+  const CParams& P = src.job(g.job_begin + blockIdx.x);
+  Ctl* c = P.ctl;
+  c->lo = -P.E;
+  c->hi = 0.0;
+  c->M = 0;
+  c->wbase = -(long long)(WIN / 2);
+  c->win_len = WIN;
+  c->empty = 0;
+}
+
+template <typename S>
+__global__ void __launch_bounds__(256) k_zafin(S src, Geo g) {
+  const CParams& P = src.job(g.job_begin + blockIdx.x);
+  Ctl* c = P.ctl;
+  unsigned long long v = 0;
+  for (int i = threadIdx.x; i < WIN; i += 256) v += gload(P.gwin + i);
+  v = wave_sum_u64(v);
+  __shared__ unsigned long long part[4];
+  if (lane_id() == 0) part[threadIdx.x / 64] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const unsigned long long n_valid = part[0] + part[1] + part[2] + part[3] + c->tail_count;
+    c->n_valid = n_valid;
+    c->n_invalid = P.n - n_valid;
+    if (n_valid == 0) {
+      c->empty = 1;
+      c->win_len = 0;
+      c->wbase = 0;
+    }
+  }
+}
+
+// =====================================================================
 // k_ewprep: equal-width binning (Sec. III-B, IV-B-3) -- the range [lo, hi]
 // cut into k = 2^B - 1 chunks of width w = (hi - lo) / k, chunk i's centre
 // lo + (i + 1/2) w; it takes the place of the histogram and the top-k
@@ -863,8 +904,15 @@ __device__ unsigned sel_kth_count(SelShared& S, unsigned long long mx, unsigned 
   return prefix;
 }
 
+// Bin ids as order-preserving unsigned keys (ids may be negative when the
+// bins are anchored at -E).
+constexpr unsigned long long ID_SIGN = 1ull << 63;
+__device__ __forceinline__ unsigned long long id_key(long long id) {
+  return (unsigned long long)id ^ ID_SIGN;
+}
+
 // The r-th smallest id (1-based) among candidates with count == tau, given
-// the smallest and largest such id.
+// the smallest and largest such id as keys.
 template <typename Visit>
 __device__ long long sel_rth_tie(SelShared& S, unsigned tau, unsigned long long r,
                                  unsigned long long tmin, unsigned long long tmax, Visit visit) {
@@ -878,7 +926,7 @@ __device__ long long sel_rth_tie(SelShared& S, unsigned tau, unsigned long long 
     const unsigned long long hmask =
         (shift + SEL_DIGIT >= 64) ? 0ull : (~0ull << (shift + SEL_DIGIT));
     visit([&](long long id, uint32_t cn) {
-      const unsigned long long rel = (unsigned long long)id - tmin;
+      const unsigned long long rel = id_key(id) - tmin;
       const bool on = cn != 0 && cn == tau && (rel & hmask) == (pre & hmask);
       lds_count(S.hist, on, (unsigned)((rel >> shift) & (SEL_BUCKETS - 1)));
     });
@@ -888,7 +936,7 @@ __device__ long long sel_rth_tie(SelShared& S, unsigned tau, unsigned long long 
     pre |= (unsigned long long)S.bucket << shift;
     __syncthreads();
   }
-  return (long long)(tmin + pre);
+  return (long long)((tmin + pre) ^ ID_SIGN);
 }
 
 // tau and the tie cut over the visited candidates (nz nonzero of them, nz > k).
@@ -902,14 +950,15 @@ __device__ void sel_threshold(SelShared& S, unsigned long long mx, unsigned long
     if (cn > tau) gt += 1;
     if (cn == tau) {
       ties += 1;
-      tmin = (unsigned long long)id < tmin ? (unsigned long long)id : tmin;
-      tmax = (unsigned long long)id > tmax ? (unsigned long long)id : tmax;
+      const unsigned long long key = id_key(id);
+      tmin = key < tmin ? key : tmin;
+      tmax = key > tmax ? key : tmax;
     }
   });
   sel_reduce4(gt, ties, tmin, tmax, S);
   const unsigned long long r = k - gt;  // ties to take, >= 1
   *tau_out = tau;
-  *cut_out = r >= ties ? (long long)tmax : sel_rth_tie(S, tau, r, tmin, tmax, visit);
+  *cut_out = r >= ties ? (long long)(tmax ^ ID_SIGN) : sel_rth_tie(S, tau, r, tmin, tmax, visit);
 }
 
 // The window counts to LDS (16-byte loads, all in flight at once), with the
@@ -1789,6 +1838,10 @@ static uint64_t clamp_blocks(uint64_t want, uint64_t cap) {
 // of jobs.
 // phases: 1 = the passes before top-k (they do not depend on B), 2 = top-k
 // and after.
+// phases bit: the zero-anchored form (k_zaprep in place of the range pass and
+// k_derive, k_zafin after the histogram); one job only
+constexpr unsigned PH_ZA = 8;
+
 template <typename S>
 static hipError_t run_chain(S src, const Geo& base, uint32_t njobs, const JobGroup* rg,
                             uint32_t nrg, const JobGroup* hg, uint32_t nhg, const JobGroup* dg,
@@ -1802,9 +1855,11 @@ static hipError_t run_chain(S src, const Geo& base, uint32_t njobs, const JobGro
                                   : clamp_blocks((uint64_t)G.cus * 2 / njobs, 64) < 8
                                         ? 8
                                         : clamp_blocks((uint64_t)G.cus * 2 / njobs, 64);
+  const bool za = (phases & PH_ZA) != 0;
   if (phases & 1) {
   NK_LAUNCH(KK_INIT, k_init<S>, njobs, 256, src, all);
-  for (uint32_t i = 0; i < nrg; ++i) {
+  if (za) NK_LAUNCH(KK_DERIVE, k_zaprep<S>, njobs, 64, src, all);
+  for (uint32_t i = 0; i < (za ? 0u : nrg); ++i) {
     const Geo g = group_geo(base, rg[i]);
     const uint64_t chunks = g.c_end - g.c_begin;
     if (!chunks) continue;
@@ -1830,7 +1885,7 @@ static hipError_t run_chain(S src, const Geo& base, uint32_t njobs, const JobGro
       else NK_LAUNCH(KK_RANGE, (k_range<double, S, false>), blocks, RNG_TPB, src, g);
     }
   }
-  NK_LAUNCH(KK_DERIVE, k_derive<S>, njobs, 64, src, all);
+  if (!za) NK_LAUNCH(KK_DERIVE, k_derive<S>, njobs, 64, src, all);
   for (uint32_t i = 0; i < nhg; ++i) {
     const Geo g = group_geo(base, hg[i]);
     const uint64_t chunks = g.c_end - g.c_begin;
@@ -1854,6 +1909,7 @@ static hipError_t run_chain(S src, const Geo& base, uint32_t njobs, const JobGro
       else NK_LAUNCH(KK_HIST, (k_hist<double, S, false, 0>), blocks, HIST_TPB, src, g);
     }
   }
+  if (za) NK_LAUNCH(KK_DERIVE, k_zafin<S>, njobs, 256, src, all);
   NK_LAUNCH(KK_HCLEAR, k_hclear<S>, dim3((unsigned)aux, njobs), 256, src, all);
   NK_LAUNCH(KK_HINSERT, k_hinsert<S>, dim3((unsigned)aux, njobs), 256, src, all);
   }
@@ -1935,6 +1991,10 @@ hipError_t launch_compress_phase(const CParams& P0, const Tuning& tn, hipStream_
                          P.prev == P.curr);
   if (grp.nt == 2) grp.nt = 0;  // one job: its two inputs are one snapshot
   return run_chain(OneJob{P}, base, 1, &grp, 1, &grp, 1, &grp, 1, &grp, 1, tn, s, phases);
+}
+
+hipError_t launch_compress_za(const CParams& P, const Tuning& tn, hipStream_t s) {
+  return launch_compress_phase(P, tn, s, 3 | PH_ZA);
 }
 
 hipError_t launch_compress_ew(const CParams& P0, const Tuning& tn, hipStream_t s) {

@@ -85,20 +85,25 @@ __device__ __forceinline__ long long bin_of(double d, double lo, double twoE) {
   return (long long)floor((d - lo) / twoE);
 }
 
-// floor(x / twoE) for x >= 0, as a double, bit-identical to flooring the
-// correctly rounded quotient.  The fast path multiplies by inv = fl(1/twoE):
-// t' = fl(x * inv) is within 2^-51 * t' of t = fl(x / twoE) (three roundings
-// of at most 2^-53 each), so floor(t') == floor(t) unless an integer lies
-// within that distance of t'.  Those cases take the exact division, and so
-// does every x when 2E is subnormal: inv is then infinite, t' infinite or
-// NaN, and the check fails.  (For x below 2^50 * twoE, as every valid ratio
-// gives, t' cannot overflow; a subnormal t' is below 1, where both floors
-// are 0.)
+// floor(x / twoE) for x of either sign, as a double, bit-identical to
+// flooring the correctly rounded quotient.  The fast path multiplies by
+// inv = fl(1/twoE): t' = fl(x * inv) is within 2^-51 |t'| of t = fl(x / twoE)
+// (three roundings of at most 2^-53 each), so floor(t') == floor(t) unless an
+// integer lies within that distance of t'.  Those cases take the exact
+// division, and so does every x when 2E is subnormal: inv is then infinite,
+// t' infinite or NaN, and the check fails.  The distance to the integer
+// below, t' - floor(t'), is exact (Sterbenz) for t' >= 0 and for t' <= -1/2;
+// in (-1/2, 0) it is above 1/2 and only its distance 1 - frac to 0 matters,
+// which is at least |t'| (t and t' then share their sign, so both floors are
+// -1).  For |x| below 2^51 * twoE, as every valid ratio gives, t' cannot
+// overflow, and neither quotient is subnormal: x = d - lo is 0 or, with d a
+// ratio (0 or at least 2^-53 in magnitude) and lo a ratio or -E, at least
+// about 2^-55 * twoE in magnitude.
 __device__ __forceinline__ double bin_floor(double x, double twoE, double inv) {
   const double t = x * inv;
   const double f = floor(t);
-  const double frac = t - f;  // exact (Sterbenz) for t >= 0
-  const double thr = t * 0x1p-49;
+  const double frac = t - f;
+  const double thr = fabs(t) * 0x1p-49;
   if ((frac > thr) && ((1.0 - frac) > thr)) return f;
   return floor(x / twoE);
 }
@@ -109,7 +114,7 @@ __device__ __forceinline__ double bin_floor_fast(double x, double inv, bool& sur
   const double t = x * inv;
   const double f = floor(t);
   const double frac = t - f;
-  const double thr = t * 0x1p-49;
+  const double thr = fabs(t) * 0x1p-49;
   sure = (frac > thr) && ((1.0 - frac) > thr);
   return f;
 }

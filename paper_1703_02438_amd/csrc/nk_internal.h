@@ -304,6 +304,9 @@ hipError_t launch_compress_batch(const BatchLaunch& b, hipStream_t s);
 hipError_t launch_compress_phase(const CParams& P, const Tuning& tn, hipStream_t s,
                                  unsigned phases);
 hipError_t launch_autob(const CParams& P, uint32_t b_lo, uint32_t b_hi, hipStream_t s);
+// One compression with the fine bins anchored at -E (centred on multiples of
+// 2E): no range pass; histogram, top-k and the rest as launch_compress.
+hipError_t launch_compress_za(const CParams& P, const Tuning& tn, hipStream_t s);
 // One compression with equal-width binning (Sec. III-B, IV-B-3): the range
 // pass, the chunk width and centres, then the same index/pack/gather passes.
 hipError_t launch_compress_ew(const CParams& P, const Tuning& tn, hipStream_t s);

@@ -136,6 +136,9 @@ numarck_decompress_workspace_bytes = _bind("numarck_decompress_workspace_bytes",
 numarck_compress = _bind("numarck_compress", _i,
                          [_vp, _vp, _u64, _i, _d, _u32, _u64, ctypes.POINTER(NumarckOut), _vp,
                           _sz, _vp])
+numarck_compress_zero_anchored = _bind("numarck_compress_zero_anchored", _i,
+                                       [_vp, _vp, _u64, _i, _d, _u32, _u64,
+                                        ctypes.POINTER(NumarckOut), _vp, _sz, _vp])
 numarck_compress_equal_width = _bind("numarck_compress_equal_width", _i,
                                      [_vp, _vp, _u64, _i, _d, _u32, _u64,
                                       ctypes.POINTER(NumarckOut), _vp, _sz, _vp])
@@ -303,12 +306,28 @@ def compress(prev: torch.Tensor, curr: torch.Tensor, E: float, B: int, block_byt
                       o["bin_ids"], o["hdr"], ws, n, prev.dtype)
 
 
+def compress_zero_anchored(prev: torch.Tensor, curr: torch.Tensor, E: float, B: int,
+                           block_bytes: int = 0, recon: bool = False, bin_ids: bool = False,
+                           ws: torch.Tensor | None = None, outputs: dict | None = None,
+                           stream=None) -> Compressed:
+    """:func:`compress` with the fine bins anchored at -E, centred on multiples
+    of 2E (numarck_compress_zero_anchored): two passes over the snapshots."""
+    return _compress_variant(numarck_compress_zero_anchored, "numarck_compress_zero_anchored",
+                             prev, curr, E, B, block_bytes, recon, bin_ids, ws, outputs, stream)
+
+
 def compress_equal_width(prev: torch.Tensor, curr: torch.Tensor, E: float, B: int,
                          block_bytes: int = 0, recon: bool = False, bin_ids: bool = False,
                          ws: torch.Tensor | None = None, outputs: dict | None = None,
                          stream=None) -> Compressed:
     """:func:`compress` with equal-width binning (numarck_compress_equal_width):
     the 2^B - 1 bins cut evenly from the range of the ratios."""
+    return _compress_variant(numarck_compress_equal_width, "numarck_compress_equal_width",
+                             prev, curr, E, B, block_bytes, recon, bin_ids, ws, outputs, stream)
+
+
+def _compress_variant(fn, name, prev, curr, E, B, block_bytes, recon, bin_ids, ws, outputs,
+                      stream) -> Compressed:
     if prev.dtype != curr.dtype or prev.numel() != curr.numel():
         raise ValueError("prev and curr must have the same dtype and size")
     if not (prev.is_cuda and curr.is_cuda):
@@ -322,10 +341,9 @@ def compress_equal_width(prev: torch.Tensor, curr: torch.Tensor, E: float, B: in
     if ws is None:
         ws = torch.empty(numarck_workspace_bytes(n, dt, B), dtype=torch.uint8, device=prev.device)
     out = out_struct(o)
-    st = numarck_compress_equal_width(_ptr(prev), _ptr(curr), n, dt, float(E), int(B),
-                                      int(block_bytes), ctypes.byref(out), _ptr(ws), ws.numel(),
-                                      _stream(stream))
-    _check(st, "numarck_compress_equal_width")
+    st = fn(_ptr(prev), _ptr(curr), n, dt, float(E), int(B), int(block_bytes), ctypes.byref(out),
+            _ptr(ws), ws.numel(), _stream(stream))
+    _check(st, name)
     return Compressed(o["packed"], o["centers"], o["incomp"], o["block_inc_off"], o["recon"],
                       o["bin_ids"], o["hdr"], ws, n, prev.dtype)
 

@@ -120,11 +120,13 @@ def test_compress_auto_validation_without_gpu(nk):
     assert call(1, 16, p=p + 8) == nk.EALIGN
 
 
-def test_compress_equal_width_validation_without_gpu(nk):
+@pytest.mark.parametrize("entry", ["numarck_compress_equal_width",
+                                   "numarck_compress_zero_anchored"])
+def test_compress_variant_validation_without_gpu(nk, entry):
     o = _out(nk)
     ws, big = 0x200000, 1 << 40
     p, q = 0x300000, 0x400000
-    call = lambda **kw: nk.numarck_compress_equal_width(
+    call = lambda **kw: getattr(nk, entry)(
         kw.get("p", p), q, 10, nk.F64, kw.get("E", 1e-3), kw.get("B", 8), 0, ctypes.byref(o),
         kw.get("ws", ws), big, None)
     assert call(B=0) == nk.EBITS
