@@ -443,6 +443,9 @@ def main():
                     help="timed runs of each batched-vs-plain comparison (0 = skip)")
     ap.add_argument("--serve-seconds", type=float, default=3.0,
                     help="seconds of Poisson arrivals of the serving measurement (0 = skip)")
+    ap.add_argument("--variant-reps", type=int, default=-1,
+                    help="timed runs of the auto-B, equal-width and zero-anchored sections "
+                         "(-1 = max(3, steps / 3), 0 = skip)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run a 1 GiB device copy first (counter calibration)")
     ap.add_argument("--summarize-pmc", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "KERNEL", "CMD"),
@@ -532,14 +535,17 @@ def main():
     in_bytes = n * 8
     value = in_bytes * args.steps / wall / 1e9
     dec = decompress_section(torch, nk, step(0), snaps[0], args.steps, stream, workload)
-    auto_b = auto_b_section(torch, nk, snaps[0], snaps[1],
-                            nk.alloc_outputs(n, torch.float64, 16, device=dev), ws,
-                            max(3, args.steps // 3), stream)
-    topk_hdr = step(0).header()
-    ew = variant_section(torch, nk, nk.compress_equal_width, snaps[0], snaps[1], topk_hdr, ws,
-                         max(3, args.steps // 3), stream)
-    za = variant_section(torch, nk, nk.compress_zero_anchored, snaps[0], snaps[1], topk_hdr, ws,
-                         max(3, args.steps // 3), stream)
+    vreps = max(3, args.steps // 3) if args.variant_reps < 0 else args.variant_reps
+    auto_b = ew = za = None
+    if vreps > 0:
+        auto_b = auto_b_section(torch, nk, snaps[0], snaps[1],
+                                nk.alloc_outputs(n, torch.float64, 16, device=dev), ws, vreps,
+                                stream)
+        topk_hdr = step(0).header()
+        ew = variant_section(torch, nk, nk.compress_equal_width, snaps[0], snaps[1], topk_hdr,
+                             ws, vreps, stream)
+        za = variant_section(torch, nk, nk.compress_zero_anchored, snaps[0], snaps[1], topk_hdr,
+                             ws, vreps, stream)
     del snaps, ws, outs, c
     torch.cuda.empty_cache()
     batched = None

@@ -419,6 +419,53 @@ class BatchJob:
     tail_cap: int = 0  # 0: n (never overflows)
 
 
+class ClosedLoop:
+    """Closed-loop compression of a time series: each snapshot is compressed
+    against the reconstruction of the one before (which a reader rebuilds
+    from the records), not against the original, so the reconstruction error
+    of every step stays within E of the reconstructed previous value instead
+    of compounding.  Each call is one numarck_compress (or the zero-anchored
+    or equal-width entry) writing its reconstruction, which becomes the next
+    call's previous snapshot; two reconstruction buffers alternate.  The
+    first snapshot is kept as given (the series' full checkpoint)."""
+
+    _FNS = {"topk": "compress", "zero_anchored": "compress_zero_anchored",
+            "equal_width": "compress_equal_width"}
+
+    def __init__(self, first: torch.Tensor, E: float, B: int, block_bytes: int = 0,
+                 binning: str = "topk", stream=None):
+        if binning not in self._FNS:
+            raise ValueError(f"unknown binning {binning}")
+        x = first.reshape(-1)
+        self.E, self.B, self.block_bytes, self.stream = E, B, block_bytes, stream
+        self._fn = globals()[self._FNS[binning]]
+        n = x.numel()
+        self._bufs = [x.clone(), torch.empty_like(x)]
+        self._cur = 0
+        self._ws = torch.empty(numarck_workspace_bytes(n, dtype_code(x.dtype), B),
+                               dtype=torch.uint8, device=x.device)
+
+    @property
+    def reconstruction(self) -> torch.Tensor:
+        """The reconstruction of the latest snapshot (what a reader decodes)."""
+        return self._bufs[self._cur]
+
+    def push(self, curr: torch.Tensor) -> Compressed:
+        """Compress `curr` against the current reconstruction; the returned
+        record's `recon` is the new reconstruction (valid until the call
+        after next)."""
+        prev = self._bufs[self._cur]
+        nxt = self._bufs[1 - self._cur]
+        n = prev.numel()
+        o = alloc_outputs(n, prev.dtype, self.B, self.block_bytes, False, False, prev.device)
+        o["recon"] = nxt
+        c = self._fn(prev, curr.reshape(-1), self.E, self.B, self.block_bytes, ws=self._ws,
+                     outputs=o, stream=self.stream)
+        c.ws = None  # the workspace is reused by the next call
+        self._cur = 1 - self._cur
+        return c
+
+
 class Plan:
     """A batch plan (numarck_plan_*): the jobs' outputs are allocated here (or
     passed in), the descriptors are uploaded once; :meth:`run` launches the
