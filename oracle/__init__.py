@@ -82,6 +82,15 @@ class Oracle:
                                      ctypes.c_uint32, ctypes.c_uint64, _VP, _VP, _VP, _VP, _VP,
                                      _VP, _VP, ctypes.POINTER(_Info)]
         lib.orc_compress.restype = ctypes.c_int
+        lib.orc_lossless_subblocks.argtypes = [ctypes.c_uint64]
+        lib.orc_lossless_subblocks.restype = ctypes.c_uint64
+        lib.orc_lossless_encode.argtypes = [_VP, ctypes.c_uint64, ctypes.c_uint32, _VP,
+                                            ctypes.POINTER(ctypes.c_uint32), _VP, _VP, _VP,
+                                            ctypes.c_uint64, ctypes.POINTER(ctypes.c_uint64)]
+        lib.orc_lossless_encode.restype = ctypes.c_int
+        lib.orc_lossless_decode.argtypes = [_VP, ctypes.c_uint32, _VP, _VP, ctypes.c_uint64,
+                                            ctypes.c_uint32, _VP]
+        lib.orc_lossless_decode.restype = ctypes.c_int
         lib.orc_compress_za.argtypes = lib.orc_compress.argtypes
         lib.orc_compress_za.restype = ctypes.c_int
         lib.orc_compress_ew.argtypes = [_VP, _VP, ctypes.c_uint64, ctypes.c_int, ctypes.c_double,
@@ -205,6 +214,39 @@ class Oracle:
         if st != 0:
             raise ValueError(f"oracle choose_B failed with status {st}")
         return int(B.value), [int(x) for x in bits]
+
+    def lossless_encode(self, packed: np.ndarray, n: int, B: int) -> dict:
+        """Lossless stage of an index table of n B-bit codes: code_of_rank,
+        k, bits_k (total bits of every order k in [0, B]), sub_off (bits) and
+        the stream words."""
+        packed = _nonempty(np.ascontiguousarray(packed, np.uint32), np.uint32)
+        nsub = int(self.lib.orc_lossless_subblocks(n))
+        cor = np.zeros(1 << B, np.uint16)
+        bits_k = np.zeros(B + 1, np.uint64)
+        sub_off = np.zeros(nsub + 1, np.uint64)
+        k = ctypes.c_uint32(0)
+        words = ctypes.c_uint64(0)
+        cap = n * 33 // 32 + nsub + 2
+        stream = np.zeros(max(cap, 1), np.uint32)
+        st = self.lib.orc_lossless_encode(_p(packed), n, B, _p(cor), ctypes.byref(k), _p(bits_k),
+                                          _p(sub_off), _p(stream), stream.size, ctypes.byref(words))
+        if st != 0:
+            raise ValueError(f"oracle lossless_encode failed with status {st}")
+        return {"code_of_rank": cor, "k": int(k.value), "bits_k": [int(x) for x in bits_k],
+                "sub_off": sub_off, "stream": stream[: words.value].copy(), "n": n, "B": B}
+
+    def lossless_decode(self, enc: dict) -> np.ndarray:
+        """The index table (packed words) of a lossless_encode result."""
+        n, B = enc["n"], enc["B"]
+        packed = np.zeros(max((n * B + 31) // 32, 1), np.uint32)
+        stream = _nonempty(enc["stream"], np.uint32)
+        st = self.lib.orc_lossless_decode(_p(np.ascontiguousarray(enc["code_of_rank"], np.uint16)),
+                                          enc["k"], _p(np.ascontiguousarray(enc["sub_off"],
+                                                                            np.uint64)),
+                                          _p(stream), n, B, _p(packed))
+        if st != 0:
+            raise ValueError(f"oracle lossless_decode failed with status {st}")
+        return packed[: (n * B + 31) // 32]
 
     def decompress(self, res: "OracleResult", prev: np.ndarray):
         prev = np.ascontiguousarray(prev)

@@ -19,9 +19,10 @@
  *   8. per-block count of earlier incompressible points          (Sec. IV-C)
  *   9. decompression by eq. (4), full and partial                (Sec. III-E, V-C)
  * plus the choice of B by eqs. (5)-(6) (Sec. IV-B-2) and, as an alternative to
- * steps 3-4, equal-width binning (Sec. III-B, IV-B-3); and bins anchored at -E
+ * steps 3-4, equal-width binning (Sec. III-B, IV-B-3); bins anchored at -E
  * (centred on multiples of 2E) in place of the smallest ratio, which needs no
- * range before the histogram.
+ * range before the histogram; and a lossless stage for the index table (an
+ * exponential-Golomb code over frequency ranks in place of ZLIB, Sec. IV-C).
  *
  * Readings taken where the paper is silent or garbled:
  *   - a point is valid when its previous value is nonzero and finite, the new
@@ -584,3 +585,150 @@ int orc_decompress_range(const orc_info* info, const void* prev, const uint32_t*
     decode_one(info, prev, packed, centers, incomp, start + t, &rank, out, t, flags);
   return ORC_OK;
 }
+
+/* ------------------------------------------------ lossless index stage */
+
+/* The paper follows the index table with a lossless stage (ZLIB per block,
+ * Sec. IV-C and V-A).  This is a tree-free prefix code in its place, so that
+ * every step stays a data-parallel pass:
+ *   - the 2^B codes are ranked by how often they occur in the table (more
+ *     often first, equal counts by the smaller code);
+ *   - the rank v of each code is written as an exponential-Golomb codeword of
+ *     order k: with x = v + 2^k and q = floor(log2 x) - k, q zero bits, a one
+ *     bit, then the low q + k bits of x, least significant first; its length
+ *     is 2 floor(log2 x) - k + 1;
+ *   - k in [0, B] is the order with the fewest bits in total, the smaller k
+ *     on equal totals;
+ *   - the table is cut into sub-blocks of ORC_SUB codes; each sub-block's bits
+ *     start at a 32-bit word (the previous one padded with zeros) and
+ *     sub_off[s] is its first bit, so any sub-block decodes on its own;
+ *   - bits are numbered least significant first within little-endian 32-bit
+ *     words, as in the index table. */
+
+static uint32_t floor_log2_u64(uint64_t x) {
+  uint32_t r = 0;
+  while (x >> (r + 1)) r++;
+  return r;
+}
+
+static uint32_t eg_len(uint64_t v, uint32_t k) {
+  return 2 * floor_log2_u64(v + ((uint64_t)1 << k)) - k + 1;
+}
+
+typedef struct {
+  uint64_t count;
+  uint32_t code;
+} sym_count;
+
+static int cmp_sym(const void* a, const void* b) {
+  const sym_count* x = (const sym_count*)a;
+  const sym_count* y = (const sym_count*)b;
+  if (x->count != y->count) return (x->count < y->count) - (x->count > y->count);
+  return (x->code > y->code) - (x->code < y->code);
+}
+
+static void put_bit(uint32_t* w, uint64_t pos, uint32_t bit) {
+  if (bit) w[pos >> 5] |= 1u << (pos & 31);
+}
+
+static uint32_t get_bit(const uint32_t* w, uint64_t pos) {
+  return (w[pos >> 5] >> (pos & 31)) & 1u;
+}
+
+uint64_t orc_lossless_subblocks(uint64_t n) { return (n + ORC_SUB - 1) / ORC_SUB; }
+
+int orc_lossless_encode(const uint32_t* packed, uint64_t n, uint32_t B, uint16_t* code_of_rank,
+                        uint32_t* k_out, uint64_t* bits_k, uint64_t* sub_off, uint32_t* stream,
+                        uint64_t cap_words, uint64_t* words_out) {
+  if (B < 1 || B > 16 || !code_of_rank || !k_out || !sub_off || !words_out) return ORC_EINVAL;
+  if (n && (!packed || !stream)) return ORC_EINVAL;
+  const uint32_t K = 1u << B;
+  sym_count* sc = (sym_count*)calloc(K, sizeof(sym_count));
+  uint32_t* rank = (uint32_t*)malloc(K * sizeof(uint32_t));
+  if (!sc || !rank) {
+    free(sc); free(rank);
+    return ORC_ENOMEM;
+  }
+  for (uint32_t c = 0; c < K; c++) sc[c].code = c;
+  for (uint64_t j = 0; j < n; j++) sc[get_index(packed, j, B)].count++;
+  /* ranks: more frequent first, ties by the smaller code */
+  qsort(sc, K, sizeof(sym_count), cmp_sym);
+  for (uint32_t r = 0; r < K; r++) {
+    code_of_rank[r] = (uint16_t)sc[r].code;
+    rank[sc[r].code] = r;
+  }
+  /* the order with the fewest bits */
+  uint32_t k = 0;
+  uint64_t best = 0;
+  for (uint32_t kk = 0; kk <= B; kk++) {
+    uint64_t bits = 0;
+    for (uint32_t r = 0; r < K; r++) bits += sc[r].count * eg_len(r, kk);
+    if (bits_k) bits_k[kk] = bits;
+    if (kk == 0 || bits < best) {
+      best = bits;
+      k = kk;
+    }
+  }
+  /* sub-block offsets: each sub-block padded to a whole word */
+  const uint64_t nsub = orc_lossless_subblocks(n);
+  sub_off[0] = 0;
+  for (uint64_t s = 0; s < nsub; s++) {
+    uint64_t bits = 0;
+    const uint64_t e = (s + 1) * ORC_SUB < n ? (s + 1) * ORC_SUB : n;
+    for (uint64_t j = s * ORC_SUB; j < e; j++) bits += eg_len(rank[get_index(packed, j, B)], k);
+    sub_off[s + 1] = sub_off[s] + (bits + 31) / 32 * 32;
+  }
+  const uint64_t words = sub_off[nsub] / 32;
+  *words_out = words;
+  *k_out = k;
+  if (words > cap_words) {
+    free(sc); free(rank);
+    return ORC_EINVAL;
+  }
+  if (words) memset(stream, 0, words * 4);
+  for (uint64_t s = 0; s < nsub; s++) {
+    uint64_t pos = sub_off[s];
+    const uint64_t e = (s + 1) * ORC_SUB < n ? (s + 1) * ORC_SUB : n;
+    for (uint64_t j = s * ORC_SUB; j < e; j++) {
+      const uint64_t x = (uint64_t)rank[get_index(packed, j, B)] + ((uint64_t)1 << k);
+      const uint32_t nb = floor_log2_u64(x); /* x has nb + 1 bits */
+      const uint32_t q = nb - k;
+      pos += q;                              /* q zeros */
+      put_bit(stream, pos++, 1u);            /* the leading one */
+      for (uint32_t b = 0; b < nb; b++) put_bit(stream, pos++, (uint32_t)(x >> b) & 1u);
+    }
+  }
+  free(sc); free(rank);
+  return ORC_OK;
+}
+
+int orc_lossless_decode(const uint16_t* code_of_rank, uint32_t k, const uint64_t* sub_off,
+                        const uint32_t* stream, uint64_t n, uint32_t B, uint32_t* packed) {
+  if (B < 1 || B > 16 || k > B || !code_of_rank || !sub_off) return ORC_EINVAL;
+  if (n && (!stream || !packed)) return ORC_EINVAL;
+  const uint64_t nsub = orc_lossless_subblocks(n);
+  memset(packed, 0, (n * B + 31) / 32 * 4);
+  for (uint64_t s = 0; s < nsub; s++) {
+    uint64_t pos = sub_off[s];
+    const uint64_t end = sub_off[s + 1];
+    const uint64_t e = (s + 1) * ORC_SUB < n ? (s + 1) * ORC_SUB : n;
+    for (uint64_t j = s * ORC_SUB; j < e; j++) {
+      uint32_t q = 0;
+      while (pos < end && !get_bit(stream, pos)) {
+        q++;
+        pos++;
+      }
+      if (pos >= end || q + k > 16) return ORC_EINVAL;
+      pos++; /* the leading one */
+      const uint32_t nb = q + k;
+      if (pos + nb > end) return ORC_EINVAL;
+      uint64_t x = (uint64_t)1 << nb;
+      for (uint32_t b = 0; b < nb; b++) x |= (uint64_t)get_bit(stream, pos++) << b;
+      const uint64_t v = x - ((uint64_t)1 << k);
+      if (v >= ((uint64_t)1 << B)) return ORC_EINVAL;
+      put_index(packed, j, B, code_of_rank[v]);
+    }
+  }
+  return ORC_OK;
+}
+

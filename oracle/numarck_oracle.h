@@ -121,6 +121,24 @@ int orc_decompress_range(const orc_info* info, const void* prev, const uint32_t*
                          const int64_t* block_inc_off, uint64_t start, uint64_t len,
                          void* out, uint32_t* flags);
 
+/* Lossless stage of the index table (in place of the paper's per-block ZLIB,
+ * Sec. IV-C): codes ranked by frequency (ties to the smaller code), ranks
+ * written as exponential-Golomb codewords of the order k in [0, B] with the
+ * fewest bits (ties to the smaller k), in sub-blocks of ORC_SUB codes that
+ * each start on a 32-bit word.  code_of_rank: 2^B entries; bits_k (optional):
+ * B + 1 totals in bits, unpadded; sub_off: n_sub + 1 bit offsets (the last is
+ * the stream's length in bits); stream: cap_words words.  *words_out gets
+ * the stream's words even when they exceed cap_words (then ORC_EINVAL). */
+#define ORC_SUB 4096
+uint64_t orc_lossless_subblocks(uint64_t n);
+int orc_lossless_encode(const uint32_t* packed, uint64_t n, uint32_t B, uint16_t* code_of_rank,
+                        uint32_t* k_out, uint64_t* bits_k, uint64_t* sub_off, uint32_t* stream,
+                        uint64_t cap_words, uint64_t* words_out);
+/* The inverse: the B-bit index table of n codes.  ORC_EINVAL on a corrupt
+ * stream (a codeword past its sub-block, or a rank of 2^B or more). */
+int orc_lossless_decode(const uint16_t* code_of_rank, uint32_t k, const uint64_t* sub_off,
+                        const uint32_t* stream, uint64_t n, uint32_t B, uint32_t* packed);
+
 #ifdef __cplusplus
 }
 #endif

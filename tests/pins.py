@@ -667,6 +667,99 @@ def pin_za_reduces_to_topk(o):
     assert fl == 0 and np.array_equal(bits(out), bits(a.recon))
 
 
+def _pack_codes(codes, B):
+    """Pack B-bit codes LSB-first into 32-bit words, character by character."""
+    bitstr = "".join(format(int(c), f"0{B}b")[::-1] for c in codes)
+    return _words_of(bitstr)
+
+
+def _words_of(bitstr):
+    bitstr = bitstr + "0" * (-len(bitstr) % 32)
+    return np.array([int(bitstr[i:i + 32][::-1], 2) for i in range(0, len(bitstr), 32)], np.uint32)
+
+
+def _eg_len(v, k):
+    """Exponential-Golomb codeword length of order k: 2 * bits(v + 2^k) - 1 - k."""
+    return 2 * (v + (1 << k)).bit_length() - 1 - k
+
+
+def pin_lossless_literal(o):
+    """Lossless index stage on hand-worked tables.  Codes [0, 0, 1, 2, 0]
+    (B = 2): ranks 0, 1, 2, order 0 (9 bits; order 1 12, order 2 15), stream
+    1 1 010 011 1 = 459.  Codes 5x5, 2x4, 7x3, 0x2, 1x1 (B = 3): ranks
+    5->0, 2->1, 7->2, 0->3, 1->4 and the unused codes after them in code
+    order; order 0 (41 bits against 42, 47, 60); codewords 1, 010, 011,
+    00100, 00110 (the bits of x after its leading one least significant
+    first)."""
+    e = o.lossless_encode(_pack_codes([0, 0, 1, 2, 0], 2), 5, 2)
+    assert e["code_of_rank"].tolist() == [0, 1, 2, 3] and e["k"] == 0
+    assert e["bits_k"] == [9, 12, 15] and e["sub_off"].tolist() == [0, 32]
+    assert e["stream"].tolist() == [459]
+    codes = [5] * 5 + [2] * 4 + [7] * 3 + [0] * 2 + [1]
+    e = o.lossless_encode(_pack_codes(codes, 3), len(codes), 3)
+    assert e["code_of_rank"].tolist() == [5, 2, 7, 0, 1, 3, 4, 6]
+    assert e["k"] == 0 and e["bits_k"] == [41, 42, 47, 60]
+    want = _words_of("1" * 5 + "010" * 4 + "011" * 3 + "00100" * 2 + "00110")
+    assert e["stream"].tolist() == want.tolist() and e["sub_off"].tolist() == [0, 64]
+    assert np.array_equal(o.lossless_decode(e), _pack_codes(codes, 3))
+    # equal totals: two codes, five each, cost 5 * 1 + 5 * 3 = 20 bits at
+    # order 0 and 5 * 2 + 5 * 2 = 20 at order 1; the smaller order is taken
+    e = o.lossless_encode(_pack_codes([0, 1] * 5, 1), 10, 1)
+    assert e["bits_k"] == [20, 20] and e["k"] == 0
+
+
+def pin_lossless_structure(o):
+    """On random tables crossing sub-block boundaries (B = 1, 5, 8, 13, 16):
+    ranks order the codes by count (ties by code), every order's total is
+    the sum of textbook exponential-Golomb lengths, the chosen order has
+    the fewest bits (the smaller on ties), each sub-block is its bits
+    rounded up to a word, the total is at least the table's entropy, and
+    decoding returns the table."""
+    rng = np.random.default_rng(61)
+    S = 4096
+    for B, n in ((1, 3 * S + 17), (5, 2 * S), (8, 5 * S + 1), (13, S + 3), (16, 2 * S + 99)):
+        K = 1 << B
+        w = rng.pareto(1.2, K) + 1e-3
+        codes = rng.choice(K, n, p=w / w.sum())
+        e = o.lossless_encode(_pack_codes(codes, B), n, B)
+        cnt = np.bincount(codes, minlength=K)
+        order = sorted(range(K), key=lambda c: (-cnt[c], c))
+        assert e["code_of_rank"].tolist() == order
+        rank = np.empty(K, np.int64)
+        rank[order] = np.arange(K)
+        tot = [sum(int(cnt[c]) * _eg_len(int(rank[c]), k) for c in range(K) if cnt[c])
+               for k in range(B + 1)]
+        assert e["bits_k"] == tot
+        k = e["k"]
+        assert tot[k] == min(tot) and all(t > tot[k] for t in tot[:k])
+        lens = np.array([_eg_len(int(r), k) for r in rank[codes]])
+        sub = [int(lens[i:i + S].sum()) for i in range(0, n, S)]
+        off = np.concatenate([[0], np.cumsum([(b + 31) // 32 * 32 for b in sub])])
+        assert e["sub_off"].tolist() == off.tolist()
+        pr = cnt[cnt > 0] / n
+        assert tot[k] >= -(cnt[cnt > 0] * np.log2(pr)).sum() - 1e-6
+        assert np.array_equal(o.lossless_decode(e), _pack_codes(codes, B))
+
+
+def pin_lossless_single_symbol_and_corrupt(o):
+    """One symbol only: rank 0, order 0, one bit per code; an empty table;
+    and a stream cut short is refused."""
+    n = 4096 + 5
+    e = o.lossless_encode(_pack_codes([3] * n, 4), n, 4)
+    assert e["k"] == 0 and e["code_of_rank"][0] == 3 and e["sub_off"].tolist() == [0, 4096, 4128]
+    assert e["stream"][:128].tolist() == [0xFFFFFFFF] * 128 and e["stream"][128] == 0x1F
+    e0 = o.lossless_encode(np.zeros(0, np.uint32), 0, 6)
+    assert e0["sub_off"].tolist() == [0] and e0["stream"].size == 0
+    bad = dict(e)
+    bad["stream"] = np.zeros_like(e["stream"])
+    try:
+        o.lossless_decode(bad)
+    except ValueError:
+        pass
+    else:
+        raise AssertionError("a stream of zeros decoded")
+
+
 ALL_PINS = [
     pin_ratio_exact, pin_validity, pin_range_minmax, pin_bins_exact, pin_histogram,
     pin_topk_brute, pin_centred_literal, pin_centred_small_k, pin_all_equal,
@@ -675,4 +768,5 @@ ALL_PINS = [
     pin_dp_bound, pin_choose_B_centred, pin_choose_B_invalid, pin_choose_B_ties_lowest,
     pin_ew_grid, pin_ew_degenerate, pin_ew_membership,
     pin_za_centred, pin_za_signed_ties, pin_za_edges, pin_za_reduces_to_topk,
+    pin_lossless_literal, pin_lossless_structure, pin_lossless_single_symbol_and_corrupt,
 ]

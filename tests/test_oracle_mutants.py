@@ -61,6 +61,18 @@ MUTANTS = [
     ("za_anchor_plus_E", "lo = -E;\n    hi = 0.0;\n  }", "lo = E;\n    hi = 0.0;\n  }"),
     ("za_anchor_zero", "lo = -E;\n    hi = 0.0;\n  }", "lo = 0.0;\n    hi = 0.0;\n  }"),
     ("za_keeps_range", "if (zero_anchor) {  /* no range", "if (0) {  /* no range"),
+    ("ll_rank_ties_higher", "return (x->code > y->code) - (x->code < y->code);",
+     "return (x->code < y->code) - (x->code > y->code);"),
+    ("ll_rank_rare_first",
+     "if (x->count != y->count) return (x->count < y->count) - (x->count > y->count);",
+     "if (x->count != y->count) return (x->count > y->count) - (x->count < y->count);"),
+    ("ll_length_plus_one", "return 2 * floor_log2_u64(v + ((uint64_t)1 << k)) - k + 1;",
+     "return 2 * floor_log2_u64(v + ((uint64_t)1 << k)) - k + 2;"),
+    ("ll_k_ties_larger", "if (kk == 0 || bits < best) {", "if (kk == 0 || bits <= best) {"),
+    ("ll_no_padding", "sub_off[s + 1] = sub_off[s] + (bits + 31) / 32 * 32;",
+     "sub_off[s + 1] = sub_off[s] + bits;"),
+    ("ll_msb_first", "put_bit(stream, pos++, (uint32_t)(x >> b) & 1u);",
+     "put_bit(stream, pos++, (uint32_t)(x >> (nb - 1 - b)) & 1u);"),
 ]
 
 
