@@ -256,6 +256,36 @@ def variant_section(torch, nk, fn, prev, curr, topk_hdr, ws, reps: int, stream) 
     }
 
 
+def lossless_section(torch, nk, c, n: int, reps: int, stream) -> dict:
+    """The lossless stage on the benchmark pair's index table: encode and
+    decode times, and the stored size against the packed table's."""
+    ws = torch.empty(nk.numarck_lossless_workspace_bytes(B), dtype=torch.uint8, device="cuda")
+    e = nk.lossless_encode(c.packed, n, B, ws=ws, stream=stream)
+    h = e.header()
+    t_enc = time_ms(torch, lambda: nk.lossless_encode(c.packed, n, B, ws=ws, stream=stream),
+                    reps, stream)
+    out = torch.empty_like(c.packed)
+    t_dec = time_ms(torch, lambda: nk.lossless_decode(e, out=out, stream=stream), reps, stream)
+    _, fl = nk.lossless_decode(e, out=out, stream=stream)
+    words = (n * B + 31) // 32
+    assert int(fl.item()) == 0 and torch.equal(out[:words], c.packed[:words])
+    hdr = c.header()
+    packed_bytes = int(hdr.packed_bytes)
+    file_plain = int(hdr.compressed_bytes)
+    file_ll = file_plain - packed_bytes + int(h.bytes)
+    return {
+        "order_k": int(h.k),
+        "bits_per_code": round(h.bits / n, 3),
+        "index_bytes": packed_bytes,
+        "lossless_bytes": int(h.bytes),
+        "index_ratio": round(packed_bytes / h.bytes, 3),
+        "file_cr_without": round(n * 8 / file_plain, 3),
+        "file_cr_with": round(n * 8 / file_ll, 3),
+        "encode_ms": round(t_enc, 4),
+        "decode_ms": round(t_dec, 4),
+    }
+
+
 def time_ms(torch, fn, reps: int, stream) -> float:
     """Average ms of fn() over reps runs, HIP events on `stream` (after one warm run)."""
     fn()
@@ -536,8 +566,9 @@ def main():
     value = in_bytes * args.steps / wall / 1e9
     dec = decompress_section(torch, nk, step(0), snaps[0], args.steps, stream, workload)
     vreps = max(3, args.steps // 3) if args.variant_reps < 0 else args.variant_reps
-    auto_b = ew = za = None
+    auto_b = ew = za = ll = None
     if vreps > 0:
+        ll = lossless_section(torch, nk, step(0), n, vreps, stream)
         auto_b = auto_b_section(torch, nk, snaps[0], snaps[1],
                                 nk.alloc_outputs(n, torch.float64, 16, device=dev), ws, vreps,
                                 stream)
@@ -586,6 +617,7 @@ def main():
         "auto_b": auto_b,
         "equal_width": ew,
         "zero_anchored": za,
+        "lossless": ll,
         "batched": batched,
         "serving": serving,
         "kernels_us": {k: round(v[1] / v[0] * 1e3, 1) for k, v in per_kernel.items()},

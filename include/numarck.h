@@ -69,6 +69,7 @@ typedef enum {
 /* Bits of numarck_header.flags (compression) and of the decompression flag word. */
 #define NUMARCK_FLAG_BAD_INDEX 1u     /* decompression met an index in [k_used, 2^B - 1) */
 #define NUMARCK_FLAG_INC_OVERRUN 2u   /* decompression met more escapes than n_inc */
+#define NUMARCK_FLAG_BAD_STREAM 8u    /* lossless decoding met a corrupt codeword stream */
 #define NUMARCK_FLAG_TAIL_OVERFLOW 4u /* compression: more points outside the on-chip bin
                                          window than the workspace's tail capacity; the
                                          outputs of that call are not valid */
@@ -428,6 +429,65 @@ const char* numarck_last_error(void);
  * clears the records.  Not thread-safe; disabled by default. */
 void numarck_timing_enable(int on);
 int numarck_timing_read(const char** names, uint32_t* launches, double* ms, int cap);
+
+/* ---- lossless stage of the index table (in place of Sec. IV-C's ZLIB) ----
+ * The paper passes each block of the index table through ZLIB.  This stage is
+ * a prefix code without a tree, every step a pass on the device:
+ *   - the 2^B codes are ranked by how often they occur in the table (more
+ *     often first, equal counts by the smaller code); code_of_rank lists them;
+ *   - rank v is written as an exponential-Golomb codeword of order k: with
+ *     x = v + 2^k and nb = floor(log2 x), nb - k zero bits, a one bit, then the
+ *     low nb bits of x least significant first (2 nb - k + 1 bits);
+ *   - k in [0, B] is the order with the fewest bits (the smaller k on ties);
+ *   - sub-blocks of 4096 codes each start on a 32-bit word (the one before is
+ *     padded with zeros); sub_off[s] is the first bit of sub-block s and
+ *     sub_off[n_sub] the stream's length in bits, so any sub-block decodes on
+ *     its own;
+ *   - bits are numbered least significant first in little-endian words. */
+typedef struct numarck_lossless_header {
+  uint64_t n;            /* codes in the table */
+  uint64_t n_sub;        /* sub-blocks: ceil(n / 4096) */
+  uint64_t stream_words; /* 32-bit words of the codeword stream */
+  uint64_t bits;         /* codeword bits, without the sub-block padding */
+  uint32_t B;            /* index width */
+  uint32_t k;            /* exponential-Golomb order */
+  uint32_t flags;        /* 0 */
+  uint32_t reserved;
+  uint64_t bytes;        /* stored size: 2 * 2^B + 8 (n_sub + 1) + 4 stream_words + this header */
+} numarck_lossless_header;
+
+/* Sub-blocks of a table of n codes: ceil(n / 4096). */
+uint64_t numarck_lossless_subblocks(uint64_t n);
+/* Stream bytes that always suffice: 4 (ceil(n (B + 1) / 32) + n_sub).  (Order
+ * k = B costs at most B + 1 bits per code, and the chosen order no more.) */
+size_t numarck_lossless_stream_bytes(uint64_t n, uint32_t B);
+/* Workspace bytes of numarck_lossless_encode. */
+size_t numarck_lossless_workspace_bytes(uint32_t B);
+
+/* Encode the index table `packed` (n codes of B bits, device) into
+ * code_of_rank (2^B uint16), sub_off (n_sub + 1 uint64, bits) and stream
+ * (stream_bytes >= numarck_lossless_stream_bytes(n, B)); hdr is a device
+ * numarck_lossless_header.  All device buffers, written in full; the call
+ * only enqueues work on `stream_`.  Errors: NUMARCK_EBITS (B), NUMARCK_EINVAL
+ * (NULL pointer, n >= 2^32), NUMARCK_ECAPACITY (stream or workspace too
+ * small), NUMARCK_EHIP. */
+numarck_status numarck_lossless_encode(const uint32_t* packed, uint64_t n, uint32_t B,
+                                       uint16_t* code_of_rank, uint64_t* sub_off,
+                                       uint32_t* stream, size_t stream_bytes,
+                                       numarck_lossless_header* hdr, void* ws, size_t ws_bytes,
+                                       void* stream_);
+/* Decode back to the B-bit index table `packed` ((n B + 31) / 32 words,
+ * device).  hdr is a HOST copy of the encoder's header; the other pointers
+ * are device buffers; flags (device uint32) is set to 0, then ORed with
+ * NUMARCK_FLAG_BAD_STREAM if a sub-block's offsets or codewords are corrupt
+ * (that sub-block's codes are then incomplete).  Reads stay within the
+ * stream's hdr->stream_words words and writes within the table.  Errors:
+ * NUMARCK_EBITS, NUMARCK_EINVAL (NULL pointer, inconsistent header),
+ * NUMARCK_EHIP. */
+numarck_status numarck_lossless_decode(const numarck_lossless_header* hdr,
+                                       const uint16_t* code_of_rank, const uint64_t* sub_off,
+                                       const uint32_t* stream, uint32_t* packed, uint32_t* flags,
+                                       void* stream_);
 
 #ifdef __cplusplus
 }

@@ -331,6 +331,72 @@ numarck_status numarck_compress(const void* prev, const void* curr, uint64_t n,
                                 nullptr, stream);
 }
 
+uint64_t numarck_lossless_subblocks(uint64_t n) { return (n + LL_SUB_CODES - 1) / LL_SUB_CODES; }
+
+size_t numarck_lossless_stream_bytes(uint64_t n, uint32_t B) {
+  if (B < 1 || B > 16) return 0;
+  return 4 * ((n * (B + 1) + 31) / 32 + numarck_lossless_subblocks(n));
+}
+
+size_t numarck_lossless_workspace_bytes(uint32_t B) {
+  if (B < 1 || B > 16) return 0;
+  return align256((size_t)8 << B) + 256;
+}
+
+numarck_status numarck_lossless_encode(const uint32_t* packed, uint64_t n, uint32_t B,
+                                       uint16_t* code_of_rank, uint64_t* sub_off,
+                                       uint32_t* stream, size_t stream_bytes,
+                                       numarck_lossless_header* hdr, void* ws, size_t ws_bytes,
+                                       void* stream_) {
+  if (B < 1 || B > 16) return NUMARCK_EBITS;
+  if (n >= ((uint64_t)1 << 32) || !code_of_rank || !sub_off || !hdr || !ws ||
+      (n && (!packed || !stream)))
+    return NUMARCK_EINVAL;
+  if (stream_bytes < numarck_lossless_stream_bytes(n, B) ||
+      ws_bytes < numarck_lossless_workspace_bytes(B))
+    return NUMARCK_ECAPACITY;
+  char* base = static_cast<char*>(ws);
+  LLParams p{};
+  p.packed = packed;
+  p.n = n;
+  p.n_sub = numarck_lossless_subblocks(n);
+  p.B = B;
+  p.counts = reinterpret_cast<uint32_t*>(base);
+  p.rank_of = reinterpret_cast<uint32_t*>(base + ((size_t)4 << B));
+  p.bits_k = reinterpret_cast<unsigned long long*>(base + align256((size_t)8 << B));
+  p.order = reinterpret_cast<uint32_t*>(base + align256((size_t)8 << B) + 17 * 8);
+  p.code_of_rank = code_of_rank;
+  p.sub_off = sub_off;
+  p.stream = stream;
+  p.hdr = hdr;
+  const hipError_t e = launch_lossless_encode(p, static_cast<hipStream_t>(stream_));
+  return e == hipSuccess ? NUMARCK_OK : hip_fail(e);
+}
+
+numarck_status numarck_lossless_decode(const numarck_lossless_header* hdr,
+                                       const uint16_t* code_of_rank, const uint64_t* sub_off,
+                                       const uint32_t* stream, uint32_t* packed, uint32_t* flags,
+                                       void* stream_) {
+  if (!hdr || !code_of_rank || !sub_off || !flags) return NUMARCK_EINVAL;
+  if (hdr->B < 1 || hdr->B > 16) return NUMARCK_EBITS;
+  if (hdr->n >= ((uint64_t)1 << 32) || hdr->k > hdr->B ||
+      hdr->n_sub != numarck_lossless_subblocks(hdr->n) || (hdr->n && (!stream || !packed)))
+    return NUMARCK_EINVAL;
+  LLDecodeParams p{};
+  p.n = hdr->n;
+  p.n_sub = hdr->n_sub;
+  p.stream_words = hdr->stream_words;
+  p.B = hdr->B;
+  p.k = hdr->k;
+  p.code_of_rank = code_of_rank;
+  p.sub_off = sub_off;
+  p.stream = stream;
+  p.packed = packed;
+  p.flags = flags;
+  const hipError_t e = launch_lossless_decode(p, static_cast<hipStream_t>(stream_));
+  return e == hipSuccess ? NUMARCK_OK : hip_fail(e);
+}
+
 numarck_status numarck_compress_zero_anchored(const void* prev, const void* curr, uint64_t n,
                                               numarck_dtype dtype, double E, uint32_t B,
                                               uint64_t block_bytes, const numarck_out* out,

@@ -1,0 +1,335 @@
+// lossless_kernels.hip -- lossless stage of the index table.
+//
+// The paper passes each block of the index table through ZLIB (Sec. IV-C,
+// V-A).  Here a prefix code without a tree takes its place, so that every
+// step is a data-parallel pass:
+//   - the 2^B codes are ranked by how often they occur (more often first,
+//     equal counts by the smaller code);
+//   - a rank v is written as an exponential-Golomb codeword of order k: with
+//     x = v + 2^k and nb = floor(log2 x), nb - k zero bits, a one bit, then
+//     the low nb bits of x least significant first (2 nb - k + 1 bits);
+//   - k in [0, B] is the order with the fewest bits in total (the smaller k on
+//     equal totals);
+//   - sub-blocks of LL_SUB codes start on 32-bit words (the previous one is
+//     padded with zeros), and sub_off[s] is the first bit of sub-block s, so
+//     any sub-block decodes on its own.
+// Bits are numbered least significant first in little-endian 32-bit words,
+// as in the index table.
+//
+// Encode: k_llclear, k_llhist (code counts), k_llrank (rank of every code by
+// counting the codes before it), k_llorder (bits of every order, the
+// choice), k_llsub (bits of every sub-block), k_llscan (offsets and the
+// header), k_llwrite.  Decode: k_llflags, k_lldecode.  The per-sub-block
+// passes give each sub-block to one lane, which walks its codes in order.
+#include "nk_device.h"
+
+namespace nk {
+
+constexpr int LL_SUB = 4096;        // codes per sub-block
+constexpr int LL_TPB = 256;
+constexpr int LL_LDS_BINS = 8192;   // code counts kept in LDS up to this many codes
+constexpr int LL_ORD_TPB = 1024;
+constexpr int LL_SCAN_TPB = 1024;
+
+__device__ __forceinline__ uint32_t ll_log2(uint32_t x) { return 31u - (uint32_t)__clz(x); }
+
+__device__ __forceinline__ uint32_t ll_len(uint32_t v, uint32_t k) {
+  return 2u * ll_log2(v + (1u << k)) - k + 1u;
+}
+
+// Code j of a B-bit table (the word after j's first word exists whenever the
+// code reaches into it).
+__device__ __forceinline__ uint32_t ll_code(const uint32_t* __restrict__ packed, uint64_t j,
+                                            uint32_t B) {
+  const uint64_t bit = j * B;
+  const uint64_t w = bit >> 5;
+  const uint32_t sh = (uint32_t)(bit & 31);
+  uint32_t v = packed[w] >> sh;
+  if (sh + B > 32) v |= packed[w + 1] << (32 - sh);
+  return v & ((1u << B) - 1u);
+}
+
+// Sequential reader of B-bit codes from word `w` on.
+struct CodeReader {
+  const uint32_t* p;
+  uint64_t w;
+  unsigned long long buf;
+  uint32_t nbits;
+  __device__ __forceinline__ uint32_t next(uint32_t B) {
+    if (nbits < B) {
+      buf |= (unsigned long long)p[w++] << nbits;
+      nbits += 32;
+    }
+    const uint32_t c = (uint32_t)buf & ((1u << B) - 1u);
+    buf >>= B;
+    nbits -= B;
+    return c;
+  }
+};
+
+__global__ void __launch_bounds__(LL_TPB) k_llclear(LLParams p) {
+  const uint32_t K = 1u << p.B;
+  const uint32_t i = blockIdx.x * LL_TPB + threadIdx.x;
+  if (i < K) p.counts[i] = 0u;
+  if (i < 17) p.bits_k[i] = 0ull;
+}
+
+__global__ void __launch_bounds__(LL_TPB) k_llhist(LLParams p) {
+  __shared__ uint32_t h[LL_LDS_BINS];
+  const uint32_t K = 1u << p.B;
+  const bool lds = K <= (uint32_t)LL_LDS_BINS;
+  if (lds) {
+    for (uint32_t i = threadIdx.x; i < K; i += LL_TPB) h[i] = 0u;
+    __syncthreads();
+  }
+  // the loop bound is the workgroup's: lds_count needs the whole wave
+  for (uint64_t base = (uint64_t)blockIdx.x * LL_TPB; base < p.n;
+       base += (uint64_t)gridDim.x * LL_TPB) {
+    const uint64_t j = base + threadIdx.x;
+    const bool on = j < p.n;
+    const uint32_t c = on ? ll_code(p.packed, j, p.B) : 0u;
+    if (lds) lds_count(h, on, c);
+    else if (on) atomicAdd(&p.counts[c], 1u);
+  }
+  if (lds) {
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < K; i += LL_TPB)
+      if (h[i]) atomicAdd(&p.counts[i], h[i]);
+  }
+}
+
+// rank(c) = #codes with a larger count, or the same count and a smaller code.
+__global__ void __launch_bounds__(LL_TPB) k_llrank(LLParams p) {
+  __shared__ uint32_t tile[LL_TPB];
+  const uint32_t K = 1u << p.B;
+  const uint32_t c = blockIdx.x * LL_TPB + threadIdx.x;
+  const uint32_t mine = c < K ? p.counts[c] : 0u;
+  uint32_t r = 0;
+  for (uint32_t t0 = 0; t0 < K; t0 += LL_TPB) {
+    __syncthreads();
+    tile[threadIdx.x] = t0 + threadIdx.x < K ? p.counts[t0 + threadIdx.x] : 0u;
+    __syncthreads();
+    const uint32_t lim = K - t0 < (uint32_t)LL_TPB ? K - t0 : (uint32_t)LL_TPB;
+    for (uint32_t i = 0; i < lim; ++i) {
+      const uint32_t o = tile[i];
+      r += (o > mine || (o == mine && t0 + i < c)) ? 1u : 0u;
+    }
+  }
+  if (c < K) {
+    p.rank_of[c] = r;
+    p.code_of_rank[r] = (uint16_t)c;
+  }
+}
+
+// Total bits of every order k in [0, B]; the order with the fewest.
+__global__ void __launch_bounds__(LL_ORD_TPB) k_llorder(LLParams p) {
+  __shared__ unsigned long long part[LL_ORD_TPB / 64][17];
+  const uint32_t K = 1u << p.B;
+  unsigned long long acc[17];
+#pragma unroll
+  for (int k = 0; k < 17; ++k) acc[k] = 0ull;
+  for (uint32_t c = threadIdx.x; c < K; c += LL_ORD_TPB) {
+    const uint32_t cnt = p.counts[c];
+    if (!cnt) continue;
+    const uint32_t r = p.rank_of[c];
+#pragma unroll
+    for (int k = 0; k < 17; ++k)
+      if ((uint32_t)k <= p.B) acc[k] += (unsigned long long)cnt * ll_len(r, (uint32_t)k);
+  }
+#pragma unroll
+  for (int k = 0; k < 17; ++k) {
+    const unsigned long long v = wave_sum_u64(acc[k]);
+    if (lane_id() == 0) part[threadIdx.x / 64][k] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t best_k = 0;
+    unsigned long long best = 0;
+    for (uint32_t k = 0; k <= p.B; ++k) {
+      unsigned long long t = 0;
+      for (int w = 0; w < LL_ORD_TPB / 64; ++w) t += part[w][k];
+      p.bits_k[k] = t;
+      if (k == 0 || t < best) {
+        best = t;
+        best_k = k;
+      }
+    }
+    *p.order = best_k;
+  }
+}
+
+// Bits of sub-block s, rounded up to a word, into sub_off[s + 1].
+__global__ void __launch_bounds__(LL_TPB) k_llsub(LLParams p) {
+  const uint64_t s = (uint64_t)blockIdx.x * LL_TPB + threadIdx.x;
+  if (s >= p.n_sub) return;
+  const uint32_t k = *p.order;
+  const uint64_t j0 = s * LL_SUB;
+  const uint64_t j1 = j0 + LL_SUB < p.n ? j0 + LL_SUB : p.n;
+  CodeReader rd{p.packed, j0 * p.B / 32, 0ull, 0u};
+  unsigned long long bits = 0;
+  for (uint64_t j = j0; j < j1; ++j) bits += ll_len(p.rank_of[rd.next(p.B)], k);
+  p.sub_off[s + 1] = (bits + 31) / 32 * 32;
+}
+
+// Inclusive scan of sub_off[1..n_sub] in place (one workgroup), then the
+// header.
+__global__ void __launch_bounds__(LL_SCAN_TPB) k_llscan(LLParams p) {
+  __shared__ unsigned long long part[LL_SCAN_TPB];
+  const uint64_t ns = p.n_sub;
+  const uint64_t per = (ns + LL_SCAN_TPB - 1) / LL_SCAN_TPB;
+  const uint64_t a = 1 + (uint64_t)threadIdx.x * per;
+  uint64_t b = a + per;
+  b = b < ns + 1 ? b : ns + 1;
+  unsigned long long sum = 0;
+  for (uint64_t i = a; i < b; ++i) sum += p.sub_off[i];
+  part[threadIdx.x] = sum;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long run = 0;
+    for (int t = 0; t < LL_SCAN_TPB; ++t) {
+      const unsigned long long v = part[t];
+      part[t] = run;
+      run += v;
+    }
+  }
+  __syncthreads();
+  unsigned long long run = part[threadIdx.x];
+  for (uint64_t i = a; i < b; ++i) {
+    run += p.sub_off[i];
+    p.sub_off[i] = run;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    p.sub_off[0] = 0;
+    const uint32_t k = *p.order;
+    numarck_lossless_header* h = p.hdr;
+    const unsigned long long total = ns ? p.sub_off[ns] : 0ull;
+    h->n = p.n;
+    h->n_sub = ns;
+    h->stream_words = total / 32;
+    h->bits = p.bits_k[k];
+    h->B = p.B;
+    h->k = k;
+    h->flags = 0;
+    h->reserved = 0;
+    h->bytes = ((uint64_t)2 << p.B) + 8 * (ns + 1) + 4 * (total / 32) +
+               sizeof(numarck_lossless_header);
+  }
+}
+
+// Sub-block s's codewords, from word sub_off[s] / 32 on.
+__global__ void __launch_bounds__(LL_TPB) k_llwrite(LLParams p) {
+  const uint64_t s = (uint64_t)blockIdx.x * LL_TPB + threadIdx.x;
+  if (s >= p.n_sub) return;
+  const uint32_t k = *p.order;
+  const uint64_t j0 = s * LL_SUB;
+  const uint64_t j1 = j0 + LL_SUB < p.n ? j0 + LL_SUB : p.n;
+  CodeReader rd{p.packed, j0 * p.B / 32, 0ull, 0u};
+  uint64_t ow = p.sub_off[s] / 32;
+  unsigned long long ob = 0;
+  uint32_t on = 0;  // bits held in ob (< 32 between codewords)
+  for (uint64_t j = j0; j < j1; ++j) {
+    const uint32_t x = p.rank_of[rd.next(p.B)] + (1u << k);
+    const uint32_t nb = ll_log2(x);
+    const uint32_t q = nb - k;
+    // q zeros, the leading one at bit q, the low nb bits of x above it
+    const unsigned long long cw =
+        (1ull << q) | ((unsigned long long)(x ^ (1u << nb)) << (q + 1));
+    ob |= cw << on;  // on + (q + 1 + nb) <= 31 + 33
+    on += q + 1 + nb;
+    while (on >= 32) {
+      p.stream[ow++] = (uint32_t)ob;
+      ob >>= 32;
+      on -= 32;
+    }
+  }
+  if (on) p.stream[ow] = (uint32_t)ob;
+}
+
+__global__ void k_llflags(uint32_t* flags) { *flags = 0u; }
+
+// Sub-block s back to its B-bit codes.  A codeword that runs past its
+// sub-block, one of more than 33 bits or a rank of 2^B or more sets the flag
+// and ends the sub-block.
+__global__ void __launch_bounds__(LL_TPB) k_lldecode(LLDecodeParams p) {
+  const uint64_t s = (uint64_t)blockIdx.x * LL_TPB + threadIdx.x;
+  if (s >= p.n_sub) return;
+  const uint64_t start = p.sub_off[s], end = p.sub_off[s + 1];
+  if (start > end || end > p.stream_words * 32 || (start & 31) || (end & 31)) {
+    atomicOr(p.flags, NUMARCK_FLAG_BAD_STREAM);
+    return;
+  }
+  const uint32_t K = 1u << p.B, k = p.k;
+  uint64_t iw = start / 32;
+  const uint64_t ew = end / 32;
+  unsigned long long buf = 0;
+  uint32_t nbits = 0;
+  const uint64_t j0 = s * LL_SUB;
+  const uint64_t j1 = j0 + LL_SUB < p.n ? j0 + LL_SUB : p.n;
+  uint64_t ow = j0 * p.B / 32;
+  unsigned long long ob = 0;
+  uint32_t on = 0;
+  for (uint64_t j = j0; j < j1; ++j) {
+    while (nbits <= 32 && iw < ew) {
+      buf |= (unsigned long long)p.stream[iw++] << nbits;
+      nbits += 32;
+    }
+    const uint32_t q = buf ? (uint32_t)__builtin_ctzll(buf) : 64u;
+    const uint32_t nb = q + k;
+    if (nb > 16 || q + 1 + nb > nbits) {
+      atomicOr(p.flags, NUMARCK_FLAG_BAD_STREAM);
+      return;
+    }
+    const uint32_t low = (uint32_t)(buf >> (q + 1)) & ((1u << nb) - 1u);
+    buf >>= (q + 1 + nb);
+    nbits -= q + 1 + nb;
+    const uint32_t v = ((1u << nb) | low) - (1u << k);
+    if (v >= K) {
+      atomicOr(p.flags, NUMARCK_FLAG_BAD_STREAM);
+      return;
+    }
+    ob |= (unsigned long long)p.code_of_rank[v] << on;
+    on += p.B;
+    if (on >= 32) {
+      p.packed[ow++] = (uint32_t)ob;
+      ob >>= 32;
+      on -= 32;
+    }
+  }
+  if (on) p.packed[ow] = (uint32_t)ob;
+}
+
+#define LL_LAUNCH(kern, grid, block, ...)                                     \
+  do {                                                                        \
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(block), 0, s, __VA_ARGS__);     \
+    hipError_t e_ = hipGetLastError();                                        \
+    if (e_ != hipSuccess) return e_;                                          \
+  } while (0)
+
+hipError_t launch_lossless_encode(const LLParams& p, hipStream_t s) {
+  const uint32_t K = 1u << p.B;
+  const uint32_t kb = (K + LL_TPB - 1) / LL_TPB;
+  LL_LAUNCH(k_llclear, kb, LL_TPB, p);
+  if (p.n) {
+    uint64_t hb = (p.n + LL_TPB - 1) / LL_TPB;
+    const uint64_t cap = (uint64_t)geometry().cus * 8;
+    hb = hb < cap ? hb : cap;
+    LL_LAUNCH(k_llhist, hb, LL_TPB, p);
+  }
+  LL_LAUNCH(k_llrank, kb, LL_TPB, p);
+  LL_LAUNCH(k_llorder, 1, LL_ORD_TPB, p);
+  const uint64_t sb = (p.n_sub + LL_TPB - 1) / LL_TPB;
+  if (sb) LL_LAUNCH(k_llsub, sb, LL_TPB, p);
+  LL_LAUNCH(k_llscan, 1, LL_SCAN_TPB, p);
+  if (sb) LL_LAUNCH(k_llwrite, sb, LL_TPB, p);
+  return hipSuccess;
+}
+
+hipError_t launch_lossless_decode(const LLDecodeParams& p, hipStream_t s) {
+  LL_LAUNCH(k_llflags, 1, 1, p.flags);
+  const uint64_t sb = (p.n_sub + LL_TPB - 1) / LL_TPB;
+  if (sb) LL_LAUNCH(k_lldecode, sb, LL_TPB, p);
+  return hipSuccess;
+}
+
+}  // namespace nk

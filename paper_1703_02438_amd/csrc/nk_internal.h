@@ -304,6 +304,33 @@ hipError_t launch_compress_batch(const BatchLaunch& b, hipStream_t s);
 hipError_t launch_compress_phase(const CParams& P, const Tuning& tn, hipStream_t s,
                                  unsigned phases);
 hipError_t launch_autob(const CParams& P, uint32_t b_lo, uint32_t b_hi, hipStream_t s);
+// Lossless stage of an index table (lossless_kernels.hip).
+struct LLParams {
+  const uint32_t* packed;  // the B-bit index table
+  uint64_t n, n_sub;
+  uint32_t B;
+  uint32_t* counts;        // workspace: 2^B code counts
+  uint32_t* rank_of;       // workspace: 2^B ranks
+  unsigned long long* bits_k;  // workspace: 17 totals
+  uint32_t* order;         // workspace: the chosen order k
+  uint16_t* code_of_rank;  // out: 2^B
+  uint64_t* sub_off;       // out: n_sub + 1 bit offsets
+  uint32_t* stream;        // out
+  numarck_lossless_header* hdr;  // out (device)
+};
+struct LLDecodeParams {
+  uint64_t n, n_sub, stream_words;
+  uint32_t B, k;
+  const uint16_t* code_of_rank;
+  const uint64_t* sub_off;
+  const uint32_t* stream;
+  uint32_t* packed;        // out: the B-bit index table
+  uint32_t* flags;         // out: NUMARCK_FLAG_BAD_STREAM
+};
+hipError_t launch_lossless_encode(const LLParams& p, hipStream_t s);
+hipError_t launch_lossless_decode(const LLDecodeParams& p, hipStream_t s);
+constexpr uint64_t LL_SUB_CODES = 4096;
+
 // One compression with the fine bins anchored at -E (centred on multiples of
 // 2E): no range pass; histogram, top-k and the rest as launch_compress.
 hipError_t launch_compress_za(const CParams& P, const Tuning& tn, hipStream_t s);

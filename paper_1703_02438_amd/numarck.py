@@ -22,7 +22,7 @@ LIB_PATH = os.path.join(_HERE, "libnumarck.so")
 
 F32, F64 = 0, 1
 OK, EINVAL, EDTYPE, EBITS, EBOUND, EALIGN, ECAPACITY, EHIP, ERANGE = range(9)
-FLAG_BAD_INDEX, FLAG_INC_OVERRUN, FLAG_TAIL_OVERFLOW = 1, 2, 4
+FLAG_BAD_INDEX, FLAG_INC_OVERRUN, FLAG_TAIL_OVERFLOW, FLAG_BAD_STREAM = 1, 2, 4, 8
 
 
 class NumarckHeader(ctypes.Structure):
@@ -36,6 +36,17 @@ class NumarckHeader(ctypes.Structure):
         ("E", ctypes.c_double), ("lo", ctypes.c_double), ("hi", ctypes.c_double),
         ("packed_bytes", ctypes.c_uint64), ("compressed_bytes", ctypes.c_uint64),
         ("tail_count", ctypes.c_uint64), ("window_base", ctypes.c_int64),
+    ]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class NumarckLosslessHeader(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_uint64), ("n_sub", ctypes.c_uint64), ("stream_words", ctypes.c_uint64),
+        ("bits", ctypes.c_uint64), ("B", ctypes.c_uint32), ("k", ctypes.c_uint32),
+        ("flags", ctypes.c_uint32), ("reserved", ctypes.c_uint32), ("bytes", ctypes.c_uint64),
     ]
 
     def as_dict(self) -> dict:
@@ -136,6 +147,14 @@ numarck_decompress_workspace_bytes = _bind("numarck_decompress_workspace_bytes",
 numarck_compress = _bind("numarck_compress", _i,
                          [_vp, _vp, _u64, _i, _d, _u32, _u64, ctypes.POINTER(NumarckOut), _vp,
                           _sz, _vp])
+numarck_lossless_subblocks = _bind("numarck_lossless_subblocks", _u64, [_u64])
+numarck_lossless_stream_bytes = _bind("numarck_lossless_stream_bytes", _sz, [_u64, _u32])
+numarck_lossless_workspace_bytes = _bind("numarck_lossless_workspace_bytes", _sz, [_u32])
+numarck_lossless_encode = _bind("numarck_lossless_encode", _i,
+                                [_vp, _u64, _u32, _vp, _vp, _vp, _sz, _vp, _vp, _sz, _vp])
+numarck_lossless_decode = _bind("numarck_lossless_decode", _i,
+                                [ctypes.POINTER(NumarckLosslessHeader), _vp, _vp, _vp, _vp, _vp,
+                                 _vp])
 numarck_compress_zero_anchored = _bind("numarck_compress_zero_anchored", _i,
                                        [_vp, _vp, _u64, _i, _d, _u32, _u64,
                                         ctypes.POINTER(NumarckOut), _vp, _sz, _vp])
@@ -417,6 +436,57 @@ class BatchJob:
     B: int
     block_bytes: int = 0
     tail_cap: int = 0  # 0: n (never overflows)
+
+
+@dataclass
+class Lossless:
+    """Device buffers of the lossless stage of one index table."""
+    code_of_rank: torch.Tensor  # int16 view of 2^B uint16
+    sub_off: torch.Tensor       # int64 view of n_sub + 1 uint64 (bits)
+    stream: torch.Tensor        # int32 view of the codeword words
+    hdr: torch.Tensor           # uint8 device header
+    n: int
+    B: int
+    _host: NumarckLosslessHeader | None = None
+
+    def header(self) -> NumarckLosslessHeader:
+        if self._host is None:
+            raw = self.hdr.cpu().numpy().tobytes()
+            self._host = NumarckLosslessHeader.from_buffer_copy(raw)
+        return self._host
+
+
+def lossless_encode(packed: torch.Tensor, n: int, B: int, ws: torch.Tensor | None = None,
+                    stream=None) -> Lossless:
+    """Lossless stage of an index table of n B-bit codes (numarck_lossless_encode);
+    `packed` is e.g. ``Compressed.packed``."""
+    dev = packed.device
+    nsub = int(numarck_lossless_subblocks(n))
+    sb = numarck_lossless_stream_bytes(n, B)
+    cor = torch.empty(1 << B, dtype=torch.int16, device=dev)
+    sub = torch.empty(nsub + 1, dtype=torch.int64, device=dev)
+    st = torch.empty(max(sb // 4, 1), dtype=torch.int32, device=dev)
+    hdr = torch.empty(ctypes.sizeof(NumarckLosslessHeader), dtype=torch.uint8, device=dev)
+    if ws is None:
+        ws = torch.empty(numarck_lossless_workspace_bytes(B), dtype=torch.uint8, device=dev)
+    r = numarck_lossless_encode(_ptr(packed), n, B, _ptr(cor), _ptr(sub), _ptr(st), st.numel() * 4,
+                                _ptr(hdr), _ptr(ws), ws.numel(), _stream(stream))
+    _check(r, "numarck_lossless_encode")
+    return Lossless(cor, sub, st, hdr, n, B)
+
+
+def lossless_decode(enc: Lossless, out: torch.Tensor | None = None, stream=None):
+    """The index table of a lossless stream; returns (packed int32 words, flags)."""
+    h = enc.header()
+    dev = enc.stream.device
+    words = (enc.n * enc.B + 31) // 32
+    if out is None:
+        out = torch.empty(max(words, 1), dtype=torch.int32, device=dev)
+    flags = torch.zeros(1, dtype=torch.int32, device=dev)
+    r = numarck_lossless_decode(ctypes.byref(h), _ptr(enc.code_of_rank), _ptr(enc.sub_off),
+                                _ptr(enc.stream), _ptr(out), _ptr(flags), _stream(stream))
+    _check(r, "numarck_lossless_decode")
+    return out[:words], flags
 
 
 class ClosedLoop:
