@@ -439,14 +439,14 @@ int numarck_timing_read(const char** names, uint32_t* launches, double* ms, int 
  *     x = v + 2^k and nb = floor(log2 x), nb - k zero bits, a one bit, then the
  *     low nb bits of x least significant first (2 nb - k + 1 bits);
  *   - k in [0, B] is the order with the fewest bits (the smaller k on ties);
- *   - sub-blocks of 4096 codes each start on a 32-bit word (the one before is
+ *   - sub-blocks of 1024 codes each start on a 32-bit word (the one before is
  *     padded with zeros); sub_off[s] is the first bit of sub-block s and
  *     sub_off[n_sub] the stream's length in bits, so any sub-block decodes on
  *     its own;
  *   - bits are numbered least significant first in little-endian words. */
 typedef struct numarck_lossless_header {
   uint64_t n;            /* codes in the table */
-  uint64_t n_sub;        /* sub-blocks: ceil(n / 4096) */
+  uint64_t n_sub;        /* sub-blocks: ceil(n / 1024) */
   uint64_t stream_words; /* 32-bit words of the codeword stream */
   uint64_t bits;         /* codeword bits, without the sub-block padding */
   uint32_t B;            /* index width */
@@ -456,7 +456,7 @@ typedef struct numarck_lossless_header {
   uint64_t bytes;        /* stored size: 2 * 2^B + 8 (n_sub + 1) + 4 stream_words + this header */
 } numarck_lossless_header;
 
-/* Sub-blocks of a table of n codes: ceil(n / 4096). */
+/* Sub-blocks of a table of n codes: ceil(n / 1024). */
 uint64_t numarck_lossless_subblocks(uint64_t n);
 /* Stream bytes that always suffice: 4 (ceil(n (B + 1) / 32) + n_sub).  (Order
  * k = B costs at most B + 1 bits per code, and the chosen order no more.) */

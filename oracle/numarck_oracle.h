@@ -129,7 +129,7 @@ int orc_decompress_range(const orc_info* info, const void* prev, const uint32_t*
  * B + 1 totals in bits, unpadded; sub_off: n_sub + 1 bit offsets (the last is
  * the stream's length in bits); stream: cap_words words.  *words_out gets
  * the stream's words even when they exceed cap_words (then ORC_EINVAL). */
-#define ORC_SUB 4096
+#define ORC_SUB 1024
 uint64_t orc_lossless_subblocks(uint64_t n);
 int orc_lossless_encode(const uint32_t* packed, uint64_t n, uint32_t B, uint16_t* code_of_rank,
                         uint32_t* k_out, uint64_t* bits_k, uint64_t* sub_off, uint32_t* stream,

@@ -19,13 +19,15 @@
 // Encode: k_llclear, k_llhist (code counts), k_llrank (rank of every code by
 // counting the codes before it), k_llorder (bits of every order, the
 // choice), k_llsub (bits of every sub-block), k_llscan (offsets and the
-// header), k_llwrite.  Decode: k_llflags, k_lldecode.  The per-sub-block
-// passes give each sub-block to one lane, which walks its codes in order.
+// header), k_llwrite.  Decode: k_llflags, k_lldecode.  The encoder's
+// per-sub-block passes give each sub-block to a wave (64 consecutive codes
+// per round); the decoder gives it to one lane, which walks its codewords in
+// order (where a codeword starts is known only after the one before).
 #include "nk_device.h"
 
 namespace nk {
 
-constexpr int LL_SUB = 4096;        // codes per sub-block
+constexpr int LL_SUB = (int)LL_SUB_CODES;  // codes per sub-block
 constexpr int LL_TPB = 256;
 constexpr int LL_LDS_BINS = 8192;   // code counts kept in LDS up to this many codes
 constexpr int LL_ORD_TPB = 1024;
@@ -48,24 +50,6 @@ __device__ __forceinline__ uint32_t ll_code(const uint32_t* __restrict__ packed,
   if (sh + B > 32) v |= packed[w + 1] << (32 - sh);
   return v & ((1u << B) - 1u);
 }
-
-// Sequential reader of B-bit codes from word `w` on.
-struct CodeReader {
-  const uint32_t* p;
-  uint64_t w;
-  unsigned long long buf;
-  uint32_t nbits;
-  __device__ __forceinline__ uint32_t next(uint32_t B) {
-    if (nbits < B) {
-      buf |= (unsigned long long)p[w++] << nbits;
-      nbits += 32;
-    }
-    const uint32_t c = (uint32_t)buf & ((1u << B) - 1u);
-    buf >>= B;
-    nbits -= B;
-    return c;
-  }
-};
 
 __global__ void __launch_bounds__(LL_TPB) k_llclear(LLParams p) {
   const uint32_t K = 1u << p.B;
@@ -158,17 +142,23 @@ __global__ void __launch_bounds__(LL_ORD_TPB) k_llorder(LLParams p) {
   }
 }
 
-// Bits of sub-block s, rounded up to a word, into sub_off[s + 1].
+// Bits of sub-block s, rounded up to a word, into sub_off[s + 1].  One wave
+// per sub-block; in round i lane l takes code j0 + 64 i + l, so each round
+// reads 64 consecutive codes.
 __global__ void __launch_bounds__(LL_TPB) k_llsub(LLParams p) {
-  const uint64_t s = (uint64_t)blockIdx.x * LL_TPB + threadIdx.x;
-  if (s >= p.n_sub) return;
+  const uint64_t s = (uint64_t)blockIdx.x * (LL_TPB / 64) + threadIdx.x / 64;
+  if (s >= p.n_sub) return;  // whole waves leave
+  const int lane = lane_id();
   const uint32_t k = *p.order;
   const uint64_t j0 = s * LL_SUB;
   const uint64_t j1 = j0 + LL_SUB < p.n ? j0 + LL_SUB : p.n;
-  CodeReader rd{p.packed, j0 * p.B / 32, 0ull, 0u};
   unsigned long long bits = 0;
-  for (uint64_t j = j0; j < j1; ++j) bits += ll_len(p.rank_of[rd.next(p.B)], k);
-  p.sub_off[s + 1] = (bits + 31) / 32 * 32;
+  for (uint64_t jb = j0; jb < j1; jb += 64) {
+    const uint64_t j = jb + lane;
+    if (j < j1) bits += ll_len(p.rank_of[ll_code(p.packed, j, p.B)], k);
+  }
+  bits = wave_sum_u64(bits);
+  if (lane == 0) p.sub_off[s + 1] = (bits + 31) / 32 * 32;
 }
 
 // Inclusive scan of sub_off[1..n_sub] in place (one workgroup), then the
@@ -217,33 +207,66 @@ __global__ void __launch_bounds__(LL_SCAN_TPB) k_llscan(LLParams p) {
   }
 }
 
-// Sub-block s's codewords, from word sub_off[s] / 32 on.
+// Sub-block s's codewords, from word sub_off[s] / 32 on.  One wave per
+// sub-block, 64 consecutive codes per round: a prefix sum of the codeword
+// lengths places each codeword in a wave-private LDS window (ORed into at
+// most two words), the completed words go out, and the partial last word
+// stays as the next round's first.
+constexpr int LL_WIN = 72;  // >= (31 + 64 * 33) / 32 + 2 words
+
 __global__ void __launch_bounds__(LL_TPB) k_llwrite(LLParams p) {
-  const uint64_t s = (uint64_t)blockIdx.x * LL_TPB + threadIdx.x;
-  if (s >= p.n_sub) return;
+  __shared__ uint32_t s_win[LL_TPB / 64][LL_WIN];
+  const uint64_t s = (uint64_t)blockIdx.x * (LL_TPB / 64) + threadIdx.x / 64;
+  if (s >= p.n_sub) return;  // whole waves leave; no workgroup barrier below
+  const int lane = lane_id();
+  uint32_t* win = s_win[threadIdx.x / 64];
   const uint32_t k = *p.order;
   const uint64_t j0 = s * LL_SUB;
   const uint64_t j1 = j0 + LL_SUB < p.n ? j0 + LL_SUB : p.n;
-  CodeReader rd{p.packed, j0 * p.B / 32, 0ull, 0u};
-  uint64_t ow = p.sub_off[s] / 32;
-  unsigned long long ob = 0;
-  uint32_t on = 0;  // bits held in ob (< 32 between codewords)
-  for (uint64_t j = j0; j < j1; ++j) {
-    const uint32_t x = p.rank_of[rd.next(p.B)] + (1u << k);
-    const uint32_t nb = ll_log2(x);
-    const uint32_t q = nb - k;
-    // q zeros, the leading one at bit q, the low nb bits of x above it
-    const unsigned long long cw =
-        (1ull << q) | ((unsigned long long)(x ^ (1u << nb)) << (q + 1));
-    ob |= cw << on;  // on + (q + 1 + nb) <= 31 + 33
-    on += q + 1 + nb;
-    while (on >= 32) {
-      p.stream[ow++] = (uint32_t)ob;
-      ob >>= 32;
-      on -= 32;
+  for (int i = lane; i < LL_WIN; i += 64) win[i] = 0u;
+  wave_lds_sync();
+  uint64_t gw = p.sub_off[s] / 32;  // global word of window slot 0
+  uint32_t off = 0;                 // bits already in slot 0
+  for (uint64_t jb = j0; jb < j1; jb += 64) {
+    const uint64_t j = jb + lane;
+    const bool on = j < j1;
+    uint32_t len = 0;
+    unsigned long long cw = 0;
+    if (on) {
+      const uint32_t x = p.rank_of[ll_code(p.packed, j, p.B)] + (1u << k);
+      const uint32_t nb = ll_log2(x);
+      const uint32_t q = nb - k;
+      cw = (1ull << q) | ((unsigned long long)(x ^ (1u << nb)) << (q + 1));
+      len = q + 1 + nb;
     }
+    // inclusive prefix sum of the lengths over the wave
+    uint32_t inc = len;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t t = __shfl_up(inc, o, 64);
+      if (lane >= o) inc += t;
+    }
+    const uint32_t total = __shfl(inc, 63, 64);
+    if (on) {
+      const uint32_t pos = off + inc - len;
+      const uint32_t w = pos >> 5, sh = pos & 31;
+      atomicOr(&win[w], (uint32_t)(cw << sh));
+      if (sh + len > 32) atomicOr(&win[w + 1], (uint32_t)((cw << sh) >> 32));
+    }
+    wave_lds_sync();
+    const uint32_t end = off + total;
+    const uint32_t full = end >> 5;
+    for (uint32_t i = lane; i < full; i += 64) p.stream[gw + i] = win[i];
+    const uint32_t carry = win[full];
+    wave_lds_sync();
+    for (int i = lane; i < LL_WIN; i += 64) win[i] = 0u;
+    wave_lds_sync();
+    if (lane == 0) win[0] = carry;
+    wave_lds_sync();
+    gw += full;
+    off = end & 31;
   }
-  if (on) p.stream[ow] = (uint32_t)ob;
+  if (off && lane == 0) p.stream[gw] = win[0];
 }
 
 __global__ void k_llflags(uint32_t* flags) { *flags = 0u; }
@@ -318,10 +341,10 @@ hipError_t launch_lossless_encode(const LLParams& p, hipStream_t s) {
   }
   LL_LAUNCH(k_llrank, kb, LL_TPB, p);
   LL_LAUNCH(k_llorder, 1, LL_ORD_TPB, p);
-  const uint64_t sb = (p.n_sub + LL_TPB - 1) / LL_TPB;
-  if (sb) LL_LAUNCH(k_llsub, sb, LL_TPB, p);
+  const uint64_t wb = (p.n_sub + LL_TPB / 64 - 1) / (LL_TPB / 64);  // a wave per sub-block
+  if (wb) LL_LAUNCH(k_llsub, wb, LL_TPB, p);
   LL_LAUNCH(k_llscan, 1, LL_SCAN_TPB, p);
-  if (sb) LL_LAUNCH(k_llwrite, sb, LL_TPB, p);
+  if (wb) LL_LAUNCH(k_llwrite, wb, LL_TPB, p);
   return hipSuccess;
 }
 

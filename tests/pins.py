@@ -716,7 +716,7 @@ def pin_lossless_structure(o):
     rounded up to a word, the total is at least the table's entropy, and
     decoding returns the table."""
     rng = np.random.default_rng(61)
-    S = 4096
+    S = 1024
     for B, n in ((1, 3 * S + 17), (5, 2 * S), (8, 5 * S + 1), (13, S + 3), (16, 2 * S + 99)):
         K = 1 << B
         w = rng.pareto(1.2, K) + 1e-3
@@ -744,10 +744,10 @@ def pin_lossless_structure(o):
 def pin_lossless_single_symbol_and_corrupt(o):
     """One symbol only: rank 0, order 0, one bit per code; an empty table;
     and a stream cut short is refused."""
-    n = 4096 + 5
+    n = 1024 + 5
     e = o.lossless_encode(_pack_codes([3] * n, 4), n, 4)
-    assert e["k"] == 0 and e["code_of_rank"][0] == 3 and e["sub_off"].tolist() == [0, 4096, 4128]
-    assert e["stream"][:128].tolist() == [0xFFFFFFFF] * 128 and e["stream"][128] == 0x1F
+    assert e["k"] == 0 and e["code_of_rank"][0] == 3 and e["sub_off"].tolist() == [0, 1024, 1056]
+    assert e["stream"][:32].tolist() == [0xFFFFFFFF] * 32 and e["stream"][32] == 0x1F
     e0 = o.lossless_encode(np.zeros(0, np.uint32), 0, 6)
     assert e0["sub_off"].tolist() == [0] and e0["stream"].size == 0
     bad = dict(e)

@@ -246,8 +246,8 @@ def test_lossless_validation_without_gpu(nk):
     assert enc(hdr=None) == nk.EINVAL and enc(packed=None) == nk.EINVAL
     assert enc(sb=m.numarck_lossless_stream_bytes(100, 8) - 4) == nk.ECAPACITY
     assert enc(wsb=m.numarck_lossless_workspace_bytes(8) - 1) == nk.ECAPACITY
-    assert m.numarck_lossless_subblocks(0) == 0 and m.numarck_lossless_subblocks(4097) == 2
-    assert m.numarck_lossless_stream_bytes(4096, 8) == 4 * (4096 * 9 // 32 + 1)
+    assert m.numarck_lossless_subblocks(0) == 0 and m.numarck_lossless_subblocks(1025) == 2
+    assert m.numarck_lossless_stream_bytes(4096, 8) == 4 * (4096 * 9 // 32 + 4)
     h = m.NumarckLosslessHeader(n=10, n_sub=1, stream_words=1, bits=10, B=8, k=9)
     dec = lambda hh: m.numarck_lossless_decode(ctypes.byref(hh), 0x400000, 0x500000, 0x600000,
                                                0x800000, 0x900000, None)

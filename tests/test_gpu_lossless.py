@@ -61,13 +61,13 @@ def ll_compare(nk, packed, n, B, label=""):
 @pytest.mark.parametrize("B", [1, 2, 3, 5, 8, 10, 12, 13, 14, 16])
 def test_lossless_random_tables(nk, B):
     rng = np.random.default_rng(70 + B)
-    n = 3 * 4096 + 1234
+    n = 3 * 1024 + 1234
     w = rng.pareto(1.1, 1 << B) + 1e-3
     codes = rng.choice(1 << B, n, p=w / w.sum())
     ll_compare(nk, _table(codes, B), n, B, label="pareto")
 
 
-@pytest.mark.parametrize("n", [0, 1, 31, 4096, 4097, 8192 + 5])
+@pytest.mark.parametrize("n", [0, 1, 31, 1024, 1025, 2048 + 5, 40_000])
 def test_lossless_sizes(nk, n):
     rng = np.random.default_rng(n)
     codes = rng.integers(0, 1 << 6, n) if n else np.zeros(0, np.int64)
@@ -106,7 +106,7 @@ def test_lossless_corrupt_stream_flagged(nk):
     past the stream are reported in the flag word, with every access in
     bounds."""
     rng = np.random.default_rng(5)
-    n = 2 * 4096 + 7
+    n = 2 * 1024 + 7
     codes = rng.integers(0, 16, n)
     t = torch.from_numpy(_table(codes, 4).view(np.int32)).cuda()
     e = nk.lossless_encode(t, n, 4)
