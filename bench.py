@@ -302,7 +302,8 @@ def time_ms(torch, fn, reps: int, stream) -> float:
 
 def batched_vs_plain(torch, nk, jobs, reps: int) -> dict:
     """One workload of many jobs: plain per-job launches, one batched plan, and
-    the plan replayed as a HIP graph (input GB/s of each)."""
+    the plan replayed as a HIP graph, and the batch with zero-anchored bins
+    (input GB/s of each)."""
     stream = torch.cuda.current_stream()
     in_bytes = sum(j.curr.numel() * j.curr.element_size() for j in jobs)
     wss = [torch.empty(nk.numarck_workspace_bytes(j.curr.numel(), nk.dtype_code(j.curr.dtype), j.B),
@@ -326,7 +327,13 @@ def batched_vs_plain(torch, nk, jobs, reps: int) -> dict:
     flags = [plan.results()[i].header().flags for i in range(len(jobs))]
     assert not any(flags), flags
     plan.close()
+    # the same batch with the bins anchored at -E (no range pass)
+    zplan = nk.Plan(jobs, outputs=outs, stream=stream, zero_anchored=True)
+    t_za = time_ms(torch, lambda: zplan.run(stream), reps, stream)
+    zplan.close()
     return {
+        "za_batched_gbs": round(in_bytes / t_za / 1e6, 1),
+        "za_batched_ms": round(t_za, 3),
         "jobs": len(jobs),
         "input_bytes": in_bytes,
         "plain_gbs": round(in_bytes / t_plain / 1e6, 1),

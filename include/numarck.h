@@ -308,6 +308,13 @@ size_t numarck_batch_workspace_bytes(const numarck_job* jobs, uint32_t njobs);
 numarck_status numarck_plan_create(const numarck_job* jobs, uint32_t njobs,
                                    const numarck_tuning* tune, void* ws, size_t ws_bytes,
                                    void* stream, numarck_plan** plan);
+/* As numarck_plan_create, with every job's bins anchored at -E as in
+ * numarck_compress_zero_anchored (two reads of each snapshot instead of
+ * three; same outputs as that call for each job). */
+numarck_status numarck_plan_create_zero_anchored(const numarck_job* jobs, uint32_t njobs,
+                                                 const numarck_tuning* tune, void* ws,
+                                                 size_t ws_bytes, void* stream,
+                                                 numarck_plan** plan);
 /* Compress every job of the plan on `stream`. */
 numarck_status numarck_plan_run(const numarck_plan* plan, void* stream);
 /* Capture numarck_plan_run on `stream` (not the null stream) into a HIP graph

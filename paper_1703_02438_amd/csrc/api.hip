@@ -627,9 +627,9 @@ size_t numarck_batch_workspace_bytes(const numarck_job* jobs, uint32_t njobs) {
   return total;
 }
 
-numarck_status numarck_plan_create(const numarck_job* jobs, uint32_t njobs,
-                                   const numarck_tuning* tune, void* ws, size_t ws_bytes,
-                                   void* stream, numarck_plan** plan_out) {
+static numarck_status plan_create(const numarck_job* jobs, uint32_t njobs,
+                                  const numarck_tuning* tune, void* ws, size_t ws_bytes,
+                                  void* stream, numarck_plan** plan_out, uint32_t za) {
   if (!plan_out) return NUMARCK_EINVAL;
   *plan_out = nullptr;
   if (!jobs || njobs == 0 || njobs > NUMARCK_MAX_JOBS || !ws) return NUMARCK_EINVAL;
@@ -848,8 +848,22 @@ numarck_status numarck_plan_create(const numarck_job* jobs, uint32_t njobs,
   bl.hgroups = pl->hgroups.data();
   bl.n_hgroups = (uint32_t)pl->hgroups.size();
   bl.tune = tn;
+  bl.za = za;
   *plan_out = pl;
   return NUMARCK_OK;
+}
+
+numarck_status numarck_plan_create(const numarck_job* jobs, uint32_t njobs,
+                                   const numarck_tuning* tune, void* ws, size_t ws_bytes,
+                                   void* stream, numarck_plan** plan_out) {
+  return plan_create(jobs, njobs, tune, ws, ws_bytes, stream, plan_out, 0);
+}
+
+numarck_status numarck_plan_create_zero_anchored(const numarck_job* jobs, uint32_t njobs,
+                                                 const numarck_tuning* tune, void* ws,
+                                                 size_t ws_bytes, void* stream,
+                                                 numarck_plan** plan_out) {
+  return plan_create(jobs, njobs, tune, ws, ws_bytes, stream, plan_out, 1);
 }
 
 numarck_status numarck_plan_run(const numarck_plan* plan, void* stream) {

@@ -1839,7 +1839,7 @@ static uint64_t clamp_blocks(uint64_t want, uint64_t cap) {
 // phases: 1 = the passes before top-k (they do not depend on B), 2 = top-k
 // and after.
 // phases bit: the zero-anchored form (k_zaprep in place of the range pass and
-// k_derive, k_zafin after the histogram); one job only
+// k_derive, k_zafin after the histogram)
 constexpr unsigned PH_ZA = 8;
 
 template <typename S>
@@ -2053,7 +2053,8 @@ hipError_t launch_compress_batch(const BatchLaunch& b, hipStream_t s) {
   base.unit0 = b.unit0_dev;
   base.chunk_vec = b.tune.chunk_vec ? b.tune.chunk_vec : 4096;  // groups carry their own
   return run_chain(JobTable{b.jobs_dev}, base, b.njobs, b.rgroups, b.n_rgroups, b.hgroups,
-                   b.n_hgroups, b.dgroups, b.n_dgroups, b.egroups, b.n_egroups, b.tune, s);
+                   b.n_hgroups, b.dgroups, b.n_dgroups, b.egroups, b.n_egroups, b.tune, s,
+                   3u | (b.za ? PH_ZA : 0u));
 }
 
 // =====================================================================

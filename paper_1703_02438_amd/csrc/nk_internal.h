@@ -295,6 +295,7 @@ struct BatchLaunch {
   const JobGroup* hgroups;  // histogram pass: the same runs and chains
   uint32_t n_hgroups;
   Tuning tune;
+  uint32_t za;  // 1: bins anchored at -E (no range pass)
 };
 hipError_t launch_compress_batch(const BatchLaunch& b, hipStream_t s);
 // One compression in two halves around the choice of B: phase 1 runs the

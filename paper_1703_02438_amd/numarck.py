@@ -187,6 +187,10 @@ numarck_batch_workspace_bytes = _bind("numarck_batch_workspace_bytes", _sz,
 numarck_plan_create = _bind("numarck_plan_create", _i,
                             [ctypes.POINTER(NumarckJob), _u32, ctypes.POINTER(NumarckTuning), _vp,
                              _sz, _vp, ctypes.POINTER(_vp)])
+numarck_plan_create_zero_anchored = _bind("numarck_plan_create_zero_anchored", _i,
+                                          [ctypes.POINTER(NumarckJob), _u32,
+                                           ctypes.POINTER(NumarckTuning), _vp, _sz, _vp,
+                                           ctypes.POINTER(_vp)])
 numarck_plan_run = _bind("numarck_plan_run", _i, [_vp, _vp])
 numarck_plan_capture = _bind("numarck_plan_capture", _i, [_vp, _vp])
 numarck_plan_replay = _bind("numarck_plan_replay", _i, [_vp, _vp])
@@ -543,7 +547,7 @@ class Plan:
 
     def __init__(self, jobs: list[BatchJob], recon: bool = False, bin_ids: bool = False,
                  outputs: list[dict] | None = None, tune: NumarckTuning | None = None,
-                 stream=None):
+                 stream=None, zero_anchored: bool = False):
         if not jobs:
             raise ValueError("empty batch")
         self.jobs = []
@@ -564,8 +568,9 @@ class Plan:
         self.ws = torch.empty(max(numarck_batch_workspace_bytes(arr, len(jobs)), 1),
                               dtype=torch.uint8, device=dev)
         h = _vp()
-        st = numarck_plan_create(arr, len(jobs), ctypes.byref(tune) if tune is not None else None,
-                                 _ptr(self.ws), self.ws.numel(), _stream(stream), ctypes.byref(h))
+        create = numarck_plan_create_zero_anchored if zero_anchored else numarck_plan_create
+        st = create(arr, len(jobs), ctypes.byref(tune) if tune is not None else None,
+                    _ptr(self.ws), self.ws.numel(), _stream(stream), ctypes.byref(h))
         _check(st, "numarck_plan_create")
         self._h = h
 

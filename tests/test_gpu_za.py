@@ -7,7 +7,7 @@ import pytest
 import torch
 
 import oracle
-from gpu_util import assert_matches_oracle, compare_decompress, to_np
+from gpu_util import assert_matches_oracle, assert_same_compression, compare_decompress, to_np
 from paper_1703_02438_amd import inputs
 from pins import adversarial_case, mixture_case
 
@@ -153,3 +153,40 @@ def test_za_equals_topk_when_min_is_minus_E(nk):
     assert torch.equal(a.recon.view(torch.int64), b.recon.view(torch.int64))
     assert np.array_equal(to_np(a.incomp)[: ha["n_inc"]].view(np.int64),
                           to_np(b.incomp)[: hb["n_inc"]].view(np.int64))
+
+
+def test_za_plans(nk):
+    """Zero-anchored plans: time chains, unchained jobs, both element types
+    and several B in one batch; every job equals its plain zero-anchored
+    compression on every run, and some equal the oracle."""
+    def series(n, dt, seed, steps):
+        rng = np.random.default_rng(seed)
+        x = rng.lognormal(0, 1, n)
+        out = [x.astype(dt)]
+        for _ in range(steps):
+            x = x * (1 + rng.normal(0, 2e-3, n)) + np.where(rng.random(n) < 0.01,
+                                                            rng.normal(0, 0.3, n), 0)
+            out.append(x.astype(dt))
+        return [torch.from_numpy(v).cuda() for v in out]
+
+    fa = series(100_003, np.float64, 61, 4)
+    fb = series(262_147, np.float32, 62, 3)
+    other = series(50_001, np.float64, 63, 1)
+    jobs = [(fa[t], fa[t + 1], 1e-3, 8) for t in range(4)]
+    jobs.append((other[0], other[1], 1e-3, 12))
+    jobs += [(fb[t], fb[t + 1], 1e-3, 10) for t in range(3)]
+    plan = nk.Plan([nk.BatchJob(p, q, E, B) for p, q, E, B in jobs], recon=True, bin_ids=True,
+                   zero_anchored=True)
+    for rep in range(2):
+        res = plan.run()
+        torch.cuda.synchronize()
+        for i, ((p, q, E, B), c) in enumerate(zip(jobs, res)):
+            ref = nk.compress_zero_anchored(p, q, E, B, recon=True, bin_ids=True)
+            assert_same_compression(c, ref, f"za plan job {i} rep {rep}")
+    orc = oracle.get()
+    for i in (0, 4, 6):
+        p, q, E, B = jobs[i]
+        pn, qn = to_np(p), to_np(q)
+        assert_matches_oracle(nk, res[i], orc.compress(pn, qn, E, B, binning="zero_anchored"),
+                              pn, qn, E, B, check_hist=False, label=f"za plan job {i}")
+    plan.close()
