@@ -40,10 +40,15 @@ ALGO = {
 }
 
 
+# The sources the compression and decompression kernels are built from: the
+# committed counters are taken as stale when any of them changes.
+KERNEL_SOURCES = ("compress_kernels.hip", "decompress_kernels.hip", "nk_device.h", "nk_internal.h")
+
+
 def source_digest() -> str:
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1703_02438_amd", "csrc")
-    for f in sorted(os.listdir(csrc)):
+    for f in KERNEL_SOURCES:
         with open(os.path.join(csrc, f), "rb") as fh:
             h.update(f.encode() + fh.read())
     return h.hexdigest()[:16]

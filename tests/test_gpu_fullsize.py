@@ -69,3 +69,42 @@ def test_climate_1800x3600_f32_full(nk):
     prev = s.x.clone()
     curr = s.step().clone()
     _full_check(nk, prev, curr, 1e-4, 10, "climate 1800x3600")
+
+
+@pytest.mark.timeout(600)
+def test_flash_512cubed_zero_anchored_and_lossless_full(nk):
+    """The 512^3 float64 pair through the zero-anchored compression and the
+    lossless stage of its index table, as the benchmark runs them: every
+    output against the oracle run on the whole input."""
+    from paper_1703_02438_amd import inputs
+    s = inputs.FlashSeries(edge=512, seed=1705, device="cuda")
+    prev_t = s.x.clone()
+    curr_t = s.step().clone()
+    del s
+    E, B = 1e-3, 8
+    n = prev_t.numel()
+    c = nk.compress_zero_anchored(prev_t, curr_t, E, B, recon=True)
+    h = c.header().as_dict()
+    enc = nk.lossless_encode(c.packed, n, B)
+    lh = enc.header()
+    back, fl = nk.lossless_decode(enc)
+    torch.cuda.synchronize()
+    prev, curr = prev_t.cpu().numpy(), curr_t.cpu().numpy()
+    del prev_t, curr_t
+    orc = oracle.get()
+    o = orc.compress(prev, curr, E, B, binning="zero_anchored")
+    for f in HEADER_FIELDS:
+        assert h[f] == o.info[f], f"header {f}: gpu {h[f]} oracle {o.info[f]}"
+    assert h["lo"] == -E and h["flags"] == 0
+    nw = o.info["packed_words"]
+    assert np.array_equal(to_np(c.packed)[:nw].view(np.uint32), o.packed)
+    assert np.array_equal(bits(to_np(c.centers)), bits(o.centers))
+    assert np.array_equal(bits(to_np(c.incomp)[: o.info["n_inc"]]), bits(o.incomp))
+    assert np.array_equal(bits(to_np(c.recon)[:n]), bits(o.recon))
+    ol = orc.lossless_encode(o.packed, n, B)
+    assert lh.k == ol["k"] and lh.stream_words == ol["stream"].size
+    assert np.array_equal(to_np(enc.code_of_rank).view(np.uint16), ol["code_of_rank"])
+    assert np.array_equal(to_np(enc.sub_off).view(np.uint64), ol["sub_off"])
+    assert np.array_equal(to_np(enc.stream)[: lh.stream_words].view(np.uint32), ol["stream"])
+    assert int(fl.item()) == 0
+    assert np.array_equal(to_np(back)[:nw].view(np.uint32), o.packed)
