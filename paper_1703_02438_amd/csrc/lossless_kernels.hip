@@ -31,6 +31,7 @@ constexpr int LL_SUB = (int)LL_SUB_CODES;  // codes per sub-block
 constexpr int LL_TPB = 256;
 constexpr int LL_LDS_BINS = 8192;   // code counts kept in LDS up to this many codes
 constexpr int LL_ORD_TPB = 1024;
+constexpr int LL_LDS_RANKS = 1024;  // rank / code tables kept in LDS up to this many codes (small: occupancy)
 constexpr int LL_SCAN_TPB = 1024;
 
 __device__ __forceinline__ uint32_t ll_log2(uint32_t x) { return 31u - (uint32_t)__clz(x); }
@@ -146,6 +147,14 @@ __global__ void __launch_bounds__(LL_ORD_TPB) k_llorder(LLParams p) {
 // per sub-block; in round i lane l takes code j0 + 64 i + l, so each round
 // reads 64 consecutive codes.
 __global__ void __launch_bounds__(LL_TPB) k_llsub(LLParams p) {
+  __shared__ uint32_t s_rank[LL_LDS_RANKS];
+  const uint32_t K = 1u << p.B;
+  const bool lds = K <= (uint32_t)LL_LDS_RANKS;
+  if (lds) {
+    for (uint32_t i = threadIdx.x; i < K; i += LL_TPB) s_rank[i] = p.rank_of[i];
+    __syncthreads();
+  }
+  const uint32_t* rank_of = lds ? s_rank : p.rank_of;
   const uint64_t s = (uint64_t)blockIdx.x * (LL_TPB / 64) + threadIdx.x / 64;
   if (s >= p.n_sub) return;  // whole waves leave
   const int lane = lane_id();
@@ -155,38 +164,52 @@ __global__ void __launch_bounds__(LL_TPB) k_llsub(LLParams p) {
   unsigned long long bits = 0;
   for (uint64_t jb = j0; jb < j1; jb += 64) {
     const uint64_t j = jb + lane;
-    if (j < j1) bits += ll_len(p.rank_of[ll_code(p.packed, j, p.B)], k);
+    if (j < j1) bits += ll_len(rank_of[ll_code(p.packed, j, p.B)], k);
   }
   bits = wave_sum_u64(bits);
   if (lane == 0) p.sub_off[s + 1] = (bits + 31) / 32 * 32;
 }
 
-// Inclusive scan of sub_off[1..n_sub] in place (one workgroup), then the
+// Inclusive scan of sub_off[1..n_sub] in place (one workgroup, tiles of
+// LL_SCAN_TPB * 4 entries, each thread four consecutive ones), then the
 // header.
 __global__ void __launch_bounds__(LL_SCAN_TPB) k_llscan(LLParams p) {
-  __shared__ unsigned long long part[LL_SCAN_TPB];
+  __shared__ unsigned long long s_wave[LL_SCAN_TPB / 64];
   const uint64_t ns = p.n_sub;
-  const uint64_t per = (ns + LL_SCAN_TPB - 1) / LL_SCAN_TPB;
-  const uint64_t a = 1 + (uint64_t)threadIdx.x * per;
-  uint64_t b = a + per;
-  b = b < ns + 1 ? b : ns + 1;
-  unsigned long long sum = 0;
-  for (uint64_t i = a; i < b; ++i) sum += p.sub_off[i];
-  part[threadIdx.x] = sum;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    unsigned long long run = 0;
-    for (int t = 0; t < LL_SCAN_TPB; ++t) {
-      const unsigned long long v = part[t];
-      part[t] = run;
-      run += v;
+  const int lane = lane_id(), wave = threadIdx.x / 64;
+  unsigned long long carry = 0;
+  for (uint64_t t0 = 1; t0 <= ns; t0 += (uint64_t)LL_SCAN_TPB * 4) {
+    const uint64_t i0 = t0 + (uint64_t)threadIdx.x * 4;
+    unsigned long long v[4];
+    unsigned long long mine = 0;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      v[u] = i0 + u <= ns ? p.sub_off[i0 + u] : 0ull;
+      mine += v[u];
     }
-  }
-  __syncthreads();
-  unsigned long long run = part[threadIdx.x];
-  for (uint64_t i = a; i < b; ++i) {
-    run += p.sub_off[i];
-    p.sub_off[i] = run;
+    // exclusive prefix of the thread sums over the workgroup
+    unsigned long long inc = mine;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const unsigned long long t = __shfl_up(inc, o, 64);
+      if (lane >= o) inc += t;
+    }
+    if (lane == 63) s_wave[wave] = inc;
+    __syncthreads();
+    unsigned long long before = carry, total = carry;
+    for (int w = 0; w < LL_SCAN_TPB / 64; ++w) {
+      const unsigned long long x = s_wave[w];
+      before += w < wave ? x : 0ull;
+      total += x;
+    }
+    unsigned long long run = before + inc - mine;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      run += v[u];
+      if (i0 + u <= ns) p.sub_off[i0 + u] = run;
+    }
+    carry = total;
+    __syncthreads();
   }
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -216,6 +239,14 @@ constexpr int LL_WIN = 72;  // >= (31 + 64 * 33) / 32 + 2 words
 
 __global__ void __launch_bounds__(LL_TPB) k_llwrite(LLParams p) {
   __shared__ uint32_t s_win[LL_TPB / 64][LL_WIN];
+  __shared__ uint32_t s_rank[LL_LDS_RANKS];
+  const uint32_t K = 1u << p.B;
+  const bool lds = K <= (uint32_t)LL_LDS_RANKS;
+  if (lds) {
+    for (uint32_t i = threadIdx.x; i < K; i += LL_TPB) s_rank[i] = p.rank_of[i];
+    __syncthreads();
+  }
+  const uint32_t* rank_of = lds ? s_rank : p.rank_of;
   const uint64_t s = (uint64_t)blockIdx.x * (LL_TPB / 64) + threadIdx.x / 64;
   if (s >= p.n_sub) return;  // whole waves leave; no workgroup barrier below
   const int lane = lane_id();
@@ -233,7 +264,7 @@ __global__ void __launch_bounds__(LL_TPB) k_llwrite(LLParams p) {
     uint32_t len = 0;
     unsigned long long cw = 0;
     if (on) {
-      const uint32_t x = p.rank_of[ll_code(p.packed, j, p.B)] + (1u << k);
+      const uint32_t x = rank_of[ll_code(p.packed, j, p.B)] + (1u << k);
       const uint32_t nb = ll_log2(x);
       const uint32_t q = nb - k;
       cw = (1ull << q) | ((unsigned long long)(x ^ (1u << nb)) << (q + 1));
@@ -275,8 +306,16 @@ __global__ void k_llflags(uint32_t* flags) { *flags = 0u; }
 // sub-block, one of more than 33 bits or a rank of 2^B or more sets the flag
 // and ends the sub-block.
 __global__ void __launch_bounds__(LL_TPB) k_lldecode(LLDecodeParams p) {
+  __shared__ uint16_t s_code[LL_LDS_RANKS];
+  const uint32_t Kt = 1u << p.B;
+  const bool lds = Kt <= (uint32_t)LL_LDS_RANKS;
+  if (lds) {
+    for (uint32_t i = threadIdx.x; i < Kt; i += LL_TPB) s_code[i] = p.code_of_rank[i];
+    __syncthreads();
+  }
+  const uint16_t* code_of_rank = lds ? s_code : p.code_of_rank;
   const uint64_t s = (uint64_t)blockIdx.x * LL_TPB + threadIdx.x;
-  if (s >= p.n_sub) return;
+  if (s >= p.n_sub) return;  // no workgroup barrier below
   const uint64_t start = p.sub_off[s], end = p.sub_off[s + 1];
   if (start > end || end > p.stream_words * 32 || (start & 31) || (end & 31)) {
     atomicOr(p.flags, NUMARCK_FLAG_BAD_STREAM);
@@ -311,7 +350,7 @@ __global__ void __launch_bounds__(LL_TPB) k_lldecode(LLDecodeParams p) {
       atomicOr(p.flags, NUMARCK_FLAG_BAD_STREAM);
       return;
     }
-    ob |= (unsigned long long)p.code_of_rank[v] << on;
+    ob |= (unsigned long long)code_of_rank[v] << on;
     on += p.B;
     if (on >= 32) {
       p.packed[ow++] = (uint32_t)ob;
