@@ -59,22 +59,51 @@ __global__ void __launch_bounds__(LL_TPB) k_llclear(LLParams p) {
   if (i < 17) p.bits_k[i] = 0ull;
 }
 
+// Code counts.  Each lane takes 128 bits of the table per step (four words,
+// and the word after them for a code that runs past them) and counts the
+// codes that start in those bits: a step then moves 1 KiB per wave.
+__device__ __forceinline__ uint32_t ll_pick(uint32_t w0, uint32_t w1, uint32_t w2, uint32_t w3,
+                                            uint32_t w4, uint32_t i) {
+  return i == 0 ? w0 : i == 1 ? w1 : i == 2 ? w2 : i == 3 ? w3 : w4;
+}
+
 __global__ void __launch_bounds__(LL_TPB) k_llhist(LLParams p) {
   __shared__ uint32_t h[LL_LDS_BINS];
-  const uint32_t K = 1u << p.B;
+  const uint32_t K = 1u << p.B, B = p.B;
   const bool lds = K <= (uint32_t)LL_LDS_BINS;
   if (lds) {
     for (uint32_t i = threadIdx.x; i < K; i += LL_TPB) h[i] = 0u;
     __syncthreads();
   }
+  const uint64_t words = (p.n * B + 31) / 32;
+  const uint64_t chunks = (words + 3) / 4;
+  const uint32_t maxc = (128u + B - 1) / B;  // codes that can start in 128 bits
   // the loop bound is the workgroup's: lds_count needs the whole wave
-  for (uint64_t base = (uint64_t)blockIdx.x * LL_TPB; base < p.n;
+  for (uint64_t base = (uint64_t)blockIdx.x * LL_TPB; base < chunks;
        base += (uint64_t)gridDim.x * LL_TPB) {
-    const uint64_t j = base + threadIdx.x;
-    const bool on = j < p.n;
-    const uint32_t c = on ? ll_code(p.packed, j, p.B) : 0u;
-    if (lds) lds_count(h, on, c);
-    else if (on) atomicAdd(&p.counts[c], 1u);
+    const uint64_t t = base + threadIdx.x;
+    const bool live = t < chunks;
+    const uint64_t w0 = t * 4;
+    uint32_t w[5];
+#pragma unroll
+    for (int u = 0; u < 5; ++u) w[u] = live && w0 + u < words ? p.packed[w0 + u] : 0u;
+    // codes j with j * B in [128 t, 128 t + 128)
+    const uint64_t jlo = (t * 128 + B - 1) / B;
+    for (uint32_t i = 0; i < maxc; ++i) {
+      const uint64_t j = jlo + i;
+      const bool on = live && j < p.n && j * B < t * 128 + 128;
+      uint32_t c = 0;
+      if (on) {
+        const uint32_t off = (uint32_t)(j * B - t * 128);  // < 128
+        const uint32_t wi = off >> 5, sh = off & 31;
+        const unsigned long long two =
+            (unsigned long long)ll_pick(w[0], w[1], w[2], w[3], w[4], wi) |
+            ((unsigned long long)ll_pick(w[0], w[1], w[2], w[3], w[4], wi + 1) << 32);
+        c = (uint32_t)(two >> sh) & (K - 1u);
+      }
+      if (lds) lds_count(h, on, c);
+      else if (on) atomicAdd(&p.counts[c], 1u);
+    }
   }
   if (lds) {
     __syncthreads();
@@ -373,7 +402,8 @@ hipError_t launch_lossless_encode(const LLParams& p, hipStream_t s) {
   const uint32_t kb = (K + LL_TPB - 1) / LL_TPB;
   LL_LAUNCH(k_llclear, kb, LL_TPB, p);
   if (p.n) {
-    uint64_t hb = (p.n + LL_TPB - 1) / LL_TPB;
+    const uint64_t chunks = ((p.n * p.B + 31) / 32 + 3) / 4;
+    uint64_t hb = (chunks + LL_TPB - 1) / LL_TPB;
     const uint64_t cap = (uint64_t)geometry().cus * 8;
     hb = hb < cap ? hb : cap;
     LL_LAUNCH(k_llhist, hb, LL_TPB, p);
