@@ -15,6 +15,13 @@
  *     recorded so that any range can be decompressed on its own (Sec. IV-C)
  *   - decompression multiplies the previous value by one plus the bin centre
  *     of its index (eq. 4, Sec. III-E), fully or for a range (Sec. V-C).
+ * Around that path: the choice of B from the histogram (eqs. 5-6,
+ * numarck_compress_auto), bins anchored at -E that need no range pass
+ * (numarck_compress_zero_anchored, numarck_plan_create_zero_anchored),
+ * equal-width binning (Sec. III-B, IV-B-3, numarck_compress_equal_width),
+ * batches and plans of many compressions, a serving loop, and a lossless
+ * stage for the index table in place of the paper's ZLIB
+ * (numarck_lossless_encode / numarck_lossless_decode).
  *
  * Conventions shared by every entry point:
  *   - All data buffers are device memory owned by the caller.  The
