@@ -189,4 +189,18 @@ def test_za_plans(nk):
         pn, qn = to_np(p), to_np(q)
         assert_matches_oracle(nk, res[i], orc.compress(pn, qn, E, B, binning="zero_anchored"),
                               pn, qn, E, B, check_hist=False, label=f"za plan job {i}")
+    # captured as a HIP graph and replayed, with eager work between replays
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        plan.capture(s)
+    for rep in range(3):
+        with torch.cuda.stream(s):
+            res = plan.replay(s)
+        torch.cuda.current_stream().wait_stream(s)
+        torch.cuda.synchronize()
+        _ = (jobs[0][0] * 2).sum().item()  # eager work between replays
+        for i, ((p, q, E, B), c) in enumerate(zip(jobs, res)):
+            ref = nk.compress_zero_anchored(p, q, E, B, recon=True, bin_ids=True)
+            assert_same_compression(c, ref, f"za graph job {i} replay {rep}")
     plan.close()
