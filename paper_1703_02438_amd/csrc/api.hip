@@ -382,6 +382,7 @@ numarck_status numarck_lossless_decode(const numarck_lossless_header* hdr,
   if (hdr->n >= ((uint64_t)1 << 32) || hdr->k > hdr->B ||
       hdr->n_sub != numarck_lossless_subblocks(hdr->n) || (hdr->n && (!stream || !packed)))
     return NUMARCK_EINVAL;
+  if (((uintptr_t)stream & 15u) || ((uintptr_t)packed & 15u)) return NUMARCK_EALIGN;
   LLDecodeParams p{};
   p.n = hdr->n;
   p.n_sub = hdr->n_sub;

@@ -357,13 +357,50 @@ __global__ void __launch_bounds__(LL_TPB) k_lldecode(LLDecodeParams p) {
   uint32_t nbits = 0;
   const uint64_t j0 = s * LL_SUB;
   const uint64_t j1 = j0 + LL_SUB < p.n ? j0 + LL_SUB : p.n;
-  uint64_t ow = j0 * p.B / 32;
+  uint64_t ow = j0 * p.B / 32;  // a multiple of 4: sub-blocks span 32 B words
   unsigned long long ob = 0;
   uint32_t on = 0;
+  // Each lane walks its own stretch of memory, so the stream is read and the
+  // table written 16 bytes at a time: the words of the aligned group holding
+  // iw (c0..c3 from word cb; a group reaching past the sub-block is read word
+  // by word), and completed output words gathered four at a time.
+  uint64_t cb = iw & ~3ull;
+  uint32_t c0 = 0, c1 = 0, c2 = 0, c3 = 0;
+  auto load_group = [&]() {
+    if (cb + 4 <= ew) {
+      const uint4 g = *reinterpret_cast<const uint4*>(p.stream + cb);
+      c0 = g.x; c1 = g.y; c2 = g.z; c3 = g.w;
+    } else {
+      c0 = cb < ew ? p.stream[cb] : 0u;
+      c1 = cb + 1 < ew ? p.stream[cb + 1] : 0u;
+      c2 = cb + 2 < ew ? p.stream[cb + 2] : 0u;
+      c3 = cb + 3 < ew ? p.stream[cb + 3] : 0u;
+    }
+  };
+  if (iw < ew) load_group();
+  uint32_t o0 = 0, o1 = 0, o2 = 0, o3 = 0, oc = 0;
+  auto put_word = [&](uint32_t w) {
+    o0 = oc == 0 ? w : o0;
+    o1 = oc == 1 ? w : o1;
+    o2 = oc == 2 ? w : o2;
+    o3 = oc == 3 ? w : o3;
+    if (++oc == 4) {
+      *reinterpret_cast<uint4*>(p.packed + ow) = make_uint4(o0, o1, o2, o3);
+      ow += 4;
+      oc = 0;
+    }
+  };
   for (uint64_t j = j0; j < j1; ++j) {
     while (nbits <= 32 && iw < ew) {
-      buf |= (unsigned long long)p.stream[iw++] << nbits;
+      if (iw >= cb + 4) {
+        cb += 4;
+        load_group();
+      }
+      const uint32_t d = (uint32_t)(iw - cb);
+      const uint32_t w = d == 0 ? c0 : d == 1 ? c1 : d == 2 ? c2 : c3;
+      buf |= (unsigned long long)w << nbits;
       nbits += 32;
+      ++iw;
     }
     const uint32_t q = buf ? (uint32_t)__builtin_ctzll(buf) : 64u;
     const uint32_t nb = q + k;
@@ -382,12 +419,15 @@ __global__ void __launch_bounds__(LL_TPB) k_lldecode(LLDecodeParams p) {
     ob |= (unsigned long long)code_of_rank[v] << on;
     on += p.B;
     if (on >= 32) {
-      p.packed[ow++] = (uint32_t)ob;
+      put_word((uint32_t)ob);
       ob >>= 32;
       on -= 32;
     }
   }
-  if (on) p.packed[ow] = (uint32_t)ob;
+  if (oc > 0) p.packed[ow] = o0;
+  if (oc > 1) p.packed[ow + 1] = o1;
+  if (oc > 2) p.packed[ow + 2] = o2;
+  if (on) p.packed[ow + oc] = (uint32_t)ob;
 }
 
 #define LL_LAUNCH(kern, grid, block, ...)                                     \

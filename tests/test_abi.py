@@ -256,3 +256,7 @@ def test_lossless_validation_without_gpu(nk):
     assert dec(h) == nk.EINVAL  # n_sub inconsistent with n
     h.n_sub, h.B = 1, 0
     assert dec(h) == nk.EBITS
+    h.B = 8
+    misaligned = m.numarck_lossless_decode(ctypes.byref(h), 0x400000, 0x500000, 0x600004,
+                                           0x800000, 0x900000, None)
+    assert misaligned == nk.EALIGN
