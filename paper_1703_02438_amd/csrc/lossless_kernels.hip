@@ -261,10 +261,11 @@ __global__ void __launch_bounds__(LL_SCAN_TPB) k_llscan(LLParams p) {
 
 // Sub-block s's codewords, from word sub_off[s] / 32 on.  One wave per
 // sub-block, 64 consecutive codes per round: a prefix sum of the codeword
-// lengths places each codeword in a wave-private LDS window (ORed into at
-// most two words), the completed words go out, and the partial last word
-// stays as the next round's first.
-constexpr int LL_WIN = 72;  // >= (31 + 64 * 33) / 32 + 2 words
+// lengths places each codeword in the wave's LDS copy of the sub-block's
+// stream (ORed into at most two words; ORs commute, so rounds need no
+// ordering), and the wave stores the finished copy with consecutive lanes on
+// consecutive words.
+constexpr int LL_WIN = (LL_SUB * 33 + 31) / 32 + 1;  // words of the longest sub-block
 
 __global__ void __launch_bounds__(LL_TPB) k_llwrite(LLParams p) {
   __shared__ uint32_t s_win[LL_TPB / 64][LL_WIN];
@@ -283,10 +284,11 @@ __global__ void __launch_bounds__(LL_TPB) k_llwrite(LLParams p) {
   const uint32_t k = *p.order;
   const uint64_t j0 = s * LL_SUB;
   const uint64_t j1 = j0 + LL_SUB < p.n ? j0 + LL_SUB : p.n;
+  const uint64_t gw = p.sub_off[s] / 32;
+  const uint32_t words = (uint32_t)(p.sub_off[s + 1] / 32 - gw);  // <= LL_WIN - 1
   for (int i = lane; i < LL_WIN; i += 64) win[i] = 0u;
   wave_lds_sync();
-  uint64_t gw = p.sub_off[s] / 32;  // global word of window slot 0
-  uint32_t off = 0;                 // bits already in slot 0
+  uint32_t off = 0;  // bits placed so far
   for (uint64_t jb = j0; jb < j1; jb += 64) {
     const uint64_t j = jb + lane;
     const bool on = j < j1;
@@ -306,27 +308,16 @@ __global__ void __launch_bounds__(LL_TPB) k_llwrite(LLParams p) {
       const uint32_t t = __shfl_up(inc, o, 64);
       if (lane >= o) inc += t;
     }
-    const uint32_t total = __shfl(inc, 63, 64);
     if (on) {
       const uint32_t pos = off + inc - len;
       const uint32_t w = pos >> 5, sh = pos & 31;
       atomicOr(&win[w], (uint32_t)(cw << sh));
       if (sh + len > 32) atomicOr(&win[w + 1], (uint32_t)((cw << sh) >> 32));
     }
-    wave_lds_sync();
-    const uint32_t end = off + total;
-    const uint32_t full = end >> 5;
-    for (uint32_t i = lane; i < full; i += 64) p.stream[gw + i] = win[i];
-    const uint32_t carry = win[full];
-    wave_lds_sync();
-    for (int i = lane; i < LL_WIN; i += 64) win[i] = 0u;
-    wave_lds_sync();
-    if (lane == 0) win[0] = carry;
-    wave_lds_sync();
-    gw += full;
-    off = end & 31;
+    off += __shfl(inc, 63, 64);
   }
-  if (off && lane == 0) p.stream[gw] = win[0];
+  wave_lds_sync();
+  for (uint32_t i = lane; i < words; i += 64) p.stream[gw + i] = win[i];
 }
 
 __global__ void k_llflags(uint32_t* flags) { *flags = 0u; }
