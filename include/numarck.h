@@ -21,7 +21,7 @@
  * equal-width binning (Sec. III-B, IV-B-3, numarck_compress_equal_width),
  * batches and plans of many compressions, a serving loop, and a lossless
  * stage for the index table in place of the paper's ZLIB
- * (numarck_lossless_encode / numarck_lossless_decode).
+ * (numarck_lossless_encode / numarck_lossless_decode / _decode_range).
  *
  * Conventions shared by every entry point:
  *   - All data buffers are device memory owned by the caller.  The
@@ -502,6 +502,21 @@ numarck_status numarck_lossless_decode(const numarck_lossless_header* hdr,
                                        const uint16_t* code_of_rank, const uint64_t* sub_off,
                                        const uint32_t* stream, uint32_t* packed, uint32_t* flags,
                                        void* stream_);
+
+/* Partial decoding (the lossless counterpart of Sec. IV-C's independent
+ * blocks): sub-blocks [sub_begin, sub_begin + sub_count) only, each written
+ * to its own place in the full-size table `packed`; the rest of `packed` is
+ * not touched.  Sub-block s holds codes [1024 s, 1024 (s + 1)).  For
+ * numarck_decompress_range of [start, start + len) decode the sub-blocks
+ * covering the codes from the start of start's index-table block
+ * (floor(start / elems_per_block) * elems_per_block) to start + len.
+ * Errors as numarck_lossless_decode, plus NUMARCK_ERANGE when the
+ * sub-blocks run past n_sub. */
+numarck_status numarck_lossless_decode_range(const numarck_lossless_header* hdr,
+                                             const uint16_t* code_of_rank,
+                                             const uint64_t* sub_off, const uint32_t* stream,
+                                             uint64_t sub_begin, uint64_t sub_count,
+                                             uint32_t* packed, uint32_t* flags, void* stream_);
 
 #ifdef __cplusplus
 }

@@ -377,15 +377,28 @@ numarck_status numarck_lossless_decode(const numarck_lossless_header* hdr,
                                        const uint16_t* code_of_rank, const uint64_t* sub_off,
                                        const uint32_t* stream, uint32_t* packed, uint32_t* flags,
                                        void* stream_) {
+  if (!hdr) return NUMARCK_EINVAL;
+  return numarck_lossless_decode_range(hdr, code_of_rank, sub_off, stream, 0, hdr->n_sub, packed,
+                                       flags, stream_);
+}
+
+numarck_status numarck_lossless_decode_range(const numarck_lossless_header* hdr,
+                                             const uint16_t* code_of_rank,
+                                             const uint64_t* sub_off, const uint32_t* stream,
+                                             uint64_t sub_begin, uint64_t sub_count,
+                                             uint32_t* packed, uint32_t* flags, void* stream_) {
   if (!hdr || !code_of_rank || !sub_off || !flags) return NUMARCK_EINVAL;
   if (hdr->B < 1 || hdr->B > 16) return NUMARCK_EBITS;
   if (hdr->n >= ((uint64_t)1 << 32) || hdr->k > hdr->B ||
       hdr->n_sub != numarck_lossless_subblocks(hdr->n) || (hdr->n && (!stream || !packed)))
     return NUMARCK_EINVAL;
   if (((uintptr_t)stream & 15u) || ((uintptr_t)packed & 15u)) return NUMARCK_EALIGN;
+  if (sub_begin > hdr->n_sub || sub_count > hdr->n_sub - sub_begin) return NUMARCK_ERANGE;
   LLDecodeParams p{};
   p.n = hdr->n;
   p.n_sub = hdr->n_sub;
+  p.s_begin = sub_begin;
+  p.s_end = sub_begin + sub_count;
   p.stream_words = hdr->stream_words;
   p.B = hdr->B;
   p.k = hdr->k;

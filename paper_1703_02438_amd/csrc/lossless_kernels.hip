@@ -334,8 +334,8 @@ __global__ void __launch_bounds__(LL_TPB) k_lldecode(LLDecodeParams p) {
     __syncthreads();
   }
   const uint16_t* code_of_rank = lds ? s_code : p.code_of_rank;
-  const uint64_t s = (uint64_t)blockIdx.x * LL_TPB + threadIdx.x;
-  if (s >= p.n_sub) return;  // no workgroup barrier below
+  const uint64_t s = p.s_begin + (uint64_t)blockIdx.x * LL_TPB + threadIdx.x;
+  if (s >= p.s_end) return;  // no workgroup barrier below
   const uint64_t start = p.sub_off[s], end = p.sub_off[s + 1];
   if (start > end || end > p.stream_words * 32 || (start & 31) || (end & 31)) {
     atomicOr(p.flags, NUMARCK_FLAG_BAD_STREAM);
@@ -450,7 +450,7 @@ hipError_t launch_lossless_encode(const LLParams& p, hipStream_t s) {
 
 hipError_t launch_lossless_decode(const LLDecodeParams& p, hipStream_t s) {
   LL_LAUNCH(k_llflags, 1, 1, p.flags);
-  const uint64_t sb = (p.n_sub + LL_TPB - 1) / LL_TPB;
+  const uint64_t sb = (p.s_end - p.s_begin + LL_TPB - 1) / LL_TPB;
   if (sb) LL_LAUNCH(k_lldecode, sb, LL_TPB, p);
   return hipSuccess;
 }

@@ -321,6 +321,7 @@ struct LLParams {
 };
 struct LLDecodeParams {
   uint64_t n, n_sub, stream_words;
+  uint64_t s_begin, s_end;  // the sub-blocks to decode
   uint32_t B, k;
   const uint16_t* code_of_rank;
   const uint64_t* sub_off;

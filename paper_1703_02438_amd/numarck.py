@@ -155,6 +155,9 @@ numarck_lossless_encode = _bind("numarck_lossless_encode", _i,
 numarck_lossless_decode = _bind("numarck_lossless_decode", _i,
                                 [ctypes.POINTER(NumarckLosslessHeader), _vp, _vp, _vp, _vp, _vp,
                                  _vp])
+numarck_lossless_decode_range = _bind("numarck_lossless_decode_range", _i,
+                                      [ctypes.POINTER(NumarckLosslessHeader), _vp, _vp, _vp,
+                                       _u64, _u64, _vp, _vp, _vp])
 numarck_compress_zero_anchored = _bind("numarck_compress_zero_anchored", _i,
                                        [_vp, _vp, _u64, _i, _d, _u32, _u64,
                                         ctypes.POINTER(NumarckOut), _vp, _sz, _vp])
@@ -491,6 +494,22 @@ def lossless_decode(enc: Lossless, out: torch.Tensor | None = None, stream=None)
                                 _ptr(enc.stream), _ptr(out), _ptr(flags), _stream(stream))
     _check(r, "numarck_lossless_decode")
     return out[:words], flags
+
+
+def lossless_decode_codes(enc: Lossless, first: int, last: int, out: torch.Tensor, stream=None):
+    """Decode only the sub-blocks holding codes [first, last) into their places
+    in the full-size table `out` (numarck_lossless_decode_range); returns the
+    flags tensor."""
+    h = enc.header()
+    sb = 1024
+    s0 = first // sb
+    s1 = min((last + sb - 1) // sb, h.n_sub) if last > first else s0
+    flags = torch.zeros(1, dtype=torch.int32, device=out.device)
+    r = numarck_lossless_decode_range(ctypes.byref(h), _ptr(enc.code_of_rank), _ptr(enc.sub_off),
+                                      _ptr(enc.stream), s0, s1 - s0, _ptr(out), _ptr(flags),
+                                      _stream(stream))
+    _check(r, "numarck_lossless_decode_range")
+    return flags
 
 
 class ClosedLoop:

@@ -260,3 +260,6 @@ def test_lossless_validation_without_gpu(nk):
     misaligned = m.numarck_lossless_decode(ctypes.byref(h), 0x400000, 0x500000, 0x600004,
                                            0x800000, 0x900000, None)
     assert misaligned == nk.EALIGN
+    rng = lambda b, c: m.numarck_lossless_decode_range(ctypes.byref(h), 0x400000, 0x500000,
+                                                       0x600000, b, c, 0x800000, 0x900000, None)
+    assert rng(0, 2) == nk.ERANGE and rng(2, 0) == nk.ERANGE and rng(1 << 63, 1 << 63) == nk.ERANGE

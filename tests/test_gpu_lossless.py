@@ -119,3 +119,32 @@ def test_lossless_corrupt_stream_flagged(nk):
     e2.sub_off[1] = 1 << 40
     _, fl = nk.lossless_decode(e2)
     assert int(fl.item()) & nk.FLAG_BAD_STREAM
+
+
+def test_lossless_partial_decode_then_range(nk):
+    """Partial decompression through the lossless stage: only the sub-blocks
+    from the start of the range's index-table block to its end are decoded,
+    and the range decompressed from that partial table equals the range
+    decompressed from the full table; words outside those sub-blocks stay
+    untouched."""
+    prev, curr = mixture_case(300_001, 99)
+    p = torch.from_numpy(prev).cuda()
+    q = torch.from_numpy(curr).cuda()
+    B, bb = 8, 4096
+    c = nk.compress(p, q, 1e-3, B, bb)
+    n = p.numel()
+    enc = nk.lossless_encode(c.packed, n, B)
+    epb = c.header().elems_per_block
+    for s, ln in ((0, 10), (123_456, 5_000), (299_990, 11), (40_960, 4096), (77_777, 0)):
+        first = (s // epb) * epb
+        table = torch.zeros_like(c.packed)
+        fl = nk.lossless_decode_codes(enc, first, s + ln, table)
+        assert int(fl.item()) == 0
+        c2 = nk.Compressed(table, c.centers, c.incomp, c.block_inc_off, None, None, c.hdr, None,
+                           c.n, c.dtype)
+        a, afl = nk.decompress_range(c, p, s, ln)
+        b, bfl = nk.decompress_range(c2, p, s, ln)
+        assert int(afl.item()) == int(bfl.item()) == 0
+        assert torch.equal(a[:ln].view(torch.int64), b[:ln].view(torch.int64)), (s, ln)
+        w0 = (first // 1024) * 1024 * B // 32
+        assert int(table[:w0].abs().sum().item()) == 0, (s, ln)
