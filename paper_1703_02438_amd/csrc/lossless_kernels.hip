@@ -78,7 +78,8 @@ __global__ void __launch_bounds__(LL_TPB) k_llhist(LLParams p) {
   const uint64_t words = (p.n * B + 31) / 32;
   const uint64_t chunks = (words + 3) / 4;
   const uint32_t maxc = (128u + B - 1) / B;  // codes that can start in 128 bits
-  // the loop bound is the workgroup's: lds_count needs the whole wave
+  // plain LDS atomics: the codes of a wave are spread over many values, and
+  // aggregating the first lane's value first cost more than it saved
   for (uint64_t base = (uint64_t)blockIdx.x * LL_TPB; base < chunks;
        base += (uint64_t)gridDim.x * LL_TPB) {
     const uint64_t t = base + threadIdx.x;
@@ -101,8 +102,7 @@ __global__ void __launch_bounds__(LL_TPB) k_llhist(LLParams p) {
             ((unsigned long long)ll_pick(w[0], w[1], w[2], w[3], w[4], wi + 1) << 32);
         c = (uint32_t)(two >> sh) & (K - 1u);
       }
-      if (lds) lds_count(h, on, c);
-      else if (on) atomicAdd(&p.counts[c], 1u);
+      if (on) atomicAdd(lds ? &h[c] : &p.counts[c], 1u);
     }
   }
   if (lds) {
