@@ -40,18 +40,6 @@ __device__ __forceinline__ uint32_t ll_len(uint32_t v, uint32_t k) {
   return 2u * ll_log2(v + (1u << k)) - k + 1u;
 }
 
-// Code j of a B-bit table (the word after j's first word exists whenever the
-// code reaches into it).
-__device__ __forceinline__ uint32_t ll_code(const uint32_t* __restrict__ packed, uint64_t j,
-                                            uint32_t B) {
-  const uint64_t bit = j * B;
-  const uint64_t w = bit >> 5;
-  const uint32_t sh = (uint32_t)(bit & 31);
-  uint32_t v = packed[w] >> sh;
-  if (sh + B > 32) v |= packed[w + 1] << (32 - sh);
-  return v & ((1u << B) - 1u);
-}
-
 __global__ void __launch_bounds__(LL_TPB) k_llclear(LLParams p) {
   const uint32_t K = 1u << p.B;
   const uint32_t i = blockIdx.x * LL_TPB + threadIdx.x;
@@ -66,6 +54,35 @@ __device__ __forceinline__ uint32_t ll_pick(uint32_t w0, uint32_t w1, uint32_t w
                                             uint32_t w4, uint32_t i) {
   return i == 0 ? w0 : i == 1 ? w1 : i == 2 ? w2 : i == 3 ? w3 : w4;
 }
+
+// The 128-bit chunk t of sub-block s: words (plus the one after, for a code
+// that runs past them) and the range [a, b) of the sub-block's codes that
+// start in it.
+struct SubChunk {
+  uint32_t w[5];
+  uint32_t a, b;
+  __device__ __forceinline__ void load(const uint32_t* packed, uint64_t words, uint64_t ws,
+                                       uint32_t t, uint32_t ncode, uint32_t B) {
+#pragma unroll
+    for (int u = 0; u < 5; ++u) {
+      const uint64_t i = ws + 4ull * t + u;
+      w[u] = i < words ? packed[i] : 0u;
+    }
+    a = (t * 128u + B - 1) / B;
+    b = ((t + 1) * 128u + B - 1) / B;
+    a = a < ncode ? a : ncode;
+    b = b < ncode ? b : ncode;
+  }
+  // code a + i (i < b - a)
+  __device__ __forceinline__ uint32_t code(uint32_t t, uint32_t i, uint32_t B) const {
+    const uint32_t off = (a + i) * B - t * 128u;  // < 128
+    const uint32_t wi = off >> 5, sh = off & 31;
+    const unsigned long long two =
+        (unsigned long long)ll_pick(w[0], w[1], w[2], w[3], w[4], wi) |
+        ((unsigned long long)ll_pick(w[0], w[1], w[2], w[3], w[4], wi + 1) << 32);
+    return (uint32_t)(two >> sh) & ((1u << B) - 1u);
+  }
+};
 
 __global__ void __launch_bounds__(LL_TPB) k_llhist(LLParams p) {
   __shared__ uint32_t h[LL_LDS_BINS];
@@ -173,8 +190,8 @@ __global__ void __launch_bounds__(LL_ORD_TPB) k_llorder(LLParams p) {
 }
 
 // Bits of sub-block s, rounded up to a word, into sub_off[s + 1].  One wave
-// per sub-block; in round i lane l takes code j0 + 64 i + l, so each round
-// reads 64 consecutive codes.
+// per sub-block; each lane takes the codes that start in its 128-bit chunks
+// of the sub-block's words (16-byte loads).
 __global__ void __launch_bounds__(LL_TPB) k_llsub(LLParams p) {
   __shared__ uint32_t s_rank[LL_LDS_RANKS];
   const uint32_t K = 1u << p.B;
@@ -190,10 +207,14 @@ __global__ void __launch_bounds__(LL_TPB) k_llsub(LLParams p) {
   const uint32_t k = *p.order;
   const uint64_t j0 = s * LL_SUB;
   const uint64_t j1 = j0 + LL_SUB < p.n ? j0 + LL_SUB : p.n;
+  const uint32_t B = p.B, ncode = (uint32_t)(j1 - j0);
+  const uint64_t ws = j0 * B / 32, words = (p.n * B + 31) / 32;
+  const uint32_t nch = (ncode * B + 127) / 128;
   unsigned long long bits = 0;
-  for (uint64_t jb = j0; jb < j1; jb += 64) {
-    const uint64_t j = jb + lane;
-    if (j < j1) bits += ll_len(rank_of[ll_code(p.packed, j, p.B)], k);
+  for (uint32_t t = lane; t < nch; t += 64) {
+    SubChunk ch;
+    ch.load(p.packed, words, ws, t, ncode, B);
+    for (uint32_t i = 0; i < ch.b - ch.a; ++i) bits += ll_len(rank_of[ch.code(t, i, B)], k);
   }
   bits = wave_sum_u64(bits);
   if (lane == 0) p.sub_off[s + 1] = (bits + 31) / 32 * 32;
@@ -260,11 +281,11 @@ __global__ void __launch_bounds__(LL_SCAN_TPB) k_llscan(LLParams p) {
 }
 
 // Sub-block s's codewords, from word sub_off[s] / 32 on.  One wave per
-// sub-block, 64 consecutive codes per round: a prefix sum of the codeword
-// lengths places each codeword in the wave's LDS copy of the sub-block's
-// stream (ORed into at most two words; ORs commute, so rounds need no
-// ordering), and the wave stores the finished copy with consecutive lanes on
-// consecutive words.
+// sub-block, each lane a 128-bit chunk of the table per round: a wave prefix
+// sum of the lanes' codeword bits places each lane's codewords, in order, in
+// the wave's LDS copy of the sub-block's stream (ORed into at most two words
+// each; ORs commute, so rounds need no ordering), and the wave stores the
+// finished copy with consecutive lanes on consecutive words.
 constexpr int LL_WIN = (LL_SUB * 33 + 31) / 32 + 1;  // words of the longest sub-block
 
 __global__ void __launch_bounds__(LL_TPB) k_llwrite(LLParams p) {
@@ -288,31 +309,36 @@ __global__ void __launch_bounds__(LL_TPB) k_llwrite(LLParams p) {
   const uint32_t words = (uint32_t)(p.sub_off[s + 1] / 32 - gw);  // <= LL_WIN - 1
   for (int i = lane; i < LL_WIN; i += 64) win[i] = 0u;
   wave_lds_sync();
+  const uint32_t B = p.B, ncode = (uint32_t)(j1 - j0);
+  const uint64_t ws = j0 * B / 32, twords = (p.n * B + 31) / 32;
+  const uint32_t nch = (ncode * B + 127) / 128;
   uint32_t off = 0;  // bits placed so far
-  for (uint64_t jb = j0; jb < j1; jb += 64) {
-    const uint64_t j = jb + lane;
-    const bool on = j < j1;
-    uint32_t len = 0;
-    unsigned long long cw = 0;
-    if (on) {
-      const uint32_t x = rank_of[ll_code(p.packed, j, p.B)] + (1u << k);
-      const uint32_t nb = ll_log2(x);
-      const uint32_t q = nb - k;
-      cw = (1ull << q) | ((unsigned long long)(x ^ (1u << nb)) << (q + 1));
-      len = q + 1 + nb;
-    }
-    // inclusive prefix sum of the lengths over the wave
-    uint32_t inc = len;
+  for (uint32_t t0 = 0; t0 < nch; t0 += 64) {
+    const uint32_t t = t0 + lane;
+    SubChunk ch;
+    ch.a = ch.b = 0;
+    if (t < nch) ch.load(p.packed, twords, ws, t, ncode, B);
+    uint32_t mine = 0;
+    for (uint32_t i = 0; i < ch.b - ch.a; ++i) mine += ll_len(rank_of[ch.code(t, i, B)], k);
+    // inclusive prefix sum of the lanes' bits over the wave
+    uint32_t inc = mine;
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
-      const uint32_t t = __shfl_up(inc, o, 64);
-      if (lane >= o) inc += t;
+      const uint32_t v = __shfl_up(inc, o, 64);
+      if (lane >= o) inc += v;
     }
-    if (on) {
-      const uint32_t pos = off + inc - len;
+    uint32_t pos = off + inc - mine;
+    for (uint32_t i = 0; i < ch.b - ch.a; ++i) {
+      const uint32_t x = rank_of[ch.code(t, i, B)] + (1u << k);
+      const uint32_t nb = ll_log2(x);
+      const uint32_t q = nb - k;
+      const unsigned long long cw =
+          (1ull << q) | ((unsigned long long)(x ^ (1u << nb)) << (q + 1));
+      const uint32_t len = q + 1 + nb;
       const uint32_t w = pos >> 5, sh = pos & 31;
       atomicOr(&win[w], (uint32_t)(cw << sh));
       if (sh + len > 32) atomicOr(&win[w + 1], (uint32_t)((cw << sh) >> 32));
+      pos += len;
     }
     off += __shfl(inc, 63, 64);
   }
