@@ -33,6 +33,7 @@ constexpr int LL_LDS_BINS = 8192;   // code counts kept in LDS up to this many c
 constexpr int LL_ORD_TPB = 1024;
 constexpr int LL_LDS_RANKS = 1024;  // rank / code tables kept in LDS up to this many codes (small: occupancy)
 constexpr int LL_SCAN_TPB = 1024;
+constexpr int LL_SCAN_PER = 4;  // offsets per thread and tile (16 was twice as slow)
 
 __device__ __forceinline__ uint32_t ll_log2(uint32_t x) { return 31u - (uint32_t)__clz(x); }
 
@@ -221,19 +222,19 @@ __global__ void __launch_bounds__(LL_TPB) k_llsub(LLParams p) {
 }
 
 // Inclusive scan of sub_off[1..n_sub] in place (one workgroup, tiles of
-// LL_SCAN_TPB * 4 entries, each thread four consecutive ones), then the
-// header.
+// LL_SCAN_TPB * LL_SCAN_PER entries, each thread LL_SCAN_PER consecutive
+// ones), then the header.
 __global__ void __launch_bounds__(LL_SCAN_TPB) k_llscan(LLParams p) {
   __shared__ unsigned long long s_wave[LL_SCAN_TPB / 64];
   const uint64_t ns = p.n_sub;
   const int lane = lane_id(), wave = threadIdx.x / 64;
   unsigned long long carry = 0;
-  for (uint64_t t0 = 1; t0 <= ns; t0 += (uint64_t)LL_SCAN_TPB * 4) {
-    const uint64_t i0 = t0 + (uint64_t)threadIdx.x * 4;
-    unsigned long long v[4];
+  for (uint64_t t0 = 1; t0 <= ns; t0 += (uint64_t)LL_SCAN_TPB * LL_SCAN_PER) {
+    const uint64_t i0 = t0 + (uint64_t)threadIdx.x * LL_SCAN_PER;
+    unsigned long long v[LL_SCAN_PER];
     unsigned long long mine = 0;
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < LL_SCAN_PER; ++u) {
       v[u] = i0 + u <= ns ? p.sub_off[i0 + u] : 0ull;
       mine += v[u];
     }
@@ -254,7 +255,7 @@ __global__ void __launch_bounds__(LL_SCAN_TPB) k_llscan(LLParams p) {
     }
     unsigned long long run = before + inc - mine;
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < LL_SCAN_PER; ++u) {
       run += v[u];
       if (i0 + u <= ns) p.sub_off[i0 + u] = run;
     }
