@@ -20,9 +20,10 @@
 // counting the codes before it), k_llorder (bits of every order, the
 // choice), k_llsub (bits of every sub-block), k_llscan (offsets and the
 // header), k_llwrite.  Decode: k_llflags, k_lldecode.  The encoder's
-// per-sub-block passes give each sub-block to a wave (64 consecutive codes
-// per round); the decoder gives it to one lane, which walks its codewords in
-// order (where a codeword starts is known only after the one before).
+// per-sub-block passes give each sub-block to a wave (each lane a 128-bit
+// chunk of the table per round); the decoder gives it to one lane, which
+// walks its codewords in order (where a codeword starts is known only after
+// the one before).
 #include "nk_device.h"
 
 namespace nk {
