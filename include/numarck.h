@@ -232,6 +232,31 @@ numarck_status numarck_decompress_range(const numarck_header* hdr, const void* p
                                         uint32_t* flags, void* ws, size_t ws_bytes,
                                         void* stream);
 
+/* ---- partial decompression that allocates nothing ----
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * operation, arguments, result and flags as numarck_decompress_range, with no
+ * workspace argument.  The workspace is a device-global array of the library
+ * (numarck_static_scratch_bytes() bytes, one copy per device, held until the
+ * process ends); its device address is looked up once per device with
+ * hipGetSymbolAddress on the first call made with that device current.  The
+ * stream must belong to the current device.  The call never allocates:
+ * no hipMalloc, no hipFree, no allocating library routine.
+ * Every call on one device shares that device's array: calls that overlap on
+ * one device (different streams, or different host threads, without ordering
+ * between them) race and give undefined results.  Calls ordered on one stream
+ * are safe; everything the array holds is written before it is read.
+ * NUMARCK_ECAPACITY (with numarck_last_error() saying so) if the call's
+ * workspace would exceed the array; the decompression workspace does not
+ * grow with len, so this cannot happen for a valid header. */
+size_t numarck_static_scratch_bytes(void);
+numarck_status numarck_decompress_range_noalloc(const numarck_header* hdr, const void* prev,
+                                                const uint32_t* packed, const void* centers,
+                                                const void* incomp,
+                                                const int64_t* block_inc_off, uint64_t start,
+                                                uint64_t len, void* out, uint32_t* flags,
+                                                void* stream);
+
 /* ---- inspection of the last compression's histogram (Sec. IV-B-1) ----
  * After numarck_compress on the same workspace, size and dtype and on the same
  * stream, writes the nonzero fine bins (id, count), in no particular order, to

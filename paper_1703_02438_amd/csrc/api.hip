@@ -960,17 +960,30 @@ static numarck_status check_header(const numarck_header* h) {
   return NUMARCK_OK;
 }
 
+// Argument checks of a (range) decompression, the workspace aside.
+static numarck_status check_decompress_args(const numarck_header* hdr, const void* prev,
+                                            const uint32_t* packed, const void* centers,
+                                            const void* incomp, const int64_t* block_inc_off,
+                                            uint64_t start, uint64_t len, const void* out,
+                                            const uint32_t* flags) {
+  numarck_status st = check_header(hdr);
+  if (st != NUMARCK_OK) return st;
+  if (start > hdr->n || len > hdr->n - start) return NUMARCK_ERANGE;
+  if (!flags) return NUMARCK_EINVAL;
+  if (len > 0 && (!prev || !packed || !centers || !out || !block_inc_off)) return NUMARCK_EINVAL;
+  if (len > 0 && hdr->n_inc > 0 && !incomp) return NUMARCK_EINVAL;
+  return NUMARCK_OK;
+}
+
 static numarck_status decompress_impl(const numarck_header* hdr, const void* prev,
                                       const uint32_t* packed, const void* centers,
                                       const void* incomp, const int64_t* block_inc_off,
                                       uint64_t start, uint64_t len, void* out, uint32_t* flags,
                                       void* ws, size_t ws_bytes, void* stream) {
-  numarck_status st = check_header(hdr);
+  numarck_status st = check_decompress_args(hdr, prev, packed, centers, incomp, block_inc_off,
+                                            start, len, out, flags);
   if (st != NUMARCK_OK) return st;
-  if (start > hdr->n || len > hdr->n - start) return NUMARCK_ERANGE;
-  if (!flags || !ws) return NUMARCK_EINVAL;
-  if (len > 0 && (!prev || !packed || !centers || !out || !block_inc_off)) return NUMARCK_EINVAL;
-  if (len > 0 && hdr->n_inc > 0 && !incomp) return NUMARCK_EINVAL;
+  if (!ws) return NUMARCK_EINVAL;
   if (((uintptr_t)ws & 255u) != 0) return NUMARCK_EALIGN;
   size_t cnt_off = 0, pre_off = 0;
   if (ws_bytes < decompress_layout_bytes(len, &cnt_off, &pre_off)) return NUMARCK_ECAPACITY;
@@ -1019,6 +1032,76 @@ numarck_status numarck_decompress_range(const numarck_header* hdr, const void* p
                                         void* stream) {
   return decompress_impl(hdr, prev, packed, centers, incomp, block_inc_off, start, len, out,
                          flags, ws, ws_bytes, stream);
+}
+
+}  // extern "C"
+
+namespace nk {
+
+// Workspace of numarck_decompress_range_noalloc: the decompression layout (a
+// control word, the unit escape counts and the counts of the pieces before
+// the range; its size does not depend on the range) in a device-global array.
+// Each device holds its own copy until the process ends.  In host code the
+// array's name is only a host-side stand-in: kernels get the device address
+// that hipGetSymbolAddress returns on that device.
+constexpr size_t NK_STATIC_SCRATCH_BYTES = 64 * 1024;
+static __device__ __align__(256) unsigned char scratch[NK_STATIC_SCRATCH_BYTES];
+
+constexpr int NK_MAX_DEVICES = 128;
+static std::mutex g_scratch_mu;
+static void* g_scratch_dev[NK_MAX_DEVICES];
+
+// The current device's address of `scratch`, looked up once per device.
+static numarck_status static_scratch(void** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e);
+  if (dev < 0 || dev >= NK_MAX_DEVICES) {
+    g_last_error = "device ordinal beyond the static scratch table";
+    return NUMARCK_EINVAL;
+  }
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e);
+    if (!p) {
+      g_last_error = "hipGetSymbolAddress returned no address for the static scratch";
+      return NUMARCK_EHIP;
+    }
+    g_scratch_dev[dev] = p;
+  }
+  *out = g_scratch_dev[dev];
+  return NUMARCK_OK;
+}
+
+}  // namespace nk
+
+extern "C" {
+
+size_t numarck_static_scratch_bytes(void) { return NK_STATIC_SCRATCH_BYTES; }
+
+numarck_status numarck_decompress_range_noalloc(const numarck_header* hdr, const void* prev,
+                                                const uint32_t* packed, const void* centers,
+                                                const void* incomp,
+                                                const int64_t* block_inc_off, uint64_t start,
+                                                uint64_t len, void* out, uint32_t* flags,
+                                                void* stream) {
+  numarck_status st = check_decompress_args(hdr, prev, packed, centers, incomp, block_inc_off,
+                                            start, len, out, flags);
+  if (st != NUMARCK_OK) return st;
+  const size_t need = decompress_layout_bytes(len, nullptr);
+  if (need > NK_STATIC_SCRATCH_BYTES) {
+    g_last_error = "decompression workspace of " + std::to_string(need) +
+                   " bytes exceeds the static scratch of " +
+                   std::to_string(NK_STATIC_SCRATCH_BYTES);
+    return NUMARCK_ECAPACITY;
+  }
+  void* ws = nullptr;
+  st = static_scratch(&ws);
+  if (st != NUMARCK_OK) return st;
+  return decompress_impl(hdr, prev, packed, centers, incomp, block_inc_off, start, len, out,
+                         flags, ws, NK_STATIC_SCRATCH_BYTES, stream);
 }
 
 numarck_status numarck_histogram_export(const void* ws, size_t ws_bytes, uint64_t n,

@@ -174,6 +174,10 @@ numarck_decompress = _bind("numarck_decompress", _i,
 numarck_decompress_range = _bind("numarck_decompress_range", _i,
                                  [ctypes.POINTER(NumarckHeader), _vp, _vp, _vp, _vp, _vp, _u64,
                                   _u64, _vp, _vp, _vp, _sz, _vp])
+numarck_static_scratch_bytes = _bind("numarck_static_scratch_bytes", _sz, [])
+numarck_decompress_range_noalloc = _bind("numarck_decompress_range_noalloc", _i,
+                                         [ctypes.POINTER(NumarckHeader), _vp, _vp, _vp, _vp,
+                                          _vp, _u64, _u64, _vp, _vp, _vp])
 numarck_histogram_export = _bind("numarck_histogram_export", _i,
                                  [_vp, _sz, _u64, _i, _vp, _vp, _u64, _vp, _vp])
 numarck_tuning_default = _bind("numarck_tuning_default", None, [ctypes.POINTER(NumarckTuning)])
@@ -776,6 +780,19 @@ def decompress_range(c: Compressed, prev: torch.Tensor, start: int, length: int,
                                   _ptr(c.incomp), _ptr(c.block_inc_off), int(start), int(length),
                                   _ptr(out), _ptr(flags), _ptr(ws), ws.numel(), _stream(stream))
     _check(st, "numarck_decompress_range")
+    return out[:length], flags
+
+
+def decompress_range_noalloc(c: Compressed, prev: torch.Tensor, start: int, length: int,
+                             out: torch.Tensor, flags: torch.Tensor, stream=None):
+    """numarck_decompress_range_noalloc into caller-provided `out` and `flags`
+    (the library allocates nothing; its workspace is a device-global array)."""
+    h = c.header()
+    st = numarck_decompress_range_noalloc(ctypes.byref(h), _ptr(prev), _ptr(c.packed),
+                                          _ptr(c.centers), _ptr(c.incomp), _ptr(c.block_inc_off),
+                                          int(start), int(length), _ptr(out), _ptr(flags),
+                                          _stream(stream))
+    _check(st, "numarck_decompress_range_noalloc")
     return out[:length], flags
 
 

@@ -263,3 +263,19 @@ def test_lossless_validation_without_gpu(nk):
     rng = lambda b, c: m.numarck_lossless_decode_range(ctypes.byref(h), 0x400000, 0x500000,
                                                        0x600000, b, c, 0x800000, 0x900000, None)
     assert rng(0, 2) == nk.ERANGE and rng(2, 0) == nk.ERANGE and rng(1 << 63, 1 << 63) == nk.ERANGE
+
+
+def test_decompress_noalloc_validation_without_gpu(nk):
+    """The no-allocation range decompression checks its arguments like the
+    workspace form, before it touches the device."""
+    h = _header(nk)
+    args = lambda hh, s, ln, fl=0x900000: (ctypes.byref(hh), 0x300000, 0x400000, 0x500000,
+                                           0x600000, 0x700000, s, ln, 0x800000, fl, None)
+    assert nk.numarck_decompress_range_noalloc(*args(h, 900, 101)) == nk.ERANGE
+    assert nk.numarck_decompress_range_noalloc(*args(h, 1001, 0)) == nk.ERANGE
+    assert nk.numarck_decompress_range_noalloc(*args(h, 0, 10, fl=None)) == nk.EINVAL
+    bad = _header(nk)
+    bad.B = 17
+    assert nk.numarck_decompress_range_noalloc(*args(bad, 0, 10)) == nk.EBITS
+    assert nk.numarck_decompress_range_noalloc(None, *args(h, 0, 10)[1:]) == nk.EINVAL
+    assert nk.numarck_static_scratch_bytes() >= nk.numarck_decompress_workspace_bytes(1 << 31)
