@@ -349,6 +349,29 @@ numarck_status numarck_plan_create_zero_anchored(const numarck_job* jobs, uint32
                                                  numarck_plan** plan);
 /* Compress every job of the plan on `stream`. */
 numarck_status numarck_plan_run(const numarck_plan* plan, void* stream);
+/* The launch groups a plan runs, in launch order: the range-pass groups (none
+ * in a zero-anchored plan), the histogram groups, then the encoder groups.
+ * Each group covers consecutive jobs of the plan's internal order, which is
+ * the caller's order stably sorted by (dtype, encoder index-width class).
+ * Writes up to `cap` records to `out` (may be NULL) and returns the number of
+ * groups.  For tests and tuning reports; no device work. */
+typedef enum {
+  NUMARCK_PASS_RANGE = 0, NUMARCK_PASS_HIST = 1, NUMARCK_PASS_ENCODE = 2
+} numarck_pass;
+typedef struct numarck_plan_group {
+  uint32_t pass;       /* numarck_pass */
+  uint32_t dtype;      /* numarck_dtype of the group's jobs */
+  uint32_t cls;        /* encoder: 0 B < 8, 1 B = 8, 2 8 < B < 16, 3 B = 16; else 0 */
+  uint32_t first_job;  /* caller's index of the group's first job */
+  uint32_t njobs;      /* jobs in the group */
+  uint32_t chain;      /* 1: a time chain (each job's prev is the previous job's curr):
+                          the range pass sweeps it once, the histogram walks its
+                          jobs in step; 0 otherwise (always 0 for the encoder) */
+  uint32_t load_hint;  /* loads the group's kernels issue: 0 both inputs cached,
+                          1 both non-temporal, 2 prev non-temporal and curr cached */
+  uint32_t hist_lds;   /* histogram: 1 LDS window counts, 0 global counts; else 0 */
+} numarck_plan_group;
+uint32_t numarck_plan_groups(const numarck_plan* plan, numarck_plan_group* out, uint32_t cap);
 /* Capture numarck_plan_run on `stream` (not the null stream) into a HIP graph
  * kept by the plan; numarck_plan_replay launches it.  Inputs and outputs are
  * the plan's buffers: replays compress whatever they hold at that time. */

@@ -607,6 +607,7 @@ struct numarck_plan {
   std::vector<uint64_t> chunk0;      // njobs + 1
   std::vector<uint32_t> unit0;       // njobs + 1
   std::vector<nk::JobGroup> dgroups, egroups, rgroups, hgroups;
+  std::vector<uint32_t> order;       // caller's index of each job of `table`
   nk::BatchLaunch bl;
   hipEvent_t uploaded = nullptr;     // the descriptor copy has completed
   hipGraph_t graph = nullptr;
@@ -672,6 +673,7 @@ static numarck_status plan_create(const numarck_job* jobs, uint32_t njobs,
 
   numarck_plan* pl = new numarck_plan();
   pl->njobs = njobs;
+  pl->order = order;
   pl->table.resize(njobs);
   pl->chunk0.assign(njobs + 1, 0);
   pl->unit0.assign(njobs + 1, 0);
@@ -878,6 +880,36 @@ numarck_status numarck_plan_create_zero_anchored(const numarck_job* jobs, uint32
                                                  size_t ws_bytes, void* stream,
                                                  numarck_plan** plan_out) {
   return plan_create(jobs, njobs, tune, ws, ws_bytes, stream, plan_out, 1);
+}
+
+uint32_t numarck_plan_groups(const numarck_plan* plan, numarck_plan_group* out, uint32_t cap) {
+  if (!plan) return 0;
+  uint32_t w = 0;
+  auto put = [&](uint32_t pass, const JobGroup& g, uint32_t hint, uint32_t lds) {
+    if (out && w < cap) {
+      numarck_plan_group r{};
+      r.pass = pass;
+      r.dtype = (uint32_t)g.dtype;
+      r.cls = pass == NUMARCK_PASS_ENCODE ? (uint32_t)g.cls : 0u;
+      r.first_job = g.job_begin < plan->njobs ? plan->order[g.job_begin] : 0u;
+      r.njobs = g.job_end - g.job_begin;
+      r.chain = pass == NUMARCK_PASS_ENCODE ? 0u : g.chain;
+      r.load_hint = hint;
+      r.hist_lds = lds;
+      out[w] = r;
+    }
+    ++w;
+  };
+  // the hints each pass's kernels take (run_chain): the range and LDS
+  // histogram passes stream non-temporally for hint 1 only, global
+  // histogram counts always read cached, the encoder takes all three
+  if (!plan->bl.za)
+    for (const JobGroup& g : plan->rgroups) put(NUMARCK_PASS_RANGE, g, g.nt == 1 ? 1u : 0u, 0u);
+  const uint32_t lds = plan->bl.tune.hist_lds;
+  for (const JobGroup& g : plan->hgroups)
+    put(NUMARCK_PASS_HIST, g, (lds && g.nt == 1) ? 1u : 0u, lds);
+  for (const JobGroup& g : plan->egroups) put(NUMARCK_PASS_ENCODE, g, g.nt, 0u);
+  return w;
 }
 
 numarck_status numarck_plan_run(const numarck_plan* plan, void* stream) {

@@ -80,6 +80,16 @@ class NumarckJob(ctypes.Structure):
     ]
 
 
+class NumarckPlanGroup(ctypes.Structure):
+    _fields_ = [(name, ctypes.c_uint32) for name in
+                ("pass_", "dtype", "cls", "first_job", "njobs", "chain", "load_hint", "hist_lds")]
+
+    def as_dict(self) -> dict:
+        d = {name: getattr(self, name) for name, _ in self._fields_}
+        d["pass"] = ("range", "hist", "encode")[d.pop("pass_")]
+        return d
+
+
 class NumarckServerConfig(ctypes.Structure):
     _fields_ = [
         ("budget_bytes", ctypes.c_uint64), ("arena_bytes", ctypes.c_uint64),
@@ -202,6 +212,8 @@ numarck_plan_run = _bind("numarck_plan_run", _i, [_vp, _vp])
 numarck_plan_capture = _bind("numarck_plan_capture", _i, [_vp, _vp])
 numarck_plan_replay = _bind("numarck_plan_replay", _i, [_vp, _vp])
 numarck_plan_destroy = _bind("numarck_plan_destroy", None, [_vp])
+numarck_plan_groups = _bind("numarck_plan_groups", _u32,
+                            [_vp, ctypes.POINTER(NumarckPlanGroup), _u32])
 numarck_compress_batch = _bind("numarck_compress_batch", _i,
                                [ctypes.POINTER(NumarckJob), _u32, _vp, _sz, _vp])
 numarck_server_create = _bind("numarck_server_create", _i,
@@ -605,6 +617,13 @@ class Plan:
     def run(self, stream=None) -> list[Compressed]:
         _check(numarck_plan_run(self._h, _stream(stream)), "numarck_plan_run")
         return self.results()
+
+    def groups(self) -> list[dict]:
+        """The plan's launch groups (numarck_plan_groups), in launch order."""
+        k = numarck_plan_groups(self._h, None, 0)
+        arr = (NumarckPlanGroup * max(k, 1))()
+        numarck_plan_groups(self._h, arr, k)
+        return [arr[i].as_dict() for i in range(k)]
 
     def capture(self, stream):
         _check(numarck_plan_capture(self._h, _stream(stream)), "numarck_plan_capture")

@@ -1,0 +1,126 @@
+"""Batches at the sizes the benchmark runs them, through the C ABI.
+
+- A time chain of four consecutive 256^3 float64 FLASH-like pairs streams
+  640 MiB per snapshot sweep and 1 GiB per pass: the plan takes the
+  non-temporal chain sweep in the range pass and, in the encoder, loads each
+  pair's prev non-temporally and its curr cached (the shared snapshot is read
+  again by the next pair).  The plan reports those choices (numarck_plan_groups)
+  and every job equals its plain compression bit for bit; two jobs equal the
+  oracle.  The same for a zero-anchored plan of the same pairs.
+- The uneven 64-variable workload at its full cube edges (32..384, mixed
+  float32/float64, E in {1e-4, 1e-3, 1e-2}, B in {8, 10, 12}): every job
+  equals its plain compression bit for bit, two equal the oracle."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from gpu_util import assert_matches_oracle, assert_same_compression, bits, to_np
+from paper_1703_02438_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def nk():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_1703_02438_amd.numarck as nk
+    return nk
+
+
+def _same(a, b, label):
+    """Every output of two compressions, the reconstruction included."""
+    assert_same_compression(a, b, label)
+    n = a.header().n
+    if n:
+        iv = torch.int32 if a.recon.dtype == torch.float32 else torch.int64
+        assert torch.equal(a.recon[:n].view(iv), b.recon[:n].view(iv)), f"[{label}] recon"
+
+
+@pytest.fixture(scope="module")
+def flash_chain():
+    s = inputs.FlashSeries(edge=256, seed=1717, device="cuda")
+    snaps = [s.x.reshape(-1).clone()]
+    for _ in range(4):
+        snaps.append(s.step().reshape(-1).clone())
+    torch.cuda.synchronize()
+    return snaps
+
+
+def _chain_groups(plan, za):
+    g = plan.groups()
+    rng = [x for x in g if x["pass"] == "range"]
+    hist = [x for x in g if x["pass"] == "hist"]
+    enc = [x for x in g if x["pass"] == "encode"]
+    if za:
+        assert rng == [], g
+    else:
+        assert len(rng) == 1 and rng[0]["chain"] == 1 and rng[0]["njobs"] == 4, g
+        assert rng[0]["load_hint"] == 1, g  # the sweep reads every snapshot once, non-temporally
+    assert len(hist) == 1 and hist[0]["chain"] == 1 and hist[0]["hist_lds"] == 1, g
+    assert hist[0]["load_hint"] == 0, g  # pairs in step: the shared snapshot's second read is cached
+    assert len(enc) == 1 and enc[0]["njobs"] == 4 and enc[0]["cls"] == 1, g
+    assert enc[0]["load_hint"] == 2, g  # prev non-temporal, curr cached
+
+
+@pytest.mark.parametrize("za", [False, True], ids=["paper_anchor", "zero_anchored"])
+def test_streaming_time_chain(nk, flash_chain, za):
+    snaps = flash_chain
+    E, B = 1e-3, 8
+    bj = [nk.BatchJob(snaps[t], snaps[t + 1], E, B) for t in range(4)]
+    plan = nk.Plan(bj, recon=True, bin_ids=True, zero_anchored=za)
+    _chain_groups(plan, za)
+    plain_fn = nk.compress_zero_anchored if za else nk.compress
+    for rep in range(2):
+        res = plan.run()
+        torch.cuda.synchronize()
+        for t, c in enumerate(res):
+            ref = plain_fn(snaps[t], snaps[t + 1], E, B, recon=True, bin_ids=True)
+            torch.cuda.synchronize()
+            _same(c, ref, f"{'za' if za else 'topk'} pair {t} rep {rep}")
+            del ref
+    orc = oracle.get()
+    for t in (0, 3):
+        p, q = to_np(snaps[t]), to_np(snaps[t + 1])
+        if za:
+            o = orc.compress(p, q, E, B, binning="zero_anchored")
+            h = res[t].header()
+            assert h.n_inc == o.info["n_inc"] and h.k_used == o.info["k_used"]
+            nw = o.info["packed_words"]
+            assert np.array_equal(to_np(res[t].packed[:nw]).view(np.uint32), o.packed), \
+                f"za pair {t} packed"
+            assert np.array_equal(bits(to_np(res[t].incomp[:h.n_inc])), bits(o.incomp)), \
+                f"za pair {t} incomp"
+            assert np.array_equal(bits(to_np(res[t].recon[:h.n])), bits(o.recon)), \
+                f"za pair {t} recon"
+        else:
+            assert_matches_oracle(nk, res[t], orc.compress(p, q, E, B), p, q, E, B,
+                                  check_hist=False, label=f"chain pair {t}")
+    plan.close()
+
+
+def test_uneven_variables_full_edges(nk):
+    specs = inputs.batched_specs(64)  # cube edges log-uniform in [32, 384]
+    pairs = [inputs.mixture_pair(sp.n, seed=sp.seed, dtype=sp.dtype, device="cuda")
+             for sp in specs]
+    bj = [nk.BatchJob(p, q, sp.E, sp.B) for (p, q), sp in zip(pairs, specs)]
+    plan = nk.Plan(bj, recon=True, bin_ids=True)
+    g = plan.groups()
+    assert sum(x["njobs"] for x in g if x["pass"] == "encode") == 64, g
+    assert all(x["chain"] == 0 for x in g), g
+    res = plan.run()
+    torch.cuda.synchronize()
+    for i, ((p, q), sp, c) in enumerate(zip(pairs, specs, res)):
+        ref = nk.compress(p, q, sp.E, sp.B, recon=True, bin_ids=True)
+        torch.cuda.synchronize()
+        _same(c, ref, f"var {i} edge {sp.edge} {sp.dtype} E={sp.E} B={sp.B}")
+        del ref
+    orc = oracle.get()
+    # the largest variable of each element type against the oracle
+    for dt in (torch.float64, torch.float32):
+        i = max((k for k, sp in enumerate(specs) if sp.dtype == dt), key=lambda k: specs[k].n)
+        p, q = to_np(pairs[i][0]), to_np(pairs[i][1])
+        sp = specs[i]
+        assert_matches_oracle(nk, res[i], orc.compress(p, q, sp.E, sp.B), p, q, sp.E, sp.B,
+                              check_hist=False, label=f"full-edge var {i}")
+    plan.close()
