@@ -32,12 +32,21 @@ EDGE, E, B, SNAPSHOTS = 512, 1e-3, 8, 10
 # incompressible fraction alpha): what the kernel must move at minimum.
 #   range, hist : read prev + curr                      = 16
 #   encode      : read prev + curr, write B/8 + alpha*8 = 16 + B/8 + 8 alpha
-#                 (+ alpha*8 staged to scratch)
+# The encoder's staging of the incompressible values (8 alpha written to the
+# workspace, then read and written again by the placement kernel) is
+# overhead of this design, reported beside these figures, not in them.
 ALGO = {
     "range": lambda a: 16.0,
     "hist": lambda a: 16.0,
-    "encode": lambda a: 16.0 + B / 8 + 2 * 8 * a,
+    "encode": lambda a: 16.0 + B / 8 + 8 * a,
 }
+# The whole compression's minimum: read both snapshots once, write the index
+# table and the incompressible values.
+ALGO_CALL = lambda a: 16.0 + B / 8 + 8 * a
+
+# Kernels of one compression call (the library's k_* names).
+PIPELINE_KERNELS = ("init", "range", "derive", "hist", "hclear", "hinsert", "select",
+                    "tailrank", "encode", "uscan", "gather")
 
 
 # The sources the compression and decompression kernels are built from: the
@@ -54,9 +63,9 @@ def source_digest() -> str:
     return h.hexdigest()[:16]
 
 
-def load_traffic(kernel: str, workload: str):
-    """HBM traffic of `kernel` measured with rocprofv3 counters, if the
-    committed measurement matches the current kernel sources."""
+def load_pmc(kernel: str, workload: str):
+    """The committed rocprofv3 counter summary of `kernel` (or "pipeline"),
+    if it was taken on the current kernel sources."""
     path = os.path.join(ROOT, "profiles", f"pmc_{kernel}_{workload}.json")
     if not os.path.exists(path):
         return None
@@ -64,29 +73,40 @@ def load_traffic(kernel: str, workload: str):
         rec = json.load(f)
     if rec.get("source_digest") != source_digest():
         return None
-    return rec.get("bytes_per_launch")
+    return rec
+
+
+def load_traffic(kernel: str, workload: str):
+    """HBM traffic of `kernel` measured with rocprofv3 counters, if the
+    committed measurement matches the current kernel sources."""
+    rec = load_pmc(kernel, workload)
+    return rec.get("bytes_per_launch") if rec else None
 
 
 COPY_CALIB_BYTES = 1 << 30
 
 
-def calib_copy(torch, dev):
-    """A plain 1 GiB device copy (torch's copy kernel): a kernel of known
-    traffic for scaling the FETCH_SIZE / WRITE_SIZE counters."""
+def calib_copy(torch, nk, dev):
+    """The library's reference copy of 1 GiB (numarck_stream_kernel, cached
+    loads and stores): a kernel of known traffic for scaling the FETCH_SIZE /
+    WRITE_SIZE counters."""
     src = torch.empty(COPY_CALIB_BYTES // 8, dtype=torch.float64, device=dev).fill_(1.0)
     dst = torch.empty_like(src)
     for _ in range(3):
-        dst.copy_(src)
+        nk.stream_kernel(nk.STREAM_COPY, src, dst, COPY_CALIB_BYTES)
     torch.cuda.synchronize()
     del src, dst
 
 
-def summarize_pmc(fetch_dir: str, write_dir: str, kernel: str, workload: str, cmd: str):
+def summarize_pmc(fetch_dir: str, write_dir: str, workload: str, cmd: str):
     """Turn two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) of
-    `bench.py --calib-copy` into HBM bytes per launch of `kernel`, scaled by
-    what the counters read for the 1 GiB calibration copy."""
+    `bench.py --calib-copy` into HBM bytes per launch of every library kernel,
+    scaled by what the counters read for the 1 GiB calibration copy; writes
+    profiles/pmc_encode_*, pmc_decode_* (the two dominant kernels) and
+    pmc_pipeline_* (every kernel of one compression call)."""
     import csv
     import glob
+    import re
 
     def per_kernel(d, counter):
         vals = {}
@@ -95,33 +115,86 @@ def summarize_pmc(fetch_dir: str, write_dir: str, kernel: str, workload: str, cm
                 for row in csv.DictReader(fh):
                     if row.get("Counter_Name") != counter:
                         continue
-                    vals.setdefault(row["Kernel_Name"], []).append(float(row["Counter_Value"]))
+                    name = row["Kernel_Name"]
+                    m = re.search(r"nk::k_(\w+)", name)
+                    if m:
+                        k = m.group(1)
+                        if k.startswith("stream_") and "<true>" in name:
+                            k += "_nt"
+                        vals.setdefault(k, []).append(float(row["Counter_Value"]))
         return vals
 
-    out = {"kernel": kernel, "workload": workload, "command": cmd,
-           "source_digest": source_digest(), "copy_bytes": COPY_CALIB_BYTES}
-    total = 0.0
+    rec = {}
     for d, counter in ((fetch_dir, "FETCH_SIZE"), (write_dir, "WRITE_SIZE")):
         v = per_kernel(d, counter)
-        copy = [x for k, xs in v.items() if "copy" in k.lower() or "elementwise" in k.lower()
-                for x in xs if x * 1024 > 0.25 * COPY_CALIB_BYTES]
-        mine = [x for k, xs in v.items() if f"k_{kernel}<" in k or f"k_{kernel}(" in k
-                for x in xs]
-        if not copy or not mine:
-            raise SystemExit(f"no {counter} samples for the copy or k_{kernel}")
-        # full-size launches only (range decompressions launch the same kernel on 1 %)
-        mine = [x for x in mine if x >= 0.5 * max(mine)]
+        copy = [x for x in v.get("stream_copy", []) if x * 1024 > 0.25 * COPY_CALIB_BYTES]
+        if not copy:
+            raise SystemExit(f"no {counter} samples of the calibration copy")
         copy_kib = sorted(copy)[len(copy) // 2]
         scale = (COPY_CALIB_BYTES / 1024) / copy_kib
-        kib = sum(mine) / len(mine)
-        out[counter] = {"kernel_kib": kib, "copy_kib": copy_kib, "scale": scale,
-                        "dispatches": len(mine)}
-        total += kib * scale * 1024
-    out["bytes_per_launch"] = int(total)
-    path = os.path.join(ROOT, "profiles", f"pmc_{kernel}_{workload}.json")
+        for k, xs in v.items():
+            # full-size launches only (range decompressions launch the decoder on 1 %)
+            xs = [x for x in xs if x >= 0.5 * max(xs)] if k in ("decode", "dcount") else xs
+            rec.setdefault(k, {})[counter] = {"kernel_kib": sum(xs) / len(xs),
+                                              "copy_kib": copy_kib, "scale": scale,
+                                              "dispatches": len(xs)}
+    base = {"workload": workload, "command": cmd, "source_digest": source_digest(),
+            "copy_bytes": COPY_CALIB_BYTES, "copy_kernel": "nk::k_stream_copy<false>"}
+
+    def bytes_of(k):
+        r = rec[k]
+        return sum(r[c]["kernel_kib"] * r[c]["scale"] * 1024 for c in ("FETCH_SIZE", "WRITE_SIZE"))
+
+    for kernel in ("encode", "decode"):
+        if kernel not in rec:
+            raise SystemExit(f"no samples of k_{kernel}")
+        out = dict(base, kernel=kernel, **rec[kernel])
+        out["bytes_per_launch"] = int(bytes_of(kernel))
+        path = os.path.join(ROOT, "profiles", f"pmc_{kernel}_{workload}.json")
+        with open(path, "w") as f:
+            json.dump(out, f, indent=1)
+        print(path)
+    per = {}
+    for k in PIPELINE_KERNELS:
+        if k not in rec:
+            raise SystemExit(f"no samples of k_{k}")
+        r = rec[k]
+        per[k] = {"fetch_bytes": int(r["FETCH_SIZE"]["kernel_kib"] * r["FETCH_SIZE"]["scale"] * 1024),
+                  "write_bytes": int(r["WRITE_SIZE"]["kernel_kib"] * r["WRITE_SIZE"]["scale"] * 1024),
+                  "dispatches": r["FETCH_SIZE"]["dispatches"]}
+    out = dict(base, kernel="pipeline", kernels=per,
+               bytes_per_call=sum(v["fetch_bytes"] + v["write_bytes"] for v in per.values()))
+    path = os.path.join(ROOT, "profiles", f"pmc_pipeline_{workload}.json")
     with open(path, "w") as f:
         json.dump(out, f, indent=1)
     print(path)
+
+
+STREAM_KINDS = ("read", "read_nt", "write", "write_nt", "copy", "copy_nt")
+
+
+def stream_section(torch, nk, reps: int, nbytes: int = 1 << 30) -> dict:
+    """The library's reference streaming kernels (numarck_stream_kernel) on
+    1 GiB: read, write and copy, cached and non-temporal, at 2..16 workgroups
+    per compute unit; GB/s of bytes moved (a copy moves 2 x nbytes), the best
+    launch of each."""
+    src = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    stream = torch.cuda.current_stream()
+    out = {}
+    for kind, name in enumerate(STREAM_KINDS):
+        moved = 2 * nbytes if name.startswith("copy") else nbytes
+        best = None
+        for per_cu in (2, 4, 8, 16):
+            t = time_ms(torch, lambda: nk.stream_kernel(kind, src, dst, nbytes, per_cu, stream),
+                        reps, stream)
+            gbs = moved / t / 1e6
+            if best is None or gbs > best[0]:
+                best = (gbs, per_cu)
+        out[name] = {"gbs": round(best[0], 1), "per_cu": best[1]}
+    del src, dst
+    torch.cuda.empty_cache()
+    return out
 
 
 def cpu_baseline(prev, curr, sample_elems: int):
@@ -490,12 +563,15 @@ def main():
                          "(-1 = max(3, steps / 3), 0 = skip)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run a 1 GiB device copy first (counter calibration)")
-    ap.add_argument("--summarize-pmc", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "KERNEL", "CMD"),
-                    help="write profiles/pmc_<kernel>_<workload>.json from two rocprofv3 runs")
+    ap.add_argument("--stream-reps", type=int, default=5,
+                    help="timed runs of each reference streaming kernel (0 = skip)")
+    ap.add_argument("--summarize-pmc", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "CMD"),
+                    help="write profiles/pmc_{encode,decode,pipeline}_<workload>.json from two "
+                         "rocprofv3 runs")
     args = ap.parse_args()
     if args.summarize_pmc:
-        fd, wd, kern, cmd = args.summarize_pmc
-        summarize_pmc(fd, wd, kern, f"flash3d_{args.edge}cubed_f64", cmd)
+        fd, wd, cmd = args.summarize_pmc
+        summarize_pmc(fd, wd, f"flash3d_{args.edge}cubed_f64", cmd)
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this build measures one GPU; --gpus must be 1"}))
@@ -508,7 +584,8 @@ def main():
 
     dev = torch.device("cuda:0")
     if args.calib_copy:
-        calib_copy(torch, dev)
+        calib_copy(torch, nk, dev)
+    stream_ref = stream_section(torch, nk, args.stream_reps) if args.stream_reps > 0 else None
     t_gen = time.time()
     series = inputs.FlashSeries(edge=args.edge, seed=1705, device="cuda")
     snaps = [series.x.clone()]
@@ -576,6 +653,25 @@ def main():
 
     in_bytes = n * 8
     value = in_bytes * args.steps / wall / 1e9
+    # the whole call: the method's bytes and the bytes the counters measured
+    # over every kernel of one call, against the call's time
+    call_algo = ALGO_CALL(alpha) * n
+    pipe_rec = load_pmc("pipeline", workload)
+    call_meas = pipe_rec["bytes_per_call"] if pipe_rec else None
+    call_s = ms_per_step / 1e3
+    pipeline = {
+        "algorithmic_bytes_per_call": int(call_algo),
+        "algorithmic_bytes_per_element": round(ALGO_CALL(alpha), 4),
+        "measured_bytes_per_call": call_meas,
+        "measured_bytes_per_element": round(call_meas / n, 3) if call_meas else None,
+        "ms_per_call": round(ms_per_step, 4),
+        "frac_algorithmic": round(call_algo / call_s / 1e9 / HBM_PEAK_GBS, 4),
+        "frac_measured": round(call_meas / call_s / 1e9 / HBM_PEAK_GBS, 4) if call_meas else None,
+        "staging_bytes_per_call": int(3 * 8 * alpha * n),
+    }
+    if stream_ref:
+        pipeline["frac_measured_of_stream_read"] = (
+            round(call_meas / call_s / 1e9 / stream_ref["read_nt"]["gbs"], 4) if call_meas else None)
     dec = decompress_section(torch, nk, step(0), snaps[0], args.steps, stream, workload)
     vreps = max(3, args.steps // 3) if args.variant_reps < 0 else args.variant_reps
     auto_b = ew = za = ll = None
@@ -643,7 +739,9 @@ def main():
             "traffic": traffic,
             "algorithmic_bytes_per_launch": int(algo_bytes),
             "avg_launch_us": round(avg_s * 1e6, 2),
+            "pipeline": pipeline,
         },
+        "stream": stream_ref,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

@@ -379,6 +379,17 @@ numarck_status numarck_plan_capture(numarck_plan* plan, void* stream);
 numarck_status numarck_plan_replay(const numarck_plan* plan, void* stream);
 void numarck_plan_destroy(numarck_plan* plan);
 /* One-shot batch: plan, run, destroy. */
+/* Launch tuning of a batch: a coordinate descent over the numarck_tuning
+ * fields (range and histogram workgroups per compute unit, histogram window
+ * counts in LDS or in global memory, chunk size, encoder waves), each
+ * candidate timed over `reps` runs of a plan of these jobs (a candidate more
+ * than twice as slow as the best after one run is dropped).  Writes the
+ * fastest to *best, for numarck_plan_create / _zero_anchored
+ * (zero_anchored != 0 times zero-anchored plans).  Runs the jobs many times:
+ * their outputs hold the last run's results.  Synchronises the stream. */
+numarck_status numarck_plan_autotune(const numarck_job* jobs, uint32_t njobs, void* ws,
+                                     size_t ws_bytes, uint32_t reps, uint32_t zero_anchored,
+                                     void* stream, numarck_tuning* best);
 numarck_status numarck_compress_batch(const numarck_job* jobs, uint32_t njobs, void* ws,
                                       size_t ws_bytes, void* stream);
 
@@ -478,6 +489,25 @@ numarck_status numarck_server_fetch(numarck_server* s, uint32_t var, const numar
 numarck_status numarck_server_get_stats(numarck_server* s, numarck_server_stats* st);
 /* Drain, stop the scheduler, release the arena and streams. */
 void numarck_server_destroy(numarck_server* s);
+
+/* ---- reference streaming kernels (measurement, not part of the path) ----
+ * The HBM roofline the compression passes are measured against: a read, a
+ * write or a copy of `bytes` bytes with 16-byte vector accesses, cached or
+ * non-temporal, `per_cu` workgroups of 256 threads per compute unit (1..64),
+ * each thread walking the vectors grid-strided.
+ *   READ, READ_NT   : reads src; writes one 32-bit word per wave to dst,
+ *                     which must hold 16 * per_cu * (compute units) bytes
+ *   WRITE, WRITE_NT : writes dst (every 32-bit word 0x3FF00000); src unused
+ *   COPY, COPY_NT   : copies src to dst (distinct buffers)
+ * bytes must be a multiple of 16, src and dst 16-byte aligned.  EINVAL on a
+ * bad kind, size, pointer or per_cu; asynchronous on `stream`. */
+typedef enum {
+  NUMARCK_STREAM_READ = 0, NUMARCK_STREAM_READ_NT = 1,
+  NUMARCK_STREAM_WRITE = 2, NUMARCK_STREAM_WRITE_NT = 3,
+  NUMARCK_STREAM_COPY = 4, NUMARCK_STREAM_COPY_NT = 5
+} numarck_stream_kind;
+numarck_status numarck_stream_kernel(int kind, const void* src, void* dst, uint64_t bytes,
+                                     uint32_t per_cu, void* stream);
 
 /* ---- diagnostics ---- */
 const char* numarck_status_str(numarck_status s);

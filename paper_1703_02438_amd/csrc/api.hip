@@ -492,36 +492,43 @@ numarck_status numarck_autotune(const void* prev, const void* curr, uint64_t n,
   if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess)
     return hip_fail(hipGetLastError());
   numarck_status st = NUMARCK_OK;
-  auto measure = [&](const Tuning& t, float* ms) -> numarck_status {
+  auto measure = [&](const Tuning& t, uint32_t nrep, float* ms) -> numarck_status {
     const numarck_tuning pt = to_public(t);
     numarck_status r = numarck_compress_tuned(prev, curr, n, dtype, E, B, block_bytes, out, ws,
                                               ws_bytes, &pt, stream);  // warm
     if (r != NUMARCK_OK) return r;
     hipError_t e = hipEventRecord(a, s);
-    for (uint32_t i = 0; i < reps && r == NUMARCK_OK && e == hipSuccess; ++i)
+    for (uint32_t i = 0; i < nrep && r == NUMARCK_OK && e == hipSuccess; ++i)
       r = numarck_compress_tuned(prev, curr, n, dtype, E, B, block_bytes, out, ws, ws_bytes,
                                  &pt, stream);
     if (r != NUMARCK_OK) return r;
     if (e == hipSuccess) e = hipEventRecord(b, s);
     if (e == hipSuccess) e = hipEventSynchronize(b);
     if (e == hipSuccess) e = hipEventElapsedTime(ms, a, b);
+    if (e == hipSuccess) *ms /= (float)nrep;
     return e == hipSuccess ? NUMARCK_OK : hip_fail(e);
   };
   // coordinate descent from the defaults, one parameter family at a time
   Tuning cur = default_tuning();
   float cur_ms = 0.f;
-  st = measure(cur, &cur_ms);
-  const uint32_t rbpc[] = {2, 4, 8, 16};
-  // LDS counting only: global window counts serialise on the hot bins of
-  // concentrated ratio distributions (orders of magnitude slower there)
-  const uint32_t hist[][2] = {{1, 1}, {1, 2}, {1, 4}};
+  st = measure(cur, reps, &cur_ms);
+  const uint32_t rbpc[] = {1, 2, 4, 8};
+  // histogram placement: the LDS window at 1..3 workgroups per compute unit,
+  // or global window counts at 4 or 8 (no 64 KB of LDS per workgroup, so
+  // more workgroups; their atomics serialise on the hot bins of concentrated
+  // ratio distributions, which the single timed run below drops early)
+  const uint32_t hist[][2] = {{1, 1}, {1, 2}, {1, 3}, {0, 4}, {0, 8}};
   const uint32_t cvec[] = {4096, 16384, 65536, 131072};
-  const uint32_t upct[] = {25, 50, 75, 100};
+  const uint32_t upct[] = {40, 60, 80, 100};
   const uint32_t sload[] = {1, 2};
   auto try_one = [&](const Tuning& t) {
     if (st != NUMARCK_OK) return;
+    // one timed run first: a candidate more than twice as slow as the best
+    // so far is dropped without its repetitions
     float ms = 0.f;
-    st = measure(t, &ms);
+    st = measure(t, 1, &ms);
+    if (st != NUMARCK_OK || ms > 2.f * cur_ms) return;
+    st = measure(t, reps, &ms);
     if (st == NUMARCK_OK && ms < cur_ms) {
       cur = t;
       cur_ms = ms;
@@ -969,6 +976,67 @@ void numarck_plan_destroy(numarck_plan* plan) {
   delete plan;
 }
 
+numarck_status numarck_plan_autotune(const numarck_job* jobs, uint32_t njobs, void* ws,
+                                     size_t ws_bytes, uint32_t reps, uint32_t zero_anchored,
+                                     void* stream, numarck_tuning* best) {
+  if (!best) return NUMARCK_EINVAL;
+  if (reps < 1) reps = 1;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipEvent_t a = nullptr, b = nullptr;
+  if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess)
+    return hip_fail(hipGetLastError());
+  // time `nrep` runs of a plan built with tuning t (after one warm run)
+  auto measure = [&](const Tuning& t, uint32_t nrep, float* ms) -> numarck_status {
+    const numarck_tuning pt = to_public(t);
+    numarck_plan* pl = nullptr;
+    numarck_status r = plan_create(jobs, njobs, &pt, ws, ws_bytes, stream, &pl, zero_anchored);
+    if (r != NUMARCK_OK) return r;
+    r = numarck_plan_run(pl, stream);
+    hipError_t e = r == NUMARCK_OK ? hipEventRecord(a, s) : hipSuccess;
+    for (uint32_t i = 0; i < nrep && r == NUMARCK_OK && e == hipSuccess; ++i)
+      r = numarck_plan_run(pl, stream);
+    if (r == NUMARCK_OK && e == hipSuccess) e = hipEventRecord(b, s);
+    if (r == NUMARCK_OK && e == hipSuccess) e = hipEventSynchronize(b);
+    if (r == NUMARCK_OK && e == hipSuccess) e = hipEventElapsedTime(ms, a, b);
+    numarck_plan_destroy(pl);
+    if (r != NUMARCK_OK) return r;
+    if (e != hipSuccess) return hip_fail(e);
+    *ms /= (float)nrep;
+    return NUMARCK_OK;
+  };
+  // coordinate descent from the defaults, as numarck_autotune; histogram
+  // placement is where a batch of many small jobs can gain (global counts
+  // need no 64 KB of LDS per workgroup), and where concentrated ratios lose
+  // badly, which the single timed run drops early
+  Tuning cur = default_tuning();
+  float cur_ms = 0.f;
+  numarck_status st = measure(cur, reps, &cur_ms);
+  auto try_one = [&](const Tuning& t) {
+    if (st != NUMARCK_OK) return;
+    float ms = 0.f;
+    st = measure(t, 1, &ms);
+    if (st != NUMARCK_OK || ms > 2.f * cur_ms) return;
+    st = measure(t, reps, &ms);
+    if (st == NUMARCK_OK && ms < cur_ms) {
+      cur = t;
+      cur_ms = ms;
+    }
+  };
+  const uint32_t rbpc[] = {1, 2, 4, 8};
+  const uint32_t hist[][2] = {{1, 1}, {1, 2}, {1, 3}, {0, 4}, {0, 8}};
+  const uint32_t cvec[] = {4096, 16384, 65536};
+  const uint32_t upct[] = {40, 60, 80, 100};
+  for (uint32_t v : rbpc) { Tuning t = cur; t.range_blocks_per_cu = v; try_one(t); }
+  for (auto& h : hist) { Tuning t = cur; t.hist_lds = h[0]; t.hist_blocks_per_cu = h[1]; try_one(t); }
+  for (uint32_t v : cvec) { Tuning t = cur; t.chunk_vec = v; try_one(t); }
+  for (uint32_t v : upct) { Tuning t = cur; t.unit_pct = v; try_one(t); }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  if (st != NUMARCK_OK) return st;
+  *best = to_public(cur);
+  return NUMARCK_OK;
+}
+
 numarck_status numarck_compress_batch(const numarck_job* jobs, uint32_t njobs, void* ws,
                                       size_t ws_bytes, void* stream) {
   numarck_plan* pl = nullptr;
@@ -1172,6 +1240,18 @@ const char* numarck_status_str(numarck_status s) {
 }
 
 const char* numarck_last_error(void) { return g_last_error.c_str(); }
+
+numarck_status numarck_stream_kernel(int kind, const void* src, void* dst, uint64_t bytes,
+                                     uint32_t per_cu, void* stream) {
+  if (kind < NUMARCK_STREAM_READ || kind > NUMARCK_STREAM_COPY_NT) return NUMARCK_EINVAL;
+  if (bytes % 16 != 0 || per_cu < 1 || per_cu > 64 || !dst) return NUMARCK_EINVAL;
+  const bool reads = kind != NUMARCK_STREAM_WRITE && kind != NUMARCK_STREAM_WRITE_NT;
+  if (reads && !src) return NUMARCK_EINVAL;
+  if (!aligned16(dst) || (reads && !aligned16(src))) return NUMARCK_EALIGN;
+  if (bytes == 0) return NUMARCK_OK;
+  const hipError_t e = launch_stream(kind, src, dst, bytes, per_cu, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? NUMARCK_OK : hip_fail(e);
+}
 
 void numarck_timing_enable(int on) { g_timing = on != 0; }
 

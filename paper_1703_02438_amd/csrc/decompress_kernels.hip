@@ -6,10 +6,10 @@
 // owns a contiguous run of them:
 //   k_dcount   escapes in each unit's run, and in pieces of the part of
 //              start's block before the range (reads the packed indices only)
-//   k_dscan    escapes before `start` (the block table gives the count up to
-//              the start of start's block, plus the counted pieces), exclusive
-//              offsets of the runs, and the flag word cleared
-//   k_decode   each unit decodes its tiles in order: an escape takes the next
+//   k_decode   each workgroup first sums the escapes before its units (the
+//              block table's count at start's block, the counted pieces
+//              before start, the counts of the earlier units); then each
+//              unit decodes its tiles in order: an escape takes the next
 //              incompressible value, any other index gives
 //              T(prev * (1 + centre[index]))
 #include "nk_device.h"
@@ -127,6 +127,7 @@ __device__ unsigned long long wave_count_escapes(const uint32_t* __restrict__ pa
 // of the block before the range, into pieces of pre_elems indices.
 __global__ void __launch_bounds__(UNIT_TPB) k_dcount(DParams P) {
   const uint32_t wave = blockIdx.x * (UNIT_TPB / 64) + threadIdx.x / 64;
+  if (blockIdx.x == 0 && threadIdx.x == 0) gstore(P.flags, 0u);  // the decoder ORs into it
   uint64_t r0, r1;
   if (wave < P.n_units) {
     const uint64_t end = P.start + P.len;
@@ -149,25 +150,6 @@ __global__ void __launch_bounds__(UNIT_TPB) k_dcount(DParams P) {
       P.unit_cnt[wave] = (uint32_t)cnt;
     else
       P.pre_cnt[wave - P.n_units] = (uint32_t)cnt;
-  }
-}
-
-// Escapes before the range (the block table's count at start's block plus
-// the counted pieces), the unit offsets by an exclusive scan, and the flag
-// word cleared for the decoder.
-__global__ void __launch_bounds__(USCAN_TPB) k_dscan(DParams P) {
-  __shared__ unsigned long long s_pre[USCAN_TPB / 64];
-  const int tid = threadIdx.x;
-  unsigned long long pre = 0;
-  for (uint32_t i = tid; i < P.pre_units; i += USCAN_TPB) pre += gload(P.pre_cnt + i);
-  pre = wave_sum_u64(pre);
-  if (lane_id() == 0) s_pre[tid / 64] = pre;
-  (void)unit_scan(P.unit_cnt, P.n_units);  // synchronises the workgroup
-  if (tid == 0) {
-    unsigned long long base = P.len ? (unsigned long long)P.block_inc_off[P.start / P.epb] : 0ull;
-    for (int w = 0; w < USCAN_TPB / 64; ++w) base += s_pre[w];
-    P.dctl->base = base;
-    gstore(P.flags, 0u);
   }
 }
 
@@ -201,14 +183,31 @@ __global__ void __launch_bounds__(UNIT_TPB) k_decode(DParams P) {
   const bool lds_cent = ((uint64_t)1 << B) * sizeof(T) <= (uint64_t)DEC_CENT_BYTES;
   if (lds_cent)
     for (int i = tid; i < (1 << B); i += UNIT_TPB) s_cent[i] = centers[i];
+  // Escapes before this workgroup's first unit: those before `start` (the
+  // block table's count at start's block plus the counted pieces of that
+  // block before start) and the counts of the units before it.
+  __shared__ unsigned long long s_part[NWAVE];
+  __shared__ uint32_t s_cnt[NWAVE];
+  const uint32_t unit0 = blockIdx.x * NWAVE;
+  unsigned long long sum = 0;
+  for (uint32_t i = tid; i < unit0; i += UNIT_TPB) sum += gload(P.unit_cnt + i);
+  for (uint32_t i = tid; i < P.pre_units; i += UNIT_TPB) sum += gload(P.pre_cnt + i);
+  sum = wave_sum_u64(sum);
+  if (lane == 0) {
+    s_part[wave] = sum;
+    s_cnt[wave] = unit0 + wave < P.n_units ? gload(P.unit_cnt + unit0 + wave) : 0u;
+  }
   __syncthreads();
+  unsigned long long run =
+      P.len ? (unsigned long long)gload(P.block_inc_off + P.start / P.epb) : 0ull;
+#pragma unroll
+  for (int w = 0; w < NWAVE; ++w) run += s_part[w] + (w < wave ? s_cnt[w] : 0u);
 
-  const uint32_t unit = blockIdx.x * NWAVE + wave;
+  const uint32_t unit = unit0 + wave;
   uint32_t* words = s_words[wave];
   const uint64_t tb = (uint64_t)unit * P.tiles_per_unit;
   uint64_t te = tb + P.tiles_per_unit;
   te = te < P.n_tiles ? te : P.n_tiles;
-  unsigned long long run = P.dctl->base + (tb < te ? P.unit_cnt[unit] : 0u);
   const unsigned long long lt = lanemask_lt();
   bool bad = false, over = false;
   for (uint64_t tile = tb; tile < te; ++tile) {
@@ -324,7 +323,6 @@ static hipError_t launch_decode_chain(DParams P, size_t cent_lds, hipStream_t s)
   P.pre_elems = piece;
   const uint32_t waves = P.n_units + P.pre_units;
   NK_DLAUNCH(KK_DCOUNT, k_dcount, (waves + 3) / 4, UNIT_TPB, 0, P);
-  NK_DLAUNCH(KK_DSCAN, k_dscan, 1, USCAN_TPB, 0, P);
   NK_DLAUNCH(KK_DECODE, (k_decode<T, VEC>), P.n_units / 4, UNIT_TPB, cent_lds, P);
   return hipSuccess;
 }

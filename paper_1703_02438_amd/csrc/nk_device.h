@@ -119,6 +119,70 @@ __device__ __forceinline__ double bin_floor_fast(double x, double inv, bool& sur
   return f;
 }
 
+// Fine bin of the change ratio without the correctly rounded division, for
+// the passes that need only the bin and the validity of a point (the
+// histogram and the encoder).  The exact definition is
+//   d = fl(fl(q - p) / p),  valid = isfinite(p) && |d| <= cap,
+//   m = floor(fl(fl(d - lo) / bw)).
+// The fast path takes r0 = the hardware reciprocal of p, one Newton step
+// r1 = r0 + r0 (1 - p r0), and d1 = fl(q - p) * r1.  When |1 - p r0| <= 2^-20,
+// r1 is within 2^-39.9 of 1/p, so d1 is within 2^-39.6 |d1| of d (the
+// division's own rounding included).  Then:
+//   - validity is certain unless |d1| lies within 2^-36 of cap;
+//   - with x1 = fl(d1 - lo) and t1 = fl(x1 * inv), t1 differs from the exact
+//     quotient fl(fl(d - lo) / bw) by at most 2^-38 |d1| inv (the ratio's
+//     error, scaled) plus 2^-49 |t1| (the roundings, as in bin_floor), so
+//     floor(t1) is the exact bin unless an integer lies within
+//     thr = 2^-36 |d1| inv + 2^-48 |t1| of t1 (both terms taken twice over).
+// A point is `sure` when its reciprocal is that good and neither test is
+// close.  A zero, infinite or NaN p makes 1 - p r0 a NaN and a p whose
+// reciprocal overflows makes it infinite, so such points are never sure;
+// neither is a ratio at the cap or a bin edge.  The caller recomputes the
+// points that are not sure with ratio_of and floor((d - lo) / bw).  When a
+// point is sure, `valid` is its validity and the result its bin.  inv_err is
+// inv * 2^-36.
+__device__ __forceinline__ double ratio_bin_fast(double p, double q, double cap_lo,
+                                                 double cap_hi, double lo, double inv,
+                                                 double inv_err, bool& valid, bool& sure) {
+  const double qp = q - p;
+  const double r0 = __builtin_amdgcn_rcp(p);
+  const double e0 = __builtin_fma(-p, r0, 1.0);
+  const double r1 = __builtin_fma(r0, e0, r0);
+  const double d1 = qp * r1;
+  const double ad = fabs(d1);
+  const bool in_lo = ad <= cap_lo;  // false for a NaN ratio
+  const bool in_hi = ad <= cap_hi;
+  valid = in_lo;
+  const double t = (d1 - lo) * inv;
+  const double f = floor(t);
+  const double frac = t - f;
+  const double thr = __builtin_fma(ad, inv_err, fabs(t) * 0x1p-48);
+  const bool bin_ok = (frac > thr) & ((1.0 - frac) > thr);
+  // in_lo implies in_hi: a valid point needs its bin certain, an invalid one
+  // a ratio clearly past the cap
+  sure = (fabs(e0) <= 0x1p-20) & ((in_lo & bin_ok) | !in_hi);
+  return f;
+}
+
+// The fine bin and validity of a point, bit-identical to the exact
+// definition: ratio_bin_fast, and the exact division where it is unsure.
+__device__ __forceinline__ double ratio_bin(double p, double q, double cap, double cap_lo,
+                                            double cap_hi, double lo, double bw, double inv,
+                                            double inv_err, bool& valid) {
+  bool sure;
+  double m = ratio_bin_fast(p, q, cap_lo, cap_hi, lo, inv, inv_err, valid, sure);
+  if (!sure) {
+    double d;
+    valid = ratio_of(p, q, cap, d);
+    m = floor((d - lo) / bw);
+  }
+  return m;
+}
+
+// Margins of ratio_bin_fast's validity test: cap (1 -+ 2^-36).
+__device__ __forceinline__ double cap_below(double cap) { return cap * (1.0 - 0x1p-36); }
+__device__ __forceinline__ double cap_above(double cap) { return cap * (1.0 + 0x1p-36); }
+
 // Bin centre lo + (2m + 1) E from a bin id held as a double (an integer below
 // 2^51, so 2m + 1 is exact), rounded to the snapshot type and widened back.
 template <typename T>

@@ -62,7 +62,8 @@ struct Ctl {
   unsigned int flags;             // NUMARCK_FLAG_*
   unsigned int tail_bins;         // distinct tail bins (k_hinsert)
   unsigned int tail_max;          // largest tail-bin count (k_hinsert)
-  // derived by k_derive
+  // derived from the range (derive_job): written by k_hclear, read by the
+  // kernels after it (the histogram derives them itself)
   double lo, hi;
   long long M;
   long long wbase;
@@ -180,6 +181,8 @@ struct Geo {
   uint32_t chunk_vec;       // 16-byte vectors per streaming chunk
   uint32_t stream_nt;       // load hints of the streaming passes (stream_nt_for)
   uint32_t chain;           // the jobs are a time chain (see JobGroup::chain)
+  uint32_t za;              // zero-anchored bins: the window is set before the
+                            // histogram (k_init), not derived from the range
 };
 
 // Launch parameters a tuner may change (none changes any output).
@@ -344,6 +347,9 @@ int encoder_occupancy(int dtype, int cls, bool table);
 // Streaming chunks of a job (0 for an empty job, at least 1 otherwise).
 uint64_t stream_chunks(uint64_t n, int dtype, uint32_t chunk_vec);
 hipError_t launch_decompress(const DParams& p, hipStream_t s);
+// Reference read / write / copy kernels (numarck_stream_kernel).
+hipError_t launch_stream(int kind, const void* src, void* dst, uint64_t bytes, unsigned per_cu,
+                         hipStream_t s);
 hipError_t launch_histogram_export(Ctl* ctl, const uint32_t* gwin, const uint32_t* hslot,
                                    const uint32_t* hcnt, const int64_t* tail, int64_t* ids,
                                    uint32_t* counts, uint64_t capacity, uint64_t* count_dev,

@@ -184,6 +184,8 @@ numarck_decompress = _bind("numarck_decompress", _i,
 numarck_decompress_range = _bind("numarck_decompress_range", _i,
                                  [ctypes.POINTER(NumarckHeader), _vp, _vp, _vp, _vp, _vp, _u64,
                                   _u64, _vp, _vp, _vp, _sz, _vp])
+numarck_stream_kernel = _bind("numarck_stream_kernel", _i, [_i, _vp, _vp, _u64, _u32, _vp])
+STREAM_READ, STREAM_READ_NT, STREAM_WRITE, STREAM_WRITE_NT, STREAM_COPY, STREAM_COPY_NT = range(6)
 numarck_static_scratch_bytes = _bind("numarck_static_scratch_bytes", _sz, [])
 numarck_decompress_range_noalloc = _bind("numarck_decompress_range_noalloc", _i,
                                          [ctypes.POINTER(NumarckHeader), _vp, _vp, _vp, _vp,
@@ -212,6 +214,9 @@ numarck_plan_run = _bind("numarck_plan_run", _i, [_vp, _vp])
 numarck_plan_capture = _bind("numarck_plan_capture", _i, [_vp, _vp])
 numarck_plan_replay = _bind("numarck_plan_replay", _i, [_vp, _vp])
 numarck_plan_destroy = _bind("numarck_plan_destroy", None, [_vp])
+numarck_plan_autotune = _bind("numarck_plan_autotune", _i,
+                              [ctypes.POINTER(NumarckJob), _u32, _vp, _sz, _u32, _u32, _vp,
+                               ctypes.POINTER(NumarckTuning)])
 numarck_plan_groups = _bind("numarck_plan_groups", _u32,
                             [_vp, ctypes.POINTER(NumarckPlanGroup), _u32])
 numarck_compress_batch = _bind("numarck_compress_batch", _i,
@@ -575,6 +580,38 @@ class ClosedLoop:
         return c
 
 
+def _job_array(jobs: list[BatchJob], recon: bool, bin_ids: bool, outputs: list[dict] | None):
+    """The numarck_job array of a batch, its outputs and its workspace."""
+    if not jobs:
+        raise ValueError("empty batch")
+    kept, outs = [], []
+    arr = (NumarckJob * len(jobs))()
+    for i, j in enumerate(jobs):
+        p, q = j.prev.reshape(-1), j.curr.reshape(-1)
+        if p.dtype != q.dtype or p.numel() != q.numel() or not (p.is_cuda and q.is_cuda):
+            raise ValueError(f"job {i}: prev and curr must be device tensors of one dtype and size")
+        o = outputs[i] if outputs is not None else alloc_outputs(
+            p.numel(), p.dtype, j.B, j.block_bytes, recon, bin_ids, p.device)
+        arr[i] = NumarckJob(_ptr(p), _ptr(q), p.numel(), dtype_code(p.dtype), float(j.E),
+                            int(j.B), int(j.block_bytes), out_struct(o), int(j.tail_cap))
+        kept.append((p, q, j))
+        outs.append(o)
+    ws = torch.empty(max(numarck_batch_workspace_bytes(arr, len(jobs)), 1), dtype=torch.uint8,
+                     device=jobs[0].prev.device)
+    return kept, outs, arr, ws
+
+
+def plan_autotune(jobs: list[BatchJob], reps: int = 3, zero_anchored: bool = False,
+                  outputs: list[dict] | None = None, stream=None) -> NumarckTuning:
+    """numarck_plan_autotune: the fastest launch tuning for this batch."""
+    kept, outs, arr, ws = _job_array(jobs, False, False, outputs)
+    best = NumarckTuning()
+    _check(numarck_plan_autotune(arr, len(jobs), _ptr(ws), ws.numel(), int(reps),
+                                 1 if zero_anchored else 0, _stream(stream), ctypes.byref(best)),
+           "numarck_plan_autotune")
+    return best
+
+
 class Plan:
     """A batch plan (numarck_plan_*): the jobs' outputs are allocated here (or
     passed in), the descriptors are uploaded once; :meth:`run` launches the
@@ -583,25 +620,8 @@ class Plan:
     def __init__(self, jobs: list[BatchJob], recon: bool = False, bin_ids: bool = False,
                  outputs: list[dict] | None = None, tune: NumarckTuning | None = None,
                  stream=None, zero_anchored: bool = False):
-        if not jobs:
-            raise ValueError("empty batch")
-        self.jobs = []
-        self.outputs = []
-        arr = (NumarckJob * len(jobs))()
-        for i, j in enumerate(jobs):
-            p, q = j.prev.reshape(-1), j.curr.reshape(-1)
-            if p.dtype != q.dtype or p.numel() != q.numel() or not (p.is_cuda and q.is_cuda):
-                raise ValueError(f"job {i}: prev and curr must be device tensors of one dtype and size")
-            o = outputs[i] if outputs is not None else alloc_outputs(
-                p.numel(), p.dtype, j.B, j.block_bytes, recon, bin_ids, p.device)
-            arr[i] = NumarckJob(_ptr(p), _ptr(q), p.numel(), dtype_code(p.dtype), float(j.E),
-                                int(j.B), int(j.block_bytes), out_struct(o), int(j.tail_cap))
-            self.jobs.append((p, q, j))
-            self.outputs.append(o)
+        self.jobs, self.outputs, arr, self.ws = _job_array(jobs, recon, bin_ids, outputs)
         self._arr = arr
-        dev = jobs[0].prev.device
-        self.ws = torch.empty(max(numarck_batch_workspace_bytes(arr, len(jobs)), 1),
-                              dtype=torch.uint8, device=dev)
         h = _vp()
         create = numarck_plan_create_zero_anchored if zero_anchored else numarck_plan_create
         st = create(arr, len(jobs), ctypes.byref(tune) if tune is not None else None,
@@ -827,6 +847,13 @@ def histogram(c: Compressed, capacity: int | None = None, stream=None):
     _check(st, "numarck_histogram_export")
     k = int(cnt.item())
     return ids[:min(k, capacity)], counts[:min(k, capacity)], k
+
+
+def stream_kernel(kind: int, src: torch.Tensor | None, dst: torch.Tensor, nbytes: int,
+                  per_cu: int = 8, stream=None):
+    """One reference read / write / copy launch (numarck_stream_kernel)."""
+    _check(numarck_stream_kernel(int(kind), _ptr(src), _ptr(dst), int(nbytes), int(per_cu),
+                                 _stream(stream)), "numarck_stream_kernel")
 
 
 def timing_enable(on: bool = True):

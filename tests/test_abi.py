@@ -199,7 +199,7 @@ def test_plan_validation_without_gpu(nk):
 
 def test_tuning_defaults_and_files(nk, tmp_path):
     t = nk.default_tuning()
-    assert t.as_dict() == {"range_blocks_per_cu": 8, "hist_blocks_per_cu": 2, "hist_lds": 1,
+    assert t.as_dict() == {"range_blocks_per_cu": 2, "hist_blocks_per_cu": 2, "hist_lds": 1,
                            "chunk_vec": 0, "unit_pct": 100, "stream_loads": 0}
     good = tmp_path / "good.txt"
     good.write_text("# comment\nf64 27 4 2 1 8192 75 1\nf32 20 8 4 0 2048 100\n")
@@ -279,3 +279,21 @@ def test_decompress_noalloc_validation_without_gpu(nk):
     assert nk.numarck_decompress_range_noalloc(*args(bad, 0, 10)) == nk.EBITS
     assert nk.numarck_decompress_range_noalloc(None, *args(h, 0, 10)[1:]) == nk.EINVAL
     assert nk.numarck_static_scratch_bytes() >= nk.numarck_decompress_workspace_bytes(1 << 31)
+
+
+def test_stream_kernel_validation_without_gpu(nk):
+    a, b = 0x300000, 0x400000
+    assert nk.numarck_stream_kernel(6, a, b, 1 << 20, 8, None) == nk.EINVAL
+    assert nk.numarck_stream_kernel(-1, a, b, 1 << 20, 8, None) == nk.EINVAL
+    assert nk.numarck_stream_kernel(nk.STREAM_COPY, a, b, (1 << 20) + 8, 8, None) == nk.EINVAL
+    assert nk.numarck_stream_kernel(nk.STREAM_COPY, a, b, 1 << 20, 0, None) == nk.EINVAL
+    assert nk.numarck_stream_kernel(nk.STREAM_COPY, a, b, 1 << 20, 65, None) == nk.EINVAL
+    assert nk.numarck_stream_kernel(nk.STREAM_COPY, None, b, 1 << 20, 8, None) == nk.EINVAL
+    assert nk.numarck_stream_kernel(nk.STREAM_COPY, a + 8, b, 1 << 20, 8, None) == nk.EALIGN
+    assert nk.numarck_stream_kernel(nk.STREAM_WRITE, None, b + 4, 1 << 20, 8, None) == nk.EALIGN
+    assert nk.numarck_stream_kernel(nk.STREAM_READ, a, None, 1 << 20, 8, None) == nk.EINVAL
+
+
+def test_plan_autotune_validation_without_gpu(nk):
+    arr = (nk.NumarckJob * 1)()
+    assert nk.numarck_plan_autotune(arr, 1, 0x200000, 1 << 30, 2, 0, None, None) == nk.EINVAL

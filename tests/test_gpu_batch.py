@@ -236,3 +236,27 @@ def test_time_chains(nk):
         assert_matches_oracle(nk, res[i], orc.compress(pn, qn, E, B), pn, qn, E, B,
                               check_hist=False, label=f"chain job {i}")
     plan.close()
+
+
+def test_plan_autotune(nk):
+    """numarck_plan_autotune on a batch of many small uneven jobs (where the
+    histogram's placement is a real choice) returns a valid tuning; a plan
+    built with it gives every job's plain compression bit for bit, for both
+    anchorings."""
+    specs = inputs.batched_specs(48, seed=1719, lo_edge=8, hi_edge=48)
+    pairs = [inputs.mixture_pair(sp.n, seed=sp.seed, dtype=sp.dtype, device="cuda")
+             for sp in specs]
+    bj = [nk.BatchJob(p, q, sp.E, sp.B) for (p, q), sp in zip(pairs, specs)]
+    for za in (False, True):
+        best = nk.plan_autotune(bj, reps=2, zero_anchored=za)
+        d = best.as_dict()
+        assert d["hist_lds"] in (0, 1) and 1 <= d["unit_pct"] <= 100, d
+        assert 1 <= d["range_blocks_per_cu"] <= 8 and 1 <= d["hist_blocks_per_cu"] <= 8, d
+        plan = nk.Plan(bj, recon=True, bin_ids=True, tune=best, zero_anchored=za)
+        res = plan.run()
+        torch.cuda.synchronize()
+        plain = nk.compress_zero_anchored if za else nk.compress
+        for i, ((p, q), sp, c) in enumerate(zip(pairs, specs, res)):
+            ref = plain(p, q, sp.E, sp.B, recon=True, bin_ids=True)
+            assert_same_compression(c, ref, f"autotuned plan za={za} job {i} {d}")
+        plan.close()

@@ -2,6 +2,8 @@
 C ABI.  Sizes span several tiles and ragged tails; edge cases cover empty and
 one-element inputs, every index width, invalid points, the tail (out-of-
 window) path of the histogram and the capacity flag."""
+import math
+
 import numpy as np
 import pytest
 import torch
@@ -263,3 +265,61 @@ def test_subnormal_error_bound(nk, E):
     c, o, p = compare_compress(nk, prev, curr, E, 8, label="subnormal E")
     assert c.header().M == 1
     compare_decompress(nk, c, o, p, prev, _ranges(n, rng))
+
+
+def _certificate_case(n, dt, E, seed, anchor):
+    """Points that sit on or next to what decides a point's bin and validity
+    without the division: ratios on bin edges (lo + 2kE, or odd multiples of
+    E for zero-anchored bins) and one or two ulps either side, ratios at the
+    validity cap and next to it, subnormal and huge previous values, zeros
+    and non-finite values, spread through the array so that every wave mixes
+    them with ordinary points."""
+    rng = np.random.default_rng(seed)
+    p = rng.lognormal(0.0, 1.0, n) * rng.choice([-1.0, 1.0], n)
+    k = rng.integers(-300, 300, n).astype(np.float64)
+    base = -0.5 if anchor == "lo" else -E
+    d = base + 2.0 * E * k
+    d[0] = -0.5 if anchor == "lo" else d[0]  # the minimum ratio: lo = -0.5
+    if anchor == "lo":
+        d = np.maximum(d, -0.5)
+    q = p * (1.0 + d)
+    # one or two ulps either side of the edge
+    nudge = rng.integers(-2, 3, n)
+    q = q + nudge * np.spacing(q)
+    cap = math.ldexp(E, 50)
+    m = n // 50
+    idx = rng.choice(np.arange(1, n), 6 * m, replace=False)
+    a, b, c, e, f, g = np.split(idx, 6)
+    p[a] = 1.0
+    q[a] = 1.0 + cap * (1.0 + rng.integers(-4, 5, m) * 2.0 ** -52)  # at the cap
+    p[b] = rng.choice([5e-324, 1e-310, -2.2e-308, 1e-320], m)  # subnormal prev
+    q[b] = p[b] * rng.choice([1.0, 2.0, 0.5, -1.0], m)
+    p[c] = rng.choice([1.7e308, -1.0e308, 8.9e307], m)  # reciprocal near underflow
+    q[c] = p[c] * (1.0 + rng.normal(0, 2 * E, m))
+    p[e] = rng.choice([0.0, -0.0, np.inf, -np.inf, np.nan], m)
+    q[f] = rng.choice([np.inf, -np.inf, np.nan], m)
+    q[g] = p[g] * 0.75  # ratio -0.25
+    with np.errstate(all="ignore"):
+        return p.astype(dt), q.astype(dt)
+
+
+@pytest.mark.parametrize("dt", [np.float64, np.float32])
+@pytest.mark.parametrize("E,B", [(2.0 ** -10, 8), (1e-3, 10), (3e-5, 12)])
+def test_fast_bin_certificate_cases(nk, dt, E, B):
+    """The bin passes take the change ratio through a reciprocal with an error
+    certificate; where the certificate is unsure they recompute the exact
+    division.  Inputs crowded with the cases at its edges match the oracle
+    bit for bit, paper-anchored and zero-anchored."""
+    prev, curr = _certificate_case(100_003, dt, E, int(E * 1e9) + B, "lo")
+    c, o, p = compare_compress(nk, prev, curr, E, B, label="certificate")
+    compare_decompress(nk, c, o, p, prev, _ranges(prev.size, np.random.default_rng(B)))
+    prev, curr = _certificate_case(100_003, dt, E, int(E * 1e9) + B + 1, "zero")
+    o = oracle.get().compress(prev, curr, E, B, binning="zero_anchored")
+    P = torch.from_numpy(prev).to("cuda:0")
+    Q = torch.from_numpy(curr).to("cuda:0")
+    cz = nk.compress_zero_anchored(P, Q, E, B, recon=True, bin_ids=True)
+    hz = cz.header()
+    assert hz.n_inc == o.info["n_inc"] and hz.k_used == o.info["k_used"]
+    assert np.array_equal(to_np(cz.packed[: o.info["packed_words"]]).view(np.uint32), o.packed)
+    assert np.array_equal(bits(to_np(cz.incomp[: hz.n_inc])), bits(o.incomp))
+    assert np.array_equal(bits(to_np(cz.recon[: hz.n])), bits(o.recon))

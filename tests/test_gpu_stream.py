@@ -1,0 +1,40 @@
+"""The reference streaming kernels (numarck_stream_kernel) do what the
+roofline measurement assumes: the copies copy, the writes write every word,
+the reads read every vector (their per-wave words XOR to the buffer's)."""
+import numpy as np
+import pytest
+import torch
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def nk():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_1703_02438_amd.numarck as nk
+    return nk
+
+
+@pytest.mark.parametrize("nbytes", [16, 4096, (1 << 20) + 48, 3 * (1 << 24) + 16 * 777])
+@pytest.mark.parametrize("per_cu", [1, 8, 64])
+def test_stream_kernels(nk, nbytes, per_cu):
+    g = torch.Generator(device="cuda").manual_seed(nbytes + per_cu)
+    src = torch.randint(-2**31, 2**31 - 1, (nbytes // 4,), dtype=torch.int32, device="cuda",
+                        generator=g)
+    for kind in (nk.STREAM_COPY, nk.STREAM_COPY_NT):
+        dst = torch.zeros_like(src)
+        nk.stream_kernel(kind, src, dst, nbytes, per_cu)
+        torch.cuda.synchronize()
+        assert torch.equal(dst, src), kind
+    for kind in (nk.STREAM_WRITE, nk.STREAM_WRITE_NT):
+        dst = torch.zeros_like(src)
+        nk.stream_kernel(kind, None, dst, nbytes, per_cu)
+        torch.cuda.synchronize()
+        assert bool((dst == 0x3FF00000).all()), kind
+    want = int(np.bitwise_xor.reduce(src.cpu().numpy().view(np.uint32)))
+    for kind in (nk.STREAM_READ, nk.STREAM_READ_NT):
+        sink = torch.zeros(1 << 18, dtype=torch.int32, device="cuda")
+        nk.stream_kernel(kind, src, sink, nbytes, per_cu)
+        torch.cuda.synchronize()
+        got = int(np.bitwise_xor.reduce(sink.cpu().numpy().view(np.uint32)))
+        assert got == want, kind
