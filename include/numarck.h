@@ -415,7 +415,9 @@ typedef struct numarck_server numarck_server;
 
 typedef struct numarck_server_config {
   uint64_t budget_bytes; /* device bytes the server may account for: the arena plus the
-                            registered variables' resident snapshots */
+                            registered variables' snapshots, two per variable (the latest
+                            record's reference and the next previous snapshot, both
+                            pinned by the request contract below) */
   uint64_t arena_bytes;  /* device arena for records and workspaces (<= budget_bytes) */
   uint32_t slots;        /* batches in flight at once, one HIP stream each (1..8) */
   uint32_t max_batch;    /* compression requests per batch (1..NUMARCK_MAX_JOBS) */
@@ -468,8 +470,9 @@ typedef struct numarck_server_stats {
 numarck_status numarck_server_create(const numarck_server_config* cfg, numarck_server** out);
 /* Register a variable of n elements with its first snapshot `initial` (device,
  * caller-owned, kept unchanged until the variable's second compression has
- * completed).  ECAPACITY if the resident snapshots would exceed the budget or
- * one compression of it could never fit in the arena. */
+ * completed).  ECAPACITY if its two pinned snapshots (2 n L bytes) would take
+ * the resident snapshots plus the arena past the budget, or if one
+ * compression of it could never fit in the arena. */
 numarck_status numarck_server_add_variable(numarck_server* s, uint64_t n, numarck_dtype dtype,
                                            double E, uint32_t B, uint64_t block_bytes,
                                            const void* initial, uint32_t* var_id);
@@ -499,12 +502,18 @@ void numarck_server_destroy(numarck_server* s);
  *                     which must hold 16 * per_cu * (compute units) bytes
  *   WRITE, WRITE_NT : writes dst (every 32-bit word 0x3FF00000); src unused
  *   COPY, COPY_NT   : copies src to dst (distinct buffers)
- * bytes must be a multiple of 16, src and dst 16-byte aligned.  EINVAL on a
- * bad kind, size, pointer or per_cu; asynchronous on `stream`. */
+ *   READ2_WRITE16   : the encoder's traffic: src is two arrays of bytes/2
+ *                     each, read in step (non-temporal); for every 16-byte
+ *                     position one 16-bit word goes to dst (bytes/16 bytes
+ *                     written, 1/16 of the read volume)
+ * bytes must be a multiple of 16 (of 32 for READ2_WRITE16), src and dst
+ * 16-byte aligned.  EINVAL on a bad kind, size, pointer or per_cu;
+ * asynchronous on `stream`. */
 typedef enum {
   NUMARCK_STREAM_READ = 0, NUMARCK_STREAM_READ_NT = 1,
   NUMARCK_STREAM_WRITE = 2, NUMARCK_STREAM_WRITE_NT = 3,
-  NUMARCK_STREAM_COPY = 4, NUMARCK_STREAM_COPY_NT = 5
+  NUMARCK_STREAM_COPY = 4, NUMARCK_STREAM_COPY_NT = 5,
+  NUMARCK_STREAM_READ2_WRITE16 = 6
 } numarck_stream_kind;
 numarck_status numarck_stream_kernel(int kind, const void* src, void* dst, uint64_t bytes,
                                      uint32_t per_cu, void* stream);
@@ -535,23 +544,30 @@ int numarck_timing_read(const char** names, uint32_t* launches, double* ms, int 
  *     padded with zeros); sub_off[s] is the first bit of sub-block s and
  *     sub_off[n_sub] the stream's length in bits, so any sub-block decodes on
  *     its own;
+ *   - a sub-block opens with eight 16-bit offsets (4 words): the first bit of
+ *     each group of 128 consecutive codes, relative to the sub-block's first
+ *     bit (an empty group past n: where the codewords end); the groups'
+ *     codewords follow without gaps, so each group decodes on its own too
+ *     (the decoder gives each group to one lane);
  *   - bits are numbered least significant first in little-endian words. */
 typedef struct numarck_lossless_header {
   uint64_t n;            /* codes in the table */
   uint64_t n_sub;        /* sub-blocks: ceil(n / 1024) */
-  uint64_t stream_words; /* 32-bit words of the codeword stream */
-  uint64_t bits;         /* codeword bits, without the sub-block padding */
+  uint64_t stream_words; /* 32-bit words of the stream (group tables, codewords, padding) */
+  uint64_t bits;         /* codeword bits, without the group tables and the padding */
   uint32_t B;            /* index width */
   uint32_t k;            /* exponential-Golomb order */
   uint32_t flags;        /* 0 */
-  uint32_t reserved;
+  uint16_t sub_log2;     /* log2 of the codes per sub-block: 10 */
+  uint16_t group_log2;   /* log2 of the codes per group: 7 */
   uint64_t bytes;        /* stored size: 2 * 2^B + 8 (n_sub + 1) + 4 stream_words + this header */
 } numarck_lossless_header;
 
 /* Sub-blocks of a table of n codes: ceil(n / 1024). */
 uint64_t numarck_lossless_subblocks(uint64_t n);
-/* Stream bytes that always suffice: 4 (ceil(n (B + 1) / 32) + n_sub).  (Order
- * k = B costs at most B + 1 bits per code, and the chosen order no more.) */
+/* Stream bytes that always suffice: 4 (ceil(n (B + 1) / 32) + 5 n_sub).  (Order
+ * k = B costs at most B + 1 bits per code, and the chosen order no more; each
+ * sub-block adds its 4-word group table and at most one padding word.) */
 size_t numarck_lossless_stream_bytes(uint64_t n, uint32_t B);
 /* Workspace bytes of numarck_lossless_encode. */
 size_t numarck_lossless_workspace_bytes(uint32_t B);
@@ -574,8 +590,9 @@ numarck_status numarck_lossless_encode(const uint32_t* packed, uint64_t n, uint3
  * NUMARCK_FLAG_BAD_STREAM if a sub-block's offsets or codewords are corrupt
  * (that sub-block's codes are then incomplete).  Reads stay within the
  * stream's hdr->stream_words words and writes within the table.  Errors:
- * NUMARCK_EBITS, NUMARCK_EINVAL (NULL pointer, inconsistent header),
- * NUMARCK_EALIGN, NUMARCK_EHIP. */
+ * NUMARCK_EBITS, NUMARCK_EINVAL (NULL pointer, inconsistent header, a
+ * sub-block or group size other than this library's), NUMARCK_EALIGN,
+ * NUMARCK_EHIP. */
 numarck_status numarck_lossless_decode(const numarck_lossless_header* hdr,
                                        const uint16_t* code_of_rank, const uint64_t* sub_off,
                                        const uint32_t* stream, uint32_t* packed, uint32_t* flags,

@@ -27,7 +27,10 @@ FLAG_BAD_INDEX = 1
 FLAG_INC_OVERRUN = 2
 
 # Compile flags: binary64 evaluated as written (no FMA contraction, no fast-math).
-CFLAGS = ["-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared"]
+# -fopenmp: the per-element loops may run on several threads (orc_set_threads;
+# one by default), with identical results.
+CFLAGS = ["-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC",
+          "-shared"]
 
 
 def build(src: str = _SRC, out: str = _LIB_PATH, extra=()) -> str:
@@ -68,6 +71,8 @@ class Oracle:
                 raise FileNotFoundError(path)
             build()
         lib = ctypes.CDLL(path)
+        lib.orc_set_threads.argtypes = [ctypes.c_int]
+        lib.orc_set_threads.restype = ctypes.c_int
         lib.orc_ratio.argtypes = [_VP, _VP, ctypes.c_uint64, ctypes.c_int, ctypes.c_double, _VP, _VP]
         lib.orc_ratio.restype = ctypes.c_int
         lib.orc_range.argtypes = [_VP, _VP, ctypes.c_uint64, _VP, _VP]
@@ -111,6 +116,11 @@ class Oracle:
         self.lib = lib
 
     # -- individual steps ----------------------------------------------------
+    def set_threads(self, n: int) -> int:
+        """Threads of the per-element loops; returns the count in effect.
+        Results are identical for every count (tests/test_oracle_threads.py)."""
+        return int(self.lib.orc_set_threads(int(n)))
+
     def ratio(self, prev: np.ndarray, curr: np.ndarray, E: float):
         prev, curr, dt = _pair(prev, curr)
         n = prev.size
@@ -226,7 +236,7 @@ class Oracle:
         sub_off = np.zeros(nsub + 1, np.uint64)
         k = ctypes.c_uint32(0)
         words = ctypes.c_uint64(0)
-        cap = n * 33 // 32 + nsub + 2
+        cap = n * 33 // 32 + 5 * nsub + 2  # codewords, a group table and a padding word each
         stream = np.zeros(max(cap, 1), np.uint32)
         st = self.lib.orc_lossless_encode(_p(packed), n, B, _p(cor), ctypes.byref(k), _p(bits_k),
                                           _p(sub_off), _p(stream), stream.size, ctypes.byref(words))

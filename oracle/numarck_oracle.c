@@ -50,6 +50,27 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* Threads of the per-element loops (ratios, range, bin ids, candidate
+ * indices, verification).  Every such loop writes element j's results from
+ * element j's inputs only, and the range's min/max is a total order, so any
+ * thread count gives the same bytes; the histogram, the selection, the
+ * placement of the incompressible values, the packing and the block offsets
+ * stay serial.  1 by default. */
+static int g_threads = 1;
+
+int orc_set_threads(int n) {
+#ifdef _OPENMP
+  g_threads = n < 1 ? 1 : n;
+#else
+  (void)n;
+  g_threads = 1;
+#endif
+  return g_threads;
+}
 
 /* ---------------------------------------------------------------- helpers */
 
@@ -105,6 +126,7 @@ static int check_args(int dtype, double E, uint32_t B) {
 int orc_ratio(const void* prev, const void* curr, uint64_t n, int dtype, double E,
               double* d, uint8_t* valid) {
   double cap = ldexp(E, 50);
+#pragma omp parallel for schedule(static) num_threads(g_threads)
   for (uint64_t j = 0; j < n; j++) {
     double p = load_as_double(prev, dtype, j);
     double q = load_as_double(curr, dtype, j);
@@ -126,16 +148,33 @@ static int precedes(double a, double b) {
 uint64_t orc_range(const double* d, const uint8_t* valid, uint64_t n, double* lo, double* hi) {
   uint64_t nv = 0;
   double mn = 0.0, mx = 0.0;
-  for (uint64_t j = 0; j < n; j++) {
-    if (!valid[j]) continue;
-    if (nv == 0) {
-      mn = d[j];
-      mx = d[j];
-    } else {
-      if (precedes(d[j], mn)) mn = d[j];
-      if (precedes(mx, d[j])) mx = d[j];
+#pragma omp parallel num_threads(g_threads)
+  {
+    uint64_t tnv = 0;
+    double tmn = 0.0, tmx = 0.0;
+#pragma omp for schedule(static)
+    for (uint64_t j = 0; j < n; j++) {
+      if (!valid[j]) continue;
+      if (tnv == 0) {
+        tmn = d[j];
+        tmx = d[j];
+      } else {
+        if (precedes(d[j], tmn)) tmn = d[j];
+        if (precedes(tmx, d[j])) tmx = d[j];
+      }
+      tnv++;
     }
-    nv++;
+#pragma omp critical
+    if (tnv) {
+      if (nv == 0) {
+        mn = tmn;
+        mx = tmx;
+      } else {
+        if (precedes(tmn, mn)) mn = tmn;
+        if (precedes(mx, tmx)) mx = tmx;
+      }
+      nv += tnv;
+    }
   }
   *lo = mn;
   *hi = mx;
@@ -147,6 +186,7 @@ uint64_t orc_range(const double* d, const uint8_t* valid, uint64_t n, double* lo
 void orc_bin_ids(const double* d, const uint8_t* valid, uint64_t n, double lo, double E,
                  int64_t* m) {
   double width = 2.0 * E;
+#pragma omp parallel for schedule(static) num_threads(g_threads)
   for (uint64_t j = 0; j < n; j++) {
     if (valid[j])
       m[j] = (int64_t)floor((d[j] - lo) / width);
@@ -317,6 +357,7 @@ static int index_and_pack(const void* prev, const void* curr, uint64_t n, int dt
   const uint32_t esc = k;
   const size_t L = elem_size(dtype);
   uint64_t n_inc = 0;
+#pragma omp parallel for schedule(static) num_threads(g_threads)
   for (uint64_t j = 0; j < n; j++) {
     uint32_t code = esc;
     const int64_t i = cand[j];
@@ -330,13 +371,16 @@ static int index_and_pack(const void* prev, const void* curr, uint64_t n, int dt
         if (recon) store_rounded(recon, dtype, j, r);
       }
     }
-    if (code == esc) {
-      copy_elem(incomp, n_inc, curr, j, dtype);
-      n_inc++;
-      if (recon) copy_elem(recon, j, curr, j, dtype);
-    }
+    if (code == esc && recon) copy_elem(recon, j, curr, j, dtype);
     idx[j] = code;
     if (index) index[j] = (uint16_t)code;
+  }
+  /* step 6: the incompressible values, in element order */
+  for (uint64_t j = 0; j < n; j++) {
+    if (idx[j] == esc) {
+      copy_elem(incomp, n_inc, curr, j, dtype);
+      n_inc++;
+    }
   }
 
   /* step 7: packing */
@@ -433,6 +477,7 @@ static int compress_topk(const void* prev, const void* curr, uint64_t n, int dty
 
   /* each valid point's candidate index: the rank of its bin among the
      selected ones, or none */
+#pragma omp parallel for schedule(static) num_threads(g_threads)
   for (uint64_t j = 0; j < n; j++) m[j] = valid[j] ? find_sorted(sel, k_used, m[j]) : -1;
 
   orc_info part = {0};
@@ -510,6 +555,7 @@ int orc_compress_ew(const void* prev, const void* curr, uint64_t n, int dtype, d
   if (n_valid > 0)
     for (uint32_t i = 0; i < k; i++)
       store_rounded(centers, dtype, (uint64_t)i, lo + ((double)i + 0.5) * w);
+#pragma omp parallel for schedule(static) num_threads(g_threads)
   for (uint64_t j = 0; j < n; j++) {
     cand[j] = -1;
     if (!valid[j]) continue;
@@ -637,6 +683,16 @@ static uint32_t get_bit(const uint32_t* w, uint64_t pos) {
 
 uint64_t orc_lossless_subblocks(uint64_t n) { return (n + ORC_SUB - 1) / ORC_SUB; }
 
+/* The 16-bit value at bits [pos, pos + 16) and its store. */
+static void put_u16(uint32_t* w, uint64_t pos, uint32_t v) {
+  for (uint32_t b = 0; b < 16; b++) put_bit(w, pos + b, (v >> b) & 1u);
+}
+static uint32_t get_u16(const uint32_t* w, uint64_t pos) {
+  uint32_t v = 0;
+  for (uint32_t b = 0; b < 16; b++) v |= get_bit(w, pos + b) << b;
+  return v;
+}
+
 int orc_lossless_encode(const uint32_t* packed, uint64_t n, uint32_t B, uint16_t* code_of_rank,
                         uint32_t* k_out, uint64_t* bits_k, uint64_t* sub_off, uint32_t* stream,
                         uint64_t cap_words, uint64_t* words_out) {
@@ -669,11 +725,12 @@ int orc_lossless_encode(const uint32_t* packed, uint64_t n, uint32_t B, uint16_t
       k = kk;
     }
   }
-  /* sub-block offsets: each sub-block padded to a whole word */
+  /* sub-block offsets: the group table, then the codewords, padded to a
+     whole word */
   const uint64_t nsub = orc_lossless_subblocks(n);
   sub_off[0] = 0;
   for (uint64_t s = 0; s < nsub; s++) {
-    uint64_t bits = 0;
+    uint64_t bits = ORC_SUB_HEAD_BITS;
     const uint64_t e = (s + 1) * ORC_SUB < n ? (s + 1) * ORC_SUB : n;
     for (uint64_t j = s * ORC_SUB; j < e; j++) bits += eg_len(rank[get_index(packed, j, B)], k);
     sub_off[s + 1] = sub_off[s] + (bits + 31) / 32 * 32;
@@ -687,15 +744,23 @@ int orc_lossless_encode(const uint32_t* packed, uint64_t n, uint32_t B, uint16_t
   }
   if (words) memset(stream, 0, words * 4);
   for (uint64_t s = 0; s < nsub; s++) {
-    uint64_t pos = sub_off[s];
-    const uint64_t e = (s + 1) * ORC_SUB < n ? (s + 1) * ORC_SUB : n;
-    for (uint64_t j = s * ORC_SUB; j < e; j++) {
-      const uint64_t x = (uint64_t)rank[get_index(packed, j, B)] + ((uint64_t)1 << k);
-      const uint32_t nb = floor_log2_u64(x); /* x has nb + 1 bits */
-      const uint32_t q = nb - k;
-      pos += q;                              /* q zeros */
-      put_bit(stream, pos++, 1u);            /* the leading one */
-      for (uint32_t b = 0; b < nb; b++) put_bit(stream, pos++, (uint32_t)(x >> b) & 1u);
+    uint64_t pos = sub_off[s] + ORC_SUB_HEAD_BITS;
+    for (uint32_t g = 0; g < ORC_GROUPS; g++) {
+      /* group g: codes [s ORC_SUB + g ORC_GROUP, + ORC_GROUP) of the table,
+         or none past n; its first bit relative to the sub-block's */
+      put_u16(stream, sub_off[s] + 16 * g, (uint32_t)(pos - sub_off[s]));
+      uint64_t j0 = s * ORC_SUB + (uint64_t)g * ORC_GROUP;
+      uint64_t j1 = j0 + ORC_GROUP;
+      j0 = j0 < n ? j0 : n;
+      j1 = j1 < n ? j1 : n;
+      for (uint64_t j = j0; j < j1; j++) {
+        const uint64_t x = (uint64_t)rank[get_index(packed, j, B)] + ((uint64_t)1 << k);
+        const uint32_t nb = floor_log2_u64(x); /* x has nb + 1 bits */
+        const uint32_t q = nb - k;
+        pos += q;                              /* q zeros */
+        put_bit(stream, pos++, 1u);            /* the leading one */
+        for (uint32_t b = 0; b < nb; b++) put_bit(stream, pos++, (uint32_t)(x >> b) & 1u);
+      }
     }
   }
   free(sc); free(rank);
@@ -709,26 +774,37 @@ int orc_lossless_decode(const uint16_t* code_of_rank, uint32_t k, const uint64_t
   const uint64_t nsub = orc_lossless_subblocks(n);
   memset(packed, 0, (n * B + 31) / 32 * 4);
   for (uint64_t s = 0; s < nsub; s++) {
-    uint64_t pos = sub_off[s];
+    const uint64_t base = sub_off[s];
     const uint64_t end = sub_off[s + 1];
-    const uint64_t e = (s + 1) * ORC_SUB < n ? (s + 1) * ORC_SUB : n;
-    for (uint64_t j = s * ORC_SUB; j < e; j++) {
-      uint32_t q = 0;
-      while (pos < end && !get_bit(stream, pos)) {
-        q++;
-        pos++;
+    if (end < base + ORC_SUB_HEAD_BITS) return ORC_EINVAL;
+    /* every group decodes from its own offset and must end where the next
+       one starts */
+    for (uint32_t g = 0; g < ORC_GROUPS; g++) {
+      uint64_t pos = base + get_u16(stream, base + 16 * g);
+      const uint64_t gend = g + 1 < ORC_GROUPS ? base + get_u16(stream, base + 16 * (g + 1)) : end;
+      if (pos < base + ORC_SUB_HEAD_BITS || gend > end || pos > gend) return ORC_EINVAL;
+      uint64_t j0 = s * ORC_SUB + (uint64_t)g * ORC_GROUP;
+      uint64_t j1 = j0 + ORC_GROUP;
+      j0 = j0 < n ? j0 : n;
+      j1 = j1 < n ? j1 : n;
+      for (uint64_t j = j0; j < j1; j++) {
+        uint32_t q = 0;
+        while (pos < gend && !get_bit(stream, pos)) {
+          q++;
+          pos++;
+        }
+        if (pos >= gend || q + k > 16) return ORC_EINVAL;
+        pos++; /* the leading one */
+        const uint32_t nb = q + k;
+        if (pos + nb > gend) return ORC_EINVAL;
+        uint64_t x = (uint64_t)1 << nb;
+        for (uint32_t b = 0; b < nb; b++) x |= (uint64_t)get_bit(stream, pos++) << b;
+        const uint64_t v = x - ((uint64_t)1 << k);
+        if (v >= ((uint64_t)1 << B)) return ORC_EINVAL;
+        put_index(packed, j, B, code_of_rank[v]);
       }
-      if (pos >= end || q + k > 16) return ORC_EINVAL;
-      pos++; /* the leading one */
-      const uint32_t nb = q + k;
-      if (pos + nb > end) return ORC_EINVAL;
-      uint64_t x = (uint64_t)1 << nb;
-      for (uint32_t b = 0; b < nb; b++) x |= (uint64_t)get_bit(stream, pos++) << b;
-      const uint64_t v = x - ((uint64_t)1 << k);
-      if (v >= ((uint64_t)1 << B)) return ORC_EINVAL;
-      put_index(packed, j, B, code_of_rank[v]);
+      if (g + 1 < ORC_GROUPS && pos != gend) return ORC_EINVAL;
     }
   }
   return ORC_OK;
 }
-

@@ -50,6 +50,10 @@ typedef struct {
 } orc_info;
 
 /* Step 1, eq. (1): change ratio and validity of every point. */
+/* Threads of the per-element loops (1 by default); returns the count set
+ * (always 1 when built without OpenMP).  Results do not depend on it. */
+int orc_set_threads(int n);
+
 int orc_ratio(const void* prev, const void* curr, uint64_t n, int dtype, double E,
               double* d, uint8_t* valid);
 
@@ -125,17 +129,27 @@ int orc_decompress_range(const orc_info* info, const void* prev, const uint32_t*
  * Sec. IV-C): codes ranked by frequency (ties to the smaller code), ranks
  * written as exponential-Golomb codewords of the order k in [0, B] with the
  * fewest bits (ties to the smaller k), in sub-blocks of ORC_SUB codes that
- * each start on a 32-bit word.  code_of_rank: 2^B entries; bits_k (optional):
- * B + 1 totals in bits, unpadded; sub_off: n_sub + 1 bit offsets (the last is
+ * each start on a 32-bit word.  A sub-block opens with ORC_GROUPS 16-bit
+ * offsets (least significant bit first): the first bit of each group of
+ * ORC_GROUP consecutive codes, relative to the sub-block's first bit (an
+ * empty group past n: where the codewords end); the groups' codewords follow
+ * without gaps, then zero padding to the next word.  Every group decodes on
+ * its own.  code_of_rank: 2^B entries; bits_k (optional): B + 1 totals in
+ * bits of the codewords alone; sub_off: n_sub + 1 bit offsets (the last is
  * the stream's length in bits); stream: cap_words words.  *words_out gets
  * the stream's words even when they exceed cap_words (then ORC_EINVAL). */
 #define ORC_SUB 1024
+#define ORC_GROUP 128
+#define ORC_GROUPS (ORC_SUB / ORC_GROUP)
+#define ORC_SUB_HEAD_BITS (16 * ORC_GROUPS)
 uint64_t orc_lossless_subblocks(uint64_t n);
 int orc_lossless_encode(const uint32_t* packed, uint64_t n, uint32_t B, uint16_t* code_of_rank,
                         uint32_t* k_out, uint64_t* bits_k, uint64_t* sub_off, uint32_t* stream,
                         uint64_t cap_words, uint64_t* words_out);
 /* The inverse: the B-bit index table of n codes.  ORC_EINVAL on a corrupt
- * stream (a codeword past its sub-block, or a rank of 2^B or more). */
+ * stream (a group offset out of order or outside its sub-block, a codeword
+ * past its group, a group not ending where the next starts, or a rank of
+ * 2^B or more). */
 int orc_lossless_decode(const uint16_t* code_of_rank, uint32_t k, const uint64_t* sub_off,
                         const uint32_t* stream, uint64_t n, uint32_t B, uint32_t* packed);
 

@@ -335,7 +335,10 @@ uint64_t numarck_lossless_subblocks(uint64_t n) { return (n + LL_SUB_CODES - 1) 
 
 size_t numarck_lossless_stream_bytes(uint64_t n, uint32_t B) {
   if (B < 1 || B > 16) return 0;
-  return 4 * ((n * (B + 1) + 31) / 32 + numarck_lossless_subblocks(n));
+  // the codewords (order B costs at most B + 1 bits per code, the chosen
+  // order no more), and per sub-block its group table (4 words) and a
+  // padding word
+  return 4 * ((n * (B + 1) + 31) / 32 + 5 * numarck_lossless_subblocks(n));
 }
 
 size_t numarck_lossless_workspace_bytes(uint32_t B) {
@@ -392,6 +395,14 @@ numarck_status numarck_lossless_decode_range(const numarck_lossless_header* hdr,
   if (hdr->n >= ((uint64_t)1 << 32) || hdr->k > hdr->B ||
       hdr->n_sub != numarck_lossless_subblocks(hdr->n) || (hdr->n && (!stream || !packed)))
     return NUMARCK_EINVAL;
+  // the stream's layout must be this library's
+  if (hdr->sub_log2 >= 32 || hdr->group_log2 >= 32 ||
+      (1ull << hdr->sub_log2) != LL_SUB_CODES || (1ull << hdr->group_log2) != LL_GROUP_CODES) {
+    g_last_error = "lossless stream with sub-blocks of 2^" + std::to_string(hdr->sub_log2) +
+                   " codes and groups of 2^" + std::to_string(hdr->group_log2) +
+                   "; this library reads 1024 and 128";
+    return NUMARCK_EINVAL;
+  }
   if (((uintptr_t)stream & 15u) || ((uintptr_t)packed & 15u)) return NUMARCK_EALIGN;
   if (sub_begin > hdr->n_sub || sub_count > hdr->n_sub - sub_begin) return NUMARCK_ERANGE;
   LLDecodeParams p{};
@@ -1243,8 +1254,9 @@ const char* numarck_last_error(void) { return g_last_error.c_str(); }
 
 numarck_status numarck_stream_kernel(int kind, const void* src, void* dst, uint64_t bytes,
                                      uint32_t per_cu, void* stream) {
-  if (kind < NUMARCK_STREAM_READ || kind > NUMARCK_STREAM_COPY_NT) return NUMARCK_EINVAL;
-  if (bytes % 16 != 0 || per_cu < 1 || per_cu > 64 || !dst) return NUMARCK_EINVAL;
+  if (kind < NUMARCK_STREAM_READ || kind > NUMARCK_STREAM_READ2_WRITE16) return NUMARCK_EINVAL;
+  const uint64_t unit = kind == NUMARCK_STREAM_READ2_WRITE16 ? 32 : 16;
+  if (bytes % unit != 0 || per_cu < 1 || per_cu > 64 || !dst) return NUMARCK_EINVAL;
   const bool reads = kind != NUMARCK_STREAM_WRITE && kind != NUMARCK_STREAM_WRITE_NT;
   if (reads && !src) return NUMARCK_EINVAL;
   if (!aligned16(dst) || (reads && !aligned16(src))) return NUMARCK_EALIGN;

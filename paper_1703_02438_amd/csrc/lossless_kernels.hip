@@ -12,7 +12,11 @@
 //     equal totals);
 //   - sub-blocks of LL_SUB codes start on 32-bit words (the previous one is
 //     padded with zeros), and sub_off[s] is the first bit of sub-block s, so
-//     any sub-block decodes on its own.
+//     any sub-block decodes on its own;
+//   - a sub-block opens with LL_GROUPS 16-bit offsets: the first bit of each
+//     group of LL_GROUP consecutive codes relative to the sub-block's (an
+//     empty group past n: where the codewords end); the codewords follow
+//     without gaps, so any group decodes on its own too.
 // Bits are numbered least significant first in little-endian 32-bit words,
 // as in the index table.
 //
@@ -21,14 +25,17 @@
 // choice), k_llsub (bits of every sub-block), k_llscan (offsets and the
 // header), k_llwrite.  Decode: k_llflags, k_lldecode.  The encoder's
 // per-sub-block passes give each sub-block to a wave (each lane a 128-bit
-// chunk of the table per round); the decoder gives it to one lane, which
-// walks its codewords in order (where a codeword starts is known only after
-// the one before).
+// chunk of the table per round); the decoder gives each group to one lane,
+// which walks its codewords in order (where a codeword starts is known only
+// after the one before).
 #include "nk_device.h"
 
 namespace nk {
 
 constexpr int LL_SUB = (int)LL_SUB_CODES;  // codes per sub-block
+constexpr int LL_GROUP = (int)LL_GROUP_CODES;  // codes per group (restart point)
+constexpr int LL_GROUPS = LL_SUB / LL_GROUP;
+constexpr uint32_t LL_HEAD_BITS = 16u * LL_GROUPS;  // the group offsets at a sub-block's start
 constexpr int LL_TPB = 256;
 constexpr int LL_LDS_BINS = 8192;   // code counts kept in LDS up to this many codes
 constexpr int LL_ORD_TPB = 1024;
@@ -191,7 +198,8 @@ __global__ void __launch_bounds__(LL_ORD_TPB) k_llorder(LLParams p) {
   }
 }
 
-// Bits of sub-block s, rounded up to a word, into sub_off[s + 1].  One wave
+// Bits of sub-block s (its group offsets and codewords), rounded up to a
+// word, into sub_off[s + 1].  One wave
 // per sub-block; each lane takes the codes that start in its 128-bit chunks
 // of the sub-block's words (16-byte loads).
 __global__ void __launch_bounds__(LL_TPB) k_llsub(LLParams p) {
@@ -219,7 +227,7 @@ __global__ void __launch_bounds__(LL_TPB) k_llsub(LLParams p) {
     for (uint32_t i = 0; i < ch.b - ch.a; ++i) bits += ll_len(rank_of[ch.code(t, i, B)], k);
   }
   bits = wave_sum_u64(bits);
-  if (lane == 0) p.sub_off[s + 1] = (bits + 31) / 32 * 32;
+  if (lane == 0) p.sub_off[s + 1] = (LL_HEAD_BITS + bits + 31) / 32 * 32;
 }
 
 // Inclusive scan of sub_off[1..n_sub] in place (one workgroup, tiles of
@@ -276,7 +284,8 @@ __global__ void __launch_bounds__(LL_SCAN_TPB) k_llscan(LLParams p) {
     h->B = p.B;
     h->k = k;
     h->flags = 0;
-    h->reserved = 0;
+    h->sub_log2 = 10;
+    h->group_log2 = 7;
     h->bytes = ((uint64_t)2 << p.B) + 8 * (ns + 1) + 4 * (total / 32) +
                sizeof(numarck_lossless_header);
   }
@@ -288,7 +297,7 @@ __global__ void __launch_bounds__(LL_SCAN_TPB) k_llscan(LLParams p) {
 // the wave's LDS copy of the sub-block's stream (ORed into at most two words
 // each; ORs commute, so rounds need no ordering), and the wave stores the
 // finished copy with consecutive lanes on consecutive words.
-constexpr int LL_WIN = (LL_SUB * 33 + 31) / 32 + 1;  // words of the longest sub-block
+constexpr int LL_WIN = (LL_HEAD_BITS + LL_SUB * 33 + 31) / 32 + 1;  // words of the longest sub-block
 
 __global__ void __launch_bounds__(LL_TPB) k_llwrite(LLParams p) {
   __shared__ uint32_t s_win[LL_TPB / 64][LL_WIN];
@@ -314,7 +323,7 @@ __global__ void __launch_bounds__(LL_TPB) k_llwrite(LLParams p) {
   const uint32_t B = p.B, ncode = (uint32_t)(j1 - j0);
   const uint64_t ws = j0 * B / 32, twords = (p.n * B + 31) / 32;
   const uint32_t nch = (ncode * B + 127) / 128;
-  uint32_t off = 0;  // bits placed so far
+  uint32_t off = LL_HEAD_BITS;  // bits placed so far: the group offsets come first
   for (uint32_t t0 = 0; t0 < nch; t0 += 64) {
     const uint32_t t = t0 + lane;
     SubChunk ch;
@@ -331,6 +340,9 @@ __global__ void __launch_bounds__(LL_TPB) k_llwrite(LLParams p) {
     }
     uint32_t pos = off + inc - mine;
     for (uint32_t i = 0; i < ch.b - ch.a; ++i) {
+      const uint32_t c = ch.a + i;  // code within the sub-block
+      if (c % LL_GROUP == 0)        // a group starts here: its offset
+        atomicOr(&win[c / LL_GROUP / 2], pos << (16 * ((c / LL_GROUP) & 1)));
       const uint32_t x = rank_of[ch.code(t, i, B)] + (1u << k);
       const uint32_t nb = ll_log2(x);
       const uint32_t q = nb - k;
@@ -344,15 +356,20 @@ __global__ void __launch_bounds__(LL_TPB) k_llwrite(LLParams p) {
     }
     off += __shfl(inc, 63, 64);
   }
+  // groups past the table's end: the offset where the codewords end
+  if (lane < LL_GROUPS && (uint32_t)lane * LL_GROUP >= ncode)
+    atomicOr(&win[lane / 2], off << (16 * (lane & 1)));
   wave_lds_sync();
   for (uint32_t i = lane; i < words; i += 64) p.stream[gw + i] = win[i];
 }
 
 __global__ void k_llflags(uint32_t* flags) { *flags = 0u; }
 
-// Sub-block s back to its B-bit codes.  A codeword that runs past its
-// sub-block, one of more than 33 bits or a rank of 2^B or more sets the flag
-// and ends the sub-block.
+// Group g of sub-block s back to its B-bit codes, one lane per group.  A
+// group's offsets out of order or outside its sub-block, a codeword that runs
+// past its group, one of more than 33 bits, a rank of 2^B or more, or a group
+// that does not end where the next one starts set the flag (the group's codes
+// are then incomplete).
 __global__ void __launch_bounds__(LL_TPB) k_lldecode(LLDecodeParams p) {
   __shared__ uint16_t s_code[LL_LDS_RANKS];
   const uint32_t Kt = 1u << p.B;
@@ -362,42 +379,50 @@ __global__ void __launch_bounds__(LL_TPB) k_lldecode(LLDecodeParams p) {
     __syncthreads();
   }
   const uint16_t* code_of_rank = lds ? s_code : p.code_of_rank;
-  const uint64_t s = p.s_begin + (uint64_t)blockIdx.x * LL_TPB + threadIdx.x;
+  const uint64_t gi = (uint64_t)blockIdx.x * LL_TPB + threadIdx.x;
+  const uint64_t s = p.s_begin + gi / LL_GROUPS;
+  const uint32_t g = (uint32_t)(gi % LL_GROUPS);
   if (s >= p.s_end) return;  // no workgroup barrier below
   const uint64_t start = p.sub_off[s], end = p.sub_off[s + 1];
-  if (start > end || end > p.stream_words * 32 || (start & 31) || (end & 31)) {
+  if (start > end || end > p.stream_words * 32 || (start & 31) || (end & 31) ||
+      end - start < LL_HEAD_BITS) {
     atomicOr(p.flags, NUMARCK_FLAG_BAD_STREAM);
     return;
   }
-  const uint32_t K = 1u << p.B, k = p.k;
-  uint64_t iw = start / 32;
-  const uint64_t ew = end / 32;
+  // the group's bits [gs, ge): its offset, and the next group's (or the
+  // sub-block's end)
+  const uint64_t hw = start / 32;
+  const uint32_t off = (p.stream[hw + g / 2] >> (16 * (g & 1))) & 0xFFFFu;
+  const uint64_t gs = start + off;
+  const uint64_t ge =
+      g + 1 < LL_GROUPS ? start + ((p.stream[hw + (g + 1) / 2] >> (16 * ((g + 1) & 1))) & 0xFFFFu)
+                        : end;
+  if (off < LL_HEAD_BITS || gs > ge || ge > end) {
+    atomicOr(p.flags, NUMARCK_FLAG_BAD_STREAM);
+    return;
+  }
+  const uint32_t K = 1u << p.B, k = p.k, B = p.B;
+  uint64_t j0 = s * LL_SUB + (uint64_t)g * LL_GROUP;
+  uint64_t j1 = j0 + LL_GROUP;
+  j0 = j0 < p.n ? j0 : p.n;
+  j1 = j1 < p.n ? j1 : p.n;
+  // bits from gs on, 32 at a time into a 64-bit buffer; `pos` is the
+  // absolute position of the buffer's first bit
+  uint64_t iw = gs / 32;
+  const uint64_t ew = (ge + 31) / 32;
+  uint64_t pos = gs;
   unsigned long long buf = 0;
   uint32_t nbits = 0;
-  const uint64_t j0 = s * LL_SUB;
-  const uint64_t j1 = j0 + LL_SUB < p.n ? j0 + LL_SUB : p.n;
-  uint64_t ow = j0 * p.B / 32;  // a multiple of 4: sub-blocks span 32 B words
+  if (iw < ew) {
+    buf = p.stream[iw] >> (gs & 31);
+    nbits = 32 - (uint32_t)(gs & 31);
+    ++iw;
+  }
+  // the group's codes are 4B whole words of the table (128 codes of B bits),
+  // written 16 bytes at a time
+  uint64_t ow = j0 * B / 32;
   unsigned long long ob = 0;
-  uint32_t on = 0;
-  // Each lane walks its own stretch of memory, so the stream is read and the
-  // table written 16 bytes at a time: the words of the aligned group holding
-  // iw (c0..c3 from word cb; a group reaching past the sub-block is read word
-  // by word), and completed output words gathered four at a time.
-  uint64_t cb = iw & ~3ull;
-  uint32_t c0 = 0, c1 = 0, c2 = 0, c3 = 0;
-  auto load_group = [&]() {
-    if (cb + 4 <= ew) {
-      const uint4 g = *reinterpret_cast<const uint4*>(p.stream + cb);
-      c0 = g.x; c1 = g.y; c2 = g.z; c3 = g.w;
-    } else {
-      c0 = cb < ew ? p.stream[cb] : 0u;
-      c1 = cb + 1 < ew ? p.stream[cb + 1] : 0u;
-      c2 = cb + 2 < ew ? p.stream[cb + 2] : 0u;
-      c3 = cb + 3 < ew ? p.stream[cb + 3] : 0u;
-    }
-  };
-  if (iw < ew) load_group();
-  uint32_t o0 = 0, o1 = 0, o2 = 0, o3 = 0, oc = 0;
+  uint32_t on = 0, o0 = 0, o1 = 0, o2 = 0, o3 = 0, oc = 0;
   auto put_word = [&](uint32_t w) {
     o0 = oc == 0 ? w : o0;
     o1 = oc == 1 ? w : o1;
@@ -409,39 +434,42 @@ __global__ void __launch_bounds__(LL_TPB) k_lldecode(LLDecodeParams p) {
       oc = 0;
     }
   };
+  bool bad = false;
   for (uint64_t j = j0; j < j1; ++j) {
     while (nbits <= 32 && iw < ew) {
-      if (iw >= cb + 4) {
-        cb += 4;
-        load_group();
-      }
-      const uint32_t d = (uint32_t)(iw - cb);
-      const uint32_t w = d == 0 ? c0 : d == 1 ? c1 : d == 2 ? c2 : c3;
-      buf |= (unsigned long long)w << nbits;
+      buf |= (unsigned long long)p.stream[iw] << nbits;
       nbits += 32;
       ++iw;
     }
-    const uint32_t q = buf ? (uint32_t)__builtin_ctzll(buf) : 64u;
+    const uint64_t left = ge - pos;  // bits of the group not yet taken
+    const uint32_t avail = (uint64_t)nbits < left ? nbits : (uint32_t)left;
+    const unsigned long long live = avail >= 64 ? buf : (buf & ((1ull << avail) - 1ull));
+    const uint32_t q = live ? (uint32_t)__builtin_ctzll(live) : 64u;
     const uint32_t nb = q + k;
-    if (nb > 16 || q + 1 + nb > nbits) {
-      atomicOr(p.flags, NUMARCK_FLAG_BAD_STREAM);
-      return;
+    if (nb > 16 || q + 1 + nb > avail) {
+      bad = true;
+      break;
     }
     const uint32_t low = (uint32_t)(buf >> (q + 1)) & ((1u << nb) - 1u);
     buf >>= (q + 1 + nb);
     nbits -= q + 1 + nb;
+    pos += q + 1 + nb;
     const uint32_t v = ((1u << nb) | low) - (1u << k);
     if (v >= K) {
-      atomicOr(p.flags, NUMARCK_FLAG_BAD_STREAM);
-      return;
+      bad = true;
+      break;
     }
     ob |= (unsigned long long)code_of_rank[v] << on;
-    on += p.B;
+    on += B;
     if (on >= 32) {
       put_word((uint32_t)ob);
       ob >>= 32;
       on -= 32;
     }
+  }
+  if (bad || (g + 1 < LL_GROUPS && pos != ge)) {
+    atomicOr(p.flags, NUMARCK_FLAG_BAD_STREAM);
+    return;
   }
   if (oc > 0) p.packed[ow] = o0;
   if (oc > 1) p.packed[ow + 1] = o1;
@@ -478,7 +506,7 @@ hipError_t launch_lossless_encode(const LLParams& p, hipStream_t s) {
 
 hipError_t launch_lossless_decode(const LLDecodeParams& p, hipStream_t s) {
   LL_LAUNCH(k_llflags, 1, 1, p.flags);
-  const uint64_t sb = (p.s_end - p.s_begin + LL_TPB - 1) / LL_TPB;
+  const uint64_t sb = ((p.s_end - p.s_begin) * LL_GROUPS + LL_TPB - 1) / LL_TPB;
   if (sb) LL_LAUNCH(k_lldecode, sb, LL_TPB, p);
   return hipSuccess;
 }

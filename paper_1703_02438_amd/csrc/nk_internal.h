@@ -335,6 +335,7 @@ struct LLDecodeParams {
 hipError_t launch_lossless_encode(const LLParams& p, hipStream_t s);
 hipError_t launch_lossless_decode(const LLDecodeParams& p, hipStream_t s);
 constexpr uint64_t LL_SUB_CODES = 1024;
+constexpr uint64_t LL_GROUP_CODES = 128;
 
 // One compression with the fine bins anchored at -E (centred on multiples of
 // 2E): no range pass; histogram, top-k and the rest as launch_compress.

@@ -518,7 +518,9 @@ numarck_status numarck_server_add_variable(numarck_server* s, uint64_t n, numarc
   const uint64_t rws = range_ws_bytes(n);
   v.need = slice > rws ? slice : rws;
   std::lock_guard<std::mutex> lk(s->mu);
-  const uint64_t res = n * elem_bytes(dtype);
+  // two caller snapshots of the variable stay in device memory: the latest
+  // record's reference and the next compression's previous snapshot
+  const uint64_t res = 2 * n * elem_bytes(dtype);
   if (s->resident + res + s->cfg.arena_bytes > s->cfg.budget_bytes) return NUMARCK_ECAPACITY;
   // two record blocks for good (latest + next), from the top of the arena;
   // what stays below must still take any one request's workspace

@@ -1,7 +1,8 @@
 // stream_kernels.hip -- reference kernels for the HBM roofline the
 // compression passes are measured against: a read, a write and a copy of a
 // large buffer with 16-byte vector accesses, each with cached or
-// non-temporal accesses.  Not part of the compression path; the benchmark
+// non-temporal accesses, and the encoder's shape (two arrays read, a
+// 1/16-sized stream written).  Not part of the compression path; the benchmark
 // times them beside it and uses the copy as the kernel of known traffic that
 // scales the hardware byte counters.
 #include "nk_device.h"
@@ -73,6 +74,30 @@ __global__ void __launch_bounds__(STREAM_TPB) k_stream_copy(const nk_u32x4* __re
   for (; i < nvec; i += stride) sstore<NT>(dst + i, sload<NT>(src + i));
 }
 
+// The encoder's traffic shape: two arrays of nvec vectors each (the two
+// snapshots, src and src + nvec) read in step, and one 16-bit word written
+// per vector position (a 1/16 write stream, the index table of 8-bit codes
+// of 64-bit values).
+template <bool NT>
+__global__ void __launch_bounds__(STREAM_TPB) k_stream_mix(const nk_u32x4* __restrict__ src,
+                                                           uint64_t nvec,
+                                                           unsigned short* __restrict__ dst) {
+  const uint64_t stride = (uint64_t)gridDim.x * STREAM_TPB;
+  const nk_u32x4* __restrict__ a = src;
+  const nk_u32x4* __restrict__ b = src + nvec;
+  uint64_t i = (uint64_t)blockIdx.x * STREAM_TPB + threadIdx.x;
+  for (; i + stride < nvec; i += 2 * stride) {
+    const nk_u32x4 x0 = sload<NT>(a + i), y0 = sload<NT>(b + i);
+    const nk_u32x4 x1 = sload<NT>(a + i + stride), y1 = sload<NT>(b + i + stride);
+    gstore(dst + i, (unsigned short)(x0.x ^ y0.y));
+    gstore(dst + i + stride, (unsigned short)(x1.x ^ y1.y));
+  }
+  for (; i < nvec; i += stride) {
+    const nk_u32x4 x = sload<NT>(a + i), y = sload<NT>(b + i);
+    gstore(dst + i, (unsigned short)(x.x ^ y.y));
+  }
+}
+
 // Workgroups of a streaming launch: `per_cu` per compute unit, no more than
 // the vectors need.
 static unsigned stream_grid(uint64_t nvec, unsigned per_cu) {
@@ -111,6 +136,12 @@ hipError_t launch_stream(int kind, const void* src, void* dst, uint64_t bytes, u
     case NUMARCK_STREAM_COPY_NT:
       hipLaunchKernelGGL(k_stream_copy<true>, dim3(grid), dim3(STREAM_TPB), 0, s, in, out, nvec);
       break;
+    case NUMARCK_STREAM_READ2_WRITE16: {
+      const unsigned g2 = stream_grid(nvec / 2, per_cu);
+      hipLaunchKernelGGL(k_stream_mix<true>, dim3(g2), dim3(STREAM_TPB), 0, s, in, nvec / 2,
+                         static_cast<unsigned short*>(dst));
+      break;
+    }
     default:
       return hipErrorInvalidValue;
   }

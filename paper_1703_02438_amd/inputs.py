@@ -210,24 +210,25 @@ def serving_specs(count: int = 32, seed: int = 1709, lo_bytes: int = 16 << 20,
     return out
 
 
-def serving_requests(specs, rate: float, seconds: float, range_frac: float = 0.05,
-                     seed: int = 1710):
-    """Poisson arrivals at `rate` per second for `seconds`: (time, var, kind,
-    start, length); kind 0 = compress, 1 = range decompression of a random
-    contiguous range (length log-uniform from 1024 elements to n / 10)."""
+def serving_requests(specs, rate: float, count: int, range_frac: float = 0.05,
+                     seed: int = 1710, range_fracs=(0.2, 0.4, 0.6, 0.8)):
+    """`count` Poisson arrivals at `rate` per second: (time, var, kind, start,
+    length); kind 0 = compress, 1 = range decompression of a contiguous range
+    whose length is one of `range_fracs` of the variable (the partial
+    decompressions of 20/40/60/80 % timed in the paper's Table 7), at a
+    random start."""
     g = _gen(seed, "cpu")
     t, reqs = 0.0, []
-    while True:
+    while len(reqs) < count:
         u = torch.rand(5, generator=g, dtype=torch.float64).tolist()
         t += -math.log(1.0 - u[0]) / rate
-        if t >= seconds:
-            return reqs
         v = min(int(u[1] * len(specs)), len(specs) - 1)
         n = specs[v].n
         if u[2] < range_frac:
-            hi = max(n // 10, 1024)
-            ln = min(int(math.exp(math.log(1024) + u[3] * (math.log(hi) - math.log(1024)))), n)
+            f = range_fracs[min(int(u[3] * len(range_fracs)), len(range_fracs) - 1)]
+            ln = max(int(n * f), 1)
             st = min(int(u[4] * (n - ln + 1)), n - ln)
             reqs.append((t, v, 1, st, ln))
         else:
             reqs.append((t, v, 0, 0, 0))
+    return reqs

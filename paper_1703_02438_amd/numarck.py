@@ -46,7 +46,8 @@ class NumarckLosslessHeader(ctypes.Structure):
     _fields_ = [
         ("n", ctypes.c_uint64), ("n_sub", ctypes.c_uint64), ("stream_words", ctypes.c_uint64),
         ("bits", ctypes.c_uint64), ("B", ctypes.c_uint32), ("k", ctypes.c_uint32),
-        ("flags", ctypes.c_uint32), ("reserved", ctypes.c_uint32), ("bytes", ctypes.c_uint64),
+        ("flags", ctypes.c_uint32), ("sub_log2", ctypes.c_uint16),
+        ("group_log2", ctypes.c_uint16), ("bytes", ctypes.c_uint64),
     ]
 
     def as_dict(self) -> dict:
@@ -185,7 +186,8 @@ numarck_decompress_range = _bind("numarck_decompress_range", _i,
                                  [ctypes.POINTER(NumarckHeader), _vp, _vp, _vp, _vp, _vp, _u64,
                                   _u64, _vp, _vp, _vp, _sz, _vp])
 numarck_stream_kernel = _bind("numarck_stream_kernel", _i, [_i, _vp, _vp, _u64, _u32, _vp])
-STREAM_READ, STREAM_READ_NT, STREAM_WRITE, STREAM_WRITE_NT, STREAM_COPY, STREAM_COPY_NT = range(6)
+(STREAM_READ, STREAM_READ_NT, STREAM_WRITE, STREAM_WRITE_NT, STREAM_COPY, STREAM_COPY_NT,
+ STREAM_READ2_WRITE16) = range(7)
 numarck_static_scratch_bytes = _bind("numarck_static_scratch_bytes", _sz, [])
 numarck_decompress_range_noalloc = _bind("numarck_decompress_range_noalloc", _i,
                                          [ctypes.POINTER(NumarckHeader), _vp, _vp, _vp, _vp,
@@ -522,7 +524,7 @@ def lossless_decode_codes(enc: Lossless, first: int, last: int, out: torch.Tenso
     in the full-size table `out` (numarck_lossless_decode_range); returns the
     flags tensor."""
     h = enc.header()
-    sb = 1024
+    sb = 1 << h.sub_log2  # codes per sub-block, as the stream records it
     s0 = first // sb
     s1 = min((last + sb - 1) // sb, h.n_sub) if last > first else s0
     flags = torch.zeros(1, dtype=torch.int32, device=out.device)

@@ -683,24 +683,32 @@ def _eg_len(v, k):
     return 2 * (v + (1 << k)).bit_length() - 1 - k
 
 
+def _group_table(offsets):
+    """The 16-bit group offsets of a sub-block as its first four words."""
+    return [offsets[i] | (offsets[i + 1] << 16) for i in range(0, 8, 2)]
+
+
 def pin_lossless_literal(o):
     """Lossless index stage on hand-worked tables.  Codes [0, 0, 1, 2, 0]
-    (B = 2): ranks 0, 1, 2, order 0 (9 bits; order 1 12, order 2 15), stream
-    1 1 010 011 1 = 459.  Codes 5x5, 2x4, 7x3, 0x2, 1x1 (B = 3): ranks
-    5->0, 2->1, 7->2, 0->3, 1->4 and the unused codes after them in code
-    order; order 0 (41 bits against 42, 47, 60); codewords 1, 010, 011,
-    00100, 00110 (the bits of x after its leading one least significant
-    first)."""
+    (B = 2): ranks 0, 1, 2, order 0 (9 bits; order 1 12, order 2 15); the
+    sub-block opens with its eight group offsets (group 0 at bit 128, the
+    empty groups 1..7 where the codewords end, 137), then the codewords
+    1 1 010 011 1 = 459, padded to 160 bits.  Codes 5x5, 2x4, 7x3, 0x2, 1x1
+    (B = 3): ranks 5->0, 2->1, 7->2, 0->3, 1->4 and the unused codes after
+    them in code order; order 0 (41 bits against 42, 47, 60); codewords 1,
+    010, 011, 00100, 00110 (the bits of x after its leading one least
+    significant first)."""
     e = o.lossless_encode(_pack_codes([0, 0, 1, 2, 0], 2), 5, 2)
     assert e["code_of_rank"].tolist() == [0, 1, 2, 3] and e["k"] == 0
-    assert e["bits_k"] == [9, 12, 15] and e["sub_off"].tolist() == [0, 32]
-    assert e["stream"].tolist() == [459]
+    assert e["bits_k"] == [9, 12, 15] and e["sub_off"].tolist() == [0, 160]
+    assert e["stream"].tolist() == [128 | 137 << 16] + [137 | 137 << 16] * 3 + [459]
     codes = [5] * 5 + [2] * 4 + [7] * 3 + [0] * 2 + [1]
     e = o.lossless_encode(_pack_codes(codes, 3), len(codes), 3)
     assert e["code_of_rank"].tolist() == [5, 2, 7, 0, 1, 3, 4, 6]
     assert e["k"] == 0 and e["bits_k"] == [41, 42, 47, 60]
     want = _words_of("1" * 5 + "010" * 4 + "011" * 3 + "00100" * 2 + "00110")
-    assert e["stream"].tolist() == want.tolist() and e["sub_off"].tolist() == [0, 64]
+    assert e["stream"].tolist() == _group_table([128] + [169] * 7) + want.tolist()
+    assert e["sub_off"].tolist() == [0, 192]
     assert np.array_equal(o.lossless_decode(e), _pack_codes(codes, 3))
     # equal totals: two codes, five each, cost 5 * 1 + 5 * 3 = 20 bits at
     # order 0 and 5 * 2 + 5 * 2 = 20 at order 1; the smaller order is taken
@@ -733,21 +741,33 @@ def pin_lossless_structure(o):
         k = e["k"]
         assert tot[k] == min(tot) and all(t > tot[k] for t in tot[:k])
         lens = np.array([_eg_len(int(r), k) for r in rank[codes]])
-        sub = [int(lens[i:i + S].sum()) for i in range(0, n, S)]
+        sub = [128 + int(lens[i:i + S].sum()) for i in range(0, n, S)]
         off = np.concatenate([[0], np.cumsum([(b + 31) // 32 * 32 for b in sub])])
         assert e["sub_off"].tolist() == off.tolist()
+        # each sub-block's group table: 128 plus the bits of the groups before
+        words = e["stream"]
+        for si in range(len(sub)):
+            w0 = int(off[si]) // 32
+            got = [(int(words[w0 + i // 2]) >> (16 * (i % 2))) & 0xFFFF for i in range(8)]
+            gl = [int(lens[si * S + g * 128: min(si * S + (g + 1) * 128, n)].sum())
+                  if si * S + g * 128 < n else 0 for g in range(8)]
+            assert got == [128 + sum(gl[:g]) for g in range(8)], (B, si)
         pr = cnt[cnt > 0] / n
         assert tot[k] >= -(cnt[cnt > 0] * np.log2(pr)).sum() - 1e-6
         assert np.array_equal(o.lossless_decode(e), _pack_codes(codes, B))
 
 
 def pin_lossless_single_symbol_and_corrupt(o):
-    """One symbol only: rank 0, order 0, one bit per code; an empty table;
-    and a stream cut short is refused."""
+    """One symbol only: rank 0, order 0, one bit per code (groups of 128
+    bits after the group table); an empty table; a stream of zeros and a
+    stream whose group offset is moved by one bit are refused."""
     n = 1024 + 5
     e = o.lossless_encode(_pack_codes([3] * n, 4), n, 4)
-    assert e["k"] == 0 and e["code_of_rank"][0] == 3 and e["sub_off"].tolist() == [0, 1024, 1056]
-    assert e["stream"][:32].tolist() == [0xFFFFFFFF] * 32 and e["stream"][32] == 0x1F
+    assert e["k"] == 0 and e["code_of_rank"][0] == 3
+    assert e["sub_off"].tolist() == [0, 1152, 1312]
+    assert e["stream"][:4].tolist() == _group_table([128 + 128 * g for g in range(8)])
+    assert e["stream"][4:36].tolist() == [0xFFFFFFFF] * 32
+    assert e["stream"][36:41].tolist() == _group_table([128] + [133] * 7) + [0x1F]
     e0 = o.lossless_encode(np.zeros(0, np.uint32), 0, 6)
     assert e0["sub_off"].tolist() == [0] and e0["stream"].size == 0
     bad = dict(e)
@@ -758,6 +778,27 @@ def pin_lossless_single_symbol_and_corrupt(o):
         pass
     else:
         raise AssertionError("a stream of zeros decoded")
+    bad = dict(e)
+    bad["stream"] = e["stream"].copy()
+    bad["stream"][1] += 1  # group 2 starts one bit late: group 2 runs short
+    try:
+        o.lossless_decode(bad)
+    except ValueError:
+        pass
+    else:
+        raise AssertionError("a moved group offset decoded")
+    bad = dict(e)
+    bad["stream"] = e["stream"].copy()
+    # sub-block 1: the empty groups 1..7 start one bit late, so group 0 ends
+    # one bit before its successor (every codeword still in bounds)
+    bad["stream"][36] += 1 << 16
+    bad["stream"][37:40] += 1 + (1 << 16)
+    try:
+        o.lossless_decode(bad)
+    except ValueError:
+        pass
+    else:
+        raise AssertionError("a group ending before its successor decoded")
 
 
 ALL_PINS = [

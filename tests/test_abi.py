@@ -247,8 +247,9 @@ def test_lossless_validation_without_gpu(nk):
     assert enc(sb=m.numarck_lossless_stream_bytes(100, 8) - 4) == nk.ECAPACITY
     assert enc(wsb=m.numarck_lossless_workspace_bytes(8) - 1) == nk.ECAPACITY
     assert m.numarck_lossless_subblocks(0) == 0 and m.numarck_lossless_subblocks(1025) == 2
-    assert m.numarck_lossless_stream_bytes(4096, 8) == 4 * (4096 * 9 // 32 + 4)
-    h = m.NumarckLosslessHeader(n=10, n_sub=1, stream_words=1, bits=10, B=8, k=9)
+    assert m.numarck_lossless_stream_bytes(4096, 8) == 4 * (4096 * 9 // 32 + 5 * 4)
+    h = m.NumarckLosslessHeader(n=10, n_sub=1, stream_words=5, bits=10, B=8, k=9, sub_log2=10,
+                                group_log2=7)
     dec = lambda hh: m.numarck_lossless_decode(ctypes.byref(hh), 0x400000, 0x500000, 0x600000,
                                                0x800000, 0x900000, None)
     assert dec(h) == nk.EINVAL  # k > B
@@ -257,6 +258,11 @@ def test_lossless_validation_without_gpu(nk):
     h.n_sub, h.B = 1, 0
     assert dec(h) == nk.EBITS
     h.B = 8
+    h.sub_log2 = 12  # a stream of another layout
+    assert dec(h) == nk.EINVAL
+    h.sub_log2, h.group_log2 = 10, 6
+    assert dec(h) == nk.EINVAL
+    h.group_log2 = 7
     misaligned = m.numarck_lossless_decode(ctypes.byref(h), 0x400000, 0x500000, 0x600004,
                                            0x800000, 0x900000, None)
     assert misaligned == nk.EALIGN
@@ -283,7 +289,9 @@ def test_decompress_noalloc_validation_without_gpu(nk):
 
 def test_stream_kernel_validation_without_gpu(nk):
     a, b = 0x300000, 0x400000
-    assert nk.numarck_stream_kernel(6, a, b, 1 << 20, 8, None) == nk.EINVAL
+    assert nk.numarck_stream_kernel(7, a, b, 1 << 20, 8, None) == nk.EINVAL
+    assert nk.numarck_stream_kernel(nk.STREAM_READ2_WRITE16, a, b, (1 << 20) + 16, 8,
+                                    None) == nk.EINVAL
     assert nk.numarck_stream_kernel(-1, a, b, 1 << 20, 8, None) == nk.EINVAL
     assert nk.numarck_stream_kernel(nk.STREAM_COPY, a, b, (1 << 20) + 8, 8, None) == nk.EINVAL
     assert nk.numarck_stream_kernel(nk.STREAM_COPY, a, b, 1 << 20, 0, None) == nk.EINVAL

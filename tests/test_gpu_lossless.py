@@ -51,6 +51,7 @@ def ll_compare(nk, packed, n, B, label=""):
     sw = h.stream_words
     assert np.array_equal(to_np(e.stream)[:sw].view(np.uint32), o["stream"]), f"{tag} stream"
     assert h.bytes == (2 << B) + 8 * (h.n_sub + 1) + 4 * sw + 56
+    assert (h.sub_log2, h.group_log2) == (10, 7), tag
     out, fl = nk.lossless_decode(e)
     assert int(fl.item()) == 0, tag
     words = (n * B + 31) // 32
@@ -118,6 +119,19 @@ def test_lossless_corrupt_stream_flagged(nk):
     e2.header()
     e2.sub_off[1] = 1 << 40
     _, fl = nk.lossless_decode(e2)
+    assert int(fl.item()) & nk.FLAG_BAD_STREAM
+    # a group offset moved by one bit: group 2 of sub-block 0 starts late, so
+    # group 1 ends before its successor (and group 2 runs short)
+    e3 = nk.lossless_encode(t, n, 4)
+    e3.header()
+    e3.stream[1] += 1
+    _, fl = nk.lossless_decode(e3)
+    assert int(fl.item()) & nk.FLAG_BAD_STREAM
+    # a group table with an offset inside the table itself
+    e4 = nk.lossless_encode(t, n, 4)
+    e4.header()
+    e4.stream[0] = 5
+    _, fl = nk.lossless_decode(e4)
     assert int(fl.item()) & nk.FLAG_BAD_STREAM
 
 

@@ -206,3 +206,21 @@ def test_bounded_tail_retry(nk):
     ref, fl = nk.decompress_range(plain, snaps[0], n - 5000, 4000)
     assert torch.equal(part[:4000].view(torch.int64), ref[:4000].view(torch.int64))
     srv.close()
+
+
+def test_budget_counts_two_snapshots_per_variable(nk):
+    """A variable pins two of its caller's snapshots (the latest record's
+    reference and the next previous snapshot): admission charges 2 n L bytes
+    against the budget, beside the arena."""
+    n = 1 << 20
+    arena = 256 << 20
+    # room for the arena plus one variable's two snapshots, but not a second
+    budget = arena + 2 * n * 8 + n * 8
+    srv = nk.Server(budget_bytes=budget, arena_bytes=arena, slots=1, max_batch=2)
+    snaps = _series(n, np.float64, 77, 1)
+    srv.add_variable(snaps[0], 1e-3, 8)
+    assert srv.stats()["resident_bytes"] == 2 * n * 8
+    with pytest.raises(nk.NumarckError) as e:
+        srv.add_variable(snaps[1], 1e-3, 8)  # one snapshot's worth would fit, two do not
+    assert e.value.status == nk.ECAPACITY
+    srv.close()

@@ -14,7 +14,7 @@ MUTANTS = [
     ("ratio_sign", "double r = (q - p) / p;", "double r = (p - q) / p;"),
     ("ratio_denominator", "double r = (q - p) / p;", "double r = (q - p) / q;"),
     ("cap_dropped", "isfinite(r) && fabs(r) <= cap;", "isfinite(r);"),
-    ("lo_is_max", "if (precedes(d[j], mn)) mn = d[j];", "if (precedes(mn, d[j])) mn = d[j];"),
+    ("lo_is_max", "if (precedes(d[j], tmn)) tmn = d[j];", "if (precedes(tmn, d[j])) tmn = d[j];"),
     ("zero_order", "return a == b && signbit(a) && !signbit(b);", "return 0;"),
     ("bin_width_E", "double width = 2.0 * E;", "double width = E;"),
     ("bin_round", "(int64_t)floor((d[j] - lo) / width)", "(int64_t)round((d[j] - lo) / width)"),
@@ -73,6 +73,17 @@ MUTANTS = [
      "sub_off[s + 1] = sub_off[s] + bits;"),
     ("ll_msb_first", "put_bit(stream, pos++, (uint32_t)(x >> b) & 1u);",
      "put_bit(stream, pos++, (uint32_t)(x >> (nb - 1 - b)) & 1u);"),
+    ("ll_group_offset_absolute", "put_u16(stream, sub_off[s] + 16 * g, (uint32_t)(pos - sub_off[s]));",
+     "put_u16(stream, sub_off[s] + 16 * g, (uint32_t)pos);"),
+    ("ll_no_group_table", "uint64_t bits = ORC_SUB_HEAD_BITS;", "uint64_t bits = 0;"),
+    ("ll_group_half_size",
+     "uint64_t j0 = s * ORC_SUB + (uint64_t)g * ORC_GROUP;\n      uint64_t j1 = j0 + ORC_GROUP;\n"
+     "      j0 = j0 < n ? j0 : n;\n      j1 = j1 < n ? j1 : n;\n      for (uint64_t j = j0; j < j1; j++) {\n"
+     "        const uint64_t x",
+     "uint64_t j0 = s * ORC_SUB + (uint64_t)g * (ORC_GROUP / 2);\n      uint64_t j1 = j0 + ORC_GROUP;\n"
+     "      j0 = j0 < n ? j0 : n;\n      j1 = j1 < n ? j1 : n;\n      for (uint64_t j = j0; j < j1; j++) {\n"
+     "        const uint64_t x"),
+    ("ll_group_end_unchecked", "if (g + 1 < ORC_GROUPS && pos != gend) return ORC_EINVAL;", ""),
 ]
 
 
