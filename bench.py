@@ -45,8 +45,8 @@ ALGO = {
 ALGO_CALL = lambda a: 16.0 + B / 8 + 8 * a
 
 # Kernels of one compression call (the library's k_* names).
-PIPELINE_KERNELS = ("init", "range", "derive", "hist", "hclear", "hinsert", "select",
-                    "tailrank", "encode", "uscan", "gather")
+PIPELINE_KERNELS = ("init", "range", "hist", "hclear", "hinsert", "select",
+                    "tailrank", "encode", "gather")
 
 
 # The sources the compression and decompression kernels are built from: the
@@ -170,20 +170,78 @@ def summarize_pmc(fetch_dir: str, write_dir: str, workload: str, cmd: str):
     print(path)
 
 
-STREAM_KINDS = ("read", "read_nt", "write", "write_nt", "copy", "copy_nt")
+def summarize_trace(trace_csv: str, out_md: str, title: str, cmd: str):
+    """A rocprofv3 --kernel-trace CSV to a markdown table of the library's
+    kernels, one row per kernel and grid size (a range decompression and a
+    full one launch the same decoder with different grids), and the sum of
+    the compression call's kernels."""
+    import csv
+
+    rows = {}
+    for r in csv.DictReader(open(trace_csv)):
+        name = r["Kernel_Name"]
+        if "nk::k_" not in name:
+            continue
+        name = name.replace("void ", "", 1)
+        grid = int(r.get("Grid_Size_X") or r.get("Grid_Size") or 0)
+        wg = int(r.get("Workgroup_Size_X") or r.get("Workgroup_Size") or 1)
+        d = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
+        rows.setdefault(name, []).append((grid // max(wg, 1), d))
+    # a kernel launched with several grids: the largest grid (the whole
+    # array) and the smaller ones (partial decompressions) are kept apart
+    split = {}
+    for name, xs in rows.items():
+        gmax = max(g for g, _ in xs)
+        one = len({g for g, _ in xs}) == 1
+        for g, d in xs:
+            key = (name, "one size" if one else "largest" if g == gmax else "smaller")
+            split.setdefault(key, []).append(d)
+    rows = split
+    lines = [f"# {title}", "", "Command (from the repository root, on one MI355X):", "", "```",
+             cmd, "```", "",
+             "Per-dispatch kernel trace (rocprofv3 `--kernel-trace`), library kernels only.  A",
+             "kernel launched with several grids has a row for its largest grid (the whole array)",
+             "and one for the smaller grids (range decompressions).", "",
+             "| kernel | grid | calls | avg us | min us | max us |",
+             "|---|---|---:|---:|---:|---:|"]
+    call = 0.0
+    for (name, wgs), ds in sorted(rows.items(), key=lambda kv: -sum(kv[1])):
+        avg = sum(ds) / len(ds)
+        lines.append(f"| `{name}` | {wgs} | {len(ds)} | {avg:.1f} | {min(ds):.1f} | {max(ds):.1f} |")
+    comp = {}
+    for (name, wgs), ds in rows.items():
+        for k in PIPELINE_KERNELS:
+            if f"nk::k_{k}<" in name or f"nk::k_{k}(" in name:
+                comp.setdefault(k, []).extend(ds)
+    if comp:
+        lines += ["", "Compression call (average of each kernel, summed):", ""]
+        for k in PIPELINE_KERNELS:
+            if k in comp:
+                a = sum(comp[k]) / len(comp[k])
+                call += a
+                lines.append(f"- `k_{k}`: {a:.1f} us")
+        lines.append(f"- sum: {call:.1f} us")
+    with open(out_md, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print(out_md)
+
+
+STREAM_KINDS = ("read", "read_nt", "write", "write_nt", "copy", "copy_nt", "read2_write16")
 
 
 def stream_section(torch, nk, reps: int, nbytes: int = 1 << 30) -> dict:
     """The library's reference streaming kernels (numarck_stream_kernel) on
-    1 GiB: read, write and copy, cached and non-temporal, at 2..16 workgroups
-    per compute unit; GB/s of bytes moved (a copy moves 2 x nbytes), the best
+    1 GiB: read, write and copy, cached and non-temporal, and the encoder's
+    shape (two arrays read, 1/16 of that written), at 2..16 workgroups per
+    compute unit; GB/s of bytes moved (a copy moves 2 x nbytes), the best
     launch of each."""
     src = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda").fill_(1.0)
     dst = torch.empty_like(src)
     stream = torch.cuda.current_stream()
     out = {}
     for kind, name in enumerate(STREAM_KINDS):
-        moved = 2 * nbytes if name.startswith("copy") else nbytes
+        moved = (2 * nbytes if name.startswith("copy") else
+                 nbytes + nbytes // 16 if name == "read2_write16" else nbytes)
         best = None
         for per_cu in (2, 4, 8, 16):
             t = time_ms(torch, lambda: nk.stream_kernel(kind, src, dst, nbytes, per_cu, stream),
@@ -197,24 +255,54 @@ def stream_section(torch, nk, reps: int, nbytes: int = 1 << 30) -> dict:
     return out
 
 
-def cpu_baseline(prev, curr, sample_elems: int):
-    import numpy as np
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
+
+# Host threads of the CPU baseline: the host's share for one GPU.
+CPU_THREADS_MAX = 16
+
+
+def cpu_baseline(prev, curr, sample_elems: int, n_total: int):
+    """The C oracle on the host cores: the whole compression of pair 0 (or
+    its first `sample_elems` values), once with the per-element loops on all
+    threads of the host's share and once on one thread (identical results;
+    the histogram sort, selection, packing and placement are serial)."""
     import oracle
 
     p = prev[:sample_elems].cpu().numpy()
     q = curr[:sample_elems].cpu().numpy()
     o = oracle.get()
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    threads = o.set_threads(min(avail, CPU_THREADS_MAX))
     t = time.perf_counter()
     o.compress(p, q, E, B, recon=False)
-    dt = time.perf_counter() - t
+    dt_mt = time.perf_counter() - t
+    o.set_threads(1)
+    t = time.perf_counter()
+    o.compress(p, q, E, B, recon=False)
+    dt_1 = time.perf_counter() - t
+    what = "all of pair 0" if p.size == n_total else f"first {p.size} elements of pair 0"
     return {
-        "value": round(p.size * 8 / dt / 1e9, 4),
+        "value": round(p.size * 8 / dt_mt / 1e9, 4),
         "unit": "GB/s",
-        "cores": 1,
+        "cores": threads,
         "kind": "oracle",
-        "sample": f"first {p.size} elements of pair 0 ({p.size * 8 / 2**20:.0f} MiB), "
-                  f"single-threaded C oracle, {dt:.2f} s",
+        "sample": f"{what} ({p.size * 8 / 2**20:.0f} MiB), C oracle, per-element loops on "
+                  f"{threads} threads: {dt_mt:.2f} s",
+        "cpu_model": cpu_model(),
+        "host_cpus": avail,
+        "single_thread": {"value": round(p.size * 8 / dt_1 / 1e9, 4), "seconds": round(dt_1, 2)},
     }
 
 
@@ -424,11 +512,116 @@ def batched_vs_plain(torch, nk, jobs, reps: int) -> dict:
     }
 
 
+CLIMATE_SNAPSHOTS, CLIMATE_PER_LAUNCH = 192, 16
+
+
+def climate_series_section(torch, nk, inputs, reps: int, spill: bool) -> dict:
+    """The climate-like time series at full length: 192 snapshots of 3600 x
+    1800 float32 (E = 1e-4, B = 10), its 191 consecutive pairs compressed as
+    191 plain calls, and as 12 batched launches of at most 16 pairs (time
+    chains: each plan reads a shared snapshot once per range pass); also
+    with zero-anchored bins, with the histogram's window counts forced to
+    global memory, and with the batch autotuner's choice.  `spill`: outliers
+    U[-0.9, 1.5] on 1 % of the cells (about 12,000 fine bins, ties at the
+    k-th count) instead of U[-0.05, 0.05]."""
+    kw = {"outlier_lo": -0.9, "outlier_hi": 1.5} if spill else {}
+    s = inputs.ClimateSeries(nlat=1800, nlon=3600, seed=1707, device="cuda", **kw)
+    snaps = [s.x.clone()] + [s.step().clone() for _ in range(CLIMATE_SNAPSHOTS - 1)]
+    del s
+    E_c, B_c = 1e-4, 10
+    jobs = [nk.BatchJob(snaps[t], snaps[t + 1], E_c, B_c) for t in range(CLIMATE_SNAPSHOTS - 1)]
+    n = snaps[0].numel()
+    in_bytes = len(jobs) * n * 4
+    stream = torch.cuda.current_stream()
+    outs = [nk.alloc_outputs(n, torch.float32, B_c) for _ in jobs]
+    ws = torch.empty(nk.numarck_workspace_bytes(n, nk.F32, B_c), dtype=torch.uint8, device="cuda")
+
+    def plain():
+        for j, o in zip(jobs, outs):
+            nk.compress(j.prev, j.curr, E_c, B_c, ws=ws, outputs=o, stream=stream)
+
+    t_plain = time_ms(torch, plain, reps, stream)
+    del ws
+    groups = [list(range(i, min(i + CLIMATE_PER_LAUNCH, len(jobs))))
+              for i in range(0, len(jobs), CLIMATE_PER_LAUNCH)]
+
+    def plans(za=False, tune=None):
+        return [nk.Plan([jobs[i] for i in g], outputs=[outs[i] for i in g], stream=stream,
+                        zero_anchored=za, tune=tune) for g in groups]
+
+    def run_all(ps):
+        for p in ps:
+            p.run(stream)
+
+    res = {"pairs": len(jobs), "launches": len(groups), "input_bytes": in_bytes,
+           "plain_ms": round(t_plain, 3), "plain_gbs": round(in_bytes / t_plain / 1e6, 1)}
+    first = [jobs[i] for i in groups[0]]
+    tuned = nk.plan_autotune(first, reps=2, outputs=[outs[i] for i in groups[0]], stream=stream)
+    glob = nk.default_tuning()
+    glob.hist_lds, glob.hist_blocks_per_cu = 0, 8
+    for name, za, tune in (("batched", False, None), ("za_batched", True, None),
+                           ("global_hist_batched", False, glob), ("tuned_batched", False, tuned)):
+        ps = plans(za, tune)
+        t = time_ms(torch, lambda: run_all(ps), reps, stream)
+        for p in ps:
+            p.close()
+        res[f"{name}_ms"] = round(t, 3)
+        res[f"{name}_gbs"] = round(in_bytes / t / 1e6, 1)
+    h = nk.header_from_device(outs[0]["hdr"])
+    assert h.flags == 0
+    res["speedup"] = round(res["plain_ms"] / res["batched_ms"], 2)
+    res["tuning"] = tuned.as_dict()
+    res["pair0"] = {"M": int(h.M), "n_nonzero": int(h.n_nonzero), "alpha": round(h.n_inc / n, 5),
+                    "tau": int(h.tau)}
+    del snaps, jobs, outs
+    torch.cuda.empty_cache()
+    return res
+
+
+def small_call_section(torch, nk, inputs, reps: int = 200) -> dict:
+    """The 64^3 float64 mixture pair (E = 1e-3, B = 8; 4 MiB of input, which
+    the caches hold): latency of one plain compression and of one full
+    decompression, HIP events around each call."""
+    n = 64 ** 3
+    p, q = inputs.mixture_pair(n, seed=1704)
+    p, q = p.cuda(), q.cuda()
+    stream = torch.cuda.current_stream()
+    ws = torch.empty(nk.numarck_workspace_bytes(n, nk.F64, 8), dtype=torch.uint8, device="cuda")
+    outs = nk.alloc_outputs(n, torch.float64, 8)
+    c = nk.compress(p, q, 1e-3, 8, ws=ws, outputs=outs, stream=stream)
+    out = torch.empty(n, dtype=torch.float64, device="cuda")
+
+    def per_call(fn):
+        for _ in range(10):
+            fn()
+        torch.cuda.synchronize()
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(reps)]
+        for a, b in evs:
+            a.record(stream)
+            fn()
+            b.record(stream)
+        torch.cuda.synchronize()
+        return [a.elapsed_time(b) * 1e3 for a, b in evs]
+
+    lc = per_call(lambda: nk.compress(p, q, 1e-3, 8, ws=ws, outputs=outs, stream=stream))
+    ld = per_call(lambda: nk.decompress(c, p, out=out, stream=stream))
+    import numpy as np
+
+    q50 = lambda x: round(float(np.percentile(x, 50)), 1)
+    q99 = lambda x: round(float(np.percentile(x, 99)), 1)
+    return {"workload": "mixture 64^3 f64, E=1e-3, B=8", "n": n,
+            "compress_us": {"p50": q50(lc), "p99": q99(lc)},
+            "decompress_us": {"p50": q50(ld), "p99": q99(ld)},
+            "compress_gbs_p50": round(n * 8 / q50(lc) / 1e3, 1)}
+
+
 def batched_section(torch, nk, inputs, reps: int) -> dict:
     """The uneven 64-variable workload (cube edges log-uniform in [32, 384],
-    60 % float64, E in {1e-4, 1e-3, 1e-2}, B in {8, 10, 12}), 16 consecutive
-    pairs of a 3600 x 1800 float32 climate-like series (E = 1e-4, B = 10), and
-    the 9 consecutive pairs of the 512^3 float64 FLASH-like series."""
+    60 % float64, E in {1e-4, 1e-3, 1e-2}, B in {8, 10, 12}), the 191
+    consecutive pairs of a 3600 x 1800 float32 climate-like series (E = 1e-4,
+    B = 10; and its outlier-heavy variant), and the 9 consecutive pairs of
+    the 512^3 float64 FLASH-like series."""
     out = {}
     jobs = []
     for sp in inputs.batched_specs(64):
@@ -436,13 +629,9 @@ def batched_section(torch, nk, inputs, reps: int) -> dict:
         jobs.append(nk.BatchJob(p, q, sp.E, sp.B))
     out["uneven_64vars"] = batched_vs_plain(torch, nk, jobs, reps)
     del jobs
-    s = inputs.ClimateSeries(nlat=1800, nlon=3600, seed=1707, device="cuda")
-    snaps = [s.x.clone()] + [s.step().clone() for _ in range(16)]
-    del s
-    out["climate_16pairs"] = batched_vs_plain(
-        torch, nk, [nk.BatchJob(snaps[t], snaps[t + 1], 1e-4, 10) for t in range(16)], reps)
-    del snaps
     torch.cuda.empty_cache()
+    out["climate_191pairs"] = climate_series_section(torch, nk, inputs, reps, spill=False)
+    out["climate_191pairs_spill"] = climate_series_section(torch, nk, inputs, reps, spill=True)
     # the 9 consecutive pairs of the 512^3 float64 FLASH-like series as one
     # batch (a time chain: its range pass reads each snapshot once)
     s = inputs.FlashSeries(edge=512, seed=1705, device="cuda")
@@ -457,26 +646,54 @@ def batched_section(torch, nk, inputs, reps: int) -> dict:
 
 
 SERVE_BUDGET = 200 << 30
+SERVE_RATE = 200.0
+SERVE_REQUESTS = 12000
+SERVE_SPEEDUPS = (1, 5, 25)
+RANGE_POOL = 4  # output buffers of the range requests, reused round robin
 
 
-def serving_section(torch, nk, inputs, seconds: float, rate: float = 200.0) -> dict:
-    """The serving loop: 32 live variables (sizes log-uniform 16 MB .. 4 GB,
-    float32/float64, E in {1e-4, 1e-3}, B = 8) with their previous snapshots
-    resident, Poisson arrivals at `rate` requests/s for `seconds`, 5 % of them
-    range decompressions, admission under a 200 GB budget.  Then the same
-    server saturated: every variable's next compression submitted at once."""
+def _lat(xs):
     import numpy as np
 
+    if not xs:
+        return None
+    a = np.asarray(xs)
+    return {"p50": round(float(np.percentile(a, 50)), 3), "p99": round(float(np.percentile(a, 99)), 3),
+            "max": round(float(a.max()), 3)}
+
+
+def serving_section(torch, nk, inputs, requests: int, rate: float = SERVE_RATE) -> dict:
+    """The serving loop: 32 live variables (sizes log-uniform 16 MB .. 4 GB,
+    float32/float64, E in {1e-4, 1e-3}, B = 8), `requests` Poisson arrivals
+    at `rate` per second, 5 % of them range decompressions of 20/40/60/80 %
+    of a variable, admission under a 200 GB budget (the arena plus two
+    pinned snapshots per variable).  The same request list is replayed at 1x,
+    5x and 25x the rate, then the server is saturated (every variable's next
+    compression at once); then the 25x list is served one request at a time
+    through plain numarck_compress / numarck_decompress_range calls, each
+    waited for, as the serial baseline.  Latency is arrival to completion."""
     specs = inputs.serving_specs()
     snaps = []
     for sp in specs:  # two snapshots per variable; compressions alternate between them
         p, q = inputs.mixture_pair(sp.n, seed=sp.seed, dtype=sp.dtype, device="cuda")
         snaps.append((p, q))
+    max_range = max(int(sp.n * 0.8) * sp.dtype.itemsize for sp in specs)
+    pool = [torch.empty(max_range // 8 + 1, dtype=torch.float64, device="cuda")
+            for _ in range(RANGE_POOL)]
     torch.cuda.synchronize()
-    resident = sum(sp.n * sp.dtype.itemsize for sp in specs)
+    resident = sum(2 * sp.n * sp.dtype.itemsize for sp in specs)
     free, _ = torch.cuda.mem_get_info()
     arena = min(SERVE_BUDGET - resident, free - (8 << 30))
     srv = nk.Server(budget_bytes=SERVE_BUDGET, arena_bytes=arena, slots=2, max_batch=32)
+
+    def poll_all():
+        got = []
+        while True:
+            part = srv.poll(4096)
+            if not part:
+                return got
+            got += part
+
     for sp, (p, q) in zip(specs, snaps):
         srv.add_variable(p, sp.E, sp.B)
     state = [0] * len(specs)  # index of the resident snapshot
@@ -485,65 +702,116 @@ def serving_section(torch, nk, inputs, seconds: float, rate: float = 200.0) -> d
         state[v] ^= 1
         srv.compress(v, snaps[v][state[v]])
     srv.drain()
-    assert all(c["status"] == 0 for c in srv.poll())
-    reqs = inputs.serving_requests(specs, rate, seconds)
-    outs = {}
-    done = []
-    t0 = time.perf_counter()
-    for (t, v, kind, st, ln) in reqs:
-        while time.perf_counter() - t0 < t:
-            time.sleep(5e-5)
-        if kind == 0:
-            state[v] ^= 1
-            srv.compress(v, snaps[v][state[v]])
-        else:
-            tk, o = srv.range(v, st, ln)
-            outs[tk] = o
-        if len(done) % 16 == 0:
-            done += srv.poll()
-    srv.drain()
-    done += srv.poll()
-    comp = [c for c in done if c["kind"] == 0]
-    rng = [c for c in done if c["kind"] == 1]
-    assert all(c["status"] == 0 and c["flags"] == 0 for c in done), \
-        [c for c in done if c["status"] or c["flags"]][:3]
-    lat = np.array([c["done_us"] - c["submit_us"] for c in comp]) / 1e3
-    rlat = np.array([c["done_us"] - c["submit_us"] for c in rng]) / 1e3 if rng else np.zeros(1)
-    span_s = (max(c["done_us"] for c in done) - min(c["submit_us"] for c in done)) / 1e6
-    in_bytes = sum(c["bytes"] for c in comp)
+    assert all(c["status"] == 0 for c in poll_all())
+    reqs = inputs.serving_requests(specs, rate, requests)
+    n_range = sum(1 for r in reqs if r[2] == 1)
+
+    def range_out(i, v, ln):
+        buf = pool[i % RANGE_POOL]
+        return buf.view(specs[v].dtype)[:max(ln, 1)]
+
+    def replay(speed: float) -> dict:
+        done, ri = [], 0
+        t0 = time.perf_counter()
+        for (t, v, kind, st, ln) in reqs:
+            while time.perf_counter() - t0 < t / speed:
+                time.sleep(2e-5)
+            if kind == 0:
+                state[v] ^= 1
+                srv.compress(v, snaps[v][state[v]])
+            else:
+                srv.range(v, st, ln, out=range_out(ri, v, ln))
+                ri += 1
+            done += srv.poll(256)
+        srv.drain()
+        done += poll_all()
+        assert len(done) == len(reqs), (len(done), len(reqs))
+        assert all(c["status"] == 0 and c["flags"] == 0 for c in done), \
+            [c for c in done if c["status"] or c["flags"]][:3]
+        comp = [c for c in done if c["kind"] == 0]
+        rng = [c for c in done if c["kind"] == 1]
+        span_s = (max(c["done_us"] for c in done) - min(c["submit_us"] for c in done)) / 1e6
+        in_bytes = sum(c["bytes"] for c in comp)
+        return {"offered_gbs": round(in_bytes / (reqs[-1][0] / speed) / 1e9, 1),
+                "sustained_gbs": round(in_bytes / span_s / 1e9, 1),
+                "latency_ms": _lat([(c["done_us"] - c["submit_us"]) / 1e3 for c in comp]),
+                "range_latency_ms": _lat([(c["done_us"] - c["submit_us"]) / 1e3 for c in rng]),
+                "seconds": round(span_s, 2)}
+
+    out = {"workload": "32 live variables, 16 MB..4 GB log-uniform, f32/f64, E in {1e-4,1e-3}, "
+                       f"B=8; {len(reqs)} Poisson requests at {rate:g}/s (x1), replayed at x5 and "
+                       "x25; 5% range decompressions of 20/40/60/80% of a variable",
+           "requests": len(reqs), "range": n_range}
+    for sp_ in SERVE_SPEEDUPS:
+        out[f"x{sp_}"] = replay(float(sp_))
+        print(f"# serving x{sp_}: {json.dumps(out[f'x{sp_}'])}", file=sys.stderr, flush=True)
     # saturated: one compression of every variable submitted at once
     srv.drain()
-    srv.poll()
+    poll_all()
     sat_t0 = time.perf_counter()
     for v in range(len(specs)):
         state[v] ^= 1
         srv.compress(v, snaps[v][state[v]])
     srv.drain()
     sat_s = time.perf_counter() - sat_t0
-    sat = srv.poll()
-    assert all(c["status"] == 0 and c["flags"] == 0 for c in sat)
-    sat_bytes = sum(c["bytes"] for c in sat)
+    sat = poll_all()
+    assert len(sat) == len(specs) and all(c["status"] == 0 and c["flags"] == 0 for c in sat)
+    out["saturated_gbs"] = round(sum(c["bytes"] for c in sat) / sat_s / 1e9, 1)
     stats = srv.stats()
     srv.close()
-    del snaps, outs
+    torch.cuda.synchronize()
     torch.cuda.empty_cache()
-    return {
-        "workload": "32 live variables, 16 MB..4 GB log-uniform, f32/f64, E in {1e-4,1e-3}, B=8; "
-                    f"Poisson {rate:g} req/s for {seconds:g} s, 5% range decompressions",
-        "requests": len(done), "compress": len(comp), "range": len(rng),
-        "offered_gbs": round(in_bytes / seconds / 1e9, 1),
-        "sustained_gbs": round(in_bytes / span_s / 1e9, 1),
-        "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 3),
-                       "p99": round(float(np.percentile(lat, 99)), 3),
-                       "max": round(float(lat.max()), 3)},
-        "range_latency_ms": {"p50": round(float(np.percentile(rlat, 50)), 3),
-                             "p99": round(float(np.percentile(rlat, 99)), 3)},
-        "saturated_gbs": round(sat_bytes / sat_s / 1e9, 1),
-        "budget_gb": SERVE_BUDGET / 2**30, "resident_gb": round(resident / 2**30, 2),
-        "arena_gb": round(arena / 2**30, 2), "arena_peak_gb": round(stats["arena_peak"] / 2**30, 2),
-        "batches": stats["batches"], "max_batch": stats["max_batch_seen"],
-        "waits_for_memory": stats["waits_for_memory"],
-    }
+    out.update({"budget_gb": SERVE_BUDGET / 2**30, "resident_gb": round(resident / 2**30, 2),
+                "arena_gb": round(arena / 2**30, 2),
+                "arena_peak_gb": round(stats["arena_peak"] / 2**30, 2),
+                "batches": stats["batches"], "max_batch": stats["max_batch_seen"],
+                "waits_for_memory": stats["waits_for_memory"],
+                "tail_retries": stats["tail_retries"]})
+
+    # serial baseline: the 25x request list, one plain call at a time
+    speed = float(SERVE_SPEEDUPS[-1])
+    nmax = max(sp.n for sp in specs)
+    ws = torch.empty(nk.numarck_workspace_bytes(nmax, nk.F64, 8), dtype=torch.uint8, device="cuda")
+    recs, outs = [], []
+    for v, sp in enumerate(specs):
+        o = nk.alloc_outputs(sp.n, sp.dtype, sp.B, device="cuda")
+        outs.append(o)
+        c = nk.compress(snaps[v][state[v] ^ 1], snaps[v][state[v]], sp.E, sp.B, ws=ws, outputs=o)
+        recs.append([c, snaps[v][state[v] ^ 1]])  # the record and its reference
+    torch.cuda.synchronize()
+    for r in recs:
+        r[0].header()
+    lat_c, lat_r, in_bytes, ri = [], [], 0, 0
+    t0 = time.perf_counter()
+    for (t, v, kind, st, ln) in reqs:
+        arrive = t / speed
+        while time.perf_counter() - t0 < arrive:
+            time.sleep(2e-5)
+        sp = specs[v]
+        if kind == 0:
+            prev, curr = snaps[v][state[v]], snaps[v][state[v] ^ 1]
+            state[v] ^= 1
+            c = nk.compress(prev, curr, sp.E, sp.B, ws=ws, outputs=outs[v])
+            torch.cuda.synchronize()
+            c.header()
+            recs[v] = [c, prev]
+            lat_c.append((time.perf_counter() - t0 - arrive) * 1e3)
+            in_bytes += sp.n * sp.dtype.itemsize
+        else:
+            c, ref = recs[v]
+            _, fl = nk.decompress_range(c, ref, st, ln, out=range_out(ri, v, ln))
+            ri += 1
+            assert int(fl.item()) == 0
+            lat_r.append((time.perf_counter() - t0 - arrive) * 1e3)
+    span = time.perf_counter() - t0
+    out["serial_x25"] = {"sustained_gbs": round(in_bytes / span / 1e9, 1),
+                         "latency_ms": _lat(lat_c), "range_latency_ms": _lat(lat_r),
+                         "seconds": round(span, 2)}
+    out["served_over_serial_x25"] = round(out["x25"]["sustained_gbs"] /
+                                          out["serial_x25"]["sustained_gbs"], 2)
+    del snaps, pool, ws, recs, outs
+    torch.cuda.empty_cache()
+    return out
 
 
 def main():
@@ -552,12 +820,15 @@ def main():
     ap.add_argument("--steps", type=int, default=27)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--edge", type=int, default=EDGE)
-    ap.add_argument("--cpu-sample", type=int, default=1 << 26,
-                    help="elements of the oracle's CPU-baseline sample (0 = skip)")
+    ap.add_argument("--cpu-sample", type=int, default=1 << 27,
+                    help="elements of the oracle's CPU-baseline sample (0 = skip; the default "
+                         "is all of pair 0 at 512^3)")
+    ap.add_argument("--small-reps", type=int, default=200,
+                    help="timed calls of the 64^3 latency measurement (0 = skip)")
     ap.add_argument("--batched-reps", type=int, default=10,
                     help="timed runs of each batched-vs-plain comparison (0 = skip)")
-    ap.add_argument("--serve-seconds", type=float, default=3.0,
-                    help="seconds of Poisson arrivals of the serving measurement (0 = skip)")
+    ap.add_argument("--serve-requests", type=int, default=SERVE_REQUESTS,
+                    help="Poisson requests of the serving measurement (0 = skip)")
     ap.add_argument("--variant-reps", type=int, default=-1,
                     help="timed runs of the auto-B, equal-width and zero-anchored sections "
                          "(-1 = max(3, steps / 3), 0 = skip)")
@@ -568,7 +839,12 @@ def main():
     ap.add_argument("--summarize-pmc", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "CMD"),
                     help="write profiles/pmc_{encode,decode,pipeline}_<workload>.json from two "
                          "rocprofv3 runs")
+    ap.add_argument("--summarize-trace", nargs=4, metavar=("TRACE_CSV", "OUT_MD", "TITLE", "CMD"),
+                    help="write a markdown summary of a rocprofv3 kernel trace")
     args = ap.parse_args()
+    if args.summarize_trace:
+        summarize_trace(*args.summarize_trace)
+        return
     if args.summarize_pmc:
         fd, wd, cmd = args.summarize_pmc
         summarize_pmc(fd, wd, f"flash3d_{args.edge}cubed_f64", cmd)
@@ -687,17 +963,18 @@ def main():
                              ws, vreps, stream)
     del snaps, ws, outs, c
     torch.cuda.empty_cache()
+    small = small_call_section(torch, nk, inputs, args.small_reps) if args.small_reps > 0 else None
     batched = None
     if args.batched_reps > 0:
         batched = batched_section(torch, nk, inputs, args.batched_reps)
         print(f"# batched: {json.dumps(batched)}", file=sys.stderr, flush=True)
     serving = None
-    if args.serve_seconds > 0:
-        serving = serving_section(torch, nk, inputs, args.serve_seconds)
+    if args.serve_requests > 0:
+        serving = serving_section(torch, nk, inputs, args.serve_requests)
         print(f"# serving: {json.dumps(serving)}", file=sys.stderr, flush=True)
     cpu = None
     if args.cpu_sample > 0:
-        cpu = cpu_baseline(cpu_prev, cpu_curr, min(args.cpu_sample, n))
+        cpu = cpu_baseline(cpu_prev, cpu_curr, min(args.cpu_sample, n), n)
 
     p50 = lat[len(lat) // 2]
     p99 = lat[min(len(lat) - 1, int(round(0.99 * (len(lat) - 1))))]
@@ -721,6 +998,7 @@ def main():
             "alpha": round(alpha, 5),
         },
         "latency_ms": {"p50": round(p50, 4), "p99": round(p99, 4)},
+        "small_call": small,
         "decompress": dec,
         "auto_b": auto_b,
         "equal_width": ew,
