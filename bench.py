@@ -337,7 +337,7 @@ def decompress_section(torch, nk, c, prev, reps: int, stream, workload: str) -> 
     dl, dms = tk["decode"]
     ln = n // 100
     rnd = random.Random(1711)
-    starts = [rnd.randrange(0, n - ln) for _ in range(reps)]
+    starts = [rnd.randrange(0, n - ln) for _ in range(max(reps, 2))]
     it = iter(starts * 2)
 
     def part():
@@ -348,7 +348,7 @@ def decompress_section(torch, nk, c, prev, reps: int, stream, workload: str) -> 
                                               flags.data_ptr(), dws.data_ptr(), dws.numel(), st),
                   "numarck_decompress_range")
 
-    t_part = time_ms(torch, part, reps - 1, stream)
+    t_part = time_ms(torch, part, max(reps - 1, 1), stream)
     assert int(flags.item()) == 0
     alpha = h.n_inc / n
     algo = (8 + 8 + h.B / 8 + 8 * alpha) * n

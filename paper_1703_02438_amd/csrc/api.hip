@@ -343,7 +343,9 @@ size_t numarck_lossless_stream_bytes(uint64_t n, uint32_t B) {
 
 size_t numarck_lossless_workspace_bytes(uint32_t B) {
   if (B < 1 || B > 16) return 0;
-  return align256((size_t)8 << B) + 256;
+  // counts and ranks, the order totals, the scan's per-tile totals (n < 2^32
+  // makes at most 2^22 sub-blocks: 1024 tiles of 4096)
+  return align256((size_t)8 << B) + 256 + 8 * 1024;
 }
 
 numarck_status numarck_lossless_encode(const uint32_t* packed, uint64_t n, uint32_t B,
@@ -368,6 +370,7 @@ numarck_status numarck_lossless_encode(const uint32_t* packed, uint64_t n, uint3
   p.rank_of = reinterpret_cast<uint32_t*>(base + ((size_t)4 << B));
   p.bits_k = reinterpret_cast<unsigned long long*>(base + align256((size_t)8 << B));
   p.order = reinterpret_cast<uint32_t*>(base + align256((size_t)8 << B) + 17 * 8);
+  p.parts = reinterpret_cast<uint64_t*>(base + align256((size_t)8 << B) + 256);
   p.code_of_rank = code_of_rank;
   p.sub_off = sub_off;
   p.stream = stream;

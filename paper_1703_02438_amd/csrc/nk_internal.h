@@ -317,6 +317,7 @@ struct LLParams {
   uint32_t* rank_of;       // workspace: 2^B ranks
   unsigned long long* bits_k;  // workspace: 17 totals
   uint32_t* order;         // workspace: the chosen order k
+  uint64_t* parts;         // workspace: per-tile totals of the offset scan
   uint16_t* code_of_rank;  // out: 2^B
   uint64_t* sub_off;       // out: n_sub + 1 bit offsets
   uint32_t* stream;        // out

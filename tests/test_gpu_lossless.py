@@ -34,12 +34,17 @@ def _table(codes, B):
     return words.astype(np.uint32)[: (n * B + 31) // 32]
 
 
-def ll_compare(nk, packed, n, B, label=""):
+def ll_compare(nk, packed, n, B, label="", shift_words=0):
+    """Encode on the GPU (the table `shift_words` words past a 16-byte
+    boundary when nonzero), compare with the oracle, decode back."""
     orc = oracle.get()
     o = orc.lossless_encode(packed, n, B)
     dev = torch.device("cuda:0")
-    t = torch.from_numpy(np.ascontiguousarray(packed if packed.size else np.zeros(1, np.uint32))
-                         .view(np.int32)).to(dev)
+    src = np.ascontiguousarray(packed if packed.size else np.zeros(1, np.uint32))
+    base = torch.zeros(src.size + 4, dtype=torch.int32, device=dev)
+    t = base[shift_words:shift_words + src.size]
+    t.copy_(torch.from_numpy(src.view(np.int32)))
+    assert (t.data_ptr() % 16 == 0) == (shift_words % 4 == 0)
     e = nk.lossless_encode(t, n, B)
     h = e.header()
     tag = f"[{label} n={n} B={B}]"
@@ -68,11 +73,26 @@ def test_lossless_random_tables(nk, B):
     ll_compare(nk, _table(codes, B), n, B, label="pareto")
 
 
-@pytest.mark.parametrize("n", [0, 1, 31, 1024, 1025, 2048 + 5, 40_000])
-def test_lossless_sizes(nk, n):
-    rng = np.random.default_rng(n)
-    codes = rng.integers(0, 1 << 6, n) if n else np.zeros(0, np.int64)
-    ll_compare(nk, _table(codes, 6), n, 6, label="uniform")
+@pytest.mark.parametrize("B", [4, 6, 8, 16])
+@pytest.mark.parametrize("n", [0, 1, 31, 127, 128, 129, 1024, 1025, 2048 + 5, 40_000])
+def test_lossless_sizes(nk, n, B):
+    """Short and ragged tables: partial groups and sub-blocks, for the
+    word-aligned widths (4, 8, 16) and one that straddles words (6)."""
+    rng = np.random.default_rng(n + 100 * B)
+    codes = rng.integers(0, 1 << min(B, 6), n) if n else np.zeros(0, np.int64)
+    ll_compare(nk, _table(codes, B), n, B, label="uniform")
+
+
+@pytest.mark.parametrize("B", [4, 8, 16])
+@pytest.mark.parametrize("shift", [1, 2, 3])
+def test_lossless_table_off_16_byte_boundary(nk, B, shift):
+    """A table that does not start on a 16-byte boundary takes the kernels
+    that read it word by word: the same stream."""
+    rng = np.random.default_rng(7 * B + shift)
+    n = 5 * 1024 + 77
+    w = rng.pareto(1.3, 1 << B) + 1e-3
+    codes = rng.choice(1 << B, n, p=w / w.sum())
+    ll_compare(nk, _table(codes, B), n, B, label="unaligned", shift_words=shift)
 
 
 def test_lossless_single_symbol(nk):
@@ -102,36 +122,43 @@ def test_lossless_flash_table_gpu_compressed(nk):
     assert e.header().bytes < 0.7 * packed.size * 4  # about 5 bits per 8-bit code here
 
 
-def test_lossless_corrupt_stream_flagged(nk):
+@pytest.mark.parametrize("B", [4, 5])
+def test_lossless_corrupt_stream_flagged(nk, B):
     """A stream of zeros (every codeword's leading one missing) and offsets
     past the stream are reported in the flag word, with every access in
-    bounds."""
+    bounds (B = 4: the word-aligned decoder; 5: the general one)."""
     rng = np.random.default_rng(5)
     n = 2 * 1024 + 7
     codes = rng.integers(0, 16, n)
-    t = torch.from_numpy(_table(codes, 4).view(np.int32)).cuda()
-    e = nk.lossless_encode(t, n, 4)
+    t = torch.from_numpy(_table(codes, B).view(np.int32)).cuda()
+    e = nk.lossless_encode(t, n, B)
     e.header()
     e.stream.zero_()
     _, fl = nk.lossless_decode(e)
     assert int(fl.item()) & nk.FLAG_BAD_STREAM
-    e2 = nk.lossless_encode(t, n, 4)
+    e2 = nk.lossless_encode(t, n, B)
     e2.header()
     e2.sub_off[1] = 1 << 40
     _, fl = nk.lossless_decode(e2)
     assert int(fl.item()) & nk.FLAG_BAD_STREAM
     # a group offset moved by one bit: group 2 of sub-block 0 starts late, so
     # group 1 ends before its successor (and group 2 runs short)
-    e3 = nk.lossless_encode(t, n, 4)
+    e3 = nk.lossless_encode(t, n, B)
     e3.header()
     e3.stream[1] += 1
     _, fl = nk.lossless_decode(e3)
     assert int(fl.item()) & nk.FLAG_BAD_STREAM
     # a group table with an offset inside the table itself
-    e4 = nk.lossless_encode(t, n, 4)
+    e4 = nk.lossless_encode(t, n, B)
     e4.header()
     e4.stream[0] = 5
     _, fl = nk.lossless_decode(e4)
+    assert int(fl.item()) & nk.FLAG_BAD_STREAM
+    # a sound group table over codewords of zeros (no leading ones)
+    e5 = nk.lossless_encode(t, n, B)
+    e5.header()
+    e5.stream[4:int(e5.sub_off[1].item()) // 32] = 0
+    _, fl = nk.lossless_decode(e5)
     assert int(fl.item()) & nk.FLAG_BAD_STREAM
 
 
