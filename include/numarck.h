@@ -401,7 +401,10 @@ numarck_status numarck_compress_batch(const numarck_job* jobs, uint32_t njobs, v
  * previous one, which stays resident on the device (zero copy: the snapshot
  * buffers are the caller's).  Requests of one variable run in submission
  * order; requests of different variables are batched together (one plan per
- * batch, numarck_plan_*) and batches on different slots overlap.  A request
+ * batch, numarck_plan_*) and batches on different slots overlap: a batch
+ * takes at most max_batch compressions and at most its share of the
+ * runnable ones (their count over the free slots, rounded up), so a full
+ * queue keeps every slot busy.  A request
  * is admitted when its record and workspace fit in the arena; otherwise it
  * waits for memory to be released.  Range requests decompress part of the
  * variable's latest record (the record of its last compression submitted

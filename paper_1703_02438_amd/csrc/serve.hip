@@ -240,16 +240,45 @@ bool numarck_server::launch() {
     }
   if (!slot || pending.empty()) return false;
 
+  // Spread the runnable compressions over the free slots: a batch takes at
+  // most ceil(runnable / free slots) of them (and max_batch), so several
+  // batches run at once.  One batch of every variable leaves nothing to
+  // overlap with its slowest job or with the host's work between batches,
+  // and measured slower than a few smaller ones on concurrent streams.
+  uint32_t free_slots = 0;
+  for (const Slot& s : slots) free_slots += s.busy ? 0u : 1u;
+  uint64_t runnable = 0;
+  {
+    // the head request of every variable not busy (a variable's requests run
+    // in order); stop once every variable has been seen
+    std::vector<char> seen(vars.size(), 0);
+    size_t nseen = 0;
+    for (auto it = pending.begin(); it != pending.end() && nseen < vars.size(); ++it) {
+      const numarck_request& r = it->second.r;
+      if (seen[r.var]) continue;
+      seen[r.var] = 1;
+      ++nseen;
+      if (!vars[r.var].busy && r.kind == NUMARCK_REQ_COMPRESS) ++runnable;
+    }
+  }
+  const uint64_t share = (runnable + free_slots - 1) / free_slots;
+  const uint64_t cap = share < cfg.max_batch ? (share > 0 ? share : 1) : cfg.max_batch;
+
   std::vector<Item> comp, range;
-  std::vector<uint32_t> taken;  // variables given a request in this batch
+  // variables given a request in this batch, or held back behind one
+  std::vector<char> taken(vars.size(), 0);
+  size_t ntaken = 0;
+  auto take = [&](uint32_t var) {
+    ntaken += taken[var] ? 0u : 1u;
+    taken[var] = 1;
+  };
   bool starved = false;
-  for (auto it = pending.begin(); it != pending.end();) {
-    if (comp.size() >= cfg.max_batch && range.size() >= kMaxRangePerBatch) break;
+  for (auto it = pending.begin(); it != pending.end() && ntaken < vars.size();) {
+    if (comp.size() >= cap && range.size() >= kMaxRangePerBatch) break;
     const numarck_request& r = it->second.r;
     Variable& v = vars[r.var];
-    bool head_taken = v.busy;
-    for (uint32_t t : taken) head_taken |= (t == r.var);
-    if (head_taken) {  // an earlier request of this variable is unfinished
+    if (v.busy || taken[r.var]) {  // an earlier request of this variable is unfinished
+      take(r.var);
       ++it;
       continue;
     }
@@ -260,8 +289,8 @@ bool numarck_server::launch() {
     item.submit_us = it->second.submit_us;
     item.full_tail = it->second.full_tail;
     if (r.kind == NUMARCK_REQ_COMPRESS) {
-      if (comp.size() >= cfg.max_batch) {
-        taken.push_back(r.var);  // keep its later requests behind it
+      if (comp.size() >= cap) {
+        take(r.var);  // keep its later requests behind it
         ++it;
         continue;
       }
@@ -275,7 +304,7 @@ bool numarck_server::launch() {
       comp.push_back(item);
     } else {
       if (range.size() >= kMaxRangePerBatch) {
-        taken.push_back(r.var);
+        take(r.var);
         ++it;
         continue;
       }
@@ -290,14 +319,14 @@ bool numarck_server::launch() {
       const uint64_t off = arena.alloc(range_ws_bytes(r.len));
       if (off == Arena::kFail) {
         starved = true;
-        taken.push_back(r.var);
+        take(r.var);
         ++it;
         continue;
       }
       item.ws_off = off;
       range.push_back(item);
     }
-    taken.push_back(r.var);
+    take(r.var);
     ++it;
   }
 
