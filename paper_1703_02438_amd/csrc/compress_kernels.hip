@@ -930,6 +930,96 @@ __device__ unsigned sel_kth_count(SelShared& S, unsigned long long mx, unsigned 
   return prefix;
 }
 
+// Order-preserving 11-bit key of a count c >= 1 on a log scale: c itself
+// below 64, else its exponent e = floor(log2 c) and the six bits after the
+// leading one.  Key b >= 64 holds the counts [(64 + b % 64) << s,
+// (65 + b % 64) << s) with s = b / 64 - 1.
+__device__ __forceinline__ unsigned sel_log_key(uint32_t c) {
+  if (c < 64u) return c;
+  const unsigned e = 31u - (unsigned)__clz(c);
+  return ((e - 5u) << 6) | ((c >> (e - 6u)) & 63u);
+}
+
+// k-th largest count among the window's bins (mx >= 1: their largest) and
+// its place among the bins of that count (*r, 1-based).  A first pass over
+// log-scale keys leaves only the bins of one key's narrow range of counts,
+// usually few, for the passes over the low bits: with a few bins holding
+// most points, a first digit cut from the top of the largest count puts
+// nearly every bin in its lowest bucket and narrows nothing.
+template <typename Visit>
+__device__ unsigned sel_kth_count_log(SelShared& S, unsigned long long k, Visit visit,
+                                      unsigned long long* r) {
+  for (int i = threadIdx.x; i < SEL_BUCKETS; i += SEL_TPB) S.hist[i] = 0u;
+  __syncthreads();
+  visit([&](long long, uint32_t cn) { lds_count(S.hist, cn != 0, cn ? sel_log_key(cn) : 0u); });
+  __syncthreads();
+  sel_scan(S, k, true);
+  unsigned long long target = k - S.before;
+  const unsigned b = S.bucket;
+  __syncthreads();
+  if (b < 64u) {  // exact
+    *r = target;
+    return b;
+  }
+  const unsigned low = b / 64u - 1u;                       // bits below the key's range
+  const uint32_t base = (64u + (b & 63u)) << low;          // its smallest count
+  unsigned prefix = 0;                                     // offset from base
+  const int top = ((int)low + SEL_DIGIT - 1) / SEL_DIGIT * SEL_DIGIT;
+  for (int shift = top - SEL_DIGIT; shift >= 0; shift -= SEL_DIGIT) {
+    for (int i = threadIdx.x; i < SEL_BUCKETS; i += SEL_TPB) S.hist[i] = 0u;
+    __syncthreads();
+    visit([&](long long, uint32_t cn) {
+      const uint32_t o = cn - base;  // wraps for counts below base
+      const bool on = cn >= base && ((unsigned long long)o >> low) == 0ull &&
+                      ((unsigned long long)(o ^ prefix) >> (shift + SEL_DIGIT)) == 0ull;
+      lds_count(S.hist, on, (o >> shift) & (SEL_BUCKETS - 1));
+    });
+    __syncthreads();
+    sel_scan(S, target, true);
+    target -= S.before;
+    prefix |= S.bucket << shift;
+    __syncthreads();
+  }
+  *r = target;
+  return base + prefix;
+}
+
+// tau and the tie cut over the window alone (more than k nonzero bins): the
+// ties are bins of the window, whose ids are wbase + their place, so the
+// r-th tie in id order is found with one scan of per-thread tie counts
+// (thread t takes places [16 t, 16 t + 16)) instead of a count of the bins
+// above tau and a radix select over the ties' ids.
+template <typename Visit>
+__device__ void sel_threshold_window(SelShared& S, unsigned long long k, long long wbase,
+                                     Visit visit, unsigned* tau_out, long long* cut_out) {
+  static_assert(WIN == 16 * SEL_TPB, "16 window bins per thread");
+  unsigned long long r = 0;
+  const unsigned tau = sel_kth_count_log(S, k, visit, &r);
+  const unsigned w0 = 16u * threadIdx.x;
+  unsigned mine = 0;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) mine += S.win[w0 + i] == tau ? 1u : 0u;
+  unsigned long long tot;
+  const unsigned long long ex = sel_excl_scan(mine, S, &tot);
+  if (ex < r && r <= ex + mine) {
+    unsigned left = (unsigned)(r - ex);
+    unsigned at = w0;
+    for (int i = 0; i < 16; ++i) {
+      const bool t = S.win[w0 + i] == tau;
+      if (t && left == 1) {
+        at = w0 + i;
+        break;
+      }
+      left -= t ? 1u : 0u;
+    }
+    S.bucket = at;
+  }
+  __syncthreads();
+  *tau_out = tau;
+  *cut_out = wbase + (long long)S.bucket;
+  __syncthreads();
+}
+
 // Bin ids as order-preserving unsigned keys (ids may be negative when the
 // bins are anchored at -E).
 constexpr unsigned long long ID_SIGN = 1ull << 63;
@@ -1055,7 +1145,7 @@ __global__ void __launch_bounds__(SEL_TPB) k_select(SRC src, Geo g) {
     if (nzw >= k) {
       unsigned tw;
       long long cw;
-      sel_threshold(S, mxw, k, visit_win, &tw, &cw);
+      sel_threshold_window(S, k, wbase, visit_win, &tw, &cw);
       if (tail_max < tw) {  // no tail bin reaches the window's k-th count
         tau = tw;
         cut = cw;

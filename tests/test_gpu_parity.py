@@ -92,6 +92,31 @@ def test_centred_ties(nk, dt):
     compare_decompress(nk, c, o, p, prev)
 
 
+@pytest.mark.parametrize("base,step", [(300_000, 7), (70, 1), (5_000, 3)])
+def test_select_ties_at_large_counts(nk, base, step):
+    """Top-k with ties across the cut at counts of every size: 40 bins whose
+    counts take five values base + step j, eight bins each, and k = 15
+    (B = 4), so tau is the second-largest value and 7 of its 8 bins are
+    taken.  The counts' log-scale key leaves 0, 6 or 12 low bits to resolve
+    (base 70, 5000, 300000), the last in two passes of 11 and 1 bits."""
+    E = 2.0 ** -10
+    counts = np.array([base + step * (m % 5) for m in range(40)])
+    rng = np.random.default_rng(base)
+    b = np.repeat(np.arange(40), counts)
+    d = (2 * b + 1).astype(np.float64) * E
+    d[0] = 0.0  # the anchor: a ratio-0 point of bin 0
+    order = rng.permutation(b.size)
+    d = d[order]
+    p = (2.0 ** rng.integers(-3, 4, b.size)) * np.where(rng.random(b.size) < 0.3, -1, 1)
+    prev, curr = p.astype(np.float32), (p * (1.0 + d)).astype(np.float32)
+    c, o, _ = compare_compress(nk, prev, curr, E, 4, label=f"ties at {base}")
+    h = c.header()
+    assert h.tau == base + 3 * step and h.k_used == 15
+    # the 8 bins of the largest count, then the first 7 of the next in id order
+    top = sorted([m for m in range(40) if m % 5 == 4] + [m for m in range(40) if m % 5 == 3][:7])
+    assert to_np(c.bin_ids)[:15].tolist() == top
+
+
 def test_all_invalid(nk):
     prev = np.zeros(9000)
     curr = np.linspace(-1, 1, 9000)
