@@ -155,12 +155,13 @@ __global__ void __launch_bounds__(UNIT_TPB) k_dcount(DParams P) {
 
 // LDS budget for the centre table (used when 2^B entries fit).
 constexpr int DEC_CENT_BYTES = 32768;
+constexpr uint64_t DEC_NT_BYTES = 256ull << 20;  // output size from which accesses are non-temporal
 
 // Unit u decodes its wave tiles in order.  Each lane handles V consecutive
 // elements per round (V = 16 / sizeof(T)); VEC selects 16-byte vector loads
 // of prev and stores of out (start a multiple of V, pointers 16-byte
 // aligned), otherwise the same elements are moved one by one.
-template <typename T, bool VEC>
+template <typename T, bool VEC, bool NT>
 __global__ void __launch_bounds__(UNIT_TPB) k_decode(DParams P) {
   constexpr int V = Traits<T>::V;
   constexpr int R = DEC_ROUNDS;
@@ -224,7 +225,7 @@ __global__ void __launch_bounds__(UNIT_TPB) k_decode(DParams P) {
     for (int r = 0; r < R; ++r) {
       const uint32_t e = ((uint32_t)r * 64 + lane) * V;
       if (VEC && e + V <= tn) {
-        load_vec(prev, (t0 + e) / V, pv[r]);
+        load_vec_t<NT>(prev, (t0 + e) / V, pv[r]);
       } else {
 #pragma unroll
         for (int v = 0; v < V; ++v) pv[r][v] = e + v < tn ? prev[t0 + e + v] : (T)0;
@@ -279,9 +280,11 @@ __global__ void __launch_bounds__(UNIT_TPB) k_decode(DParams P) {
       }
       const uint64_t o = t0 + e - P.start;
       if (VEC && e + V <= tn) {
-        uint4 x;
+        nk_u32x4 x;
         __builtin_memcpy(&x, ov, 16);
-        reinterpret_cast<uint4*>(out)[o / V] = x;
+        NK_GLOBAL nk_u32x4* dst = (NK_GLOBAL nk_u32x4*)out + o / V;
+        if constexpr (NT) __builtin_nontemporal_store(x, dst);
+        else *dst = x;
       } else {
 #pragma unroll
         for (int v = 0; v < V; ++v)
@@ -304,12 +307,12 @@ __global__ void __launch_bounds__(UNIT_TPB) k_decode(DParams P) {
     if (e_ != hipSuccess) return e_;                                             \
   } while (0)
 
-template <typename T, bool VEC>
+template <typename T, bool VEC, bool NT>
 static hipError_t launch_decode_chain(DParams P, size_t cent_lds, hipStream_t s) {
   const Geometry g = geometry();
   // as many units as can be resident at once (4 per workgroup)
   int occ = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_decode<T, VEC>, UNIT_TPB,
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_decode<T, VEC, NT>, UNIT_TPB,
                                                    cent_lds) != hipSuccess || occ < 1)
     occ = 1;
   P.n_units = range_units(P.n_tiles, g.cus * occ * 4);
@@ -323,7 +326,7 @@ static hipError_t launch_decode_chain(DParams P, size_t cent_lds, hipStream_t s)
   P.pre_elems = piece;
   const uint32_t waves = P.n_units + P.pre_units;
   NK_DLAUNCH(KK_DCOUNT, k_dcount, (waves + 3) / 4, UNIT_TPB, 0, P);
-  NK_DLAUNCH(KK_DECODE, (k_decode<T, VEC>), P.n_units / 4, UNIT_TPB, cent_lds, P);
+  NK_DLAUNCH(KK_DECODE, (k_decode<T, VEC, NT>), P.n_units / 4, UNIT_TPB, cent_lds, P);
   return hipSuccess;
 }
 
@@ -333,8 +336,13 @@ static hipError_t launch_decompress_t(const DParams& P, hipStream_t s) {
   const size_t cent_lds = cent <= (size_t)DEC_CENT_BYTES ? cent : 0;
   const bool vec = (P.start % Traits<T>::V) == 0 && ((uintptr_t)P.prev & 15u) == 0 &&
                    ((uintptr_t)P.out & 15u) == 0;
-  return vec ? launch_decode_chain<T, true>(P, cent_lds, s)
-             : launch_decode_chain<T, false>(P, cent_lds, s);
+  // a large decompression streams prev and out once: non-temporal accesses
+  // keep them from displacing each other in the caches (as in the
+  // compression passes)
+  const bool nt = vec && P.len * sizeof(T) >= DEC_NT_BYTES;
+  return nt ? launch_decode_chain<T, true, true>(P, cent_lds, s)
+            : vec ? launch_decode_chain<T, true, false>(P, cent_lds, s)
+                  : launch_decode_chain<T, false, false>(P, cent_lds, s);
 }
 
 hipError_t launch_decompress(const DParams& P, hipStream_t s) {
