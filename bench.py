@@ -170,6 +170,57 @@ def summarize_pmc(fetch_dir: str, write_dir: str, workload: str, cmd: str):
     print(path)
 
 
+SQ_COUNTERS = ("SQ_WAVES", "SQ_INSTS_VALU", "SQ_INSTS_SALU", "SQ_INSTS_LDS", "SQ_INSTS_VMEM_RD",
+               "SQ_INSTS_VMEM_WR")
+
+
+def summarize_sq(sq_dir: str, workload: str, n: int, cmd: str):
+    """Instruction counts per element of the compression and decompression
+    kernels from one rocprofv3 --pmc run of SQ counters: wave instructions
+    times 64 lanes over the n elements of the call (decoder: full-size
+    launches only); writes profiles/sq_counters_<workload>.md."""
+    import csv
+    import glob
+    import re
+
+    vals = {}
+    for f in glob.glob(os.path.join(sq_dir, "**", "*counter_collection.csv"), recursive=True):
+        with open(f) as fh:
+            for row in csv.DictReader(fh):
+                m = re.search(r"nk::k_(\w+)", row["Kernel_Name"])
+                if not m or row.get("Counter_Name") not in SQ_COUNTERS:
+                    continue
+                key = (m.group(1), int(row.get("Dispatch_Id", 0) or 0))
+                vals.setdefault(key, {})[row["Counter_Name"]] = float(row["Counter_Value"])
+    per = {}
+    for (k, _), c in vals.items():
+        per.setdefault(k, []).append(c)
+    lines = [f"# SQ instruction counters, {workload} (n = {n})", "",
+             "Command (from the repository root, on one MI355X):", "", "```", cmd, "```", "",
+             "Wave-level instruction counts times 64 lanes, per element of the call "
+             "(averaged over the dispatches; the decoder's full-size launches only).", "",
+             "| kernel | dispatches | waves | VALU / elem | SALU / elem | LDS / elem "
+             "| VMEM rd / elem | VMEM wr / elem |",
+             "|---|---:|---:|---:|---:|---:|---:|---:|"]
+    order = list(PIPELINE_KERNELS) + ["dcount", "decode"]
+    for k in order:
+        xs = per.get(k, [])
+        if k in ("decode", "dcount") and xs:
+            top = max(x.get("SQ_WAVES", 0.0) for x in xs)
+            xs = [x for x in xs if x.get("SQ_WAVES", 0.0) >= 0.5 * top]
+        if not xs:
+            continue
+        avg = {c: sum(x.get(c, 0.0) for x in xs) / len(xs) for c in SQ_COUNTERS}
+        pe = {c: avg[c] * 64 / n for c in SQ_COUNTERS[1:]}
+        lines.append(f"| `k_{k}` | {len(xs)} | {avg['SQ_WAVES']:.0f} | {pe['SQ_INSTS_VALU']:.2f} "
+                     f"| {pe['SQ_INSTS_SALU']:.2f} | {pe['SQ_INSTS_LDS']:.2f} "
+                     f"| {pe['SQ_INSTS_VMEM_RD']:.3f} | {pe['SQ_INSTS_VMEM_WR']:.3f} |")
+    path = os.path.join(ROOT, "profiles", f"sq_counters_{workload}.md")
+    with open(path, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print(path)
+
+
 def summarize_trace(trace_csv: str, out_md: str, title: str, cmd: str):
     """A rocprofv3 --kernel-trace CSV to a markdown table of the library's
     kernels, one row per kernel and grid size (a range decompression and a
@@ -847,9 +898,16 @@ def main():
                          "rocprofv3 runs")
     ap.add_argument("--summarize-trace", nargs=4, metavar=("TRACE_CSV", "OUT_MD", "TITLE", "CMD"),
                     help="write a markdown summary of a rocprofv3 kernel trace")
+    ap.add_argument("--summarize-sq", nargs=2, metavar=("SQ_DIR", "CMD"),
+                    help="write profiles/sq_counters_<workload>.md from a rocprofv3 run of "
+                         "the SQ instruction counters")
     args = ap.parse_args()
     if args.summarize_trace:
         summarize_trace(*args.summarize_trace)
+        return
+    if args.summarize_sq:
+        summarize_sq(args.summarize_sq[0], f"flash3d_{args.edge}cubed_f64", args.edge ** 3,
+                     args.summarize_sq[1])
         return
     if args.summarize_pmc:
         fd, wd, cmd = args.summarize_pmc

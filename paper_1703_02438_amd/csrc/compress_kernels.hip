@@ -904,32 +904,6 @@ __device__ __forceinline__ void sel_visit(const CParams& P, const SelShared& S, 
   }
 }
 
-// k-th largest count (k-th from the top, 1-based) among the visited candidates.
-template <typename Visit>
-__device__ unsigned sel_kth_count(SelShared& S, unsigned long long mx, unsigned long long k,
-                                  Visit visit) {
-  unsigned long long target = k;
-  unsigned prefix = 0;
-  int top = 0;
-  while (top < 32 && (mx >> top) != 0) top += SEL_DIGIT;
-  for (int shift = top - SEL_DIGIT; shift >= 0; shift -= SEL_DIGIT) {
-    for (int i = threadIdx.x; i < SEL_BUCKETS; i += SEL_TPB) S.hist[i] = 0u;
-    __syncthreads();
-    const unsigned hmask =
-        (shift + SEL_DIGIT >= 32) ? 0u : (unsigned)(0xFFFFFFFFull << (shift + SEL_DIGIT));
-    visit([&](long long, uint32_t cn) {
-      const bool on = cn != 0 && (cn & hmask) == (prefix & hmask);
-      lds_count(S.hist, on, (cn >> shift) & (SEL_BUCKETS - 1));
-    });
-    __syncthreads();
-    sel_scan(S, target, true);
-    target -= S.before;
-    prefix |= S.bucket << shift;
-    __syncthreads();
-  }
-  return prefix;
-}
-
 // Order-preserving 11-bit key of a count c >= 1 on a log scale: c itself
 // below 64, else its exponent e = floor(log2 c) and the six bits after the
 // leading one.  Key b >= 64 holds the counts [(64 + b % 64) << s,
@@ -1057,9 +1031,10 @@ __device__ long long sel_rth_tie(SelShared& S, unsigned tau, unsigned long long 
 
 // tau and the tie cut over the visited candidates (nz nonzero of them, nz > k).
 template <typename Visit>
-__device__ void sel_threshold(SelShared& S, unsigned long long mx, unsigned long long k,
+__device__ void sel_threshold(SelShared& S, unsigned long long k,
                               Visit visit, unsigned* tau_out, long long* cut_out) {
-  const unsigned tau = sel_kth_count(S, mx, k, visit);
+  unsigned long long r_unused;
+  const unsigned tau = sel_kth_count_log(S, k, visit, &r_unused);
   unsigned long long gt = 0, ties = 0, tmin = ~0ull, tmax = 0;
   visit([&](long long id, uint32_t cn) {
     if (cn == 0) return;
@@ -1153,10 +1128,7 @@ __global__ void __launch_bounds__(SEL_TPB) k_select(SRC src, Geo g) {
         tail_matters = false;
       }
     }
-    if (!done) {
-      const unsigned long long mx = mxw > tail_max ? mxw : tail_max;
-      sel_threshold(S, mx, k, visit_all, &tau, &cut);
-    }
+    if (!done) sel_threshold(S, k, visit_all, &tau, &cut);
   }
   // selected <=> cnt > tau, or cnt == tau and id <= cut (cnt nonzero)
   unsigned long long sel_tail = 0, sel_below = 0;
@@ -1307,18 +1279,18 @@ __global__ void __launch_bounds__(SEL_TPB) k_autob(SRC src, Geo g, uint32_t b_lo
   {
     const uint32_t B = b_lo + blockIdx.x;
     const unsigned long long k = (1ull << B) - 1ull;
-    unsigned long long held = n_valid;
+    unsigned long long held = n_valid, r_unused;
     if (nz > k) {
       // tau from the window alone when no tail bin reaches its k-th count
       bool win_only = false;
       unsigned tau = 0;
       if (nzw >= k) {
-        tau = sel_kth_count(S, mxw, k, visit_win);
+        tau = sel_kth_count_log(S, k, visit_win, &r_unused);
         win_only = tail_max < tau;
       }
       if (!win_only) {
         gather_tail();
-        tau = sel_kth_count(S, mxw > tail_max ? mxw : tail_max, k, visit_all);
+        tau = sel_kth_count_log(S, k, visit_all, &r_unused);
       }
       unsigned long long sum_gt = 0, n_gt = 0, u0 = ~0ull, u1 = 0;
       auto above = [&](long long, uint32_t cn) {
