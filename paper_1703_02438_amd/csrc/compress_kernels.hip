@@ -417,8 +417,7 @@ template <typename S>
 __global__ void __launch_bounds__(256) k_zafin(S src, Geo g) {
   const CParams& P = src.job(g.job_begin + blockIdx.x);
   Ctl* c = P.ctl;
-  unsigned long long v = 0;
-  for (int i = threadIdx.x; i < WIN; i += 256) v += gload(P.gwin + i);
+  unsigned long long v = strided_sum_u32(P.gwin, threadIdx.x, WIN, 256);
   v = wave_sum_u64(v);
   __shared__ unsigned long long part[4];
   if (lane_id() == 0) part[threadIdx.x / 64] = v;
@@ -1808,8 +1807,7 @@ __global__ void __launch_bounds__(UNIT_TPB) k_gather(S src, Geo g) {
   // job sums all of them: the job's total)
   const bool first = unit0 == 0;
   const uint32_t lim = first ? P.n_units : (unit0 < P.n_units ? unit0 : P.n_units);
-  unsigned long long sum = 0;
-  for (uint32_t i = tid; i < lim; i += UNIT_TPB) sum += gload(P.unit_cnt + i);
+  unsigned long long sum = strided_sum_u32(P.unit_cnt, tid, lim, UNIT_TPB);
   sum = wave_sum_u64(sum);
   if (lane == 0) {
     s_part[wave] = sum;

@@ -190,9 +190,8 @@ __global__ void __launch_bounds__(UNIT_TPB) k_decode(DParams P) {
   __shared__ unsigned long long s_part[NWAVE];
   __shared__ uint32_t s_cnt[NWAVE];
   const uint32_t unit0 = blockIdx.x * NWAVE;
-  unsigned long long sum = 0;
-  for (uint32_t i = tid; i < unit0; i += UNIT_TPB) sum += gload(P.unit_cnt + i);
-  for (uint32_t i = tid; i < P.pre_units; i += UNIT_TPB) sum += gload(P.pre_cnt + i);
+  unsigned long long sum = strided_sum_u32(P.unit_cnt, tid, unit0, UNIT_TPB) +
+                           strided_sum_u32(P.pre_cnt, tid, P.pre_units, UNIT_TPB);
   sum = wave_sum_u64(sum);
   if (lane == 0) {
     s_part[wave] = sum;

@@ -242,6 +242,26 @@ __device__ __forceinline__ unsigned long long wave_min_u64(unsigned long long v)
   }
   return v;
 }
+// Sum of a[i] over i = first, first + step, ... below lim (one thread's
+// share of a workgroup-strided sum), eight loads in flight at a time: a
+// plain loop waits for each load before the next, a chain of dependent
+// round trips to L2 that cost the kernels summing a few thousand counts
+// ahead of their work about 10 us.
+__device__ __forceinline__ unsigned long long strided_sum_u32(const uint32_t* a, uint32_t first,
+                                                              uint32_t lim, uint32_t step) {
+  unsigned long long s = 0;
+  uint32_t i = first;
+  for (; i + 7 * step < lim; i += 8 * step) {
+    uint32_t x[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) x[u] = gload(a + i + u * step);
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s += x[u];
+  }
+  for (; i < lim; i += step) s += gload(a + i);
+  return s;
+}
+
 __device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) {
