@@ -744,14 +744,18 @@ __global__ void k_hclear(S src, Geo g) {
   }
 }
 
+// One tail point per thread and step; the distinct-bin count and the
+// largest count are reduced per workgroup before one pair of atomics on the
+// control block.
 template <typename S>
-__global__ void k_hinsert(S src, Geo g) {
+__global__ void __launch_bounds__(256) k_hinsert(S src, Geo g) {
   const CParams& P = src.job(g.job_begin + blockIdx.y);
   const Ctl* c = P.ctl;
   const unsigned long long used = c->tail_used;
   const unsigned long long mask = c->H - 1;
   const uint64_t gt = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const uint64_t gs = (uint64_t)gridDim.x * blockDim.x;
+  if ((uint64_t)blockIdx.x * blockDim.x >= used) return;  // whole workgroups
   unsigned long long fresh = 0, top = 0;
   for (uint64_t i = gt; i < used; i += gs) {
     const long long id = P.tail[i];
@@ -768,12 +772,23 @@ __global__ void k_hinsert(S src, Geo g) {
     }
   }
   // distinct tail bins and the largest final count (the last increment of a
-  // bin returns its final count minus one)
+  // bin returns its final count minus one), per workgroup
+  __shared__ unsigned long long s_f[4], s_t[4];
   fresh = wave_sum_u64(fresh);
   top = wave_max_u64(top);
   if (lane_id() == 0) {
-    if (fresh) atomicAdd(&P.ctl->tail_bins, (unsigned)fresh);
-    if (top) atomicMax(&P.ctl->tail_max, (unsigned)top);
+    s_f[threadIdx.x / 64] = fresh;
+    s_t[threadIdx.x / 64] = top;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long f = 0, t = 0;
+    for (int w = 0; w < 4; ++w) {
+      f += s_f[w];
+      t = s_t[w] > t ? s_t[w] : t;
+    }
+    if (f) atomicAdd(&P.ctl->tail_bins, (unsigned)f);
+    if (t) atomicMax(&P.ctl->tail_max, (unsigned)t);
   }
 }
 
