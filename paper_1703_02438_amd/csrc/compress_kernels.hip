@@ -1160,7 +1160,7 @@ __global__ void __launch_bounds__(SEL_TPB) k_select(SRC src, Geo g) {
       }
     }
   }
-  {
+  if (tail_matters) {  // uniform; otherwise both counts are 0 everywhere
     unsigned long long u0 = ~0ull, u1 = 0;
     sel_reduce4(sel_tail, sel_below, u0, u1, S);
   }
