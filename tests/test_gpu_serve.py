@@ -224,3 +224,26 @@ def test_budget_counts_two_snapshots_per_variable(nk):
         srv.add_variable(snaps[1], 1e-3, 8)  # one snapshot's worth would fit, two do not
     assert e.value.status == nk.ECAPACITY
     srv.close()
+
+
+def test_batches_spread_over_slots(nk):
+    """A batch takes at most its share of the runnable compressions (their
+    count over the free slots, rounded up): with 7 variables on 4 slots no
+    batch can hold more than 4 (3 slots busy with one each leave 4 runnable
+    for 1 free slot), whatever the timing; the records equal plain calls."""
+    snaps = [_series(n, dt, 900 + i, 2, E) for i, (n, dt, E, B) in enumerate(VARS)]
+    srv = nk.Server(budget_bytes=64 << 30, arena_bytes=1 << 30, slots=4, max_batch=32)
+    for i, (n, dt, E, B) in enumerate(VARS):
+        assert srv.add_variable(snaps[i][0], E, B) == i
+    torch.cuda.synchronize()
+    for step in (1, 2):
+        for v in range(len(VARS)):
+            srv.compress(v, snaps[v][step])
+    srv.drain()
+    done = srv.poll()
+    assert len(done) == 2 * len(VARS) and all(c["status"] == nk.OK for c in done)
+    st = srv.stats()
+    assert 1 <= st["max_batch_seen"] <= 4, st
+    for v, (n, dt, E, B) in enumerate(VARS):
+        assert_same_compression(srv.fetch(v), nk.compress(snaps[v][1], snaps[v][2], E, B),
+                                f"var {v}")
