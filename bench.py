@@ -518,9 +518,10 @@ def time_ms(torch, fn, reps: int, stream) -> float:
 
 
 def batched_vs_plain(torch, nk, jobs, reps: int) -> dict:
-    """One workload of many jobs: plain per-job launches, one batched plan, and
-    the plan replayed as a HIP graph, and the batch with zero-anchored bins
-    (input GB/s of each)."""
+    """One workload of many jobs: plain per-job launches (directly, and
+    captured in one HIP graph and replayed), one batched plan, the plan
+    replayed as a HIP graph, and the batch with zero-anchored bins (input
+    GB/s of each)."""
     stream = torch.cuda.current_stream()
     in_bytes = sum(j.curr.numel() * j.curr.element_size() for j in jobs)
     wss = [torch.empty(nk.numarck_workspace_bytes(j.curr.numel(), nk.dtype_code(j.curr.dtype), j.B),
@@ -532,7 +533,24 @@ def batched_vs_plain(torch, nk, jobs, reps: int) -> dict:
             nk.compress(j.prev, j.curr, j.E, j.B, j.block_bytes, ws=w, outputs=o, stream=stream)
 
     t_plain = time_ms(torch, plain, reps, stream)
-    del wss
+    ref = [(h.n_inc, h.compressed_bytes) for h in
+           (nk.header_from_device(o["hdr"]) for o in outs)]
+    # the same plain calls captured in one HIP graph and replayed (every
+    # launch recorded, no launch latency between them); the headers of the
+    # last replay must equal the direct calls'
+    t_plain_graph = None
+    g = torch.cuda.CUDAGraph()
+    gst = torch.cuda.Stream()
+    gst.wait_stream(stream)
+    with torch.cuda.graph(g, stream=gst):
+        for j, w, o in zip(jobs, wss, outs):
+            nk.compress(j.prev, j.curr, j.E, j.B, j.block_bytes, ws=w, outputs=o, stream=gst)
+    stream.wait_stream(gst)
+    t_plain_graph = time_ms(torch, g.replay, reps, stream)
+    torch.cuda.synchronize()
+    got = [(h.n_inc, h.compressed_bytes) for h in (nk.header_from_device(o["hdr"]) for o in outs)]
+    assert got == ref, "graph-replayed plain calls differ from the direct calls"
+    del g, wss
     plan = nk.Plan(jobs, outputs=outs, stream=stream)
     t_plan = time_ms(torch, lambda: plan.run(stream), reps, stream)
     gs = torch.cuda.Stream()
@@ -554,6 +572,7 @@ def batched_vs_plain(torch, nk, jobs, reps: int) -> dict:
         "jobs": len(jobs),
         "input_bytes": in_bytes,
         "plain_gbs": round(in_bytes / t_plain / 1e6, 1),
+        "plain_graph_gbs": round(in_bytes / t_plain_graph / 1e6, 1),
         "batched_gbs": round(in_bytes / t_plan / 1e6, 1),
         "graph_gbs": round(in_bytes / t_graph / 1e6, 1),
         "plain_ms": round(t_plain, 3),
