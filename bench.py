@@ -933,7 +933,7 @@ def main():
         summarize_pmc(fd, wd, f"flash3d_{args.edge}cubed_f64", cmd)
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build measures one GPU; --gpus must be 1"}))
+        print(json.dumps({"error": "this benchmark measures one GPU; --gpus must be 1"}))
         sys.exit(2)
 
     import torch

@@ -1853,7 +1853,7 @@ __global__ void __launch_bounds__(UNIT_TPB) k_gather(S src, Geo g) {
     gstore(P.block_inc_off + b, gload(P.block_inc_off + b) + (int64_t)off);
 }
 
-// Header of the call (Fig. 2's attributes plus the counts of this build).
+// Header of the call (Fig. 2's attributes plus this library's counts).
 __device__ void write_header(const CParams& P) {
   const Ctl* c = P.ctl;
   numarck_header* h = P.hdr;

@@ -33,19 +33,19 @@ def _ranges(n, rng, k=6, epb=None):
     return out
 
 
-def test_cfg1_fp64(nk):
+def test_mixture_64cubed_fp64(nk):
     """64^3 float64, lognormal prev with 0.1 % zeros, 3-component ratio
     mixture, E = 1e-3, B = 8."""
     prev, curr = inputs.mixture_pair(64 ** 3, seed=1704)
     prev, curr = prev.numpy(), curr.numpy()
-    c, o, p = compare_compress(nk, prev, curr, 1e-3, 8, label="cfg1")
+    c, o, p = compare_compress(nk, prev, curr, 1e-3, 8, label="mixture 64^3")
     compare_decompress(nk, c, o, p, prev, _ranges(prev.size, np.random.default_rng(1)))
 
 
-def test_cfg1_fp32(nk):
+def test_mixture_64cubed_fp32(nk):
     prev, curr = inputs.mixture_pair(64 ** 3, seed=1704, dtype=torch.float32)
     prev, curr = prev.numpy(), curr.numpy()
-    c, o, p = compare_compress(nk, prev, curr, 1e-3, 8, label="cfg1-f32")
+    c, o, p = compare_compress(nk, prev, curr, 1e-3, 8, label="mixture 64^3 f32")
     compare_decompress(nk, c, o, p, prev, _ranges(prev.size, np.random.default_rng(2)))
 
 
