@@ -589,7 +589,8 @@ numarck_status numarck_lossless_encode(const uint32_t* packed, uint64_t n, uint3
                                        void* stream_);
 /* Decode back to the B-bit index table `packed` ((n B + 31) / 32 words,
  * device).  hdr is a HOST copy of the encoder's header; the other pointers
- * are device buffers (stream and packed 16-byte aligned); flags (device uint32) is set to 0, then ORed with
+ * are device buffers (stream and packed 16-byte aligned); flags (device
+ * uint32) is set to 0, then ORed with
  * NUMARCK_FLAG_BAD_STREAM if a sub-block's offsets or codewords are corrupt
  * (that sub-block's codes are then incomplete).  Reads stay within the
  * stream's hdr->stream_words words and writes within the table.  Errors:
