@@ -88,3 +88,29 @@ def test_auto_B_equals_fixed_B(nk):
         ni = ref.header().n_inc
         assert c.header().n_inc == ni
         assert torch.equal(c.incomp[:ni].view(torch.int64), ref.incomp[:ni].view(torch.int64))
+
+
+def test_auto_B_after_another_choice(nk):
+    """Automatic calls alternating between inputs of one size whose best B
+    differ (2 and 4), into one set of outputs sized for B = 16 and one
+    workspace: every compression equals the oracle's with its B."""
+    n = 262_144
+    rng = np.random.default_rng(5)
+    d = rng.choice([0.0, 2e-3, 4e-3], n)
+    p_narrow = rng.lognormal(0, 1, n)
+    narrow = (p_narrow, p_narrow * (1 + d))
+    mix = mixture_case(n, 1704)
+    orc = oracle.get()
+    # one set of outputs and one workspace for every call
+    outs = nk.alloc_outputs(n, torch.float64, 16, 0, True, True, torch.device("cuda:0"))
+    ws = torch.empty(nk.numarck_workspace_bytes(n, nk.F64, 16), dtype=torch.uint8, device="cuda")
+    for label, (prev, curr), B_expect in (("narrow", narrow, 2), ("mixture", mix, 4),
+                                          ("mixture again", mix, 4), ("narrow again", narrow, 2)):
+        B_ref, bits_ref = orc.choose_B(prev, curr, 1e-3, 1, 16)
+        assert B_ref == B_expect
+        p = torch.from_numpy(np.ascontiguousarray(prev)).cuda()
+        q = torch.from_numpy(np.ascontiguousarray(curr)).cuda()
+        c, B, bits = nk.compress_auto(p, q, 1e-3, 1, 16, ws=ws, outputs=outs)
+        assert B == B_ref and bits == bits_ref, label
+        o = orc.compress(prev, curr, 1e-3, B)
+        assert_matches_oracle(nk, c, o, prev, curr, 1e-3, B, check_hist=False, label=label)
