@@ -50,6 +50,7 @@ Layout compress_layout(uint64_t n, uint64_t elem_bytes, uint64_t tail_cap) {
   L.unit_cnt = take((size_t)MAX_UNITS * 4);
   L.sink = take((size_t)SINK_SLOTS * 256);
   L.scratch = take((size_t)n * elem_bytes);
+  L.wcode = take((size_t)n * 2);
   L.tail = take((size_t)tail_cap * 8);
   L.hslot = take((size_t)L.hcap * 4);
   L.hcnt = take((size_t)L.hcap * 4);
@@ -229,6 +230,9 @@ static CParams make_params(const void* prev, const void* curr, uint64_t n, numar
   P.mulB = B > 1 ? (uint32_t)((((uint64_t)1 << 32) + B - 1) / B) : 0u;  // unused for B = 1
   P.unit_cnt = reinterpret_cast<uint32_t*>(base + L.unit_cnt);
   P.scratch = base + L.scratch;
+  P.wcode = reinterpret_cast<uint16_t*>(base + L.wcode);
+  P.pre = 0;  // the launcher decides
+  P.tile_elems = (uint32_t)tile;
   P.sink = base + L.sink;
   P.tail = reinterpret_cast<int64_t*>(base + L.tail);
   P.tail_cap = L.tail_cap;

@@ -536,9 +536,10 @@ __global__ void __launch_bounds__(HIST_TPB) k_hist(S src, Geo g) {
   // would stall every wave of the workgroup.
   bool have = false, empty = true;
   double lo = 0.0, wbase_d = 0.0, wlen_d = 0.0, cap = 0.0, twoE = 1.0, inv2E = 1.0;
-  double cap_lo = 0.0, cap_hi = 0.0, inv_err = 0.0;
+  double cap_lo = 0.0, cap_hi = 0.0, inv_err = 0.0, E = 0.0;
   unsigned wl = 0;
   uint32_t* gwin = nullptr;
+  uint16_t* wc = nullptr;  // window codes to write (precoded encoding), or null
   const T* prev = nullptr;
   const T* curr = nullptr;
   uint64_t n = 0, nvec = 0;
@@ -627,6 +628,8 @@ __global__ void __launch_bounds__(HIST_TPB) k_hist(S src, Geo g) {
       twoE = P.twoE;
       inv2E = P.inv2E;
       inv_err = inv2E * 0x1p-36;
+      E = P.E;
+      wc = LDSH && P.pre ? P.wcode : nullptr;
       ts = TailSink{&P.ctl->tail_count, P.tail, P.tail_cap};
     }
     if (empty) continue;  // uniform: the whole chunk belongs to this job
@@ -657,6 +660,8 @@ __global__ void __launch_bounds__(HIST_TPB) k_hist(S src, Geo g) {
         for (int u = 0; u < HIST_UNROLL; ++u) {
           const uint64_t vi = vb + (uint64_t)u * HIST_TPB;
           const bool inr = vi < v1;
+          // the vector's window codes, element v in bits [16 v, 16 v + 16)
+          typename std::conditional<V == 2, uint32_t, unsigned long long>::type cw = 0;
 #pragma unroll
           for (int v = 0; v < V; ++v) {
             bool vf;
@@ -670,7 +675,19 @@ __global__ void __launch_bounds__(HIST_TPB) k_hist(S src, Geo g) {
             mt[u][v] = m;
             tl[u][v] = valid && !inwin;
             anyt |= tl[u][v];
+            if (wc) {  // uniform
+              uint32_t code = valid ? WC_TAIL : WC_INVALID;
+              if (inwin) {
+                // the check the encoder makes with this bin's centre (Sec. III-C)
+                const double p = (double)pv[u][v], q = (double)qv[u][v];
+                const T r_t = (T)(p * (1.0 + centre_of_d<T>(m, lo, E)));
+                const bool ok = fabs((double)r_t - q) <= E * fabs(p);
+                code = (uint32_t)(int)w | (ok ? WC_OK : 0u);
+              }
+              cw |= (decltype(cw))code << (16 * v);
+            }
           }
+          if (wc && inr) gstore(reinterpret_cast<decltype(cw)*>(wc) + vi, cw);
         }
         if (__ballot(anyt)) {
 #pragma unroll
@@ -702,6 +719,17 @@ __global__ void __launch_bounds__(HIST_TPB) k_hist(S src, Geo g) {
       if (jj < n) valid = ratio_of((double)prev[jj], (double)curr[jj], cap, d);
       const double m = valid ? bin_floor(d - lo, twoE, inv2E) : 0.0;
       hist_count(win, valid, m, wbase_d, wlen_d, ts);
+      if (wc && jj < n) {
+        const double w = m - wbase_d;
+        const bool inwin = valid && w >= 0.0 && w < wlen_d;
+        uint16_t code = valid ? WC_TAIL : WC_INVALID;
+        if (inwin) {
+          const double p = (double)prev[jj], q = (double)curr[jj];
+          const T r_t = (T)(p * (1.0 + centre_of_d<T>(m, lo, E)));
+          code = (uint16_t)((int)w | (fabs((double)r_t - q) <= E * fabs(p) ? WC_OK : 0));
+        }
+        gstore(wc + jj, code);
+      }
     }
   }
   if (have) flush();
@@ -1803,10 +1831,289 @@ __global__ void __launch_bounds__(UNIT_TPB, (enc_min_waves<T, PACK, EW>)) k_enco
 // =====================================================================
 __device__ void write_header(const CParams& P);
 
+// =====================================================================
+// k_encode_pre: pass 3 from the window codes (precoded encoding)
+// =====================================================================
+// The index of point j, valid and outside the histogram window, among the
+// selected tail bins: its bin from its values (ratio_bin), a binary search
+// in the sorted selected tail ids, and the check of Sec. III-C with that
+// bin's centre; the escape code when the bin is not selected or the check
+// fails.  Out of line: it runs only for such points, and only when selected
+// tail bins exist; the encoder calls it from one loop over such points, not
+// at every code slot.
+template <typename T>
+__device__ __forceinline__ uint32_t pre_tail_index(
+    const T* prev, const T* curr, uint64_t j, const int64_t* sorted_tail, unsigned nsel_tail,
+    unsigned nsel_win, long long wbase, double lo, double E, double cap, double twoE,
+    double inv2E, uint32_t esc) {
+  const double p = (double)gload(prev + j), q = (double)gload(curr + j);
+  bool vf;
+  const double m = ratio_bin(p, q, cap, cap_below(cap), cap_above(cap), lo, twoE, inv2E,
+                             inv2E * 0x1p-36, vf);
+  const long long mi = (long long)m;
+  unsigned a = 0, b = nsel_tail;
+  while (a < b) {
+    const unsigned mid = (a + b) >> 1;
+    if (gload(sorted_tail + mid) < mi) a = mid + 1; else b = mid;
+  }
+  if (!vf || a >= nsel_tail || gload(sorted_tail + a) != mi) return esc;
+  const T r_t = (T)(p * (1.0 + centre_of_d<T>(m, lo, E)));
+  return fabs((double)r_t - q) <= E * fabs(p) ? a + (mi > wbase ? nsel_win : 0u) : esc;
+}
+
+// The histogram pass has written each point's window code (WC_*): its
+// place in the window and whether its own bin's centre passes the check of
+// Sec. III-C.  A point's index is the window LUT entry of that place when
+// the entry is a selected bin and the check passed, else the escape code.
+// A point outside the window is looked up among the selected tail bins from
+// its values, and only when such bins exist (otherwise it escapes).  So the
+// pass reads 2 bytes per point instead of both snapshots.  It stages the
+// element indices of the incompressible points; k_gather fetches their
+// values and derives the block offsets from them.  Units and compaction
+// follow k_encode; lane l of round r holds the 8 codes of elements
+// t0 + (r * 64 + l) * 8 + [0, 8).
+template <typename T, typename LT, int PACK, typename S>
+__global__ void __launch_bounds__(UNIT_TPB) k_encode_pre(S src, Geo g) {
+  constexpr int V = 8;
+  constexpr int R = PRE_ROUNDS;
+  constexpr int WT = (int)PRE_WAVE_TILE;
+  constexpr int NWAVE = UNIT_TPB / 64;
+  // codes kept in LDS for bit-packing (widths other than 8 and 16)
+  using IT = LT;
+  constexpr int PK = PACK ? PACK : 8 * (int)sizeof(IT);  // bits per code in cw
+  constexpr int CWN = V * PK / 32;                         // 32-bit words per lane-round
+  __shared__ LT s_lut[WIN];
+  __shared__ __align__(16) IT s_idx[NWAVE][PACK == 0 ? WT : 1];
+  constexpr int ESC_STAGE = 256;
+  __shared__ uint32_t s_esc[NWAVE][ESC_STAGE];
+
+  const uint32_t ublk = g.u_begin + blockIdx.x * NWAVE;
+  const uint32_t jb = g.unit0 ? find_job(g.unit0, g.job_begin, g.job_end, ublk) : g.job_begin;
+  const CParams P = src.job(jb);
+  const Ctl* c = P.ctl;
+  const int tid = threadIdx.x;
+  const int wave = __builtin_amdgcn_readfirstlane(tid / 64);
+  const int lane = lane_id();
+  const bool empty = c->empty != 0;
+  const double lo = empty ? 0.0 : c->lo;
+  const long long wbase = empty ? 0 : c->wbase;
+  const unsigned nsel_tail =
+      (unsigned)__builtin_amdgcn_readfirstlane((int)(empty ? 0u : c->nsel_tail));
+  const unsigned nsel_win = empty ? 0u : c->nsel_window;
+  const uint32_t esc = P.k;
+  const uint32_t B = P.B;
+  for (int i = tid; i < WIN; i += UNIT_TPB) s_lut[i] = (LT)gload(P.lut + i);
+  __syncthreads();
+
+  const T* __restrict__ prev = static_cast<const T*>(P.prev);
+  const T* __restrict__ curr = static_cast<const T*>(P.curr);
+  const nk_u32x4* __restrict__ wv = reinterpret_cast<const nk_u32x4*>(P.wcode);
+  uint32_t* __restrict__ stage = static_cast<uint32_t*>(P.scratch);
+  IT* idx = s_idx[wave];
+  const uint64_t nvec = P.n / V;
+  const uint32_t tile_words = (uint32_t)(WT * B / 32);
+  const uint32_t unit = ublk + wave - (g.unit0 ? g.unit0[jb] : 0u);
+  const uint64_t tb = (uint64_t)unit * P.tiles_per_unit;
+  uint64_t te = tb + P.tiles_per_unit;
+  te = te < P.n_tiles ? te : P.n_tiles;
+  const uint64_t e_base = tb * WT;
+  unsigned run = 0;  // incompressible points so far in this range
+
+  auto process = [&](auto full, uint64_t tile, const nk_u32x4 (&cv)[R]) {
+    constexpr bool FULL = decltype(full)::value;
+    const uint64_t t0 = tile * WT;
+    const uint64_t left = P.n - t0;
+    const uint32_t lim = FULL ? (uint32_t)WT
+                              : (left < (uint64_t)WT ? (uint32_t)left : (uint32_t)WT);
+    // code slot sl = r * V + v of a lane: element e0(r) + v.  okm: the slots
+    // indexed (selected bin, check passed); tm: valid slots outside the window
+    uint32_t cw[R][CWN];
+    uint32_t okm = 0, tm = 0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const uint32_t e0 = ((uint32_t)r * 64 + lane) * V;  // tile-local element
+#pragma unroll
+      for (int h = 0; h < CWN; ++h) cw[r][h] = 0;
+#pragma unroll
+      for (int v = 0; v < V; ++v) {
+        const bool inr = FULL || e0 + v < lim;
+        const uint32_t c16 = (cv[r][v / 2] >> (16 * (v & 1))) & 0xFFFFu;
+        const uint32_t l = s_lut[c16 & (uint32_t)(WIN - 1)];
+        const bool ok = inr & (c16 < WC_INVALID) & ((c16 & WC_OK) != 0) & (l != esc);
+        okm |= ok ? 1u << (r * V + v) : 0u;
+        tm |= inr & (c16 == WC_TAIL) ? 1u << (r * V + v) : 0u;
+        cw[r][(v * PK) / 32] |= (ok ? l : inr ? esc : 0u) << ((v * PK) % 32);
+      }
+    }
+    if (nsel_tail != 0 && __ballot(tm != 0)) {  // uniform test, then per lane
+      while (tm) {
+        const int sl = __builtin_ctz(tm);
+        tm &= tm - 1u;
+        const int v = sl % V;
+        const uint32_t e = ((uint32_t)(sl / V) * 64 + lane) * V + v;
+        const uint32_t code = pre_tail_index<T>(prev, curr, t0 + e, P.sorted_tail, nsel_tail,
+                                                nsel_win, wbase, lo, P.E, P.cap, P.twoE,
+                                                P.inv2E, esc);
+        if (code != esc) {  // the slot held the escape code: put the index there
+          okm |= 1u << sl;
+          const int hw = (sl / V) * CWN + (v * PK) / 32;
+          const int sh = (v * PK) % 32;
+#pragma unroll
+          for (int r = 0; r < R; ++r)
+#pragma unroll
+            for (int h = 0; h < CWN; ++h)
+              if (r * CWN + h == hw)
+                cw[r][h] = (cw[r][h] & ~(esc << sh)) | (code << sh);
+        }
+      }
+    }
+    unsigned long long emask[R][V];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const uint32_t e0 = ((uint32_t)r * 64 + lane) * V;
+#pragma unroll
+      for (int v = 0; v < V; ++v)
+        emask[r][v] = __ballot((FULL || e0 + v < lim) & !((okm >> (r * V + v)) & 1u));
+    }
+    // the indices: 8- and 16-bit codes straight to the packed stream (a
+    // lane's 8 codes are 8 or 16 contiguous bytes), others to LDS
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const uint64_t j0 = t0 + ((uint64_t)r * 64 + lane) * V;  // first element
+      if constexpr (PACK != 0) {
+        if (FULL) {
+          if constexpr (CWN == 4) {
+            nk_u32x4 x;
+            x[0] = cw[r][0]; x[1] = cw[r][1]; x[2] = cw[r][2]; x[3] = cw[r][3];
+            gstore(reinterpret_cast<nk_u32x4*>(P.packed) + j0 / 8, x);
+          } else {
+            const unsigned long long x = ((unsigned long long)cw[r][1] << 32) | cw[r][0];
+            gstore(reinterpret_cast<unsigned long long*>(P.packed) + j0 / 8, x);
+          }
+        } else {
+          using PT = typename std::conditional<PACK == 8, uint8_t, uint16_t>::type;
+          const uint64_t pe = (uint64_t)P.packed_words * (32 / PACK);  // codes in the stream
+#pragma unroll
+          for (int v = 0; v < V; ++v)
+            if (j0 + v < pe)
+              gstore(reinterpret_cast<PT*>(P.packed) + j0 + v,
+                     (PT)(cw[r][(v * PACK) / 32] >> ((v * PACK) % 32)));
+        }
+      } else {
+        IT* dst = idx + ((uint32_t)r * 64 + lane) * V;
+        if constexpr (CWN == 4) {
+          nk_u32x4 x;
+          x[0] = cw[r][0]; x[1] = cw[r][1]; x[2] = cw[r][2]; x[3] = cw[r][3];
+          *reinterpret_cast<nk_u32x4*>(dst) = x;
+        } else {
+          *reinterpret_cast<unsigned long long*>(dst) =
+              ((unsigned long long)cw[r][1] << 32) | cw[r][0];
+        }
+      }
+    }
+
+    // incompressible points in element order (round, lane, code slot);
+    // ranks are range-relative
+    const unsigned run0 = run;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      unsigned below = 0, all = 0;
+#pragma unroll
+      for (int v = 0; v < V; ++v) {
+        const unsigned long long mk = emask[r][v];
+        below += __builtin_amdgcn_mbcnt_hi((unsigned)(mk >> 32),
+                                           __builtin_amdgcn_mbcnt_lo((unsigned)mk, 0u));
+        all += (unsigned)__popcll(mk);
+      }
+      unsigned rank = run + below;
+      const uint32_t e0 = ((uint32_t)r * 64 + lane) * V;
+#pragma unroll
+      for (int v = 0; v < V; ++v) {
+        const bool escp = (emask[r][v] >> lane) & 1ull;
+        if (escp) {
+          const unsigned tl = rank - run0;  // rank within the tile
+          const uint32_t j = (uint32_t)(t0 + e0 + v);
+          if (FULL && tl < (unsigned)ESC_STAGE) s_esc[wave][tl] = j;
+          else gstore(stage + e_base + rank, j);
+        }
+        rank += escp ? 1u : 0u;
+      }
+      run += all;
+    }
+
+    wave_lds_sync();
+    if (FULL) {  // the staged escape indices, in order
+      const unsigned cnt = run - run0 < (unsigned)ESC_STAGE ? run - run0 : (unsigned)ESC_STAGE;
+      for (unsigned i = (unsigned)lane; i < cnt; i += 64)
+        gstore(stage + e_base + run0 + i, s_esc[wave][i]);
+    }
+    if constexpr (PACK == 0) {
+      // bit-pack the wave tile: word w holds bits [32w, 32w + 32) of its stream
+      const uint64_t word0 = t0 * B / 32;
+      for (uint32_t w = lane; w < tile_words; w += 64) {
+        if (word0 + w >= P.packed_words) break;
+        const uint32_t bit0 = w * 32;
+        // floor(bit0 / B) and floor((bit0 + 31) / B); mulB does not exist for B = 1
+        const uint32_t e_first = B == 1 ? bit0 : __umulhi(bit0, P.mulB);
+        const uint32_t e_last = B == 1 ? bit0 + 31 : __umulhi(bit0 + 31, P.mulB);
+        uint32_t word = 0;
+        for (uint32_t e = e_first; e <= e_last && e < (uint32_t)WT; ++e) {
+          const uint32_t v = idx[e];
+          const int sh = (int)(e * B) - (int)bit0;
+          word |= sh >= 0 ? (v << sh) : (v >> (-sh));
+        }
+        gstore(P.packed + word0 + w, word);
+      }
+    }
+    wave_lds_sync();
+  };
+
+  auto load_full = [&](uint64_t tile, nk_u32x4 (&cv)[R]) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) cv[r] = gload(wv + tile * (WT / V) + (uint64_t)r * 64 + lane);
+  };
+  auto load_part = [&](uint64_t tile, nk_u32x4 (&cv)[R]) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const uint64_t vi = tile * (WT / V) + (uint64_t)r * 64 + lane;
+      if (vi < nvec) {
+        cv[r] = gload(wv + vi);
+      } else {
+#pragma unroll
+        for (int h = 0; h < 4; ++h) {
+          const uint64_t j = vi * V + 2 * h;
+          const uint32_t a = j < P.n ? gload(P.wcode + j) : WC_INVALID;
+          const uint32_t b = j + 1 < P.n ? gload(P.wcode + j + 1) : WC_INVALID;
+          cv[r][h] = a | (b << 16);
+        }
+      }
+    }
+  };
+  const uint64_t full_tiles = nvec / (WT / V);  // tiles with every vector in range
+  const uint64_t tf = te < full_tiles ? te : (tb > full_tiles ? tb : full_tiles);
+  nk_u32x4 ca[R], cb[R];
+  if (tb < tf) {
+    load_full(tb, ca);
+    for (uint64_t tile = tb;; tile += 2) {
+      const uint64_t n1 = tile + 1 < tf ? tile + 1 : tile;
+      load_full(n1, cb);
+      process(std::true_type{}, tile, ca);
+      if (tile + 1 >= tf) break;
+      const uint64_t n2 = tile + 2 < tf ? tile + 2 : tile + 1;
+      load_full(n2, ca);
+      process(std::true_type{}, tile + 1, cb);
+      if (tile + 2 >= tf) break;
+    }
+  }
+  for (uint64_t tile = tf; tile < te; ++tile) {  // at most the array's last tile
+    load_part(tile, ca);
+    process(std::false_type{}, tile, ca);
+  }
+  if (lane == 0 && unit < P.n_units) gstore(P.unit_cnt + unit, run);
+}
+
 template <typename T, typename S>
 __global__ void __launch_bounds__(UNIT_TPB) k_gather(S src, Geo g) {
-  constexpr int V = Traits<T>::V;
-  constexpr int WT = ENC_ROUNDS * 64 * V;
   constexpr int NWAVE = UNIT_TPB / 64;
   __shared__ unsigned long long s_part[NWAVE];
   __shared__ uint32_t s_cnt[NWAVE];
@@ -1840,17 +2147,57 @@ __global__ void __launch_bounds__(UNIT_TPB) k_gather(S src, Geo g) {
   for (int w = 0; w < wave; ++w) off += s_cnt[w];
   const uint32_t unit = unit0 + wave;
   if (unit >= P.n_units) return;
-  const uint64_t e0 = (uint64_t)unit * P.tiles_per_unit * WT;
+  const uint64_t span = P.tiles_per_unit * P.tile_elems;  // elements of a unit range
+  const uint64_t e0 = (uint64_t)unit * span;
   if (e0 >= P.n) return;
-  uint64_t e1 = e0 + P.tiles_per_unit * WT;
+  uint64_t e1 = e0 + span;
   e1 = e1 < P.n ? e1 : P.n;
   const unsigned cnt = s_cnt[wave];
-  const T* __restrict__ scratch = static_cast<const T*>(P.scratch);
   T* __restrict__ incomp = static_cast<T*>(P.incomp);
-  for (unsigned i = lane; i < cnt; i += 64) gstore(incomp + off + i, gload(scratch + e0 + i));
-  const uint64_t b0 = (e0 + P.epb - 1) / P.epb;
-  for (uint64_t b = b0 + lane; b * P.epb < e1; b += 64)
-    gstore(P.block_inc_off + b, gload(P.block_inc_off + b) + (int64_t)off);
+  if (P.pre) {
+    // staged element indices: fetch the values from curr, eight per lane
+    // in flight (the fetches are scattered: each waits a full memory latency)
+    const uint32_t* __restrict__ st = static_cast<const uint32_t*>(P.scratch);
+    const T* __restrict__ curr = static_cast<const T*>(P.curr);
+    constexpr int GU = 8;
+    for (unsigned i0 = 0; i0 < cnt; i0 += 64 * GU) {
+      uint32_t jx[GU];
+      T vx[GU];
+#pragma unroll
+      for (int u = 0; u < GU; ++u) {
+        const unsigned i = i0 + (unsigned)u * 64 + (unsigned)lane;
+        jx[u] = i < cnt ? gload(st + e0 + i) : 0u;
+      }
+#pragma unroll
+      for (int u = 0; u < GU; ++u) {
+        const unsigned i = i0 + (unsigned)u * 64 + (unsigned)lane;
+        vx[u] = i < cnt ? gload(curr + jx[u]) : (T)0;
+      }
+#pragma unroll
+      for (int u = 0; u < GU; ++u) {
+        const unsigned i = i0 + (unsigned)u * 64 + (unsigned)lane;
+        if (i < cnt) gstore(incomp + off + i, vx[u]);
+      }
+    }
+    // block b starting in the range: off plus the range's incompressible
+    // points before its first element (the staged indices ascend)
+    const uint64_t b0 = (e0 + P.epb - 1) / P.epb;
+    for (uint64_t b = b0 + lane; b * P.epb < e1; b += 64) {
+      const uint64_t first = b * P.epb;
+      unsigned a = 0, z = cnt;
+      while (a < z) {
+        const unsigned mid = (a + z) >> 1;
+        if ((uint64_t)gload(st + e0 + mid) < first) a = mid + 1; else z = mid;
+      }
+      gstore(P.block_inc_off + b, (int64_t)(off + a));
+    }
+  } else {
+    const T* __restrict__ scratch = static_cast<const T*>(P.scratch);
+    for (unsigned i = lane; i < cnt; i += 64) gstore(incomp + off + i, gload(scratch + e0 + i));
+    const uint64_t b0 = (e0 + P.epb - 1) / P.epb;
+    for (uint64_t b = b0 + lane; b * P.epb < e1; b += 64)
+      gstore(P.block_inc_off + b, gload(P.block_inc_off + b) + (int64_t)off);
+  }
 }
 
 // Header of the call (Fig. 2's attributes plus this library's counts).
@@ -1919,6 +2266,26 @@ static void (*encoder_kernel(int cls, uint32_t nt))(S, Geo) {
   if constexpr (std::is_same<S, JobTable>::value)
     if (nt == 2) return encoder_kernel_nt<T, S, 2>(cls);
   return nt == 1 ? encoder_kernel_nt<T, S, 1>(cls) : encoder_kernel_nt<T, S, 0>(cls);
+}
+
+// Kernel of a precoded encoder specialisation (single jobs).
+template <typename T>
+static void (*encoder_pre_kernel(int cls))(OneJob, Geo) {
+  switch (cls) {
+    case 0: return k_encode_pre<T, uint8_t, 0, OneJob>;
+    case 1: return k_encode_pre<T, uint8_t, 8, OneJob>;
+    case 2: return k_encode_pre<T, uint16_t, 0, OneJob>;
+    default: return k_encode_pre<T, uint16_t, 16, OneJob>;
+  }
+}
+
+static int encoder_pre_occupancy(int dtype, int cls) {
+  void (*k)(OneJob, Geo) = dtype == NUMARCK_F32 ? encoder_pre_kernel<float>(cls)
+                                                : encoder_pre_kernel<double>(cls);
+  int occ = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k, UNIT_TPB, 0) != hipSuccess || occ < 1)
+    occ = 1;
+  return occ;
 }
 
 template <typename S>
@@ -2063,6 +2430,10 @@ static hipError_t run_chain(S src, const Geo& base, uint32_t njobs, const JobGro
     void (*k)(S, Geo) = eg[i].dtype == NUMARCK_F32
                             ? encoder_kernel<float, S>(eg[i].cls, g.stream_nt)
                             : encoder_kernel<double, S>(eg[i].cls, g.stream_nt);
+    if constexpr (std::is_same<S, OneJob>::value)
+      if (eg[i].pre)
+        k = eg[i].dtype == NUMARCK_F32 ? encoder_pre_kernel<float>(eg[i].cls)
+                                       : encoder_pre_kernel<double>(eg[i].cls);
     NK_LAUNCH(KK_ENCODE, k, blocks, UNIT_TPB, src, g);
   }
   for (uint32_t i = 0; i < ndg; ++i) {
@@ -2101,7 +2472,16 @@ hipError_t launch_compress_phase(const CParams& P0, const Tuning& tn, hipStream_
   const Geometry G = geometry();
   CParams P = P0;
   const int cls = enc_class(P.B);
-  const int occ = encoder_occupancy(P.dtype, cls, false);
+  // Precoded encoding wherever the histogram counts in LDS and no
+  // reconstruction is asked for (the encoder then never reads the values of
+  // its compressible points).
+  P.pre = tn.hist_lds && P.recon == nullptr ? 1u : 0u;
+  if (P.pre) {
+    P.tile_elems = (uint32_t)PRE_WAVE_TILE;
+    P.n_tiles = (P.n + PRE_WAVE_TILE - 1) / PRE_WAVE_TILE;
+  }
+  const int occ = P.pre ? encoder_pre_occupancy(P.dtype, cls)
+                        : encoder_occupancy(P.dtype, cls, false);
   const uint64_t resident = (uint64_t)G.cus * occ * 4 * tn.unit_pct / 100;
   P.n_units = range_units(P.n_tiles, (int)(resident < 4 ? 4 : resident));
   P.tiles_per_unit = (P.n_tiles + P.n_units - 1) / P.n_units;
@@ -2117,6 +2497,7 @@ hipError_t launch_compress_phase(const CParams& P0, const Tuning& tn, hipStream_
   grp.c_end = stream_chunks(P.n, P.dtype, base.chunk_vec);
   grp.u_begin = 0;
   grp.u_end = P.n_units;
+  grp.pre = P.pre;
   grp.nt = stream_nt_for(tn.stream_loads, 2 * P.n * (P.dtype == NUMARCK_F32 ? 4 : 8),
                          P.prev == P.curr);
   if (grp.nt == 2) grp.nt = 0;  // one job: its two inputs are one snapshot

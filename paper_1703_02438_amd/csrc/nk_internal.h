@@ -95,7 +95,7 @@ struct DCtl {
 
 // Workspace layout of one compression (byte offsets from the workspace base).
 struct Layout {
-  size_t ctl, gwin, lut, sel_tail, sorted_tail, unit_cnt, sink, scratch, tail, hslot,
+  size_t ctl, gwin, lut, sel_tail, sorted_tail, unit_cnt, sink, scratch, wcode, tail, hslot,
       hcnt, total;
   uint64_t tail_cap, hcap;
 };
@@ -126,7 +126,14 @@ struct CParams {
   int64_t* sel_tail;
   int64_t* sorted_tail;
   uint32_t* unit_cnt;  // incompressible points per encoder unit, then their offsets
-  void* scratch;       // incompressible values staged per unit range
+  void* scratch;       // incompressible values (or, precoded, their element
+                       // indices) staged per unit range
+  // Precoded encoding (pre != 0): the histogram pass also writes each
+  // point's window code (WC_* below) and the encoder reads those 2 bytes in
+  // place of the 2L bytes of the snapshots.
+  uint16_t* wcode;
+  uint32_t pre;
+  uint32_t tile_elems;  // elements of an encoder wave tile
   void* sink;          // SINK_SLOTS x 256 bytes written by masked-off lanes (never read)
   uint32_t n_units;
   uint64_t tiles_per_unit;
@@ -212,6 +219,8 @@ struct JobGroup {
   // the chunks keep the batch numbering and each workgroup stays on one job,
   // consecutive jobs in step.
   uint32_t chain;
+  // Encoder groups: the jobs take the precoded encoding (CParams::pre).
+  uint32_t pre;
 };
 inline int enc_class(uint32_t B) { return B < 8 ? 0 : B == 8 ? 1 : B < 16 ? 2 : 3; }
 
@@ -258,6 +267,20 @@ inline uint32_t chunk_vec_for(uint32_t fixed, uint64_t vecs, int cus) {
 
 // Elements of one encoder / decoder wave tile for an element size (16-byte vectors).
 inline uint64_t enc_wave_tile(uint64_t elem_bytes) { return ENC_ROUNDS * 64 * (16 / elem_bytes); }
+
+// Window codes of the precoded encoding, one 16-bit word per point: a valid
+// point inside the histogram window holds its window place w (bits 0-13,
+// WIN = 2^14) and, in bit 14, whether the reconstruction from its own bin's
+// centre passes the error check of Sec. III-C (the check the encoder makes
+// when that bin is selected); an invalid point holds WC_INVALID, a valid
+// point outside the window WC_TAIL.
+constexpr uint16_t WC_OK = 0x4000;
+constexpr uint16_t WC_INVALID = 0x8000;
+constexpr uint16_t WC_TAIL = 0xC000;
+static_assert(WIN == 1 << 14, "window places fit 14 bits");
+// Rounds of 8 codes (one 16-byte load) per lane in a precoded encoder tile.
+constexpr int PRE_ROUNDS = 2;
+constexpr uint64_t PRE_WAVE_TILE = PRE_ROUNDS * 64 * 8;
 inline uint64_t dec_wave_tile(uint64_t elem_bytes) { return DEC_ROUNDS * 64 * (16 / elem_bytes); }
 // Units (waves) of a range-partitioned pass over `tiles` wave tiles, at most
 // `resident` (the waves that fit on the device at once); a multiple of the 4
