@@ -687,12 +687,14 @@ static numarck_status plan_create(const numarck_job* jobs, uint32_t njobs,
   }
   if (numarck_batch_workspace_bytes(jobs, njobs) > ws_bytes) return NUMARCK_ECAPACITY;
 
-  // order: element type, then encoder class (each launch covers a contiguous run)
+  // order: element type, then encoder class, then the encoding (precoded
+  // unless a reconstruction is asked for); each launch covers a contiguous run
+  auto pre_of = [&](uint32_t i) { return tn.hist_lds && jobs[i].out.recon == nullptr ? 1 : 0; };
   std::vector<uint32_t> order(njobs);
   for (uint32_t i = 0; i < njobs; ++i) order[i] = i;
   std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) {
-    const int ka = (int)jobs[a].dtype * 8 + enc_class(jobs[a].B);
-    const int kb = (int)jobs[b].dtype * 8 + enc_class(jobs[b].B);
+    const int ka = (int)jobs[a].dtype * 16 + enc_class(jobs[a].B) * 2 + pre_of(a);
+    const int kb = (int)jobs[b].dtype * 16 + enc_class(jobs[b].B) * 2 + pre_of(b);
     return ka < kb;
   });
 
@@ -710,6 +712,12 @@ static numarck_status plan_create(const numarck_job* jobs, uint32_t njobs,
     const Layout L = compress_layout(j.n, eb, job_tail_cap(j));
     pl->table[r] = make_params(j.prev, j.curr, j.n, j.dtype, j.E, j.B, j.block_bytes, &j.out,
                                base + off, L);
+    if (pre_of(order[r])) {
+      CParams& P = pl->table[r];
+      P.pre = 1;
+      P.tile_elems = (uint32_t)PRE_WAVE_TILE;
+      P.n_tiles = (P.n + PRE_WAVE_TILE - 1) / PRE_WAVE_TILE;
+    }
     off += align256(L.total);
   }
   // streaming chunks: each element type's group gets its own chunk size
@@ -749,10 +757,13 @@ static numarck_status plan_create(const numarck_job* jobs, uint32_t njobs,
   for (uint32_t r = 0; r < njobs;) {
     uint32_t e = r + 1;
     const int dt = pl->table[r].dtype, cls = enc_class(pl->table[r].B);
-    while (e < njobs && pl->table[e].dtype == dt && enc_class(pl->table[e].B) == cls) ++e;
+    const uint32_t pre = pl->table[r].pre;
+    while (e < njobs && pl->table[e].dtype == dt && enc_class(pl->table[e].B) == cls &&
+           pl->table[e].pre == pre)
+      ++e;
     uint64_t tiles = 0;
     for (uint32_t q = r; q < e; ++q) tiles += pl->table[q].n_tiles;
-    const int occ = encoder_occupancy(dt, cls, true);
+    const int occ = pre ? encoder_pre_occupancy(dt, cls, true) : encoder_occupancy(dt, cls, true);
     uint64_t resident = (uint64_t)G.cus * occ * 4 * tn.unit_pct / 100;
     if (resident < 4) resident = 4;
     for (uint32_t q = r; q < e; ++q) {
@@ -769,6 +780,7 @@ static numarck_status plan_create(const numarck_job* jobs, uint32_t njobs,
     JobGroup g{};
     g.dtype = dt;
     g.cls = cls;
+    g.pre = pre;
     g.nt = stream_nt_for(tn.stream_loads, gbytes, shared_inputs);
     g.chunk_vec = cvec_of[r];
     g.job_begin = r;

@@ -2268,24 +2268,30 @@ static void (*encoder_kernel(int cls, uint32_t nt))(S, Geo) {
   return nt == 1 ? encoder_kernel_nt<T, S, 1>(cls) : encoder_kernel_nt<T, S, 0>(cls);
 }
 
-// Kernel of a precoded encoder specialisation (single jobs).
-template <typename T>
-static void (*encoder_pre_kernel(int cls))(OneJob, Geo) {
+// Kernel of a precoded encoder specialisation.
+template <typename T, typename S>
+static void (*encoder_pre_kernel(int cls))(S, Geo) {
   switch (cls) {
-    case 0: return k_encode_pre<T, uint8_t, 0, OneJob>;
-    case 1: return k_encode_pre<T, uint8_t, 8, OneJob>;
-    case 2: return k_encode_pre<T, uint16_t, 0, OneJob>;
-    default: return k_encode_pre<T, uint16_t, 16, OneJob>;
+    case 0: return k_encode_pre<T, uint8_t, 0, S>;
+    case 1: return k_encode_pre<T, uint8_t, 8, S>;
+    case 2: return k_encode_pre<T, uint16_t, 0, S>;
+    default: return k_encode_pre<T, uint16_t, 16, S>;
   }
 }
 
-static int encoder_pre_occupancy(int dtype, int cls) {
-  void (*k)(OneJob, Geo) = dtype == NUMARCK_F32 ? encoder_pre_kernel<float>(cls)
-                                                : encoder_pre_kernel<double>(cls);
+template <typename S>
+static int encoder_pre_occupancy_t(int dtype, int cls) {
+  void (*k)(S, Geo) = dtype == NUMARCK_F32 ? encoder_pre_kernel<float, S>(cls)
+                                           : encoder_pre_kernel<double, S>(cls);
   int occ = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k, UNIT_TPB, 0) != hipSuccess || occ < 1)
     occ = 1;
   return occ;
+}
+
+int encoder_pre_occupancy(int dtype, int cls, bool table) {
+  return table ? encoder_pre_occupancy_t<JobTable>(dtype, cls)
+               : encoder_pre_occupancy_t<OneJob>(dtype, cls);
 }
 
 template <typename S>
@@ -2430,10 +2436,9 @@ static hipError_t run_chain(S src, const Geo& base, uint32_t njobs, const JobGro
     void (*k)(S, Geo) = eg[i].dtype == NUMARCK_F32
                             ? encoder_kernel<float, S>(eg[i].cls, g.stream_nt)
                             : encoder_kernel<double, S>(eg[i].cls, g.stream_nt);
-    if constexpr (std::is_same<S, OneJob>::value)
-      if (eg[i].pre)
-        k = eg[i].dtype == NUMARCK_F32 ? encoder_pre_kernel<float>(eg[i].cls)
-                                       : encoder_pre_kernel<double>(eg[i].cls);
+    if (eg[i].pre)
+      k = eg[i].dtype == NUMARCK_F32 ? encoder_pre_kernel<float, S>(eg[i].cls)
+                                     : encoder_pre_kernel<double, S>(eg[i].cls);
     NK_LAUNCH(KK_ENCODE, k, blocks, UNIT_TPB, src, g);
   }
   for (uint32_t i = 0; i < ndg; ++i) {
@@ -2480,7 +2485,7 @@ hipError_t launch_compress_phase(const CParams& P0, const Tuning& tn, hipStream_
     P.tile_elems = (uint32_t)PRE_WAVE_TILE;
     P.n_tiles = (P.n + PRE_WAVE_TILE - 1) / PRE_WAVE_TILE;
   }
-  const int occ = P.pre ? encoder_pre_occupancy(P.dtype, cls)
+  const int occ = P.pre ? encoder_pre_occupancy(P.dtype, cls, false)
                         : encoder_occupancy(P.dtype, cls, false);
   const uint64_t resident = (uint64_t)G.cus * occ * 4 * tn.unit_pct / 100;
   P.n_units = range_units(P.n_tiles, (int)(resident < 4 ? 4 : resident));

@@ -369,6 +369,7 @@ hipError_t launch_compress_za(const CParams& P, const Tuning& tn, hipStream_t s)
 hipError_t launch_compress_ew(const CParams& P, const Tuning& tn, hipStream_t s);
 // Resident workgroups per CU of one encoder specialisation (for sizing units).
 int encoder_occupancy(int dtype, int cls, bool table);
+int encoder_pre_occupancy(int dtype, int cls, bool table);
 // Streaming chunks of a job (0 for an empty job, at least 1 otherwise).
 uint64_t stream_chunks(uint64_t n, int dtype, uint32_t chunk_vec);
 hipError_t launch_decompress(const DParams& p, hipStream_t s);
