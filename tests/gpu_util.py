@@ -78,10 +78,15 @@ def assert_matches_oracle(nk, c, o, prev, curr, E, B, block_bytes=0, check_hist=
 
 
 def compare_compress(nk, prev, curr, E, B, block_bytes=0, check_hist=True, label=""):
-    """Compress on both sides and assert every output is identical."""
+    """Compress on both sides and assert every output is identical: once with
+    the reconstruction (the encoder that reads both snapshots) and once
+    without (the precoded encoder, from the histogram pass's window codes)."""
     o = oracle.get().compress(prev, curr, E, B, block_bytes=block_bytes)
     c, p, q = gpu_compress(nk, prev, curr, E, B, block_bytes)
     assert_matches_oracle(nk, c, o, prev, curr, E, B, block_bytes, check_hist, label)
+    c2 = nk.compress(p, q, E, B, block_bytes=block_bytes, bin_ids=True)
+    assert c2.recon is None
+    assert_matches_oracle(nk, c2, o, prev, curr, E, B, block_bytes, False, label + " precoded")
     return c, o, p
 
 

@@ -69,6 +69,10 @@ def test_auto_B_matches_oracle(nk, case):
     assert c.header().B == B
     o = orc.compress(prev, curr, E, B)
     assert_matches_oracle(nk, c, o, prev, curr, E, B, check_hist=False, label=f"auto {case}")
+    c2, B2, _ = nk.compress_auto(p, q, E, lo, hi, bin_ids=True)  # the precoded encoder
+    assert B2 == B
+    assert_matches_oracle(nk, c2, o, prev, curr, E, B, check_hist=False,
+                          label=f"auto precoded {case}")
     if case in ("mixture_f64", "tail_bins"):
         compare_decompress(nk, c, o, p, prev, [(0, prev.size), (prev.size // 3, 1000)],
                            label=f"auto {case}")

@@ -49,9 +49,14 @@ def _mixed_jobs():
     return jobs
 
 
-def _run_plan(nk, jobs, graph=False, tune=None):
+# with the reconstruction (the encoder reads both snapshots) and without it
+# (the precoded encoder)
+RECON = pytest.mark.parametrize("recon", [True, False], ids=["reads_snapshots", "precoded"])
+
+
+def _run_plan(nk, jobs, graph=False, tune=None, recon=True):
     bj = [nk.BatchJob(_dev(p), _dev(q), E, B, bb) for p, q, E, B, bb in jobs]
-    plan = nk.Plan(bj, recon=True, bin_ids=True, tune=tune)
+    plan = nk.Plan(bj, recon=recon, bin_ids=True, tune=tune)
     if graph:
         s = torch.cuda.Stream()
         s.wait_stream(torch.cuda.current_stream())
@@ -64,9 +69,10 @@ def _run_plan(nk, jobs, graph=False, tune=None):
     return plan, bj, res
 
 
-def test_mixed_batch_vs_oracle(nk):
+@RECON
+def test_mixed_batch_vs_oracle(nk, recon):
     jobs = _mixed_jobs()
-    plan, bj, res = _run_plan(nk, jobs)
+    plan, bj, res = _run_plan(nk, jobs, recon=recon)
     torch.cuda.synchronize()
     orc = oracle.get()
     for i, ((p, q, E, B, bb), c) in enumerate(zip(jobs, res)):
@@ -79,23 +85,25 @@ def test_mixed_batch_vs_oracle(nk):
     plan.close()
 
 
-def test_batch_equals_plain_and_one_shot(nk):
+@RECON
+def test_batch_equals_plain_and_one_shot(nk, recon):
     jobs = _mixed_jobs()
-    plan, bj, res = _run_plan(nk, jobs)
-    one = nk.compress_batch(bj, recon=True, bin_ids=True)
+    plan, bj, res = _run_plan(nk, jobs, recon=recon)
+    one = nk.compress_batch(bj, recon=recon, bin_ids=True)
     for i, (j, c, c1) in enumerate(zip(bj, res, one)):
-        plain = nk.compress(j.prev, j.curr, j.E, j.B, j.block_bytes, recon=True, bin_ids=True)
+        plain = nk.compress(j.prev, j.curr, j.E, j.B, j.block_bytes, recon=recon, bin_ids=True)
         assert_same_compression(c, plain, f"plan vs plain job{i}")
         assert_same_compression(c1, plain, f"one-shot vs plain job{i}")
     plan.close()
 
 
-def test_graph_replays(nk):
+@RECON
+def test_graph_replays(nk, recon):
     """A captured plan replays several times, with eager work and new input
     values between replays; every replay matches the oracle on what the
     inputs held at that time."""
     jobs = _mixed_jobs()[:6]
-    plan, bj, res = _run_plan(nk, jobs, graph=True)
+    plan, bj, res = _run_plan(nk, jobs, graph=True, recon=recon)
     torch.cuda.synchronize()
     orc = oracle.get()
     s = torch.cuda.Stream()

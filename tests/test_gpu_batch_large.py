@@ -9,7 +9,9 @@
   oracle.  The same for a zero-anchored plan of the same pairs.
 - The uneven 64-variable workload at its full cube edges (32..384, mixed
   float32/float64, E in {1e-4, 1e-3, 1e-2}, B in {8, 10, 12}): every job
-  equals its plain compression bit for bit, two equal the oracle."""
+  equals its plain compression bit for bit, two equal the oracle.
+Both run with the reconstruction (the encoder that reads both snapshots) and
+without it (the precoded encoder, the benchmark's configuration)."""
 import numpy as np
 import pytest
 import torch
@@ -32,7 +34,8 @@ def _same(a, b, label):
     """Every output of two compressions, the reconstruction included."""
     assert_same_compression(a, b, label)
     n = a.header().n
-    if n:
+    assert (a.recon is None) == (b.recon is None)
+    if n and a.recon is not None:
         iv = torch.int32 if a.recon.dtype == torch.float32 else torch.int64
         assert torch.equal(a.recon[:n].view(iv), b.recon[:n].view(iv)), f"[{label}] recon"
 
@@ -63,19 +66,23 @@ def _chain_groups(plan, za):
     assert enc[0]["load_hint"] == 2, g  # prev non-temporal, curr cached
 
 
+RECON = pytest.mark.parametrize("recon", [True, False], ids=["reads_snapshots", "precoded"])
+
+
+@RECON
 @pytest.mark.parametrize("za", [False, True], ids=["paper_anchor", "zero_anchored"])
-def test_streaming_time_chain(nk, flash_chain, za):
+def test_streaming_time_chain(nk, flash_chain, za, recon):
     snaps = flash_chain
     E, B = 1e-3, 8
     bj = [nk.BatchJob(snaps[t], snaps[t + 1], E, B) for t in range(4)]
-    plan = nk.Plan(bj, recon=True, bin_ids=True, zero_anchored=za)
+    plan = nk.Plan(bj, recon=recon, bin_ids=True, zero_anchored=za)
     _chain_groups(plan, za)
     plain_fn = nk.compress_zero_anchored if za else nk.compress
     for rep in range(2):
         res = plan.run()
         torch.cuda.synchronize()
         for t, c in enumerate(res):
-            ref = plain_fn(snaps[t], snaps[t + 1], E, B, recon=True, bin_ids=True)
+            ref = plain_fn(snaps[t], snaps[t + 1], E, B, recon=recon, bin_ids=True)
             torch.cuda.synchronize()
             _same(c, ref, f"{'za' if za else 'topk'} pair {t} rep {rep}")
             del ref
@@ -91,27 +98,29 @@ def test_streaming_time_chain(nk, flash_chain, za):
                 f"za pair {t} packed"
             assert np.array_equal(bits(to_np(res[t].incomp[:h.n_inc])), bits(o.incomp)), \
                 f"za pair {t} incomp"
-            assert np.array_equal(bits(to_np(res[t].recon[:h.n])), bits(o.recon)), \
-                f"za pair {t} recon"
+            if recon:
+                assert np.array_equal(bits(to_np(res[t].recon[:h.n])), bits(o.recon)), \
+                    f"za pair {t} recon"
         else:
             assert_matches_oracle(nk, res[t], orc.compress(p, q, E, B), p, q, E, B,
                                   check_hist=False, label=f"chain pair {t}")
     plan.close()
 
 
-def test_uneven_variables_full_edges(nk):
+@RECON
+def test_uneven_variables_full_edges(nk, recon):
     specs = inputs.batched_specs(64)  # cube edges log-uniform in [32, 384]
     pairs = [inputs.mixture_pair(sp.n, seed=sp.seed, dtype=sp.dtype, device="cuda")
              for sp in specs]
     bj = [nk.BatchJob(p, q, sp.E, sp.B) for (p, q), sp in zip(pairs, specs)]
-    plan = nk.Plan(bj, recon=True, bin_ids=True)
+    plan = nk.Plan(bj, recon=recon, bin_ids=True)
     g = plan.groups()
     assert sum(x["njobs"] for x in g if x["pass"] == "encode") == 64, g
     assert all(x["chain"] == 0 for x in g), g
     res = plan.run()
     torch.cuda.synchronize()
     for i, ((p, q), sp, c) in enumerate(zip(pairs, specs, res)):
-        ref = nk.compress(p, q, sp.E, sp.B, recon=True, bin_ids=True)
+        ref = nk.compress(p, q, sp.E, sp.B, recon=recon, bin_ids=True)
         torch.cuda.synchronize()
         _same(c, ref, f"var {i} edge {sp.edge} {sp.dtype} E={sp.E} B={sp.B}")
         del ref

@@ -20,10 +20,17 @@ def nk():
 
 
 def _full_check(nk, prev_t, curr_t, E, B, label):
+    """Both encoders: with the reconstruction (reading both snapshots) and
+    without (the precoded encoder, the benchmark's configuration)."""
     n = prev_t.numel()
     dt = prev_t.dtype
     ws = torch.empty(nk.numarck_workspace_bytes(n, nk.dtype_code(dt), B), dtype=torch.uint8,
                      device="cuda")
+    c2 = nk.compress(prev_t, curr_t, E, B, ws=ws)
+    h2 = c2.header().as_dict()
+    pre = {"packed": to_np(c2.packed), "centers": to_np(c2.centers),
+           "incomp": to_np(c2.incomp)[: h2["n_inc"]], "blocks": to_np(c2.block_inc_off)}
+    del c2
     c = nk.compress(prev_t, curr_t, E, B, recon=True, bin_ids=True, ws=ws)
     h = c.header().as_dict()
     out, fl = nk.decompress(c, prev_t)
@@ -43,6 +50,13 @@ def _full_check(nk, prev_t, curr_t, E, B, label):
     assert np.array_equal(to_np(c.block_inc_off)[: o.info["n_blocks"]], o.block_inc_off)
     assert np.array_equal(bits(to_np(c.recon)[:n]), bits(o.recon))
     assert np.array_equal(to_np(c.bin_ids)[: o.info["k_used"]], o.sel_ids)
+    for f in HEADER_FIELDS:
+        assert h2[f] == o.info[f], f"[{label} precoded] header {f}"
+    assert h2["flags"] == 0
+    assert np.array_equal(pre["packed"][: o.info["packed_words"]].view(np.uint32), o.packed)
+    assert np.array_equal(bits(pre["centers"]), bits(o.centers))
+    assert np.array_equal(bits(pre["incomp"]), bits(o.incomp))
+    assert np.array_equal(pre["blocks"][: o.info["n_blocks"]], o.block_inc_off)
     ref, rfl = oracle.get().decompress(o, prev)
     assert int(fl.item()) == rfl == 0
     assert np.array_equal(bits(to_np(out)), bits(ref))
@@ -83,6 +97,10 @@ def test_flash_512cubed_zero_anchored_and_lossless_full(nk):
     del s
     E, B = 1e-3, 8
     n = prev_t.numel()
+    c2 = nk.compress_zero_anchored(prev_t, curr_t, E, B)  # precoded, as the benchmark runs it
+    h2 = c2.header().as_dict()
+    pre = (to_np(c2.packed), to_np(c2.incomp)[: h2["n_inc"]])
+    del c2
     c = nk.compress_zero_anchored(prev_t, curr_t, E, B, recon=True)
     h = c.header().as_dict()
     enc = nk.lossless_encode(c.packed, n, B)
@@ -101,6 +119,9 @@ def test_flash_512cubed_zero_anchored_and_lossless_full(nk):
     assert np.array_equal(bits(to_np(c.centers)), bits(o.centers))
     assert np.array_equal(bits(to_np(c.incomp)[: o.info["n_inc"]]), bits(o.incomp))
     assert np.array_equal(bits(to_np(c.recon)[:n]), bits(o.recon))
+    assert all(h2[f] == o.info[f] for f in HEADER_FIELDS)
+    assert np.array_equal(pre[0][:nw].view(np.uint32), o.packed)
+    assert np.array_equal(bits(pre[1]), bits(o.incomp))
     ol = orc.lossless_encode(o.packed, n, B)
     assert lh.k == ol["k"] and lh.stream_words == ol["stream"].size
     assert np.array_equal(to_np(enc.code_of_rank).view(np.uint16), ol["code_of_rank"])

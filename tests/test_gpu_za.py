@@ -31,6 +31,10 @@ def za_compare(nk, prev, curr, E, B, block_bytes=0, label="", ranges=None):
     torch.cuda.synchronize()
     assert_matches_oracle(nk, c, o, prev, curr, E, B, block_bytes, check_hist=True,
                           label=f"za {label}")
+    # without the reconstruction: the precoded encoder
+    c2 = nk.compress_zero_anchored(p, q, E, B, block_bytes, bin_ids=True)
+    assert_matches_oracle(nk, c2, o, prev, curr, E, B, block_bytes, check_hist=False,
+                          label=f"za precoded {label}")
     if ranges is not None:
         compare_decompress(nk, c, o, p, prev, ranges, label=f"za {label}")
     return c, o
