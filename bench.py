@@ -289,22 +289,25 @@ def summarize_trace(trace_csv: str, out_md: str, title: str, cmd: str):
     print(out_md)
 
 
-STREAM_KINDS = ("read", "read_nt", "write", "write_nt", "copy", "copy_nt", "read2_write16")
+STREAM_KINDS = ("read", "read_nt", "write", "write_nt", "copy", "copy_nt", "read2_write16",
+                "read2_write8")
 
 
 def stream_section(torch, nk, reps: int, nbytes: int = 1 << 30) -> dict:
     """The library's reference streaming kernels (numarck_stream_kernel) on
-    1 GiB: read, write and copy, cached and non-temporal, and the encoder's
-    shape (two arrays read, 1/16 of that written), at 2..16 workgroups per
-    compute unit; GB/s of bytes moved (a copy moves 2 x nbytes), the best
-    launch of each."""
+    1 GiB: read, write and copy, cached and non-temporal, and two read and
+    write mixes (two arrays read, 1/16 of that written: an encoder reading
+    both snapshots; 1/8: the histogram pass writing window codes), at 2..16
+    workgroups per compute unit; GB/s of bytes moved (a copy moves 2 x
+    nbytes), the best launch of each."""
     src = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda").fill_(1.0)
     dst = torch.empty_like(src)
     stream = torch.cuda.current_stream()
     out = {}
     for kind, name in enumerate(STREAM_KINDS):
         moved = (2 * nbytes if name.startswith("copy") else
-                 nbytes + nbytes // 16 if name == "read2_write16" else nbytes)
+                 nbytes + nbytes // 16 if name == "read2_write16" else
+                 nbytes + nbytes // 8 if name == "read2_write8" else nbytes)
         best = None
         for per_cu in (2, 4, 8, 16):
             t = time_ms(torch, lambda: nk.stream_kernel(kind, src, dst, nbytes, per_cu, stream),

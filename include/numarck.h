@@ -509,14 +509,17 @@ void numarck_server_destroy(numarck_server* s);
  *                     each, read in step (non-temporal); for every 16-byte
  *                     position one 16-bit word goes to dst (bytes/16 bytes
  *                     written, 1/16 of the read volume)
- * bytes must be a multiple of 16 (of 32 for READ2_WRITE16), src and dst
+ *   READ2_WRITE8    : the same with one 32-bit word per position (bytes/8
+ *                     bytes written, 1/8 of the read volume: the histogram
+ *                     pass writing the window codes of 64-bit values)
+ * bytes must be a multiple of 16 (of 32 for the READ2 kinds), src and dst
  * 16-byte aligned.  EINVAL on a bad kind, size, pointer or per_cu;
  * asynchronous on `stream`. */
 typedef enum {
   NUMARCK_STREAM_READ = 0, NUMARCK_STREAM_READ_NT = 1,
   NUMARCK_STREAM_WRITE = 2, NUMARCK_STREAM_WRITE_NT = 3,
   NUMARCK_STREAM_COPY = 4, NUMARCK_STREAM_COPY_NT = 5,
-  NUMARCK_STREAM_READ2_WRITE16 = 6
+  NUMARCK_STREAM_READ2_WRITE16 = 6, NUMARCK_STREAM_READ2_WRITE8 = 7
 } numarck_stream_kind;
 numarck_status numarck_stream_kernel(int kind, const void* src, void* dst, uint64_t bytes,
                                      uint32_t per_cu, void* stream);

@@ -1273,8 +1273,9 @@ const char* numarck_last_error(void) { return g_last_error.c_str(); }
 
 numarck_status numarck_stream_kernel(int kind, const void* src, void* dst, uint64_t bytes,
                                      uint32_t per_cu, void* stream) {
-  if (kind < NUMARCK_STREAM_READ || kind > NUMARCK_STREAM_READ2_WRITE16) return NUMARCK_EINVAL;
-  const uint64_t unit = kind == NUMARCK_STREAM_READ2_WRITE16 ? 32 : 16;
+  if (kind < NUMARCK_STREAM_READ || kind > NUMARCK_STREAM_READ2_WRITE8) return NUMARCK_EINVAL;
+  const uint64_t unit =
+      kind == NUMARCK_STREAM_READ2_WRITE16 || kind == NUMARCK_STREAM_READ2_WRITE8 ? 32 : 16;
   if (bytes % unit != 0 || per_cu < 1 || per_cu > 64 || !dst) return NUMARCK_EINVAL;
   const bool reads = kind != NUMARCK_STREAM_WRITE && kind != NUMARCK_STREAM_WRITE_NT;
   if (reads && !src) return NUMARCK_EINVAL;

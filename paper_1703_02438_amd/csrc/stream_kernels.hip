@@ -74,14 +74,15 @@ __global__ void __launch_bounds__(STREAM_TPB) k_stream_copy(const nk_u32x4* __re
   for (; i < nvec; i += stride) sstore<NT>(dst + i, sload<NT>(src + i));
 }
 
-// The encoder's traffic shape: two arrays of nvec vectors each (the two
-// snapshots, src and src + nvec) read in step, and one 16-bit word written
-// per vector position (a 1/16 write stream, the index table of 8-bit codes
-// of 64-bit values).
-template <bool NT>
+// Two arrays of nvec vectors each (the two snapshots, src and src + nvec)
+// read in step, and one word W written per vector position: a 16-bit word is
+// the shape of an encoder that reads both snapshots (a 1/16 write stream, the
+// index table of 8-bit codes of 64-bit values); a 32-bit word that of the
+// histogram pass writing window codes (1/8: two 16-bit codes per vector of
+// 64-bit values).
+template <bool NT, typename W>
 __global__ void __launch_bounds__(STREAM_TPB) k_stream_mix(const nk_u32x4* __restrict__ src,
-                                                           uint64_t nvec,
-                                                           unsigned short* __restrict__ dst) {
+                                                           uint64_t nvec, W* __restrict__ dst) {
   const uint64_t stride = (uint64_t)gridDim.x * STREAM_TPB;
   const nk_u32x4* __restrict__ a = src;
   const nk_u32x4* __restrict__ b = src + nvec;
@@ -89,12 +90,12 @@ __global__ void __launch_bounds__(STREAM_TPB) k_stream_mix(const nk_u32x4* __res
   for (; i + stride < nvec; i += 2 * stride) {
     const nk_u32x4 x0 = sload<NT>(a + i), y0 = sload<NT>(b + i);
     const nk_u32x4 x1 = sload<NT>(a + i + stride), y1 = sload<NT>(b + i + stride);
-    gstore(dst + i, (unsigned short)(x0.x ^ y0.y));
-    gstore(dst + i + stride, (unsigned short)(x1.x ^ y1.y));
+    gstore(dst + i, (W)(x0.x ^ y0.y));
+    gstore(dst + i + stride, (W)(x1.x ^ y1.y));
   }
   for (; i < nvec; i += stride) {
     const nk_u32x4 x = sload<NT>(a + i), y = sload<NT>(b + i);
-    gstore(dst + i, (unsigned short)(x.x ^ y.y));
+    gstore(dst + i, (W)(x.x ^ y.y));
   }
 }
 
@@ -138,8 +139,14 @@ hipError_t launch_stream(int kind, const void* src, void* dst, uint64_t bytes, u
       break;
     case NUMARCK_STREAM_READ2_WRITE16: {
       const unsigned g2 = stream_grid(nvec / 2, per_cu);
-      hipLaunchKernelGGL(k_stream_mix<true>, dim3(g2), dim3(STREAM_TPB), 0, s, in, nvec / 2,
-                         static_cast<unsigned short*>(dst));
+      hipLaunchKernelGGL((k_stream_mix<true, unsigned short>), dim3(g2), dim3(STREAM_TPB), 0, s,
+                         in, nvec / 2, static_cast<unsigned short*>(dst));
+      break;
+    }
+    case NUMARCK_STREAM_READ2_WRITE8: {
+      const unsigned g2 = stream_grid(nvec / 2, per_cu);
+      hipLaunchKernelGGL((k_stream_mix<true, unsigned int>), dim3(g2), dim3(STREAM_TPB), 0, s,
+                         in, nvec / 2, static_cast<unsigned int*>(dst));
       break;
     }
     default:

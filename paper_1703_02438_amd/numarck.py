@@ -187,7 +187,7 @@ numarck_decompress_range = _bind("numarck_decompress_range", _i,
                                   _u64, _vp, _vp, _vp, _sz, _vp])
 numarck_stream_kernel = _bind("numarck_stream_kernel", _i, [_i, _vp, _vp, _u64, _u32, _vp])
 (STREAM_READ, STREAM_READ_NT, STREAM_WRITE, STREAM_WRITE_NT, STREAM_COPY, STREAM_COPY_NT,
- STREAM_READ2_WRITE16) = range(7)
+ STREAM_READ2_WRITE16, STREAM_READ2_WRITE8) = range(8)
 numarck_static_scratch_bytes = _bind("numarck_static_scratch_bytes", _sz, [])
 numarck_decompress_range_noalloc = _bind("numarck_decompress_range_noalloc", _i,
                                          [ctypes.POINTER(NumarckHeader), _vp, _vp, _vp, _vp,

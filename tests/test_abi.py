@@ -289,9 +289,9 @@ def test_decompress_noalloc_validation_without_gpu(nk):
 
 def test_stream_kernel_validation_without_gpu(nk):
     a, b = 0x300000, 0x400000
-    assert nk.numarck_stream_kernel(7, a, b, 1 << 20, 8, None) == nk.EINVAL
-    assert nk.numarck_stream_kernel(nk.STREAM_READ2_WRITE16, a, b, (1 << 20) + 16, 8,
-                                    None) == nk.EINVAL
+    assert nk.numarck_stream_kernel(8, a, b, 1 << 20, 8, None) == nk.EINVAL
+    for kind in (nk.STREAM_READ2_WRITE16, nk.STREAM_READ2_WRITE8):
+        assert nk.numarck_stream_kernel(kind, a, b, (1 << 20) + 16, 8, None) == nk.EINVAL
     assert nk.numarck_stream_kernel(-1, a, b, 1 << 20, 8, None) == nk.EINVAL
     assert nk.numarck_stream_kernel(nk.STREAM_COPY, a, b, (1 << 20) + 8, 8, None) == nk.EINVAL
     assert nk.numarck_stream_kernel(nk.STREAM_COPY, a, b, 1 << 20, 0, None) == nk.EINVAL

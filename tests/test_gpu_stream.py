@@ -42,18 +42,21 @@ def test_stream_kernels(nk, nbytes, per_cu):
 
 @pytest.mark.parametrize("nbytes", [32, (1 << 20) + 96, 3 * (1 << 24) + 32 * 777])
 @pytest.mark.parametrize("per_cu", [1, 8])
-def test_stream_read2_write16(nk, nbytes, per_cu):
-    """Position i of the two halves gives dst[i] = low 16 bits of
-    (a[i].x ^ b[i].y), every position written."""
-    g = torch.Generator(device="cuda").manual_seed(nbytes * 3 + per_cu)
+@pytest.mark.parametrize("word", [16, 32])
+def test_stream_read2_write(nk, nbytes, per_cu, word):
+    """Position i of the two halves gives dst[i] = the low 16 (READ2_WRITE16)
+    or 32 (READ2_WRITE8) bits of (a[i].x ^ b[i].y), every position written."""
+    g = torch.Generator(device="cuda").manual_seed(nbytes * 3 + per_cu + word)
     src = torch.randint(-2**31, 2**31 - 1, (nbytes // 4,), dtype=torch.int32, device="cuda",
                         generator=g)
     half = nbytes // 32
-    dst = torch.full((half + 8,), -1, dtype=torch.int16, device="cuda")
-    nk.stream_kernel(nk.STREAM_READ2_WRITE16, src, dst, nbytes, per_cu)
+    tdt, ndt = (torch.int16, np.uint16) if word == 16 else (torch.int32, np.uint32)
+    dst = torch.full((half + 8,), -1, dtype=tdt, device="cuda")
+    kind = nk.STREAM_READ2_WRITE16 if word == 16 else nk.STREAM_READ2_WRITE8
+    nk.stream_kernel(kind, src, dst, nbytes, per_cu)
     torch.cuda.synchronize()
     s = src.cpu().numpy().view(np.uint32).reshape(-1, 4)
-    want = ((s[:half, 0] ^ s[half:2 * half, 1]) & 0xFFFF).astype(np.uint16)
-    got = dst.cpu().numpy().view(np.uint16)
+    want = ((s[:half, 0] ^ s[half:2 * half, 1]) & ((1 << word) - 1)).astype(ndt)
+    got = dst.cpu().numpy().view(ndt)
     assert np.array_equal(got[:half], want)
-    assert np.all(got[half:] == 0xFFFF)
+    assert np.all(got[half:] == np.iinfo(ndt).max)
