@@ -1172,7 +1172,13 @@ __global__ void __launch_bounds__(SEL_TPB) k_select(SRC src, Geo g) {
     }
     if (!done) sel_threshold(S, k, visit_all, &tau, &cut);
   }
-  // selected <=> cnt > tau, or cnt == tau and id <= cut (cnt nonzero)
+  // selected <=> cnt > tau, or cnt == tau and id <= cut (cnt nonzero).
+  // With k <= SEL_TPB the selected tail ids also go to LDS (the radix
+  // histogram's space, free from here on) and are ranked at the end of this
+  // kernel; larger k leaves them to k_tailrank.
+  const bool rank_here = k <= (uint32_t)SEL_TPB;
+  long long* s_tail = reinterpret_cast<long long*>(S.hist);
+  static_assert(sizeof(S.hist) >= SEL_TPB * sizeof(long long), "tail ids fit");
   unsigned long long sel_tail = 0, sel_below = 0;
   if (tail_matters) {
     for (unsigned long long si = tid; si < H; si += SEL_TPB) {
@@ -1185,6 +1191,7 @@ __global__ void __launch_bounds__(SEL_TPB) k_select(SRC src, Geo g) {
         if (id < wbase) sel_below += 1;
         const unsigned pos = atomicAdd(&S.tail_pos, 1u);
         gstore(P.sel_tail + pos, (int64_t)id);
+        if (rank_here) s_tail[pos] = id;  // pos < k
       }
     }
   }
@@ -1249,6 +1256,20 @@ __global__ void __launch_bounds__(SEL_TPB) k_select(SRC src, Geo g) {
     c->k_used = (unsigned)(nz < k ? nz : k);
     c->nsel_tail = (unsigned)sel_tail;
     c->nsel_tail_below = (unsigned)sel_below;
+  }
+  // the selected tail bins in id order (what k_tailrank does for larger k):
+  // thread i ranks the i-th id by counting the smaller ones (ids distinct)
+  if (rank_here && sel_tail != 0) {  // uniform
+    const unsigned t = (unsigned)sel_tail;
+    if ((unsigned)tid < t) {
+      const long long id = s_tail[tid];
+      unsigned r = 0;
+      for (unsigned j = 0; j < t; ++j) r += s_tail[j] < id ? 1u : 0u;
+      gstore(P.sorted_tail + r, (int64_t)id);
+      const unsigned idx = r + (id > wbase ? (unsigned)nwin_sel : 0u);
+      gstore(centers + idx, (T)centre_of<T>(id, lo, P.E));
+      if (P.bin_ids) gstore(P.bin_ids + idx, (int64_t)id);
+    }
   }
 }
 
@@ -1364,7 +1385,7 @@ __global__ void __launch_bounds__(TR_TPB) k_tailrank(S src, Geo g) {
   __shared__ long long chunk[TR_TPB];
   const Ctl* c = P.ctl;
   const unsigned t = c->nsel_tail;
-  if (t == 0) return;
+  if (t == 0 || P.k <= (uint32_t)SEL_TPB) return;  // none, or ranked by k_select
   const long long wbase = c->wbase;
   const unsigned nwin = c->nsel_window;
   const double lo = c->lo;
@@ -1902,7 +1923,12 @@ __global__ void __launch_bounds__(UNIT_TPB) k_encode_pre(S src, Geo g) {
   const unsigned nsel_win = empty ? 0u : c->nsel_window;
   const uint32_t esc = P.k;
   const uint32_t B = P.B;
-  for (int i = tid; i < WIN; i += UNIT_TPB) s_lut[i] = (LT)gload(P.lut + i);
+  // the LUT's 16-bit entries, eight per 16-byte load
+  for (int i = tid; i < WIN / 8; i += UNIT_TPB) {
+    const nk_u32x4 x = gload(reinterpret_cast<const nk_u32x4*>(P.lut) + i);
+#pragma unroll
+    for (int h = 0; h < 8; ++h) s_lut[8 * i + h] = (LT)(x[h / 2] >> (16 * (h & 1)));
+  }
   __syncthreads();
 
   const T* __restrict__ prev = static_cast<const T*>(P.prev);
@@ -1925,10 +1951,10 @@ __global__ void __launch_bounds__(UNIT_TPB) k_encode_pre(S src, Geo g) {
     const uint64_t left = P.n - t0;
     const uint32_t lim = FULL ? (uint32_t)WT
                               : (left < (uint64_t)WT ? (uint32_t)left : (uint32_t)WT);
-    // code slot sl = r * V + v of a lane: element e0(r) + v.  okm: the slots
-    // indexed (selected bin, check passed); tm: valid slots outside the window
+    // code slot sl = r * V + v of a lane: element e0(r) + v.  inm: the slots
+    // in range; okm: the slots indexed (selected bin, check passed)
     uint32_t cw[R][CWN];
-    uint32_t okm = 0, tm = 0;
+    uint32_t okm = 0, inm = FULL ? (1u << (R * V)) - 1u : 0u;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const uint32_t e0 = ((uint32_t)r * 64 + lane) * V;  // tile-local element
@@ -1939,13 +1965,23 @@ __global__ void __launch_bounds__(UNIT_TPB) k_encode_pre(S src, Geo g) {
         const bool inr = FULL || e0 + v < lim;
         const uint32_t c16 = (cv[r][v / 2] >> (16 * (v & 1))) & 0xFFFFu;
         const uint32_t l = s_lut[c16 & (uint32_t)(WIN - 1)];
-        const bool ok = inr & (c16 < WC_INVALID) & ((c16 & WC_OK) != 0) & (l != esc);
-        okm |= ok ? 1u << (r * V + v) : 0u;
-        tm |= inr & (c16 == WC_TAIL) ? 1u << (r * V + v) : 0u;
-        cw[r][(v * PK) / 32] |= (ok ? l : inr ? esc : 0u) << ((v * PK) % 32);
+        // bits 15-14 = 01: valid, inside the window, check passed
+        const uint32_t code = (c16 >> 14) == 1u ? l : esc;
+        if (!FULL) inm |= inr ? 1u << (r * V + v) : 0u;
+        okm |= inr & (code != esc) ? 1u << (r * V + v) : 0u;
+        cw[r][(v * PK) / 32] |= (inr ? code : 0u) << ((v * PK) % 32);
       }
     }
-    if (nsel_tail != 0 && __ballot(tm != 0)) {  // uniform test, then per lane
+    if (nsel_tail != 0) {  // uniform: points outside the window may be indexed
+      uint32_t tm = 0;
+#pragma unroll
+      for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+          const uint32_t c16 = (cv[r][v / 2] >> (16 * (v & 1))) & 0xFFFFu;
+          tm |= c16 == WC_TAIL ? 1u << (r * V + v) : 0u;
+        }
+      tm &= inm;
       while (tm) {
         const int sl = __builtin_ctz(tm);
         tm &= tm - 1u;
@@ -1966,14 +2002,6 @@ __global__ void __launch_bounds__(UNIT_TPB) k_encode_pre(S src, Geo g) {
                 cw[r][h] = (cw[r][h] & ~(esc << sh)) | (code << sh);
         }
       }
-    }
-    unsigned long long emask[R][V];
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const uint32_t e0 = ((uint32_t)r * 64 + lane) * V;
-#pragma unroll
-      for (int v = 0; v < V; ++v)
-        emask[r][v] = __ballot((FULL || e0 + v < lim) & !((okm >> (r * V + v)) & 1u));
     }
     // the indices: 8- and 16-bit codes straight to the packed stream (a
     // lane's 8 codes are 8 or 16 contiguous bytes), others to LDS
@@ -2013,30 +2041,34 @@ __global__ void __launch_bounds__(UNIT_TPB) k_encode_pre(S src, Geo g) {
     }
 
     // incompressible points in element order (round, lane, code slot);
-    // ranks are range-relative
+    // ranks are range-relative.  A lane's escapes of a round number at most
+    // 8: the escapes of the lanes below it are counted bit by bit of those
+    // counts (four ballots), then each lane stages its own in order.
+    const uint32_t em = inm & ~okm;
     const unsigned run0 = run;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
+      const uint32_t er = (em >> (r * V)) & ((1u << V) - 1u);
+      const uint32_t cnt = (uint32_t)__builtin_popcount(er);
       unsigned below = 0, all = 0;
 #pragma unroll
-      for (int v = 0; v < V; ++v) {
-        const unsigned long long mk = emask[r][v];
-        below += __builtin_amdgcn_mbcnt_hi((unsigned)(mk >> 32),
-                                           __builtin_amdgcn_mbcnt_lo((unsigned)mk, 0u));
-        all += (unsigned)__popcll(mk);
+      for (int b = 0; b < 4; ++b) {
+        const unsigned long long bm = __ballot((cnt >> b) & 1u);
+        below += __builtin_amdgcn_mbcnt_hi((unsigned)(bm >> 32),
+                                           __builtin_amdgcn_mbcnt_lo((unsigned)bm, 0u)) << b;
+        all += (unsigned)__popcll(bm) << b;
       }
       unsigned rank = run + below;
       const uint32_t e0 = ((uint32_t)r * 64 + lane) * V;
-#pragma unroll
-      for (int v = 0; v < V; ++v) {
-        const bool escp = (emask[r][v] >> lane) & 1ull;
-        if (escp) {
-          const unsigned tl = rank - run0;  // rank within the tile
-          const uint32_t j = (uint32_t)(t0 + e0 + v);
-          if (FULL && tl < (unsigned)ESC_STAGE) s_esc[wave][tl] = j;
-          else gstore(stage + e_base + rank, j);
-        }
-        rank += escp ? 1u : 0u;
+      uint32_t e = er;
+      while (e) {
+        const uint32_t v = (uint32_t)__builtin_ctz(e);
+        e &= e - 1u;
+        const unsigned tl = rank - run0;  // rank within the tile
+        const uint32_t j = (uint32_t)(t0 + e0 + v);
+        if (FULL && tl < (unsigned)ESC_STAGE) s_esc[wave][tl] = j;
+        else gstore(stage + e_base + rank, j);
+        ++rank;
       }
       run += all;
     }
@@ -2421,12 +2453,15 @@ static hipError_t run_chain(S src, const Geo& base, uint32_t njobs, const JobGro
   for (uint32_t i = 0; i < ndg; ++i) {
     const Geo g = group_geo(base, dg[i]);
     const uint32_t nj = g.job_end - g.job_begin;
+    // k_select ranks the selected tail bins itself when k <= SEL_TPB
+    bool tailrank = true;
+    if constexpr (std::is_same<S, OneJob>::value) tailrank = src.p.k > (uint32_t)SEL_TPB;
     if (dg[i].dtype == NUMARCK_F32) {
       NK_LAUNCH(KK_SELECT, (k_select<float, S>), nj, SEL_TPB, src, g);
-      NK_LAUNCH(KK_TAILRANK, (k_tailrank<float, S>), dim3(64, nj), TR_TPB, src, g);
+      if (tailrank) NK_LAUNCH(KK_TAILRANK, (k_tailrank<float, S>), dim3(64, nj), TR_TPB, src, g);
     } else {
       NK_LAUNCH(KK_SELECT, (k_select<double, S>), nj, SEL_TPB, src, g);
-      NK_LAUNCH(KK_TAILRANK, (k_tailrank<double, S>), dim3(64, nj), TR_TPB, src, g);
+      if (tailrank) NK_LAUNCH(KK_TAILRANK, (k_tailrank<double, S>), dim3(64, nj), TR_TPB, src, g);
     }
   }
   for (uint32_t i = 0; i < neg; ++i) {
