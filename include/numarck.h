@@ -146,7 +146,12 @@ size_t numarck_decompress_workspace_bytes(uint64_t len);
  * out        : host pointer to the output descriptor (device buffers)
  * ws         : device workspace of ws_bytes (>= numarck_workspace_bytes_tail(n, 0))
  * Inputs are only read; outputs are fully written (packed padding bits are 0,
- * centre slots past k_used are 0). */
+ * centre slots past k_used are 0).  Without out->recon the snapshots are read
+ * twice: the histogram pass also stores each point's bin place and the
+ * outcome of its error check (Sec. III-C) in the workspace, 2 bytes a point,
+ * and the indexing pass reads those; with out->recon, which needs both values
+ * of every point, the indexing pass reads the snapshots a third time.  The
+ * outputs are the same either way. */
 numarck_status numarck_compress(const void* prev, const void* curr, uint64_t n,
                                 numarck_dtype dtype, double E, uint32_t B,
                                 uint64_t block_bytes, const numarck_out* out, void* ws,
@@ -157,8 +162,8 @@ numarck_status numarck_compress(const void* prev, const void* curr, uint64_t n,
  * at -E instead of at the smallest valid ratio: bin m holds the ratios with
  * floor((d + E) / 2E) == m (m may be negative) and is centred on 2mE
  * (lo + (2m + 1) E with lo = -E).  Without a range to find first, the call
- * reads the snapshots twice (histogram, then index and pack) rather than
- * three times.  Top-k, verification, escapes, packing and blocks are
+ * reads the snapshots once fewer than numarck_compress (once without
+ * out->recon, twice with it).  Top-k, verification, escapes, packing and blocks are
  * unchanged, and so is the output format: numarck_decompress and
  * numarck_decompress_range read it.  Header: lo = -E, hi = 0, M = 0;
  * window_base is the first bin of the on-chip window, -8192.  bin_ids, if
@@ -274,7 +279,9 @@ numarck_status numarck_histogram_export(const void* ws, size_t ws_bytes, uint64_
 typedef struct numarck_tuning {
   uint32_t range_blocks_per_cu; /* pass-1 workgroups per compute unit */
   uint32_t hist_blocks_per_cu;  /* histogram workgroups per compute unit */
-  uint32_t hist_lds;            /* 1: window counts in LDS (64 KB per workgroup); 0: in global memory */
+  uint32_t hist_lds;            /* 1: window counts in LDS (64 KB per workgroup); 0: in global
+                                   memory, and the indexing pass reads the snapshots again
+                                   (no window codes) */
   uint32_t chunk_vec;           /* 16-byte vectors per streaming chunk of the first two passes;
                                    0: automatic, about four chunks per compute unit for each
                                    element type's group (a power of two in [4096, 65536]) */
