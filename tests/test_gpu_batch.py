@@ -85,6 +85,29 @@ def test_mixed_batch_vs_oracle(nk, recon):
     plan.close()
 
 
+def test_plan_mixing_both_encoders(nk):
+    """Jobs with and without a reconstruction in one plan: the plan keeps the
+    two encodings in separate encoder launches, and every job equals the
+    oracle (its reconstruction too, where asked for)."""
+    jobs = _mixed_jobs()
+    bj = [nk.BatchJob(_dev(p), _dev(q), E, B, bb) for p, q, E, B, bb in jobs]
+    outs = [nk.alloc_outputs(max(j.prev.numel(), 0), j.prev.dtype, j.B, j.block_bytes,
+                             recon=(i % 2 == 0), bin_ids=True) for i, j in enumerate(bj)]
+    plan = nk.Plan(bj, outputs=outs)
+    enc = [g for g in plan.groups() if g["pass"] == "encode"]
+    assert sum(g["njobs"] for g in enc) == len(bj)
+    keys = [(g["dtype"], g["cls"]) for g in enc]
+    assert len(keys) > len(set(keys)), enc  # a class split by encoding
+    res = plan.run()
+    torch.cuda.synchronize()
+    orc = oracle.get()
+    for i, ((p, q, E, B, bb), c) in enumerate(zip(jobs, res)):
+        assert (c.recon is not None) == (i % 2 == 0)
+        o = orc.compress(p, q, E, B, block_bytes=bb)
+        assert_matches_oracle(nk, c, o, p, q, E, B, bb, check_hist=False, label=f"mixed job{i}")
+    plan.close()
+
+
 @RECON
 def test_batch_equals_plain_and_one_shot(nk, recon):
     jobs = _mixed_jobs()
