@@ -1859,9 +1859,9 @@ __device__ void write_header(const CParams& P);
 // selected tail bins: its bin from its values (ratio_bin), a binary search
 // in the sorted selected tail ids, and the check of Sec. III-C with that
 // bin's centre; the escape code when the bin is not selected or the check
-// fails.  Out of line: it runs only for such points, and only when selected
-// tail bins exist; the encoder calls it from one loop over such points, not
-// at every code slot.
+// fails.  It runs only for such points, and only when selected tail bins
+// exist; the encoder calls it from one loop per tile over such points rather
+// than at each of its code slots, which keeps the tile loop short.
 template <typename T>
 __device__ __forceinline__ uint32_t pre_tail_index(
     const T* prev, const T* curr, uint64_t j, const int64_t* sorted_tail, unsigned nsel_tail,
