@@ -109,6 +109,35 @@ def test_plan_mixing_both_encoders(nk):
 
 
 @RECON
+def test_batch_selected_tail_bins(nk, recon):
+    """Selected bins on both sides of the window in jobs of one batch: with
+    k <= 1024 (B = 8, 10) k_select ranks them, with larger k (B = 12, 16)
+    k_tailrank does, in the same launches; every job equals the oracle."""
+    rng = np.random.default_rng(77)
+    jobs = []
+    for i, (B, dt) in enumerate([(8, np.float64), (12, np.float64), (10, np.float32),
+                                 (16, np.float32), (8, np.float32)]):
+        n = 150_000 + 1000 * i
+        prev = rng.lognormal(0, 1, n)
+        u = rng.random(n)
+        r = np.where(u < 0.3, rng.normal(0, 1e-5, n),
+                     np.where(u < 0.5, rng.normal(0.4, 3e-5, n),
+                              np.where(u < 0.7, rng.normal(-0.45, 3e-5, n),
+                                       rng.uniform(-0.5, 0.5, n))))
+        jobs.append((prev.astype(dt), (prev * (1 + r)).astype(dt), 1e-5, B, 0))
+    plan, bj, res = _run_plan(nk, jobs, recon=recon)
+    torch.cuda.synchronize()
+    orc = oracle.get()
+    for i, ((p, q, E, B, bb), c) in enumerate(zip(jobs, res)):
+        o = orc.compress(p, q, E, B, block_bytes=bb)
+        h = c.header()
+        ids = o.sel_ids
+        assert (ids < h.window_base).any() and (ids >= h.window_base + 16384).any(), i
+        assert_matches_oracle(nk, c, o, p, q, E, B, bb, check_hist=False, label=f"tail job{i}")
+    plan.close()
+
+
+@RECON
 def test_batch_equals_plain_and_one_shot(nk, recon):
     jobs = _mixed_jobs()
     plan, bj, res = _run_plan(nk, jobs, recon=recon)
